@@ -1,0 +1,274 @@
+"""Single-vertex CT-AUX Markov chain (Sec. 2.3), plain NumPy float64.
+
+Weights (Sec. 2.3, the expansion of Z and the auxiliary-field decoupling):
+
+* cosh(gamma) = 1 + U beta Nc / (2 K_exp) for the single-band Hubbard model
+  (N_corr = Nc);
+* a configuration {(r_i, tau_i, s_i)}, i = 1..k, weighs
+  (K_exp / (2 beta Nc))^k prod_sigma det N_sigma^{-1};
+* N_sigma^{-1} = e^{V_sigma} - g_sigma (e^{V_sigma} - 1), e^{V_sigma,i} =
+  e^{sigma gamma s_i} (sigma = +1 up, -1 down), g = -G0 between vertices
+  with the 0+ value on the diagonal (see ``g0.Propagator``).
+
+Moves (Sec. 2.3, the Metropolis updates of the vertex configuration): each
+proposal draws five uniforms u0..u4 from a Mersenne-twister stream.  u0 < 1/2
+proposes inserting a vertex at site floor(u1 Nc), time u2 beta, auxiliary
+spin +1 if u3 < 1/2 else -1, accepted with probability
+min(1, |K_exp/(k+1) prod_sigma ratio_sigma|); otherwise the vertex at list
+position floor(u1 k) is proposed for removal with factor k/K_exp (a removal
+at k = 0 is a rejected no-op).  u4 is compared with |R|; the sign of the
+configuration is multiplied by sgn(R) on acceptance.
+
+Determinant ratios and updates are the textbook single-vertex ones:
+insertion is a bordered inverse (Schur complement d - W N Q), removal the
+cofactor identity ratio = N_pp followed by the rank-one downdate
+N_{-p,-p} - N_{-p,p} N_{p,-p} / N_pp.  The submatrix method of Sec. 2.3 fuses
+k_s of these single updates into one rank-k_s operation and, with the "abort"
+or exact treatment of a spin touched twice, produces exactly this chain, so
+this chain is the plain definition the GPU path must reproduce.
+
+A sweep is max(k_start, 1) proposals rounded up to a multiple of k_s (the
+paper counts sweeps between measurements without defining one).
+"""
+import math
+import numpy as np
+
+from . import geometry, g0 as g0mod
+
+
+class Model:
+    """Hubbard model on a periodic cluster, finite-size mode."""
+
+    def __init__(self, a1=(2, 0), a2=(0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0,
+                 K_exp=1.0, n_tau=1000, use_table=True):
+        self.a1, self.a2 = tuple(a1), tuple(a2)
+        self.t, self.tp, self.U, self.beta, self.mu = t, tp, U, beta, mu
+        self.K_exp = K_exp
+        self.n_tau = n_tau
+        self.sites = geometry.cluster_sites(self.a1, self.a2)
+        self.K = geometry.cluster_momenta(self.a1, self.a2)
+        self.Nc = len(self.sites)
+        self.diff = geometry.diff_table(self.a1, self.a2)
+        self.eps = geometry.dispersion(self.K, t, tp)
+        self.xi = self.eps - mu
+        self.gamma = math.acosh(1.0 + U * beta * self.Nc / (2.0 * K_exp))
+        self.table = g0mod.g0_table(self.sites, self.K, self.xi, beta, n_tau)
+        analytic = (lambda d, tau: self._g0_exact(d, tau))
+        self.prop = g0mod.Propagator(self.diff, beta,
+                                     table=self.table if use_table else None,
+                                     analytic=analytic)
+
+    def _g0_exact(self, d, tau):
+        d = np.asarray(d)
+        tau = np.asarray(tau, float)
+        flat_d, flat_t = d.ravel(), tau.ravel()
+        gk = g0mod.g0_K_tau(self.xi, flat_t, self.beta)               # (NcK, T)
+        ph = np.exp(1j * self.sites[flat_d].astype(float) @ self.K.T)  # (T, NcK)
+        val = np.einsum("tk,kt->t", ph, gk).real / self.Nc
+        return val.reshape(d.shape)
+
+    def ev(self, s, spin):
+        """e^{V_sigma} for auxiliary spins s; spin 0 = up (+), 1 = down (-)."""
+        sig = 1.0 if spin == 0 else -1.0
+        return np.exp(sig * self.gamma * np.asarray(s, dtype=np.float64))
+
+
+def n_inverse(model, r, t, s, spin):
+    """N_sigma^{-1} = e^V - g (e^V - 1) for a vertex list."""
+    ev = model.ev(s, spin)
+    g = model.prop.matrix(r, t)
+    return np.diag(ev) - g * (ev - 1.0)[None, :]
+
+
+class Walker:
+    """One CT-AUX Markov chain with single-vertex updates."""
+
+    def __init__(self, model, seed, k_s=16, record=False):
+        self.m = model
+        self.rng = np.random.Generator(np.random.MT19937(seed))
+        self.k_s = int(k_s)
+        self.r = np.zeros(0, np.int64)
+        self.t = np.zeros(0, np.float64)
+        self.s = np.zeros(0, np.int64)
+        self.id = np.zeros(0, np.int64)
+        self.N = [np.zeros((0, 0)), np.zeros((0, 0))]
+        self.sign = 1.0
+        self.next_id = 0
+        self.record = record
+        self.trace = []
+        self.n_prop = 0
+        self.n_acc_ins = 0
+        self.n_acc_rem = 0
+        self.drifts = []
+
+    @property
+    def k(self):
+        return len(self.r)
+
+    # -- configuration ----------------------------------------------------
+    def set_config(self, r, t, s, ids=None):
+        self.r = np.asarray(r, np.int64).copy()
+        self.t = np.asarray(t, np.float64).copy()
+        self.s = np.asarray(s, np.int64).copy()
+        k = len(self.r)
+        self.id = np.arange(k, dtype=np.int64) if ids is None else np.asarray(ids, np.int64).copy()
+        self.next_id = int(self.id.max()) + 1 if k else 0
+        sgn = 1.0
+        for spin in range(2):
+            A = n_inverse(self.m, self.r, self.t, self.s, spin)
+            self.N[spin] = np.linalg.inv(A) if k else np.zeros((0, 0))
+            if k:
+                sgn *= np.sign(np.linalg.det(A))
+        self.sign = sgn
+
+    def random_config(self, k):
+        """k random interacting vertices (App. B, initial-configuration-size)."""
+        u = self.rng.random((k, 3))
+        r = np.floor(u[:, 0] * self.m.Nc).astype(np.int64)
+        t = u[:, 1] * self.m.beta
+        s = np.where(u[:, 2] < 0.5, 1, -1)
+        self.set_config(r, t, s)
+
+    def refresh(self):
+        """Replace N by a direct float64 inversion; return the relative drift."""
+        drift = 0.0
+        for spin in range(2):
+            if self.k == 0:
+                continue
+            Nn = np.linalg.inv(n_inverse(self.m, self.r, self.t, self.s, spin))
+            drift = max(drift, np.max(np.abs(self.N[spin] - Nn)) / np.max(np.abs(Nn)))
+            self.N[spin] = Nn
+        self.drifts.append(drift)
+        return drift
+
+    # -- moves ------------------------------------------------------------
+    def _insert_ratio(self, rq, tq, sq):
+        m = self.m
+        out = []
+        g_Iq = m.prop.g(self.r, self.t, rq, tq)
+        g_qI = m.prop.g(rq, tq, self.r, self.t)
+        g_qq = float(m.prop.g(rq, tq, rq, tq))
+        for spin in range(2):
+            evq = float(m.ev(sq, spin))
+            evI = m.ev(self.s, spin)
+            Q = -g_Iq * (evq - 1.0)
+            W = -g_qI * (evI - 1.0)
+            d = evq - g_qq * (evq - 1.0)
+            NQ = self.N[spin] @ Q
+            WN = W @ self.N[spin]
+            ratio = d - W @ NQ
+            out.append((ratio, NQ, WN))
+        return out
+
+    def _do_insert(self, rq, tq, sq, parts):
+        for spin in range(2):
+            ratio, NQ, WN = parts[spin]
+            k = self.k
+            Nn = np.empty((k + 1, k + 1))
+            Nn[:k, :k] = self.N[spin] + np.outer(NQ, WN) / ratio
+            Nn[:k, k] = -NQ / ratio
+            Nn[k, :k] = -WN / ratio
+            Nn[k, k] = 1.0 / ratio
+            self.N[spin] = Nn
+        new_id = self.next_id
+        self.next_id += 1
+        self.r = np.append(self.r, rq)
+        self.t = np.append(self.t, tq)
+        self.s = np.append(self.s, sq)
+        self.id = np.append(self.id, new_id)
+        return new_id
+
+    def _do_remove(self, p):
+        last = self.k - 1
+        for spin in range(2):
+            N = self.N[spin]
+            if p != last:
+                perm = np.arange(self.k)
+                perm[p], perm[last] = last, p
+                N = N[np.ix_(perm, perm)]
+            self.N[spin] = N[:-1, :-1] - np.outer(N[:-1, -1], N[-1, :-1]) / N[-1, -1]
+        for name in ("r", "t", "s", "id"):
+            a = getattr(self, name)
+            a[p] = a[last]
+            setattr(self, name, a[:-1].copy())
+
+    def step(self):
+        """One proposal; returns (kind, accepted)."""
+        m = self.m
+        u = self.rng.random(5)
+        self.n_prop += 1
+        k = self.k
+        if u[0] < 0.5:
+            rq = int(math.floor(u[1] * m.Nc))
+            tq = u[2] * m.beta
+            sq = 1 if u[3] < 0.5 else -1
+            parts = self._insert_ratio(rq, tq, sq)
+            R = m.K_exp / (k + 1) * parts[0][0] * parts[1][0]
+            acc = u[4] < abs(R)
+            new_id = -1
+            if acc:
+                self.sign *= math.copysign(1.0, R)
+                new_id = self._do_insert(rq, tq, sq, parts)
+                self.n_acc_ins += 1
+            if self.record:
+                self.trace.append((0, rq, tq, sq, new_id, u[4], R, bool(acc)))
+            return 0, acc
+        if k == 0:
+            if self.record:
+                self.trace.append((1, -1, 0.0, 0, -1, u[4], 0.0, False))
+            return 1, False
+        p = int(math.floor(u[1] * k))
+        R = k / m.K_exp * self.N[0][p, p] * self.N[1][p, p]
+        acc = u[4] < abs(R)
+        tid = int(self.id[p])
+        if acc:
+            self.sign *= math.copysign(1.0, R)
+            self._do_remove(p)
+            self.n_acc_rem += 1
+        if self.record:
+            self.trace.append((1, -1, 0.0, 0, tid, u[4], R, bool(acc)))
+        return 1, acc
+
+    def sweep_length(self):
+        ks = self.k_s
+        return int(math.ceil(max(self.k, 1) / ks) * ks)
+
+    def sweep(self):
+        for _ in range(self.sweep_length()):
+            self.step()
+
+    def weight_sign(self):
+        """Sign of prod_sigma det N_sigma^{-1} recomputed from scratch."""
+        sgn = 1.0
+        for spin in range(2):
+            if self.k:
+                sgn *= np.sign(np.linalg.det(n_inverse(self.m, self.r, self.t, self.s, spin)))
+        return sgn
+
+    def canonical(self):
+        """(ids, N_up, N_dn) with vertices sorted by id."""
+        o = np.argsort(self.id)
+        return self.id[o], self.N[0][np.ix_(o, o)], self.N[1][np.ix_(o, o)]
+
+
+TRACE_FIELDS = ("kind", "site", "tau", "aux_spin", "id", "u_accept", "ratio", "accepted")
+
+
+def trace_arrays(trace):
+    """Column arrays from a recorded trace.
+
+    id is the new vertex's id for an accepted insertion and the target's id
+    for a removal (-1 otherwise)."""
+    if not trace:
+        return {f: np.zeros(0) for f in TRACE_FIELDS}
+    cols = list(zip(*trace))
+    return {
+        "kind": np.array(cols[0], np.uint8),
+        "site": np.array(cols[1], np.int32),
+        "tau": np.array(cols[2], np.float64),
+        "aux_spin": np.array(cols[3], np.int8),
+        "id": np.array(cols[4], np.int64),
+        "u_accept": np.array(cols[5], np.float64),
+        "ratio": np.array(cols[6], np.float64),
+        "accepted": np.array(cols[7], np.uint8),
+    }

@@ -1,0 +1,259 @@
+"""CPU check of the submatrix (delayed) update algebra the HIP kernels use.
+
+Sec. 2.3 fuses k_s single-spin updates into one rank-k_s operation but gives
+no formulas; the identities below follow from N^{-1} = e^V - g (e^V - 1).
+With G = N g, for a set S of flipped auxiliary spins with
+Delta_p = e^{V'_p - V_p} - 1:
+
+* Gamma_S = G_SS - diag((1 + Delta_p) / Delta_p);
+* det N'^{-1} / det N^{-1} = prod_{p in S} (-Delta_p) det Gamma_S, so adding q to
+  S multiplies the ratio by (-Delta_q)(Gamma_qq - Gamma_qS Gamma_S^{-1} Gamma_Sq)
+  and taking q out again divides it, i.e. multiplies it by
+  (Gamma_S^{-1})_qq / (-Delta_q);
+* N' = N + (E_S - G_{.S}) Gamma_S^{-1} N_{S.};
+* an insertion flips a non-interacting spin (V = 0) whose N row is
+  X_q = g_{q,I} (e^{V_I} - 1) N and column e_q; removing flips V_p -> 0 and
+  deletes row and column p.
+
+``WindowModel`` is a NumPy transcription of the kernel pipeline (gathers,
+candidate rows, Gram matrix of the window, sequential Schur loop, fold with
+compaction).  It is test code: the HIP library does not import it.  Replaying
+an oracle trace through it must reproduce every ratio and the final N.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ctaux
+
+
+def test_gamma_identities_random():
+    rng = np.random.default_rng(0)
+    m = ctaux.Model(a1=(2, 0), a2=(0, 2), U=4.0, beta=3.0, n_tau=500)
+    for trial in range(20):
+        k = int(rng.integers(3, 12))
+        r = rng.integers(0, 4, size=k)
+        t = rng.random(k) * m.beta
+        s = rng.choice([-1, 1], size=k)
+        spin = trial % 2
+        Ninv = ctaux.n_inverse(m, r, t, s, spin)
+        N = np.linalg.inv(Ninv)
+        g = m.prop.matrix(r, t)
+        G = N @ g
+        S = rng.choice(k, size=int(rng.integers(1, k)), replace=False)
+        s_new = s.copy()
+        s_new[S] = -s[S]
+        V = (1 if spin == 0 else -1) * m.gamma * s
+        Vn = (1 if spin == 0 else -1) * m.gamma * s_new
+        Delta = np.exp(Vn[S] - V[S]) - 1.0
+        Gam = G[np.ix_(S, S)] - np.diag((1 + Delta) / Delta)
+        ratio = np.prod(-Delta) * np.linalg.det(Gam)
+        Ninv_new = ctaux.n_inverse(m, r, t, s_new, spin)
+        assert abs(ratio - np.linalg.det(Ninv_new) / np.linalg.det(Ninv)) < 1e-10 * abs(ratio)
+        E = np.zeros((k, len(S)))
+        E[S, np.arange(len(S))] = 1.0
+        N_fold = N + (E - G[:, S]) @ np.linalg.solve(Gam, N[S, :])
+        assert np.max(np.abs(N_fold - np.linalg.inv(Ninv_new))) < 1e-11 * np.max(np.abs(N_fold))
+
+
+class WindowModel:
+    """NumPy transcription of the window pipeline, replaying forced decisions."""
+
+    def __init__(self, model, r, t, s, ids):
+        self.m = model
+        self.r, self.t, self.s, self.id = (np.array(x) for x in (r, t, s, ids))
+        self.N = [np.linalg.inv(ctaux.n_inverse(model, self.r, self.t, self.s, sp)) for sp in (0, 1)]
+        self.ratios = []
+
+    def ev(self, s, sp):
+        return self.m.ev(s, sp)
+
+    def window(self, props):
+        """props: list of (kind, site, tau, s, id, accepted)."""
+        m = self.m
+        k0 = len(self.r)
+        slot_of = {int(v): i for i, v in enumerate(self.id)}
+        # -- element list: candidates and window-start targets --------------
+        el_r, el_t, el_s, el_slot = [], [], [], []      # slot -1 for candidates
+        cand_of_id = {}
+        prop_el = []
+        for (kind, site, tau, sq, vid, acc) in props:
+            if kind == 0:
+                prop_el.append(len(el_r))
+                el_r.append(site); el_t.append(tau); el_s.append(sq); el_slot.append(-1)
+                if acc:
+                    cand_of_id[int(vid)] = prop_el[-1]
+            else:
+                if int(vid) in cand_of_id:
+                    prop_el.append(cand_of_id[int(vid)])
+                    continue
+                p = slot_of[int(vid)]
+                if p in el_slot:
+                    prop_el.append(el_slot.index(p))
+                    continue
+                prop_el.append(len(el_r))
+                el_r.append(self.r[p]); el_t.append(self.t[p]); el_s.append(self.s[p]); el_slot.append(p)
+        nE = len(el_r)
+        el_r, el_t, el_s, el_slot = map(np.array, (el_r, el_t, el_s, el_slot))
+        cand = el_slot < 0
+        ci = np.where(cand)[0]
+        ti = np.where(~cand)[0]
+        tslot = el_slot[ti]
+        # gathers only for insertion candidates: column g_{I,c}, row g_{c,I}, g_{c,c'}
+        gcol = m.prop.g(self.r[:, None], self.t[:, None], el_r[None, ci], el_t[None, ci])  # (k0, nC)
+        grow = m.prop.g(el_r[ci, None], el_t[ci, None], self.r[None, :], self.t[None, :])  # (nC, k0)
+        gCC = m.prop.g(el_r[ci, None], el_t[ci, None], el_r[None, ci], el_t[None, ci])
+        Rw, Gram, Xs = [], [], []
+        for sp in (0, 1):
+            evI = self.ev(self.s, sp)
+            X = (grow * (evI - 1.0)[None, :]) @ self.N[sp]             # candidate rows of N_ext
+            R = np.zeros((nE, k0))
+            R[ci] = X
+            R[ti] = self.N[sp][tslot, :]
+            Gm = np.zeros((nE, nE))
+            # candidate columns: G_{x,c} = R_x . g_{I,c} (+ g_{x,c} for candidate rows)
+            Gm[:, ci] = R @ gcol
+            Gm[np.ix_(ci, ci)] += gCC
+            # columns of existing vertices p come from N itself:
+            # G_{.p} = (e^{V_p} N_ext{.p} - e_p) / (e^{V_p} - 1)
+            evp = evI[tslot]
+            Gm[:, ti] = R[:, tslot] * (evp / (evp - 1.0))[None, :]
+            Gm[ti, ti] -= 1.0 / (evp - 1.0)
+            Rw.append(R)
+            Gram.append(Gm)
+        # -- sequential Schur loop ---------------------------------------
+        S, Dl = [], [[], []]
+        Ginv = [np.zeros((0, 0)), np.zeros((0, 0))]
+        kcur = k0
+        for (kind, site, tau, sq, vid, acc), q in zip(props, prop_el):
+            if q in S:
+                j = S.index(q)
+                rat = [Ginv[sp][j, j] / (-Dl[sp][j]) for sp in (0, 1)]
+            else:
+                rat, parts = [], []
+                for sp in (0, 1):
+                    sgn = 1.0 if sp == 0 else -1.0
+                    if cand[q]:
+                        D = math.exp(sgn * m.gamma * el_s[q]) - 1.0
+                    else:
+                        D = math.exp(-sgn * m.gamma * el_s[q]) - 1.0
+                    gqq = Gram[sp][q, q] - (1 + D) / D
+                    gqS = Gram[sp][q, S]
+                    gSq = Gram[sp][S, q]
+                    L = Ginv[sp] @ gSq
+                    Rr = gqS @ Ginv[sp]
+                    schur = gqq - gqS @ L
+                    rat.append(-D * schur)
+                    parts.append((D, L, Rr, schur))
+            fac = m.K_exp / (kcur + 1) if kind == 0 else kcur / m.K_exp
+            self.ratios.append(fac * rat[0] * rat[1])
+            if not acc:
+                continue
+            if q in S:
+                j = S.index(q)
+                for sp in (0, 1):
+                    A = Ginv[sp]
+                    A = A - np.outer(A[:, j], A[j, :]) / A[j, j]
+                    keep = np.arange(len(S)) != j
+                    Ginv[sp] = A[np.ix_(keep, keep)]
+                    Dl[sp].pop(j)
+                S.pop(j)
+            else:
+                for sp in (0, 1):
+                    D, L, Rr, schur = parts[sp]
+                    n = len(S)
+                    B = np.empty((n + 1, n + 1))
+                    B[:n, :n] = Ginv[sp] + np.outer(L, Rr) / schur
+                    B[:n, n] = -L / schur
+                    B[n, :n] = -Rr / schur
+                    B[n, n] = 1.0 / schur
+                    Ginv[sp] = B
+                    Dl[sp].append(D)
+                S.append(q)
+            kcur += 1 if kind == 0 else -1
+        # -- fold in the extended space, then compaction --------------------
+        ins = [q for q in S if cand[q]]
+        rem = [el_slot[q] for q in S if not cand[q]]
+        mi = len(ins)
+        kx = k0 + mi
+        row_of = {}
+        for q in S:
+            row_of[q] = (k0 + ins.index(q)) if cand[q] else el_slot[q]
+        ins_ids = []
+        id_iter = iter([p[4] for p in props if p[0] == 0 and p[5]])
+        cand_id = {}
+        for (kind, site, tau, sq, vid, acc), q in zip(props, prop_el):
+            if kind == 0 and acc:
+                cand_id[q] = vid
+        for sp in (0, 1):
+            Next = np.zeros((kx, kx))
+            Next[:k0, :k0] = self.N[sp]
+            for j, q in enumerate(ins):
+                Next[k0 + j, :k0] = Rw[sp][q]
+                Next[k0 + j, k0 + j] = 1.0
+            if S:
+                # A = E_S - G_ext[:, S]; existing p: (e^{V_p}/(e^{V_p}-1)) (e_p - N_ext{.p});
+                # candidate c: e_c - [N g_{I,c}; G_{C_S, c}]
+                evI = self.ev(self.s, sp)
+                A = np.zeros((kx, len(S)))
+                for j, q in enumerate(S):
+                    if cand[q]:
+                        A[:k0, j] = -self.N[sp] @ m.prop.g(self.r, self.t, el_r[q], el_t[q])
+                        for jj, qq in enumerate(ins):
+                            A[k0 + jj, j] = -Gram[sp][qq, q]
+                        A[row_of[q], j] += 1.0
+                    else:
+                        p = el_slot[q]
+                        e = np.zeros(kx)
+                        e[p] = 1.0
+                        A[:, j] = evI[p] / (evI[p] - 1.0) * (e - Next[:, p])
+                rows = [row_of[q] for q in S]
+                Next = Next + A @ (Ginv[sp] @ Next[rows, :])
+            keep = np.array([i for i in range(kx) if i not in rem], dtype=int)
+            self.N[sp] = Next[np.ix_(keep, keep)]
+        new_r = np.concatenate([self.r, el_r[ins]])
+        new_t = np.concatenate([self.t, el_t[ins]])
+        new_s = np.concatenate([self.s, el_s[ins]])
+        new_id = np.concatenate([self.id, np.array([cand_id[q] for q in ins], dtype=self.id.dtype)])
+        keep = np.array([i for i in range(kx) if i not in rem], dtype=int)
+        self.r, self.t, self.s, self.id = new_r[keep], new_t[keep], new_s[keep], new_id[keep]
+
+    def canonical(self):
+        o = np.argsort(self.id)
+        return self.id[o], self.N[0][np.ix_(o, o)], self.N[1][np.ix_(o, o)]
+
+
+@pytest.mark.parametrize("k_s,seed", [(4, 1), (16, 2), (64, 3)])
+def test_window_model_replays_oracle(k_s, seed):
+    m = ctaux.Model(a1=(2, 0), a2=(0, 2), U=4.0, beta=5.0, n_tau=1000)
+    w = ctaux.Walker(m, seed=seed, k_s=k_s, record=False)
+    w.random_config(25)
+    for _ in range(20):              # equilibrate, then replay from a refreshed state
+        w.sweep()
+    w.refresh()
+    w.record = True
+    r0, t0, s0, id0 = w.r.copy(), w.t.copy(), w.s.copy(), w.id.copy()
+    for _ in range(6):
+        w.sweep()
+    tr = w.trace
+    wm = WindowModel(m, r0, t0, s0, id0)
+    n_unflip = 0
+    for i in range(0, len(tr), k_s):
+        chunk = tr[i:i + k_s]
+        props = [(rec[0], rec[1], rec[2], rec[3], rec[4], rec[7]) for rec in chunk]
+        inserted = {p[4] for p in props if p[0] == 0 and p[5]}
+        n_unflip += sum(1 for p in props if p[0] == 1 and p[4] in inserted)
+        # removal at k = 0 carries no target; the model skips such records
+        props = [p for p in props if not (p[0] == 1 and p[4] < 0)]
+        wm.window(props)
+    ref = np.array([rec[6] for rec in tr if not (rec[0] == 1 and rec[4] < 0)])
+    got = np.array(wm.ratios)
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-10
+    ids, Nu, Nd = w.canonical()
+    ids2, Nu2, Nd2 = wm.canonical()
+    assert np.array_equal(ids, ids2)
+    for A, B in ((Nu, Nu2), (Nd, Nd2)):
+        assert np.max(np.abs(A - B)) / np.max(np.abs(A)) < 1e-10
+    if k_s == 64:
+        assert n_unflip > 0      # the exact "spin touched twice" path was exercised
