@@ -1,0 +1,207 @@
+/*
+ * dcax.h -- C ABI of the CT-AUX walker library for AMD MI355X (gfx950).
+ *
+ * The library implements the hot path of the continuous-time auxiliary-field
+ * (CT-AUX) cluster solver of Hahner et al., "DCA++: A software framework to
+ * solve correlated electron problems with modern quantum cluster methods",
+ * Sec. 2.3: Metropolis insertion and removal of auxiliary-field vertices,
+ * their fusion into submatrix (delayed) updates of the walker matrices
+ * N_sigma = [e^{V_sigma} - G0 (e^{V_sigma} - 1)]^{-1}, and the measurement of
+ * M = (e^V - 1) N that yields G(K, i w_n) = G0 - G0 <M> G0 / beta.
+ *
+ * Conventions
+ *   - All functions return a dcax_status; no C++ exception crosses the ABI.
+ *   - Pointers named *_dev are device pointers on the walker's GPU; all other
+ *     pointers are host pointers.  The caller owns every buffer it passes.
+ *   - Every call enqueues its GPU work on the stream given at creation.  Calls
+ *     that return host data (ratio_out, drift_out, the copy/get functions)
+ *     synchronise that stream before returning.
+ *   - Kernels latch numerical faults (a non-finite ratio, a zero pivot, an
+ *     order beyond max_order) in a device status word.  The next synchronising
+ *     call returns it; from then on the walker answers DCAX_E_STATE until
+ *     dcax_set_config() installs a fresh configuration.
+ *   - Handles are not thread-safe; distinct handles are independent.
+ *   - Sites are numbered by the cluster enumeration below; vertices carry a
+ *     64-bit id, assigned in order of accepted insertion (the initial
+ *     configuration takes ids 0..k-1 unless dcax_set_config gives others).
+ *
+ * Cluster enumeration (App. B, domains group "cluster": superlattice vectors
+ * in the lattice basis).  Sites are the quotient Z^2 / (a1 Z + a2 Z); a site's
+ * canonical representative is A f with A = [a1 a2] and fractional coordinates
+ * f wrapped into [0, 1); sites are ordered by the representative's (y, x).
+ * Momenta are K = 2 pi q / |det A| with integer q in [0, |det A|)^2 and
+ * q . a_i = 0 mod |det A|, ordered by (q_y, q_x).
+ */
+#ifndef DCAX_H
+#define DCAX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DCAX_ABI_VERSION 1
+
+typedef enum {
+  DCAX_OK = 0,
+  DCAX_E_INVAL = -1,    /* invalid argument; nothing was enqueued */
+  DCAX_E_NOMEM = -2,    /* the allocator returned NULL */
+  DCAX_E_HIP = -3,      /* a HIP runtime call failed (message in dcax_last_error) */
+  DCAX_E_NUMERIC = -4,  /* a kernel met a non-finite ratio or a zero pivot */
+  DCAX_E_CAPACITY = -5, /* the order would exceed max_order */
+  DCAX_E_TRACE = -6,    /* a replay record names a vertex id that is not present */
+  DCAX_E_STATE = -7     /* the walker holds a latched error; call dcax_set_config */
+} dcax_status;
+
+typedef enum {
+  DCAX_FP64 = 0,        /* N, candidate GEMMs, fold and measurement in FP64 */
+  DCAX_FP32_MIXED = 1   /* N and its GEMMs in FP32 (MFMA, FP32 accumulation);
+                           Gamma^{-1}, ratios and the refresh stay FP64 */
+} dcax_precision;
+
+typedef struct dcax_walker_s* dcax_walker;
+
+/* Device memory source.  alloc(bytes, ctx) returns a device pointer aligned
+ * to 256 bytes or NULL; free(ptr, ctx) releases it.  A NULL allocator makes
+ * the library call hipMalloc/hipFree itself. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} dcax_allocator;
+
+/* One vertex of a configuration (Sec. 2.3: a site, an imaginary time and an
+ * auxiliary spin s = +1/-1 coupling n_up - n_down at that site). */
+typedef struct {
+  int64_t id;
+  int32_t site;
+  int32_t aux_spin;
+  double tau;           /* in [0, beta) */
+} dcax_vertex;
+
+/* One recorded proposal, replayed with its decision forced (dcax_sweep).
+ * kind 0 = insertion at (site, tau, aux_spin), taking `id` if accepted;
+ * kind 1 = removal of the vertex with id `id` (id -1: removal proposed at
+ * order 0, a rejected no-op).  u_accept is the uniform the decision was drawn
+ * with; the library counts decisions on which its own ratio would disagree. */
+typedef struct {
+  int32_t kind;
+  int32_t site;
+  int32_t aux_spin;
+  int32_t accepted;
+  double tau;
+  int64_t id;
+  double u_accept;
+} dcax_proposal;
+
+/* Model and run parameters (App. B names in quotes). */
+typedef struct {
+  int32_t abi_version;     /* must be DCAX_ABI_VERSION */
+  int32_t cluster[4];      /* "cluster": a1 = (c[0], c[1]), a2 = (c[2], c[3]) */
+  double t, tp;            /* nearest and next-nearest neighbour hopping */
+  double U;                /* "U", on-site interaction */
+  double beta;             /* "beta", inverse temperature */
+  double mu;               /* chemical potential measured from U/2 (mu = 0: half filling) */
+  double K_exp;            /* "expansion-parameter-K" */
+  int32_t n_tau;           /* G0 table points on [0+, beta-], both ends included */
+  int32_t precision;       /* dcax_precision */
+  int32_t submatrix_k;     /* "max-submatrix-size", 1..64 */
+  int32_t refresh_every;   /* sweeps between FP64 refreshes of N inside dcax_sweep; 0 = never */
+  int32_t max_order;       /* largest expansion order the walker may reach */
+  int32_t n_freq;          /* Matsubara frequencies measured, n = 0 .. n_freq-1 */
+  uint64_t seed;           /* "seed" of the walker's counter-based generator */
+} dcax_params;
+
+/* Counters since creation or the last dcax_set_config. */
+typedef struct {
+  int64_t proposals;
+  int64_t accepted_insertions;
+  int64_t accepted_removals;
+  int64_t windows;          /* submatrix windows folded */
+  int64_t flips_folded;     /* sum over windows of the fold rank m */
+  int64_t decision_mismatches; /* replay: u_accept on the other side of |R| */
+  int64_t sweeps;
+  double sign;              /* sign of the current configuration */
+  double fold_flops;        /* algorithmic flops of the rank-m folds, 2 k'^2 m per spin */
+  double fold_bytes;        /* algorithmic bytes of the folds: N read and written once */
+  double fold_seconds;      /* summed fold kernel time (dcax_set_timing) */
+  int64_t fold_launches;    /* fold launches timed */
+  double accept_seconds;    /* summed accept-loop kernel time (dcax_set_timing) */
+  double window_seconds;    /* summed time of whole windows (dcax_set_timing) */
+  int64_t aborted_windows;  /* windows closed early by a carried removal */
+  double last_drift;        /* drift of the last refresh inside dcax_sweep */
+  double max_drift;         /* largest such drift */
+} dcax_stats;
+
+/* Create a walker: copies the parameters, builds the cluster tables and the
+ * G0(r, tau) table on the GPU (Sec. 2.1's bare propagator of the isolated
+ * cluster) and allocates memory for max_order.  The configuration is empty.
+ * n_walkers must be 1.  `stream` is a hipStream_t (NULL: the default stream). */
+dcax_status dcax_walker_create(const dcax_params* p, int32_t n_walkers, const dcax_allocator* a,
+                               void* stream, dcax_walker* out);
+dcax_status dcax_walker_destroy(dcax_walker w);
+
+/* Run Markov-chain proposals (Sec. 2.3, Metropolis insertion/removal fused
+ * into submatrix updates of at most submatrix_k proposals).
+ *   replay == NULL: n_sweeps sweeps from the walker's own generator; a sweep is
+ *     max(k, 1) proposals rounded up to a multiple of submatrix_k, k taken at
+ *     the sweep's start.  N is refreshed every refresh_every sweeps.
+ *   replay != NULL: the n_replay records are replayed in order with forced
+ *     decisions (n_sweeps is ignored); ratio_out (nullable, length n_replay)
+ *     receives the library's full acceptance ratio R for each record. */
+dcax_status dcax_sweep(dcax_walker w, int32_t n_sweeps, const dcax_proposal* replay,
+                       int64_t n_replay, double* ratio_out);
+
+/* Rebuild N_sigma = [e^V - g (e^V - 1)]^{-1} from scratch in FP64 (gathers
+ * plus Gauss-Jordan inversion with partial pivoting).  drift_out (nullable)
+ * receives max|N_before - N_after| / max|N_after| over both spins. */
+dcax_status dcax_refresh(dcax_walker w, double* drift_out);
+
+/* Accumulate the measurement of the current configuration (Sec. 2.3):
+ *   acc_dev (complex128 [2 spins][Nc momenta][n_freq], interleaved re, im)
+ *     += sign * M_sigma(K, i w_n), with
+ *     M_sigma(K, i w_n) = (1/Nc) sum_ij e^{i (w_n tau_i - K r_i)} [(e^V - 1) N]_ij
+ *                                        e^{-i (w_n tau_j - K r_j)};
+ *   aux_dev (3 doubles) += [sign, sign * (1/Nc) tr M_up, sign * (1/Nc) tr M_down].
+ * The trace terms are the equal-time coefficient of G's 1/(i w)^2 tail. */
+dcax_status dcax_measure_G(dcax_walker w, double* acc_dev, double* aux_dev);
+
+/* G(K, i w_n) = G0 - G0 <M> G0 / beta with <M> = acc / sign (Sec. 2.3), and
+ * G(K, tau) on n_tau_out points tau_l = l beta / (n_tau_out - 1) (l = 0 is 0+,
+ * the last point beta-) from the frequency data with the 1/(i w)^2 tail
+ * removed and added back in closed form.  Inputs as accumulated by
+ * dcax_measure_G; outputs (device): Giw_dev complex128 [2][Nc][n_freq],
+ * Gtau_dev double [2][Nc][n_tau_out] (nullable when n_tau_out == 0). */
+dcax_status dcax_finalize_G(dcax_walker w, const double* acc_dev, const double* aux_dev,
+                            double* Giw_dev, int32_t n_tau_out, double* Gtau_dev);
+
+/* Introspection and checkpointing. */
+dcax_status dcax_get_order(dcax_walker w, int32_t* k);
+/* Copy N_spin in canonical order (vertex id ascending) into host[ld * k];
+ * ids_host (nullable) receives the k ids in that order.  FP32 walkers are
+ * widened to double. */
+dcax_status dcax_copy_N(dcax_walker w, int32_t spin, double* host, int64_t ld, int64_t* ids_host);
+dcax_status dcax_get_config(dcax_walker w, dcax_vertex* host, int32_t cap, int32_t* k);
+/* Install a configuration (ids must be distinct and >= 0) and rebuild N by
+ * dcax_refresh; clears a latched error and the counters. */
+dcax_status dcax_set_config(dcax_walker w, const dcax_vertex* host, int32_t k);
+dcax_status dcax_get_stats(dcax_walker w, dcax_stats* out);
+/* Time the fold and accept kernels and whole windows with HIP events on the
+ * walker's stream (on != 0) or stop timing (on == 0).  Timings accumulate into
+ * dcax_stats; they cost two events per timed launch. */
+dcax_status dcax_set_timing(dcax_walker w, int32_t on);
+/* The G0(r, tau) table the walker uses, [Nc][n_tau], standard sign convention
+ * G0 = -<T c c+>. */
+dcax_status dcax_copy_g0_table(dcax_walker w, double* host);
+/* Cluster geometry: sites [Nc][2] (int32) and momenta [Nc][2] (double). */
+dcax_status dcax_cluster(const dcax_params* p, int32_t* n_sites, int32_t* sites, double* momenta);
+
+/* Thread-local message for the last non-OK status. */
+const char* dcax_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCAX_H */

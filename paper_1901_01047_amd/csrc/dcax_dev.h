@@ -1,0 +1,191 @@
+// Internal device-side definitions of the CT-AUX walker library (gfx950).
+//
+// One walker owns, in HBM: its vertex arrays (structure of arrays), the two
+// walker matrices N_up and N_down (column-major, leading dimension `ld`,
+// capacity `cap` = max_order + submatrix_k so that a window's inserted rows
+// fit before compaction), the G0(r, tau) table, and the window scratch
+// buffers below.  Mutable scalars (order, sign, cursors, counters, the
+// latched status) live in a device-resident control block so that a whole
+// sweep can be enqueued without host round trips.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "dcax.h"
+
+namespace dcax {
+
+constexpr int KS_MAX = 64;   // largest submatrix size (window proposals)
+constexpr int WG = 256;      // threads per workgroup of the streaming kernels
+
+enum StatusCode { ST_OK = 0, ST_NUMERIC = 1, ST_CAPACITY = 2, ST_TRACE = 3 };
+
+struct Ctl {
+  int k;            // current expansion order
+  int status;       // latched StatusCode
+  int active;       // the current window has work
+  int nP;           // proposals in the window
+  int nE;           // window elements (candidates + removal targets)
+  int nC;           // insertion candidates
+  int m;            // |S| after the accept loop (fold rank)
+  int mi;           // inserted spins in S
+  int mr;           // removed spins in S
+  int k0;           // order at the window start
+  int kx;           // extended order k0 + mi
+  int knew;         // order after compaction
+  long long next_id;
+  long long pos;    // replay cursor or global proposal counter
+  long long end;    // end of the replay batch or of the sweep
+  double sign;
+  long long n_prop, n_acc_ins, n_acc_rem, n_windows, sum_m, n_mismatch, n_sweeps;
+  double fold_flops;
+  long long carry_id;  // removal target carried into the next window, -1 none
+  long long n_abort;   // windows closed early by a carried removal
+  double fold_bytes;   // algorithmic bytes of the folds (N read and written)
+  long long n_folds;   // windows with a non-empty fold
+};
+
+struct WinProp {      // one proposal of the current window
+  int kind;           // 0 insertion, 1 removal
+  int el;             // window element, -1 for a no-op removal at k = 0
+  int forced;         // replay decision (-1: decide from u)
+  int carried;        // removal whose target was fixed before this window
+  double u;           // acceptance uniform
+  long long ridx;     // replay index (ratio output), -1 if none
+  long long gidx;     // global proposal index (generator counter)
+};
+
+// Everything a kernel needs, passed by value.  T is the storage type of N
+// and of its GEMM operands (double, or float in the mixed mode).
+template <typename T>
+struct View {
+  // model
+  int Nc, n_tau, ks, cap, ld, max_order;
+  double beta, h, gamma, K_exp;
+  double ev[2][2];            // e^{V}: [spin][0 for s = +1, 1 for s = -1]
+  const int* diff;            // [Nc * Nc] index of r_i - r_j
+  const double* table;        // [Nc][n_tau] G0(r, tau_l), standard convention
+  // state
+  Ctl* ctl;
+  int* v_site;
+  double* v_tau;
+  int* v_s;
+  long long* v_id;
+  T* N[2];
+  // window scratch
+  WinProp* wp;
+  int* el_site;
+  double* el_tau;
+  int* el_s;
+  int* el_slot;               // slot of a removal target, -1 for a candidate
+  int* el_cand;               // candidate index or -1
+  int* cand_el;
+  long long* cand_id;
+  int* S;                     // element of each fold column, S order
+  int* ins_el;                // inserted elements in S order (mi)
+  T* gcol;                    // [ks][cap] g_{I,c}
+  T* W[2];                    // [ks][cap] g_{c,I} (e^{V_I} - 1)
+  double* gCC;                // [ks][ks] g_{c,c'}
+  T* X[2];                    // [ks][cap] X_c = W_c N
+  double* gram[2];            // [ks][ks] G restricted to the window elements
+  double* ginv[2];            // [ks][ks] Gamma_S^{-1}
+  T* Y[2];                    // [ks][cap] N g_{I,c} for inserted spins
+  T* A[2];                    // [ks][cap] fold left factor, column-major
+  T* B[2];                    // [ks][cap] fold right factor, row-major
+  double* ratio_out;          // device copy of the replay ratios
+  const dcax_proposal* replay;
+};
+
+// ---------------------------------------------------------------- helpers
+__device__ inline void latch(Ctl* c, int code) { atomicCAS(&c->status, 0, code); }
+
+__device__ inline int s01(int s) { return s > 0 ? 0 : 1; }
+
+// Linear interpolation of the table at dtau in [0, beta]: l = floor(dtau/h),
+// f = dtau/h - l, (1 - f) T[l] + f T[l+1], l clamped to n_tau - 2; dtau = 0
+// gives the 0+ value.
+template <typename T>
+__device__ inline double g0_interp(const View<T>& w, int d, double dtau) {
+  double x = dtau / w.h;
+  int l = (int)floor(x);
+  l = l < 0 ? 0 : (l > w.n_tau - 2 ? w.n_tau - 2 : l);
+  double f = x - (double)l;
+  const double* t = w.table + (size_t)d * w.n_tau;
+  return (1.0 - f) * t[l] + f * t[l + 1];
+}
+
+// g(i, j) = <T c_i(tau_i) c+_j(tau_j)>_0 = -G0(r_i - r_j, tau_i - tau_j) for
+// tau_i >= tau_j (0+ at equal times), and +G0(r_i - r_j, tau_i - tau_j + beta)
+// for tau_i < tau_j (antiperiodicity).
+template <typename T>
+__device__ inline double gfun(const View<T>& w, int ri, double ti, int rj, double tj) {
+  int d = w.diff[ri * w.Nc + rj];
+  double dt = ti - tj;
+  if (dt < 0.0) return g0_interp(w, d, dt + w.beta);
+  return -g0_interp(w, d, dt);
+}
+
+// ------------------------------------------------------------------ MFMA
+// 16x16x4 matrix-core instructions.  Operand layout (both precisions): lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16].  Result register i of lane l
+// holds D[row(l, i)][l % 16] with row = 4 i + l / 16 in FP64 and
+// 4 (l / 16) + i in FP32.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4_t acc_t;
+  __device__ static inline acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int i) { return 4 * i + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+  typedef f4_t acc_t;
+  __device__ static inline acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
+// ------------------------------------------------------------ generator
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC 2011): a keyed bijection of a 128-bit counter.  The
+// counter is (proposal index, draw slot), the key the walker's seed, so every
+// proposal's uniforms are a pure function of its index.
+__host__ __device__ inline void philox_round(uint32_t c[4], const uint32_t k[2]) {
+  const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+  const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+  const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+  const uint32_t n0 = hi1 ^ c[1] ^ k[0], n2 = hi0 ^ c[3] ^ k[1];
+  c[0] = n0;
+  c[1] = lo1;
+  c[2] = n2;
+  c[3] = lo0;
+}
+
+__host__ __device__ inline void philox4x32(uint32_t c[4], uint64_t seed) {
+  uint32_t k[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int r = 0; r < 10; ++r) {
+    philox_round(c, k);
+    k[0] += 0x9E3779B9u;
+    k[1] += 0xBB67AE85u;
+  }
+}
+
+// Two uniforms in [0, 1) with 53 random bits each, for draw slot `slot` of
+// proposal `g`.
+__host__ __device__ inline void uniforms2(uint64_t seed, long long g, uint32_t slot, double& u, double& v) {
+  uint32_t c[4] = {(uint32_t)g, (uint32_t)((uint64_t)g >> 32), slot, 0x43545841u};
+  philox4x32(c, seed);
+  u = ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6)) * (1.0 / 9007199254740992.0);
+  v = ((double)(c[2] >> 5) * 67108864.0 + (double)(c[3] >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace dcax

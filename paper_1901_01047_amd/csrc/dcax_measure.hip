@@ -1,0 +1,261 @@
+// Green's-function measurement, Sec. 2.3: per configuration and spin,
+// M = (e^V - 1) N and
+//   M(K, i w_n) = (1/Nc) sum_{ij} e^{i (w_n tau_i - K r_i)} M_ij e^{-i (w_n tau_j - K r_j)},
+// accumulated with the configuration's sign; G = G0 - G0 <M> G0 / beta.
+//
+// The contraction is site-blocked: vertices are bucketed by site (each
+// bucket padded to a multiple of 16), M is copied into that order, and for
+// every pair of sites (a, b) and tile of 16 frequencies one wavefront forms
+//   M(a, b; w_n) = sum_{i in a} e^{i w_n tau_i} sum_{j in b} M_ij e^{-i w_n tau_j}
+// with the inner sum on the matrix cores (4 k^2 N_w flops per spin rather
+// than the 4 k^2 Nc N_w of the unblocked form).  A small kernel then applies
+// the momentum phases and adds sign * M(K, i w_n) to the caller's buffer.
+#include "dcax_dev.h"
+
+namespace dcax {
+
+struct MeasureBufs {
+  int* order = nullptr;    // [kpad] original slot of sorted row, -1 for padding
+  int* off = nullptr;      // [Nc + 1] bucket offsets (multiples of 16)
+  void* Ms[2] = {nullptr, nullptr};  // [kpad][kpad] sorted M, column-major
+  void* E = nullptr;       // [kpad][n_freq][2] e^{-i w_n tau_j} for sorted j
+  double* Mab[2] = {nullptr, nullptr};  // [Nc][Nc][n_freq][2]
+  int kpad_cap = 0;
+  int n_freq = 0;
+};
+
+// Counting sort of the vertices by site, buckets padded to 16 rows.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_meas_sort(View<T> w, int* order, int* off, int kpad_cap) {
+  const int k = w.ctl->k;
+  const int Nc = w.Nc;
+  extern __shared__ int cnt_s[];  // [Nc + 1]
+  for (int a = threadIdx.x; a <= Nc; a += WG) cnt_s[a] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += WG) atomicAdd(&cnt_s[w.v_site[i]], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int o = 0;
+    for (int a = 0; a < Nc; ++a) {
+      const int c = cnt_s[a];
+      cnt_s[a] = o;
+      off[a] = o;
+      o += (c + 15) & ~15;
+    }
+    off[Nc] = o;
+    cnt_s[Nc] = o;
+  }
+  __syncthreads();
+  const int kpad = cnt_s[Nc];
+  for (int i = threadIdx.x; i < kpad && i < kpad_cap; i += WG) order[i] = -1;
+  __syncthreads();
+  // stable placement: one thread per site keeps the original order
+  for (int a = threadIdx.x; a < Nc; a += WG) {
+    int o = off[a];
+    for (int i = 0; i < k; ++i)
+      if (w.v_site[i] == a) order[o++] = i;
+  }
+}
+
+// Ms[i'][j'] = (e^{V_i} - 1) N[i][j] in sorted order (zero on padding), and
+// the phase table E[j'][n] = e^{-i w_n tau_j}.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_meas_copy(View<T> w, const int* order, const int* off, T* Ms0, T* Ms1,
+                                                  int ldm) {
+  const int kpad = off[w.Nc];
+  const int jp = blockIdx.y;
+  const int ip = blockIdx.x * WG + threadIdx.x;
+  if (jp >= kpad || ip >= kpad) return;
+  const int i = order[ip], j = order[jp];
+  T v0 = 0, v1 = 0;
+  if (i >= 0 && j >= 0) {
+    const int si = s01(w.v_s[i]);
+    const size_t o = i + (size_t)j * w.ld;
+    v0 = (T)((w.ev[0][si] - 1.0) * (double)w.N[0][o]);
+    v1 = (T)((w.ev[1][si] - 1.0) * (double)w.N[1][o]);
+  }
+  Ms0[ip + (size_t)jp * ldm] = v0;
+  Ms1[ip + (size_t)jp * ldm] = v1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_meas_phase(View<T> w, const int* order, const int* off, T* E, int n_freq) {
+  const int kpad = off[w.Nc];
+  const int jp = blockIdx.y;
+  const int n = blockIdx.x * WG + threadIdx.x;
+  if (jp >= kpad || n >= n_freq) return;
+  const int j = order[jp];
+  double c = 0.0, s = 0.0;
+  if (j >= 0) {
+    const double wn = (2.0 * n + 1.0) * M_PI / w.beta;
+    sincos(wn * w.v_tau[j], &s, &c);
+  }
+  E[2 * ((size_t)jp * n_freq + n)] = (T)c;
+  E[2 * ((size_t)jp * n_freq + n) + 1] = (T)(-s);
+}
+
+// One wavefront per (a, b, 16-frequency tile, spin).  D^T[n][i'] =
+// sum_{j' in b} E[j'][n] Ms[i'][j'] on the matrix cores (real and imaginary
+// parts of E separately), then the row phases e^{i w_n tau_i} and the sum
+// over i' in a.
+template <typename T>
+__global__ void __launch_bounds__(64) k_meas_block(View<T> w, const int* order, const int* off, const T* Ms0,
+                                                   const T* Ms1, int ldm, const T* E, int n_freq, double* Mab0,
+                                                   double* Mab1) {
+  const int Nc = w.Nc;
+  const int ab = blockIdx.x;
+  const int a = ab / Nc, b = ab % Nc;
+  const int n0 = blockIdx.y * 16;
+  const int sp = blockIdx.z;
+  const T* Ms = sp ? Ms1 : Ms0;
+  double* Mab = sp ? Mab1 : Mab0;
+  const int lane = threadIdx.x;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ia0 = off[a], ia1 = off[a + 1], jb0 = off[b], jb1 = off[b + 1];
+  double sre[4] = {0, 0, 0, 0}, sim[4] = {0, 0, 0, 0};
+  const int na = n0 + li;   // frequency of this lane's A' operand row
+  for (int ib = ia0; ib < ia1; ib += 16) {
+    typename Mfma<T>::acc_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+    const int ip = ib + li;
+    for (int jp = jb0; jp < jb1; jp += 4) {
+      const int jk = jp + lk;
+      const T m = Ms[ip + (size_t)jk * ldm];
+      T er = 0, ei = 0;
+      if (na < n_freq) {
+        er = E[2 * ((size_t)jk * n_freq + na)];
+        ei = E[2 * ((size_t)jk * n_freq + na) + 1];
+      }
+      dr = Mfma<T>::run(er, m, dr);
+      di = Mfma<T>::run(ei, m, di);
+    }
+    // lane holds D[n = n0 + row(lane, r)][i' = ib + li]
+    const int i = order[ip];
+    if (i >= 0) {
+      const double ti = w.v_tau[i];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = n0 + Mfma<T>::row(lane, r);
+        const double wn = (2.0 * n + 1.0) * M_PI / w.beta;
+        double s, c;
+        sincos(wn * ti, &s, &c);
+        const double xr = (double)dr[r], xi = (double)di[r];
+        sre[r] += c * xr - s * xi;
+        sim[r] += c * xi + s * xr;
+      }
+    }
+  }
+  // sum over the 16 lanes that share a frequency set (li varies)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    for (int o = 1; o < 16; o <<= 1) {
+      sre[r] += __shfl_xor(sre[r], o, 64);
+      sim[r] += __shfl_xor(sim[r], o, 64);
+    }
+  }
+  if (li == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = n0 + Mfma<T>::row(lane, r);
+      if (n < n_freq) {
+        const size_t o = 2 * (((size_t)a * Nc + b) * n_freq + n);
+        Mab[o] = sre[r];
+        Mab[o + 1] = sim[r];
+      }
+    }
+  }
+}
+
+// acc[sp][K][n] += sign (1/Nc) sum_ab e^{-i K (r_a - r_b)} M(a, b; w_n).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_meas_K(View<T> w, const int* sites, const double* Kp, const double* Mab0,
+                                               const double* Mab1, int n_freq, double* acc) {
+  const int Nc = w.Nc;
+  const int n = blockIdx.x * WG + threadIdx.x;
+  const int q = blockIdx.y, sp = blockIdx.z;
+  const double sign = w.ctl->sign;
+  const double* Mab = sp ? Mab1 : Mab0;
+  if (n < n_freq) {
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < Nc; ++a)
+      for (int b = 0; b < Nc; ++b) {
+        const double ph = -(Kp[2 * q] * (double)(sites[2 * a] - sites[2 * b]) +
+                            Kp[2 * q + 1] * (double)(sites[2 * a + 1] - sites[2 * b + 1]));
+        double s, c;
+        sincos(ph, &s, &c);
+        const size_t o = 2 * (((size_t)a * Nc + b) * n_freq + n);
+        re += c * Mab[o] - s * Mab[o + 1];
+        im += c * Mab[o + 1] + s * Mab[o];
+      }
+    const size_t o = 2 * (((size_t)sp * Nc + q) * n_freq + n);
+    acc[o] += sign * re / (double)Nc;
+    acc[o + 1] += sign * im / (double)Nc;
+  }
+}
+
+// aux += [sign, sign tr(M_up)/Nc, sign tr(M_dn)/Nc]; one block per spin.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_meas_diag(View<T> w, double* aux) {
+  const int sp = blockIdx.x;
+  const double sign = w.ctl->sign;
+  __shared__ double red[WG];
+  const int k = w.ctl->k;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < k; i += WG)
+    s += (w.ev[sp][s01(w.v_s[i])] - 1.0) * (double)w.N[sp][i + (size_t)i * w.ld];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = WG / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    aux[1 + sp] += sign * red[0] / (double)w.Nc;
+    if (sp == 0) aux[0] += sign;
+  }
+}
+
+// G(K, i w_n) = G0 - G0 <M> G0 / beta and the tail-corrected G(K, tau).
+__global__ void __launch_bounds__(WG) k_finalize(int Nc, int n_freq, double beta, const double* xi, const double* acc,
+                                                 const double* aux, double* Giw, int n_tau_out, double* Gtau) {
+  const int q = blockIdx.y, sp = blockIdx.z;
+  const int x = blockIdx.x * WG + threadIdx.x;
+  const double sgn = aux[0];
+  const double e = xi[q];
+  if (x < n_freq) {
+    const double wn = (2.0 * x + 1.0) * M_PI / beta;
+    // G0 = 1 / (i w - xi) = (-xi - i w) / (xi^2 + w^2)
+    const double d = e * e + wn * wn;
+    const double gr = -e / d, gi = -wn / d;
+    const size_t o = 2 * (((size_t)sp * Nc + q) * n_freq + x);
+    const double mr = acc[o] / sgn, mi = acc[o + 1] / sgn;
+    // G0^2
+    const double g2r = gr * gr - gi * gi, g2i = 2.0 * gr * gi;
+    Giw[o] = gr - (g2r * mr - g2i * mi) / beta;
+    Giw[o + 1] = gi - (g2r * mi + g2i * mr) / beta;
+  }
+  if (Gtau && x < n_tau_out) {
+    const double tau = (x == n_tau_out - 1) ? beta : (double)x * (beta / (double)(n_tau_out - 1));
+    const double A = -(aux[1 + sp] / sgn) / beta;
+    double s = 0.0;
+    for (int n = 0; n < n_freq; ++n) {
+      const double wn = (2.0 * n + 1.0) * M_PI / beta;
+      const double d = e * e + wn * wn;
+      const double gr = -e / d, gi = -wn / d;
+      const double g2r = gr * gr - gi * gi, g2i = 2.0 * gr * gi;
+      const size_t o = 2 * (((size_t)sp * Nc + q) * n_freq + n);
+      const double mr = acc[o] / sgn, mi = acc[o + 1] / sgn;
+      const double dgr = -(g2r * mr - g2i * mi) / beta;
+      const double dgi = -(g2r * mi + g2i * mr) / beta;
+      // subtract the tail A / (i w)^2 = -A / w^2 (real)
+      const double rr = dgr + A / (wn * wn), ri = dgi;
+      double sn, cs;
+      sincos(wn * tau, &sn, &cs);
+      // Re[e^{-i w tau} (rr + i ri)] = cs rr + sn ri
+      s += cs * rr + sn * ri;
+    }
+    const double g0 = (e >= 0.0) ? -exp(-e * tau) / (1.0 + exp(-beta * e)) : -exp(e * (beta - tau)) / (exp(beta * e) + 1.0);
+    Gtau[((size_t)sp * Nc + q) * n_tau_out + x] = g0 + (2.0 / beta) * s + A * (2.0 * tau - beta) / 4.0;
+  }
+}
+
+}  // namespace dcax

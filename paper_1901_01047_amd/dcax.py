@@ -1,0 +1,268 @@
+"""Python binding of the CT-AUX walker library (include/dcax.h).
+
+Argument marshalling only: every step of the Markov chain, the updates of N,
+the refresh and the measurement run in the HIP kernels of ``libdcax.so``.
+PyTorch provides device memory (through the library's allocator callback,
+backed by torch's caching allocator) and the HIP stream.
+
+The shared library is built in-tree by ``paper_1901_01047_amd.build``; if it
+is missing, importing this module raises -- there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdcax.so")
+
+DCAX_ABI_VERSION = 1
+DCAX_FP64 = 0
+DCAX_FP32_MIXED = 1
+
+STATUS = {0: "DCAX_OK", -1: "DCAX_E_INVAL", -2: "DCAX_E_NOMEM", -3: "DCAX_E_HIP", -4: "DCAX_E_NUMERIC",
+          -5: "DCAX_E_CAPACITY", -6: "DCAX_E_TRACE", -7: "DCAX_E_STATE"}
+
+
+class DcaxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("cluster", ctypes.c_int32 * 4),
+                ("t", ctypes.c_double), ("tp", ctypes.c_double), ("U", ctypes.c_double),
+                ("beta", ctypes.c_double), ("mu", ctypes.c_double), ("K_exp", ctypes.c_double),
+                ("n_tau", ctypes.c_int32), ("precision", ctypes.c_int32), ("submatrix_k", ctypes.c_int32),
+                ("refresh_every", ctypes.c_int32), ("max_order", ctypes.c_int32), ("n_freq", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class Vertex(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("site", ctypes.c_int32), ("aux_spin", ctypes.c_int32),
+                ("tau", ctypes.c_double)]
+
+
+class Proposal(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("site", ctypes.c_int32), ("aux_spin", ctypes.c_int32),
+                ("accepted", ctypes.c_int32), ("tau", ctypes.c_double), ("id", ctypes.c_int64),
+                ("u_accept", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("proposals", ctypes.c_int64), ("accepted_insertions", ctypes.c_int64),
+                ("accepted_removals", ctypes.c_int64), ("windows", ctypes.c_int64),
+                ("flips_folded", ctypes.c_int64), ("decision_mismatches", ctypes.c_int64),
+                ("sweeps", ctypes.c_int64), ("sign", ctypes.c_double), ("fold_flops", ctypes.c_double),
+                ("fold_bytes", ctypes.c_double), ("fold_seconds", ctypes.c_double),
+                ("fold_launches", ctypes.c_int64), ("accept_seconds", ctypes.c_double),
+                ("window_seconds", ctypes.c_double), ("aborted_windows", ctypes.c_int64),
+                ("last_drift", ctypes.c_double), ("max_drift", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+PROPOSAL_DTYPE = np.dtype([("kind", np.int32), ("site", np.int32), ("aux_spin", np.int32),
+                           ("accepted", np.int32), ("tau", np.float64), ("id", np.int64),
+                           ("u_accept", np.float64)])
+VERTEX_DTYPE = np.dtype([("id", np.int64), ("site", np.int32), ("aux_spin", np.int32), ("tau", np.float64)])
+
+# exported symbols, in the order include/dcax.h declares them
+EXPORTS = ("dcax_walker_create", "dcax_walker_destroy", "dcax_sweep", "dcax_refresh", "dcax_measure_G",
+           "dcax_finalize_G", "dcax_get_order", "dcax_copy_N", "dcax_get_config", "dcax_set_config",
+           "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table", "dcax_cluster", "dcax_last_error")
+
+_lib = None
+
+
+def load():
+    """Load libdcax.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; run paper_1901_01047_amd.build.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    sig = {
+        "dcax_walker_create": [P(Params), ctypes.c_int32, P(Allocator), vp, P(vp)],
+        "dcax_walker_destroy": [vp],
+        "dcax_sweep": [vp, ctypes.c_int32, vp, ctypes.c_int64, vp],
+        "dcax_refresh": [vp, P(ctypes.c_double)],
+        "dcax_measure_G": [vp, vp, vp],
+        "dcax_finalize_G": [vp, vp, vp, vp, ctypes.c_int32, vp],
+        "dcax_get_order": [vp, P(ctypes.c_int32)],
+        "dcax_copy_N": [vp, ctypes.c_int32, vp, ctypes.c_int64, vp],
+        "dcax_get_config": [vp, vp, ctypes.c_int32, P(ctypes.c_int32)],
+        "dcax_set_config": [vp, vp, ctypes.c_int32],
+        "dcax_get_stats": [vp, P(Stats)],
+        "dcax_set_timing": [vp, ctypes.c_int32],
+        "dcax_copy_g0_table": [vp, vp],
+        "dcax_cluster": [P(Params), P(ctypes.c_int32), vp, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.dcax_last_error.argtypes = []
+    lib.dcax_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != 0:
+        raise DcaxError(st, load().dcax_last_error().decode())
+
+
+def make_params(cluster=(2, 0, 0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0, K_exp=1.0, n_tau=1000,
+                precision=DCAX_FP64, submatrix_k=16, refresh_every=0, max_order=512, n_freq=64,
+                seed=985456376):
+    p = Params()
+    p.abi_version = DCAX_ABI_VERSION
+    for i in range(4):
+        p.cluster[i] = int(cluster[i])
+    p.t, p.tp, p.U, p.beta, p.mu, p.K_exp = t, tp, U, beta, mu, K_exp
+    p.n_tau, p.precision, p.submatrix_k = n_tau, precision, submatrix_k
+    p.refresh_every, p.max_order, p.n_freq, p.seed = refresh_every, max_order, n_freq, seed
+    return p
+
+
+def cluster(params):
+    """(sites[Nc, 2] int32, momenta[Nc, 2] float64) by the library's enumeration."""
+    lib = load()
+    n = ctypes.c_int32()
+    _check(lib.dcax_cluster(ctypes.byref(params), ctypes.byref(n), None, None))
+    sites = np.zeros((n.value, 2), np.int32)
+    K = np.zeros((n.value, 2), np.float64)
+    _check(lib.dcax_cluster(ctypes.byref(params), ctypes.byref(n), sites.ctypes.data, K.ctypes.data))
+    return sites, K
+
+
+class Walker:
+    """One CT-AUX walker on the current torch device and stream."""
+
+    def __init__(self, params, device=None, stream=None):
+        import torch
+        self._torch = torch
+        lib = load()
+        self.params = params
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        dev_index = self.device.index
+        sptr = self.stream.cuda_stream
+
+        def _alloc(nbytes, ctx):
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev_index, sptr)
+
+        def _free(ptr, ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        self._allocator = Allocator(self._alloc_cb, self._free_cb, None)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.dcax_walker_create(ctypes.byref(params), 1, ctypes.byref(self._allocator),
+                                          ctypes.c_void_p(sptr), ctypes.byref(h)))
+        self._h = h
+        sites, K = cluster(params)
+        self.Nc = len(sites)
+        self.sites, self.K = sites, K
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().dcax_walker_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- chain ---------------------------------------------------------
+    def sweep(self, n=1):
+        _check(load().dcax_sweep(self._h, int(n), None, 0, None))
+
+    def replay(self, records):
+        """Replay a structured array of PROPOSAL_DTYPE; returns the ratios."""
+        rec = np.ascontiguousarray(records, dtype=PROPOSAL_DTYPE)
+        ratios = np.zeros(len(rec), np.float64)
+        _check(load().dcax_sweep(self._h, 0, rec.ctypes.data, len(rec), ratios.ctypes.data))
+        return ratios
+
+    def refresh(self):
+        d = ctypes.c_double()
+        _check(load().dcax_refresh(self._h, ctypes.byref(d)))
+        return d.value
+
+    # -- configuration -------------------------------------------------
+    @property
+    def order(self):
+        k = ctypes.c_int32()
+        _check(load().dcax_get_order(self._h, ctypes.byref(k)))
+        return k.value
+
+    def set_config(self, site, tau, aux_spin, ids=None):
+        k = len(site)
+        v = np.zeros(k, VERTEX_DTYPE)
+        v["site"], v["tau"], v["aux_spin"] = site, tau, aux_spin
+        v["id"] = np.arange(k) if ids is None else ids
+        _check(load().dcax_set_config(self._h, v.ctypes.data if k else None, k))
+
+    def get_config(self):
+        k = self.order
+        v = np.zeros(max(k, 1), VERTEX_DTYPE)
+        kk = ctypes.c_int32()
+        _check(load().dcax_get_config(self._h, v.ctypes.data, len(v), ctypes.byref(kk)))
+        return v[:kk.value]
+
+    def copy_N(self, spin):
+        """(ids, N) in canonical (id ascending) order, float64."""
+        k = self.order
+        out = np.zeros((k, k), np.float64)
+        ids = np.zeros(k, np.int64)
+        if k:
+            _check(load().dcax_copy_N(self._h, int(spin), out.ctypes.data, k, ids.ctypes.data))
+        return ids, out
+
+    def stats(self):
+        s = Stats()
+        _check(load().dcax_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def set_timing(self, on=True):
+        _check(load().dcax_set_timing(self._h, 1 if on else 0))
+
+    def g0_table(self):
+        t = np.zeros((self.Nc, self.params.n_tau), np.float64)
+        _check(load().dcax_copy_g0_table(self._h, t.ctypes.data))
+        return t
+
+    # -- measurement ---------------------------------------------------
+    def new_accumulator(self):
+        torch = self._torch
+        acc = torch.zeros((2, self.Nc, max(self.params.n_freq, 1), 2), dtype=torch.float64, device=self.device)
+        aux = torch.zeros(3, dtype=torch.float64, device=self.device)
+        return acc, aux
+
+    def measure(self, acc, aux):
+        _check(load().dcax_measure_G(self._h, ctypes.c_void_p(acc.data_ptr()), ctypes.c_void_p(aux.data_ptr())))
+
+    def finalize(self, acc, aux, n_tau_out=0):
+        torch = self._torch
+        Giw = torch.zeros_like(acc)
+        Gt = torch.zeros((2, self.Nc, max(n_tau_out, 1)), dtype=torch.float64, device=self.device)
+        _check(load().dcax_finalize_G(self._h, ctypes.c_void_p(acc.data_ptr()), ctypes.c_void_p(aux.data_ptr()),
+                                      ctypes.c_void_p(Giw.data_ptr()), int(n_tau_out),
+                                      ctypes.c_void_p(Gt.data_ptr()) if n_tau_out else None))
+        return Giw, (Gt if n_tau_out else None)

@@ -1,0 +1,121 @@
+"""The HIP walker's own Markov chain (counter-based generator), on MI355X.
+
+Statistical pins, as for the oracle:
+* U = 0: gamma = 0, every ratio is K/(k+1) or k/K, the order is Poisson(K);
+* Hubbard atom: the order follows the two-Poisson mixture
+  p_k ~ [K^k + (K + beta U/2)^k] / k!;
+* 2x2 cluster at half filling: spin-averaged G(K, i w_n) and G(K, tau) against
+  exact diagonalisation (criterion: at most max(1, 1% of n) points beyond
+  3 sigma, none beyond 4.5 sigma);
+* N stays within 1e-10 of the direct inverse over thousands of windows.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import ed, geometry, measure, stats  # noqa: E402
+from paper_1901_01047_amd import dcax  # noqa: E402
+from paper_1901_01047_amd.workloads import params_kwargs  # noqa: E402
+from tests.ctaux_cases import model  # noqa: E402
+
+
+def order_samples(w, n_sweeps):
+    ks = []
+    for _ in range(n_sweeps):
+        w.sweep(1)
+        ks.append(w.order)
+    return np.array(ks)
+
+
+def test_free_limit_poisson():
+    print("[chain] U=0 Poisson", flush=True)
+    p = dcax.make_params(cluster=(2, 0, 0, 2), U=0.0, beta=2.0, K_exp=3.0, n_tau=200, submatrix_k=8,
+                         max_order=128, n_freq=0, seed=17)
+    w = dcax.Walker(p)
+    order_samples(w, 200)
+    ks = order_samples(w, 4000)
+    assert abs(ks.mean() - 3.0) < 0.15 and abs(ks.var() - 3.0) < 0.5
+    ids, N = w.copy_N(0)
+    assert np.allclose(N, np.eye(len(ids)), atol=1e-14)
+    w.close()
+
+
+def test_atom_order_distribution():
+    print("[chain] atom order law", flush=True)
+    U, beta, K = 4.0, 2.0, 1.0
+    p = dcax.make_params(cluster=(1, 0, 0, 1), t=0.0, U=U, beta=beta, K_exp=K, n_tau=64, submatrix_k=4,
+                         max_order=128, n_freq=0, seed=23)
+    w = dcax.Walker(p)
+    order_samples(w, 500)
+    ks = order_samples(w, 30000)
+    kmax = 25
+    kk = np.arange(kmax + 1)
+    a, b = K, K + beta * U / 2
+    logp = np.logaddexp(kk * np.log(a), kk * np.log(b)) - np.array([math.lgamma(x + 1) for x in kk])
+    pk = np.exp(logp - logp.max())
+    pk /= pk.sum()
+    B = 40
+    blocks = ks[: (len(ks) // B) * B].reshape(B, -1)
+    hist = np.array([np.bincount(np.minimum(x, kmax), minlength=kmax + 1) / len(x) for x in blocks])
+    est, err = hist.mean(0), hist.std(0, ddof=1) / np.sqrt(B)
+    z = np.abs(est - pk) / np.maximum(err, 1e-4)
+    print("  max z", z[:14].max(), flush=True)
+    assert z[:14].max() < 4.5
+    w.close()
+
+
+def test_2x2_green_function_vs_ed():
+    print("[chain] 2x2 vs ED", flush=True)
+    name = "2x2_U4_b5"
+    nf = 512
+    w = dcax.Walker(dcax.make_params(**params_kwargs(name, n_freq=nf, refresh_every=50)))
+    m = model(name)
+    w.sweep(100)
+    B, per = 32, 100
+    accs = []
+    for b in range(B):
+        acc, aux = w.new_accumulator()
+        for _ in range(per):
+            w.sweep(1)
+            w.measure(acc, aux)
+        a = acc.cpu().numpy()
+        accs.append((a[..., 0] + 1j * a[..., 1], aux.cpu().numpy().copy()))
+    sM = np.array([x[0] for x in accs])          # (B, 2, Nc, nf) bin sums of s*M
+    sA = np.array([x[1] for x in accs])          # (B, 3)
+    e = ed.ED(geometry.hopping_matrix(m.a1, m.a2), U=m.U, mu=m.mu, beta=m.beta)
+    ph = ed.momentum_phases(m.sites, m.K)
+    taus = np.linspace(0.05, m.beta - 0.05, 20)
+
+    def G_of(sMb, sAb):
+        Mavg = sMb / sAb[0]
+        g_iw = np.mean([measure.finalize_G_iw(m, Mavg[sp], 24) for sp in range(2)], axis=0)
+        g_t = np.mean([measure.G_tau_from_iw(m, Mavg[sp], np.full(m.Nc, sAb[1 + sp] / sAb[0]), nf, taus)
+                       for sp in range(2)], axis=0)
+        return g_iw, g_t
+
+    tot_M, tot_A = sM.sum(0), sA.sum(0)
+    g_iw, g_t = G_of(tot_M[..., :nf], tot_A)
+    loo = [G_of(tot_M - sM[b], tot_A - sA[b]) for b in range(B)]
+    li = np.array([x[0] for x in loo])
+    lt = np.array([x[1] for x in loo])
+    err_re = np.sqrt((B - 1) / B * ((li.real - li.real.mean(0)) ** 2).sum(0))
+    err_im = np.sqrt((B - 1) / B * ((li.imag - li.imag.mean(0)) ** 2).sum(0))
+    err_t = np.sqrt((B - 1) / B * ((lt - lt.mean(0)) ** 2).sum(0))
+    zs = []
+    for iK in range(2):     # (pi,pi) and (0,pi) mirror these at half filling
+        want = e.G_iw(ph[iK], 0, 24)
+        zs.append(np.abs(g_iw[iK].real - want.real) / np.maximum(err_re[iK], 1e-12))
+        zs.append(np.abs(g_iw[iK].imag - want.imag) / err_im[iK])
+        zs.append(np.abs(g_t[iK] - e.G_tau(ph[iK], 0, taus)) / err_t[iK])
+    z = np.concatenate(zs)
+    n_out = int((z >= 3).sum())
+    print(f"  points {len(z)}, beyond 3 sigma {n_out}, max z {z.max():.2f}", flush=True)
+    assert n_out <= max(1, round(0.01 * len(z))) and z.max() < 4.5
+    st = w.stats()
+    assert st["sign"] == 1.0
+    assert w.refresh() < 1e-10
+    w.close()

@@ -1,0 +1,209 @@
+"""Parity of the HIP path with the oracle, through the C ABI (MI355X).
+
+* G0(r, tau) table against the oracle's table;
+* refresh (FP64 Gauss-Jordan) against direct inversion;
+* replay of oracle traces with forced decisions: every ratio within 1e-10
+  relative, N normwise within 1e-10, same vertex ids, no decision on the
+  other side of |R|;
+* the measurement M(K, i w_n) of a fixed configuration, and the finalisation
+  G = G0 - G0 <M> G0 / beta, against the oracle's direct sums;
+* error paths that the host can force (unknown replay id, latched state).
+
+Tolerances (FP64): ratios |R - R_orc| <= 1e-10 |R_orc|; N
+max|N - N_orc| <= 1e-10 max|N_orc| (rows of N span e^{+-gamma}, so the
+elementwise relative error is ill-posed); measurement and finalisation
+1e-12 relative to the largest element (direct sums of O(k^2 N_w) terms).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import ctaux, measure  # noqa: E402
+from paper_1901_01047_amd import dcax  # noqa: E402
+from paper_1901_01047_amd.workloads import CONFIGS, params_kwargs  # noqa: E402
+from tests.ctaux_cases import model, oracle_trace  # noqa: E402
+
+
+def walker(name, **over):
+    p = dcax.make_params(**params_kwargs(name, **over))
+    return dcax.Walker(p)
+
+
+def rel_norm(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("name", ["2x2_U4_b5", "4x4_U4_b10", "6x6_U6_b20"])
+def test_g0_table(name):
+    print(f"[g0 table] {name}", flush=True)
+    m = model(name)
+    w = walker(name, max_order=64)
+    t = w.g0_table()
+    assert np.max(np.abs(t - m.table)) < 1e-13
+    w.close()
+
+
+@pytest.mark.parametrize("name,k", [("2x2_U4_b5", 30), ("4x4_U4_b10", 300), ("4x4_U4_b10", 77)])
+def test_refresh_equals_direct_inverse(name, k):
+    print(f"[refresh] {name} k={k}", flush=True)
+    m = model(name)
+    ow = ctaux.Walker(m, seed=7)
+    ow.random_config(k)
+    w = walker(name)
+    w.set_config(ow.r, ow.t, ow.s, ow.id)
+    assert w.order == k
+    for sp in range(2):
+        ids, N = w.copy_N(sp)
+        ids_o, Nu, Nd = ow.canonical()
+        assert np.array_equal(ids, ids_o)
+        assert rel_norm(N, Nu if sp == 0 else Nd) < 1e-12
+    assert w.stats()["sign"] == ow.sign
+    assert w.refresh() < 1e-12
+    w.close()
+
+
+REPLAY_CASES = [
+    # name, k_s, initial order, warm-up sweeps, recorded proposals
+    ("2x2_U4_b5", 16, 20, 30, 800),
+    ("2x2_U4_b5", 1, 20, 30, 120),
+    ("2x2_U4_b5", 64, 20, 30, 800),
+    ("4x4_U4_b10", 32, 280, 3, 700),
+    ("4x4_U4_b10", 64, 280, 3, 700),
+]
+
+
+@pytest.mark.parametrize("name,k_s,k_init,warm,n_rec", REPLAY_CASES)
+def test_replay_parity(name, k_s, k_init, warm, n_rec):
+    print(f"[replay] {name} k_s={k_s} k_init={k_init} n={n_rec}", flush=True)
+    m = model(name)
+    init, rec, ratios_o, ow = oracle_trace(m, seed=CONFIGS[name]["seed"], k_s=k_s, init_order=k_init,
+                                           warm_sweeps=warm, rec_proposals=n_rec)
+    w = walker(name, submatrix_k=k_s)
+    w.set_config(*init)
+    ratios = w.replay(rec)
+    noop = (rec["kind"] == 1) & (rec["id"] < 0)
+    good = ~noop
+    rel = np.abs(ratios[good] - ratios_o[good]) / np.abs(ratios_o[good])
+    print(f"  ratio rel err: max {rel.max():.2e} median {np.median(rel):.2e}", flush=True)
+    assert rel.max() < 1e-10
+    assert np.all(ratios[noop] == 0.0)
+    ids_o, Nu, Nd = ow.canonical()
+    for sp, No in ((0, Nu), (1, Nd)):
+        ids, N = w.copy_N(sp)
+        assert np.array_equal(ids, ids_o)
+        e = rel_norm(N, No)
+        print(f"  N[{sp}] normwise err {e:.2e} (k={len(ids)})", flush=True)
+        assert e < 1e-10
+    st = w.stats()
+    assert st["decision_mismatches"] == 0
+    assert st["accepted_insertions"] == int(((rec["kind"] == 0) & (rec["accepted"] == 1)).sum())
+    assert st["sign"] == ow.sign
+    assert w.refresh() < 1e-10
+    w.close()
+
+
+def test_replay_from_empty_configuration():
+    print("[replay] empty start", flush=True)
+    m = model("2x2_U4_b5")
+    ow = ctaux.Walker(m, seed=3, k_s=8, record=True)
+    for _ in range(300):
+        ow.step()
+    from tests.ctaux_cases import records
+    rec, ratios_o = records(ow.trace)
+    assert ((rec["kind"] == 1) & (rec["id"] < 0)).any()      # removals at k = 0 occur
+    w = walker("2x2_U4_b5", submatrix_k=8)
+    ratios = w.replay(rec)
+    good = ~((rec["kind"] == 1) & (rec["id"] < 0))
+    assert np.max(np.abs(ratios[good] - ratios_o[good]) / np.abs(ratios_o[good])) < 1e-10
+    ids_o, Nu, _ = ow.canonical()
+    ids, N = w.copy_N(0)
+    assert np.array_equal(ids, ids_o) and rel_norm(N, Nu) < 1e-10
+    w.close()
+
+
+@pytest.mark.parametrize("name,k", [("2x2_U4_b5", 25), ("4x4_U4_b10", 300)])
+def test_measurement_matches_direct_sums(name, k):
+    print(f"[measure] {name} k={k}", flush=True)
+    m = model(name)
+    ow = ctaux.Walker(m, seed=11)
+    ow.random_config(k)
+    nf = CONFIGS[name]["n_freq"]
+    w = walker(name)
+    w.set_config(ow.r, ow.t, ow.s, ow.id)
+    acc, aux = w.new_accumulator()
+    w.measure(acc, aux)
+    w.measure(acc, aux)          # accumulates: twice the single measurement
+    got = acc.cpu().numpy()
+    got = got[..., 0] + 1j * got[..., 1]
+    for sp in range(2):
+        M = measure.M_matrix(m, ow, sp)
+        want = 2 * ow.sign * measure.M_K_iw(m, ow.r, ow.t, M, nf)
+        e = np.max(np.abs(got[sp] - want)) / np.max(np.abs(want))
+        print(f"  spin {sp}: rel err {e:.2e}", flush=True)
+        assert e < 1e-12
+        d = aux.cpu().numpy()[1 + sp]
+        assert abs(d - 2 * ow.sign * np.trace(M) / m.Nc) < 1e-12 * max(1.0, abs(d))
+    assert aux.cpu().numpy()[0] == 2 * ow.sign
+    w.close()
+
+
+def test_finalize_matches_oracle():
+    print("[finalize]", flush=True)
+    name = "2x2_U4_b5"
+    m = model(name)
+    nf = CONFIGS[name]["n_freq"]
+    w = walker(name)
+    rng = np.random.default_rng(5)
+    Mk = (rng.normal(size=(2, m.Nc, nf)) + 1j * rng.normal(size=(2, m.Nc, nf))) * 0.3
+    aux = np.array([0.8, 0.21, -0.13])
+    acc = np.stack([Mk.real, Mk.imag], axis=-1) * aux[0]
+    acc_t = torch.tensor(acc, device="cuda")
+    aux_t = torch.tensor(aux, device="cuda")
+    taus = np.linspace(0.0, m.beta, 41)
+    Giw, Gt = w.finalize(acc_t, aux_t, n_tau_out=41)
+    Giw = Giw.cpu().numpy()
+    Giw = Giw[..., 0] + 1j * Giw[..., 1]
+    Gt = Gt.cpu().numpy()
+    for sp in range(2):
+        want = measure.finalize_G_iw(m, Mk[sp], nf)
+        assert np.max(np.abs(Giw[sp] - want)) < 1e-13
+        want_t = measure.G_tau_from_iw(m, Mk[sp], np.full(m.Nc, aux[1 + sp] / aux[0]), nf, taus)
+        assert np.max(np.abs(Gt[sp] - want_t)) < 1e-11
+    w.close()
+
+
+def test_unknown_replay_id_latches_trace_error():
+    print("[errors] unknown id", flush=True)
+    m = model("2x2_U4_b5")
+    ow = ctaux.Walker(m, seed=1)
+    ow.random_config(10)
+    w = walker("2x2_U4_b5")
+    w.set_config(ow.r, ow.t, ow.s, ow.id)
+    rec = np.zeros(3, dcax.PROPOSAL_DTYPE)
+    rec["kind"] = 1
+    rec["id"] = [3, 12345, 4]
+    rec["u_accept"] = 0.5
+    with pytest.raises(dcax.DcaxError) as e:
+        w.replay(rec)
+    assert e.value.status == -6
+    with pytest.raises(dcax.DcaxError) as e:
+        w.sweep(1)
+    assert e.value.status == -7
+    w.set_config(ow.r, ow.t, ow.s, ow.id)    # clears the latched error
+    w.sweep(1)
+    w.close()
+
+
+def test_invalid_replay_records_rejected_on_host():
+    w = walker("2x2_U4_b5")
+    rec = np.zeros(1, dcax.PROPOSAL_DTYPE)
+    rec["kind"] = 0
+    rec["site"] = 9           # outside the 4-site cluster
+    rec["aux_spin"] = 1
+    with pytest.raises(dcax.DcaxError) as e:
+        w.replay(rec)
+    assert e.value.status == -1
+    w.sweep(1)                 # nothing was enqueued; the walker is still usable
+    w.close()
