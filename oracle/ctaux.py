@@ -118,7 +118,7 @@ class Walker:
             A = n_inverse(self.m, self.r, self.t, self.s, spin)
             self.N[spin] = np.linalg.inv(A) if k else np.zeros((0, 0))
             if k:
-                sgn *= np.sign(np.linalg.det(A))
+                sgn *= np.linalg.slogdet(A)[0]
         self.sign = sgn
 
     def random_config(self, k):
@@ -242,7 +242,7 @@ class Walker:
         sgn = 1.0
         for spin in range(2):
             if self.k:
-                sgn *= np.sign(np.linalg.det(n_inverse(self.m, self.r, self.t, self.s, spin)))
+                sgn *= np.linalg.slogdet(n_inverse(self.m, self.r, self.t, self.s, spin))[0]
         return sgn
 
     def canonical(self):
