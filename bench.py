@@ -1,0 +1,181 @@
+"""Benchmark: accepted vertex updates per second of the CT-AUX walker.
+
+A step is one pass of the whole hot path: one Markov-chain sweep (submatrix
+windows: gathers, candidate GEMM, FP64 accept loop, rank-m fold, compaction),
+one measurement of M(K, i w_n) accumulated on the GPU, and, every
+`refresh_every` sweeps, the FP64 refresh of N.  The workload is the 4x4
+Hubbard cluster (U = 4, beta = 10, n ~ 0.95, one walker, k_s = 32, 256
+Matsubara frequencies), synthetic inputs.  The same workload runs in FP64 and
+in the FP32-mixed mode; `value` is the FP64 figure.
+
+Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBs": 8000.0, "fp64_mfma_TFs": 78.6, "fp32_mfma_TFs": 157.3}
+WORKLOAD = "4x4_U4_b10"
+
+
+def initial_config(rng, Nc, beta, k):
+    """Seeded random vertices: sites, times and auxiliary spins uniform."""
+    import numpy as np
+    site = rng.integers(0, Nc, size=k).astype(np.int32)
+    tau = rng.random(k) * beta
+    s = np.where(rng.random(k) < 0.5, 1, -1).astype(np.int32)
+    return site, tau, s
+
+
+def roofline(stats0, stats1, precision):
+    flops = stats1["fold_flops"] - stats0["fold_flops"]
+    nbytes = stats1["fold_bytes"] - stats0["fold_bytes"]
+    secs = stats1["fold_seconds"] - stats0["fold_seconds"]
+    launches = stats1["fold_launches"] - stats0["fold_launches"]
+    if secs <= 0 or launches <= 0:
+        return None
+    peak_tf = PEAK["fp64_mfma_TFs"] if precision == "fp64" else PEAK["fp32_mfma_TFs"]
+    ai = flops / max(nbytes, 1.0)
+    ridge = peak_tf * 1e12 / (PEAK["hbm_GBs"] * 1e9)
+    if ai < ridge:
+        achieved = nbytes / secs / 1e9
+        out = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+               "frac": achieved / PEAK["hbm_GBs"]}
+    else:
+        achieved = flops / secs / 1e12
+        out = {"bound": "mfma", "achieved": achieved, "peak": peak_tf, "unit": "TFLOP/s",
+               "frac": achieved / peak_tf}
+    out.update({"traffic": None, "kernel": "k_fold", "launches": launches,
+                "avg_launch_us": secs / launches * 1e6, "flops_per_launch": flops / launches,
+                "bytes_per_launch": nbytes / launches, "tflops": flops / secs / 1e12,
+                "frac_of_mfma_peak": flops / secs / 1e12 / peak_tf})
+    return out
+
+
+def run_gpu(precision, steps, warmup, seed_offset=0):
+    import numpy as np
+    import torch
+    from paper_1901_01047_amd import dcax
+    from paper_1901_01047_amd.workloads import CONFIGS, params_kwargs
+    cfg = CONFIGS[WORKLOAD]
+    prec = dcax.DCAX_FP64 if precision == "fp64" else dcax.DCAX_FP32_MIXED
+    p = dcax.make_params(**params_kwargs(WORKLOAD, seed=cfg["seed"] + seed_offset), precision=prec,
+                         refresh_every=32)
+    w = dcax.Walker(p)
+    rng = np.random.default_rng(cfg["seed"] + 100 + seed_offset)
+    w.set_config(*initial_config(rng, w.Nc, cfg["beta"], 280))
+    acc, aux = w.new_accumulator()
+    for _ in range(warmup):
+        w.sweep(1)
+        w.measure(acc, aux)
+    w.set_timing(True)
+    torch.cuda.synchronize()
+    s0 = w.stats()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        w.sweep(1)
+        w.measure(acc, aux)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s1 = w.stats()
+    dt = t1 - t0
+    acc_upd = (s1["accepted_insertions"] - s0["accepted_insertions"]) + \
+        (s1["accepted_removals"] - s0["accepted_removals"])
+    props = s1["proposals"] - s0["proposals"]
+    windows = s1["windows"] - s0["windows"]
+    res = {
+        "value": acc_upd / dt, "seconds": dt, "ms_per_step": dt / steps * 1e3,
+        "proposals_per_s": props / dt, "acceptance": acc_upd / max(props, 1),
+        "mean_order": w.order, "windows": windows,
+        "mean_fold_rank": (s1["flips_folded"] - s0["flips_folded"]) / max(windows, 1),
+        "roofline": roofline(s0, s1, precision),
+        "kernel_seconds": {"fold": s1["fold_seconds"] - s0["fold_seconds"],
+                           "accept_loop": s1["accept_seconds"] - s0["accept_seconds"],
+                           "windows_total": s1["window_seconds"] - s0["window_seconds"]},
+        "sign": s1["sign"], "refresh_max_drift": s1["max_drift"],
+        "aborted_windows": s1["aborted_windows"] - s0["aborted_windows"],
+    }
+    cfg_out = w.get_config()
+    w.close()
+    return res, cfg_out
+
+
+def cpu_baseline(cfg_vertices, seconds=15.0):
+    """The oracle, as it stands, timed on the host from the GPU's configuration."""
+    import numpy as np
+    from oracle import ctaux
+    from paper_1901_01047_amd.workloads import CONFIGS
+    c = CONFIGS[WORKLOAD]
+    cl = c["cluster"]
+    m = ctaux.Model(a1=(cl[0], cl[1]), a2=(cl[2], cl[3]), t=c["t"], tp=c["tp"], U=c["U"], beta=c["beta"],
+                    mu=c["mu"], K_exp=c["K_exp"], n_tau=c["n_tau"])
+    w = ctaux.Walker(m, seed=c["seed"] + 7, k_s=c["submatrix_k"])
+    w.set_config(cfg_vertices["site"], cfg_vertices["tau"], cfg_vertices["aux_spin"])
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    a0 = w.n_acc_ins + w.n_acc_rem
+    p0 = w.n_prop
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        w.step()
+        n += 1
+    dt = time.perf_counter() - t0
+    acc = w.n_acc_ins + w.n_acc_rem - a0
+    return {"value": acc / dt, "unit": "updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n} single-vertex proposals ({w.n_prop - p0}) of the {WORKLOAD} chain from the GPU "
+                      f"walker's equilibrated configuration (order {len(cfg_vertices)}), {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-only", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(walkers are independent chains: see DESIGN.md for how the path shards)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_1901_01047_amd import dcax
+    dcax.load()
+    from paper_1901_01047_amd.workloads import CONFIGS
+    c = CONFIGS[WORKLOAD]
+    r64, cfg_v = run_gpu("fp64", args.steps, args.warmup)
+    out = {
+        "metric": "accepted vertex updates/s (CT-AUX walker, FP64) + N-update fold TFLOP/s (% roofline)",
+        "value": r64["value"], "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{WORKLOAD}: 4x4 periodic Hubbard cluster, t=1, U=4, beta=10, "
+                               f"mu={c['mu']} (n~0.95), K=1, 1 walker, k_s={c['submatrix_k']}, "
+                               f"{c['n_freq']} Matsubara freqs, refresh every 32 sweeps",
+                   "step": "1 sweep + 1 measurement of M(K,iw_n)"},
+        "roofline": r64["roofline"],
+        "fp64": {k: v for k, v in r64.items() if k != "roofline"},
+    }
+    if not args.fp64_only:
+        r32, _ = run_gpu("mixed", args.steps, args.warmup)
+        out["fp32_mixed"] = r32
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg_v, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

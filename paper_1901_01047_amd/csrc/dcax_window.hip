@@ -682,7 +682,12 @@ __global__ void __launch_bounds__(WG) k_fold_prep(View<T> w, const T* R0, const 
   __shared__ int e_s[KS_MAX], row_s[KS_MAX], cand_s[KS_MAX], slot_s[KS_MAX], ins_s[KS_MAX];
   __shared__ double f_s[KS_MAX];
   const int t = threadIdx.x;
-  for (int idx = t; idx < m * m; idx += WG) gi_s[(idx / m) * KS_MAX + idx % m] = w.ginv[sp][(idx / m) * KS_MAX + idx % m];
+  // the product below runs over all KS_MAX columns: entries beyond m must be
+  // zero, not whatever an earlier kernel left in LDS
+  for (int idx = t; idx < KS_MAX * KS_MAX; idx += WG) {
+    const int a = idx / KS_MAX, b = idx % KS_MAX;
+    gi_s[idx] = (a < m && b < m) ? w.ginv[sp][idx] : 0.0;
+  }
   if (t < m) {
     const int e = w.S[t];
     e_s[t] = e;
