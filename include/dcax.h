@@ -114,7 +114,8 @@ typedef struct {
   uint64_t seed;           /* "seed" of the walker's counter-based generator */
 } dcax_params;
 
-/* Counters since creation or the last dcax_set_config. */
+/* Counters since creation or the last dcax_set_config (timings and drifts
+ * are per handle). */
 typedef struct {
   int64_t proposals;
   int64_t accepted_insertions;
@@ -135,36 +136,45 @@ typedef struct {
   double max_drift;         /* largest such drift */
 } dcax_stats;
 
-/* Create a walker: copies the parameters, builds the cluster tables and the
- * G0(r, tau) table on the GPU (Sec. 2.1's bare propagator of the isolated
- * cluster) and allocates memory for max_order.  The configuration is empty.
- * n_walkers must be 1.  `stream` is a hipStream_t (NULL: the default stream). */
+/* Create a batch of n_walkers independent walkers (Markov chains; Sec. 3.1,
+ * "Parallelization": all walkers of a process on its GPU).  p points to
+ * n_walkers parameter sets, which may differ in every field except
+ * precision.  Copies the parameters, builds each walker's cluster tables and
+ * G0(r, tau) table on the GPU (the bare propagator of the isolated cluster,
+ * Sec. 2.1) and allocates memory for its max_order.  Configurations start
+ * empty.  Every later call covers the whole batch in one launch per kernel.
+ * `stream` is a hipStream_t (NULL: the default stream). */
 dcax_status dcax_walker_create(const dcax_params* p, int32_t n_walkers, const dcax_allocator* a,
                                void* stream, dcax_walker* out);
 dcax_status dcax_walker_destroy(dcax_walker w);
 
 /* Run Markov-chain proposals (Sec. 2.3, Metropolis insertion/removal fused
  * into submatrix updates of at most submatrix_k proposals).
- *   replay == NULL: n_sweeps sweeps from the walker's own generator; a sweep is
- *     max(k, 1) proposals rounded up to a multiple of submatrix_k, k taken at
- *     the sweep's start.  N is refreshed every refresh_every sweeps.
- *   replay != NULL: the n_replay records are replayed in order with forced
- *     decisions (n_sweeps is ignored); ratio_out (nullable, length n_replay)
- *     receives the library's full acceptance ratio R for each record. */
+ *   replay == NULL: n_sweeps sweeps of every walker from its own generator; a
+ *     sweep is max(k, 1) proposals rounded up to a multiple of submatrix_k, k
+ *     taken at the sweep's start.  N is refreshed every refresh_every sweeps
+ *     (walker 0's parameter).
+ *   replay != NULL (single-walker handles only): the n_replay records are
+ *     replayed in order with forced decisions (n_sweeps is ignored);
+ *     ratio_out (nullable, length n_replay) receives the library's full
+ *     acceptance ratio R for each record. */
 dcax_status dcax_sweep(dcax_walker w, int32_t n_sweeps, const dcax_proposal* replay,
                        int64_t n_replay, double* ratio_out);
 
-/* Rebuild N_sigma = [e^V - g (e^V - 1)]^{-1} from scratch in FP64 (gathers
- * plus Gauss-Jordan inversion with partial pivoting).  drift_out (nullable)
- * receives max|N_before - N_after| / max|N_after| over both spins. */
+/* Rebuild N_sigma = [e^V - g (e^V - 1)]^{-1} of every walker from scratch in
+ * FP64 (gathers plus Gauss-Jordan inversion with partial pivoting).
+ * drift_out (nullable) receives max|N_before - N_after| / max|N_after|, the
+ * largest over spins and walkers. */
 dcax_status dcax_refresh(dcax_walker w, double* drift_out);
 
-/* Accumulate the measurement of the current configuration (Sec. 2.3):
- *   acc_dev (complex128 [2 spins][Nc momenta][n_freq], interleaved re, im)
- *     += sign * M_sigma(K, i w_n), with
+/* Accumulate the measurement of every walker's configuration (Sec. 2.3):
+ *   acc_dev holds one block per walker, in walker order, each complex128
+ *   [2 spins][Nc momenta][max(n_freq, 1)] (interleaved re, im), so walker i's
+ *   block starts 4 sum_{j<i} Nc_j max(n_freq_j, 1) doubles in;
+ *   each block += sign * M_sigma(K, i w_n), with
  *     M_sigma(K, i w_n) = (1/Nc) sum_ij e^{i (w_n tau_i - K r_i)} [(e^V - 1) N]_ij
  *                                        e^{-i (w_n tau_j - K r_j)};
- *   aux_dev (3 doubles) += [sign, sign * (1/Nc) tr M_up, sign * (1/Nc) tr M_down].
+ *   aux_dev ([n_walkers][3] doubles) += [sign, sign (1/Nc) tr M_up, sign (1/Nc) tr M_down].
  * The trace terms are the equal-time coefficient of G's 1/(i w)^2 tail. */
 dcax_status dcax_measure_G(dcax_walker w, double* acc_dev, double* aux_dev);
 
@@ -172,29 +182,31 @@ dcax_status dcax_measure_G(dcax_walker w, double* acc_dev, double* aux_dev);
  * G(K, tau) on n_tau_out points tau_l = l beta / (n_tau_out - 1) (l = 0 is 0+,
  * the last point beta-) from the frequency data with the 1/(i w)^2 tail
  * removed and added back in closed form.  Inputs as accumulated by
- * dcax_measure_G; outputs (device): Giw_dev complex128 [2][Nc][n_freq],
- * Gtau_dev double [2][Nc][n_tau_out] (nullable when n_tau_out == 0). */
+ * dcax_measure_G; outputs (device): Giw_dev in the layout of acc_dev,
+ * Gtau_dev double, one [2][Nc][n_tau_out] block per walker in walker order
+ * (nullable when n_tau_out == 0). */
 dcax_status dcax_finalize_G(dcax_walker w, const double* acc_dev, const double* aux_dev,
                             double* Giw_dev, int32_t n_tau_out, double* Gtau_dev);
 
-/* Introspection and checkpointing. */
-dcax_status dcax_get_order(dcax_walker w, int32_t* k);
+/* Introspection and checkpointing; `walker` indexes the batch (0-based). */
+dcax_status dcax_get_order(dcax_walker w, int32_t walker, int32_t* k);
 /* Copy N_spin in canonical order (vertex id ascending) into host[ld * k];
  * ids_host (nullable) receives the k ids in that order.  FP32 walkers are
  * widened to double. */
-dcax_status dcax_copy_N(dcax_walker w, int32_t spin, double* host, int64_t ld, int64_t* ids_host);
-dcax_status dcax_get_config(dcax_walker w, dcax_vertex* host, int32_t cap, int32_t* k);
+dcax_status dcax_copy_N(dcax_walker w, int32_t walker, int32_t spin, double* host, int64_t ld, int64_t* ids_host);
+dcax_status dcax_get_config(dcax_walker w, int32_t walker, dcax_vertex* host, int32_t cap, int32_t* k);
 /* Install a configuration (ids must be distinct and >= 0) and rebuild N by
  * dcax_refresh; clears a latched error and the counters. */
-dcax_status dcax_set_config(dcax_walker w, const dcax_vertex* host, int32_t k);
-dcax_status dcax_get_stats(dcax_walker w, dcax_stats* out);
+dcax_status dcax_set_config(dcax_walker w, int32_t walker, const dcax_vertex* host, int32_t k);
+/* walker = -1 sums the counters over the batch (sign: walker 0's). */
+dcax_status dcax_get_stats(dcax_walker w, int32_t walker, dcax_stats* out);
 /* Time the fold and accept kernels and whole windows with HIP events on the
  * walker's stream (on != 0) or stop timing (on == 0).  Timings accumulate into
  * dcax_stats; they cost two events per timed launch. */
 dcax_status dcax_set_timing(dcax_walker w, int32_t on);
 /* The G0(r, tau) table the walker uses, [Nc][n_tau], standard sign convention
  * G0 = -<T c c+>. */
-dcax_status dcax_copy_g0_table(dcax_walker w, double* host);
+dcax_status dcax_copy_g0_table(dcax_walker w, int32_t walker, double* host);
 /* Cluster geometry: sites [Nc][2] (int32) and momenta [Nc][2] (double). */
 dcax_status dcax_cluster(const dcax_params* p, int32_t* n_sites, int32_t* sites, double* momenta);
 

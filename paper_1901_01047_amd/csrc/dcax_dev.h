@@ -42,6 +42,7 @@ struct Ctl {
   long long n_abort;   // windows closed early by a carried removal
   double fold_bytes;   // algorithmic bytes of the folds (N read and written)
   long long n_folds;   // windows with a non-empty fold
+  double drift;        // drift measured by the last refresh
 };
 
 struct WinProp {      // one proposal of the current window
@@ -54,16 +55,23 @@ struct WinProp {      // one proposal of the current window
   long long gidx;     // global proposal index (generator counter)
 };
 
-// Everything a kernel needs, passed by value.  T is the storage type of N
-// and of its GEMM operands (double, or float in the mixed mode).
+// Everything a kernel needs about one walker.  A launch covers a batch of
+// walkers: kernels receive a device array of views and pick theirs by
+// blockIdx.z (or blockIdx.z / 2 where z also carries the spin).  T is the
+// storage type of N and of its GEMM operands (double, or float in the mixed
+// mode).
 template <typename T>
 struct View {
   // model
   int Nc, n_tau, ks, cap, ld, max_order;
   double beta, h, gamma, K_exp;
   double ev[2][2];            // e^{V}: [spin][0 for s = +1, 1 for s = -1]
+  uint64_t seed;              // generator key
   const int* diff;            // [Nc * Nc] index of r_i - r_j
   const double* table;        // [Nc][n_tau] G0(r, tau_l), standard convention
+  const int* sites;           // [Nc][2]
+  const double* Kp;           // [Nc][2]
+  const double* xi;           // [Nc] eps_K - mu
   // state
   Ctl* ctl;
   int* v_site;
@@ -78,14 +86,17 @@ struct View {
   int* el_s;
   int* el_slot;               // slot of a removal target, -1 for a candidate
   int* el_cand;               // candidate index or -1
+  int* el_row;                // row of each element in the extended N
   int* cand_el;
   long long* cand_id;
   int* S;                     // element of each fold column, S order
   int* ins_el;                // inserted elements in S order (mi)
+  int* remap;                 // [cap] compaction source of each destination
+  int* moves;                 // [2 KS_MAX + 1] compaction (dst, src) pairs, count
   T* gcol;                    // [ks][cap] g_{I,c}
   T* W[2];                    // [ks][cap] g_{c,I} (e^{V_I} - 1)
   double* gCC;                // [ks][ks] g_{c,c'}
-  T* X[2];                    // [ks][cap] X_c = W_c N
+  T* R[2];                    // [KS_MAX][cap] rows of the extended N per element
   double* gram[2];            // [ks][ks] G restricted to the window elements
   double* ginv[2];            // [ks][ks] Gamma_S^{-1}
   T* Y[2];                    // [ks][cap] N g_{I,c} for inserted spins
@@ -93,6 +104,25 @@ struct View {
   T* B[2];                    // [ks][cap] fold right factor, row-major
   double* ratio_out;          // device copy of the replay ratios
   const dcax_proposal* replay;
+  // refresh scratch (FP64)
+  double* M[2];               // [cap][cap]
+  double* P[2];               // [cap][NB] panel columns
+  double* Tm[2];              // [NB][cap] panel rows
+  int* ipiv[2];               // [cap]
+  int* perm[2];               // [cap]
+  double* blkmax;             // per-block maxima of the drift
+  double* detsign;            // [2]
+  // measurement scratch
+  int n_freq;
+  int kpad_cap;
+  int* m_order;               // [kpad_cap]
+  int* m_off;                 // [Nc + 1]
+  T* m_Ms[2];                 // [kpad_cap][kpad_cap]
+  T* m_E;                     // [kpad_cap][n_freq][2]
+  double* m_Mab[2];           // [Nc][Nc][n_freq][2]
+  long long acc_off;          // offset (doubles) of this walker's accumulator block
+  int nc_prefix;              // sum of Nc over the preceding walkers
+  int wid;
 };
 
 // ---------------------------------------------------------------- helpers

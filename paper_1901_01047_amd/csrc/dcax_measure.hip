@@ -14,22 +14,16 @@
 
 namespace dcax {
 
-struct MeasureBufs {
-  int* order = nullptr;    // [kpad] original slot of sorted row, -1 for padding
-  int* off = nullptr;      // [Nc + 1] bucket offsets (multiples of 16)
-  void* Ms[2] = {nullptr, nullptr};  // [kpad][kpad] sorted M, column-major
-  void* E = nullptr;       // [kpad][n_freq][2] e^{-i w_n tau_j} for sorted j
-  double* Mab[2] = {nullptr, nullptr};  // [Nc][Nc][n_freq][2]
-  int kpad_cap = 0;
-  int n_freq = 0;
-};
-
 // Counting sort of the vertices by site, buckets padded to 16 rows.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_sort(View<T> w, int* order, int* off, int kpad_cap) {
+__global__ void __launch_bounds__(WG) k_meas_sort(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
+  int* order = w.m_order;
+  int* off = w.m_off;
+  const int kpad_cap = w.kpad_cap;
   const int k = w.ctl->k;
   const int Nc = w.Nc;
-  extern __shared__ int cnt_s[];  // [Nc + 1]
+  __shared__ int cnt_s[4097];  // [Nc + 1], Nc <= 4096
   for (int a = threadIdx.x; a <= Nc; a += WG) cnt_s[a] = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < k; i += WG) atomicAdd(&cnt_s[w.v_site[i]], 1);
@@ -60,8 +54,13 @@ __global__ void __launch_bounds__(WG) k_meas_sort(View<T> w, int* order, int* of
 // Ms[i'][j'] = (e^{V_i} - 1) N[i][j] in sorted order (zero on padding), and
 // the phase table E[j'][n] = e^{-i w_n tau_j}.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_copy(View<T> w, const int* order, const int* off, T* Ms0, T* Ms1,
-                                                  int ldm) {
+__global__ void __launch_bounds__(WG) k_meas_copy(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
+  const int* order = w.m_order;
+  const int* off = w.m_off;
+  T* Ms0 = w.m_Ms[0];
+  T* Ms1 = w.m_Ms[1];
+  const int ldm = w.kpad_cap;
   const int kpad = off[w.Nc];
   const int jp = blockIdx.y;
   const int ip = blockIdx.x * WG + threadIdx.x;
@@ -79,7 +78,12 @@ __global__ void __launch_bounds__(WG) k_meas_copy(View<T> w, const int* order, c
 }
 
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_phase(View<T> w, const int* order, const int* off, T* E, int n_freq) {
+__global__ void __launch_bounds__(WG) k_meas_phase(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
+  const int* order = w.m_order;
+  const int* off = w.m_off;
+  T* E = w.m_E;
+  const int n_freq = w.n_freq;
   const int kpad = off[w.Nc];
   const int jp = blockIdx.y;
   const int n = blockIdx.x * WG + threadIdx.x;
@@ -99,16 +103,21 @@ __global__ void __launch_bounds__(WG) k_meas_phase(View<T> w, const int* order, 
 // parts of E separately), then the row phases e^{i w_n tau_i} and the sum
 // over i' in a.
 template <typename T>
-__global__ void __launch_bounds__(64) k_meas_block(View<T> w, const int* order, const int* off, const T* Ms0,
-                                                   const T* Ms1, int ldm, const T* E, int n_freq, double* Mab0,
-                                                   double* Mab1) {
+__global__ void __launch_bounds__(64) k_meas_block(const View<T>* __restrict__ vs, int nc_max) {
+  const View<T>& w = vs[blockIdx.z];
+  const int* order = w.m_order;
+  const int* off = w.m_off;
+  const int ldm = w.kpad_cap;
+  const T* E = w.m_E;
+  const int n_freq = w.n_freq;
   const int Nc = w.Nc;
-  const int ab = blockIdx.x;
-  const int a = ab / Nc, b = ab % Nc;
+  const int sp = blockIdx.x / (nc_max * nc_max);
+  const int ab = blockIdx.x % (nc_max * nc_max);
+  const int a = ab / nc_max, b = ab % nc_max;
   const int n0 = blockIdx.y * 16;
-  const int sp = blockIdx.z;
-  const T* Ms = sp ? Ms1 : Ms0;
-  double* Mab = sp ? Mab1 : Mab0;
+  if (a >= Nc || b >= Nc || n0 >= n_freq) return;
+  const T* Ms = w.m_Ms[sp];
+  double* Mab = w.m_Mab[sp];
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
   const int ia0 = off[a], ia1 = off[a + 1], jb0 = off[b], jb1 = off[b + 1];
@@ -167,13 +176,19 @@ __global__ void __launch_bounds__(64) k_meas_block(View<T> w, const int* order, 
 
 // acc[sp][K][n] += sign (1/Nc) sum_ab e^{-i K (r_a - r_b)} M(a, b; w_n).
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_K(View<T> w, const int* sites, const double* Kp, const double* Mab0,
-                                               const double* Mab1, int n_freq, double* acc) {
+__global__ void __launch_bounds__(WG) k_meas_K(const View<T>* __restrict__ vs, double* acc_all) {
+  const View<T>& w = vs[blockIdx.z >> 1];
+  const int sp = blockIdx.z & 1;
   const int Nc = w.Nc;
+  const int n_freq = w.n_freq;
   const int n = blockIdx.x * WG + threadIdx.x;
-  const int q = blockIdx.y, sp = blockIdx.z;
+  const int q = blockIdx.y;
+  if (q >= Nc) return;
+  const int* sites = w.sites;
+  const double* Kp = w.Kp;
+  double* acc = acc_all + w.acc_off;
   const double sign = w.ctl->sign;
-  const double* Mab = sp ? Mab1 : Mab0;
+  const double* Mab = w.m_Mab[sp];
   if (n < n_freq) {
     double re = 0.0, im = 0.0;
     for (int a = 0; a < Nc; ++a)
@@ -194,7 +209,9 @@ __global__ void __launch_bounds__(WG) k_meas_K(View<T> w, const int* sites, cons
 
 // aux += [sign, sign tr(M_up)/Nc, sign tr(M_dn)/Nc]; one block per spin.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_diag(View<T> w, double* aux) {
+__global__ void __launch_bounds__(WG) k_meas_diag(const View<T>* __restrict__ vs, double* aux_all) {
+  const View<T>& w = vs[blockIdx.z];
+  double* aux = aux_all + 3 * (size_t)w.wid;
   const int sp = blockIdx.x;
   const double sign = w.ctl->sign;
   __shared__ double red[WG];
@@ -214,13 +231,24 @@ __global__ void __launch_bounds__(WG) k_meas_diag(View<T> w, double* aux) {
   }
 }
 
-// G(K, i w_n) = G0 - G0 <M> G0 / beta and the tail-corrected G(K, tau).
-__global__ void __launch_bounds__(WG) k_finalize(int Nc, int n_freq, double beta, const double* xi, const double* acc,
-                                                 const double* aux, double* Giw, int n_tau_out, double* Gtau) {
-  const int q = blockIdx.y, sp = blockIdx.z;
+// G(K, i w_n) = G0 - G0 <M> G0 / beta and the tail-corrected G(K, tau)
+// (blockIdx.z = 2 walker + spin, blockIdx.y = momentum).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_finalize(const View<T>* __restrict__ vs, const double* acc_all,
+                                                 const double* aux_all, double* Giw_all, int n_tau_out,
+                                                 double* Gtau_all) {
+  const View<T>& w = vs[blockIdx.z >> 1];
+  const int sp = blockIdx.z & 1;
+  const int q = blockIdx.y;
+  const int Nc = w.Nc, n_freq = w.n_freq;
+  if (q >= Nc) return;
+  const double beta = w.beta;
+  const double* acc = acc_all + w.acc_off;
+  double* Giw = Giw_all + w.acc_off;
+  const double* aux = aux_all + 3 * (size_t)w.wid;
   const int x = blockIdx.x * WG + threadIdx.x;
   const double sgn = aux[0];
-  const double e = xi[q];
+  const double e = w.xi[q];
   if (x < n_freq) {
     const double wn = (2.0 * x + 1.0) * M_PI / beta;
     // G0 = 1 / (i w - xi) = (-xi - i w) / (xi^2 + w^2)
@@ -228,12 +256,12 @@ __global__ void __launch_bounds__(WG) k_finalize(int Nc, int n_freq, double beta
     const double gr = -e / d, gi = -wn / d;
     const size_t o = 2 * (((size_t)sp * Nc + q) * n_freq + x);
     const double mr = acc[o] / sgn, mi = acc[o + 1] / sgn;
-    // G0^2
     const double g2r = gr * gr - gi * gi, g2i = 2.0 * gr * gi;
     Giw[o] = gr - (g2r * mr - g2i * mi) / beta;
     Giw[o + 1] = gi - (g2r * mi + g2i * mr) / beta;
   }
-  if (Gtau && x < n_tau_out) {
+  if (Gtau_all && x < n_tau_out) {
+    double* Gtau = Gtau_all + (size_t)2 * w.nc_prefix * n_tau_out;
     const double tau = (x == n_tau_out - 1) ? beta : (double)x * (beta / (double)(n_tau_out - 1));
     const double A = -(aux[1 + sp] / sgn) / beta;
     double s = 0.0;
@@ -257,5 +285,17 @@ __global__ void __launch_bounds__(WG) k_finalize(int Nc, int n_freq, double beta
     Gtau[((size_t)sp * Nc + q) * n_tau_out + x] = g0 + (2.0 / beta) * s + A * (2.0 * tau - beta) / 4.0;
   }
 }
+
+#define DCAX_INSTANTIATE_MEASURE(T)                                                             \
+  template __global__ void k_meas_sort<T>(const View<T>*);                                      \
+  template __global__ void k_meas_copy<T>(const View<T>*);                                      \
+  template __global__ void k_meas_phase<T>(const View<T>*);                                     \
+  template __global__ void k_meas_block<T>(const View<T>*, int);                                \
+  template __global__ void k_meas_K<T>(const View<T>*, double*);                                \
+  template __global__ void k_meas_diag<T>(const View<T>*, double*);                             \
+  template __global__ void k_finalize<T>(const View<T>*, const double*, const double*, double*, int, double*);
+
+DCAX_INSTANTIATE_MEASURE(double)
+DCAX_INSTANTIATE_MEASURE(float)
 
 }  // namespace dcax

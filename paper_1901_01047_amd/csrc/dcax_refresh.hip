@@ -7,9 +7,10 @@
 //   (pivot search over the not yet pivoted rows, row swap, in-place GJ step);
 //   the other columns receive the panel's row swaps and then the rank-NB
 //   update  A_{.x} <- P_{.J} A_{Jx} + (A_{.x} with rows J zeroed),
-//   where P holds the eliminated panel columns, run on the MFMA fold kernel.
+//   where P holds the eliminated panel columns, run on the MFMA fold tile.
 // The column permutation implied by the row swaps is undone when the result
-// is copied into N.
+// is copied into N.  All walkers of a batch step through the panels
+// together; a walker whose order is below the current panel skips it.
 #include "dcax_dev.h"
 
 namespace dcax {
@@ -17,23 +18,32 @@ namespace dcax {
 constexpr int NB = 32;
 
 template <typename T>
-__global__ void __launch_bounds__(WG) k_build_ninv(View<T> w, double* M0, double* M1, int k, int ldm) {
+__global__ void __launch_bounds__(WG) k_build_ninv(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
+  const int k = w.ctl->k;
   const int j = blockIdx.y;
   const int i = blockIdx.x * WG + threadIdx.x;
   if (i >= k || j >= k) return;
   const double g = gfun(w, w.v_site[i], w.v_tau[i], w.v_site[j], w.v_tau[j]);
   const int sj = s01(w.v_s[j]);
   const double e0 = w.ev[0][sj], e1 = w.ev[1][sj];
-  M0[i + (size_t)j * ldm] = (i == j ? e0 : 0.0) - g * (e0 - 1.0);
-  M1[i + (size_t)j * ldm] = (i == j ? e1 : 0.0) - g * (e1 - 1.0);
+  const size_t o = i + (size_t)j * w.cap;
+  w.M[0][o] = (i == j ? e0 : 0.0) - g * (e0 - 1.0);
+  w.M[1][o] = (i == j ? e1 : 0.0) - g * (e1 - 1.0);
 }
 
-// Eliminates panel columns [p0, p0 + nb) of both matrices (blockIdx.x = spin).
-__global__ void __launch_bounds__(WG) k_gj_panel(double* M0, double* M1, int k, int ldm, int p0, int nb,
-                                                 int* ipiv0, int* ipiv1, Ctl* ctl, double* detsign) {
+// Eliminates panel columns [p0, p0 + nb) (blockIdx.x = spin, blockIdx.z =
+// walker).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_gj_panel(const View<T>* __restrict__ vs, int p0) {
+  const View<T>& w = vs[blockIdx.z];
+  const int k = w.ctl->k;
+  if (p0 >= k) return;
+  const int nb = (k - p0 < NB) ? k - p0 : NB;
   const int sp = blockIdx.x;
-  double* M = sp ? M1 : M0;
-  int* ipiv = sp ? ipiv1 : ipiv0;
+  double* M = w.M[sp];
+  int* ipiv = w.ipiv[sp];
+  const size_t ldm = w.cap;
   const int t = threadIdx.x;
   __shared__ double vmax_s[WG];
   __shared__ int imax_s[WG];
@@ -67,10 +77,10 @@ __global__ void __launch_bounds__(WG) k_gj_panel(double* M0, double* M1, int k, 
     const double pv = vmax_s[0];
     if (t == 0) {
       ipiv[c] = piv;
-      if (!(pv > 0.0) || !isfinite(pv)) latch(ctl, ST_NUMERIC);
+      if (!(pv > 0.0) || !isfinite(pv)) latch(w.ctl, ST_NUMERIC);
     }
     // swap rows c and piv inside the panel, then scale row c
-    if (t < nb && piv != c) {
+    if (t < nb && piv != c && piv < k) {
       const size_t col = (size_t)(p0 + t) * ldm;
       const double x = M[c + col];
       M[c + col] = M[piv + col];
@@ -79,7 +89,7 @@ __global__ void __launch_bounds__(WG) k_gj_panel(double* M0, double* M1, int k, 
     __syncthreads();
     const double a_cc = M[c + (size_t)c * ldm];
     // sign of det: product of the pivots, one factor -1 per row interchange
-    if (t == 0) detsign[sp] *= ((a_cc < 0.0) ? -1.0 : 1.0) * ((piv != c) ? -1.0 : 1.0);
+    if (t == 0) w.detsign[sp] *= ((a_cc < 0.0) ? -1.0 : 1.0) * ((piv != c) ? -1.0 : 1.0);
     __syncthreads();
     if (t < nb) {
       const size_t col = (size_t)(p0 + t) * ldm;
@@ -102,16 +112,20 @@ __global__ void __launch_bounds__(WG) k_gj_panel(double* M0, double* M1, int k, 
 }
 
 // Applies the panel's row swaps to the other columns, moves their panel rows
-// into Tm (row-major, [nb][ldt]) and zeroes them; copies the panel columns
-// into P (column-major).  One thread per column.
-__global__ void __launch_bounds__(WG) k_gj_prep(double* M0, double* M1, int k, int ldm, int p0, int nb,
-                                                const int* ipiv0, const int* ipiv1, double* P0, double* P1,
-                                                double* T0, double* T1, int ldt) {
+// into Tm (row-major, [nb][cap]) and zeroes them; copies the panel columns
+// into P (column-major).  One thread per column (blockIdx.y = spin).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_gj_prep(const View<T>* __restrict__ vs, int p0) {
+  const View<T>& w = vs[blockIdx.z];
+  const int k = w.ctl->k;
+  if (p0 >= k) return;
+  const int nb = (k - p0 < NB) ? k - p0 : NB;
   const int sp = blockIdx.y;
-  double* M = sp ? M1 : M0;
-  const int* ipiv = sp ? ipiv1 : ipiv0;
-  double* P = sp ? P1 : P0;
-  double* Tm = sp ? T1 : T0;
+  double* M = w.M[sp];
+  const int* ipiv = w.ipiv[sp];
+  double* P = w.P[sp];
+  double* Tm = w.Tm[sp];
+  const size_t ldm = w.cap, ldt = w.cap;
   const int j = blockIdx.x * WG + threadIdx.x;
   if (j >= k) return;
   const size_t col = (size_t)j * ldm;
@@ -119,7 +133,7 @@ __global__ void __launch_bounds__(WG) k_gj_prep(double* M0, double* M1, int k, i
   if (!in_panel) {
     for (int c = p0; c < p0 + nb; ++c) {
       const int piv = ipiv[c];
-      if (piv != c) {
+      if (piv != c && piv < k) {
         const double x = M[c + col];
         M[c + col] = M[piv + col];
         M[piv + col] = x;
@@ -134,24 +148,68 @@ __global__ void __launch_bounds__(WG) k_gj_prep(double* M0, double* M1, int k, i
       M[p0 + r + col] = 0.0;
     }
   }
-  // panel column copy: thread j copies row j of the panel
   for (int x = 0; x < nb; ++x) P[j + (size_t)x * ldt] = M[j + (size_t)(p0 + x) * ldm];
 }
 
-// N[:, j] = M[:, perm[j]] (rounded to T), and per-block maxima of
-// |N_old - N_new| and |N_new| for the drift.
+// Trailing update M += P Tm of panel p0 (blockIdx.z = 2 walker + spin).
 template <typename T>
-__global__ void __launch_bounds__(WG) k_refresh_store(View<T> w, const double* M0, const double* M1, int k, int ldm,
-                                                      const int* perm0, const int* perm1, double* blkmax, int measure) {
-  const int sp = blockIdx.z;
-  const double* M = sp ? M1 : M0;
-  const int* perm = sp ? perm1 : perm0;
+__global__ void __launch_bounds__(WG) k_gj_update(const View<T>* __restrict__ vs, int p0) {
+  const View<T>& w = vs[blockIdx.z >> 1];
+  const int sp = blockIdx.z & 1;
+  const int k = w.ctl->k;
+  if (p0 >= k) return;
+  const int nb = (k - p0 < NB) ? k - p0 : NB;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  if (i0 >= k || j0 >= k) return;
+  fold_tile<double>(w.M[sp], w.cap, w.P[sp], w.cap, w.Tm[sp], w.cap, k, k, nb, i0, j0);
+}
+
+// Column permutation implied by the row interchanges: inv(A) = inv(P A) P,
+// i.e. the column swaps (c, ipiv[c]) applied for c = k-1 down to 0.  One
+// thread per walker and spin replays them in LDS (blockIdx.x = spin).
+constexpr int PERM_MAX = 32768 + 128;
+template <typename T>
+__global__ void __launch_bounds__(64) k_gj_perm(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
+  const int k = w.ctl->k;
+  const int sp = blockIdx.x;
+  __shared__ unsigned short col_s[PERM_MAX];
+  for (int j = threadIdx.x; j < k; j += 64) col_s[j] = (unsigned short)j;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int* ipiv = w.ipiv[sp];
+    for (int c = k - 1; c >= 0; --c) {
+      int q = ipiv[c];
+      if (q < 0 || q >= k) {
+        latch(w.ctl, ST_NUMERIC);
+        q = c;
+      }
+      const unsigned short x = col_s[c];
+      col_s[c] = col_s[q];
+      col_s[q] = x;
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += 64) w.perm[sp][j] = col_s[j];
+}
+
+// N[:, j] = M[:, perm[j]] (rounded to T), and per-block maxima of
+// |N_old - N_new| and |N_new| for the drift (blockIdx.z = 2 walker + spin).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_refresh_store(const View<T>* __restrict__ vs, int measure) {
+  const View<T>& w = vs[blockIdx.z >> 1];
+  const int sp = blockIdx.z & 1;
+  const int k = w.ctl->k;
+  const int nbx = (k + WG - 1) / WG;
+  if ((int)blockIdx.x >= nbx || (int)blockIdx.y >= k) return;
+  const double* M = w.M[sp];
+  const int* perm = w.perm[sp];
   T* N = w.N[sp];
   const int j = blockIdx.y;
   const int i = blockIdx.x * WG + threadIdx.x;
   double dmax = 0.0, nmax = 0.0;
-  if (i < k && j < k) {
-    const double v = M[i + (size_t)perm[j] * ldm];
+  if (i < k) {
+    const double v = M[i + (size_t)perm[j] * w.cap];
     const size_t o = i + (size_t)j * w.ld;
     if (measure) {
       dmax = fabs((double)N[o] - v);
@@ -171,17 +229,47 @@ __global__ void __launch_bounds__(WG) k_refresh_store(View<T> w, const double* M
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const size_t b = ((size_t)sp * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    blkmax[2 * b] = a_s[0];
-    blkmax[2 * b + 1] = b_s[0];
+    const size_t b = ((size_t)sp * k + j) * nbx + blockIdx.x;
+    w.blkmax[2 * b] = a_s[0];
+    w.blkmax[2 * b + 1] = b_s[0];
   }
 }
 
-template __global__ void k_build_ninv<double>(View<double>, double*, double*, int, int);
-template __global__ void k_build_ninv<float>(View<float>, double*, double*, int, int);
-template __global__ void k_refresh_store<double>(View<double>, const double*, const double*, int, int, const int*,
-                                                 const int*, double*, int);
-template __global__ void k_refresh_store<float>(View<float>, const double*, const double*, int, int, const int*,
-                                                const int*, double*, int);
+// drift = max |N_old - N_new| / max |N_new| over both spins, into ctl->drift.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_drift(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
+  const int k = w.ctl->k;
+  const size_t n = (size_t)2 * k * ((k + WG - 1) / WG);
+  double a = 0.0, b = 0.0;
+  for (size_t x = threadIdx.x; x < n; x += WG) {
+    a = fmax(a, w.blkmax[2 * x]);
+    b = fmax(b, w.blkmax[2 * x + 1]);
+  }
+  __shared__ double a_s[WG], b_s[WG];
+  a_s[threadIdx.x] = a;
+  b_s[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = WG / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      a_s[threadIdx.x] = fmax(a_s[threadIdx.x], a_s[threadIdx.x + o]);
+      b_s[threadIdx.x] = fmax(b_s[threadIdx.x], b_s[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) w.ctl->drift = (b_s[0] > 0.0) ? a_s[0] / b_s[0] : 0.0;
+}
+
+#define DCAX_INSTANTIATE_REFRESH(T)                                   \
+  template __global__ void k_build_ninv<T>(const View<T>*);           \
+  template __global__ void k_gj_panel<T>(const View<T>*, int);        \
+  template __global__ void k_gj_prep<T>(const View<T>*, int);         \
+  template __global__ void k_gj_update<T>(const View<T>*, int);       \
+  template __global__ void k_refresh_store<T>(const View<T>*, int);   \
+  template __global__ void k_gj_perm<T>(const View<T>*);              \
+  template __global__ void k_drift<T>(const View<T>*);
+
+DCAX_INSTANTIATE_REFRESH(double)
+DCAX_INSTANTIATE_REFRESH(float)
 
 }  // namespace dcax

@@ -13,10 +13,10 @@
 // det N'^{-1} / det N^{-1} = prod_S (-Delta_p) det Gamma_S.
 //
 // Kernels, in launch order: k_prep_replay | k_prep_rng, k_gather, k_cand_x,
-// k_gram, k_accept, k_ygemm, k_fold_prep, k_fold, k_compact_plan,
-// k_compact_move.  Each reads the window sizes from the control block and
-// returns at once when the window is inactive, so the host may enqueue
-// windows without reading anything back.
+// k_gram, k_accept (which also plans the compaction and closes the window's
+// bookkeeping), k_ygemm, k_fold_prep, k_fold, k_compact_move.  Each reads the
+// window sizes from the control block and returns at once when the window is
+// inactive, so the host may enqueue windows without reading anything back.
 #include "dcax_dev.h"
 
 namespace dcax {
@@ -27,7 +27,8 @@ namespace dcax {
 // and one per distinct window-start vertex proposed for removal; a removal
 // of a vertex inserted earlier in the same window refers to that candidate.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_prep_replay(View<T> w) {
+__global__ void __launch_bounds__(WG) k_prep_replay(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
   Ctl* c = w.ctl;
   __shared__ long long tid_s[KS_MAX];
   __shared__ int tslot_s[KS_MAX];
@@ -122,7 +123,9 @@ __global__ void __launch_bounds__(WG) k_prep_replay(View<T> w) {
 // first attempt would hit (floor(u_index k0)).  A removal carried over from
 // an aborted window keeps the target it had already chosen.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_prep_rng(View<T> w, uint64_t seed) {
+__global__ void __launch_bounds__(WG) k_prep_rng(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
+  const uint64_t seed = w.seed;
   Ctl* c = w.ctl;
   __shared__ int nP_s, k0_s, carry_slot_s;
   __shared__ long long carry_s;
@@ -221,7 +224,10 @@ __global__ void __launch_bounds__(WG) k_prep_rng(View<T> w, uint64_t seed) {
 // both spins, candidate-candidate entries g_{c,c'}, and the rows N_{p.} of
 // the removal targets copied out contiguously.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_gather(View<T> w, T* R0, T* R1) {
+__global__ void __launch_bounds__(WG) k_gather(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
+  T* R0 = w.R[0];
+  T* R1 = w.R[1];
   const Ctl* c = w.ctl;
   if (!c->active) return;
   const int e = blockIdx.y;
@@ -260,7 +266,8 @@ __global__ void __launch_bounds__(WG) k_gather(View<T> w, T* R0, T* R1) {
 // matrix cores), written as rows e = element(c) of R.  Tiles of N are staged
 // through LDS so that HBM reads run down the columns.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_cand_x(View<T> w, T* R0, T* R1) {
+__global__ void __launch_bounds__(WG) k_cand_x(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
   if (!c->active) return;
   const int nC = c->nC;
@@ -270,7 +277,7 @@ __global__ void __launch_bounds__(WG) k_cand_x(View<T> w, T* R0, T* R1) {
   const int sp = blockIdx.y;
   const T* N = w.N[sp];
   const T* Wm = w.W[sp];
-  T* R = sp ? R1 : R0;
+  T* R = w.R[sp];
   __shared__ T As[64][17];
   __shared__ T Bs[16][65];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -318,7 +325,8 @@ __global__ void __launch_bounds__(WG) k_cand_x(View<T> w, T* R0, T* R1) {
 //   column of a target p:     G_{x,p} = (e^{V_p} R_x[p] - delta_{xp}) / (e^{V_p} - 1)
 // where R_x is row x of the extended N (X_c for candidates, N_{p.} for targets).
 template <typename T>
-__global__ void __launch_bounds__(WG) k_gram(View<T> w, const T* R0, const T* R1) {
+__global__ void __launch_bounds__(WG) k_gram(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
   if (!c->active) return;
   const int x = blockIdx.x, sp = blockIdx.y;
@@ -326,7 +334,7 @@ __global__ void __launch_bounds__(WG) k_gram(View<T> w, const T* R0, const T* R1
   if (x >= nE) return;
   const int k0 = c->k0, nC = c->nC;
   const int cx = w.el_cand[x];
-  const T* Rx = (sp ? R1 : R0) + (size_t)x * w.cap;
+  const T* Rx = w.R[sp] + (size_t)x * w.cap;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double* G = w.gram[sp] + x * KS_MAX;
   for (int cc = wv; cc < nC; cc += WG / 64) {
@@ -364,7 +372,12 @@ __global__ void __launch_bounds__(WG) k_gram(View<T> w, const T* R0, const T* R1
 constexpr int MAX_ATTEMPTS = 1 << 16;
 
 template <typename T>
-__global__ void __launch_bounds__(WG) k_accept(View<T> w, int* el_row, uint64_t seed) {
+__global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
+  int* el_row = w.el_row;
+  int* remap = w.remap;
+  int* moves = w.moves;
+  const uint64_t seed = w.seed;
   Ctl* c = w.ctl;
   if (!c->active) return;
   __shared__ double gram_s[2][KS_MAX * KS_MAX];
@@ -374,6 +387,9 @@ __global__ void __launch_bounds__(WG) k_accept(View<T> w, int* el_row, uint64_t 
   __shared__ double rat_s[2], schur_s[2], D_s[2];
   __shared__ int m_s, acc_s, kcur_s, q_s, abort_s, nins_s;
   __shared__ double sign_s;
+  // everything the sequential loop touches per proposal lives in LDS
+  __shared__ WinProp wp_s[KS_MAX];
+  __shared__ int cand_s[KS_MAX], spin_s[KS_MAX], slot_s[KS_MAX];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int nE = c->nE, nP = c->nP, k0 = c->k0;
   for (int idx = t; idx < 2 * KS_MAX * KS_MAX; idx += WG) {
@@ -381,6 +397,12 @@ __global__ void __launch_bounds__(WG) k_accept(View<T> w, int* el_row, uint64_t 
     gram_s[sp][r] = ((r / KS_MAX) < nE && (r % KS_MAX) < nE) ? w.gram[sp][r] : 0.0;
   }
   if (t < KS_MAX) pos_s[t] = -1;
+  if (t < nP) wp_s[t] = w.wp[t];
+  if (t < nE) {
+    cand_s[t] = w.el_cand[t];
+    spin_s[t] = w.el_s[t];
+    slot_s[t] = w.el_slot[t];
+  }
   if (t == 0) {
     m_s = 0;
     nins_s = 0;
@@ -393,7 +415,7 @@ __global__ void __launch_bounds__(WG) k_accept(View<T> w, int* el_row, uint64_t 
   long long carry = -1;
   int bad = 0, n_done = nP;
   for (int j = 0; j < nP; ++j) {
-    const WinProp p = w.wp[j];
+    const WinProp p = wp_s[j];
     if (t == 0) {
       int q = p.el, ab = 0;
       if (p.forced < 0 && p.kind == 1 && !p.carried) {
@@ -411,7 +433,7 @@ __global__ void __launch_bounds__(WG) k_accept(View<T> w, int* el_row, uint64_t 
                 e = p.el;
               } else {
                 for (int x = 0; x < nE; ++x)
-                  if (w.el_slot[x] == slot) e = x;
+                  if (slot_s[x] == slot) e = x;
               }
               if (e >= 0 && pos_s[e] >= 0) continue;
               if (e < 0) {
@@ -445,12 +467,12 @@ __global__ void __launch_bounds__(WG) k_accept(View<T> w, int* el_row, uint64_t 
       continue;
     }
     const int pq = pos_s[q];
-    const int is_c = w.el_cand[q] >= 0;
+    const int is_c = cand_s[q] >= 0;
     if (pq >= 0) {
       if (t < 2) rat_s[t] = ginv_s[t][pq * KS_MAX + pq] / (-dl_s[t][pq]);
     } else if (wv < 2) {
       const int sp = wv;
-      const double ev = w.ev[sp][s01(w.el_s[q])];
+      const double ev = w.ev[sp][s01(spin_s[q])];
       const double D = is_c ? ev - 1.0 : 1.0 / ev - 1.0;
       double L = 0.0;
       if (lane < m) {
@@ -491,7 +513,7 @@ __global__ void __launch_bounds__(WG) k_accept(View<T> w, int* el_row, uint64_t 
         if (R < 0.0) sign_s = -sign_s;
         if (p.kind == 0) {
           ++n_ins;
-          const int cc = w.el_cand[q];
+          const int cc = cand_s[q];
           if (p.forced < 0) w.cand_id[cc] = next_id++;
           insl_s[nins_s++] = q;
         } else {
@@ -580,26 +602,59 @@ __global__ void __launch_bounds__(WG) k_accept(View<T> w, int* el_row, uint64_t 
     const int sp = idx / (m * m), r = idx % (m * m), a = r / m, b = r % m;
     w.ginv[sp][a * KS_MAX + b] = ginv_s[sp][a * KS_MAX + b];
   }
+  // Epilogue: the fold's column order, the new vertex arrays and the plan
+  // that removes the deleted rows and columns of N.  Inserted spins take
+  // slots k0 .. k0+mi-1; holes left below the new order are filled from the
+  // surviving slots above it (remap[dst] = src, moves[] = (dst, src) pairs).
+  // Nothing later in the window reads the vertex arrays or the order, so
+  // both are final here.
+  __shared__ int ins_s[KS_MAX], hole_s[KS_MAX], src_s[KS_MAX], mi_s, nh_s;
+  const int knew = kcur_s;
   if (t == 0) {
     int mi = 0, mr = 0;
+    int rem[KS_MAX];
     for (int s = 0; s < m; ++s) {
       const int e = S_s[s];
       w.S[s] = e;
-      if (w.el_cand[e] >= 0) {
+      if (cand_s[e] >= 0) {
+        ins_s[mi] = e;
         w.ins_el[mi] = e;
         el_row[e] = k0 + mi;
         ++mi;
       } else {
-        el_row[e] = w.el_slot[e];
-        ++mr;
+        el_row[e] = slot_s[e];
+        rem[mr++] = slot_s[e];
       }
     }
+    for (int a = 1; a < mr; ++a)
+      for (int b = a; b > 0 && rem[b - 1] > rem[b]; --b) {
+        const int x = rem[b];
+        rem[b] = rem[b - 1];
+        rem[b - 1] = x;
+      }
+    const int kx = k0 + mi;
+    int nh = 0, ns = 0, r = 0;
+    for (int a = 0; a < mr; ++a)
+      if (rem[a] < knew) hole_s[nh++] = rem[a];
+    for (int i = knew; i < kx; ++i) {
+      while (r < mr && rem[r] < i) ++r;
+      if (r < mr && rem[r] == i) continue;
+      src_s[ns++] = i;
+    }
+    for (int h = 0; h < nh; ++h) {
+      moves[2 * h] = hole_s[h];
+      moves[2 * h + 1] = src_s[h];
+    }
+    moves[2 * KS_MAX] = nh;
+    mi_s = mi;
+    nh_s = nh;
     if (bad) latch(c, ST_NUMERIC);
     c->m = m;
     c->mi = mi;
     c->mr = mr;
-    c->kx = k0 + mi;
-    c->knew = kcur_s;
+    c->kx = kx;
+    c->knew = knew;
+    c->k = knew;
     c->sign = sign_s;
     c->next_id = next_id;
     c->n_prop += n_done;
@@ -607,22 +662,48 @@ __global__ void __launch_bounds__(WG) k_accept(View<T> w, int* el_row, uint64_t 
     c->n_acc_rem += n_rem;
     c->n_mismatch += n_mis;
     c->pos += n_done;
+    c->n_windows += 1;
     if (carry >= 0) {
       c->carry_id = carry;
       c->n_abort += 1;
     }
-    if (m == 0) {
-      // nothing to fold: the window ends here with the order unchanged
-      c->n_windows += 1;
-      c->active = 0;
+    if (m > 0) {
+      const double x = (double)kx;
+      c->fold_flops += 2.0 * 2.0 * x * x * (double)m;
+      c->fold_bytes += 2.0 * 2.0 * x * x * (double)sizeof(T);
+      c->n_folds += 1;
+      c->sum_m += m;
+    } else {
+      c->active = 0;      // nothing to fold: the window ends here
     }
+  }
+  __syncthreads();
+  const int mi = mi_s, nh = nh_s;
+  if (m == 0) return;
+  for (int i = t; i < knew; i += WG) remap[i] = i;
+  if (t < mi) {
+    const int e = ins_s[t];
+    w.v_site[k0 + t] = w.el_site[e];
+    w.v_tau[k0 + t] = w.el_tau[e];
+    w.v_s[k0 + t] = spin_s[e];
+    w.v_id[k0 + t] = w.cand_id[cand_s[e]];
+  }
+  __syncthreads();
+  if (t < nh) {
+    const int d = hole_s[t], sidx = src_s[t];
+    remap[d] = sidx;
+    w.v_site[d] = w.v_site[sidx];
+    w.v_tau[d] = w.v_tau[sidx];
+    w.v_s[d] = w.v_s[sidx];
+    w.v_id[d] = w.v_id[sidx];
   }
 }
 
 // --------------------------------------------------------- Y = N g_{I,c}
 // Columns G_{I,c} = N g_{I,c} for the inserted spins (a k0 x k0 x mi GEMM).
 template <typename T>
-__global__ void __launch_bounds__(WG) k_ygemm(View<T> w) {
+__global__ void __launch_bounds__(WG) k_ygemm(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
   if (!c->active) return;
   const int mi = c->mi, k0 = c->k0;
@@ -672,7 +753,9 @@ __global__ void __launch_bounds__(WG) k_ygemm(View<T> w) {
 //   B = Gamma_S^{-1} N_{S.} with the rows of the extended N;
 // and the extension of N itself: row k0+j = X_c, column k0+j = e_{k0+j}.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_fold_prep(View<T> w, const T* R0, const T* R1, const int* el_row) {
+__global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
+  const int* el_row = w.el_row;
   const Ctl* c = w.ctl;
   if (!c->active) return;
   const int m = c->m;
@@ -701,7 +784,7 @@ __global__ void __launch_bounds__(WG) k_fold_prep(View<T> w, const T* R0, const 
   __syncthreads();
   const int i = blockIdx.x * WG + t;
   if (i >= kx) return;
-  const T* R = sp ? R1 : R0;
+  const T* R = w.R[sp];
   T* N = w.N[sp];
   const size_t ld = w.ld;
   // A, column-major [s][i]
@@ -743,36 +826,13 @@ __global__ void __launch_bounds__(WG) k_fold_prep(View<T> w, const T* R0, const 
 }
 
 // ---------------------------------------------------------------- fold
-// In-place rank-K update C += A B for two independent matrices (the spins),
-// on the matrix cores.  A is column-major (lda), B row-major (ldb), C
-// column-major (ldc).  The MFMA computes the transposed tile, D = B^T A^T,
-// so that the 16 lanes of a row group walk down a column of C (contiguous
-// 128-byte reads and writes).  Sizes come from the control block (window
-// fold) or from the arguments (refresh).
+// In-place rank-K update C += A B on the matrix cores.  A is column-major
+// (lda), B row-major (ldb), C column-major (ldc).  The MFMA computes the
+// transposed tile, D = B^T A^T, so that the 16 lanes of a row group walk
+// down a column of C (contiguous 128-byte reads and writes).
 template <typename T>
-struct FoldArgs {
-  T* C[2];
-  const T* A[2];
-  const T* B[2];
-  int ldc, lda, ldb;
-  int M, N, K;
-  const Ctl* ctl;
-};
-
-template <typename T>
-__global__ void __launch_bounds__(WG) k_fold(FoldArgs<T> f) {
-  int M = f.M, Nn = f.N, K = f.K;
-  if (f.ctl) {
-    if (!f.ctl->active) return;
-    M = Nn = f.ctl->kx;
-    K = f.ctl->m;
-  }
-  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
-  if (K == 0 || i0 >= M || j0 >= Nn) return;
-  const int sp = blockIdx.z;
-  T* C = f.C[sp];
-  const T* A = f.A[sp];
-  const T* B = f.B[sp];
+__device__ inline void fold_tile(T* C, int ldc, const T* A, int lda, const T* B, int ldb, int M, int Nn, int K,
+                                 int i0, int j0) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int jb = j0 + wv * 16;
   const int li = lane & 15, lk = lane >> 4;
@@ -783,16 +843,16 @@ __global__ void __launch_bounds__(WG) k_fold(FoldArgs<T> f) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int jj = jb + Mfma<T>::row(lane, r);
-      acc[rb][r] = (ii < M && jj < Nn) ? C[ii + (size_t)jj * f.ldc] : (T)0;
+      acc[rb][r] = (ii < M && jj < Nn) ? C[ii + (size_t)jj * ldc] : (T)0;
     }
   }
   for (int s = 0; s < K; s += 4) {
     const int sk = s + lk;
-    const T a = (sk < K && jb + li < Nn) ? B[(size_t)sk * f.ldb + jb + li] : (T)0;
+    const T a = (sk < K && jb + li < Nn) ? B[(size_t)sk * ldb + jb + li] : (T)0;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       const int ii = i0 + rb * 16 + li;
-      const T b = (sk < K && ii < M) ? A[(size_t)sk * f.lda + ii] : (T)0;
+      const T b = (sk < K && ii < M) ? A[(size_t)sk * lda + ii] : (T)0;
       acc[rb] = Mfma<T>::run(a, b, acc[rb]);
     }
   }
@@ -802,79 +862,38 @@ __global__ void __launch_bounds__(WG) k_fold(FoldArgs<T> f) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int jj = jb + Mfma<T>::row(lane, r);
-      if (ii < M && jj < Nn) C[ii + (size_t)jj * f.ldc] = acc[rb][r];
+      if (ii < M && jj < Nn) C[ii + (size_t)jj * ldc] = acc[rb][r];
     }
   }
+}
+
+// Window fold N_ext += A B for every walker of the batch and both spins
+// (blockIdx.z = 2 walker + spin).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_fold(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z >> 1];
+  const int sp = blockIdx.z & 1;
+  const Ctl* c = w.ctl;
+  if (!c->active) return;
+  const int kx = c->kx, m = c->m;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  if (m == 0 || i0 >= kx || j0 >= kx) return;
+  fold_tile<T>(w.N[sp], w.ld, w.A[sp], w.cap, w.B[sp], w.cap, kx, kx, m, i0, j0);
 }
 
 // ----------------------------------------------------------- compaction
-// Drop the rows and columns of removed vertices: holes below the new order
-// are filled with the surviving rows/columns above it.  The plan kernel also
-// writes the inserted vertices into slots k0 .. k0+mi-1 and compacts the
-// vertex arrays; remap[i] is the source index of destination i.
+// Drop the rows and columns of removed vertices: with remap and moves from
+// the accept kernel, N[i][d] = N[remap(i)][s] and N[d][i] = N[s][remap(i)]
+// for every move (d, s).  Sources lie at or above the new order and are
+// never written, so the copy is race-free in place.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_compact_plan(View<T> w, int* remap, int* moves) {
+__global__ void __launch_bounds__(WG) k_compact_move(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z >> 1];
+  const int* remap = w.remap;
+  const int* moves = w.moves;
   Ctl* c = w.ctl;
   if (!c->active) return;
-  __shared__ int hole_s[KS_MAX], src_s[KS_MAX], nh_s;
-  const int t = threadIdx.x;
-  const int k0 = c->k0, mi = c->mi, m = c->m, kx = c->kx, knew = c->knew;
-  if (t < mi) {
-    const int e = w.ins_el[t];
-    const int cc = w.el_cand[e];
-    w.v_site[k0 + t] = w.el_site[e];
-    w.v_tau[k0 + t] = w.el_tau[e];
-    w.v_s[k0 + t] = w.el_s[e];
-    w.v_id[k0 + t] = w.cand_id[cc];
-  }
-  for (int i = t; i < knew; i += WG) remap[i] = i;
-  __syncthreads();
-  if (t == 0) {
-    // removed slots (all < k0), sorted
-    int rem[KS_MAX];
-    int nr = 0;
-    for (int s = 0; s < m; ++s) {
-      const int e = w.S[s];
-      if (w.el_cand[e] < 0) rem[nr++] = w.el_slot[e];
-    }
-    for (int a = 1; a < nr; ++a)
-      for (int b = a; b > 0 && rem[b - 1] > rem[b]; --b) {
-        const int x = rem[b];
-        rem[b] = rem[b - 1];
-        rem[b - 1] = x;
-      }
-    int nh = 0, ns = 0, r = 0;
-    for (int a = 0; a < nr; ++a)
-      if (rem[a] < knew) hole_s[nh++] = rem[a];
-    for (int i = knew; i < kx; ++i) {
-      while (r < nr && rem[r] < i) ++r;
-      if (r < nr && rem[r] == i) continue;
-      src_s[ns++] = i;
-    }
-    nh_s = nh;
-    for (int h = 0; h < nh; ++h) {
-      moves[2 * h] = hole_s[h];
-      moves[2 * h + 1] = src_s[h];
-    }
-    moves[2 * KS_MAX] = nh;
-  }
-  __syncthreads();
-  const int nh = nh_s;
-  if (t < nh) {
-    const int d = hole_s[t], s = src_s[t];
-    remap[d] = s;
-    w.v_site[d] = w.v_site[s];
-    w.v_tau[d] = w.v_tau[s];
-    w.v_s[d] = w.v_s[s];
-    w.v_id[d] = w.v_id[s];
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(WG) k_compact_move(View<T> w, const int* remap, const int* moves) {
-  Ctl* c = w.ctl;
-  if (!c->active) return;
-  const int h = blockIdx.y, sp = blockIdx.z;
+  const int h = blockIdx.y, sp = blockIdx.z & 1;
   const int nh = moves[2 * KS_MAX];
   const int knew = c->knew;
   const int i = blockIdx.x * WG + threadIdx.x;
@@ -888,39 +907,17 @@ __global__ void __launch_bounds__(WG) k_compact_move(View<T> w, const int* remap
   }
 }
 
-// Closes the window: the new order and the fold statistics.
-template <typename T>
-__global__ void k_window_end(View<T> w) {
-  Ctl* c = w.ctl;
-  if (!c->active) return;
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const double kx = (double)c->kx;
-    c->fold_flops += 2.0 * 2.0 * kx * kx * (double)c->m;
-    c->fold_bytes += 2.0 * 2.0 * kx * kx * (double)sizeof(T);
-    c->n_folds += 1;
-    c->sum_m += c->m;
-    c->n_windows += 1;
-    c->k = c->knew;
-    c->active = 0;
-  }
-}
-
-// k_accept with m == 0 already set the order (no fold needed) -- the order
-// stays k0 + 0; nothing else changes.
-
-#define DCAX_INSTANTIATE(T)                                                                     \
-  template __global__ void k_prep_replay<T>(View<T>);                                           \
-  template __global__ void k_gather<T>(View<T>, T*, T*);                                        \
-  template __global__ void k_cand_x<T>(View<T>, T*, T*);                                        \
-  template __global__ void k_gram<T>(View<T>, const T*, const T*);                              \
-  template __global__ void k_accept<T>(View<T>, int*, uint64_t);                                \
-  template __global__ void k_prep_rng<T>(View<T>, uint64_t);                                    \
-  template __global__ void k_ygemm<T>(View<T>);                                                 \
-  template __global__ void k_fold_prep<T>(View<T>, const T*, const T*, const int*);             \
-  template __global__ void k_fold<T>(FoldArgs<T>);                                              \
-  template __global__ void k_compact_plan<T>(View<T>, int*, int*);                              \
-  template __global__ void k_compact_move<T>(View<T>, const int*, const int*);                  \
-  template __global__ void k_window_end<T>(View<T>);
+#define DCAX_INSTANTIATE(T)                                              \
+  template __global__ void k_prep_replay<T>(const View<T>*);             \
+  template __global__ void k_prep_rng<T>(const View<T>*);                \
+  template __global__ void k_gather<T>(const View<T>*);                  \
+  template __global__ void k_cand_x<T>(const View<T>*);                  \
+  template __global__ void k_gram<T>(const View<T>*);                    \
+  template __global__ void k_accept<T>(const View<T>*);                  \
+  template __global__ void k_ygemm<T>(const View<T>*);                   \
+  template __global__ void k_fold_prep<T>(const View<T>*);               \
+  template __global__ void k_fold<T>(const View<T>*);                    \
+  template __global__ void k_compact_move<T>(const View<T>*);
 
 DCAX_INSTANTIATE(double)
 DCAX_INSTANTIATE(float)

@@ -99,13 +99,13 @@ def load():
         "dcax_refresh": [vp, P(ctypes.c_double)],
         "dcax_measure_G": [vp, vp, vp],
         "dcax_finalize_G": [vp, vp, vp, vp, ctypes.c_int32, vp],
-        "dcax_get_order": [vp, P(ctypes.c_int32)],
-        "dcax_copy_N": [vp, ctypes.c_int32, vp, ctypes.c_int64, vp],
-        "dcax_get_config": [vp, vp, ctypes.c_int32, P(ctypes.c_int32)],
-        "dcax_set_config": [vp, vp, ctypes.c_int32],
-        "dcax_get_stats": [vp, P(Stats)],
+        "dcax_get_order": [vp, ctypes.c_int32, P(ctypes.c_int32)],
+        "dcax_copy_N": [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64, vp],
+        "dcax_get_config": [vp, ctypes.c_int32, vp, ctypes.c_int32, P(ctypes.c_int32)],
+        "dcax_set_config": [vp, ctypes.c_int32, vp, ctypes.c_int32],
+        "dcax_get_stats": [vp, ctypes.c_int32, P(Stats)],
         "dcax_set_timing": [vp, ctypes.c_int32],
-        "dcax_copy_g0_table": [vp, vp],
+        "dcax_copy_g0_table": [vp, ctypes.c_int32, vp],
         "dcax_cluster": [P(Params), P(ctypes.c_int32), vp, vp],
     }
     for name, args in sig.items():
@@ -148,13 +148,19 @@ def cluster(params):
 
 
 class Walker:
-    """One CT-AUX walker on the current torch device and stream."""
+    """A batch of CT-AUX walkers (one by default) on the current torch device and stream.
+
+    `params` is one Params or a sequence of them (one per walker; all share
+    the precision).  Per-walker methods take `walker=0`."""
 
     def __init__(self, params, device=None, stream=None):
         import torch
         self._torch = torch
         lib = load()
-        self.params = params
+        plist = list(params) if isinstance(params, (list, tuple)) else [params]
+        self.plist = plist
+        self.params = plist[0]
+        self.W = len(plist)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
         dev_index = self.device.index
@@ -169,14 +175,22 @@ class Walker:
         self._alloc_cb = ALLOC_FN(_alloc)
         self._free_cb = FREE_FN(_free)
         self._allocator = Allocator(self._alloc_cb, self._free_cb, None)
+        arr = (Params * self.W)(*plist)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _check(lib.dcax_walker_create(ctypes.byref(params), 1, ctypes.byref(self._allocator),
-                                          ctypes.c_void_p(sptr), ctypes.byref(h)))
+            _check(lib.dcax_walker_create(arr, self.W, ctypes.byref(self._allocator), ctypes.c_void_p(sptr),
+                                          ctypes.byref(h)))
         self._h = h
-        sites, K = cluster(params)
-        self.Nc = len(sites)
-        self.sites, self.K = sites, K
+        self.sites, self.K, self.Ncs = [], [], []
+        for p in plist:
+            sites, K = cluster(p)
+            self.sites.append(sites)
+            self.K.append(K)
+            self.Ncs.append(len(sites))
+        self.Nc = self.Ncs[0]
+        # accumulator layout: walker blocks of [2][Nc][max(n_freq, 1)][2] doubles, in walker order
+        self.acc_sizes = [2 * nc * max(p.n_freq, 1) * 2 for nc, p in zip(self.Ncs, plist)]
+        self.acc_offsets = np.concatenate([[0], np.cumsum(self.acc_sizes)[:-1]]).astype(np.int64)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -194,7 +208,7 @@ class Walker:
         _check(load().dcax_sweep(self._h, int(n), None, 0, None))
 
     def replay(self, records):
-        """Replay a structured array of PROPOSAL_DTYPE; returns the ratios."""
+        """Replay a structured array of PROPOSAL_DTYPE (single-walker handle); returns the ratios."""
         rec = np.ascontiguousarray(records, dtype=PROPOSAL_DTYPE)
         ratios = np.zeros(len(rec), np.float64)
         _check(load().dcax_sweep(self._h, 0, rec.ctypes.data, len(rec), ratios.ctypes.data))
@@ -206,54 +220,72 @@ class Walker:
         return d.value
 
     # -- configuration -------------------------------------------------
-    @property
-    def order(self):
+    def order_of(self, walker=0):
         k = ctypes.c_int32()
-        _check(load().dcax_get_order(self._h, ctypes.byref(k)))
+        _check(load().dcax_get_order(self._h, int(walker), ctypes.byref(k)))
         return k.value
 
-    def set_config(self, site, tau, aux_spin, ids=None):
+    @property
+    def order(self):
+        return self.order_of(0)
+
+    def orders(self):
+        return [self.order_of(i) for i in range(self.W)]
+
+    def set_config(self, site, tau, aux_spin, ids=None, walker=0):
         k = len(site)
         v = np.zeros(k, VERTEX_DTYPE)
         v["site"], v["tau"], v["aux_spin"] = site, tau, aux_spin
         v["id"] = np.arange(k) if ids is None else ids
-        _check(load().dcax_set_config(self._h, v.ctypes.data if k else None, k))
+        _check(load().dcax_set_config(self._h, int(walker), v.ctypes.data if k else None, k))
 
-    def get_config(self):
-        k = self.order
+    def get_config(self, walker=0):
+        k = self.order_of(walker)
         v = np.zeros(max(k, 1), VERTEX_DTYPE)
         kk = ctypes.c_int32()
-        _check(load().dcax_get_config(self._h, v.ctypes.data, len(v), ctypes.byref(kk)))
+        _check(load().dcax_get_config(self._h, int(walker), v.ctypes.data, len(v), ctypes.byref(kk)))
         return v[:kk.value]
 
-    def copy_N(self, spin):
+    def copy_N(self, spin, walker=0):
         """(ids, N) in canonical (id ascending) order, float64."""
-        k = self.order
+        k = self.order_of(walker)
         out = np.zeros((k, k), np.float64)
         ids = np.zeros(k, np.int64)
         if k:
-            _check(load().dcax_copy_N(self._h, int(spin), out.ctypes.data, k, ids.ctypes.data))
+            _check(load().dcax_copy_N(self._h, int(walker), int(spin), out.ctypes.data, k, ids.ctypes.data))
         return ids, out
 
-    def stats(self):
+    def stats(self, walker=-1):
+        """Counters of one walker, or summed over the batch (walker=-1)."""
         s = Stats()
-        _check(load().dcax_get_stats(self._h, ctypes.byref(s)))
+        _check(load().dcax_get_stats(self._h, int(walker), ctypes.byref(s)))
         return {f: getattr(s, f) for f, _ in Stats._fields_}
 
     def set_timing(self, on=True):
         _check(load().dcax_set_timing(self._h, 1 if on else 0))
 
-    def g0_table(self):
-        t = np.zeros((self.Nc, self.params.n_tau), np.float64)
-        _check(load().dcax_copy_g0_table(self._h, t.ctypes.data))
+    def g0_table(self, walker=0):
+        p = self.plist[walker]
+        t = np.zeros((self.Ncs[walker], p.n_tau), np.float64)
+        _check(load().dcax_copy_g0_table(self._h, int(walker), t.ctypes.data))
         return t
 
     # -- measurement ---------------------------------------------------
     def new_accumulator(self):
+        """(acc, aux): acc holds every walker's [2][Nc][n_freq][2] block; aux is [W][3]."""
         torch = self._torch
-        acc = torch.zeros((2, self.Nc, max(self.params.n_freq, 1), 2), dtype=torch.float64, device=self.device)
-        aux = torch.zeros(3, dtype=torch.float64, device=self.device)
+        acc = torch.zeros(int(sum(self.acc_sizes)), dtype=torch.float64, device=self.device)
+        aux = torch.zeros((self.W, 3), dtype=torch.float64, device=self.device)
+        if self.W == 1:
+            acc = acc.view(2, self.Nc, max(self.params.n_freq, 1), 2)
+            aux = aux.view(3)
         return acc, aux
+
+    def acc_block(self, acc, walker):
+        """One walker's [2][Nc][n_freq][2] view of a batch accumulator."""
+        flat = acc.reshape(-1)
+        o, n = int(self.acc_offsets[walker]), self.acc_sizes[walker]
+        return flat[o:o + n].view(2, self.Ncs[walker], max(self.plist[walker].n_freq, 1), 2)
 
     def measure(self, acc, aux):
         _check(load().dcax_measure_G(self._h, ctypes.c_void_p(acc.data_ptr()), ctypes.c_void_p(aux.data_ptr())))
@@ -261,8 +293,11 @@ class Walker:
     def finalize(self, acc, aux, n_tau_out=0):
         torch = self._torch
         Giw = torch.zeros_like(acc)
-        Gt = torch.zeros((2, self.Nc, max(n_tau_out, 1)), dtype=torch.float64, device=self.device)
+        n_gt = 2 * sum(self.Ncs) * max(n_tau_out, 1)
+        Gt = torch.zeros(n_gt, dtype=torch.float64, device=self.device)
         _check(load().dcax_finalize_G(self._h, ctypes.c_void_p(acc.data_ptr()), ctypes.c_void_p(aux.data_ptr()),
                                       ctypes.c_void_p(Giw.data_ptr()), int(n_tau_out),
                                       ctypes.c_void_p(Gt.data_ptr()) if n_tau_out else None))
+        if self.W == 1:
+            Gt = Gt.view(2, self.Nc, max(n_tau_out, 1))
         return Giw, (Gt if n_tau_out else None)

@@ -75,7 +75,9 @@ def test_create_rejects_degenerate_cluster_and_batch(lib):
     h = ctypes.c_void_p()
     assert lib.dcax_walker_create(ctypes.byref(p), 1, None, None, ctypes.byref(h)) == -1
     p = dcax.make_params()
-    assert lib.dcax_walker_create(ctypes.byref(p), 2, None, None, ctypes.byref(h)) == -1
+    assert lib.dcax_walker_create(ctypes.byref(p), 0, None, None, ctypes.byref(h)) == -1
+    two = (dcax.Params * 2)(dcax.make_params(), dcax.make_params(precision=dcax.DCAX_FP32_MIXED))
+    assert lib.dcax_walker_create(two, 2, None, None, ctypes.byref(h)) == -1    # mixed precisions
     assert lib.dcax_walker_create(ctypes.byref(p), 1, None, None, None) == -1
 
 
@@ -92,5 +94,5 @@ def test_cluster_enumeration_matches_oracle(c):
 def test_null_walker_calls(lib):
     assert lib.dcax_walker_destroy(None) == 0
     k = ctypes.c_int32()
-    assert lib.dcax_get_order(None, ctypes.byref(k)) == -1
+    assert lib.dcax_get_order(None, 0, ctypes.byref(k)) == -1
     assert lib.dcax_sweep(None, 1, None, 0, None) == -1

@@ -1,0 +1,81 @@
+"""FP32-mixed mode against the FP64 oracle and the FP64 path (MI355X).
+
+In the mixed mode N and its GEMMs (candidate rows, fold, measurement) are
+FP32 on the matrix cores with FP32 accumulation; Gamma^{-1}, the ratios and
+the refresh stay FP64.  Both walkers replay the same oracle trace with
+forced decisions, so they hold identical configurations and the differences
+below are the precision effect alone.  Reported per result (printed and
+written to gpurun_out/mixed_precision.json when that folder exists):
+ratio error vs the oracle (scaled by max(|R|, 1)), N error vs the oracle
+(normwise), and G(K, i w_n) error of the mixed path vs the FP64 path.
+
+Bounds asserted are loose sanity bounds for FP32 storage (2^-24 ~ 6e-8 per
+element): ratios 1e-4, N 1e-4 normwise, G(K, i w_n) 1e-4 relative to max|G|.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1901_01047_amd import dcax  # noqa: E402
+from paper_1901_01047_amd.workloads import CONFIGS, params_kwargs  # noqa: E402
+from tests.ctaux_cases import model, oracle_trace  # noqa: E402
+
+RESULTS = {}
+
+
+@pytest.mark.parametrize("name,k_s,k_init,warm,n_rec", [("2x2_U4_b5", 16, 20, 30, 640),
+                                                        ("4x4_U4_b10", 32, 280, 10, 640)])
+def test_mixed_precision_errors(name, k_s, k_init, warm, n_rec):
+    print(f"[mixed] {name}", flush=True)
+    m = model(name)
+    init, rec, ratios_o, ow = oracle_trace(m, seed=CONFIGS[name]["seed"] + 1, k_s=k_s, init_order=k_init,
+                                           warm_sweeps=warm, rec_proposals=n_rec)
+    nf = min(CONFIGS[name]["n_freq"], 256)
+    walkers = {}
+    for prec in (dcax.DCAX_FP64, dcax.DCAX_FP32_MIXED):
+        w = dcax.Walker(dcax.make_params(**params_kwargs(name, submatrix_k=k_s, n_freq=nf), precision=prec))
+        w.set_config(*init)
+        walkers[prec] = w
+    accs = {p: walkers[p].new_accumulator() for p in walkers}
+    ratios = {p: [] for p in walkers}
+    chunks = np.array_split(np.arange(len(rec)), 8)
+    for ch in chunks:
+        for p, w in walkers.items():
+            ratios[p].append(w.replay(rec[ch]))
+            w.measure(*accs[p])
+    good = ~((rec["kind"] == 1) & (rec["id"] < 0))
+    out = {}
+    for p, tag in ((dcax.DCAX_FP64, "fp64"), (dcax.DCAX_FP32_MIXED, "mixed")):
+        r = np.concatenate(ratios[p])
+        scaled = np.abs(r[good] - ratios_o[good]) / np.maximum(np.abs(ratios_o[good]), 1.0)
+        rel = np.abs(r[good] - ratios_o[good]) / np.abs(ratios_o[good])
+        ids_o, Nu, Nd = ow.canonical()
+        nerr = max(np.max(np.abs(walkers[p].copy_N(sp)[1] - No)) / np.max(np.abs(No))
+                   for sp, No in ((0, Nu), (1, Nd)))
+        out[tag] = {"ratio_err_scaled_max": float(scaled.max()), "ratio_rel_err_median": float(np.median(rel)),
+                    "ratio_rel_err_p99": float(np.quantile(rel, 0.99)), "N_err_normwise": float(nerr),
+                    "decision_mismatches": int(walkers[p].stats()["decision_mismatches"])}
+    a64 = accs[dcax.DCAX_FP64][0].cpu().numpy()
+    a32 = accs[dcax.DCAX_FP32_MIXED][0].cpu().numpy()
+    out["mixed"]["M_Kw_err_vs_fp64_rel_max"] = float(np.max(np.abs(a32 - a64)) / np.max(np.abs(a64)))
+    # G = G0 - G0 M G0 / beta: the error in G is |G0|^2 |dM| / beta
+    G64, _ = walkers[dcax.DCAX_FP64].finalize(*accs[dcax.DCAX_FP64])
+    G32, _ = walkers[dcax.DCAX_FP32_MIXED].finalize(*accs[dcax.DCAX_FP32_MIXED])
+    G64, G32 = G64.cpu().numpy(), G32.cpu().numpy()
+    out["mixed"]["G_Kw_err_vs_fp64_rel_max"] = float(np.max(np.abs(G32 - G64)) / np.max(np.abs(G64)))
+    print(json.dumps({name: out}), flush=True)
+    RESULTS[name] = out
+    if os.path.isdir("gpurun_out"):
+        with open("gpurun_out/mixed_precision.json", "w") as f:
+            json.dump(RESULTS, f, indent=1)
+    assert out["fp64"]["ratio_err_scaled_max"] < 1e-10 and out["fp64"]["N_err_normwise"] < 1e-10
+    assert out["mixed"]["ratio_err_scaled_max"] < 1e-4
+    assert out["mixed"]["N_err_normwise"] < 1e-4
+    assert out["mixed"]["G_Kw_err_vs_fp64_rel_max"] < 1e-4
+    for w in walkers.values():
+        w.close()
