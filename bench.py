@@ -57,7 +57,7 @@ def roofline(stats0, stats1, precision):
     return out
 
 
-def run_gpu(precision, steps, warmup, seed_offset=0):
+def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False):
     import numpy as np
     import torch
     from paper_1901_01047_amd import dcax
@@ -67,6 +67,7 @@ def run_gpu(precision, steps, warmup, seed_offset=0):
     p = dcax.make_params(**params_kwargs(WORKLOAD, seed=cfg["seed"] + seed_offset), precision=prec,
                          refresh_every=32)
     w = dcax.Walker(p)
+    w.set_graphs(graphs)
     rng = np.random.default_rng(cfg["seed"] + 100 + seed_offset)
     w.set_config(*initial_config(rng, w.Nc, cfg["beta"], 280))
     acc, aux = w.new_accumulator()
@@ -143,6 +144,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
+    ap.add_argument("--graphs", choices=("on", "off"), default="off",
+                    help="replay each sweep as a captured hipGraph")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -156,7 +159,8 @@ def main():
     dcax.load()
     from paper_1901_01047_amd.workloads import CONFIGS
     c = CONFIGS[WORKLOAD]
-    r64, cfg_v = run_gpu("fp64", args.steps, args.warmup)
+    graphs = args.graphs == "on"
+    r64, cfg_v = run_gpu("fp64", args.steps, args.warmup, graphs=graphs)
     out = {
         "metric": "accepted vertex updates/s (CT-AUX walker, FP64) + N-update fold TFLOP/s (% roofline)",
         "value": r64["value"], "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -165,12 +169,13 @@ def main():
         "config": {"workload": f"{WORKLOAD}: 4x4 periodic Hubbard cluster, t=1, U=4, beta=10, "
                                f"mu={c['mu']} (n~0.95), K=1, 1 walker, k_s={c['submatrix_k']}, "
                                f"{c['n_freq']} Matsubara freqs, refresh every 32 sweeps",
-                   "step": "1 sweep + 1 measurement of M(K,iw_n)"},
+                   "step": "1 sweep + 1 measurement of M(K,iw_n)",
+                   "launch": "hipGraph per sweep" if graphs else "eager launches"},
         "roofline": r64["roofline"],
         "fp64": {k: v for k, v in r64.items() if k != "roofline"},
     }
     if not args.fp64_only:
-        r32, _ = run_gpu("mixed", args.steps, args.warmup)
+        r32, _ = run_gpu("mixed", args.steps, args.warmup, graphs=graphs)
         out["fp32_mixed"] = r32
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg_v, args.cpu_seconds)

@@ -107,7 +107,7 @@ typedef struct {
   double K_exp;            /* "expansion-parameter-K" */
   int32_t n_tau;           /* G0 table points on [0+, beta-], both ends included */
   int32_t precision;       /* dcax_precision */
-  int32_t submatrix_k;     /* "max-submatrix-size", 1..64 */
+  int32_t submatrix_k;     /* "max-submatrix-size", 1..64 (changeable later) */
   int32_t refresh_every;   /* sweeps between FP64 refreshes of N inside dcax_sweep; 0 = never */
   int32_t max_order;       /* largest expansion order the walker may reach */
   int32_t n_freq;          /* Matsubara frequencies measured, n = 0 .. n_freq-1 */
@@ -187,6 +187,24 @@ dcax_status dcax_measure_G(dcax_walker w, double* acc_dev, double* aux_dev);
  * (nullable when n_tau_out == 0). */
 dcax_status dcax_finalize_G(dcax_walker w, const double* acc_dev, const double* aux_dev,
                             double* Giw_dev, int32_t n_tau_out, double* Gtau_dev);
+
+/* Change the submatrix size of one walker (walker >= 0) or of all (-1),
+ * 1..64; takes effect at the next window.  The Markov chain is unaffected:
+ * the submatrix size only groups proposals (Sec. 2.3, submatrix updates). */
+dcax_status dcax_set_submatrix_k(dcax_walker w, int32_t walker, int32_t ks);
+
+/* Autotuner for the submatrix size: runs sweeps_per_trial generator-mode
+ * sweeps of the whole batch with each k_s in {8, 16, 24, 32, 48, 64}, timed
+ * with HIP events, and keeps the k_s with the most accepted updates per
+ * second (written to *chosen_ks, its rate to *rate_out; both nullable).  The
+ * trial sweeps are ordinary Markov-chain sweeps (they count as warm-up). */
+dcax_status dcax_autotune(dcax_walker w, int32_t sweeps_per_trial, int32_t* chosen_ks, double* rate_out);
+
+/* Replay generator-mode sweeps as hipGraphs (on != 0): one graph per
+ * (order bound rounded up to 64, window count), captured on first use and
+ * launched on a library-owned stream that is ordered after and before the
+ * caller's stream with events.  Off by default. */
+dcax_status dcax_set_graphs(dcax_walker w, int32_t on);
 
 /* Introspection and checkpointing; `walker` indexes the batch (0-based). */
 dcax_status dcax_get_order(dcax_walker w, int32_t walker, int32_t* k);

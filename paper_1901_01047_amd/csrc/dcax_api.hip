@@ -9,6 +9,7 @@
 // grids are sized by host-side upper bounds.
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -198,6 +199,16 @@ struct dcax_walker_s {
   long long replay_cap = 0;
   long long sweeps_done = 0;
   double last_drift = 0.0, max_drift = 0.0;
+  // sweeps replayed as hipGraphs (dcax_set_graphs)
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> fold, accept, window;
+  };
+  bool use_graphs = false;
+  hipStream_t gstream = nullptr;         // library stream the graphs run on
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::map<std::pair<int, int>, GraphEntry> graphs;
+  GraphEntry* capturing = nullptr;
   // live kernel timing (dcax_set_timing)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -216,7 +227,33 @@ struct dcax_walker_s {
     if (ptr) blocks.push_back(ptr);
     return ptr;
   }
+  // drops every captured sweep graph (their launch shapes or events are stale)
+  void clear_graphs() {
+    for (auto& kv : graphs) {
+      (void)hipGraphExecDestroy(kv.second.exec);
+      for (auto* v : {&kv.second.fold, &kv.second.accept, &kv.second.window})
+        for (auto& pr : *v) {
+          if (pr.first) ev_pool.push_back(pr.first);
+          if (pr.second) ev_pool.push_back(pr.second);
+        }
+    }
+    graphs.clear();
+  }
   void release() {
+    for (auto& kv : graphs) {
+      (void)hipGraphExecDestroy(kv.second.exec);
+      for (auto* v : {&kv.second.fold, &kv.second.accept, &kv.second.window})
+        for (auto& pr : *v) {
+          if (pr.first) (void)hipEventDestroy(pr.first);
+          if (pr.second) (void)hipEventDestroy(pr.second);
+        }
+    }
+    graphs.clear();
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (gstream) (void)hipStreamDestroy(gstream);
+    ev_in = ev_out = nullptr;
+    gstream = nullptr;
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     ev_pool.clear();
     for (void* b : blocks) {
@@ -252,7 +289,28 @@ struct dcax_walker_s {
     drain(pend_window, window_s, nullptr);
   }
   void mark(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, hipEvent_t a, hipEvent_t b) {
-    if (timing) v.push_back({a, b});
+    if (!timing) return;
+    if (capturing) {
+      // events recorded inside a captured graph belong to that graph
+      auto* dst = (&v == &pend_fold) ? &capturing->fold : (&v == &pend_accept) ? &capturing->accept
+                                                                                 : &capturing->window;
+      dst->push_back({a, b});
+    } else {
+      v.push_back({a, b});
+    }
+  }
+  // after a replayed graph has completed: its events hold this launch's times
+  void harvest(GraphEntry& g) {
+    auto acc = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double& sum, long long* n) {
+      for (auto& pr : v) {
+        float ms = 0.f;
+        if (pr.first && pr.second && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) sum += ms * 1e-3;
+        if (n) ++*n;
+      }
+    };
+    acc(g.fold, fold_s, &fold_launches);
+    acc(g.accept, accept_s, nullptr);
+    acc(g.window, window_s, nullptr);
   }
   hipEvent_t rec() {
     if (!timing) return nullptr;
@@ -410,6 +468,52 @@ void enqueue_measure(dcax_walker w, double* acc, double* aux) {
   hipLaunchKernelGGL(k_meas_K<T>, dim3(cdiv(nf, WG), ncm, 2 * W), dim3(WG), 0, s, vs, acc);
 }
 
+// One sweep's kernels (sweep start plus nwin windows with growing bounds).
+void enqueue_sweep(dcax_walker w, int kb, int nwin) {
+  if (w->mixed) hipLaunchKernelGGL(k_begin_sweep<float>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<float>());
+  else hipLaunchKernelGGL(k_begin_sweep<double>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<double>());
+  for (int i = 0; i < nwin; ++i) {
+    kb = std::min(w->mo_max, kb + w->ks_max);
+    if (w->mixed) enqueue_window<float>(w, kb, false);
+    else enqueue_window<double>(w, kb, false);
+  }
+}
+
+// Replays the sweep as a hipGraph captured once per (order bound, window
+// count).  Graphs run on the library's own stream, ordered after and before
+// the caller's stream by events.
+dcax_status launch_sweep_graph(dcax_walker w, int kb, int nwin) {
+  const int kq = std::min(w->mo_max, ((kb + 63) / 64) * 64);
+  const auto key = std::make_pair(kq, nwin);
+  auto it = w->graphs.find(key);
+  if (it == w->graphs.end()) {
+    if (!w->gstream) {
+      HIPCHK(hipStreamCreateWithFlags(&w->gstream, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming));
+    }
+    dcax_walker_s::GraphEntry g;
+    hipStream_t user = w->stream;
+    HIPCHK(hipStreamBeginCapture(w->gstream, hipStreamCaptureModeThreadLocal));
+    w->stream = w->gstream;
+    w->capturing = &g;
+    enqueue_sweep(w, kq, nwin);
+    w->capturing = nullptr;
+    w->stream = user;
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamEndCapture(w->gstream, &graph));
+    HIPCHK(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    it = w->graphs.emplace(key, std::move(g)).first;
+  }
+  HIPCHK(hipEventRecord(w->ev_in, w->stream));
+  HIPCHK(hipStreamWaitEvent(w->gstream, w->ev_in, 0));
+  HIPCHK(hipGraphLaunch(it->second.exec, w->gstream));
+  HIPCHK(hipEventRecord(w->ev_out, w->gstream));
+  HIPCHK(hipStreamWaitEvent(w->stream, w->ev_out, 0));
+  return DCAX_OK;
+}
+
 dcax_status sweep_rng(dcax_walker w, int n_sweeps) {
   dcax_status st = sync_all(w);
   if (st != DCAX_OK) return st;
@@ -419,15 +523,18 @@ dcax_status sweep_rng(dcax_walker w, int n_sweeps) {
       nwin = std::max(nwin, cdiv(std::max(x.k_host, 1), x.ks));
       kb = std::max(kb, x.k_host);
     }
-    if (w->mixed) hipLaunchKernelGGL(k_begin_sweep<float>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<float>());
-    else hipLaunchKernelGGL(k_begin_sweep<double>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<double>());
-    for (int i = 0; i < nwin; ++i) {
-      kb = std::min(w->mo_max, kb + w->ks_max);
-      if (w->mixed) enqueue_window<float>(w, kb, false);
-      else enqueue_window<double>(w, kb, false);
+    dcax_walker_s::GraphEntry* replayed = nullptr;
+    if (w->use_graphs) {
+      st = launch_sweep_graph(w, kb, nwin);
+      if (st != DCAX_OK) return st;
+      const int kq = std::min(w->mo_max, ((kb + 63) / 64) * 64);
+      replayed = &w->graphs[std::make_pair(kq, nwin)];
+    } else {
+      enqueue_sweep(w, kb, nwin);
     }
     HIPCHK(hipGetLastError());
     st = sync_all(w);
+    if (replayed && w->timing) w->harvest(*replayed);
     if (st != DCAX_OK) return st;
     // windows closed early by a carried removal leave proposals of the sweep
     for (;;) {
@@ -455,7 +562,7 @@ dcax_status sweep_rng(dcax_walker w, int n_sweeps) {
 
 template <typename T>
 size_t walker_bytes(const WalkerHost& x) {
-  const size_t ks = x.ks, cap = x.cap, ld = x.ld, Nc = x.geo.Nc, kp = x.kpad_cap;
+  const size_t ks = KS_MAX, cap = x.cap, ld = x.ld, Nc = x.geo.Nc, kp = x.kpad_cap;
   const size_t nf = std::max(x.p.n_freq, 1);
   size_t b = 0;
   auto add = [&](size_t n) { b += (n + 255) & ~size_t(255); };
@@ -511,7 +618,7 @@ void wire_walker(dcax_walker w, WalkerHost& x, int wid, char* base, Ctl* ctl) {
     base += (bytes + 255) & ~size_t(255);
     return (void*)p;
   };
-  const size_t ks = x.ks, cap = x.cap, ld = x.ld, Nc = x.geo.Nc, kp = x.kpad_cap;
+  const size_t ks = KS_MAX, cap = x.cap, ld = x.ld, Nc = x.geo.Nc, kp = x.kpad_cap;
   const size_t nf = std::max(x.p.n_freq, 1);
   v.Nc = (int)Nc;
   v.n_tau = x.p.n_tau;
@@ -646,6 +753,28 @@ dcax_status repoint_replay(dcax_walker w) {
 template <typename T>
 const View<T>& view0(dcax_walker w, int i) { return hview<T>(w->wk[i]); }
 
+template <typename T>
+dcax_status upload_views(dcax_walker w) {
+  std::vector<View<T>> hv(w->W);
+  for (int i = 0; i < w->W; ++i) hv[i] = hview<T>(w->wk[i]);
+  HIPCHK(hipMemcpyAsync(w->d_views, hv.data(), sizeof(View<T>) * w->W, hipMemcpyHostToDevice, w->stream));
+  HIPCHK(hipStreamSynchronize(w->stream));
+  return DCAX_OK;
+}
+
+dcax_status set_ks(dcax_walker w, int walker, int ks) {
+  for (int i = 0; i < w->W; ++i) {
+    if (walker >= 0 && i != walker) continue;
+    w->wk[i].ks = ks;
+    w->wk[i].v64.ks = ks;
+    w->wk[i].v32.ks = ks;
+  }
+  w->ks_max = 0;
+  for (const auto& x : w->wk) w->ks_max = std::max(w->ks_max, x.ks);
+  w->clear_graphs();
+  return w->mixed ? upload_views<float>(w) : upload_views<double>(w);
+}
+
 }  // namespace
 
 // ================================================================= C ABI
@@ -693,7 +822,7 @@ dcax_status dcax_walker_create(const dcax_params* p, int32_t n_walkers, const dc
     build_geometry(p[i].cluster, x.geo);
     x.ks = p[i].submatrix_k;
     x.max_order = p[i].max_order;
-    x.cap = ((p[i].max_order + x.ks + 63) / 64) * 64;
+    x.cap = ((p[i].max_order + KS_MAX + 63) / 64) * 64;
     x.ld = x.cap;
     x.kpad_cap = x.cap + 16 * x.geo.Nc;
     x.gamma = std::acosh(1.0 + p[i].U * p[i].beta * (double)x.geo.Nc / (2.0 * p[i].K_exp));
@@ -969,9 +1098,70 @@ dcax_status dcax_get_stats(dcax_walker w, int32_t walker, dcax_stats* out) {
   return st;
 }
 
+dcax_status dcax_set_submatrix_k(dcax_walker w, int32_t walker, int32_t ks) {
+  if (!w) return fail(DCAX_E_INVAL, "walker is NULL");
+  if (walker < -1 || walker >= w->W) return fail(DCAX_E_INVAL, "walker index out of range");
+  if (ks < 1 || ks > KS_MAX) return fail(DCAX_E_INVAL, "submatrix_k must be in 1..64");
+  dcax_status st = sync_all(w);
+  if (st != DCAX_OK) return st;
+  return set_ks(w, walker, ks);
+}
+
+dcax_status dcax_autotune(dcax_walker w, int32_t sweeps_per_trial, int32_t* chosen_ks, double* rate_out) {
+  dcax_status st = check_latched(w);
+  if (st != DCAX_OK) return st;
+  if (sweeps_per_trial < 1) return fail(DCAX_E_INVAL, "sweeps_per_trial must be >= 1");
+  static const int cand[] = {8, 16, 24, 32, 48, 64};
+  int best = w->ks_max;
+  double best_rate = -1.0;
+  for (int ks : cand) {
+    st = set_ks(w, -1, ks);
+    if (st != DCAX_OK) return st;
+    st = sync_all(w);
+    if (st != DCAX_OK) return st;
+    long long a0 = 0;
+    for (const Ctl& h : w->h_ctl) a0 += h.n_acc_ins + h.n_acc_rem;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, w->stream));
+    st = sweep_rng(w, sweeps_per_trial);
+    if (st != DCAX_OK) return st;
+    HIPCHK(hipEventRecord(e1, w->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    st = sync_all(w);
+    if (st != DCAX_OK) return st;
+    long long a1 = 0;
+    for (const Ctl& h : w->h_ctl) a1 += h.n_acc_ins + h.n_acc_rem;
+    const double rate = ms > 0.f ? (double)(a1 - a0) / (ms * 1e-3) : 0.0;
+    if (rate > best_rate) {
+      best_rate = rate;
+      best = ks;
+    }
+  }
+  st = set_ks(w, -1, best);
+  if (st != DCAX_OK) return st;
+  if (chosen_ks) *chosen_ks = best;
+  if (rate_out) *rate_out = best_rate;
+  return DCAX_OK;
+}
+
+dcax_status dcax_set_graphs(dcax_walker w, int32_t on) {
+  if (!w) return fail(DCAX_E_INVAL, "walker is NULL");
+  dcax_status st = sync_all(w);
+  w->use_graphs = on != 0;
+  if (!w->use_graphs) w->clear_graphs();
+  return st;
+}
+
 dcax_status dcax_set_timing(dcax_walker w, int32_t on) {
   if (!w) return fail(DCAX_E_INVAL, "walker is NULL");
   dcax_status st = sync_all(w);  // drains pending events
+  if (w->timing != (on != 0)) w->clear_graphs();
   w->timing = on != 0;
   return st;
 }

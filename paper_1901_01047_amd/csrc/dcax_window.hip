@@ -146,16 +146,32 @@ __global__ void __launch_bounds__(WG) k_prep_rng(const View<T>* __restrict__ vs)
   if (carry >= 0)
     for (int i = t; i < k0; i += WG)
       if (w.v_id[i] == carry) carry_slot_s = i;
+  // the window's uniforms, one proposal per thread
+  __shared__ double u_s[KS_MAX][5];
+  __shared__ int slot0_s[KS_MAX];
+  const long long pos = c->pos;
+  if (t < nP) {
+    const long long g = pos + t;
+    double u_dummy;
+    uniforms2(seed, g, 0u, u_s[t][0], u_s[t][1]);
+    uniforms2(seed, g, 1u, u_s[t][2], u_s[t][3]);
+    uniforms2(seed, g, 2u, u_s[t][4], u_dummy);
+    int slot = -1;
+    if (k0 > 0) {
+      double ub, ui;
+      uniforms2(seed, g, 3u, ub, ui);
+      slot = (int)(ui * (double)k0);
+      if (slot >= k0) slot = k0 - 1;
+    }
+    slot0_s[t] = slot;
+  }
   __syncthreads();
   if (t != 0) return;
-  const long long pos = c->pos;
   int nE = 0, nC = 0;
   for (int j = 0; j < nP; ++j) {
     const long long g = pos + j;
-    double u_kind, u_site, u_tau, u_spin, u_acc, u_dummy;
-    uniforms2(seed, g, 0u, u_kind, u_site);
-    uniforms2(seed, g, 1u, u_tau, u_spin);
-    uniforms2(seed, g, 2u, u_acc, u_dummy);
+    const double u_kind = u_s[j][0], u_site = u_s[j][1], u_tau = u_s[j][2], u_spin = u_s[j][3];
+    const double u_acc = u_s[j][4];
     WinProp p;
     p.forced = -1;
     p.carried = 0;
@@ -188,12 +204,7 @@ __global__ void __launch_bounds__(WG) k_prep_rng(const View<T>* __restrict__ vs)
       p.el = e;
     } else {
       p.kind = 1;
-      if (k0 > 0) {
-        double ub, ui;
-        uniforms2(seed, g, 3u, ub, ui);
-        slot = (int)(ui * (double)k0);
-        if (slot >= k0) slot = k0 - 1;
-      }
+      slot = slot0_s[j];     // the first attempt's window-start vertex
     }
     if (slot >= 0) {
       int e = -1;
@@ -380,8 +391,11 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
   const uint64_t seed = w.seed;
   Ctl* c = w.ctl;
   if (!c->active) return;
-  __shared__ double gram_s[2][KS_MAX * KS_MAX];
-  __shared__ double ginv_s[2][KS_MAX * KS_MAX];
+  // LDS rows are padded to LS doubles: with a stride of 64 doubles every lane
+  // reading one column of a tile would hit the same bank.
+  constexpr int LS = KS_MAX + 1;
+  __shared__ double gram_s[2][KS_MAX * LS];
+  __shared__ double ginv_s[2][KS_MAX * LS];
   __shared__ double Lv[2][KS_MAX], Rv[2][KS_MAX], dl_s[2][KS_MAX];
   __shared__ int S_s[KS_MAX], pos_s[KS_MAX], insl_s[KS_MAX];
   __shared__ double rat_s[2], schur_s[2], D_s[2];
@@ -394,7 +408,8 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
   const int nE = c->nE, nP = c->nP, k0 = c->k0;
   for (int idx = t; idx < 2 * KS_MAX * KS_MAX; idx += WG) {
     const int sp = idx / (KS_MAX * KS_MAX), r = idx % (KS_MAX * KS_MAX);
-    gram_s[sp][r] = ((r / KS_MAX) < nE && (r % KS_MAX) < nE) ? w.gram[sp][r] : 0.0;
+    const int ra = r / KS_MAX, rb = r % KS_MAX;
+    gram_s[sp][ra * LS + rb] = (ra < nE && rb < nE) ? w.gram[sp][r] : 0.0;
   }
   if (t < KS_MAX) pos_s[t] = -1;
   if (t < nP) wp_s[t] = w.wp[t];
@@ -469,20 +484,20 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
     const int pq = pos_s[q];
     const int is_c = cand_s[q] >= 0;
     if (pq >= 0) {
-      if (t < 2) rat_s[t] = ginv_s[t][pq * KS_MAX + pq] / (-dl_s[t][pq]);
+      if (t < 2) rat_s[t] = ginv_s[t][pq * LS + pq] / (-dl_s[t][pq]);
     } else if (wv < 2) {
       const int sp = wv;
       const double ev = w.ev[sp][s01(spin_s[q])];
       const double D = is_c ? ev - 1.0 : 1.0 / ev - 1.0;
       double L = 0.0;
       if (lane < m) {
-        for (int b = 0; b < m; ++b) L += ginv_s[sp][lane * KS_MAX + b] * gram_s[sp][S_s[b] * KS_MAX + q];
+        for (int b = 0; b < m; ++b) L += ginv_s[sp][lane * LS + b] * gram_s[sp][S_s[b] * LS + q];
         Lv[sp][lane] = L;
       }
-      double part = (lane < m) ? gram_s[sp][q * KS_MAX + S_s[lane]] * L : 0.0;
+      double part = (lane < m) ? gram_s[sp][q * LS + S_s[lane]] * L : 0.0;
       part = wave_sum(part);
       if (lane == 0) {
-        const double sch = gram_s[sp][q * KS_MAX + q] - (1.0 + D) / D - part;
+        const double sch = gram_s[sp][q * LS + q] - (1.0 + D) / D - part;
         schur_s[sp] = sch;
         D_s[sp] = D;
         rat_s[sp] = -D * sch;
@@ -534,7 +549,7 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
         const int sp = wv;
         if (lane < m) {
           double Rr = 0.0;
-          for (int a = 0; a < m; ++a) Rr += gram_s[sp][q * KS_MAX + S_s[a]] * ginv_s[sp][a * KS_MAX + lane];
+          for (int a = 0; a < m; ++a) Rr += gram_s[sp][q * LS + S_s[a]] * ginv_s[sp][a * LS + lane];
           Rv[sp][lane] = Rr;
         }
       }
@@ -544,11 +559,11 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
         const int sp = idx / (mm * mm), r = idx % (mm * mm), a = r / mm, b = r % mm;
         const double inv = 1.0 / schur_s[sp];
         double v;
-        if (a < m && b < m) v = ginv_s[sp][a * KS_MAX + b] + Lv[sp][a] * Rv[sp][b] * inv;
+        if (a < m && b < m) v = ginv_s[sp][a * LS + b] + Lv[sp][a] * Rv[sp][b] * inv;
         else if (a == m && b < m) v = -Rv[sp][b] * inv;
         else if (a < m) v = -Lv[sp][a] * inv;
         else v = inv;
-        ginv_s[sp][a * KS_MAX + b] = v;
+        ginv_s[sp][a * LS + b] = v;
       }
       __syncthreads();
       if (t == 0) {
@@ -563,24 +578,24 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
       const int js = pq, last = m - 1;
       if (t < 2 * m) {
         const int sp = t / m, a = t % m;
-        Lv[sp][a] = ginv_s[sp][a * KS_MAX + js];
-        Rv[sp][a] = ginv_s[sp][js * KS_MAX + a];
+        Lv[sp][a] = ginv_s[sp][a * LS + js];
+        Rv[sp][a] = ginv_s[sp][js * LS + a];
       }
       __syncthreads();
       for (int idx = t; idx < 2 * m * m; idx += WG) {
         const int sp = idx / (m * m), r = idx % (m * m), a = r / m, b = r % m;
-        ginv_s[sp][a * KS_MAX + b] -= Lv[sp][a] * Rv[sp][b] / Lv[sp][js];
+        ginv_s[sp][a * LS + b] -= Lv[sp][a] * Rv[sp][b] / Lv[sp][js];
       }
       __syncthreads();
       if (js != last) {
         for (int idx = t; idx < 2 * m; idx += WG) {
           const int sp = idx / m, b = idx % m;
-          ginv_s[sp][js * KS_MAX + b] = ginv_s[sp][last * KS_MAX + b];
+          ginv_s[sp][js * LS + b] = ginv_s[sp][last * LS + b];
         }
         __syncthreads();
         for (int idx = t; idx < 2 * m; idx += WG) {
           const int sp = idx / m, a = idx % m;
-          ginv_s[sp][a * KS_MAX + js] = ginv_s[sp][a * KS_MAX + last];
+          ginv_s[sp][a * LS + js] = ginv_s[sp][a * LS + last];
         }
       }
       __syncthreads();
@@ -600,7 +615,7 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
   const int m = m_s;
   for (int idx = t; idx < 2 * m * m; idx += WG) {
     const int sp = idx / (m * m), r = idx % (m * m), a = r / m, b = r % m;
-    w.ginv[sp][a * KS_MAX + b] = ginv_s[sp][a * KS_MAX + b];
+    w.ginv[sp][a * KS_MAX + b] = ginv_s[sp][a * LS + b];
   }
   // Epilogue: the fold's column order, the new vertex arrays and the plan
   // that removes the deleted rows and columns of N.  Inserted spins take
@@ -608,11 +623,10 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
   // surviving slots above it (remap[dst] = src, moves[] = (dst, src) pairs).
   // Nothing later in the window reads the vertex arrays or the order, so
   // both are final here.
-  __shared__ int ins_s[KS_MAX], hole_s[KS_MAX], src_s[KS_MAX], mi_s, nh_s;
+  __shared__ int ins_s[KS_MAX], hole_s[KS_MAX], src_s[KS_MAX], rem[KS_MAX], mi_s, nh_s;
   const int knew = kcur_s;
   if (t == 0) {
     int mi = 0, mr = 0;
-    int rem[KS_MAX];
     for (int s = 0; s < m; ++s) {
       const int e = S_s[s];
       w.S[s] = e;

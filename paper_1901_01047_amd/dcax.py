@@ -77,7 +77,8 @@ VERTEX_DTYPE = np.dtype([("id", np.int64), ("site", np.int32), ("aux_spin", np.i
 # exported symbols, in the order include/dcax.h declares them
 EXPORTS = ("dcax_walker_create", "dcax_walker_destroy", "dcax_sweep", "dcax_refresh", "dcax_measure_G",
            "dcax_finalize_G", "dcax_get_order", "dcax_copy_N", "dcax_get_config", "dcax_set_config",
-           "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table", "dcax_cluster", "dcax_last_error")
+           "dcax_set_submatrix_k", "dcax_autotune", "dcax_set_graphs", "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table",
+           "dcax_cluster", "dcax_last_error")
 
 _lib = None
 
@@ -105,6 +106,9 @@ def load():
         "dcax_set_config": [vp, ctypes.c_int32, vp, ctypes.c_int32],
         "dcax_get_stats": [vp, ctypes.c_int32, P(Stats)],
         "dcax_set_timing": [vp, ctypes.c_int32],
+        "dcax_set_submatrix_k": [vp, ctypes.c_int32, ctypes.c_int32],
+        "dcax_autotune": [vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_double)],
+        "dcax_set_graphs": [vp, ctypes.c_int32],
         "dcax_copy_g0_table": [vp, ctypes.c_int32, vp],
         "dcax_cluster": [P(Params), P(ctypes.c_int32), vp, vp],
     }
@@ -260,6 +264,19 @@ class Walker:
         s = Stats()
         _check(load().dcax_get_stats(self._h, int(walker), ctypes.byref(s)))
         return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def set_submatrix_k(self, ks, walker=-1):
+        _check(load().dcax_set_submatrix_k(self._h, int(walker), int(ks)))
+
+    def autotune(self, sweeps_per_trial=5):
+        """Pick the submatrix size with the most accepted updates/s; returns (k_s, rate)."""
+        ks = ctypes.c_int32()
+        rate = ctypes.c_double()
+        _check(load().dcax_autotune(self._h, int(sweeps_per_trial), ctypes.byref(ks), ctypes.byref(rate)))
+        return ks.value, rate.value
+
+    def set_graphs(self, on=True):
+        _check(load().dcax_set_graphs(self._h, 1 if on else 0))
 
     def set_timing(self, on=True):
         _check(load().dcax_set_timing(self._h, 1 if on else 0))
