@@ -87,6 +87,7 @@ class Walker:
         self.m = model
         self.rng = np.random.Generator(np.random.MT19937(seed))
         self.k_s = int(k_s)
+        self.frozen_length = 0
         self.r = np.zeros(0, np.int64)
         self.t = np.zeros(0, np.float64)
         self.s = np.zeros(0, np.int64)
@@ -230,8 +231,20 @@ class Walker:
         return 1, acc
 
     def sweep_length(self):
+        """Proposals in the next sweep, a multiple of k_s.
+
+        The length is frozen by freeze_sweep_length (after the warm-up); until
+        then it is max(k, 1) for the current order k.  Measuring between
+        sweeps whose length depends on the state would sample a distribution
+        other than the weight (the order of the atom shifts visibly), so a
+        measured chain uses a frozen length."""
         ks = self.k_s
-        return int(math.ceil(max(self.k, 1) / ks) * ks)
+        L = self.frozen_length if self.frozen_length else max(self.k, 1)
+        return int(math.ceil(L / ks) * ks)
+
+    def freeze_sweep_length(self, mean_order):
+        """Fix the sweep length at the rounded mean order (at least 1)."""
+        self.frozen_length = max(int(round(mean_order)), 1)
 
     def sweep(self):
         for _ in range(self.sweep_length()):

@@ -14,8 +14,14 @@ def run_chain(model, seed, sweeps, warmup=100, n_freq=64, k_s=16, initial_order=
     w = ctaux.Walker(model, seed, k_s=k_s, record=record)
     if initial_order:
         w.random_config(initial_order)
-    for _ in range(warmup):
+    warm_orders = []
+    for n in range(warmup):
+        if 2 * n >= warmup:
+            warm_orders.append(w.k)
         w.sweep()
+    # measured sweeps have a fixed length: the mean order over the second
+    # half of the warm-up (the current order without a warm-up)
+    w.freeze_sweep_length(np.mean(warm_orders) if warm_orders else w.k)
     acc = measure.Accumulator(model, n_freq)
     orders = []
     for n in range(sweeps):

@@ -115,3 +115,36 @@ def test_free_limit_is_poisson():
         assert np.allclose(w.N[sp], np.eye(w.k))
     assert abs(np.mean(ks) - 2.0) < 0.1
     assert abs(np.var(ks) - 2.0) < 0.3
+
+
+def test_atom_order_distribution_per_sweep():
+    """Sampling once per sweep reproduces the order law when the sweep length
+    is frozen after the warm-up (as the library's and the oracle's measured
+    chains do); a length that follows the current order would not."""
+    U, beta, K = 4.0, 2.0, 1.0
+    m = atom(U=U, beta=beta, K_exp=K)
+    w = ctaux.Walker(m, seed=9, k_s=4)
+    warm = []
+    for n in range(400):
+        if n >= 200:
+            warm.append(w.k)
+        w.sweep()
+    w.freeze_sweep_length(np.mean(warm))
+    assert w.sweep_length() % 4 == 0 and w.sweep_length() >= 4
+    orders = []
+    for _ in range(14000):
+        w.sweep()
+        orders.append(w.k)
+    orders = np.array(orders)
+    kmax = 25
+    ks = np.arange(kmax + 1)
+    a, b = K, K + beta * U / 2
+    logp = np.logaddexp(ks * np.log(a), ks * np.log(b)) - np.array([math.lgamma(k + 1) for k in ks])
+    p = np.exp(logp - logp.max())
+    p /= p.sum()
+    B = 40
+    blocks = orders[: (len(orders) // B) * B].reshape(B, -1)
+    hist = np.array([np.bincount(np.minimum(x, kmax), minlength=kmax + 1) / len(x) for x in blocks])
+    est, err = hist.mean(axis=0), hist.std(axis=0, ddof=1) / np.sqrt(B)
+    z = np.abs(est - p) / np.maximum(err, 1e-4)
+    assert np.max(z[:14]) < 4.5, list(zip(est[:14], p[:14], z[:14]))
