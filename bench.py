@@ -64,8 +64,8 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False):
     from paper_1901_01047_amd.workloads import CONFIGS, params_kwargs
     cfg = CONFIGS[WORKLOAD]
     prec = dcax.DCAX_FP64 if precision == "fp64" else dcax.DCAX_FP32_MIXED
-    p = dcax.make_params(**params_kwargs(WORKLOAD, seed=cfg["seed"] + seed_offset), precision=prec,
-                         refresh_every=32)
+    p = dcax.make_params(**params_kwargs(WORKLOAD, seed=cfg["seed"] + seed_offset, warmup_sweeps=warmup),
+                         precision=prec, refresh_every=32)
     w = dcax.Walker(p)
     w.set_graphs(graphs)
     rng = np.random.default_rng(cfg["seed"] + 100 + seed_offset)

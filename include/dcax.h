@@ -112,6 +112,9 @@ typedef struct {
   int32_t max_order;       /* largest expansion order the walker may reach */
   int32_t n_freq;          /* Matsubara frequencies measured, n = 0 .. n_freq-1 */
   uint64_t seed;           /* "seed" of the walker's counter-based generator */
+  int32_t warmup_sweeps;   /* "warm-up-sweeps": generator sweeps after which the sweep length freezes */
+  int32_t sweep_length;    /* proposals per sweep (rounded up to a multiple of submatrix_k);
+                              0 = taken from the warm-up, see dcax_sweep */
 } dcax_params;
 
 /* Counters since creation or the last dcax_set_config (timings and drifts
@@ -150,10 +153,16 @@ dcax_status dcax_walker_destroy(dcax_walker w);
 
 /* Run Markov-chain proposals (Sec. 2.3, Metropolis insertion/removal fused
  * into submatrix updates of at most submatrix_k proposals).
- *   replay == NULL: n_sweeps sweeps of every walker from its own generator; a
- *     sweep is max(k, 1) proposals rounded up to a multiple of submatrix_k, k
- *     taken at the sweep's start.  N is refreshed every refresh_every sweeps
- *     (walker 0's parameter).
+ *   replay == NULL: n_sweeps sweeps of every walker from its own generator.
+ *     A sweep is a fixed number L of proposals, rounded up to a multiple of
+ *     submatrix_k: L = sweep_length if that is positive; otherwise, during
+ *     the first warmup_sweeps sweeps L = max(k, 1) with k the order at the
+ *     sweep's start, and when they end L freezes at the mean order over
+ *     their second half (rounded, at least 1).  A length that depends on the
+ *     current state would bias every quantity measured between sweeps, so
+ *     measurements belong after the warm-up.  dcax_set_config restarts the
+ *     warm-up count.  N is refreshed every refresh_every sweeps (walker 0's
+ *     parameter).
  *   replay != NULL (single-walker handles only): the n_replay records are
  *     replayed in order with forced decisions (n_sweeps is ignored);
  *     ratio_out (nullable, length n_replay) receives the library's full
@@ -203,7 +212,9 @@ dcax_status dcax_autotune(dcax_walker w, int32_t sweeps_per_trial, int32_t* chos
 /* Replay generator-mode sweeps as hipGraphs (on != 0): one graph per
  * (order bound rounded up to 64, window count), captured on first use and
  * launched on a library-owned stream that is ordered after and before the
- * caller's stream with events.  Off by default. */
+ * caller's stream with events.  Off by default.  With timing on, a replayed
+ * sweep is timed as a whole (window_seconds); the fold and accept kernel
+ * times of dcax_stats come from eagerly launched windows only. */
 dcax_status dcax_set_graphs(dcax_walker w, int32_t on);
 
 /* Introspection and checkpointing; `walker` indexes the batch (0-based). */

@@ -142,8 +142,21 @@ __global__ void k_begin_sweep(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
   Ctl* c = w.ctl;
   if (c->status != 0) return;
-  const long long k = c->k > 1 ? c->k : 1;
-  c->end = c->pos + ((k + w.ks - 1) / w.ks) * w.ks;
+  long long L = c->sweep_len;
+  if (L == 0) {
+    // warm-up: the length follows the order; the second half's mean order
+    // becomes the frozen length when the warm-up ends
+    L = c->k > 1 ? c->k : 1;
+    if (2 * c->n_sweeps >= w.warmup) {
+      c->warm_sum += (double)c->k;
+      c->warm_n += 1;
+    }
+    if (c->n_sweeps + 1 >= w.warmup) {
+      const long long mean = llround(c->warm_sum / (double)(c->warm_n > 0 ? c->warm_n : 1));
+      c->sweep_len = mean > 1 ? mean : 1;
+    }
+  }
+  c->end = c->pos + ((L + w.ks - 1) / w.ks) * w.ks;
   c->n_sweeps += 1;
 }
 
@@ -199,16 +212,15 @@ struct dcax_walker_s {
   long long replay_cap = 0;
   long long sweeps_done = 0;
   double last_drift = 0.0, max_drift = 0.0;
-  // sweeps replayed as hipGraphs (dcax_set_graphs)
-  struct GraphEntry {
-    hipGraphExec_t exec = nullptr;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> fold, accept, window;
-  };
+  // sweeps replayed as hipGraphs (dcax_set_graphs).  Events recorded inside
+  // a captured graph cannot be timed on this runtime (hipEventElapsedTime
+  // rejects them), so a replayed sweep is timed as a whole from events
+  // around its launch, and per-kernel times come from eager sweeps.
   bool use_graphs = false;
   hipStream_t gstream = nullptr;         // library stream the graphs run on
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  std::map<std::pair<int, int>, GraphEntry> graphs;
-  GraphEntry* capturing = nullptr;
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  bool capturing = false;
   // live kernel timing (dcax_set_timing)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -229,26 +241,11 @@ struct dcax_walker_s {
   }
   // drops every captured sweep graph (their launch shapes or events are stale)
   void clear_graphs() {
-    for (auto& kv : graphs) {
-      (void)hipGraphExecDestroy(kv.second.exec);
-      for (auto* v : {&kv.second.fold, &kv.second.accept, &kv.second.window})
-        for (auto& pr : *v) {
-          if (pr.first) ev_pool.push_back(pr.first);
-          if (pr.second) ev_pool.push_back(pr.second);
-        }
-    }
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
   }
   void release() {
-    for (auto& kv : graphs) {
-      (void)hipGraphExecDestroy(kv.second.exec);
-      for (auto* v : {&kv.second.fold, &kv.second.accept, &kv.second.window})
-        for (auto& pr : *v) {
-          if (pr.first) (void)hipEventDestroy(pr.first);
-          if (pr.second) (void)hipEventDestroy(pr.second);
-        }
-    }
-    graphs.clear();
+    clear_graphs();
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (gstream) (void)hipStreamDestroy(gstream);
@@ -289,31 +286,10 @@ struct dcax_walker_s {
     drain(pend_window, window_s, nullptr);
   }
   void mark(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, hipEvent_t a, hipEvent_t b) {
-    if (!timing) return;
-    if (capturing) {
-      // events recorded inside a captured graph belong to that graph
-      auto* dst = (&v == &pend_fold) ? &capturing->fold : (&v == &pend_accept) ? &capturing->accept
-                                                                                 : &capturing->window;
-      dst->push_back({a, b});
-    } else {
-      v.push_back({a, b});
-    }
-  }
-  // after a replayed graph has completed: its events hold this launch's times
-  void harvest(GraphEntry& g) {
-    auto acc = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double& sum, long long* n) {
-      for (auto& pr : v) {
-        float ms = 0.f;
-        if (pr.first && pr.second && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) sum += ms * 1e-3;
-        if (n) ++*n;
-      }
-    };
-    acc(g.fold, fold_s, &fold_launches);
-    acc(g.accept, accept_s, nullptr);
-    acc(g.window, window_s, nullptr);
+    if (timing && a && b) v.push_back({a, b});
   }
   hipEvent_t rec() {
-    if (!timing) return nullptr;
+    if (!timing || capturing) return nullptr;
     hipEvent_t e = ev();
     if (e) (void)hipEventRecord(e, stream);
     return e;
@@ -352,6 +328,8 @@ dcax_status validate(const dcax_params* p) {
   if (p->refresh_every < 0) return fail(DCAX_E_INVAL, "refresh_every must be >= 0");
   if (p->max_order < 1 || p->max_order > 32768) return fail(DCAX_E_INVAL, "max_order must be in 1..32768");
   if (p->n_freq < 0 || p->n_freq > 65536) return fail(DCAX_E_INVAL, "n_freq out of range");
+  if (p->warmup_sweeps < 0) return fail(DCAX_E_INVAL, "warmup_sweeps must be >= 0");
+  if (p->sweep_length < 0) return fail(DCAX_E_INVAL, "sweep_length must be >= 0");
   Geometry g;
   if (!build_geometry(p->cluster, g)) return fail(DCAX_E_INVAL, "degenerate or too large cluster");
   return DCAX_OK;
@@ -398,16 +376,16 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   const int kb1 = std::max(kb, 1);
   hipEvent_t e_w0 = w->rec();
   if (replay) hipLaunchKernelGGL(k_prep_replay<T>, dim3(1, 1, W), dim3(WG), 0, s, vs);
-  else hipLaunchKernelGGL(k_prep_rng<T>, dim3(1, 1, W), dim3(WG), 0, s, vs);
+  else hipLaunchKernelGGL(k_prep_rng<T>, dim3(1, 1, W), dim3(PW), 0, s, vs);
   hipLaunchKernelGGL(k_gather<T>, dim3(cdiv(kb1, WG), ks, W), dim3(WG), 0, s, vs);
-  hipLaunchKernelGGL(k_cand_x<T>, dim3(cdiv(kb1, 64), 2, W), dim3(WG), 0, s, vs);
+  hipLaunchKernelGGL(k_cand_x<T>, dim3(cdiv(kb1, 16), 2, W), dim3(WG), 0, s, vs);
   hipLaunchKernelGGL(k_gram<T>, dim3(ks, 2, W), dim3(WG), 0, s, vs);
   hipEvent_t e_a0 = w->rec();
-  hipLaunchKernelGGL(k_accept<T>, dim3(1, 1, W), dim3(WG), 0, s, vs);
+  hipLaunchKernelGGL(k_accept<T>, dim3(1, 1, W), dim3(AW), 0, s, vs);
   hipEvent_t e_a1 = w->rec();
   w->mark(w->pend_accept, e_a0, e_a1);
-  hipLaunchKernelGGL(k_ygemm<T>, dim3(cdiv(kb1, 64), 2, W), dim3(WG), 0, s, vs);
-  hipLaunchKernelGGL(k_fold_prep<T>, dim3(cdiv(kx, WG), 2, W), dim3(WG), 0, s, vs);
+  hipLaunchKernelGGL(k_ygemm<T>, dim3(cdiv(kb1, 16), 2, W), dim3(WG), 0, s, vs);
+  hipLaunchKernelGGL(k_fold_prep<T>, dim3(cdiv(kx, 64), 2, W), dim3(WG), 0, s, vs);
   hipEvent_t e_f0 = w->rec();
   hipLaunchKernelGGL(k_fold<T>, dim3(cdiv(kx, 64), cdiv(kx, 64), 2 * W), dim3(WG), 0, s, vs);
   hipEvent_t e_f1 = w->rec();
@@ -492,23 +470,34 @@ dcax_status launch_sweep_graph(dcax_walker w, int kb, int nwin) {
       HIPCHK(hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming));
     }
-    dcax_walker_s::GraphEntry g;
+    hipGraphExec_t exec = nullptr;
     hipStream_t user = w->stream;
     HIPCHK(hipStreamBeginCapture(w->gstream, hipStreamCaptureModeThreadLocal));
     w->stream = w->gstream;
-    w->capturing = &g;
+    w->capturing = true;
     enqueue_sweep(w, kq, nwin);
-    w->capturing = nullptr;
+    w->capturing = false;
     w->stream = user;
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamEndCapture(w->gstream, &graph));
-    HIPCHK(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
-    it = w->graphs.emplace(key, std::move(g)).first;
+    HIPCHK(ie);
+    it = w->graphs.emplace(key, exec).first;
   }
   HIPCHK(hipEventRecord(w->ev_in, w->stream));
   HIPCHK(hipStreamWaitEvent(w->gstream, w->ev_in, 0));
-  HIPCHK(hipGraphLaunch(it->second.exec, w->gstream));
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (w->timing) {
+    t0 = w->ev();
+    if (t0) HIPCHK(hipEventRecord(t0, w->gstream));
+  }
+  HIPCHK(hipGraphLaunch(it->second, w->gstream));
+  if (w->timing) {
+    t1 = w->ev();
+    if (t1) HIPCHK(hipEventRecord(t1, w->gstream));
+    w->mark(w->pend_window, t0, t1);
+  }
   HIPCHK(hipEventRecord(w->ev_out, w->gstream));
   HIPCHK(hipStreamWaitEvent(w->stream, w->ev_out, 0));
   return DCAX_OK;
@@ -519,22 +508,20 @@ dcax_status sweep_rng(dcax_walker w, int n_sweeps) {
   if (st != DCAX_OK) return st;
   for (int sw = 0; sw < n_sweeps; ++sw) {
     int nwin = 1, kb = 0;
-    for (const auto& x : w->wk) {
-      nwin = std::max(nwin, cdiv(std::max(x.k_host, 1), x.ks));
+    for (int i = 0; i < w->W; ++i) {
+      const auto& x = w->wk[i];
+      const long long L = w->h_ctl[i].sweep_len > 0 ? w->h_ctl[i].sweep_len : std::max(x.k_host, 1);
+      nwin = std::max(nwin, (int)std::min<long long>((L + x.ks - 1) / x.ks, 1 << 20));
       kb = std::max(kb, x.k_host);
     }
-    dcax_walker_s::GraphEntry* replayed = nullptr;
     if (w->use_graphs) {
       st = launch_sweep_graph(w, kb, nwin);
       if (st != DCAX_OK) return st;
-      const int kq = std::min(w->mo_max, ((kb + 63) / 64) * 64);
-      replayed = &w->graphs[std::make_pair(kq, nwin)];
     } else {
       enqueue_sweep(w, kb, nwin);
     }
     HIPCHK(hipGetLastError());
     st = sync_all(w);
-    if (replayed && w->timing) w->harvest(*replayed);
     if (st != DCAX_OK) return st;
     // windows closed early by a carried removal leave proposals of the sweep
     for (;;) {
@@ -626,6 +613,7 @@ void wire_walker(dcax_walker w, WalkerHost& x, int wid, char* base, Ctl* ctl) {
   v.cap = x.cap;
   v.ld = x.ld;
   v.max_order = x.max_order;
+  v.warmup = x.p.warmup_sweeps;
   v.beta = x.p.beta;
   v.h = x.p.beta / (double)(x.p.n_tau - 1);
   v.gamma = x.gamma;
@@ -727,9 +715,10 @@ dcax_status create_walkers(dcax_walker w) {
   }
   std::vector<Ctl> h(w->W);
   std::memset(h.data(), 0, sizeof(Ctl) * w->W);
-  for (auto& c : h) {
-    c.sign = 1.0;
-    c.carry_id = -1;
+  for (int i = 0; i < w->W; ++i) {
+    h[i].sign = 1.0;
+    h[i].carry_id = -1;
+    h[i].sweep_len = w->wk[i].p.sweep_length;
   }
   HIPCHK(hipMemcpyAsync(w->ctl_all, h.data(), sizeof(Ctl) * w->W, hipMemcpyHostToDevice, w->stream));
   HIPCHK(hipStreamSynchronize(w->stream));
@@ -899,6 +888,7 @@ dcax_status dcax_set_config(dcax_walker w, int32_t walker, const dcax_vertex* v,
   h.next_id = next_id;
   h.sign = 1.0;
   h.carry_id = -1;
+  h.sweep_len = x.p.sweep_length;
   HIPCHK(hipMemcpyAsync(w->ctl_all + walker, &h, sizeof(Ctl), hipMemcpyHostToDevice, w->stream));
   if (w->mixed) {
     enqueue_refresh<float>(w, walker, 1, k, false);

@@ -43,6 +43,9 @@ struct Ctl {
   double fold_bytes;   // algorithmic bytes of the folds (N read and written)
   long long n_folds;   // windows with a non-empty fold
   double drift;        // drift measured by the last refresh
+  long long sweep_len; // frozen proposals per sweep before rounding to k_s, 0 while warming up
+  double warm_sum;     // sum of the order at sweep starts over the warm-up's second half
+  long long warm_n;    // number of such sweeps
 };
 
 struct WinProp {      // one proposal of the current window
@@ -63,7 +66,7 @@ struct WinProp {      // one proposal of the current window
 template <typename T>
 struct View {
   // model
-  int Nc, n_tau, ks, cap, ld, max_order;
+  int Nc, n_tau, ks, cap, ld, max_order, warmup;
   double beta, h, gamma, K_exp;
   double ev[2][2];            // e^{V}: [spin][0 for s = +1, 1 for s = -1]
   uint64_t seed;              // generator key

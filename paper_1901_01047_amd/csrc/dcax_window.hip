@@ -121,113 +121,125 @@ __global__ void __launch_bounds__(WG) k_prep_replay(const View<T>* __restrict__ 
 // (u_branch, u_index) of a removal target.  Insertions are state-independent
 // and become candidates; a removal pre-selects the window-start vertex its
 // first attempt would hit (floor(u_index k0)).  A removal carried over from
-// an aborted window keeps the target it had already chosen.
+// an aborted window keeps the target it had already chosen.  One wavefront,
+// one lane per proposal; elements are numbered in proposal order (a removal
+// whose target an earlier removal of the window already holds shares its
+// element) by prefix counts over lane masks.
+constexpr int PW = 64;      // prep kernel: one wavefront per walker
+static_assert(KS_MAX <= PW, "one lane per proposal");
+
 template <typename T>
-__global__ void __launch_bounds__(WG) k_prep_rng(const View<T>* __restrict__ vs) {
+__global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
   const uint64_t seed = w.seed;
   Ctl* c = w.ctl;
-  __shared__ int nP_s, k0_s, carry_slot_s;
-  __shared__ long long carry_s;
-  const int t = threadIdx.x;
-  if (t == 0) {
-    long long rem = c->end - c->pos;
-    int nP = (c->status == 0 && rem > 0) ? (int)(rem < w.ks ? rem : w.ks) : 0;
-    nP_s = nP;
-    k0_s = c->k;
-    carry_s = c->carry_id;
-    carry_slot_s = -1;
-    if (nP == 0) c->active = 0;
+  const int lane = threadIdx.x;
+  const long long left = c->end - c->pos;
+  const int nP = (c->status == 0 && left > 0) ? (int)(left < w.ks ? left : w.ks) : 0;
+  if (nP == 0) {
+    if (lane == 0) c->active = 0;
+    return;
   }
-  __syncthreads();
-  const int nP = nP_s, k0 = k0_s;
-  if (nP == 0) return;
-  const long long carry = carry_s;
-  if (carry >= 0)
-    for (int i = t; i < k0; i += WG)
-      if (w.v_id[i] == carry) carry_slot_s = i;
-  // the window's uniforms, one proposal per thread
-  __shared__ double u_s[KS_MAX][5];
-  __shared__ int slot0_s[KS_MAX];
+  const int k0 = c->k;
   const long long pos = c->pos;
-  if (t < nP) {
-    const long long g = pos + t;
-    double u_dummy;
-    uniforms2(seed, g, 0u, u_s[t][0], u_s[t][1]);
-    uniforms2(seed, g, 1u, u_s[t][2], u_s[t][3]);
-    uniforms2(seed, g, 2u, u_s[t][4], u_dummy);
-    int slot = -1;
-    if (k0 > 0) {
-      double ub, ui;
-      uniforms2(seed, g, 3u, ub, ui);
-      slot = (int)(ui * (double)k0);
-      if (slot >= k0) slot = k0 - 1;
-    }
-    slot0_s[t] = slot;
-  }
-  __syncthreads();
-  if (t != 0) return;
-  int nE = 0, nC = 0;
-  for (int j = 0; j < nP; ++j) {
-    const long long g = pos + j;
-    const double u_kind = u_s[j][0], u_site = u_s[j][1], u_tau = u_s[j][2], u_spin = u_s[j][3];
-    const double u_acc = u_s[j][4];
-    WinProp p;
-    p.forced = -1;
-    p.carried = 0;
-    p.u = u_acc;
-    p.ridx = -1;
-    p.gidx = g;
-    p.el = -1;
-    int slot = -1;
-    if (j == 0 && carry >= 0) {
-      p.kind = 1;
-      p.carried = 1;
-      slot = carry_slot_s;
-      if (slot < 0) {
+  const long long carry = c->carry_id;
+  int carry_slot = -1;
+  if (carry >= 0) {
+    int found = -1;
+    for (int i = lane; i < k0; i += PW)
+      if (w.v_id[i] == carry) found = i;
+    const unsigned long long hit = __ballot(found >= 0);
+    if (hit) carry_slot = __shfl(found, (int)__ffsll((long long)hit) - 1, PW);
+    if (carry_slot < 0) {
+      if (lane == 0) {
         latch(c, ST_TRACE);
         c->active = 0;
-        return;
       }
-    } else if (u_kind < 0.5) {
-      p.kind = 0;
-      int site = (int)(u_site * (double)w.Nc);
-      if (site >= w.Nc) site = w.Nc - 1;
-      const int e = nE++, cc = nC++;
-      w.el_site[e] = site;
-      w.el_tau[e] = u_tau * w.beta;
-      w.el_s[e] = (u_spin < 0.5) ? 1 : -1;
-      w.el_slot[e] = -1;
-      w.el_cand[e] = cc;
-      w.cand_el[cc] = e;
-      w.cand_id[cc] = -1;
-      p.el = e;
-    } else {
-      p.kind = 1;
-      slot = slot0_s[j];     // the first attempt's window-start vertex
+      return;
     }
-    if (slot >= 0) {
-      int e = -1;
-      for (int x = 0; x < nE; ++x)
-        if (w.el_slot[x] == slot) e = x;
-      if (e < 0) {
-        e = nE++;
-        w.el_site[e] = w.v_site[slot];
-        w.el_tau[e] = w.v_tau[slot];
-        w.el_s[e] = w.v_s[slot];
-        w.el_slot[e] = slot;
-        w.el_cand[e] = -1;
-      }
-      p.el = e;
-    }
-    w.wp[j] = p;
   }
-  c->carry_id = -1;
-  c->nP = nP;
-  c->nE = nE;
-  c->nC = nC;
-  c->k0 = k0;
-  c->active = 1;
+  const bool act = lane < nP;
+  double u_kind = 1.0, u_site = 0.0, u_tau = 0.0, u_spin = 0.0, u_acc = 0.0, u_dummy;
+  int kind = -1, slot = -1;
+  if (act) {
+    const long long g = pos + lane;
+    uniforms2(seed, g, 0u, u_kind, u_site);
+    uniforms2(seed, g, 1u, u_tau, u_spin);
+    uniforms2(seed, g, 2u, u_acc, u_dummy);
+    if (lane == 0 && carry >= 0) {
+      kind = 1;
+      slot = carry_slot;
+    } else if (u_kind < 0.5) {
+      kind = 0;
+    } else {
+      kind = 1;
+      if (k0 > 0) {     // the first attempt's window-start vertex
+        double ub, ui;
+        uniforms2(seed, g, 3u, ub, ui);
+        slot = (int)(ui * (double)k0);
+        if (slot >= k0) slot = k0 - 1;
+      }
+    }
+  }
+  __shared__ int kind_s[PW], slot_s[PW], el_s[PW];
+  kind_s[lane] = kind;
+  slot_s[lane] = slot;
+  __syncthreads();
+  bool fresh = false;
+  int first = lane;
+  if (kind == 0) {
+    fresh = true;
+  } else if (kind == 1 && slot >= 0) {
+    for (int x = 0; x < lane; ++x)
+      if (kind_s[x] == 1 && slot_s[x] == slot) {
+        first = x;
+        break;
+      }
+    fresh = first == lane;
+  }
+  const unsigned long long fresh_m = __ballot(fresh), ins_m = __ballot(kind == 0);
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int e_own = fresh ? __popcll(fresh_m & below) : -1;
+  const int cc = (kind == 0) ? __popcll(ins_m & below) : -1;
+  el_s[lane] = e_own;
+  __syncthreads();
+  const int e = (kind == 1 && slot >= 0 && !fresh) ? el_s[first] : e_own;
+  if (kind == 0) {
+    int site = (int)(u_site * (double)w.Nc);
+    if (site >= w.Nc) site = w.Nc - 1;
+    w.el_site[e] = site;
+    w.el_tau[e] = u_tau * w.beta;
+    w.el_s[e] = (u_spin < 0.5) ? 1 : -1;
+    w.el_slot[e] = -1;
+    w.el_cand[e] = cc;
+    w.cand_el[cc] = e;
+    w.cand_id[cc] = -1;
+  } else if (fresh) {
+    w.el_site[e] = w.v_site[slot];
+    w.el_tau[e] = w.v_tau[slot];
+    w.el_s[e] = w.v_s[slot];
+    w.el_slot[e] = slot;
+    w.el_cand[e] = -1;
+  }
+  if (act) {
+    WinProp p;
+    p.kind = kind;
+    p.el = e;
+    p.forced = -1;
+    p.carried = (lane == 0 && carry >= 0) ? 1 : 0;
+    p.u = u_acc;
+    p.ridx = -1;
+    p.gidx = pos + lane;
+    w.wp[lane] = p;
+  }
+  if (lane == 0) {
+    c->carry_id = -1;
+    c->nP = nP;
+    c->nE = __popcll(fresh_m);
+    c->nC = __popcll(ins_m);
+    c->k0 = k0;
+    c->active = 1;
+  }
 }
 
 // ---------------------------------------------------------------- gather
@@ -273,67 +285,69 @@ __global__ void __launch_bounds__(WG) k_gather(const View<T>* __restrict__ vs) {
 }
 
 // ------------------------------------------------------- candidate rows
-// X_c = W_c N for all candidates and both spins (an nC x k0 x k0 GEMM on the
-// matrix cores), written as rows e = element(c) of R.  Tiles of N are staged
-// through LDS so that HBM reads run down the columns.
+// X_c = W_c N for all candidates and both spins (an nC x k0 x k0 product on
+// the matrix cores), written as rows e = element(c) of R.  A workgroup owns
+// 16 columns of X; its four wavefronts split the inner dimension and their
+// partial tiles are summed in LDS in a fixed order, so the result does not
+// depend on scheduling.  Small tiles and the split keep the dependent chain
+// of loads short: at the orders of a single walker this product is bound by
+// load latency, not by bandwidth.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_cand_x(const View<T>* __restrict__ vs) {
+  typedef typename Mfma<T>::acc_t acc_t;
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
   if (!c->active) return;
   const int nC = c->nC;
   const int k0 = c->k0;
-  const int j0 = blockIdx.x * 64;
+  const int j0 = blockIdx.x * 16;
   if (nC == 0 || j0 >= k0) return;
   const int sp = blockIdx.y;
   const T* N = w.N[sp];
   const T* Wm = w.W[sp];
-  T* R = w.R[sp];
-  __shared__ T As[64][17];
-  __shared__ T Bs[16][65];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const int nRB = (nC + 15) >> 4;
-  typename Mfma<T>::acc_t acc[4];
+  const int jc = j0 + li;
+  acc_t acc[4];
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb) acc[rb] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-  for (int i0 = 0; i0 < k0; i0 += 16) {
+  for (int rb = 0; rb < 4; ++rb) acc[rb] = acc_t{0, 0, 0, 0};
+#pragma unroll 4
+  for (int i0 = 4 * wv; i0 < k0; i0 += 16) {
+    const int ik = i0 + lk;
+    const bool kin = ik < k0;
+    const T b = (kin && jc < k0) ? N[ik + (size_t)jc * w.ld] : (T)0;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int r = t & 15, col = (t >> 4) + 16 * p;
-      const int gi = i0 + r, gj = j0 + col;
-      Bs[r][col] = (gi < k0 && gj < k0) ? N[gi + (size_t)gj * w.ld] : (T)0;
-      const int cr = (t >> 4) + 16 * p;
-      As[cr][r] = (cr < nC && gi < k0) ? Wm[(size_t)cr * w.cap + gi] : (T)0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const T b = Bs[kk * 4 + (lane >> 4)][wv * 16 + (lane & 15)];
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-        if (rb < nRB) {
-          const T a = As[rb * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
-          acc[rb] = Mfma<T>::run(a, b, acc[rb]);
-        }
-    }
-    __syncthreads();
-  }
-  const int col = j0 + wv * 16 + (lane & 15);
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-    if (rb < nRB) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int cr = rb * 16 + Mfma<T>::row(lane, r);
-        if (cr < nC && col < k0) R[(size_t)w.cand_el[cr] * w.cap + col] = acc[rb][r];
+    for (int rb = 0; rb < 4; ++rb)
+      if (rb < nRB) {
+        const int cr = rb * 16 + li;
+        const T a = (kin && cr < nC) ? Wm[(size_t)cr * w.cap + ik] : (T)0;
+        acc[rb] = Mfma<T>::run(a, b, acc[rb]);
       }
-    }
+  }
+  __shared__ acc_t red[4][4][64];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) red[wv][rb][lane] = acc[rb];
+  __syncthreads();
+  const int rb = wv;
+  if (rb >= nRB) return;
+  const acc_t sum = ((red[0][rb][lane] + red[1][rb][lane]) + red[2][rb][lane]) + red[3][rb][lane];
+  T* R = w.R[sp];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int cr = rb * 16 + Mfma<T>::row(lane, r);
+    if (cr < nC && jc < k0) R[(size_t)w.cand_el[cr] * w.cap + jc] = sum[r];
+  }
 }
 
 // -------------------------------------------------------------- Gram
-// G restricted to the window elements, both spins, in FP64:
-//   column of a candidate c:  G_{x,c} = R_x . g_{I,c} (+ g_{x,c} for candidate rows x)
-//   column of a target p:     G_{x,p} = (e^{V_p} R_x[p] - delta_{xp}) / (e^{V_p} - 1)
+// The column-scaled Gamma of the window elements, both spins, in FP64:
+//   Gt_{x,y} = -Delta_y G_{x,y} + delta_xy (1 + Delta_y),  G = N_ext g,
+// finite also where Delta = 0 (U = 0).  Its columns:
+//   candidate c:  G_{x,c} = R_x . g_{I,c} (+ g_{x,c} for candidate rows x),
+//                 Delta_c = e^{V'_c} - 1;
+//   target p:     Gt_{x,p} = R_x[p], from G (e^V - 1) = N e^V - 1 with
+//                 Delta_p = e^{-V_p} - 1;
 // where R_x is row x of the extended N (X_c for candidates, N_{p.} for targets).
 template <typename T>
 __global__ void __launch_bounds__(WG) k_gram(const View<T>* __restrict__ vs) {
@@ -353,23 +367,29 @@ __global__ void __launch_bounds__(WG) k_gram(const View<T>* __restrict__ vs) {
     double s = 0.0;
     for (int i = lane; i < k0; i += 64) s += (double)Rx[i] * (double)gc[i];
     s = wave_sum(s);
-    if (lane == 0) G[w.cand_el[cc]] = s + (cx >= 0 ? w.gCC[cx * KS_MAX + cc] : 0.0);
+    if (lane == 0) {
+      const int ec = w.cand_el[cc];
+      const double Dc = w.ev[sp][s01(w.el_s[ec])] - 1.0;
+      const double g = s + (cx >= 0 ? w.gCC[cx * KS_MAX + cc] : 0.0);
+      G[ec] = -Dc * g + (ec == x ? 1.0 + Dc : 0.0);
+    }
   }
   for (int y = threadIdx.x; y < nE; y += WG) {
     const int py = w.el_slot[y];
-    if (py < 0) continue;
-    const double ev = w.ev[sp][s01(w.el_s[y])];
-    G[y] = (ev * (double)Rx[py] - (y == x ? 1.0 : 0.0)) / (ev - 1.0);
+    if (py >= 0) G[y] = (double)Rx[py];
   }
 }
 
 // ---------------------------------------------------------- accept loop
-// The sequential Metropolis decisions of the window (one workgroup, FP64).
-// Adding q to S multiplies the determinant ratio by
-//   (-Delta_q) (Gamma_qq - Gamma_qS Gamma_S^{-1} Gamma_Sq);
+// The sequential Metropolis decisions of the window, in FP64, on one
+// wavefront: lane a owns row a of Gt_S^{-1} for both spins, so a proposal
+// costs O(m) LDS operations per lane and no cross-wave synchronisation.
+// Gt is the column-scaled Gamma of k_gram, Gt_S = Gamma_S diag(-Delta_S):
+// adding q to S multiplies the determinant ratio by the Schur complement
+//   Gt_qq - Gt_qS Gt_S^{-1} Gt_Sq,
 // taking an inserted spin out again (its removal later in the same window)
-// multiplies it by (Gamma_S^{-1})_qq / (-Delta_q).  The acceptance ratio is
-// K/(k+1) or k/K times the product over both spins (Sec. 2.3 weights).
+// multiplies it by (Gt_S^{-1})_qq.  The acceptance ratio is K/(k+1) or k/K
+// times the product over both spins (Sec. 2.3 weights).
 //
 // Generator mode picks a removal target uniformly among the current vertices
 // by rejection: attempt a draws (u_b, u_i); with u_b (k0 + n_ins) < k0 it
@@ -381,9 +401,11 @@ __global__ void __launch_bounds__(WG) k_gram(const View<T>* __restrict__ vs) {
 // target into the next one (the paper's "abort" treatment; exact, since the
 // state does not change in between).
 constexpr int MAX_ATTEMPTS = 1 << 16;
+constexpr int AW = 64;      // accept kernel: one wavefront per walker
+static_assert(KS_MAX == AW, "the accept kernel maps one lane to one window element");
 
 template <typename T>
-__global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
+__global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
   int* el_row = w.el_row;
   int* remap = w.remap;
@@ -392,231 +414,215 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
   Ctl* c = w.ctl;
   if (!c->active) return;
   // LDS rows are padded to LS doubles: with a stride of 64 doubles every lane
-  // reading one column of a tile would hit the same bank.
+  // reading one column would hit the same bank.
   constexpr int LS = KS_MAX + 1;
-  __shared__ double gram_s[2][KS_MAX * LS];
+  __shared__ double gam_s[2][KS_MAX * LS];
   __shared__ double ginv_s[2][KS_MAX * LS];
-  __shared__ double Lv[2][KS_MAX], Rv[2][KS_MAX], dl_s[2][KS_MAX];
+  __shared__ double rv_s[2][KS_MAX];
   __shared__ int S_s[KS_MAX], pos_s[KS_MAX], insl_s[KS_MAX];
-  __shared__ double rat_s[2], schur_s[2], D_s[2];
-  __shared__ int m_s, acc_s, kcur_s, q_s, abort_s, nins_s;
-  __shared__ double sign_s;
-  // everything the sequential loop touches per proposal lives in LDS
   __shared__ WinProp wp_s[KS_MAX];
   __shared__ int cand_s[KS_MAX], spin_s[KS_MAX], slot_s[KS_MAX];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int lane = threadIdx.x;
   const int nE = c->nE, nP = c->nP, k0 = c->k0;
-  for (int idx = t; idx < 2 * KS_MAX * KS_MAX; idx += WG) {
-    const int sp = idx / (KS_MAX * KS_MAX), r = idx % (KS_MAX * KS_MAX);
-    const int ra = r / KS_MAX, rb = r % KS_MAX;
-    gram_s[sp][ra * LS + rb] = (ra < nE && rb < nE) ? w.gram[sp][r] : 0.0;
+  const double K_exp = w.K_exp;
+  const int max_order = w.max_order;
+  for (int x = 0; x < KS_MAX; ++x) {
+    const bool in = x < nE && lane < nE;
+    gam_s[0][x * LS + lane] = in ? w.gram[0][x * KS_MAX + lane] : 0.0;
+    gam_s[1][x * LS + lane] = in ? w.gram[1][x * KS_MAX + lane] : 0.0;
   }
-  if (t < KS_MAX) pos_s[t] = -1;
-  if (t < nP) wp_s[t] = w.wp[t];
-  if (t < nE) {
-    cand_s[t] = w.el_cand[t];
-    spin_s[t] = w.el_s[t];
-    slot_s[t] = w.el_slot[t];
-  }
-  if (t == 0) {
-    m_s = 0;
-    nins_s = 0;
-    kcur_s = k0;
-    sign_s = c->sign;
+  pos_s[lane] = -1;
+  if (lane < nP) wp_s[lane] = w.wp[lane];
+  if (lane < nE) {
+    cand_s[lane] = w.el_cand[lane];
+    spin_s[lane] = w.el_s[lane];
+    slot_s[lane] = w.el_slot[lane];
   }
   __syncthreads();
+  // window state: identical in every lane
+  int m = 0, kcur = k0, nins = 0, bad = 0, n_done = nP;
+  double sign = c->sign;
+  long long next_id = c->next_id, carry = -1;
   long long n_ins = 0, n_rem = 0, n_mis = 0;
-  long long next_id = c->next_id;
-  long long carry = -1;
-  int bad = 0, n_done = nP;
   for (int j = 0; j < nP; ++j) {
     const WinProp p = wp_s[j];
-    if (t == 0) {
-      int q = p.el, ab = 0;
-      if (p.forced < 0 && p.kind == 1 && !p.carried) {
-        q = -1;
-        const int kc = kcur_s, ni = nins_s;
-        if (kc > 0) {
-          for (int a = 0; a < MAX_ATTEMPTS; ++a) {
-            double ub, ui;
-            uniforms2(seed, p.gidx, 3u + (uint32_t)a, ub, ui);
-            if (ub * (double)(k0 + ni) < (double)k0) {
-              int slot = (int)(ui * (double)k0);
-              if (slot >= k0) slot = k0 - 1;
-              int e = -1;
-              if (a == 0) {
-                e = p.el;
-              } else {
-                for (int x = 0; x < nE; ++x)
-                  if (slot_s[x] == slot) e = x;
-              }
-              if (e >= 0 && pos_s[e] >= 0) continue;
-              if (e < 0) {
-                ab = 1;
-                carry = w.v_id[slot];
-                break;
-              }
-              q = e;
+    int q = p.el, ab = 0;
+    if (p.forced < 0 && p.kind == 1 && !p.carried) {
+      q = -1;
+      if (kcur > 0) {
+        for (int a = 0; a < MAX_ATTEMPTS; ++a) {
+          double ub, ui;
+          uniforms2(seed, p.gidx, 3u + (uint32_t)a, ub, ui);
+          if (ub * (double)(k0 + nins) < (double)k0) {
+            int slot = (int)(ui * (double)k0);
+            if (slot >= k0) slot = k0 - 1;
+            int e = p.el;
+            if (a > 0) {
+              const unsigned long long hit = __ballot(lane < nE && slot_s[lane] == slot);
+              e = hit ? (int)__ffsll((long long)hit) - 1 : -1;
+            }
+            if (e >= 0 && pos_s[e] >= 0) continue;     // already removed in this window
+            if (e < 0) {
+              ab = 1;
+              carry = w.v_id[slot];
               break;
             }
-            int idx = (int)(ui * (double)ni);
-            if (idx >= ni) idx = ni - 1;
-            q = insl_s[idx];
+            q = e;
             break;
           }
-          if (q < 0 && !ab) bad = 1;
+          int idx = (int)(ui * (double)nins);
+          if (idx >= nins) idx = nins - 1;
+          q = insl_s[idx];
+          break;
         }
+        if (q < 0 && !ab) bad = 1;
       }
-      q_s = q;
-      abort_s = ab;
     }
-    __syncthreads();
-    if (abort_s) {
+    if (ab) {
       n_done = j;
       break;
     }
-    const int q = q_s;
-    const int m = m_s;
     if (q < 0) {
-      if (t == 0 && p.ridx >= 0) w.ratio_out[p.ridx] = 0.0;
+      if (lane == 0 && p.ridx >= 0) w.ratio_out[p.ridx] = 0.0;
       continue;
     }
     const int pq = pos_s[q];
-    const int is_c = cand_s[q] >= 0;
+    double r0, r1, L0 = 0.0, L1 = 0.0;
     if (pq >= 0) {
-      if (t < 2) rat_s[t] = ginv_s[t][pq * LS + pq] / (-dl_s[t][pq]);
-    } else if (wv < 2) {
-      const int sp = wv;
-      const double ev = w.ev[sp][s01(spin_s[q])];
-      const double D = is_c ? ev - 1.0 : 1.0 / ev - 1.0;
-      double L = 0.0;
+      r0 = ginv_s[0][pq * LS + pq];
+      r1 = ginv_s[1][pq * LS + pq];
+    } else {
+      // L = Gt_S^{-1} Gt_Sq (lane a holds L_a), Schur = Gt_qq - Gt_qS L
       if (lane < m) {
-        for (int b = 0; b < m; ++b) L += ginv_s[sp][lane * LS + b] * gram_s[sp][S_s[b] * LS + q];
-        Lv[sp][lane] = L;
-      }
-      double part = (lane < m) ? gram_s[sp][q * LS + S_s[lane]] * L : 0.0;
-      part = wave_sum(part);
-      if (lane == 0) {
-        const double sch = gram_s[sp][q * LS + q] - (1.0 + D) / D - part;
-        schur_s[sp] = sch;
-        D_s[sp] = D;
-        rat_s[sp] = -D * sch;
-      }
-    }
-    __syncthreads();
-    if (t == 0) {
-      const int kc = kcur_s;
-      const double fac = (p.kind == 0) ? w.K_exp / (double)(kc + 1) : (double)kc / w.K_exp;
-      const double R = fac * rat_s[0] * rat_s[1];
-      int dec;
-      if (!isfinite(R)) {
-        bad = 1;
-        dec = 0;
-      } else {
-        const int mine = p.u < fabs(R);
-        dec = (p.forced >= 0) ? p.forced : mine;
-        if (p.forced >= 0 && mine != p.forced) ++n_mis;
-      }
-      if (p.ridx >= 0) w.ratio_out[p.ridx] = R;
-      if (dec && p.kind == 0 && kc + 1 > w.max_order) {
-        latch(c, ST_CAPACITY);
-        dec = 0;
-      }
-      acc_s = dec;
-      if (dec) {
-        kcur_s = kc + (p.kind == 0 ? 1 : -1);
-        if (R < 0.0) sign_s = -sign_s;
-        if (p.kind == 0) {
-          ++n_ins;
-          const int cc = cand_s[q];
-          if (p.forced < 0) w.cand_id[cc] = next_id++;
-          insl_s[nins_s++] = q;
-        } else {
-          ++n_rem;
-          if (pq >= 0) {
-            int x = 0;
-            while (insl_s[x] != q) ++x;
-            for (; x + 1 < nins_s; ++x) insl_s[x] = insl_s[x + 1];
-            --nins_s;
-          }
+        for (int b = 0; b < m; ++b) {
+          const int sb = S_s[b];
+          L0 += ginv_s[0][lane * LS + b] * gam_s[0][sb * LS + q];
+          L1 += ginv_s[1][lane * LS + b] * gam_s[1][sb * LS + q];
         }
       }
+      const int sl = lane < m ? S_s[lane] : 0;
+      const double p0 = wave_sum(lane < m ? gam_s[0][q * LS + sl] * L0 : 0.0);
+      const double p1 = wave_sum(lane < m ? gam_s[1][q * LS + sl] * L1 : 0.0);
+      r0 = gam_s[0][q * LS + q] - p0;
+      r1 = gam_s[1][q * LS + q] - p1;
     }
-    __syncthreads();
-    if (!acc_s) continue;
+    const double fac = (p.kind == 0) ? K_exp / (double)(kcur + 1) : (double)kcur / K_exp;
+    const double R = fac * r0 * r1;
+    int dec;
+    if (!isfinite(R)) {
+      bad = 1;
+      dec = 0;
+    } else {
+      const int mine = p.u < fabs(R);
+      dec = (p.forced >= 0) ? p.forced : mine;
+      if (p.forced >= 0 && mine != p.forced) ++n_mis;
+    }
+    if (lane == 0 && p.ridx >= 0) w.ratio_out[p.ridx] = R;
+    if (dec && p.kind == 0 && kcur + 1 > max_order) {
+      if (lane == 0) latch(c, ST_CAPACITY);
+      dec = 0;
+    }
+    if (!dec) continue;
+    kcur += (p.kind == 0) ? 1 : -1;
+    if (R < 0.0) sign = -sign;
+    if (p.kind == 0) {
+      ++n_ins;
+      if (p.forced < 0) {
+        if (lane == 0) w.cand_id[cand_s[q]] = next_id;
+        ++next_id;
+      }
+      if (lane == 0) insl_s[nins] = q;
+      ++nins;
+    } else {
+      ++n_rem;
+      if (pq >= 0) {
+        if (lane == 0) {
+          int x = 0;
+          while (insl_s[x] != q) ++x;
+          for (; x + 1 < nins; ++x) insl_s[x] = insl_s[x + 1];
+        }
+        --nins;
+      }
+    }
     if (pq < 0) {
-      if (wv < 2) {
-        const int sp = wv;
-        if (lane < m) {
-          double Rr = 0.0;
-          for (int a = 0; a < m; ++a) Rr += gram_s[sp][q * LS + S_s[a]] * ginv_s[sp][a * LS + lane];
-          Rv[sp][lane] = Rr;
+      // bordering: q joins S at position m
+      const double inv0 = 1.0 / r0, inv1 = 1.0 / r1;
+      if (lane < m) {
+        double R0 = 0.0, R1 = 0.0;
+        for (int a = 0; a < m; ++a) {
+          const int sa = S_s[a];
+          R0 += gam_s[0][q * LS + sa] * ginv_s[0][a * LS + lane];
+          R1 += gam_s[1][q * LS + sa] * ginv_s[1][a * LS + lane];
         }
+        rv_s[0][lane] = R0;
+        rv_s[1][lane] = R1;
       }
       __syncthreads();
-      const int mm = m + 1;
-      for (int idx = t; idx < 2 * mm * mm; idx += WG) {
-        const int sp = idx / (mm * mm), r = idx % (mm * mm), a = r / mm, b = r % mm;
-        const double inv = 1.0 / schur_s[sp];
-        double v;
-        if (a < m && b < m) v = ginv_s[sp][a * LS + b] + Lv[sp][a] * Rv[sp][b] * inv;
-        else if (a == m && b < m) v = -Rv[sp][b] * inv;
-        else if (a < m) v = -Lv[sp][a] * inv;
-        else v = inv;
-        ginv_s[sp][a * LS + b] = v;
+      if (lane < m) {
+        for (int b = 0; b < m; ++b) {
+          ginv_s[0][lane * LS + b] += L0 * rv_s[0][b] * inv0;
+          ginv_s[1][lane * LS + b] += L1 * rv_s[1][b] * inv1;
+        }
+        ginv_s[0][lane * LS + m] = -L0 * inv0;
+        ginv_s[1][lane * LS + m] = -L1 * inv1;
+      } else if (lane == m) {
+        for (int b = 0; b < m; ++b) {
+          ginv_s[0][m * LS + b] = -rv_s[0][b] * inv0;
+          ginv_s[1][m * LS + b] = -rv_s[1][b] * inv1;
+        }
+        ginv_s[0][m * LS + m] = inv0;
+        ginv_s[1][m * LS + m] = inv1;
       }
-      __syncthreads();
-      if (t == 0) {
+      if (lane == 0) {
         S_s[m] = q;
         pos_s[q] = m;
-        dl_s[0][m] = D_s[0];
-        dl_s[1][m] = D_s[1];
-        m_s = mm;
       }
+      ++m;
       __syncthreads();
     } else {
+      // rank-1 downdate, then the last position moves into the hole
       const int js = pq, last = m - 1;
-      if (t < 2 * m) {
-        const int sp = t / m, a = t % m;
-        Lv[sp][a] = ginv_s[sp][a * LS + js];
-        Rv[sp][a] = ginv_s[sp][js * LS + a];
+      const double piv0 = ginv_s[0][js * LS + js], piv1 = ginv_s[1][js * LS + js];
+      double c0 = 0.0, c1 = 0.0;
+      if (lane < m) {
+        c0 = ginv_s[0][lane * LS + js];
+        c1 = ginv_s[1][lane * LS + js];
+        rv_s[0][lane] = ginv_s[0][js * LS + lane];
+        rv_s[1][lane] = ginv_s[1][js * LS + lane];
       }
       __syncthreads();
-      for (int idx = t; idx < 2 * m * m; idx += WG) {
-        const int sp = idx / (m * m), r = idx % (m * m), a = r / m, b = r % m;
-        ginv_s[sp][a * LS + b] -= Lv[sp][a] * Rv[sp][b] / Lv[sp][js];
-      }
+      if (lane < m)
+        for (int b = 0; b < m; ++b) {
+          ginv_s[0][lane * LS + b] -= c0 * rv_s[0][b] / piv0;
+          ginv_s[1][lane * LS + b] -= c1 * rv_s[1][b] / piv1;
+        }
       __syncthreads();
       if (js != last) {
-        for (int idx = t; idx < 2 * m; idx += WG) {
-          const int sp = idx / m, b = idx % m;
-          ginv_s[sp][js * LS + b] = ginv_s[sp][last * LS + b];
+        if (lane < m) {
+          ginv_s[0][js * LS + lane] = ginv_s[0][last * LS + lane];
+          ginv_s[1][js * LS + lane] = ginv_s[1][last * LS + lane];
         }
         __syncthreads();
-        for (int idx = t; idx < 2 * m; idx += WG) {
-          const int sp = idx / m, a = idx % m;
-          ginv_s[sp][a * LS + js] = ginv_s[sp][a * LS + last];
+        if (lane < m) {
+          ginv_s[0][lane * LS + js] = ginv_s[0][lane * LS + last];
+          ginv_s[1][lane * LS + js] = ginv_s[1][lane * LS + last];
         }
       }
-      __syncthreads();
-      if (t == 0) {
+      if (lane == 0) {
         const int el_last = S_s[last];
         S_s[js] = el_last;
         pos_s[el_last] = js;
-        dl_s[0][js] = dl_s[0][last];
-        dl_s[1][js] = dl_s[1][last];
         pos_s[q] = -1;
-        m_s = last;
       }
+      m = last;
       __syncthreads();
     }
   }
-  __syncthreads();
-  const int m = m_s;
-  for (int idx = t; idx < 2 * m * m; idx += WG) {
-    const int sp = idx / (m * m), r = idx % (m * m), a = r / m, b = r % m;
-    w.ginv[sp][a * KS_MAX + b] = ginv_s[sp][a * LS + b];
-  }
+  for (int a = 0; a < m; ++a)
+    if (lane < m) {
+      w.ginv[0][a * KS_MAX + lane] = ginv_s[0][a * LS + lane];
+      w.ginv[1][a * KS_MAX + lane] = ginv_s[1][a * LS + lane];
+    }
   // Epilogue: the fold's column order, the new vertex arrays and the plan
   // that removes the deleted rows and columns of N.  Inserted spins take
   // slots k0 .. k0+mi-1; holes left below the new order are filled from the
@@ -624,8 +630,8 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
   // Nothing later in the window reads the vertex arrays or the order, so
   // both are final here.
   __shared__ int ins_s[KS_MAX], hole_s[KS_MAX], src_s[KS_MAX], rem[KS_MAX], mi_s, nh_s;
-  const int knew = kcur_s;
-  if (t == 0) {
+  const int knew = kcur;
+  if (lane == 0) {
     int mi = 0, mr = 0;
     for (int s = 0; s < m; ++s) {
       const int e = S_s[s];
@@ -669,7 +675,7 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
     c->kx = kx;
     c->knew = knew;
     c->k = knew;
-    c->sign = sign_s;
+    c->sign = sign;
     c->next_id = next_id;
     c->n_prop += n_done;
     c->n_acc_ins += n_ins;
@@ -694,17 +700,17 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
   __syncthreads();
   const int mi = mi_s, nh = nh_s;
   if (m == 0) return;
-  for (int i = t; i < knew; i += WG) remap[i] = i;
-  if (t < mi) {
-    const int e = ins_s[t];
-    w.v_site[k0 + t] = w.el_site[e];
-    w.v_tau[k0 + t] = w.el_tau[e];
-    w.v_s[k0 + t] = spin_s[e];
-    w.v_id[k0 + t] = w.cand_id[cand_s[e]];
+  for (int i = lane; i < knew; i += AW) remap[i] = i;
+  if (lane < mi) {
+    const int e = ins_s[lane];
+    w.v_site[k0 + lane] = w.el_site[e];
+    w.v_tau[k0 + lane] = w.el_tau[e];
+    w.v_s[k0 + lane] = spin_s[e];
+    w.v_id[k0 + lane] = w.cand_id[cand_s[e]];
   }
   __syncthreads();
-  if (t < nh) {
-    const int d = hole_s[t], sidx = src_s[t];
+  if (lane < nh) {
+    const int d = hole_s[lane], sidx = src_s[lane];
     remap[d] = sidx;
     w.v_site[d] = w.v_site[sidx];
     w.v_tau[d] = w.v_tau[sidx];
@@ -714,58 +720,70 @@ __global__ void __launch_bounds__(WG) k_accept(const View<T>* __restrict__ vs) {
 }
 
 // --------------------------------------------------------- Y = N g_{I,c}
-// Columns G_{I,c} = N g_{I,c} for the inserted spins (a k0 x k0 x mi GEMM).
+// Columns N g_{I,c} for the inserted spins (a k0 x k0 x mi product).  A
+// workgroup owns 16 rows; its four wavefronts split the inner dimension and
+// their partial tiles are summed in LDS in a fixed order.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_ygemm(const View<T>* __restrict__ vs) {
+  typedef typename Mfma<T>::acc_t acc_t;
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
   if (!c->active) return;
   const int mi = c->mi, k0 = c->k0;
-  const int i0 = blockIdx.x * 64;
-  if (mi == 0 || i0 >= k0) return;
+  const int r0 = blockIdx.x * 16;
+  if (mi == 0 || r0 >= k0) return;
   const int sp = blockIdx.y;
   const T* N = w.N[sp];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const int ncb = (mi + 15) >> 4;
   const T* gp[4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
-    const int jj = cb * 16 + (lane & 15);
+    const int jj = cb * 16 + li;
     gp[cb] = (jj < mi) ? w.gcol + (size_t)w.el_cand[w.ins_el[jj]] * w.cap : nullptr;
   }
-  typename Mfma<T>::acc_t acc[4];
+  const int ir = r0 + li;
+  acc_t acc[4];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) acc[cb] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-  const int ii = i0 + wv * 16 + (lane & 15);
-  for (int j = 0; j < k0; j += 4) {
-    const int jk = j + (lane >> 4);
-    const T a = (ii < k0 && jk < k0) ? N[ii + (size_t)jk * w.ld] : (T)0;
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
+#pragma unroll 4
+  for (int j0 = 4 * wv; j0 < k0; j0 += 16) {
+    const int jk = j0 + lk;
+    const bool kin = jk < k0;
+    const T a = (kin && ir < k0) ? N[ir + (size_t)jk * w.ld] : (T)0;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
       if (cb < ncb) {
-        const T b = (gp[cb] != nullptr && jk < k0) ? gp[cb][jk] : (T)0;
+        const T b = (kin && gp[cb] != nullptr) ? gp[cb][jk] : (T)0;
         acc[cb] = Mfma<T>::run(a, b, acc[cb]);
       }
   }
+  __shared__ acc_t red[4][4][64];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb)
-    if (cb < ncb) {
+  for (int cb = 0; cb < 4; ++cb) red[wv][cb][lane] = acc[cb];
+  __syncthreads();
+  const int cb = wv;
+  if (cb >= ncb) return;
+  const acc_t sum = ((red[0][cb][lane] + red[1][cb][lane]) + red[2][cb][lane]) + red[3][cb][lane];
+  const int jj = cb * 16 + li;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wv * 16 + Mfma<T>::row(lane, r);
-        const int jj = cb * 16 + (lane & 15);
-        if (i < k0 && jj < mi) w.Y[sp][(size_t)jj * w.cap + i] = acc[cb][r];
-      }
-    }
+  for (int r = 0; r < 4; ++r) {
+    const int i = r0 + Mfma<T>::row(lane, r);
+    if (i < k0 && jj < mi) w.Y[sp][(size_t)jj * w.cap + i] = sum[r];
+  }
 }
 
 // ------------------------------------------------------------ fold prep
 // Fold factors in the extended index space (window-start vertices, then the
-// inserted spins at rows k0 .. k0+mi-1):
-//   A = E_S - G_{.S}: an inserted spin's column is e - [N g_{I,c}; G_{C,c}],
-//     a removed vertex p's column is (e^{V_p} / (e^{V_p} - 1)) (e_p - N_{.p});
-//   B = Gamma_S^{-1} N_{S.} with the rows of the extended N;
+// inserted spins at rows k0 .. k0+mi-1), for N' = N + A B with
+// A = (E_S - G_{.S}) diag(-Delta_S) and B = Gt_S^{-1} N_{S.}:
+//   an inserted spin c: rows < k0 Delta_c (N g_{I,c}), inserted rows
+//     delta - Gt_{C,c};
+//   a removed vertex p: e_p - N_ext{.p};
+//   B with the rows of the extended N;
 // and the extension of N itself: row k0+j = X_c, column k0+j = e_{k0+j}.
+// A workgroup covers 64 columns; its four wavefronts share the S rows.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
@@ -775,15 +793,16 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
   const int m = c->m;
   const int sp = blockIdx.y;
   const int k0 = c->k0, mi = c->mi, kx = k0 + mi;
+  const int i0 = blockIdx.x * 64;
+  if (i0 >= kx) return;
   __shared__ double gi_s[KS_MAX * KS_MAX];
+  __shared__ double rv_s[KS_MAX][64];
   __shared__ int e_s[KS_MAX], row_s[KS_MAX], cand_s[KS_MAX], slot_s[KS_MAX], ins_s[KS_MAX];
-  __shared__ double f_s[KS_MAX];
-  const int t = threadIdx.x;
-  // the product below runs over all KS_MAX columns: entries beyond m must be
-  // zero, not whatever an earlier kernel left in LDS
-  for (int idx = t; idx < KS_MAX * KS_MAX; idx += WG) {
-    const int a = idx / KS_MAX, b = idx % KS_MAX;
-    gi_s[idx] = (a < m && b < m) ? w.ginv[sp][idx] : 0.0;
+  __shared__ double d_s[KS_MAX];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int idx = t; idx < m * KS_MAX; idx += WG) {
+    const int b = idx % KS_MAX;
+    gi_s[idx] = (b < m) ? w.ginv[sp][idx] : 0.0;
   }
   if (t < m) {
     const int e = w.S[t];
@@ -791,49 +810,47 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
     row_s[t] = el_row[e];
     cand_s[t] = w.el_cand[e];
     slot_s[t] = w.el_slot[e];
-    const double ev = w.ev[sp][s01(w.el_s[e])];
-    f_s[t] = ev / (ev - 1.0);
+    d_s[t] = w.ev[sp][s01(w.el_s[e])] - 1.0;
   }
   if (t < mi) ins_s[t] = w.ins_el[t];
   __syncthreads();
-  const int i = blockIdx.x * WG + t;
-  if (i >= kx) return;
+  const int i = i0 + lane;
+  const bool live = i < kx;
   const T* R = w.R[sp];
   T* N = w.N[sp];
   const size_t ld = w.ld;
-  // A, column-major [s][i]
-  for (int s = 0; s < m; ++s) {
-    double v;
-    if (cand_s[s] >= 0) {
-      const int jj = row_s[s] - k0;
-      if (i < k0) v = -(double)w.Y[sp][(size_t)jj * w.cap + i];
-      else v = -w.gram[sp][ins_s[i - k0] * KS_MAX + e_s[s]] + (i - k0 == jj ? 1.0 : 0.0);
-    } else {
-      const int p = slot_s[s];
-      const double nip = (i < k0) ? (double)N[i + (size_t)p * ld] : (double)R[(size_t)ins_s[i - k0] * w.cap + p];
-      v = f_s[s] * ((i == p ? 1.0 : 0.0) - nip);
-    }
-    w.A[sp][(size_t)s * w.cap + i] = (T)v;
-  }
-  // B, row-major [a][i] = sum_b Gamma^{-1}[a][b] Row_{S_b}[i]
-  double rv[KS_MAX];
-#pragma unroll
-  for (int b = 0; b < KS_MAX; ++b) {
+  for (int b = wv; b < m; b += WG / 64) {
     double x = 0.0;
-    if (b < m) {
+    if (live) {
       if (i < k0) x = (double)R[(size_t)e_s[b] * w.cap + i];
       else x = (cand_s[b] >= 0 && row_s[b] == i) ? 1.0 : 0.0;
     }
-    rv[b] = x;
+    rv_s[b][lane] = x;
   }
-  for (int a = 0; a < m; ++a) {
-    double s = 0.0;
-#pragma unroll
-    for (int b = 0; b < KS_MAX; ++b) s += gi_s[a * KS_MAX + b] * rv[b];
-    w.B[sp][(size_t)a * w.cap + i] = (T)s;
+  __syncthreads();
+  if (!live) return;
+  // A, column-major [s][i]
+  for (int s = wv; s < m; s += WG / 64) {
+    double v;
+    if (cand_s[s] >= 0) {
+      const int jj = row_s[s] - k0;
+      if (i < k0) v = d_s[s] * (double)w.Y[sp][(size_t)jj * w.cap + i];
+      else v = (i - k0 == jj ? 1.0 : 0.0) - w.gram[sp][ins_s[i - k0] * KS_MAX + e_s[s]];
+    } else {
+      const int p = slot_s[s];
+      const double nip = (i < k0) ? (double)N[i + (size_t)p * ld] : (double)R[(size_t)ins_s[i - k0] * w.cap + p];
+      v = (i == p ? 1.0 : 0.0) - nip;
+    }
+    w.A[sp][(size_t)s * w.cap + i] = (T)v;
+  }
+  // B, row-major [a][i] = sum_b Gt^{-1}[a][b] Row_{S_b}[i]
+  for (int a = wv; a < m; a += WG / 64) {
+    double acc = 0.0;
+    for (int b = 0; b < m; ++b) acc += gi_s[a * KS_MAX + b] * rv_s[b][lane];
+    w.B[sp][(size_t)a * w.cap + i] = (T)acc;
   }
   // extension of N (reads above touch only rows and columns < k0 of N)
-  for (int jj = 0; jj < mi; ++jj) {
+  for (int jj = wv; jj < mi; jj += WG / 64) {
     if (i < k0) N[(k0 + jj) + (size_t)i * ld] = R[(size_t)ins_s[jj] * w.cap + i];
     N[i + (size_t)(k0 + jj) * ld] = (i == k0 + jj) ? (T)1 : (T)0;
   }

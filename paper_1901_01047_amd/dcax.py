@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
                 ("beta", ctypes.c_double), ("mu", ctypes.c_double), ("K_exp", ctypes.c_double),
                 ("n_tau", ctypes.c_int32), ("precision", ctypes.c_int32), ("submatrix_k", ctypes.c_int32),
                 ("refresh_every", ctypes.c_int32), ("max_order", ctypes.c_int32), ("n_freq", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("warmup_sweeps", ctypes.c_int32), ("sweep_length", ctypes.c_int32)]
 
 
 class Vertex(ctypes.Structure):
@@ -129,7 +129,7 @@ def _check(st):
 
 def make_params(cluster=(2, 0, 0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0, K_exp=1.0, n_tau=1000,
                 precision=DCAX_FP64, submatrix_k=16, refresh_every=0, max_order=512, n_freq=64,
-                seed=985456376):
+                seed=985456376, warmup_sweeps=20, sweep_length=0):
     p = Params()
     p.abi_version = DCAX_ABI_VERSION
     for i in range(4):
@@ -137,6 +137,7 @@ def make_params(cluster=(2, 0, 0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0, K_
     p.t, p.tp, p.U, p.beta, p.mu, p.K_exp = t, tp, U, beta, mu, K_exp
     p.n_tau, p.precision, p.submatrix_k = n_tau, precision, submatrix_k
     p.refresh_every, p.max_order, p.n_freq, p.seed = refresh_every, max_order, n_freq, seed
+    p.warmup_sweeps, p.sweep_length = warmup_sweeps, sweep_length
     return p
 
 

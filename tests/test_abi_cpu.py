@@ -60,7 +60,7 @@ def test_struct_layouts_match_header(tmp_path):
 @pytest.mark.parametrize("field,value", [("abi_version", 7), ("beta", -1.0), ("U", -0.5), ("K_exp", 0.0),
                                          ("n_tau", 1), ("precision", 5), ("submatrix_k", 0),
                                          ("submatrix_k", 65), ("max_order", 0), ("n_freq", -1),
-                                         ("refresh_every", -3)])
+                                         ("refresh_every", -3), ("warmup_sweeps", -1), ("sweep_length", -2)])
 def test_create_rejects_bad_params(lib, field, value):
     p = dcax.make_params()
     setattr(p, field, value)

@@ -85,19 +85,20 @@ def test_batch_finalize_layout():
     wb.close()
 
 
-@pytest.mark.parametrize("precision", [dcax.DCAX_FP64, dcax.DCAX_FP32_MIXED])
-def test_graph_sweeps_equal_eager_sweeps(precision):
+@pytest.mark.parametrize("precision,timing", [(dcax.DCAX_FP64, False), (dcax.DCAX_FP32_MIXED, False),
+                                              (dcax.DCAX_FP64, True)])
+def test_graph_sweeps_equal_eager_sweeps(precision, timing):
     """Sweeps replayed as captured hipGraphs follow the same trajectory.
 
     The graph path launches the same kernels with launch shapes rounded up to
     the next order bucket, so the chains must stay bit-identical; measurements
     and synchronisations run eagerly between the replays, and every replay is
     compared through the state it leaves."""
-    print(f"[graph] precision {precision}", flush=True)
+    print(f"[graph] precision {precision} timing {timing}", flush=True)
     plist = [params(d, precision) for d in BATCH]
     we, wg = dcax.Walker(plist), dcax.Walker(plist)
     wg.set_graphs(True)
-    wg.set_timing(True)
+    wg.set_timing(timing)
     acc_e, aux_e = we.new_accumulator()
     acc_g, aux_g = wg.new_accumulator()
     for sw in range(25):
@@ -114,8 +115,9 @@ def test_graph_sweeps_equal_eager_sweeps(precision):
             assert np.array_equal(ie, ig) and np.array_equal(Ne, Ng), f"walker {i} spin {sp}: N differs"
     assert torch.equal(acc_e, acc_g) and torch.equal(aux_e, aux_g)
     st = wg.stats()
-    assert st["fold_launches"] > 0 and st["fold_seconds"] > 0.0
+    if timing:
+        assert st["window_seconds"] > 0.0     # replayed sweeps are timed as a whole
     assert st["proposals"] == we.stats()["proposals"]
-    print(f"  graph replays identical; fold launches timed {st['fold_launches']}", flush=True)
+    print(f"  graph replays identical; timed {st['window_seconds']:.4f} s", flush=True)
     we.close()
     wg.close()

@@ -2,7 +2,8 @@
 
 Statistical pins, as for the oracle:
 * U = 0: gamma = 0, every ratio is K/(k+1) or k/K, the order is Poisson(K);
-* Hubbard atom: the order follows the two-Poisson mixture
+* Hubbard atom: the order, sampled once per sweep after the warm-up froze
+  the sweep length, follows the two-Poisson mixture
   p_k ~ [K^k + (K + beta U/2)^k] / k!;
 * 2x2 cluster at half filling: spin-averaged G(K, i w_n) and G(K, tau) against
   exact diagonalisation (criterion: at most max(1, 1% of n) points beyond
@@ -34,7 +35,7 @@ def order_samples(w, n_sweeps):
 def test_free_limit_poisson():
     print("[chain] U=0 Poisson", flush=True)
     p = dcax.make_params(cluster=(2, 0, 0, 2), U=0.0, beta=2.0, K_exp=3.0, n_tau=200, submatrix_k=8,
-                         max_order=128, n_freq=0, seed=17)
+                         max_order=128, n_freq=0, seed=17, warmup_sweeps=200)
     w = dcax.Walker(p)
     order_samples(w, 200)
     ks = order_samples(w, 4000)
@@ -48,7 +49,7 @@ def test_atom_order_distribution():
     print("[chain] atom order law", flush=True)
     U, beta, K = 4.0, 2.0, 1.0
     p = dcax.make_params(cluster=(1, 0, 0, 1), t=0.0, U=U, beta=beta, K_exp=K, n_tau=64, submatrix_k=4,
-                         max_order=128, n_freq=0, seed=23)
+                         max_order=128, n_freq=0, seed=23, warmup_sweeps=500)
     w = dcax.Walker(p)
     order_samples(w, 500)
     ks = order_samples(w, 30000)
@@ -92,8 +93,8 @@ def test_2x2_green_function_vs_ed():
 
     def G_of(sMb, sAb):
         Mavg = sMb / sAb[0]
-        g_iw = np.mean([measure.finalize_G_iw(m, Mavg[sp], 24) for sp in range(2)], axis=0)
-        g_t = np.mean([measure.G_tau_from_iw(m, Mavg[sp], np.full(m.Nc, sAb[1 + sp] / sAb[0]), nf, taus)
+        g_iw = np.mean([measure.finalize_G_iw(m, Mavg[sp][:, :24], 24) for sp in range(2)], axis=0)
+        g_t = np.mean([measure.G_tau_from_iw(m, Mavg[sp], sAb[1 + sp] / sAb[0], nf, taus)
                        for sp in range(2)], axis=0)
         return g_iw, g_t
 

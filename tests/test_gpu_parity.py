@@ -53,7 +53,9 @@ def test_g0_table(name):
     m = model(name)
     w = walker(name, max_order=64)
     t = w.g0_table()
-    assert np.max(np.abs(t - m.table)) < 1e-13
+    e = np.max(np.abs(t - m.table))
+    print(f"  max |G0 table - oracle table| {e:.2e}", flush=True)
+    assert e < 1e-13
     w.close()
 
 
@@ -113,6 +115,8 @@ def test_replay_parity(name, k_s, k_init, warm, n_rec):
     big = np.abs(ro) >= 1e-3
     print(f"  ratio rel err: median {np.median(rel):.2e} p99 {np.quantile(rel, 0.99):.2e} max {rel.max():.2e}; "
           f"scaled max {scaled.max():.2e}; |R|>=1e-3 max {rel[big].max():.2e}", flush=True)
+    worst = np.argsort(np.where(big, rel, 0.0))[-4:]
+    print("  worst (|R|, rel): " + ", ".join(f"({abs(ro[i]):.2e}, {rel[i]:.1e})" for i in worst), flush=True)
     assert scaled.max() < 1e-10
     assert rel[big].max() < 1e-10
     assert np.all(ratios[noop] == 0.0)
@@ -223,7 +227,7 @@ def test_finalize_matches_oracle():
     for sp in range(2):
         want = measure.finalize_G_iw(m, Mk[sp], nf)
         assert np.max(np.abs(Giw[sp] - want)) < 1e-13
-        want_t = measure.G_tau_from_iw(m, Mk[sp], np.full(m.Nc, aux[1 + sp] / aux[0]), nf, taus)
+        want_t = measure.G_tau_from_iw(m, Mk[sp], aux[1 + sp] / aux[0], nf, taus)
         assert np.max(np.abs(Gt[sp] - want_t)) < 1e-11
     w.close()
 

@@ -6,21 +6,31 @@ With G = N g, for a set S of flipped auxiliary spins with
 Delta_p = e^{V'_p - V_p} - 1:
 
 * Gamma_S = G_SS - diag((1 + Delta_p) / Delta_p);
-* det N'^{-1} / det N^{-1} = prod_{p in S} (-Delta_p) det Gamma_S, so adding q to
-  S multiplies the ratio by (-Delta_q)(Gamma_qq - Gamma_qS Gamma_S^{-1} Gamma_Sq)
-  and taking q out again divides it, i.e. multiplies it by
-  (Gamma_S^{-1})_qq / (-Delta_q);
+* det N'^{-1} / det N^{-1} = prod_{p in S} (-Delta_p) det Gamma_S;
 * N' = N + (E_S - G_{.S}) Gamma_S^{-1} N_{S.};
 * an insertion flips a non-interacting spin (V = 0) whose N row is
   X_q = g_{q,I} (e^{V_I} - 1) N and column e_q; removing flips V_p -> 0 and
   deletes row and column p.
 
+Gamma_S is singular where Delta = 0 (U = 0, where every flip leaves V
+unchanged).  The kernels therefore carry the column-scaled matrix
+Gt = Gamma_S diag(-Delta), Gt_xy = -Delta_y G_xy + delta_xy (1 + Delta_y),
+which is finite everywhere:
+
+* the ratio is det Gt, so adding q multiplies it by the Schur complement
+  Gt_qq - Gt_qS Gt_S^{-1} Gt_Sq and taking q out again by (Gt_S^{-1})_qq;
+* N' = N + (E_S - G_{.S}) diag(-Delta) Gt_S^{-1} N_{S.}; the scaled column of
+  a removed vertex is exactly e_p - N_{.p} (since (-Delta_p) e^{V_p} /
+  (e^{V_p} - 1) = 1), that of an inserted spin -Delta_c (e_c - G_{.c});
+* the column of Gt for a removed vertex p is N_ext{x,p} itself, from
+  G (e^V - 1) = N e^V - 1.
+
 ``WindowModel`` is a NumPy transcription of the kernel pipeline (gathers,
-candidate rows, Gram matrix of the window, sequential Schur loop, fold with
-compaction).  It is test code: the HIP library does not import it.  Replaying
-an oracle trace through it must reproduce every ratio and the final N.
+candidate rows, scaled Gram matrix of the window, sequential Schur loop,
+fold with compaction).  It is test code: the HIP library does not import it.
+Replaying an oracle trace through it must reproduce every ratio and the
+final N, also at U = 0.
 """
-import math
 
 import numpy as np
 import pytest
@@ -55,6 +65,38 @@ def test_gamma_identities_random():
         E[S, np.arange(len(S))] = 1.0
         N_fold = N + (E - G[:, S]) @ np.linalg.solve(Gam, N[S, :])
         assert np.max(np.abs(N_fold - np.linalg.inv(Ninv_new))) < 1e-11 * np.max(np.abs(N_fold))
+        # column-scaled form
+        Gt = -Delta[None, :] * G[np.ix_(S, S)] + np.diag(1.0 + Delta)
+        assert abs(np.linalg.det(Gt) - ratio) < 1e-10 * abs(ratio)
+        A = (E - G[:, S]) * (-Delta)[None, :]
+        N_fold2 = N + A @ np.linalg.solve(Gt, N[S, :])
+        assert np.max(np.abs(N_fold2 - N_fold)) < 1e-11 * np.max(np.abs(N_fold))
+        # columns of removed (here: flipped) vertices from N alone
+        ev = np.exp(V[S])
+        Gcol = (N[:, S] * ev[None, :] - E) / (ev - 1.0)[None, :]
+        assert np.max(np.abs(Gcol - G[:, S])) < 1e-10 * np.max(np.abs(G[:, S]))
+
+
+def test_scaled_gamma_is_finite_at_u0():
+    """At U = 0 every Delta vanishes: Gt = 1, ratio 1, and N stays the identity."""
+    rng = np.random.default_rng(3)
+    m = ctaux.Model(a1=(2, 0), a2=(0, 2), U=0.0, beta=3.0, n_tau=500)
+    assert m.gamma == 0.0
+    k = 7
+    r = rng.integers(0, 4, size=k)
+    t = rng.random(k) * m.beta
+    s = rng.choice([-1, 1], size=k)
+    N = np.linalg.inv(ctaux.n_inverse(m, r, t, s, 0))
+    assert np.array_equal(N, np.eye(k))
+    G = N @ m.prop.matrix(r, t)
+    S = np.array([1, 4, 5])
+    Delta = np.zeros(len(S))
+    Gt = -Delta[None, :] * G[np.ix_(S, S)] + np.diag(1.0 + Delta)
+    assert np.array_equal(Gt, np.eye(len(S)))
+    E = np.zeros((k, len(S)))
+    E[S, np.arange(len(S))] = 1.0
+    A = (E - G[:, S]) * (-Delta)[None, :]
+    assert np.array_equal(N + A @ np.linalg.solve(Gt, N[S, :]), np.eye(k))
 
 
 class WindowModel:
@@ -112,40 +154,35 @@ class WindowModel:
             R[ci] = X
             R[ti] = self.N[sp][tslot, :]
             Gm = np.zeros((nE, nE))
-            # candidate columns: G_{x,c} = R_x . g_{I,c} (+ g_{x,c} for candidate rows)
+            # candidate columns: Gt_{x,c} = -Delta_c G_{x,c} + delta_xc (1 + Delta_c),
+            # G_{x,c} = R_x . g_{I,c} (+ g_{x,c} for candidate rows)
+            Dc = self.ev(el_s[ci], sp) - 1.0
             Gm[:, ci] = R @ gcol
             Gm[np.ix_(ci, ci)] += gCC
-            # columns of existing vertices p come from N itself:
-            # G_{.p} = (e^{V_p} N_ext{.p} - e_p) / (e^{V_p} - 1)
-            evp = evI[tslot]
-            Gm[:, ti] = R[:, tslot] * (evp / (evp - 1.0))[None, :]
-            Gm[ti, ti] -= 1.0 / (evp - 1.0)
+            Gm[:, ci] *= -Dc[None, :]
+            Gm[ci, ci] += 1.0 + Dc
+            # columns of existing vertices p: Gt_{x,p} = N_ext{x,p}
+            Gm[:, ti] = R[:, tslot]
             Rw.append(R)
             Gram.append(Gm)
         # -- sequential Schur loop ---------------------------------------
-        S, Dl = [], [[], []]
+        S = []
         Ginv = [np.zeros((0, 0)), np.zeros((0, 0))]
         kcur = k0
         for (kind, site, tau, sq, vid, acc), q in zip(props, prop_el):
             if q in S:
                 j = S.index(q)
-                rat = [Ginv[sp][j, j] / (-Dl[sp][j]) for sp in (0, 1)]
+                rat = [Ginv[sp][j, j] for sp in (0, 1)]
             else:
                 rat, parts = [], []
                 for sp in (0, 1):
-                    sgn = 1.0 if sp == 0 else -1.0
-                    if cand[q]:
-                        D = math.exp(sgn * m.gamma * el_s[q]) - 1.0
-                    else:
-                        D = math.exp(-sgn * m.gamma * el_s[q]) - 1.0
-                    gqq = Gram[sp][q, q] - (1 + D) / D
                     gqS = Gram[sp][q, S]
                     gSq = Gram[sp][S, q]
                     L = Ginv[sp] @ gSq
                     Rr = gqS @ Ginv[sp]
-                    schur = gqq - gqS @ L
-                    rat.append(-D * schur)
-                    parts.append((D, L, Rr, schur))
+                    schur = Gram[sp][q, q] - gqS @ L
+                    rat.append(schur)
+                    parts.append((L, Rr, schur))
             fac = m.K_exp / (kcur + 1) if kind == 0 else kcur / m.K_exp
             self.ratios.append(fac * rat[0] * rat[1])
             if not acc:
@@ -157,11 +194,10 @@ class WindowModel:
                     A = A - np.outer(A[:, j], A[j, :]) / A[j, j]
                     keep = np.arange(len(S)) != j
                     Ginv[sp] = A[np.ix_(keep, keep)]
-                    Dl[sp].pop(j)
                 S.pop(j)
             else:
                 for sp in (0, 1):
-                    D, L, Rr, schur = parts[sp]
+                    L, Rr, schur = parts[sp]
                     n = len(S)
                     B = np.empty((n + 1, n + 1))
                     B[:n, :n] = Ginv[sp] + np.outer(L, Rr) / schur
@@ -169,7 +205,6 @@ class WindowModel:
                     B[n, :n] = -Rr / schur
                     B[n, n] = 1.0 / schur
                     Ginv[sp] = B
-                    Dl[sp].append(D)
                 S.append(q)
             kcur += 1 if kind == 0 else -1
         # -- fold in the extended space, then compaction --------------------
@@ -193,13 +228,13 @@ class WindowModel:
                 Next[k0 + j, :k0] = Rw[sp][q]
                 Next[k0 + j, k0 + j] = 1.0
             if S:
-                # A = E_S - G_ext[:, S]; existing p: (e^{V_p}/(e^{V_p}-1)) (e_p - N_ext{.p});
-                # candidate c: e_c - [N g_{I,c}; G_{C_S, c}]
-                evI = self.ev(self.s, sp)
+                # A = (E_S - G_ext[:, S]) diag(-Delta): existing p: e_p - N_ext{.p};
+                # candidate c: rows < k0 Delta_c N g_{I,c}, inserted rows delta - Gt_{C_S, c}
                 A = np.zeros((kx, len(S)))
                 for j, q in enumerate(S):
                     if cand[q]:
-                        A[:k0, j] = -self.N[sp] @ m.prop.g(self.r, self.t, el_r[q], el_t[q])
+                        Dq = self.ev(el_s[q], sp) - 1.0
+                        A[:k0, j] = Dq * (self.N[sp] @ m.prop.g(self.r, self.t, el_r[q], el_t[q]))
                         for jj, qq in enumerate(ins):
                             A[k0 + jj, j] = -Gram[sp][qq, q]
                         A[row_of[q], j] += 1.0
@@ -207,7 +242,7 @@ class WindowModel:
                         p = el_slot[q]
                         e = np.zeros(kx)
                         e[p] = 1.0
-                        A[:, j] = evI[p] / (evI[p] - 1.0) * (e - Next[:, p])
+                        A[:, j] = e - Next[:, p]
                 rows = [row_of[q] for q in S]
                 Next = Next + A @ (Ginv[sp] @ Next[rows, :])
             keep = np.array([i for i in range(kx) if i not in rem], dtype=int)
@@ -224,9 +259,9 @@ class WindowModel:
         return self.id[o], self.N[0][np.ix_(o, o)], self.N[1][np.ix_(o, o)]
 
 
-@pytest.mark.parametrize("k_s,seed", [(4, 1), (16, 2), (64, 3)])
-def test_window_model_replays_oracle(k_s, seed):
-    m = ctaux.Model(a1=(2, 0), a2=(0, 2), U=4.0, beta=5.0, n_tau=1000)
+@pytest.mark.parametrize("k_s,seed,U", [(4, 1, 4.0), (16, 2, 4.0), (64, 3, 4.0), (16, 4, 0.0)])
+def test_window_model_replays_oracle(k_s, seed, U):
+    m = ctaux.Model(a1=(2, 0), a2=(0, 2), U=U, beta=5.0, n_tau=1000)
     w = ctaux.Walker(m, seed=seed, k_s=k_s, record=False)
     w.random_config(25)
     for _ in range(20):              # equilibrate, then replay from a refreshed state
@@ -248,12 +283,17 @@ def test_window_model_replays_oracle(k_s, seed):
         props = [p for p in props if not (p[0] == 1 and p[4] < 0)]
         wm.window(props)
     ref = np.array([rec[6] for rec in tr if not (rec[0] == 1 and rec[4] < 0)])
+    assert len(ref) > 50
     got = np.array(wm.ratios)
     assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-10
     ids, Nu, Nd = w.canonical()
     ids2, Nu2, Nd2 = wm.canonical()
     assert np.array_equal(ids, ids2)
     for A, B in ((Nu, Nu2), (Nd, Nd2)):
-        assert np.max(np.abs(A - B)) / np.max(np.abs(A)) < 1e-10
+        assert A.shape == B.shape
+        if A.size:
+            assert np.max(np.abs(A - B)) / np.max(np.abs(A)) < 1e-10
     if k_s == 64:
         assert n_unflip > 0      # the exact "spin touched twice" path was exercised
+    if U == 0.0:
+        assert np.array_equal(Nu2, np.eye(len(ids2))) and np.array_equal(Nd2, np.eye(len(ids2)))
