@@ -50,10 +50,12 @@ def roofline(stats0, stats1, precision):
         achieved = flops / secs / 1e12
         out = {"bound": "mfma", "achieved": achieved, "peak": peak_tf, "unit": "TFLOP/s",
                "frac": achieved / peak_tf}
+    attainable = min(peak_tf, PEAK["hbm_GBs"] * 1e9 * ai / 1e12)
     out.update({"traffic": None, "kernel": "k_fold", "launches": launches,
                 "avg_launch_us": secs / launches * 1e6, "flops_per_launch": flops / launches,
-                "bytes_per_launch": nbytes / launches, "tflops": flops / secs / 1e12,
-                "frac_of_mfma_peak": flops / secs / 1e12 / peak_tf})
+                "bytes_per_launch": nbytes / launches, "arith_intensity": ai, "tflops": flops / secs / 1e12,
+                "frac_of_mfma_peak": flops / secs / 1e12 / peak_tf,
+                "attainable_tflops": attainable, "frac_of_attainable": flops / secs / 1e12 / attainable})
     return out
 
 
@@ -101,9 +103,57 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False):
         "sign": s1["sign"], "refresh_max_drift": s1["max_drift"],
         "aborted_windows": s1["aborted_windows"] - s0["aborted_windows"],
     }
+    if graphs:
+        # kernels inside a replayed graph cannot be timed one by one: the fold
+        # figures come from eager sweeps right after the timed region
+        w.set_graphs(False)
+        r0 = w.stats()
+        for _ in range(min(steps, 30)):
+            w.sweep(1)
+            w.measure(acc, aux)
+        torch.cuda.synchronize()
+        res["roofline"] = roofline(r0, w.stats(), precision)
+        if res["roofline"]:
+            res["roofline"]["pass"] = "eager sweeps after the timed region"
     cfg_out = w.get_config()
     w.close()
     return res, cfg_out
+
+
+def run_batch(precision, steps, warmup, n_walkers=512):
+    """The batched workload: n_walkers walkers of uneven cluster size, U and
+    beta in one handle (one launch per kernel covers all of them)."""
+    import torch
+    from paper_1901_01047_amd import dcax
+    from paper_1901_01047_amd.workloads import batch_configs
+    prec = dcax.DCAX_FP64 if precision == "fp64" else dcax.DCAX_FP32_MIXED
+    plist = [dcax.make_params(**dict(d, warmup_sweeps=warmup), precision=prec, refresh_every=32)
+             for d in batch_configs(n_walkers)]
+    w = dcax.Walker(plist)
+    acc, aux = w.new_accumulator()
+    t0 = time.perf_counter()
+    w.sweep(warmup)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    w.set_timing(True)
+    s0 = w.stats()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        w.sweep(1)
+        w.measure(acc, aux)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s1 = w.stats()
+    acc_upd = (s1["accepted_insertions"] - s0["accepted_insertions"]) + \
+        (s1["accepted_removals"] - s0["accepted_removals"])
+    orders = w.orders()
+    res = {"value": acc_upd / dt, "ms_per_step": dt / steps * 1e3, "walkers": n_walkers,
+           "proposals_per_s": (s1["proposals"] - s0["proposals"]) / dt,
+           "order_min_mean_max": [min(orders), sum(orders) / len(orders), max(orders)],
+           "mean_fold_rank": (s1["flips_folded"] - s0["flips_folded"]) / max(s1["windows"] - s0["windows"], 1),
+           "warmup_seconds": t_warm, "roofline": roofline(s0, s1, precision)}
+    w.close()
+    return res
 
 
 def cpu_baseline(cfg_vertices, seconds=15.0):
@@ -146,10 +196,13 @@ def main():
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--graphs", choices=("on", "off"), default="off",
                     help="replay each sweep as a captured hipGraph")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="also run the batched workload with this many walkers (FP64 and FP32-mixed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(walkers are independent chains: see DESIGN.md for how the path shards)", file=sys.stderr)
+              "(walkers are independent Markov chains: on several GPUs each would run its own walkers "
+              "and the accumulators would be all-reduced once at the end)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -177,6 +230,9 @@ def main():
     if not args.fp64_only:
         r32, _ = run_gpu("mixed", args.steps, args.warmup, graphs=graphs)
         out["fp32_mixed"] = r32
+    if args.batch:
+        out["batch"] = {"fp64": run_batch("fp64", args.steps, args.warmup, args.batch),
+                        "fp32_mixed": run_batch("mixed", args.steps, args.warmup, args.batch)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg_v, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -110,7 +110,8 @@ typedef struct {
   int32_t submatrix_k;     /* "max-submatrix-size", 1..64 (changeable later) */
   int32_t refresh_every;   /* sweeps between FP64 refreshes of N inside dcax_sweep; 0 = never */
   int32_t max_order;       /* largest expansion order the walker may reach */
-  int32_t n_freq;          /* Matsubara frequencies measured, n = 0 .. n_freq-1 */
+  int32_t n_freq;          /* Matsubara frequencies measured, n = 0 .. n_freq-1; with n_freq > 0
+                              the cluster may have at most 256 sites */
   uint64_t seed;           /* "seed" of the walker's counter-based generator */
   int32_t warmup_sweeps;   /* "warm-up-sweeps": generator sweeps after which the sweep length freezes */
   int32_t sweep_length;    /* proposals per sweep (rounded up to a multiple of submatrix_k);

@@ -332,6 +332,8 @@ dcax_status validate(const dcax_params* p) {
   if (p->sweep_length < 0) return fail(DCAX_E_INVAL, "sweep_length must be >= 0");
   Geometry g;
   if (!build_geometry(p->cluster, g)) return fail(DCAX_E_INVAL, "degenerate or too large cluster");
+  if (p->n_freq > 0 && g.Nc > MEAS_NC_MAX)
+    return fail(DCAX_E_INVAL, "the measurement supports clusters of at most 256 sites");
   return DCAX_OK;
 }
 

@@ -216,6 +216,44 @@ __host__ __device__ inline void uniforms2(uint64_t seed, long long g, uint32_t s
   v = ((double)(c[2] >> 5) * 67108864.0 + (double)(c[3] >> 6)) * (1.0 / 9007199254740992.0);
 }
 
+// Global-memory view of a pointer held in a View.  Pointers loaded from a
+// struct in memory are generic (flat) to the compiler; flat accesses count
+// against the LDS wait counter too, so a flat store inside an LDS-bound loop
+// stalls every later LDS read until the store has reached memory.
+template <typename P>
+__device__ inline __attribute__((address_space(1))) P* gp(P* p) {
+  return (__attribute__((address_space(1))) P*)p;
+}
+
+// Values every lane of the wavefront holds, moved to scalar registers so
+// that loops and branches on them stay uniform (the compiler cannot prove
+// uniformity of values read from LDS or memory).
+__device__ inline int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline long long uni(long long x) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+  return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ inline double uni(double x) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+// The value a uniform-indexed lane holds (v_readlane, no LDS round trip).
+__device__ inline double lane_value(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum of v over lanes 0 .. n-1, in lane order, identical in every lane.
+__device__ inline double lanes_sum(double v, int n) {
+  double s = 0.0;
+  for (int a = 0; a < n; ++a) s += lane_value(v, a);
+  return s;
+}
+
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;

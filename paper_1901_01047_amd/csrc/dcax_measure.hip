@@ -14,40 +14,47 @@
 
 namespace dcax {
 
-// Counting sort of the vertices by site, buckets padded to 16 rows.
+// Counting sort of the vertices by site, buckets padded to 16 rows.  The
+// sites are staged in LDS; one thread per site places its vertices in their
+// original order (stable).
+constexpr int SORT_MAX = 32768 + 128;
 template <typename T>
 __global__ void __launch_bounds__(WG) k_meas_sort(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
-  int* order = w.m_order;
-  int* off = w.m_off;
+  const auto order = gp(w.m_order);
+  const auto off = gp(w.m_off);
+  const auto v_site = gp(w.v_site);
   const int kpad_cap = w.kpad_cap;
   const int k = w.ctl->k;
   const int Nc = w.Nc;
   __shared__ int cnt_s[4097];  // [Nc + 1], Nc <= 4096
+  __shared__ unsigned short site_s[SORT_MAX];
   for (int a = threadIdx.x; a <= Nc; a += WG) cnt_s[a] = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < k; i += WG) atomicAdd(&cnt_s[w.v_site[i]], 1);
+  for (int i = threadIdx.x; i < k; i += WG) {
+    const int a = v_site[i];
+    site_s[i] = (unsigned short)a;
+    atomicAdd(&cnt_s[a], 1);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     int o = 0;
     for (int a = 0; a < Nc; ++a) {
       const int c = cnt_s[a];
       cnt_s[a] = o;
-      off[a] = o;
       o += (c + 15) & ~15;
     }
-    off[Nc] = o;
     cnt_s[Nc] = o;
   }
   __syncthreads();
   const int kpad = cnt_s[Nc];
+  for (int a = threadIdx.x; a <= Nc; a += WG) off[a] = cnt_s[a];
   for (int i = threadIdx.x; i < kpad && i < kpad_cap; i += WG) order[i] = -1;
   __syncthreads();
-  // stable placement: one thread per site keeps the original order
   for (int a = threadIdx.x; a < Nc; a += WG) {
-    int o = off[a];
+    int o = cnt_s[a];
     for (int i = 0; i < k; ++i)
-      if (w.v_site[i] == a) order[o++] = i;
+      if (site_s[i] == a) order[o++] = i;
   }
 }
 
@@ -105,10 +112,11 @@ __global__ void __launch_bounds__(WG) k_meas_phase(const View<T>* __restrict__ v
 template <typename T>
 __global__ void __launch_bounds__(64) k_meas_block(const View<T>* __restrict__ vs, int nc_max) {
   const View<T>& w = vs[blockIdx.z];
-  const int* order = w.m_order;
-  const int* off = w.m_off;
+  const auto order = gp(w.m_order);
+  const auto off = gp(w.m_off);
   const int ldm = w.kpad_cap;
-  const T* E = w.m_E;
+  const auto E = gp(w.m_E);
+  const auto v_tau = gp(w.v_tau);
   const int n_freq = w.n_freq;
   const int Nc = w.Nc;
   const int sp = blockIdx.x / (nc_max * nc_max);
@@ -116,8 +124,8 @@ __global__ void __launch_bounds__(64) k_meas_block(const View<T>* __restrict__ v
   const int a = ab / nc_max, b = ab % nc_max;
   const int n0 = blockIdx.y * 16;
   if (a >= Nc || b >= Nc || n0 >= n_freq) return;
-  const T* Ms = w.m_Ms[sp];
-  double* Mab = w.m_Mab[sp];
+  const auto Ms = gp(w.m_Ms[sp]);
+  const auto Mab = gp(w.m_Mab[sp]);
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
   const int ia0 = off[a], ia1 = off[a + 1], jb0 = off[b], jb1 = off[b + 1];
@@ -140,7 +148,7 @@ __global__ void __launch_bounds__(64) k_meas_block(const View<T>* __restrict__ v
     // lane holds D[n = n0 + row(lane, r)][i' = ib + li]
     const int i = order[ip];
     if (i >= 0) {
-      const double ti = w.v_tau[i];
+      const double ti = v_tau[i];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int n = n0 + Mfma<T>::row(lane, r);
@@ -174,7 +182,10 @@ __global__ void __launch_bounds__(64) k_meas_block(const View<T>* __restrict__ v
   }
 }
 
-// acc[sp][K][n] += sign (1/Nc) sum_ab e^{-i K (r_a - r_b)} M(a, b; w_n).
+// acc[sp][K][n] += sign (1/Nc) sum_ab e^{-i K (r_a - r_b)} M(a, b; w_n),
+// with the site phases phi(K, a) = e^{-i K r_a} tabulated in LDS:
+// e^{-i K (r_a - r_b)} = phi(K, a) conj(phi(K, b)).
+constexpr int MEAS_NC_MAX = 256;
 template <typename T>
 __global__ void __launch_bounds__(WG) k_meas_K(const View<T>* __restrict__ vs, double* acc_all) {
   const View<T>& w = vs[blockIdx.z >> 1];
@@ -184,27 +195,35 @@ __global__ void __launch_bounds__(WG) k_meas_K(const View<T>* __restrict__ vs, d
   const int n = blockIdx.x * WG + threadIdx.x;
   const int q = blockIdx.y;
   if (q >= Nc) return;
-  const int* sites = w.sites;
-  const double* Kp = w.Kp;
-  double* acc = acc_all + w.acc_off;
-  const double sign = w.ctl->sign;
-  const double* Mab = w.m_Mab[sp];
-  if (n < n_freq) {
-    double re = 0.0, im = 0.0;
-    for (int a = 0; a < Nc; ++a)
-      for (int b = 0; b < Nc; ++b) {
-        const double ph = -(Kp[2 * q] * (double)(sites[2 * a] - sites[2 * b]) +
-                            Kp[2 * q + 1] * (double)(sites[2 * a + 1] - sites[2 * b + 1]));
-        double s, c;
-        sincos(ph, &s, &c);
-        const size_t o = 2 * (((size_t)a * Nc + b) * n_freq + n);
-        re += c * Mab[o] - s * Mab[o + 1];
-        im += c * Mab[o + 1] + s * Mab[o];
-      }
-    const size_t o = 2 * (((size_t)sp * Nc + q) * n_freq + n);
-    acc[o] += sign * re / (double)Nc;
-    acc[o + 1] += sign * im / (double)Nc;
+  __shared__ double pr_s[MEAS_NC_MAX], pi_s[MEAS_NC_MAX];
+  for (int a = threadIdx.x; a < Nc; a += WG) {
+    const double ph = -(w.Kp[2 * q] * (double)w.sites[2 * a] + w.Kp[2 * q + 1] * (double)w.sites[2 * a + 1]);
+    double s, c;
+    sincos(ph, &s, &c);
+    pr_s[a] = c;
+    pi_s[a] = s;
   }
+  __syncthreads();
+  if (n >= n_freq) return;
+  const auto Mab = gp(w.m_Mab[sp]);
+  double re = 0.0, im = 0.0;
+  for (int a = 0; a < Nc; ++a) {
+    // t = sum_b conj(phi_b) M(a, b)
+    double tr = 0.0, ti = 0.0;
+    for (int b = 0; b < Nc; ++b) {
+      const size_t o = 2 * (((size_t)a * Nc + b) * n_freq + n);
+      const double mr = Mab[o], mi = Mab[o + 1];
+      tr += pr_s[b] * mr + pi_s[b] * mi;
+      ti += pr_s[b] * mi - pi_s[b] * mr;
+    }
+    re += pr_s[a] * tr - pi_s[a] * ti;
+    im += pr_s[a] * ti + pi_s[a] * tr;
+  }
+  const auto acc = gp(acc_all + w.acc_off);
+  const double sign = w.ctl->sign;
+  const size_t o = 2 * (((size_t)sp * Nc + q) * n_freq + n);
+  acc[o] += sign * re / (double)Nc;
+  acc[o + 1] += sign * im / (double)Nc;
 }
 
 // aux += [sign, sign tr(M_up)/Nc, sign tr(M_dn)/Nc]; one block per spin.

@@ -33,7 +33,102 @@ __global__ void __launch_bounds__(WG) k_build_ninv(const View<T>* __restrict__ v
 }
 
 // Eliminates panel columns [p0, p0 + nb) (blockIdx.x = spin, blockIdx.z =
-// walker).
+// walker).  The k x nb panel is staged in LDS when it fits (k <= PANEL_ROWS),
+// otherwise the steps run on global memory; the pivot search reduces within
+// wavefronts first.  Ties in |pivot| go to the smaller row index.
+constexpr int PANEL_ROWS = 512;
+
+__device__ inline void argmax_wave(double& v, int& i) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v2 = __shfl_xor(v, o, 64);
+    const int i2 = __shfl_xor(i, o, 64);
+    if (v2 > v || (v2 == v && i2 < i)) {
+      v = v2;
+      i = i2;
+    }
+  }
+}
+
+// Panel element (r, x): LDS column-major with stride k, or M in global memory.
+struct PanelLds {
+  double* s;
+  int k;
+  __device__ double& operator()(int r, int x) const { return s[x * k + r]; }
+};
+struct PanelGlobal {
+  __attribute__((address_space(1))) double* m;
+  size_t ld;
+  int p0;
+  __device__ __attribute__((address_space(1))) double& operator()(int r, int x) const {
+    return m[r + (size_t)(p0 + x) * ld];
+  }
+};
+
+template <typename Acc>
+__device__ inline double gj_panel_steps(Acc at, int k, int p0, int nb, __attribute__((address_space(1))) int* ipiv,
+                                        Ctl* ctl) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  __shared__ double vmax_s[WG / 64], row_s[NB];
+  __shared__ int imax_s[WG / 64];
+  double dsign = 1.0;
+  for (int cidx = 0; cidx < nb; ++cidx) {
+    const int c = p0 + cidx;
+    double best = -1.0;
+    int bi = k;
+    for (int r = c + t; r < k; r += WG) {
+      const double v = fabs((double)at(r, cidx));
+      if (v > best) {
+        best = v;
+        bi = r;
+      }
+    }
+    argmax_wave(best, bi);
+    if (lane == 0) {
+      vmax_s[wv] = best;
+      imax_s[wv] = bi;
+    }
+    __syncthreads();
+    double pv = vmax_s[0];
+    int piv = imax_s[0];
+    for (int x = 1; x < WG / 64; ++x)
+      if (vmax_s[x] > pv || (vmax_s[x] == pv && imax_s[x] < piv)) {
+        pv = vmax_s[x];
+        piv = imax_s[x];
+      }
+    if (t == 0) {
+      ipiv[c] = piv;
+      if (!(pv > 0.0) || !isfinite(pv)) latch(ctl, ST_NUMERIC);
+    }
+    // swap rows c and piv inside the panel, then scale row c
+    if (t < nb && piv != c && piv < k) {
+      const double x = at(c, t);
+      at(c, t) = at(piv, t);
+      at(piv, t) = x;
+    }
+    __syncthreads();
+    const double a_cc = at(c, cidx);
+    // sign of det: product of the pivots, one factor -1 per row interchange
+    dsign *= ((a_cc < 0.0) ? -1.0 : 1.0) * ((piv != c) ? -1.0 : 1.0);
+    __syncthreads();
+    if (t < nb) {
+      const double v = (t == cidx) ? 1.0 / a_cc : at(c, t) / a_cc;
+      at(c, t) = v;
+      row_s[t] = v;
+    }
+    __syncthreads();
+    for (int r = t; r < k; r += WG) {
+      if (r == c) continue;
+      const double f = at(r, cidx);
+      for (int x = 0; x < nb; ++x) {
+        if (x == cidx) at(r, x) = -f * row_s[x];
+        else at(r, x) -= f * row_s[x];
+      }
+    }
+    __syncthreads();
+  }
+  return dsign;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(WG) k_gj_panel(const View<T>* __restrict__ vs, int p0) {
   const View<T>& w = vs[blockIdx.z];
@@ -41,74 +136,22 @@ __global__ void __launch_bounds__(WG) k_gj_panel(const View<T>* __restrict__ vs,
   if (p0 >= k) return;
   const int nb = (k - p0 < NB) ? k - p0 : NB;
   const int sp = blockIdx.x;
-  double* M = w.M[sp];
-  int* ipiv = w.ipiv[sp];
+  const auto Mg = gp(w.M[sp]);
   const size_t ldm = w.cap;
   const int t = threadIdx.x;
-  __shared__ double vmax_s[WG];
-  __shared__ int imax_s[WG];
-  __shared__ double row_s[NB];
-  for (int cidx = 0; cidx < nb; ++cidx) {
-    const int c = p0 + cidx;
-    double best = -1.0;
-    int bi = k;
-    for (int r = c + t; r < k; r += WG) {
-      const double v = fabs(M[r + (size_t)c * ldm]);
-      if (v > best) {
-        best = v;
-        bi = r;
-      }
-    }
-    vmax_s[t] = best;
-    imax_s[t] = bi;
+  __shared__ double pan_s[PANEL_ROWS * NB];
+  double dsign;
+  if (k <= PANEL_ROWS) {
+    for (int x = 0; x < nb; ++x)
+      for (int r = t; r < k; r += WG) pan_s[x * k + r] = Mg[r + (size_t)(p0 + x) * ldm];
     __syncthreads();
-    for (int o = WG / 2; o > 0; o >>= 1) {
-      if (t < o) {
-        const double v2 = vmax_s[t + o];
-        const int i2 = imax_s[t + o];
-        if (v2 > vmax_s[t] || (v2 == vmax_s[t] && i2 < imax_s[t])) {
-          vmax_s[t] = v2;
-          imax_s[t] = i2;
-        }
-      }
-      __syncthreads();
-    }
-    const int piv = imax_s[0];
-    const double pv = vmax_s[0];
-    if (t == 0) {
-      ipiv[c] = piv;
-      if (!(pv > 0.0) || !isfinite(pv)) latch(w.ctl, ST_NUMERIC);
-    }
-    // swap rows c and piv inside the panel, then scale row c
-    if (t < nb && piv != c && piv < k) {
-      const size_t col = (size_t)(p0 + t) * ldm;
-      const double x = M[c + col];
-      M[c + col] = M[piv + col];
-      M[piv + col] = x;
-    }
-    __syncthreads();
-    const double a_cc = M[c + (size_t)c * ldm];
-    // sign of det: product of the pivots, one factor -1 per row interchange
-    if (t == 0) w.detsign[sp] *= ((a_cc < 0.0) ? -1.0 : 1.0) * ((piv != c) ? -1.0 : 1.0);
-    __syncthreads();
-    if (t < nb) {
-      const size_t col = (size_t)(p0 + t) * ldm;
-      const double v = (p0 + t == c) ? 1.0 / a_cc : M[c + col] / a_cc;
-      M[c + col] = v;
-      row_s[t] = v;
-    }
-    __syncthreads();
-    for (int r = t; r < k; r += WG) {
-      if (r == c) continue;
-      const double f = M[r + (size_t)c * ldm];
-      for (int x = 0; x < nb; ++x) {
-        const size_t o = r + (size_t)(p0 + x) * ldm;
-        if (p0 + x == c) M[o] = -f * row_s[x];
-        else M[o] -= f * row_s[x];
-      }
-    }
-    __syncthreads();
+    dsign = gj_panel_steps(PanelLds{pan_s, k}, k, p0, nb, gp(w.ipiv[sp]), w.ctl);
+    for (int x = 0; x < nb; ++x)
+      for (int r = t; r < k; r += WG) Mg[r + (size_t)(p0 + x) * ldm] = pan_s[x * k + r];
+  } else {
+    dsign = gj_panel_steps(PanelGlobal{Mg, ldm, p0}, k, p0, nb, gp(w.ipiv[sp]), w.ctl);
   }
+  if (t == 0) w.detsign[sp] *= dsign;
 }
 
 // Applies the panel's row swaps to the other columns, moves their panel rows
@@ -121,10 +164,10 @@ __global__ void __launch_bounds__(WG) k_gj_prep(const View<T>* __restrict__ vs, 
   if (p0 >= k) return;
   const int nb = (k - p0 < NB) ? k - p0 : NB;
   const int sp = blockIdx.y;
-  double* M = w.M[sp];
-  const int* ipiv = w.ipiv[sp];
-  double* P = w.P[sp];
-  double* Tm = w.Tm[sp];
+  const auto M = gp(w.M[sp]);
+  const auto ipiv = gp(w.ipiv[sp]);
+  const auto P = gp(w.P[sp]);
+  const auto Tm = gp(w.Tm[sp]);
   const size_t ldm = w.cap, ldt = w.cap;
   const int j = blockIdx.x * WG + threadIdx.x;
   if (j >= k) return;

@@ -303,8 +303,8 @@ __global__ void __launch_bounds__(WG) k_cand_x(const View<T>* __restrict__ vs) {
   const int j0 = blockIdx.x * 16;
   if (nC == 0 || j0 >= k0) return;
   const int sp = blockIdx.y;
-  const T* N = w.N[sp];
-  const T* Wm = w.W[sp];
+  const auto N = gp(w.N[sp]);
+  const auto Wm = gp(w.W[sp]);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nRB = (nC + 15) >> 4;
@@ -332,11 +332,12 @@ __global__ void __launch_bounds__(WG) k_cand_x(const View<T>* __restrict__ vs) {
   const int rb = wv;
   if (rb >= nRB) return;
   const acc_t sum = ((red[0][rb][lane] + red[1][rb][lane]) + red[2][rb][lane]) + red[3][rb][lane];
-  T* R = w.R[sp];
+  const auto R = gp(w.R[sp]);
+  const auto cand_el = gp(w.cand_el);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int cr = rb * 16 + Mfma<T>::row(lane, r);
-    if (cr < nC && jc < k0) R[(size_t)w.cand_el[cr] * w.cap + jc] = sum[r];
+    if (cr < nC && jc < k0) R[(size_t)cand_el[cr] * w.cap + jc] = sum[r];
   }
 }
 
@@ -359,11 +360,11 @@ __global__ void __launch_bounds__(WG) k_gram(const View<T>* __restrict__ vs) {
   if (x >= nE) return;
   const int k0 = c->k0, nC = c->nC;
   const int cx = w.el_cand[x];
-  const T* Rx = w.R[sp] + (size_t)x * w.cap;
+  const auto Rx = gp(w.R[sp] + (size_t)x * w.cap);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double* G = w.gram[sp] + x * KS_MAX;
+  const auto G = gp(w.gram[sp] + x * KS_MAX);
   for (int cc = wv; cc < nC; cc += WG / 64) {
-    const T* gc = w.gcol + (size_t)cc * w.cap;
+    const auto gc = gp(w.gcol + (size_t)cc * w.cap);
     double s = 0.0;
     for (int i = lane; i < k0; i += 64) s += (double)Rx[i] * (double)gc[i];
     s = wave_sum(s);
@@ -407,45 +408,74 @@ static_assert(KS_MAX == AW, "the accept kernel maps one lane to one window eleme
 template <typename T>
 __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
-  int* el_row = w.el_row;
-  int* remap = w.remap;
-  int* moves = w.moves;
+  auto el_row = gp(w.el_row);
+  auto remap = gp(w.remap);
+  auto moves = gp(w.moves);
   const uint64_t seed = w.seed;
   Ctl* c = w.ctl;
   if (!c->active) return;
+  // nothing inside the proposal loop touches global memory: candidate ids and
+  // replay ratios are collected in LDS and written after it
   // LDS rows are padded to LS doubles: with a stride of 64 doubles every lane
   // reading one column would hit the same bank.
   constexpr int LS = KS_MAX + 1;
+  constexpr int CH = 8;       // columns per chunk of the row loops
   __shared__ double gam_s[2][KS_MAX * LS];
   __shared__ double ginv_s[2][KS_MAX * LS];
-  __shared__ double rv_s[2][KS_MAX];
+  
   __shared__ int S_s[KS_MAX], pos_s[KS_MAX], insl_s[KS_MAX];
   __shared__ WinProp wp_s[KS_MAX];
   __shared__ int cand_s[KS_MAX], spin_s[KS_MAX], slot_s[KS_MAX];
+  __shared__ long long cid_s[KS_MAX];
+  __shared__ double rout_s[KS_MAX];
   const int lane = threadIdx.x;
-  const int nE = c->nE, nP = c->nP, k0 = c->k0;
-  const double K_exp = w.K_exp;
-  const int max_order = w.max_order;
-  for (int x = 0; x < KS_MAX; ++x) {
-    const bool in = x < nE && lane < nE;
-    gam_s[0][x * LS + lane] = in ? w.gram[0][x * KS_MAX + lane] : 0.0;
-    gam_s[1][x * LS + lane] = in ? w.gram[1][x * KS_MAX + lane] : 0.0;
+  const int nE = uni(c->nE), nP = uni(c->nP), k0 = uni(c->k0), nC = uni(c->nC);
+  const double K_exp = uni(w.K_exp);
+  const int max_order = uni(w.max_order);
+  // only rows and columns below nE are ever read
+  const auto gram0 = gp(w.gram[0]), gram1 = gp(w.gram[1]);
+  // rows x < nE of both spins, loads issued four rows at a time
+  for (int x0 = 0; x0 < nE; x0 += 4) {
+    double g0[4], g1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = x0 + u < nE && lane < nE;
+      g0[u] = in ? gram0[(x0 + u) * KS_MAX + lane] : 0.0;
+      g1[u] = in ? gram1[(x0 + u) * KS_MAX + lane] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (x0 + u < nE) {
+        gam_s[0][(x0 + u) * LS + lane] = g0[u];
+        gam_s[1][(x0 + u) * LS + lane] = g1[u];
+      }
   }
   pos_s[lane] = -1;
   if (lane < nP) wp_s[lane] = w.wp[lane];
   if (lane < nE) {
-    cand_s[lane] = w.el_cand[lane];
-    spin_s[lane] = w.el_s[lane];
-    slot_s[lane] = w.el_slot[lane];
+    cand_s[lane] = gp(w.el_cand)[lane];
+    spin_s[lane] = gp(w.el_s)[lane];
+    slot_s[lane] = gp(w.el_slot)[lane];
   }
+  if (lane < nC) cid_s[lane] = gp(w.cand_id)[lane];
   __syncthreads();
-  // window state: identical in every lane
-  int m = 0, kcur = k0, nins = 0, bad = 0, n_done = nP;
-  double sign = c->sign;
-  long long next_id = c->next_id, carry = -1;
+  // window state: identical in every lane, except sa = S[lane], the element
+  // at position `lane` of S (valid below m)
+  int m = 0, kcur = k0, nins = 0, bad = 0, n_done = nP, sa = 0;
+  double sign = uni(c->sign);
+  long long next_id = uni(c->next_id), carry = -1;
   long long n_ins = 0, n_rem = 0, n_mis = 0;
   for (int j = 0; j < nP; ++j) {
-    const WinProp p = wp_s[j];
+    m = uni(m);
+    kcur = uni(kcur);
+    nins = uni(nins);
+    WinProp p = wp_s[j];
+    p.kind = uni(p.kind);
+    p.el = uni(p.el);
+    p.forced = uni(p.forced);
+    p.carried = uni(p.carried);
+    p.u = uni(p.u);
+    p.gidx = uni(p.gidx);
     int q = p.el, ab = 0;
     if (p.forced < 0 && p.kind == 1 && !p.carried) {
       q = -1;
@@ -461,10 +491,10 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
               const unsigned long long hit = __ballot(lane < nE && slot_s[lane] == slot);
               e = hit ? (int)__ffsll((long long)hit) - 1 : -1;
             }
-            if (e >= 0 && pos_s[e] >= 0) continue;     // already removed in this window
+            if (e >= 0 && uni(pos_s[e]) >= 0) continue;     // already removed in this window
             if (e < 0) {
               ab = 1;
-              carry = w.v_id[slot];
+              carry = uni(gp(w.v_id)[slot]);
               break;
             }
             q = e;
@@ -472,7 +502,7 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
           }
           int idx = (int)(ui * (double)nins);
           if (idx >= nins) idx = nins - 1;
-          q = insl_s[idx];
+          q = uni(insl_s[idx]);
           break;
         }
         if (q < 0 && !ab) bad = 1;
@@ -483,28 +513,42 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
       break;
     }
     if (q < 0) {
-      if (lane == 0 && p.ridx >= 0) w.ratio_out[p.ridx] = 0.0;
+      if (lane == 0) rout_s[j] = 0.0;
       continue;
     }
-    const int pq = pos_s[q];
-    double r0, r1, L0 = 0.0, L1 = 0.0;
+    const int pq = uni(pos_s[q]);
+    double r0, r1, L0 = 0.0, L1 = 0.0, w0 = 0.0, w1 = 0.0;
     if (pq >= 0) {
-      r0 = ginv_s[0][pq * LS + pq];
-      r1 = ginv_s[1][pq * LS + pq];
+      r0 = uni(ginv_s[0][pq * LS + pq]);
+      r1 = uni(ginv_s[1][pq * LS + pq]);
     } else {
-      // L = Gt_S^{-1} Gt_Sq (lane a holds L_a), Schur = Gt_qq - Gt_qS L
-      if (lane < m) {
-        for (int b = 0; b < m; ++b) {
-          const int sb = S_s[b];
-          L0 += ginv_s[0][lane * LS + b] * gam_s[0][sb * LS + q];
-          L1 += ginv_s[1][lane * LS + b] * gam_s[1][sb * LS + q];
+      // lane a holds Gt_{S_a q} and Gt_{q S_a}; L = Gt_S^{-1} Gt_Sq (lane a
+      // holds L_a) with the Gt_{S_b q} read from lane b's register, and the
+      // Schur complement Gt_qq - Gt_qS L summed over lanes in order
+      const bool in = lane < m;
+      w0 = in ? gam_s[0][q * LS + sa] : 0.0;
+      w1 = in ? gam_s[1][q * LS + sa] : 0.0;
+      const double v0 = in ? gam_s[0][sa * LS + q] : 0.0, v1 = in ? gam_s[1][sa * LS + q] : 0.0;
+      // chunks of CH columns: the loads of a chunk are issued together
+      for (int b0 = 0; b0 < m; b0 += CH) {
+        double g0[CH], g1[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int b = min(b0 + u, KS_MAX - 1);
+          g0[u] = ginv_s[0][lane * LS + b];
+          g1[u] = ginv_s[1][lane * LS + b];
         }
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+          if (b0 + u < m) {
+            L0 += g0[u] * lane_value(v0, b0 + u);
+            L1 += g1[u] * lane_value(v1, b0 + u);
+          }
       }
-      const int sl = lane < m ? S_s[lane] : 0;
-      const double p0 = wave_sum(lane < m ? gam_s[0][q * LS + sl] * L0 : 0.0);
-      const double p1 = wave_sum(lane < m ? gam_s[1][q * LS + sl] * L1 : 0.0);
-      r0 = gam_s[0][q * LS + q] - p0;
-      r1 = gam_s[1][q * LS + q] - p1;
+      L0 = in ? L0 : 0.0;
+      L1 = in ? L1 : 0.0;
+      r0 = uni(gam_s[0][q * LS + q] - lanes_sum(w0 * L0, m));
+      r1 = uni(gam_s[1][q * LS + q] - lanes_sum(w1 * L1, m));
     }
     const double fac = (p.kind == 0) ? K_exp / (double)(kcur + 1) : (double)kcur / K_exp;
     const double R = fac * r0 * r1;
@@ -517,7 +561,7 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
       dec = (p.forced >= 0) ? p.forced : mine;
       if (p.forced >= 0 && mine != p.forced) ++n_mis;
     }
-    if (lane == 0 && p.ridx >= 0) w.ratio_out[p.ridx] = R;
+    if (lane == 0) rout_s[j] = R;
     if (dec && p.kind == 0 && kcur + 1 > max_order) {
       if (lane == 0) latch(c, ST_CAPACITY);
       dec = 0;
@@ -528,7 +572,7 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     if (p.kind == 0) {
       ++n_ins;
       if (p.forced < 0) {
-        if (lane == 0) w.cand_id[cand_s[q]] = next_id;
+        if (lane == 0) cid_s[cand_s[q]] = next_id;
         ++next_id;
       }
       if (lane == 0) insl_s[nins] = q;
@@ -546,29 +590,50 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     }
     if (pq < 0) {
       // bordering: q joins S at position m
+      // R = Gt_qS Gt_S^{-1} (lane b holds R_b), then the bordered inverse
       const double inv0 = 1.0 / r0, inv1 = 1.0 / r1;
-      if (lane < m) {
-        double R0 = 0.0, R1 = 0.0;
-        for (int a = 0; a < m; ++a) {
-          const int sa = S_s[a];
-          R0 += gam_s[0][q * LS + sa] * ginv_s[0][a * LS + lane];
-          R1 += gam_s[1][q * LS + sa] * ginv_s[1][a * LS + lane];
+      double R0 = 0.0, R1 = 0.0;
+      for (int a0 = 0; a0 < m; a0 += CH) {
+        double g0[CH], g1[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int a = min(a0 + u, KS_MAX - 1);
+          g0[u] = ginv_s[0][a * LS + lane];
+          g1[u] = ginv_s[1][a * LS + lane];
         }
-        rv_s[0][lane] = R0;
-        rv_s[1][lane] = R1;
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+          if (a0 + u < m) {
+            R0 += lane_value(w0, a0 + u) * g0[u];
+            R1 += lane_value(w1, a0 + u) * g1[u];
+          }
       }
-      __syncthreads();
-      if (lane < m) {
-        for (int b = 0; b < m; ++b) {
-          ginv_s[0][lane * LS + b] += L0 * rv_s[0][b] * inv0;
-          ginv_s[1][lane * LS + b] += L1 * rv_s[1][b] * inv1;
+      const double l0 = L0 * inv0, l1 = L1 * inv1;
+      for (int b0 = 0; b0 < m; b0 += CH) {
+        double g0[CH], g1[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int b = min(b0 + u, KS_MAX - 1);
+          g0[u] = ginv_s[0][lane * LS + b];
+          g1[u] = ginv_s[1][lane * LS + b];
         }
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+          if (b0 + u < m) {
+            const double r0u = lane_value(R0, b0 + u), r1u = lane_value(R1, b0 + u);
+            if (lane < m) {
+              ginv_s[0][lane * LS + b0 + u] = g0[u] + l0 * r0u;
+              ginv_s[1][lane * LS + b0 + u] = g1[u] + l1 * r1u;
+            }
+          }
+      }
+      if (lane < m) {
         ginv_s[0][lane * LS + m] = -L0 * inv0;
         ginv_s[1][lane * LS + m] = -L1 * inv1;
       } else if (lane == m) {
         for (int b = 0; b < m; ++b) {
-          ginv_s[0][m * LS + b] = -rv_s[0][b] * inv0;
-          ginv_s[1][m * LS + b] = -rv_s[1][b] * inv1;
+          ginv_s[0][m * LS + b] = -lane_value(R0, b) * inv0;
+          ginv_s[1][m * LS + b] = -lane_value(R1, b) * inv1;
         }
         ginv_s[0][m * LS + m] = inv0;
         ginv_s[1][m * LS + m] = inv1;
@@ -577,25 +642,36 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
         S_s[m] = q;
         pos_s[q] = m;
       }
+      if (lane == m) sa = q;
       ++m;
       __syncthreads();
     } else {
       // rank-1 downdate, then the last position moves into the hole
       const int js = pq, last = m - 1;
       const double piv0 = ginv_s[0][js * LS + js], piv1 = ginv_s[1][js * LS + js];
-      double c0 = 0.0, c1 = 0.0;
-      if (lane < m) {
-        c0 = ginv_s[0][lane * LS + js];
-        c1 = ginv_s[1][lane * LS + js];
-        rv_s[0][lane] = ginv_s[0][js * LS + lane];
-        rv_s[1][lane] = ginv_s[1][js * LS + lane];
-      }
+      const bool in = lane < m;
+      const double c0 = in ? ginv_s[0][lane * LS + js] : 0.0, c1 = in ? ginv_s[1][lane * LS + js] : 0.0;
+      const double rw0 = in ? ginv_s[0][js * LS + lane] : 0.0, rw1 = in ? ginv_s[1][js * LS + lane] : 0.0;
       __syncthreads();
-      if (lane < m)
-        for (int b = 0; b < m; ++b) {
-          ginv_s[0][lane * LS + b] -= c0 * rv_s[0][b] / piv0;
-          ginv_s[1][lane * LS + b] -= c1 * rv_s[1][b] / piv1;
+      const double f0 = c0 / piv0, f1 = c1 / piv1;
+      for (int b0 = 0; b0 < m; b0 += CH) {
+        double g0[CH], g1[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int b = min(b0 + u, KS_MAX - 1);
+          g0[u] = ginv_s[0][lane * LS + b];
+          g1[u] = ginv_s[1][lane * LS + b];
         }
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+          if (b0 + u < m) {
+            const double r0u = lane_value(rw0, b0 + u), r1u = lane_value(rw1, b0 + u);
+            if (in) {
+              ginv_s[0][lane * LS + b0 + u] = g0[u] - f0 * r0u;
+              ginv_s[1][lane * LS + b0 + u] = g1[u] - f1 * r1u;
+            }
+          }
+      }
       __syncthreads();
       if (js != last) {
         if (lane < m) {
@@ -614,60 +690,66 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
         pos_s[el_last] = js;
         pos_s[q] = -1;
       }
+      const int s_last = __shfl(sa, last, AW);
+      if (lane == js) sa = s_last;
       m = last;
       __syncthreads();
     }
   }
-  for (int a = 0; a < m; ++a)
-    if (lane < m) {
-      w.ginv[0][a * KS_MAX + lane] = ginv_s[0][a * LS + lane];
-      w.ginv[1][a * KS_MAX + lane] = ginv_s[1][a * LS + lane];
-    }
+  __syncthreads();
+  {
+    const auto gi0 = gp(w.ginv[0]), gi1 = gp(w.ginv[1]);
+    for (int a = 0; a < m; ++a)
+      if (lane < m) {
+        gi0[a * KS_MAX + lane] = ginv_s[0][a * LS + lane];
+        gi1[a * KS_MAX + lane] = ginv_s[1][a * LS + lane];
+      }
+    if (lane < n_done && wp_s[lane].ridx >= 0) gp(w.ratio_out)[wp_s[lane].ridx] = rout_s[lane];
+    if (lane < c->nC) gp(w.cand_id)[lane] = cid_s[lane];
+  }
   // Epilogue: the fold's column order, the new vertex arrays and the plan
   // that removes the deleted rows and columns of N.  Inserted spins take
   // slots k0 .. k0+mi-1; holes left below the new order are filled from the
   // surviving slots above it (remap[dst] = src, moves[] = (dst, src) pairs).
   // Nothing later in the window reads the vertex arrays or the order, so
   // both are final here.
-  __shared__ int ins_s[KS_MAX], hole_s[KS_MAX], src_s[KS_MAX], rem[KS_MAX], mi_s, nh_s;
+  __shared__ int ins_s[KS_MAX], hole_s[KS_MAX], src_s[KS_MAX], rem[KS_MAX], row_s[KS_MAX];
   const int knew = kcur;
+  // lane s < m looks at the element in position s of S; inserted spins are
+  // numbered in S order, removed slots ranked by value (they are distinct)
+  const int e_l = lane < m ? sa : -1;
+  const bool isc = lane < m && cand_s[e_l] >= 0;
+  const bool isr = lane < m && !isc;
+  const unsigned long long cmask = __ballot(isc), rmask = __ballot(isr);
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int mi = __popcll(cmask), mr = __popcll(rmask);
+  const int slot_l = isr ? slot_s[e_l] : 0x7fffffff;
+  if (isc) {
+    const int x = __popcll(cmask & below);
+    ins_s[x] = e_l;
+    row_s[lane] = k0 + x;
+  }
+  int rank = 0;
+  for (int b = 0; b < m; ++b) rank += __builtin_amdgcn_readlane(slot_l, b) < slot_l;
+  if (isr) {
+    row_s[lane] = slot_l;
+    rem[rank] = slot_l;
+  }
+  __syncthreads();
+  const int kx = k0 + mi;
+  // holes: the removed slots below the new order, in increasing order;
+  // sources: the surviving slots in [knew, kx) (there are as many)
+  const int nh = __popcll(__ballot(isr && slot_l < knew));
+  if (lane < nh) hole_s[lane] = rem[lane];
+  bool surv = false;
+  if (lane < kx - knew) {
+    surv = true;
+    for (int a = 0; a < mr; ++a) surv &= rem[a] != knew + lane;
+  }
+  const unsigned long long smask = __ballot(surv);
+  if (surv) src_s[__popcll(smask & below)] = knew + lane;
   if (lane == 0) {
-    int mi = 0, mr = 0;
-    for (int s = 0; s < m; ++s) {
-      const int e = S_s[s];
-      w.S[s] = e;
-      if (cand_s[e] >= 0) {
-        ins_s[mi] = e;
-        w.ins_el[mi] = e;
-        el_row[e] = k0 + mi;
-        ++mi;
-      } else {
-        el_row[e] = slot_s[e];
-        rem[mr++] = slot_s[e];
-      }
-    }
-    for (int a = 1; a < mr; ++a)
-      for (int b = a; b > 0 && rem[b - 1] > rem[b]; --b) {
-        const int x = rem[b];
-        rem[b] = rem[b - 1];
-        rem[b - 1] = x;
-      }
-    const int kx = k0 + mi;
-    int nh = 0, ns = 0, r = 0;
-    for (int a = 0; a < mr; ++a)
-      if (rem[a] < knew) hole_s[nh++] = rem[a];
-    for (int i = knew; i < kx; ++i) {
-      while (r < mr && rem[r] < i) ++r;
-      if (r < mr && rem[r] == i) continue;
-      src_s[ns++] = i;
-    }
-    for (int h = 0; h < nh; ++h) {
-      moves[2 * h] = hole_s[h];
-      moves[2 * h + 1] = src_s[h];
-    }
     moves[2 * KS_MAX] = nh;
-    mi_s = mi;
-    nh_s = nh;
     if (bad) latch(c, ST_NUMERIC);
     c->m = m;
     c->mi = mi;
@@ -698,24 +780,58 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     }
   }
   __syncthreads();
-  const int mi = mi_s, nh = nh_s;
   if (m == 0) return;
+  if (lane < m) {
+    const int e = S_s[lane];
+    gp(w.S)[lane] = e;
+    el_row[e] = row_s[lane];
+  }
+  if (lane < mi) gp(w.ins_el)[lane] = ins_s[lane];
+  if (lane < nh) {
+    moves[2 * lane] = hole_s[lane];
+    moves[2 * lane + 1] = src_s[lane];
+  }
   for (int i = lane; i < knew; i += AW) remap[i] = i;
+  const auto v_site = gp(w.v_site), v_s = gp(w.v_s);
+  const auto v_tau = gp(w.v_tau);
+  const auto v_id = gp(w.v_id);
+  // window-start vertices that fill holes keep their values: read them
+  // before the inserted spins land on slots >= k0
+  int h_site = 0, h_s = 0;
+  double h_tau = 0.0;
+  long long h_id = 0;
+  const bool hole = lane < nh && src_s[lane] < k0;
+  if (hole) {
+    const int sidx = src_s[lane];
+    h_site = v_site[sidx];
+    h_tau = v_tau[sidx];
+    h_s = v_s[sidx];
+    h_id = v_id[sidx];
+  }
+  __syncthreads();
   if (lane < mi) {
     const int e = ins_s[lane];
-    w.v_site[k0 + lane] = w.el_site[e];
-    w.v_tau[k0 + lane] = w.el_tau[e];
-    w.v_s[k0 + lane] = spin_s[e];
-    w.v_id[k0 + lane] = w.cand_id[cand_s[e]];
+    v_site[k0 + lane] = gp(w.el_site)[e];
+    v_tau[k0 + lane] = gp(w.el_tau)[e];
+    v_s[k0 + lane] = spin_s[e];
+    v_id[k0 + lane] = cid_s[cand_s[e]];
   }
   __syncthreads();
   if (lane < nh) {
     const int d = hole_s[lane], sidx = src_s[lane];
     remap[d] = sidx;
-    w.v_site[d] = w.v_site[sidx];
-    w.v_tau[d] = w.v_tau[sidx];
-    w.v_s[d] = w.v_s[sidx];
-    w.v_id[d] = w.v_id[sidx];
+    if (sidx >= k0) {
+      // an inserted spin moves into the hole: its values are in LDS
+      const int e = ins_s[sidx - k0];
+      h_site = gp(w.el_site)[e];
+      h_tau = gp(w.el_tau)[e];
+      h_s = spin_s[e];
+      h_id = cid_s[cand_s[e]];
+    }
+    v_site[d] = h_site;
+    v_tau[d] = h_tau;
+    v_s[d] = h_s;
+    v_id[d] = h_id;
   }
 }
 
@@ -733,15 +849,18 @@ __global__ void __launch_bounds__(WG) k_ygemm(const View<T>* __restrict__ vs) {
   const int r0 = blockIdx.x * 16;
   if (mi == 0 || r0 >= k0) return;
   const int sp = blockIdx.y;
-  const T* N = w.N[sp];
+  const auto N = gp(w.N[sp]);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int ncb = (mi + 15) >> 4;
-  const T* gp[4];
+  // the inserted spins' columns g_{I,c}; absent columns read a zero column
+  // offset of -1 (never dereferenced)
+  const auto gcol = gp(w.gcol);
+  long long goff[4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
     const int jj = cb * 16 + li;
-    gp[cb] = (jj < mi) ? w.gcol + (size_t)w.el_cand[w.ins_el[jj]] * w.cap : nullptr;
+    goff[cb] = (jj < mi) ? (long long)w.el_cand[w.ins_el[jj]] * w.cap : -1;
   }
   const int ir = r0 + li;
   acc_t acc[4];
@@ -755,7 +874,7 @@ __global__ void __launch_bounds__(WG) k_ygemm(const View<T>* __restrict__ vs) {
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
       if (cb < ncb) {
-        const T b = (kin && gp[cb] != nullptr) ? gp[cb][jk] : (T)0;
+        const T b = (kin && goff[cb] >= 0) ? gcol[goff[cb] + jk] : (T)0;
         acc[cb] = Mfma<T>::run(a, b, acc[cb]);
       }
   }
@@ -770,7 +889,7 @@ __global__ void __launch_bounds__(WG) k_ygemm(const View<T>* __restrict__ vs) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = r0 + Mfma<T>::row(lane, r);
-    if (i < k0 && jj < mi) w.Y[sp][(size_t)jj * w.cap + i] = sum[r];
+    if (i < k0 && jj < mi) gp(w.Y[sp])[(size_t)jj * w.cap + i] = sum[r];
   }
 }
 
@@ -864,6 +983,9 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
 template <typename T>
 __device__ inline void fold_tile(T* C, int ldc, const T* A, int lda, const T* B, int ldb, int M, int Nn, int K,
                                  int i0, int j0) {
+  const auto Cg = gp(C);
+  const auto Ag = gp(A);
+  const auto Bg = gp(B);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int jb = j0 + wv * 16;
   const int li = lane & 15, lk = lane >> 4;
@@ -874,16 +996,16 @@ __device__ inline void fold_tile(T* C, int ldc, const T* A, int lda, const T* B,
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int jj = jb + Mfma<T>::row(lane, r);
-      acc[rb][r] = (ii < M && jj < Nn) ? C[ii + (size_t)jj * ldc] : (T)0;
+      acc[rb][r] = (ii < M && jj < Nn) ? Cg[ii + (size_t)jj * ldc] : (T)0;
     }
   }
   for (int s = 0; s < K; s += 4) {
     const int sk = s + lk;
-    const T a = (sk < K && jb + li < Nn) ? B[(size_t)sk * ldb + jb + li] : (T)0;
+    const T a = (sk < K && jb + li < Nn) ? Bg[(size_t)sk * ldb + jb + li] : (T)0;
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       const int ii = i0 + rb * 16 + li;
-      const T b = (sk < K && ii < M) ? A[(size_t)sk * lda + ii] : (T)0;
+      const T b = (sk < K && ii < M) ? Ag[(size_t)sk * lda + ii] : (T)0;
       acc[rb] = Mfma<T>::run(a, b, acc[rb]);
     }
   }
@@ -893,7 +1015,7 @@ __device__ inline void fold_tile(T* C, int ldc, const T* A, int lda, const T* B,
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int jj = jb + Mfma<T>::row(lane, r);
-      if (ii < M && jj < Nn) C[ii + (size_t)jj * ldc] = acc[rb][r];
+      if (ii < M && jj < Nn) Cg[ii + (size_t)jj * ldc] = acc[rb][r];
     }
   }
 }
@@ -930,7 +1052,7 @@ __global__ void __launch_bounds__(WG) k_compact_move(const View<T>* __restrict__
   const int i = blockIdx.x * WG + threadIdx.x;
   if (h < nh && i < knew) {
     const int d = moves[2 * h], s = moves[2 * h + 1];
-    T* N = w.N[sp];
+    const auto N = gp(w.N[sp]);
     const size_t ld = w.ld;
     const int si = remap[i];
     N[i + (size_t)d * ld] = N[si + (size_t)s * ld];

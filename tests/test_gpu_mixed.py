@@ -5,7 +5,7 @@ FP32 on the matrix cores with FP32 accumulation; Gamma^{-1}, the ratios and
 the refresh stay FP64.  Both walkers replay the same oracle trace with
 forced decisions, so they hold identical configurations and the differences
 below are the precision effect alone.  Reported per result (printed and
-written to gpurun_out/mixed_precision.json when that folder exists):
+written to $DCAX_RESULTS_DIR/mixed_precision.json when that variable is set):
 ratio error vs the oracle (scaled by max(|R|, 1)), N error vs the oracle
 (normwise), and G(K, i w_n) error of the mixed path vs the FP64 path.
 
@@ -74,8 +74,8 @@ def test_mixed_precision_errors(name, k_s, k_init, warm, n_rec):
     out["mixed"]["G_Kw_err_vs_fp64_rel_max"] = float(np.max(np.abs(G32 - G64)) / np.max(np.abs(G64)))
     print(json.dumps({name: out}), flush=True)
     RESULTS[name] = out
-    if os.path.isdir("gpurun_out"):
-        with open("gpurun_out/mixed_precision.json", "w") as f:
+    if os.environ.get("DCAX_RESULTS_DIR"):
+        with open(os.path.join(os.environ["DCAX_RESULTS_DIR"], "mixed_precision.json"), "w") as f:
             json.dump(RESULTS, f, indent=1)
     assert out["fp64"]["ratio_err_scaled_max"] < 1e-10 and out["fp64"]["N_err_normwise"] < 1e-10
     e32, e64 = float(np.finfo(np.float32).eps), float(np.finfo(np.float64).eps)
