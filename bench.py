@@ -59,19 +59,21 @@ def roofline(stats0, stats1, precision):
     return out
 
 
-def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False):
+def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None, walkers=1):
     import numpy as np
     import torch
     from paper_1901_01047_amd import dcax
     from paper_1901_01047_amd.workloads import CONFIGS, params_kwargs
-    cfg = CONFIGS[WORKLOAD]
+    workload = workload or WORKLOAD
+    cfg = CONFIGS[workload]
     prec = dcax.DCAX_FP64 if precision == "fp64" else dcax.DCAX_FP32_MIXED
-    p = dcax.make_params(**params_kwargs(WORKLOAD, seed=cfg["seed"] + seed_offset, warmup_sweeps=warmup),
-                         precision=prec, refresh_every=32)
-    w = dcax.Walker(p)
+    plist = [dcax.make_params(**params_kwargs(workload, seed=cfg["seed"] + seed_offset + i, warmup_sweeps=warmup),
+                              precision=prec, refresh_every=32) for i in range(walkers)]
+    w = dcax.Walker(plist if walkers > 1 else plist[0])
     w.set_graphs(graphs)
-    rng = np.random.default_rng(cfg["seed"] + 100 + seed_offset)
-    w.set_config(*initial_config(rng, w.Nc, cfg["beta"], 280))
+    for i in range(walkers):
+        rng = np.random.default_rng(cfg["seed"] + 100 + seed_offset + i)
+        w.set_config(*initial_config(rng, w.Ncs[i], cfg["beta"], cfg["k_init"]), walker=i)
     acc, aux = w.new_accumulator()
     for _ in range(warmup):
         w.sweep(1)
@@ -94,7 +96,7 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False):
     res = {
         "value": acc_upd / dt, "seconds": dt, "ms_per_step": dt / steps * 1e3,
         "proposals_per_s": props / dt, "acceptance": acc_upd / max(props, 1),
-        "mean_order": w.order, "windows": windows,
+        "mean_order": sum(w.orders()) / walkers, "windows": windows, "walkers": walkers,
         "mean_fold_rank": (s1["flips_folded"] - s0["flips_folded"]) / max(windows, 1),
         "roofline": roofline(s0, s1, precision),
         "kernel_seconds": {"fold": s1["fold_seconds"] - s0["fold_seconds"],
@@ -156,17 +158,20 @@ def run_batch(precision, steps, warmup, n_walkers=512):
     return res
 
 
-def cpu_baseline(cfg_vertices, seconds=15.0):
-    """The oracle, as it stands, timed on the host from the GPU's configuration."""
+def cpu_baseline(seconds=15.0, workload=None):
+    """The oracle, as it stands, timed on the host: the same workload from a
+    seeded random configuration of the workload's typical order."""
     import numpy as np
     from oracle import ctaux
     from paper_1901_01047_amd.workloads import CONFIGS
-    c = CONFIGS[WORKLOAD]
+    workload = workload or WORKLOAD
+    c = CONFIGS[workload]
     cl = c["cluster"]
     m = ctaux.Model(a1=(cl[0], cl[1]), a2=(cl[2], cl[3]), t=c["t"], tp=c["tp"], U=c["U"], beta=c["beta"],
                     mu=c["mu"], K_exp=c["K_exp"], n_tau=c["n_tau"])
     w = ctaux.Walker(m, seed=c["seed"] + 7, k_s=c["submatrix_k"])
-    w.set_config(cfg_vertices["site"], cfg_vertices["tau"], cfg_vertices["aux_spin"])
+    rng = np.random.default_rng(c["seed"] + 200)
+    w.set_config(*initial_config(rng, m.Nc, c["beta"], c["k_init"]))
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
@@ -182,8 +187,8 @@ def cpu_baseline(cfg_vertices, seconds=15.0):
     dt = time.perf_counter() - t0
     acc = w.n_acc_ins + w.n_acc_rem - a0
     return {"value": acc / dt, "unit": "updates/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{n} single-vertex proposals ({w.n_prop - p0}) of the {WORKLOAD} chain from the GPU "
-                      f"walker's equilibrated configuration (order {len(cfg_vertices)}), {dt:.1f} s wall"}
+            "sample": f"{n} single-vertex proposals ({w.n_prop - p0}) of the {workload} chain from a seeded "
+                      f"random configuration of order {c['k_init']}, {dt:.1f} s wall"}
 
 
 def main():
@@ -196,6 +201,9 @@ def main():
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--graphs", choices=("on", "off"), default="off",
                     help="replay each sweep as a captured hipGraph")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="single-walker (or --walkers) workload from paper_1901_01047_amd.workloads.CONFIGS")
+    ap.add_argument("--walkers", type=int, default=1)
     ap.add_argument("--batch", type=int, default=0,
                     help="also run the batched workload with this many walkers (FP64 and FP32-mixed)")
     args = ap.parse_args()
@@ -211,16 +219,18 @@ def main():
     from paper_1901_01047_amd import dcax
     dcax.load()
     from paper_1901_01047_amd.workloads import CONFIGS
-    c = CONFIGS[WORKLOAD]
+    wl = args.workload
+    c = CONFIGS[wl]
     graphs = args.graphs == "on"
-    r64, cfg_v = run_gpu("fp64", args.steps, args.warmup, graphs=graphs)
+    r64, cfg_v = run_gpu("fp64", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers)
     out = {
         "metric": "accepted vertex updates/s (CT-AUX walker, FP64) + N-update fold TFLOP/s (% roofline)",
         "value": r64["value"], "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": r64["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{WORKLOAD}: 4x4 periodic Hubbard cluster, t=1, U=4, beta=10, "
-                               f"mu={c['mu']} (n~0.95), K=1, 1 walker, k_s={c['submatrix_k']}, "
+        "config": {"workload": f"{wl}: {c['cluster'][0]}x{c['cluster'][3]} periodic Hubbard cluster, t=1, "
+                               f"t'={c['tp']}, U={c['U']}, beta={c['beta']}, mu={c['mu']} (n~{c['n_target']}), "
+                               f"K=1, {args.walkers} walker(s), k_s={c['submatrix_k']}, "
                                f"{c['n_freq']} Matsubara freqs, refresh every 32 sweeps",
                    "step": "1 sweep + 1 measurement of M(K,iw_n)",
                    "launch": "hipGraph per sweep" if graphs else "eager launches"},
@@ -228,13 +238,13 @@ def main():
         "fp64": {k: v for k, v in r64.items() if k != "roofline"},
     }
     if not args.fp64_only:
-        r32, _ = run_gpu("mixed", args.steps, args.warmup, graphs=graphs)
+        r32, _ = run_gpu("mixed", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers)
         out["fp32_mixed"] = r32
     if args.batch:
         out["batch"] = {"fp64": run_batch("fp64", args.steps, args.warmup, args.batch),
                         "fp32_mixed": run_batch("mixed", args.steps, args.warmup, args.batch)}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg_v, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, wl)
     print(json.dumps(out), flush=True)
 
 

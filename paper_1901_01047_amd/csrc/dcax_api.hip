@@ -379,9 +379,10 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   hipEvent_t e_w0 = w->rec();
   if (replay) hipLaunchKernelGGL(k_prep_replay<T>, dim3(1, 1, W), dim3(WG), 0, s, vs);
   else hipLaunchKernelGGL(k_prep_rng<T>, dim3(1, 1, W), dim3(PW), 0, s, vs);
-  hipLaunchKernelGGL(k_gather<T>, dim3(cdiv(kb1, WG), ks, W), dim3(WG), 0, s, vs);
+  const int ne = std::min(2 * ks, KS_MAX);   // elements: candidates, targets, second attempts
+  hipLaunchKernelGGL(k_gather<T>, dim3(cdiv(kb1, WG), ne, W), dim3(WG), 0, s, vs);
   hipLaunchKernelGGL(k_cand_x<T>, dim3(cdiv(kb1, 16), 2, W), dim3(WG), 0, s, vs);
-  hipLaunchKernelGGL(k_gram<T>, dim3(ks, 2, W), dim3(WG), 0, s, vs);
+  hipLaunchKernelGGL(k_gram<T>, dim3(ne, 2, W), dim3(WG), 0, s, vs);
   hipEvent_t e_a0 = w->rec();
   hipLaunchKernelGGL(k_accept<T>, dim3(1, 1, W), dim3(AW), 0, s, vs);
   hipEvent_t e_a1 = w->rec();
@@ -392,7 +393,7 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   hipLaunchKernelGGL(k_fold<T>, dim3(cdiv(kx, 64), cdiv(kx, 64), 2 * W), dim3(WG), 0, s, vs);
   hipEvent_t e_f1 = w->rec();
   w->mark(w->pend_fold, e_f0, e_f1);
-  hipLaunchKernelGGL(k_compact_move<T>, dim3(cdiv(kx, WG), KS_MAX, 2 * W), dim3(WG), 0, s, vs);
+  hipLaunchKernelGGL(k_compact_move<T>, dim3(cdiv(kx, WG), 1, 2 * W), dim3(WG), 0, s, vs);
   hipEvent_t e_w1 = w->rec();
   w->mark(w->pend_window, e_w0, e_w1);
 }
@@ -442,9 +443,10 @@ void enqueue_measure(dcax_walker w, double* acc, double* aux) {
   const int kb = std::min(w->kpad_max, w->kmax_host() + 16 * ncm);
   const int kb1 = std::max(kb, 1);
   hipLaunchKernelGGL(k_meas_sort<T>, dim3(1, 1, W), dim3(WG), 0, s, vs);
-  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cdiv(kb1, WG), kb1, W), dim3(WG), 0, s, vs);
-  hipLaunchKernelGGL(k_meas_phase<T>, dim3(cdiv(nf, WG), kb1, W), dim3(WG), 0, s, vs);
-  hipLaunchKernelGGL(k_meas_block<T>, dim3(2 * ncm * ncm, cdiv(nf, 16), W), dim3(64), 0, s, vs, ncm);
+  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cdiv(kb1, WG), cdiv(kb1, MCOLS), W), dim3(WG), 0, s, vs);
+  hipLaunchKernelGGL(k_meas_phase<T>, dim3(cdiv(nf, WG), cdiv(kb1, MCOLS), W), dim3(WG), 0, s, vs);
+  const int groups = cdiv(ncm * ncm, (WG / 64) * MPAIRS);
+  hipLaunchKernelGGL(k_meas_block<T>, dim3(2 * groups, cdiv(nf, 16), W), dim3(WG), 0, s, vs, ncm);
   hipLaunchKernelGGL(k_meas_K<T>, dim3(cdiv(nf, WG), ncm, 2 * W), dim3(WG), 0, s, vs, acc);
 }
 

@@ -54,6 +54,7 @@ struct WinProp {      // one proposal of the current window
   int forced;         // replay decision (-1: decide from u)
   int carried;        // removal whose target was fixed before this window
   double u;           // acceptance uniform
+  double ub0, ui0;    // a removal's first target attempt (generator mode)
   long long ridx;     // replay index (ratio output), -1 if none
   long long gidx;     // global proposal index (generator counter)
 };
@@ -247,11 +248,21 @@ __device__ inline double lane_value(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-// Sum of v over lanes 0 .. n-1, in lane order, identical in every lane.
+// Sum of v over lanes 0 .. n-1 (four interleaved partial sums, combined in
+// a fixed order), identical in every lane.
 __device__ inline double lanes_sum(double v, int n) {
-  double s = 0.0;
-  for (int a = 0; a < n; ++a) s += lane_value(v, a);
-  return s;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int a = 0;
+  for (; a + 4 <= n; a += 4) {
+    s0 += lane_value(v, a);
+    s1 += lane_value(v, a + 1);
+    s2 += lane_value(v, a + 2);
+    s3 += lane_value(v, a + 3);
+  }
+  if (a < n) s0 += lane_value(v, a);
+  if (a + 1 < n) s1 += lane_value(v, a + 1);
+  if (a + 2 < n) s2 += lane_value(v, a + 2);
+  return (s0 + s1) + (s2 + s3);
 }
 
 __device__ inline double wave_sum(double v) {

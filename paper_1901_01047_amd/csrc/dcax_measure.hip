@@ -58,59 +58,73 @@ __global__ void __launch_bounds__(WG) k_meas_sort(const View<T>* __restrict__ vs
   }
 }
 
-// Ms[i'][j'] = (e^{V_i} - 1) N[i][j] in sorted order (zero on padding), and
-// the phase table E[j'][n] = e^{-i w_n tau_j}.
+// Ms[i'][j'] = (e^{V_i} - 1) N[i][j] in sorted order (zero on padding), 16
+// sorted columns per workgroup.
+constexpr int MCOLS = 16;
 template <typename T>
 __global__ void __launch_bounds__(WG) k_meas_copy(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
-  const int* order = w.m_order;
-  const int* off = w.m_off;
-  T* Ms0 = w.m_Ms[0];
-  T* Ms1 = w.m_Ms[1];
+  const auto order = gp(w.m_order);
+  const auto off = gp(w.m_off);
+  const auto Ms0 = gp(w.m_Ms[0]);
+  const auto Ms1 = gp(w.m_Ms[1]);
+  const auto N0 = gp(w.N[0]);
+  const auto N1 = gp(w.N[1]);
   const int ldm = w.kpad_cap;
   const int kpad = off[w.Nc];
-  const int jp = blockIdx.y;
   const int ip = blockIdx.x * WG + threadIdx.x;
-  if (jp >= kpad || ip >= kpad) return;
-  const int i = order[ip], j = order[jp];
-  T v0 = 0, v1 = 0;
-  if (i >= 0 && j >= 0) {
+  if (ip >= kpad || (int)blockIdx.y * MCOLS >= kpad) return;
+  const int i = order[ip];
+  double f0 = 0.0, f1 = 0.0;
+  if (i >= 0) {
     const int si = s01(w.v_s[i]);
-    const size_t o = i + (size_t)j * w.ld;
-    v0 = (T)((w.ev[0][si] - 1.0) * (double)w.N[0][o]);
-    v1 = (T)((w.ev[1][si] - 1.0) * (double)w.N[1][o]);
+    f0 = w.ev[0][si] - 1.0;
+    f1 = w.ev[1][si] - 1.0;
   }
-  Ms0[ip + (size_t)jp * ldm] = v0;
-  Ms1[ip + (size_t)jp * ldm] = v1;
+  for (int jp = blockIdx.y * MCOLS; jp < (int)(blockIdx.y + 1) * MCOLS && jp < kpad; ++jp) {
+    const int j = order[jp];
+    T v0 = 0, v1 = 0;
+    if (i >= 0 && j >= 0) {
+      const size_t o = i + (size_t)j * w.ld;
+      v0 = (T)(f0 * (double)N0[o]);
+      v1 = (T)(f1 * (double)N1[o]);
+    }
+    Ms0[ip + (size_t)jp * ldm] = v0;
+    Ms1[ip + (size_t)jp * ldm] = v1;
+  }
 }
 
+// Phase table E[j'][n] = e^{-i w_n tau_j} in sorted order, 16 rows per
+// workgroup.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_meas_phase(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
-  const int* order = w.m_order;
-  const int* off = w.m_off;
-  T* E = w.m_E;
+  const auto order = gp(w.m_order);
+  const auto off = gp(w.m_off);
+  const auto E = gp(w.m_E);
   const int n_freq = w.n_freq;
   const int kpad = off[w.Nc];
-  const int jp = blockIdx.y;
   const int n = blockIdx.x * WG + threadIdx.x;
-  if (jp >= kpad || n >= n_freq) return;
-  const int j = order[jp];
-  double c = 0.0, s = 0.0;
-  if (j >= 0) {
-    const double wn = (2.0 * n + 1.0) * M_PI / w.beta;
-    sincos(wn * w.v_tau[j], &s, &c);
+  if (n >= n_freq) return;
+  const double wn = (2.0 * n + 1.0) * M_PI / w.beta;
+  for (int jp = blockIdx.y * MCOLS; jp < (int)(blockIdx.y + 1) * MCOLS && jp < kpad; ++jp) {
+    const int j = order[jp];
+    double c = 0.0, s = 0.0;
+    if (j >= 0) sincos(wn * w.v_tau[j], &s, &c);
+    E[2 * ((size_t)jp * n_freq + n)] = (T)c;
+    E[2 * ((size_t)jp * n_freq + n) + 1] = (T)(-s);
   }
-  E[2 * ((size_t)jp * n_freq + n)] = (T)c;
-  E[2 * ((size_t)jp * n_freq + n) + 1] = (T)(-s);
 }
 
-// One wavefront per (a, b, 16-frequency tile, spin).  D^T[n][i'] =
-// sum_{j' in b} E[j'][n] Ms[i'][j'] on the matrix cores (real and imaginary
-// parts of E separately), then the row phases e^{i w_n tau_i} and the sum
-// over i' in a.
+// For each pair of sites (a, b), spin and tile of 16 frequencies:
+// D^T[n][i'] = sum_{j' in b} E[j'][n] Ms[i'][j'] on the matrix cores (real
+// and imaginary parts of E separately), then the row phases e^{i w_n tau_i}
+// and the sum over i' in a.  A wavefront takes MPAIRS consecutive pairs; a
+// workgroup four wavefronts (blockIdx.x = 2 group + spin).
+constexpr int MPAIRS = 1;
 template <typename T>
-__global__ void __launch_bounds__(64) k_meas_block(const View<T>* __restrict__ vs, int nc_max) {
+__global__ void __launch_bounds__(WG) k_meas_block(const View<T>* __restrict__ vs, int nc_max) {
+  (void)nc_max;
   const View<T>& w = vs[blockIdx.z];
   const auto order = gp(w.m_order);
   const auto off = gp(w.m_off);
@@ -119,64 +133,66 @@ __global__ void __launch_bounds__(64) k_meas_block(const View<T>* __restrict__ v
   const auto v_tau = gp(w.v_tau);
   const int n_freq = w.n_freq;
   const int Nc = w.Nc;
-  const int sp = blockIdx.x / (nc_max * nc_max);
-  const int ab = blockIdx.x % (nc_max * nc_max);
-  const int a = ab / nc_max, b = ab % nc_max;
+  const int sp = blockIdx.x & 1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int pair0 = ((blockIdx.x >> 1) * (WG / 64) + wv) * MPAIRS;
   const int n0 = blockIdx.y * 16;
-  if (a >= Nc || b >= Nc || n0 >= n_freq) return;
+  if (pair0 >= Nc * Nc || n0 >= n_freq) return;
   const auto Ms = gp(w.m_Ms[sp]);
   const auto Mab = gp(w.m_Mab[sp]);
-  const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
-  const int ia0 = off[a], ia1 = off[a + 1], jb0 = off[b], jb1 = off[b + 1];
-  double sre[4] = {0, 0, 0, 0}, sim[4] = {0, 0, 0, 0};
   const int na = n0 + li;   // frequency of this lane's A' operand row
-  for (int ib = ia0; ib < ia1; ib += 16) {
-    typename Mfma<T>::acc_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
-    const int ip = ib + li;
-    for (int jp = jb0; jp < jb1; jp += 4) {
-      const int jk = jp + lk;
-      const T m = Ms[ip + (size_t)jk * ldm];
-      T er = 0, ei = 0;
-      if (na < n_freq) {
-        er = E[2 * ((size_t)jk * n_freq + na)];
-        ei = E[2 * ((size_t)jk * n_freq + na) + 1];
+  for (int ab = pair0; ab < pair0 + MPAIRS && ab < Nc * Nc; ++ab) {
+    const int a = ab / Nc, b = ab % Nc;
+    const int ia0 = off[a], ia1 = off[a + 1], jb0 = off[b], jb1 = off[b + 1];
+    double sre[4] = {0, 0, 0, 0}, sim[4] = {0, 0, 0, 0};
+    for (int ib = ia0; ib < ia1; ib += 16) {
+      typename Mfma<T>::acc_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+      const int ip = ib + li;
+      for (int jp = jb0; jp < jb1; jp += 4) {
+        const int jk = jp + lk;
+        const T m = Ms[ip + (size_t)jk * ldm];
+        T er = 0, ei = 0;
+        if (na < n_freq) {
+          er = E[2 * ((size_t)jk * n_freq + na)];
+          ei = E[2 * ((size_t)jk * n_freq + na) + 1];
+        }
+        dr = Mfma<T>::run(er, m, dr);
+        di = Mfma<T>::run(ei, m, di);
       }
-      dr = Mfma<T>::run(er, m, dr);
-      di = Mfma<T>::run(ei, m, di);
+      // lane holds D[n = n0 + row(lane, r)][i' = ib + li]
+      const int i = order[ip];
+      if (i >= 0) {
+        const double ti = v_tau[i];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int n = n0 + Mfma<T>::row(lane, r);
+          const double wn = (2.0 * n + 1.0) * M_PI / w.beta;
+          double s, c;
+          sincos(wn * ti, &s, &c);
+          const double xr = (double)dr[r], xi = (double)di[r];
+          sre[r] += c * xr - s * xi;
+          sim[r] += c * xi + s * xr;
+        }
+      }
     }
-    // lane holds D[n = n0 + row(lane, r)][i' = ib + li]
-    const int i = order[ip];
-    if (i >= 0) {
-      const double ti = v_tau[i];
+    // sum over the 16 lanes that share a frequency set (li varies)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      for (int o = 1; o < 16; o <<= 1) {
+        sre[r] += __shfl_xor(sre[r], o, 64);
+        sim[r] += __shfl_xor(sim[r], o, 64);
+      }
+    }
+    if (li == 0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int n = n0 + Mfma<T>::row(lane, r);
-        const double wn = (2.0 * n + 1.0) * M_PI / w.beta;
-        double s, c;
-        sincos(wn * ti, &s, &c);
-        const double xr = (double)dr[r], xi = (double)di[r];
-        sre[r] += c * xr - s * xi;
-        sim[r] += c * xi + s * xr;
-      }
-    }
-  }
-  // sum over the 16 lanes that share a frequency set (li varies)
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    for (int o = 1; o < 16; o <<= 1) {
-      sre[r] += __shfl_xor(sre[r], o, 64);
-      sim[r] += __shfl_xor(sim[r], o, 64);
-    }
-  }
-  if (li == 0) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int n = n0 + Mfma<T>::row(lane, r);
-      if (n < n_freq) {
-        const size_t o = 2 * (((size_t)a * Nc + b) * n_freq + n);
-        Mab[o] = sre[r];
-        Mab[o + 1] = sim[r];
+        if (n < n_freq) {
+          const size_t o = 2 * (((size_t)a * Nc + b) * n_freq + n);
+          Mab[o] = sre[r];
+          Mab[o + 1] = sim[r];
+        }
       }
     }
   }

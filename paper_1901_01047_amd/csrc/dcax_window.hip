@@ -10,7 +10,9 @@
 //   N' = N + (E_S - G_{.S}) Gamma_S^{-1} N_{S.},
 // followed by removal of the deleted rows and columns.  With G = N g and
 // Delta_p = e^{V'_p - V_p} - 1: Gamma_S = G_SS - diag((1 + Delta)/Delta) and
-// det N'^{-1} / det N^{-1} = prod_S (-Delta_p) det Gamma_S.
+// det N'^{-1} / det N^{-1} = prod_S (-Delta_p) det Gamma_S.  The kernels carry
+// the column-scaled Gt = Gamma diag(-Delta), finite also where Delta = 0:
+// det Gt is the ratio and N' = N + (E_S - G_{.S}) diag(-Delta) Gt^{-1} N_{S.}.
 //
 // Kernels, in launch order: k_prep_replay | k_prep_rng, k_gather, k_cand_x,
 // k_gram, k_accept (which also plans the compaction and closes the window's
@@ -67,6 +69,8 @@ __global__ void __launch_bounds__(WG) k_prep_replay(const View<T>* __restrict__ 
     p.forced = r.accepted ? 1 : 0;
     p.carried = 0;
     p.u = r.u_accept;
+    p.ub0 = 0.0;
+    p.ui0 = 0.0;
     p.ridx = pos + j;
     p.gidx = pos + j;
     p.el = -1;
@@ -135,14 +139,14 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
   Ctl* c = w.ctl;
   const int lane = threadIdx.x;
   const long long left = c->end - c->pos;
-  const int nP = (c->status == 0 && left > 0) ? (int)(left < w.ks ? left : w.ks) : 0;
+  const int nP = uni((c->status == 0 && left > 0) ? (int)(left < w.ks ? left : w.ks) : 0);
   if (nP == 0) {
     if (lane == 0) c->active = 0;
     return;
   }
-  const int k0 = c->k;
-  const long long pos = c->pos;
-  const long long carry = c->carry_id;
+  const int k0 = uni(c->k);
+  const long long pos = uni(c->pos);
+  const long long carry = uni(c->carry_id);
   int carry_slot = -1;
   if (carry >= 0) {
     int found = -1;
@@ -160,6 +164,7 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
   }
   const bool act = lane < nP;
   double u_kind = 1.0, u_site = 0.0, u_tau = 0.0, u_spin = 0.0, u_acc = 0.0, u_dummy;
+  double ub0 = 0.0, ui0 = 0.0;
   int kind = -1, slot = -1;
   if (act) {
     const long long g = pos + lane;
@@ -173,10 +178,9 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
       kind = 0;
     } else {
       kind = 1;
+      uniforms2(seed, g, 3u, ub0, ui0);
       if (k0 > 0) {     // the first attempt's window-start vertex
-        double ub, ui;
-        uniforms2(seed, g, 3u, ub, ui);
-        slot = (int)(ui * (double)k0);
+        slot = (int)(ui0 * (double)k0);
         if (slot >= k0) slot = k0 - 1;
       }
     }
@@ -204,6 +208,29 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
   el_s[lane] = e_own;
   __syncthreads();
   const int e = (kind == 1 && slot >= 0 && !fresh) ? el_s[first] : e_own;
+  // A removal's second target attempt is prepared too (as long as elements
+  // remain), so that a redraw after hitting an already removed vertex rarely
+  // has to close the window.  Its slot does not depend on the state; whether
+  // the attempt happens does, and an unused element costs nothing.
+  const int nE0 = __popcll(fresh_m);
+  int slot1 = -1;
+  if (kind == 1 && !(lane == 0 && carry >= 0) && k0 > 0) {
+    double ub1, ui1;
+    uniforms2(seed, pos + lane, 4u, ub1, ui1);
+    slot1 = (int)(ui1 * (double)k0);
+    if (slot1 >= k0) slot1 = k0 - 1;
+  }
+  // duplicates: a slot already prepared by any first attempt, or by the
+  // second attempt of an earlier proposal (register broadcasts, no LDS)
+  bool fresh1 = slot1 >= 0;
+  const int slot_r = (kind == 1) ? slot : -1;
+  for (int x = 0; x < nP; ++x) {
+    fresh1 &= __builtin_amdgcn_readlane(slot_r, x) != slot1;
+    fresh1 &= !(x < lane && __builtin_amdgcn_readlane(slot1, x) == slot1);
+  }
+  const unsigned long long fresh1_m = __ballot(fresh1);
+  const int e1 = nE0 + __popcll(fresh1_m & below);
+  const int nE = min(nE0 + __popcll(fresh1_m), KS_MAX);
   if (kind == 0) {
     int site = (int)(u_site * (double)w.Nc);
     if (site >= w.Nc) site = w.Nc - 1;
@@ -221,6 +248,13 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
     w.el_slot[e] = slot;
     w.el_cand[e] = -1;
   }
+  if (fresh1 && e1 < KS_MAX) {
+    w.el_site[e1] = w.v_site[slot1];
+    w.el_tau[e1] = w.v_tau[slot1];
+    w.el_s[e1] = w.v_s[slot1];
+    w.el_slot[e1] = slot1;
+    w.el_cand[e1] = -1;
+  }
   if (act) {
     WinProp p;
     p.kind = kind;
@@ -228,6 +262,8 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
     p.forced = -1;
     p.carried = (lane == 0 && carry >= 0) ? 1 : 0;
     p.u = u_acc;
+    p.ub0 = ub0;
+    p.ui0 = ui0;
     p.ridx = -1;
     p.gidx = pos + lane;
     w.wp[lane] = p;
@@ -235,7 +271,7 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
   if (lane == 0) {
     c->carry_id = -1;
     c->nP = nP;
-    c->nE = __popcll(fresh_m);
+    c->nE = nE;
     c->nC = __popcll(ins_m);
     c->k0 = k0;
     c->active = 1;
@@ -475,14 +511,20 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     p.forced = uni(p.forced);
     p.carried = uni(p.carried);
     p.u = uni(p.u);
+    p.ub0 = uni(p.ub0);
+    p.ui0 = uni(p.ui0);
     p.gidx = uni(p.gidx);
     int q = p.el, ab = 0;
     if (p.forced < 0 && p.kind == 1 && !p.carried) {
       q = -1;
       if (kcur > 0) {
         for (int a = 0; a < MAX_ATTEMPTS; ++a) {
-          double ub, ui;
-          uniforms2(seed, p.gidx, 3u + (uint32_t)a, ub, ui);
+          double ub = p.ub0, ui = p.ui0;
+          if (a > 0) {
+            uniforms2(seed, p.gidx, 3u + (uint32_t)a, ub, ui);
+            ub = uni(ub);
+            ui = uni(ui);
+          }
           if (ub * (double)(k0 + nins) < (double)k0) {
             int slot = (int)(ui * (double)k0);
             if (slot >= k0) slot = k0 - 1;
@@ -538,12 +580,20 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
           g0[u] = ginv_s[0][lane * LS + b];
           g1[u] = ginv_s[1][lane * LS + b];
         }
+        double e0 = 0.0, e1 = 0.0, o0 = 0.0, o1 = 0.0;
 #pragma unroll
-        for (int u = 0; u < CH; ++u)
+        for (int u = 0; u < CH; u += 2) {
           if (b0 + u < m) {
-            L0 += g0[u] * lane_value(v0, b0 + u);
-            L1 += g1[u] * lane_value(v1, b0 + u);
+            e0 += g0[u] * lane_value(v0, b0 + u);
+            e1 += g1[u] * lane_value(v1, b0 + u);
           }
+          if (b0 + u + 1 < m) {
+            o0 += g0[u + 1] * lane_value(v0, b0 + u + 1);
+            o1 += g1[u + 1] * lane_value(v1, b0 + u + 1);
+          }
+        }
+        L0 += e0 + o0;
+        L1 += e1 + o1;
       }
       L0 = in ? L0 : 0.0;
       L1 = in ? L1 : 0.0;
@@ -601,12 +651,20 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
           g0[u] = ginv_s[0][a * LS + lane];
           g1[u] = ginv_s[1][a * LS + lane];
         }
+        double e0 = 0.0, e1 = 0.0, o0 = 0.0, o1 = 0.0;
 #pragma unroll
-        for (int u = 0; u < CH; ++u)
+        for (int u = 0; u < CH; u += 2) {
           if (a0 + u < m) {
-            R0 += lane_value(w0, a0 + u) * g0[u];
-            R1 += lane_value(w1, a0 + u) * g1[u];
+            e0 += lane_value(w0, a0 + u) * g0[u];
+            e1 += lane_value(w1, a0 + u) * g1[u];
           }
+          if (a0 + u + 1 < m) {
+            o0 += lane_value(w0, a0 + u + 1) * g0[u + 1];
+            o1 += lane_value(w1, a0 + u + 1) * g1[u + 1];
+          }
+        }
+        R0 += e0 + o0;
+        R1 += e1 + o1;
       }
       const double l0 = L0 * inv0, l1 = L1 * inv1;
       for (int b0 = 0; b0 < m; b0 += CH) {
@@ -1042,19 +1100,20 @@ __global__ void __launch_bounds__(WG) k_fold(const View<T>* __restrict__ vs) {
 template <typename T>
 __global__ void __launch_bounds__(WG) k_compact_move(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z >> 1];
-  const int* remap = w.remap;
-  const int* moves = w.moves;
+  const auto remap = gp(w.remap);
+  const auto moves = gp(w.moves);
   Ctl* c = w.ctl;
   if (!c->active) return;
-  const int h = blockIdx.y, sp = blockIdx.z & 1;
+  const int sp = blockIdx.z & 1;
   const int nh = moves[2 * KS_MAX];
   const int knew = c->knew;
   const int i = blockIdx.x * WG + threadIdx.x;
-  if (h < nh && i < knew) {
+  if (nh == 0 || i >= knew) return;
+  const auto N = gp(w.N[sp]);
+  const size_t ld = w.ld;
+  const int si = remap[i];
+  for (int h = 0; h < nh; ++h) {
     const int d = moves[2 * h], s = moves[2 * h + 1];
-    const auto N = gp(w.N[sp]);
-    const size_t ld = w.ld;
-    const int si = remap[i];
     N[i + (size_t)d * ld] = N[si + (size_t)s * ld];
     N[d + (size_t)i * ld] = N[s + (size_t)si * ld];
   }

@@ -15,19 +15,19 @@ CONFIGS = {
     # 2x2 periodic cluster at half filling; small enough for the oracle
     "2x2_U4_b5": dict(cluster=(2, 0, 0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0, K_exp=1.0,
                       n_tau=1000, submatrix_k=16, n_freq=1024, max_order=256, sweeps=10000,
-                      warmup_sweeps=100, seed=BASE_SEED, n_target=1.0),
+                      warmup_sweeps=100, seed=BASE_SEED, n_target=1.0, k_init=26),
     # 4x4 cluster, n ~ 0.95, expansion order ~ 300
     "4x4_U4_b10": dict(cluster=(4, 0, 0, 4), t=1.0, tp=0.0, U=4.0, beta=10.0, mu=-0.74, K_exp=1.0,
                        n_tau=2001, submatrix_k=32, n_freq=256, max_order=1024, sweeps=100000,
-                       warmup_sweeps=100, seed=BASE_SEED + 2, n_target=0.95),
+                       warmup_sweeps=100, seed=BASE_SEED + 2, n_target=0.95, k_init=240),
     # 6x6 cluster, t' = -0.15, n ~ 0.9, expansion order ~ 2000
     "6x6_U6_b20": dict(cluster=(6, 0, 0, 6), t=1.0, tp=-0.15, U=6.0, beta=20.0, mu=-0.8, K_exp=1.0,
                        n_tau=4001, submatrix_k=64, n_freq=256, max_order=4096, sweeps=1000,
-                       warmup_sweeps=100, seed=BASE_SEED + 3, n_target=0.90),
+                       warmup_sweeps=100, seed=BASE_SEED + 3, n_target=0.90, k_init=2000),
     # 8x8 cluster, n ~ 0.9, expansion order ~ 6000
     "8x8_U7_b30": dict(cluster=(8, 0, 0, 8), t=1.0, tp=0.0, U=7.0, beta=30.0, mu=-0.9, K_exp=1.0,
                        n_tau=6001, submatrix_k=64, n_freq=512, max_order=8192, sweeps=10,
-                       warmup_sweeps=10, seed=BASE_SEED + 5000, n_target=0.90),
+                       warmup_sweeps=10, seed=BASE_SEED + 5000, n_target=0.90, k_init=6000),
 }
 
 

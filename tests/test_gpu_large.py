@@ -1,0 +1,70 @@
+"""Parity at the full sizes of the large workloads (MI355X).
+
+The 6x6 (k ~ 2000) and 8x8 (k ~ 6000) clusters run with the submatrix size
+and precision the benchmark uses.  The oracle records a short trace (two
+windows) from a seeded random configuration of the workload's order; the
+library replays it with forced decisions, and every ratio of the trace and
+the final N are compared with the oracle.  Random configurations of these
+orders are far from equilibrium and badly conditioned: the same submatrix
+algebra evaluated in plain NumPy FP64 already lands 1e-8 (6x6) from the
+oracle's single-vertex chain.  So every ratio must be within
+max(1e-10 max(|R|, 1), 10 x that algebra's own error), and N normwise
+within max(1e-10, 10 x its error).  In the FP32-mixed mode the bounds scale
+the FP64 errors by eps32 / eps64 (within 10x).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1901_01047_amd import dcax  # noqa: E402
+from paper_1901_01047_amd.workloads import CONFIGS, params_kwargs  # noqa: E402
+from tests.ctaux_cases import model, oracle_trace  # noqa: E402
+from tests.test_gpu_parity import algebra_gauge, rel_norm  # noqa: E402
+
+LARGE = ["6x6_U6_b20", "8x8_U7_b30"]
+
+
+@pytest.mark.parametrize("name", LARGE)
+def test_large_replay_parity(name):
+    c = CONFIGS[name]
+    k_s = c["submatrix_k"]
+    print(f"[large replay] {name} k_init={c['k_init']} k_s={k_s}", flush=True)
+    m = model(name)
+    init, rec, ratios_o, ow = oracle_trace(m, seed=c["seed"] + 11, k_s=k_s, init_order=c["k_init"],
+                                           warm_sweeps=0, rec_proposals=2 * k_s)
+    print("  oracle trace recorded", flush=True)
+    noop = (rec["kind"] == 1) & (rec["id"] < 0)
+    good = ~noop
+    ro = ratios_o[good]
+    r_wm, (ids_wm, Nu_wm, Nd_wm) = algebra_gauge(m, init, rec, k_s)
+    err_wm = np.abs(r_wm - ro)
+    ids_o, Nu, Nd = ow.canonical()
+    e_wm = [rel_norm(Nu_wm, Nu), rel_norm(Nd_wm, Nd)]
+    results = {}
+    for prec, tag in ((dcax.DCAX_FP64, "fp64"), (dcax.DCAX_FP32_MIXED, "mixed")):
+        w = dcax.Walker(dcax.make_params(**params_kwargs(name), precision=prec))
+        w.set_config(*init)
+        ratios = w.replay(rec)
+        err = np.abs(ratios[good] - ro)
+        scaled = err / np.maximum(np.abs(ro), 1.0)
+        rel = err / np.abs(ro)
+        nerr = []
+        for sp in range(2):
+            ids, N = w.copy_N(sp)
+            assert np.array_equal(ids, ids_o)
+            nerr.append(rel_norm(N, (Nu, Nd)[sp]))
+        results[tag] = (scaled, rel, err, nerr, w.stats()["decision_mismatches"])
+        print(f"  {tag}: ratio scaled max {scaled.max():.2e}, rel median {np.median(rel):.2e} max {rel.max():.2e}; "
+              f"N normwise {max(nerr):.2e} (FP64 algebra {max(e_wm):.2e}); k = {len(ids_o)}", flush=True)
+        w.close()
+    scaled, rel, err, nerr, mis = results["fp64"]
+    assert mis == 0
+    assert np.all(err <= np.maximum(1e-10 * np.maximum(np.abs(ro), 1.0), 10 * err_wm))
+    for sp in range(2):
+        assert nerr[sp] < max(1e-10, 10 * e_wm[sp])
+    e32, e64 = float(np.finfo(np.float32).eps), float(np.finfo(np.float64).eps)
+    scaled32, _, _, nerr32, _ = results["mixed"]
+    assert scaled32.max() < 10 * max(scaled.max() * e32 / e64, e32)
+    assert max(nerr32) < 10 * max(max(nerr) * e32 / e64, e32)
