@@ -32,7 +32,30 @@ def initial_config(rng, Nc, beta, k):
     return site, tau, s
 
 
-def roofline(stats0, stats1, precision):
+def fold_traffic(workload, precision):
+    """HBM bytes per k_fold launch from the committed counter summary, while
+    the fold kernel's source is the one the counters were taken on."""
+    import hashlib
+    if workload != WORKLOAD or precision != "fp64":
+        return None
+    try:
+        src = open(os.path.join(ROOT, "paper_1901_01047_amd", "csrc", "dcax_window.hip")).read()
+        a = src.index("// ---------------------------------------------------------------- fold\n")
+        b = src.index("// ----------------------------------------------------------- compaction")
+        h = hashlib.sha256(src[a:b].encode()).hexdigest()
+        vals = {}
+        for line in open(os.path.join(ROOT, "profiles", "traffic_k_fold_4x4_U4_b10.md")):
+            if " = " in line and line.split(" = ")[0].strip() in ("traffic_bytes_per_launch", "fold_source_sha256"):
+                k, v = line.split(" = ", 1)
+                vals[k.strip()] = v.strip()
+        if vals.get("fold_source_sha256") != h:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def roofline(stats0, stats1, precision, traffic=None):
     flops = stats1["fold_flops"] - stats0["fold_flops"]
     nbytes = stats1["fold_bytes"] - stats0["fold_bytes"]
     secs = stats1["fold_seconds"] - stats0["fold_seconds"]
@@ -51,7 +74,7 @@ def roofline(stats0, stats1, precision):
         out = {"bound": "mfma", "achieved": achieved, "peak": peak_tf, "unit": "TFLOP/s",
                "frac": achieved / peak_tf}
     attainable = min(peak_tf, PEAK["hbm_GBs"] * 1e9 * ai / 1e12)
-    out.update({"traffic": None, "kernel": "k_fold", "launches": launches,
+    out.update({"traffic": traffic, "kernel": "k_fold", "launches": launches,
                 "avg_launch_us": secs / launches * 1e6, "flops_per_launch": flops / launches,
                 "bytes_per_launch": nbytes / launches, "arith_intensity": ai, "tflops": flops / secs / 1e12,
                 "frac_of_mfma_peak": flops / secs / 1e12 / peak_tf,
@@ -98,7 +121,7 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
         "proposals_per_s": props / dt, "acceptance": acc_upd / max(props, 1),
         "mean_order": sum(w.orders()) / walkers, "windows": windows, "walkers": walkers,
         "mean_fold_rank": (s1["flips_folded"] - s0["flips_folded"]) / max(windows, 1),
-        "roofline": roofline(s0, s1, precision),
+        "roofline": roofline(s0, s1, precision, fold_traffic(workload, precision)),
         "kernel_seconds": {"fold": s1["fold_seconds"] - s0["fold_seconds"],
                            "accept_loop": s1["accept_seconds"] - s0["accept_seconds"],
                            "windows_total": s1["window_seconds"] - s0["window_seconds"]},
@@ -114,7 +137,7 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
             w.sweep(1)
             w.measure(acc, aux)
         torch.cuda.synchronize()
-        res["roofline"] = roofline(r0, w.stats(), precision)
+        res["roofline"] = roofline(r0, w.stats(), precision, fold_traffic(workload, precision))
         if res["roofline"]:
             res["roofline"]["pass"] = "eager sweeps after the timed region"
     cfg_out = w.get_config()
@@ -206,7 +229,20 @@ def main():
     ap.add_argument("--walkers", type=int, default=1)
     ap.add_argument("--batch", type=int, default=0,
                     help="also run the batched workload with this many walkers (FP64 and FP32-mixed)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 256 MiB five times (a known-size reference for "
+                         "hardware traffic counters) and print its size")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 256 << 20
+        x = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(walkers are independent Markov chains: on several GPUs each would run its own walkers "

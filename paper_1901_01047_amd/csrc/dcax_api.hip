@@ -381,13 +381,18 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   else hipLaunchKernelGGL(k_prep_rng<T>, dim3(1, 1, W), dim3(PW), 0, s, vs);
   const int ne = std::min(2 * ks, KS_MAX);   // elements: candidates, targets, second attempts
   hipLaunchKernelGGL(k_gather<T>, dim3(cdiv(kb1, WG), ne, W), dim3(WG), 0, s, vs);
-  hipLaunchKernelGGL(k_cand_x<T>, dim3(cdiv(kb1, 16), 2, W), dim3(WG), 0, s, vs);
-  hipLaunchKernelGGL(k_gram<T>, dim3(ne, 2, W), dim3(WG), 0, s, vs);
+  // few workgroups: 16 wavefronts each; large batches: 4
+  const bool wide = (long long)cdiv(kb1, 16) * 2 * W < 4096;
+  if (wide) hipLaunchKernelGGL((k_cand_x<T, 16>), dim3(cdiv(kb1, 16), 2, W), dim3(1024), 0, s, vs);
+  else hipLaunchKernelGGL((k_cand_x<T, 4>), dim3(cdiv(kb1, 16), 2, W), dim3(256), 0, s, vs);
+  if ((long long)ne * 2 * W < 4096) hipLaunchKernelGGL((k_gram<T, 16>), dim3(ne, 2, W), dim3(1024), 0, s, vs);
+  else hipLaunchKernelGGL((k_gram<T, 4>), dim3(ne, 2, W), dim3(256), 0, s, vs);
   hipEvent_t e_a0 = w->rec();
   hipLaunchKernelGGL(k_accept<T>, dim3(1, 1, W), dim3(AW), 0, s, vs);
   hipEvent_t e_a1 = w->rec();
   w->mark(w->pend_accept, e_a0, e_a1);
-  hipLaunchKernelGGL(k_ygemm<T>, dim3(cdiv(kb1, 16), 2, W), dim3(WG), 0, s, vs);
+  if (wide) hipLaunchKernelGGL((k_ygemm<T, 16>), dim3(cdiv(kb1, 16), 2, W), dim3(1024), 0, s, vs);
+  else hipLaunchKernelGGL((k_ygemm<T, 4>), dim3(cdiv(kb1, 16), 2, W), dim3(256), 0, s, vs);
   hipLaunchKernelGGL(k_fold_prep<T>, dim3(cdiv(kx, 64), 2, W), dim3(WG), 0, s, vs);
   hipEvent_t e_f0 = w->rec();
   hipLaunchKernelGGL(k_fold<T>, dim3(cdiv(kx, 64), cdiv(kx, 64), 2 * W), dim3(WG), 0, s, vs);

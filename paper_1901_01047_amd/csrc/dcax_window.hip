@@ -320,16 +320,23 @@ __global__ void __launch_bounds__(WG) k_gather(const View<T>* __restrict__ vs) {
   }
 }
 
+// The candidate GEMMs and the Gram kernel split the inner dimension (the
+// order k) over the NW wavefronts of a workgroup: 16 when a launch has few
+// workgroups (a single walker: short chains of dependent loads per
+// wavefront, many loads in flight), 4 for large batches (enough workgroups
+// already; fewer idle wavefronts on small walkers).
+
 // ------------------------------------------------------- candidate rows
 // X_c = W_c N for all candidates and both spins (an nC x k0 x k0 product on
 // the matrix cores), written as rows e = element(c) of R.  A workgroup owns
-// 16 columns of X; its four wavefronts split the inner dimension and their
+// 16 columns of X; its wavefronts split the inner dimension and their
 // partial tiles are summed in LDS in a fixed order, so the result does not
 // depend on scheduling.  Small tiles and the split keep the dependent chain
 // of loads short: at the orders of a single walker this product is bound by
 // load latency, not by bandwidth.
-template <typename T>
-__global__ void __launch_bounds__(WG) k_cand_x(const View<T>* __restrict__ vs) {
+template <typename T, int NW>
+__global__ void __launch_bounds__(NW * 64) k_cand_x(const View<T>* __restrict__ vs) {
+  constexpr int GWV = NW;
   typedef typename Mfma<T>::acc_t acc_t;
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
@@ -349,7 +356,7 @@ __global__ void __launch_bounds__(WG) k_cand_x(const View<T>* __restrict__ vs) {
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) acc[rb] = acc_t{0, 0, 0, 0};
 #pragma unroll 4
-  for (int i0 = 4 * wv; i0 < k0; i0 += 16) {
+  for (int i0 = 4 * wv; i0 < k0; i0 += 4 * GWV) {
     const int ik = i0 + lk;
     const bool kin = ik < k0;
     const T b = (kin && jc < k0) ? N[ik + (size_t)jc * w.ld] : (T)0;
@@ -361,13 +368,14 @@ __global__ void __launch_bounds__(WG) k_cand_x(const View<T>* __restrict__ vs) {
         acc[rb] = Mfma<T>::run(a, b, acc[rb]);
       }
   }
-  __shared__ acc_t red[4][4][64];
+  __shared__ acc_t red[GWV][4][64];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) red[wv][rb][lane] = acc[rb];
   __syncthreads();
   const int rb = wv;
   if (rb >= nRB) return;
-  const acc_t sum = ((red[0][rb][lane] + red[1][rb][lane]) + red[2][rb][lane]) + red[3][rb][lane];
+  acc_t sum = red[0][rb][lane];
+  for (int v = 1; v < GWV; ++v) sum += red[v][rb][lane];
   const auto R = gp(w.R[sp]);
   const auto cand_el = gp(w.cand_el);
 #pragma unroll
@@ -386,8 +394,9 @@ __global__ void __launch_bounds__(WG) k_cand_x(const View<T>* __restrict__ vs) {
 //   target p:     Gt_{x,p} = R_x[p], from G (e^V - 1) = N e^V - 1 with
 //                 Delta_p = e^{-V_p} - 1;
 // where R_x is row x of the extended N (X_c for candidates, N_{p.} for targets).
-template <typename T>
-__global__ void __launch_bounds__(WG) k_gram(const View<T>* __restrict__ vs) {
+template <typename T, int NW>
+__global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs) {
+  constexpr int GWV = NW, GW = NW * 64;
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
   if (!c->active) return;
@@ -399,7 +408,7 @@ __global__ void __launch_bounds__(WG) k_gram(const View<T>* __restrict__ vs) {
   const auto Rx = gp(w.R[sp] + (size_t)x * w.cap);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const auto G = gp(w.gram[sp] + x * KS_MAX);
-  for (int cc = wv; cc < nC; cc += WG / 64) {
+  for (int cc = wv; cc < nC; cc += GWV) {
     const auto gc = gp(w.gcol + (size_t)cc * w.cap);
     double s = 0.0;
     for (int i = lane; i < k0; i += 64) s += (double)Rx[i] * (double)gc[i];
@@ -411,7 +420,7 @@ __global__ void __launch_bounds__(WG) k_gram(const View<T>* __restrict__ vs) {
       G[ec] = -Dc * g + (ec == x ? 1.0 + Dc : 0.0);
     }
   }
-  for (int y = threadIdx.x; y < nE; y += WG) {
+  for (int y = threadIdx.x; y < nE; y += GW) {
     const int py = w.el_slot[y];
     if (py >= 0) G[y] = (double)Rx[py];
   }
@@ -895,10 +904,11 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
 
 // --------------------------------------------------------- Y = N g_{I,c}
 // Columns N g_{I,c} for the inserted spins (a k0 x k0 x mi product).  A
-// workgroup owns 16 rows; its four wavefronts split the inner dimension and
-// their partial tiles are summed in LDS in a fixed order.
-template <typename T>
-__global__ void __launch_bounds__(WG) k_ygemm(const View<T>* __restrict__ vs) {
+// workgroup owns 16 rows; its wavefronts split the inner dimension and their
+// partial tiles are summed in LDS in a fixed order.
+template <typename T, int NW>
+__global__ void __launch_bounds__(NW * 64) k_ygemm(const View<T>* __restrict__ vs) {
+  constexpr int GWV = NW;
   typedef typename Mfma<T>::acc_t acc_t;
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
@@ -925,7 +935,7 @@ __global__ void __launch_bounds__(WG) k_ygemm(const View<T>* __restrict__ vs) {
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
 #pragma unroll 4
-  for (int j0 = 4 * wv; j0 < k0; j0 += 16) {
+  for (int j0 = 4 * wv; j0 < k0; j0 += 4 * GWV) {
     const int jk = j0 + lk;
     const bool kin = jk < k0;
     const T a = (kin && ir < k0) ? N[ir + (size_t)jk * w.ld] : (T)0;
@@ -936,13 +946,14 @@ __global__ void __launch_bounds__(WG) k_ygemm(const View<T>* __restrict__ vs) {
         acc[cb] = Mfma<T>::run(a, b, acc[cb]);
       }
   }
-  __shared__ acc_t red[4][4][64];
+  __shared__ acc_t red[GWV][4][64];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) red[wv][cb][lane] = acc[cb];
   __syncthreads();
   const int cb = wv;
   if (cb >= ncb) return;
-  const acc_t sum = ((red[0][cb][lane] + red[1][cb][lane]) + red[2][cb][lane]) + red[3][cb][lane];
+  acc_t sum = red[0][cb][lane];
+  for (int v = 1; v < GWV; ++v) sum += red[v][cb][lane];
   const int jj = cb * 16 + li;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -1123,10 +1134,13 @@ __global__ void __launch_bounds__(WG) k_compact_move(const View<T>* __restrict__
   template __global__ void k_prep_replay<T>(const View<T>*);             \
   template __global__ void k_prep_rng<T>(const View<T>*);                \
   template __global__ void k_gather<T>(const View<T>*);                  \
-  template __global__ void k_cand_x<T>(const View<T>*);                  \
-  template __global__ void k_gram<T>(const View<T>*);                    \
+  template __global__ void k_cand_x<T, 4>(const View<T>*);               \
+  template __global__ void k_cand_x<T, 16>(const View<T>*);              \
+  template __global__ void k_gram<T, 4>(const View<T>*);                 \
+  template __global__ void k_gram<T, 16>(const View<T>*);                \
   template __global__ void k_accept<T>(const View<T>*);                  \
-  template __global__ void k_ygemm<T>(const View<T>*);                   \
+  template __global__ void k_ygemm<T, 4>(const View<T>*);                \
+  template __global__ void k_ygemm<T, 16>(const View<T>*);               \
   template __global__ void k_fold_prep<T>(const View<T>*);               \
   template __global__ void k_fold<T>(const View<T>*);                    \
   template __global__ void k_compact_move<T>(const View<T>*);
