@@ -102,8 +102,11 @@ def test_scaled_gamma_is_finite_at_u0():
 class WindowModel:
     """NumPy transcription of the window pipeline, replaying forced decisions."""
 
-    def __init__(self, model, r, t, s, ids):
+    def __init__(self, model, r, t, s, ids, schur="sweep"):
         self.m = model
+        # "sweep": Gauss-Jordan sweeps of the window's Gram matrix (ratios are
+        # diagonal entries); "border": the inverse over S grown by bordering
+        self.schur = schur
         self.r, self.t, self.s, self.id = (np.array(x) for x in (r, t, s, ids))
         self.N = [np.linalg.inv(ctaux.n_inverse(model, self.r, self.t, self.s, sp)) for sp in (0, 1)]
         self.ratios = []
@@ -166,47 +169,8 @@ class WindowModel:
             Rw.append(R)
             Gram.append(Gm)
         # -- sequential Schur loop ---------------------------------------
-        S = []
-        Ginv = [np.zeros((0, 0)), np.zeros((0, 0))]
-        kcur = k0
-        for (kind, site, tau, sq, vid, acc), q in zip(props, prop_el):
-            if q in S:
-                j = S.index(q)
-                rat = [Ginv[sp][j, j] for sp in (0, 1)]
-            else:
-                rat, parts = [], []
-                for sp in (0, 1):
-                    gqS = Gram[sp][q, S]
-                    gSq = Gram[sp][S, q]
-                    L = Ginv[sp] @ gSq
-                    Rr = gqS @ Ginv[sp]
-                    schur = Gram[sp][q, q] - gqS @ L
-                    rat.append(schur)
-                    parts.append((L, Rr, schur))
-            fac = m.K_exp / (kcur + 1) if kind == 0 else kcur / m.K_exp
-            self.ratios.append(fac * rat[0] * rat[1])
-            if not acc:
-                continue
-            if q in S:
-                j = S.index(q)
-                for sp in (0, 1):
-                    A = Ginv[sp]
-                    A = A - np.outer(A[:, j], A[j, :]) / A[j, j]
-                    keep = np.arange(len(S)) != j
-                    Ginv[sp] = A[np.ix_(keep, keep)]
-                S.pop(j)
-            else:
-                for sp in (0, 1):
-                    L, Rr, schur = parts[sp]
-                    n = len(S)
-                    B = np.empty((n + 1, n + 1))
-                    B[:n, :n] = Ginv[sp] + np.outer(L, Rr) / schur
-                    B[:n, n] = -L / schur
-                    B[n, :n] = -Rr / schur
-                    B[n, n] = 1.0 / schur
-                    Ginv[sp] = B
-                S.append(q)
-            kcur += 1 if kind == 0 else -1
+        loop = self._sweep_loop if self.schur == "sweep" else self._border_loop
+        S, Ginv = loop(props, prop_el, Gram, k0)
         # -- fold in the extended space, then compaction --------------------
         ins = [q for q in S if cand[q]]
         rem = [el_slot[q] for q in S if not cand[q]]
@@ -254,13 +218,91 @@ class WindowModel:
         keep = np.array([i for i in range(kx) if i not in rem], dtype=int)
         self.r, self.t, self.s, self.id = new_r[keep], new_t[keep], new_s[keep], new_id[keep]
 
+    def _border_loop(self, props, prop_el, Gram, kcur):
+        """Inverse over S grown by bordering and shrunk by a rank-1 downdate."""
+        m = self.m
+        S = []
+        Ginv = [np.zeros((0, 0)), np.zeros((0, 0))]
+        for (kind, site, tau, sq, vid, acc), q in zip(props, prop_el):
+            if q in S:
+                j = S.index(q)
+                rat = [Ginv[sp][j, j] for sp in (0, 1)]
+            else:
+                rat, parts = [], []
+                for sp in (0, 1):
+                    gqS = Gram[sp][q, S]
+                    gSq = Gram[sp][S, q]
+                    L = Ginv[sp] @ gSq
+                    Rr = gqS @ Ginv[sp]
+                    schur = Gram[sp][q, q] - gqS @ L
+                    rat.append(schur)
+                    parts.append((L, Rr, schur))
+            fac = m.K_exp / (kcur + 1) if kind == 0 else kcur / m.K_exp
+            self.ratios.append(fac * rat[0] * rat[1])
+            if not acc:
+                continue
+            if q in S:
+                j = S.index(q)
+                for sp in (0, 1):
+                    A = Ginv[sp]
+                    A = A - np.outer(A[:, j], A[j, :]) / A[j, j]
+                    keep = np.arange(len(S)) != j
+                    Ginv[sp] = A[np.ix_(keep, keep)]
+                S.pop(j)
+            else:
+                for sp in (0, 1):
+                    L, Rr, schur = parts[sp]
+                    n = len(S)
+                    B = np.empty((n + 1, n + 1))
+                    B[:n, :n] = Ginv[sp] + np.outer(L, Rr) / schur
+                    B[:n, n] = -L / schur
+                    B[n, :n] = -Rr / schur
+                    B[n, n] = 1.0 / schur
+                    Ginv[sp] = B
+                S.append(q)
+            kcur += 1 if kind == 0 else -1
+        return S, Ginv
+
+    def _sweep_loop(self, props, prop_el, Gram, kcur):
+        """Sweep tableau T (one per spin), started at the Gram matrix.  After
+        sweeping the set S, T_SS = -Gt_S^{-1} and the other diagonal entries
+        are the Schur complements Gt_qq - Gt_qS Gt_S^{-1} Gt_Sq: the ratio of
+        flipping q is T_qq, that of unflipping q in S is -T_qq, and either
+        acceptance is one sweep (reverse sweep for an unflip) on q."""
+        T = [Gram[0].copy(), Gram[1].copy()]
+        S = []
+        for (kind, site, tau, sq, vid, acc), q in zip(props, prop_el):
+            sgn = -1.0 if q in S else 1.0
+            rat = [sgn * T[sp][q, q] for sp in (0, 1)]
+            fac = self.m.K_exp / (kcur + 1) if kind == 0 else kcur / self.m.K_exp
+            self.ratios.append(fac * rat[0] * rat[1])
+            if not acc:
+                continue
+            for sp in (0, 1):
+                A = T[sp]
+                inv = 1.0 / A[q, q]
+                col, row = A[:, q].copy(), A[q, :] * inv
+                A -= np.outer(col, row)
+                A[q, :] = sgn * row
+                A[:, q] = sgn * col * inv
+                A[q, q] = -inv
+            if sgn < 0:
+                j = S.index(q)
+                S[j] = S[-1]             # the last position fills the hole
+                S.pop()
+            else:
+                S.append(q)
+            kcur += 1 if kind == 0 else -1
+        return S, [-T[sp][np.ix_(S, S)] for sp in (0, 1)]
+
     def canonical(self):
         o = np.argsort(self.id)
         return self.id[o], self.N[0][np.ix_(o, o)], self.N[1][np.ix_(o, o)]
 
 
+@pytest.mark.parametrize("schur", ["sweep", "border"])
 @pytest.mark.parametrize("k_s,seed,U", [(4, 1, 4.0), (16, 2, 4.0), (64, 3, 4.0), (16, 4, 0.0)])
-def test_window_model_replays_oracle(k_s, seed, U):
+def test_window_model_replays_oracle(k_s, seed, U, schur):
     m = ctaux.Model(a1=(2, 0), a2=(0, 2), U=U, beta=5.0, n_tau=1000)
     w = ctaux.Walker(m, seed=seed, k_s=k_s, record=False)
     w.random_config(25)
@@ -272,7 +314,7 @@ def test_window_model_replays_oracle(k_s, seed, U):
     for _ in range(6):
         w.sweep()
     tr = w.trace
-    wm = WindowModel(m, r0, t0, s0, id0)
+    wm = WindowModel(m, r0, t0, s0, id0, schur=schur)
     n_unflip = 0
     for i in range(0, len(tr), k_s):
         chunk = tr[i:i + k_s]
