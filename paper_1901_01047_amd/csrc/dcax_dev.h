@@ -242,27 +242,16 @@ __device__ inline double uni(double x) {
 }
 
 // The value a uniform-indexed lane holds (v_readlane, no LDS round trip).
+__device__ inline int lane_value(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
 __device__ inline double lane_value(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
   return __hiloint2double(hi, lo);
 }
-
-// Sum of v over lanes 0 .. n-1 (four interleaved partial sums, combined in
-// a fixed order), identical in every lane.
-__device__ inline double lanes_sum(double v, int n) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int a = 0;
-  for (; a + 4 <= n; a += 4) {
-    s0 += lane_value(v, a);
-    s1 += lane_value(v, a + 1);
-    s2 += lane_value(v, a + 2);
-    s3 += lane_value(v, a + 3);
-  }
-  if (a < n) s0 += lane_value(v, a);
-  if (a + 1 < n) s1 += lane_value(v, a + 1);
-  if (a + 2 < n) s2 += lane_value(v, a + 2);
-  return (s0 + s1) + (s2 + s3);
+__device__ inline long long lane_value(long long v, int src) {
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), src);
+  return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 __device__ inline double wave_sum(double v) {

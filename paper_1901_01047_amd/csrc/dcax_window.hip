@@ -447,9 +447,27 @@ __global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs
 // target into the next one (the paper's "abort" treatment; exact, since the
 // state does not change in between).
 constexpr int MAX_ATTEMPTS = 1 << 16;
-constexpr int AW = 64;      // accept kernel: one wavefront per walker
-static_assert(KS_MAX == AW, "the accept kernel maps one lane to one window element");
+constexpr int AWV = 4;            // accept kernel: wavefronts per walker
+constexpr int AW = 64 * AWV;
+static_assert(KS_MAX == 64, "the accept kernel maps one lane to one window element");
 
+// Sweep tableau, one per spin, started at the window's scaled Gram matrix Gt.
+// A Gauss-Jordan sweep on element q (pivot d = T_qq) maps T to
+//   T_qq -> -1/d,  T_qc -> T_qc/d,  T_rq -> T_rq/d,  T_rc -> T_rc - T_rq T_qc/d,
+// and the reverse sweep, which undoes it, flips the signs of row and column
+// q.  After sweeping the set S, T_SS = -Gt_S^{-1} and every other diagonal
+// entry T_qq is the Schur complement Gt_qq - Gt_qS Gt_S^{-1} Gt_Sq.  So
+// flipping q has ratio T_qq, unflipping q in S has ratio (Gt_S^{-1})_qq =
+// -T_qq, and accepting either is one (reverse) sweep: a rank-1 update with
+// no reductions.
+//
+// The proposal loop runs in all four wavefronts of the workgroup with the
+// same uniform control flow; each keeps the window state in registers (lane
+// e: element e's position in S, slot, candidate index and diagonal entries;
+// lane j: proposal j; lane a: the element at position a of S; lane i: the
+// i-th spin inserted in this window), so a rejected proposal costs register
+// reads only.  An accepted one is swept with lane c owning column c and the
+// rows dealt to the wavefronts in chunks of CH, between two barriers.
 template <typename T>
 __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
@@ -459,90 +477,91 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
   const uint64_t seed = w.seed;
   Ctl* c = w.ctl;
   if (!c->active) return;
-  // nothing inside the proposal loop touches global memory: candidate ids and
-  // replay ratios are collected in LDS and written after it
-  // LDS rows are padded to LS doubles: with a stride of 64 doubles every lane
-  // reading one column would hit the same bank.
+  // rows padded to LS doubles so that the lanes of a row hit distinct banks
   constexpr int LS = KS_MAX + 1;
-  constexpr int CH = 8;       // columns per chunk of the row loops
-  __shared__ double gam_s[2][KS_MAX * LS];
-  __shared__ double ginv_s[2][KS_MAX * LS];
-  
-  __shared__ int S_s[KS_MAX], pos_s[KS_MAX], insl_s[KS_MAX];
-  __shared__ WinProp wp_s[KS_MAX];
-  __shared__ int cand_s[KS_MAX], spin_s[KS_MAX], slot_s[KS_MAX];
+  constexpr int CH = 4;
+  __shared__ double T_s[2][KS_MAX * LS];
   __shared__ long long cid_s[KS_MAX];
   __shared__ double rout_s[KS_MAX];
-  const int lane = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = uni(t >> 6);
+  const bool t0 = t == 0, w0 = wv == 0;
   const int nE = uni(c->nE), nP = uni(c->nP), k0 = uni(c->k0), nC = uni(c->nC);
   const double K_exp = uni(w.K_exp);
   const int max_order = uni(w.max_order);
-  // only rows and columns below nE are ever read
-  const auto gram0 = gp(w.gram[0]), gram1 = gp(w.gram[1]);
-  // rows x < nE of both spins, loads issued four rows at a time
-  for (int x0 = 0; x0 < nE; x0 += 4) {
-    double g0[4], g1[4];
+  {
+    // Gram rows x < nE of both spins; wavefront wv loads rows 16 wv .. 16 wv + 15
+    const auto gram0 = gp(w.gram[0]), gram1 = gp(w.gram[1]);
+    double g0[16], g1[16];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool in = x0 + u < nE && lane < nE;
-      g0[u] = in ? gram0[(x0 + u) * KS_MAX + lane] : 0.0;
-      g1[u] = in ? gram1[(x0 + u) * KS_MAX + lane] : 0.0;
+    for (int u = 0; u < 16; ++u) {
+      const int x = wv * 16 + u;
+      const bool in = x < nE && lane < nE;
+      g0[u] = in ? gram0[x * KS_MAX + lane] : 0.0;
+      g1[u] = in ? gram1[x * KS_MAX + lane] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (x0 + u < nE) {
-        gam_s[0][(x0 + u) * LS + lane] = g0[u];
-        gam_s[1][(x0 + u) * LS + lane] = g1[u];
+    for (int u = 0; u < 16; ++u) {
+      const int x = wv * 16 + u;
+      if (x < nE) {
+        T_s[0][x * LS + lane] = g0[u];
+        T_s[1][x * LS + lane] = g1[u];
       }
+    }
   }
-  pos_s[lane] = -1;
-  if (lane < nP) wp_s[lane] = w.wp[lane];
+  // per-lane window state (identical in every wavefront)
+  int p_kind = 0, p_el = -1, p_forced = -1, p_carried = 0;
+  double p_u = 0.0, p_ub0 = 0.0, p_ui0 = 0.0;
+  long long p_ridx = -1, p_gidx = 0;
+  if (lane < nP) {
+    const WinProp& x = w.wp[lane];
+    p_kind = x.kind;
+    p_el = x.el;
+    p_forced = x.forced;
+    p_carried = x.carried;
+    p_u = x.u;
+    p_ub0 = x.ub0;
+    p_ui0 = x.ui0;
+    p_ridx = x.ridx;
+    p_gidx = x.gidx;
+  }
+  int e_cand = -1, e_spin = 0, e_slot = -1;
   if (lane < nE) {
-    cand_s[lane] = gp(w.el_cand)[lane];
-    spin_s[lane] = gp(w.el_s)[lane];
-    slot_s[lane] = gp(w.el_slot)[lane];
+    e_cand = gp(w.el_cand)[lane];
+    e_spin = gp(w.el_s)[lane];
+    e_slot = gp(w.el_slot)[lane];
   }
-  if (lane < nC) cid_s[lane] = gp(w.cand_id)[lane];
+  if (t < nC) cid_s[t] = gp(w.cand_id)[t];
+  int pos_r = -1, sa = 0, insl = 0;
   __syncthreads();
-  // window state: identical in every lane, except sa = S[lane], the element
-  // at position `lane` of S (valid below m)
-  int m = 0, kcur = k0, nins = 0, bad = 0, n_done = nP, sa = 0;
+  double dg0 = T_s[0][lane * LS + lane], dg1 = T_s[1][lane * LS + lane];
+  int m = 0, kcur = k0, nins = 0, bad = 0, n_done = nP;
   double sign = uni(c->sign);
   long long next_id = uni(c->next_id), carry = -1;
   long long n_ins = 0, n_rem = 0, n_mis = 0;
   for (int j = 0; j < nP; ++j) {
-    m = uni(m);
-    kcur = uni(kcur);
-    nins = uni(nins);
-    WinProp p = wp_s[j];
-    p.kind = uni(p.kind);
-    p.el = uni(p.el);
-    p.forced = uni(p.forced);
-    p.carried = uni(p.carried);
-    p.u = uni(p.u);
-    p.ub0 = uni(p.ub0);
-    p.ui0 = uni(p.ui0);
-    p.gidx = uni(p.gidx);
-    int q = p.el, ab = 0;
-    if (p.forced < 0 && p.kind == 1 && !p.carried) {
+    const int kind = lane_value(p_kind, j), el = lane_value(p_el, j);
+    const int forced = lane_value(p_forced, j), carried = lane_value(p_carried, j);
+    int q = el, ab = 0;
+    if (forced < 0 && kind == 1 && !carried) {
       q = -1;
       if (kcur > 0) {
+        const long long gidx = lane_value(p_gidx, j);
         for (int a = 0; a < MAX_ATTEMPTS; ++a) {
-          double ub = p.ub0, ui = p.ui0;
+          double ub = lane_value(p_ub0, j), ui = lane_value(p_ui0, j);
           if (a > 0) {
-            uniforms2(seed, p.gidx, 3u + (uint32_t)a, ub, ui);
+            uniforms2(seed, gidx, 3u + (uint32_t)a, ub, ui);
             ub = uni(ub);
             ui = uni(ui);
           }
           if (ub * (double)(k0 + nins) < (double)k0) {
             int slot = (int)(ui * (double)k0);
             if (slot >= k0) slot = k0 - 1;
-            int e = p.el;
+            int e = el;
             if (a > 0) {
-              const unsigned long long hit = __ballot(lane < nE && slot_s[lane] == slot);
+              const unsigned long long hit = __ballot(lane < nE && e_slot == slot);
               e = hit ? (int)__ffsll((long long)hit) - 1 : -1;
             }
-            if (e >= 0 && uni(pos_s[e]) >= 0) continue;     // already removed in this window
+            if (e >= 0 && lane_value(pos_r, e) >= 0) continue;     // already removed in this window
             if (e < 0) {
               ab = 1;
               carry = uni(gp(w.v_id)[slot]);
@@ -553,7 +572,7 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
           }
           int idx = (int)(ui * (double)nins);
           if (idx >= nins) idx = nins - 1;
-          q = uni(insl_s[idx]);
+          q = lane_value(insl, idx);
           break;
         }
         if (q < 0 && !ab) bad = 1;
@@ -564,258 +583,168 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
       break;
     }
     if (q < 0) {
-      if (lane == 0) rout_s[j] = 0.0;
+      if (t0) rout_s[j] = 0.0;
       continue;
     }
-    const int pq = uni(pos_s[q]);
-    double r0, r1, L0 = 0.0, L1 = 0.0, w0 = 0.0, w1 = 0.0;
-    if (pq >= 0) {
-      r0 = uni(ginv_s[0][pq * LS + pq]);
-      r1 = uni(ginv_s[1][pq * LS + pq]);
-    } else {
-      // lane a holds Gt_{S_a q} and Gt_{q S_a}; L = Gt_S^{-1} Gt_Sq (lane a
-      // holds L_a) with the Gt_{S_b q} read from lane b's register, and the
-      // Schur complement Gt_qq - Gt_qS L summed over lanes in order
-      const bool in = lane < m;
-      w0 = in ? gam_s[0][q * LS + sa] : 0.0;
-      w1 = in ? gam_s[1][q * LS + sa] : 0.0;
-      const double v0 = in ? gam_s[0][sa * LS + q] : 0.0, v1 = in ? gam_s[1][sa * LS + q] : 0.0;
-      // chunks of CH columns: the loads of a chunk are issued together
-      for (int b0 = 0; b0 < m; b0 += CH) {
-        double g0[CH], g1[CH];
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-          const int b = min(b0 + u, KS_MAX - 1);
-          g0[u] = ginv_s[0][lane * LS + b];
-          g1[u] = ginv_s[1][lane * LS + b];
-        }
-        double e0 = 0.0, e1 = 0.0, o0 = 0.0, o1 = 0.0;
-#pragma unroll
-        for (int u = 0; u < CH; u += 2) {
-          if (b0 + u < m) {
-            e0 += g0[u] * lane_value(v0, b0 + u);
-            e1 += g1[u] * lane_value(v1, b0 + u);
-          }
-          if (b0 + u + 1 < m) {
-            o0 += g0[u + 1] * lane_value(v0, b0 + u + 1);
-            o1 += g1[u + 1] * lane_value(v1, b0 + u + 1);
-          }
-        }
-        L0 += e0 + o0;
-        L1 += e1 + o1;
-      }
-      L0 = in ? L0 : 0.0;
-      L1 = in ? L1 : 0.0;
-      r0 = uni(gam_s[0][q * LS + q] - lanes_sum(w0 * L0, m));
-      r1 = uni(gam_s[1][q * LS + q] - lanes_sum(w1 * L1, m));
-    }
-    const double fac = (p.kind == 0) ? K_exp / (double)(kcur + 1) : (double)kcur / K_exp;
-    const double R = fac * r0 * r1;
+    const int pq = lane_value(pos_r, q);
+    const double sgn = (pq >= 0) ? -1.0 : 1.0;
+    const double d0 = lane_value(dg0, q), d1 = lane_value(dg1, q);
+    const double fac = (kind == 0) ? K_exp / (double)(kcur + 1) : (double)kcur / K_exp;
+    const double R = fac * (sgn * d0) * (sgn * d1);
     int dec;
     if (!isfinite(R)) {
       bad = 1;
       dec = 0;
     } else {
-      const int mine = p.u < fabs(R);
-      dec = (p.forced >= 0) ? p.forced : mine;
-      if (p.forced >= 0 && mine != p.forced) ++n_mis;
+      const int mine = lane_value(p_u, j) < fabs(R);
+      dec = (forced >= 0) ? forced : mine;
+      if (forced >= 0 && mine != forced) ++n_mis;
     }
-    if (lane == 0) rout_s[j] = R;
-    if (dec && p.kind == 0 && kcur + 1 > max_order) {
-      if (lane == 0) latch(c, ST_CAPACITY);
+    if (t0) rout_s[j] = R;
+    if (dec && kind == 0 && kcur + 1 > max_order) {
+      if (t0) latch(c, ST_CAPACITY);
       dec = 0;
     }
     if (!dec) continue;
-    kcur += (p.kind == 0) ? 1 : -1;
+    kcur += (kind == 0) ? 1 : -1;
     if (R < 0.0) sign = -sign;
-    if (p.kind == 0) {
+    if (kind == 0) {
       ++n_ins;
-      if (p.forced < 0) {
-        if (lane == 0) cid_s[cand_s[q]] = next_id;
+      if (forced < 0) {
+        const int cq = lane_value(e_cand, q);
+        if (t0) cid_s[cq] = next_id;
         ++next_id;
       }
-      if (lane == 0) insl_s[nins] = q;
+      if (lane == nins) insl = q;
       ++nins;
     } else {
       ++n_rem;
       if (pq >= 0) {
-        if (lane == 0) {
-          int x = 0;
-          while (insl_s[x] != q) ++x;
-          for (; x + 1 < nins; ++x) insl_s[x] = insl_s[x + 1];
-        }
+        // an unflipped insertion leaves the list of inserted spins
+        const unsigned long long at = __ballot(lane < nins && insl == q);
+        const int x = (int)__ffsll((long long)at) - 1;
+        const int next = __shfl(insl, lane + 1, 64);
+        if (lane >= x) insl = next;
         --nins;
       }
     }
+    {
+      const double inv0 = 1.0 / d0, inv1 = 1.0 / d1;
+      const bool isq = lane == q;
+      const double tq0 = T_s[0][q * LS + lane], tq1 = T_s[1][q * LS + lane];
+      // new row q; lane q's own column becomes sgn T_rq / d, which the update
+      // below produces with a zero weight on the old value
+      const double rq0 = isq ? -inv0 : sgn * (tq0 * inv0), rq1 = isq ? -inv1 : sgn * (tq1 * inv1);
+      const double f0 = isq ? -sgn * inv0 : tq0 * inv0, f1 = isq ? -sgn * inv1 : tq1 * inv1;
+      const double a_l = isq ? 0.0 : 1.0;
+      __syncthreads();      // row q has been read everywhere
+      for (int r0_ = wv * CH; r0_ < nE; r0_ += AWV * CH) {
+        double pc0[CH], pc1[CH], v0[CH], v1[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int r = r0_ + u;
+          pc0[u] = T_s[0][r * LS + q];
+          pc1[u] = T_s[1][r * LS + q];
+          v0[u] = T_s[0][r * LS + lane];
+          v1[u] = T_s[1][r * LS + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int r = r0_ + u;
+          T_s[0][r * LS + lane] = fma(-pc0[u], f0, a_l * v0[u]);
+          T_s[1][r * LS + lane] = fma(-pc1[u], f1, a_l * v1[u]);
+        }
+      }
+      if ((q / CH) % AWV == wv) {
+        // this wavefront swept row q above; its final values
+        T_s[0][q * LS + lane] = rq0;
+        T_s[1][q * LS + lane] = rq1;
+      }
+    }
     if (pq < 0) {
-      // bordering: q joins S at position m
-      // R = Gt_qS Gt_S^{-1} (lane b holds R_b), then the bordered inverse
-      const double inv0 = 1.0 / r0, inv1 = 1.0 / r1;
-      double R0 = 0.0, R1 = 0.0;
-      for (int a0 = 0; a0 < m; a0 += CH) {
-        double g0[CH], g1[CH];
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-          const int a = min(a0 + u, KS_MAX - 1);
-          g0[u] = ginv_s[0][a * LS + lane];
-          g1[u] = ginv_s[1][a * LS + lane];
-        }
-        double e0 = 0.0, e1 = 0.0, o0 = 0.0, o1 = 0.0;
-#pragma unroll
-        for (int u = 0; u < CH; u += 2) {
-          if (a0 + u < m) {
-            e0 += lane_value(w0, a0 + u) * g0[u];
-            e1 += lane_value(w1, a0 + u) * g1[u];
-          }
-          if (a0 + u + 1 < m) {
-            o0 += lane_value(w0, a0 + u + 1) * g0[u + 1];
-            o1 += lane_value(w1, a0 + u + 1) * g1[u + 1];
-          }
-        }
-        R0 += e0 + o0;
-        R1 += e1 + o1;
-      }
-      const double l0 = L0 * inv0, l1 = L1 * inv1;
-      for (int b0 = 0; b0 < m; b0 += CH) {
-        double g0[CH], g1[CH];
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-          const int b = min(b0 + u, KS_MAX - 1);
-          g0[u] = ginv_s[0][lane * LS + b];
-          g1[u] = ginv_s[1][lane * LS + b];
-        }
-#pragma unroll
-        for (int u = 0; u < CH; ++u)
-          if (b0 + u < m) {
-            const double r0u = lane_value(R0, b0 + u), r1u = lane_value(R1, b0 + u);
-            if (lane < m) {
-              ginv_s[0][lane * LS + b0 + u] = g0[u] + l0 * r0u;
-              ginv_s[1][lane * LS + b0 + u] = g1[u] + l1 * r1u;
-            }
-          }
-      }
-      if (lane < m) {
-        ginv_s[0][lane * LS + m] = -L0 * inv0;
-        ginv_s[1][lane * LS + m] = -L1 * inv1;
-      } else if (lane == m) {
-        for (int b = 0; b < m; ++b) {
-          ginv_s[0][m * LS + b] = -lane_value(R0, b) * inv0;
-          ginv_s[1][m * LS + b] = -lane_value(R1, b) * inv1;
-        }
-        ginv_s[0][m * LS + m] = inv0;
-        ginv_s[1][m * LS + m] = inv1;
-      }
-      if (lane == 0) {
-        S_s[m] = q;
-        pos_s[q] = m;
-      }
+      // q joins S at position m
+      if (lane == q) pos_r = m;
       if (lane == m) sa = q;
       ++m;
-      __syncthreads();
     } else {
-      // rank-1 downdate, then the last position moves into the hole
+      // the last position of S moves into the hole
       const int js = pq, last = m - 1;
-      const double piv0 = ginv_s[0][js * LS + js], piv1 = ginv_s[1][js * LS + js];
-      const bool in = lane < m;
-      const double c0 = in ? ginv_s[0][lane * LS + js] : 0.0, c1 = in ? ginv_s[1][lane * LS + js] : 0.0;
-      const double rw0 = in ? ginv_s[0][js * LS + lane] : 0.0, rw1 = in ? ginv_s[1][js * LS + lane] : 0.0;
-      __syncthreads();
-      const double f0 = c0 / piv0, f1 = c1 / piv1;
-      for (int b0 = 0; b0 < m; b0 += CH) {
-        double g0[CH], g1[CH];
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-          const int b = min(b0 + u, KS_MAX - 1);
-          g0[u] = ginv_s[0][lane * LS + b];
-          g1[u] = ginv_s[1][lane * LS + b];
-        }
-#pragma unroll
-        for (int u = 0; u < CH; ++u)
-          if (b0 + u < m) {
-            const double r0u = lane_value(rw0, b0 + u), r1u = lane_value(rw1, b0 + u);
-            if (in) {
-              ginv_s[0][lane * LS + b0 + u] = g0[u] - f0 * r0u;
-              ginv_s[1][lane * LS + b0 + u] = g1[u] - f1 * r1u;
-            }
-          }
-      }
-      __syncthreads();
-      if (js != last) {
-        if (lane < m) {
-          ginv_s[0][js * LS + lane] = ginv_s[0][last * LS + lane];
-          ginv_s[1][js * LS + lane] = ginv_s[1][last * LS + lane];
-        }
-        __syncthreads();
-        if (lane < m) {
-          ginv_s[0][lane * LS + js] = ginv_s[0][lane * LS + last];
-          ginv_s[1][lane * LS + js] = ginv_s[1][lane * LS + last];
-        }
-      }
-      if (lane == 0) {
-        const int el_last = S_s[last];
-        S_s[js] = el_last;
-        pos_s[el_last] = js;
-        pos_s[q] = -1;
-      }
-      const int s_last = __shfl(sa, last, AW);
-      if (lane == js) sa = s_last;
+      const int el_last = lane_value(sa, last);
+      if (lane == el_last) pos_r = js;
+      if (lane == q) pos_r = -1;
+      if (lane == js) sa = el_last;
       m = last;
-      __syncthreads();
+    }
+    __syncthreads();
+    dg0 = T_s[0][lane * LS + lane];
+    dg1 = T_s[1][lane * LS + lane];
+  }
+  {
+    // Gt_S^{-1} in the order of S: -T over the rows and columns of S
+    const auto gi0 = gp(w.ginv[0]), gi1 = gp(w.ginv[1]);
+    for (int a = wv; a < m; a += AWV) {
+      const int ea = lane_value(sa, a);
+      if (lane < m) {
+        gi0[a * KS_MAX + lane] = -T_s[0][ea * LS + sa];
+        gi1[a * KS_MAX + lane] = -T_s[1][ea * LS + sa];
+      }
     }
   }
   __syncthreads();
-  {
-    const auto gi0 = gp(w.ginv[0]), gi1 = gp(w.ginv[1]);
-    for (int a = 0; a < m; ++a)
-      if (lane < m) {
-        gi0[a * KS_MAX + lane] = ginv_s[0][a * LS + lane];
-        gi1[a * KS_MAX + lane] = ginv_s[1][a * LS + lane];
-      }
-    if (lane < n_done && wp_s[lane].ridx >= 0) gp(w.ratio_out)[wp_s[lane].ridx] = rout_s[lane];
-    if (lane < c->nC) gp(w.cand_id)[lane] = cid_s[lane];
+  if (w0) {
+    if (lane < n_done && p_ridx >= 0) gp(w.ratio_out)[p_ridx] = rout_s[lane];
+    if (lane < nC) gp(w.cand_id)[lane] = cid_s[lane];
   }
   // Epilogue: the fold's column order, the new vertex arrays and the plan
   // that removes the deleted rows and columns of N.  Inserted spins take
   // slots k0 .. k0+mi-1; holes left below the new order are filled from the
   // surviving slots above it (remap[dst] = src, moves[] = (dst, src) pairs).
   // Nothing later in the window reads the vertex arrays or the order, so
-  // both are final here.
+  // both are final here.  Every wavefront computes the plan (their registers
+  // agree); the first one stores it.
   __shared__ int ins_s[KS_MAX], hole_s[KS_MAX], src_s[KS_MAX], rem[KS_MAX], row_s[KS_MAX];
   const int knew = kcur;
   // lane s < m looks at the element in position s of S; inserted spins are
   // numbered in S order, removed slots ranked by value (they are distinct)
-  const int e_l = lane < m ? sa : -1;
-  const bool isc = lane < m && cand_s[e_l] >= 0;
+  // (the shuffles run in every lane: a lane that skips one would not serve
+  // its value to the others)
+  const int e_l = lane < m ? sa : 0;
+  const int cand_l = __shfl(e_cand, e_l, 64), eslot_l = __shfl(e_slot, e_l, 64);
+  const bool isc = lane < m && cand_l >= 0;
   const bool isr = lane < m && !isc;
   const unsigned long long cmask = __ballot(isc), rmask = __ballot(isr);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int mi = __popcll(cmask), mr = __popcll(rmask);
-  const int slot_l = isr ? slot_s[e_l] : 0x7fffffff;
-  if (isc) {
-    const int x = __popcll(cmask & below);
-    ins_s[x] = e_l;
-    row_s[lane] = k0 + x;
-  }
+  const int slot_l = isr ? eslot_l : 0x7fffffff;
   int rank = 0;
   for (int b = 0; b < m; ++b) rank += __builtin_amdgcn_readlane(slot_l, b) < slot_l;
-  if (isr) {
-    row_s[lane] = slot_l;
-    rem[rank] = slot_l;
+  if (w0) {
+    if (isc) {
+      const int x = __popcll(cmask & below);
+      ins_s[x] = e_l;
+      row_s[lane] = k0 + x;
+    }
+    if (isr) {
+      row_s[lane] = slot_l;
+      rem[rank] = slot_l;
+    }
   }
   __syncthreads();
   const int kx = k0 + mi;
   // holes: the removed slots below the new order, in increasing order;
   // sources: the surviving slots in [knew, kx) (there are as many)
   const int nh = __popcll(__ballot(isr && slot_l < knew));
-  if (lane < nh) hole_s[lane] = rem[lane];
   bool surv = false;
   if (lane < kx - knew) {
     surv = true;
     for (int a = 0; a < mr; ++a) surv &= rem[a] != knew + lane;
   }
   const unsigned long long smask = __ballot(surv);
-  if (surv) src_s[__popcll(smask & below)] = knew + lane;
-  if (lane == 0) {
+  if (w0) {
+    if (lane < nh) hole_s[lane] = rem[lane];
+    if (surv) src_s[__popcll(smask & below)] = knew + lane;
+  }
+  if (t0) {
     moves[2 * KS_MAX] = nh;
     if (bad) latch(c, ST_NUMERIC);
     c->m = m;
@@ -848,17 +777,18 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
   }
   __syncthreads();
   if (m == 0) return;
-  if (lane < m) {
-    const int e = S_s[lane];
-    gp(w.S)[lane] = e;
-    el_row[e] = row_s[lane];
+  for (int i = t; i < knew; i += AW) remap[i] = i;
+  if (w0) {
+    if (lane < m) {
+      gp(w.S)[lane] = sa;
+      el_row[sa] = row_s[lane];
+    }
+    if (lane < mi) gp(w.ins_el)[lane] = ins_s[lane];
+    if (lane < nh) {
+      moves[2 * lane] = hole_s[lane];
+      moves[2 * lane + 1] = src_s[lane];
+    }
   }
-  if (lane < mi) gp(w.ins_el)[lane] = ins_s[lane];
-  if (lane < nh) {
-    moves[2 * lane] = hole_s[lane];
-    moves[2 * lane + 1] = src_s[lane];
-  }
-  for (int i = lane; i < knew; i += AW) remap[i] = i;
   const auto v_site = gp(w.v_site), v_s = gp(w.v_s);
   const auto v_tau = gp(w.v_tau);
   const auto v_id = gp(w.v_id);
@@ -867,7 +797,7 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
   int h_site = 0, h_s = 0;
   double h_tau = 0.0;
   long long h_id = 0;
-  const bool hole = lane < nh && src_s[lane] < k0;
+  const bool hole = w0 && lane < nh && src_s[lane] < k0;
   if (hole) {
     const int sidx = src_s[lane];
     h_site = v_site[sidx];
@@ -876,24 +806,27 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     h_id = v_id[sidx];
   }
   __syncthreads();
-  if (lane < mi) {
-    const int e = ins_s[lane];
-    v_site[k0 + lane] = gp(w.el_site)[e];
-    v_tau[k0 + lane] = gp(w.el_tau)[e];
-    v_s[k0 + lane] = spin_s[e];
-    v_id[k0 + lane] = cid_s[cand_s[e]];
+  const int e_ins = lane < mi ? ins_s[lane] : 0;
+  const int s_ins = __shfl(e_spin, e_ins, 64), c_ins = __shfl(e_cand, e_ins, 64);
+  if (w0 && lane < mi) {
+    v_site[k0 + lane] = gp(w.el_site)[e_ins];
+    v_tau[k0 + lane] = gp(w.el_tau)[e_ins];
+    v_s[k0 + lane] = s_ins;
+    v_id[k0 + lane] = cid_s[c_ins];
   }
+  // an inserted spin that moves into a hole: its element's values
+  int e_h = 0;
+  if (lane < nh && src_s[lane] >= k0) e_h = ins_s[src_s[lane] - k0];
+  const int s_h = __shfl(e_spin, e_h, 64), c_h = __shfl(e_cand, e_h, 64);
   __syncthreads();
-  if (lane < nh) {
+  if (w0 && lane < nh) {
     const int d = hole_s[lane], sidx = src_s[lane];
     remap[d] = sidx;
     if (sidx >= k0) {
-      // an inserted spin moves into the hole: its values are in LDS
-      const int e = ins_s[sidx - k0];
-      h_site = gp(w.el_site)[e];
-      h_tau = gp(w.el_tau)[e];
-      h_s = spin_s[e];
-      h_id = cid_s[cand_s[e]];
+      h_site = gp(w.el_site)[e_h];
+      h_tau = gp(w.el_tau)[e_h];
+      h_s = s_h;
+      h_id = cid_s[c_h];
     }
     v_site[d] = h_site;
     v_tau[d] = h_tau;
