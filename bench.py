@@ -21,6 +21,9 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBs": 8000.0, "fp64_mfma_TFs": 78.6, "fp32_mfma_TFs": 157.3}
 WORKLOAD = "4x4_U4_b10"
+# a pseudo-random 1/TIMING_EVERY of the windows carries HIP events (each
+# event idles the queue for a few microseconds)
+TIMING_EVERY = 8
 
 
 def initial_config(rng, Nc, beta, k):
@@ -56,12 +59,20 @@ def fold_traffic(workload, precision):
 
 
 def roofline(stats0, stats1, precision, traffic=None):
-    flops = stats1["fold_flops"] - stats0["fold_flops"]
-    nbytes = stats1["fold_bytes"] - stats0["fold_bytes"]
-    secs = stats1["fold_seconds"] - stats0["fold_seconds"]
-    launches = stats1["fold_launches"] - stats0["fold_launches"]
-    if secs <= 0 or launches <= 0:
+    """Fold-kernel roofline over the timed region.  The algorithmic flops and
+    bytes cover every fold launch; the durations come from the sampled
+    launches (HIP events on a pseudo-random share of the windows), so the
+    per-launch averages of both are divided into each other."""
+    d = lambda k: stats1[k] - stats0[k]
+    timed = d("fold_launches")
+    total = d("windows_enqueued")
+    secs_timed = d("fold_seconds")
+    if secs_timed <= 0 or timed <= 0 or total <= 0:
         return None
+    launches = total
+    secs = secs_timed / timed * total        # estimated fold time over every launch
+    flops = d("fold_flops")
+    nbytes = d("fold_bytes")
     peak_tf = PEAK["fp64_mfma_TFs"] if precision == "fp64" else PEAK["fp32_mfma_TFs"]
     ai = flops / max(nbytes, 1.0)
     ridge = peak_tf * 1e12 / (PEAK["hbm_GBs"] * 1e9)
@@ -74,12 +85,22 @@ def roofline(stats0, stats1, precision, traffic=None):
         out = {"bound": "mfma", "achieved": achieved, "peak": peak_tf, "unit": "TFLOP/s",
                "frac": achieved / peak_tf}
     attainable = min(peak_tf, PEAK["hbm_GBs"] * 1e9 * ai / 1e12)
-    out.update({"traffic": traffic, "kernel": "k_fold", "launches": launches,
+    out.update({"traffic": traffic, "kernel": "k_fold", "launches": launches, "timed_launches": timed,
                 "avg_launch_us": secs / launches * 1e6, "flops_per_launch": flops / launches,
                 "bytes_per_launch": nbytes / launches, "arith_intensity": ai, "tflops": flops / secs / 1e12,
                 "frac_of_mfma_peak": flops / secs / 1e12 / peak_tf,
                 "attainable_tflops": attainable, "frac_of_attainable": flops / secs / 1e12 / attainable})
     return out
+
+
+def kernel_us(s0, s1):
+    """Average fold, accept-loop and whole-window durations of the timed windows."""
+    n = s1["fold_launches"] - s0["fold_launches"]
+    if n <= 0:
+        return None
+    return {k: (s1[f] - s0[f]) / n * 1e6 for k, f in
+            (("fold", "fold_seconds"), ("accept_loop", "accept_seconds"), ("window", "window_seconds"))} | \
+        {"timed_windows": n, "windows": s1["windows_enqueued"] - s0["windows_enqueued"]}
 
 
 def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None, walkers=1):
@@ -98,16 +119,12 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
         rng = np.random.default_rng(cfg["seed"] + 100 + seed_offset + i)
         w.set_config(*initial_config(rng, w.Ncs[i], cfg["beta"], cfg["k_init"]), walker=i)
     acc, aux = w.new_accumulator()
-    for _ in range(warmup):
-        w.sweep(1)
-        w.measure(acc, aux)
-    w.set_timing(True)
+    w.sweep_measure(warmup, acc, aux)
+    w.set_timing(TIMING_EVERY)
     torch.cuda.synchronize()
     s0 = w.stats()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        w.sweep(1)
-        w.measure(acc, aux)
+    w.sweep_measure(steps, acc, aux)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     s1 = w.stats()
@@ -122,9 +139,7 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
         "mean_order": sum(w.orders()) / walkers, "windows": windows, "walkers": walkers,
         "mean_fold_rank": (s1["flips_folded"] - s0["flips_folded"]) / max(windows, 1),
         "roofline": roofline(s0, s1, precision, fold_traffic(workload, precision)),
-        "kernel_seconds": {"fold": s1["fold_seconds"] - s0["fold_seconds"],
-                           "accept_loop": s1["accept_seconds"] - s0["accept_seconds"],
-                           "windows_total": s1["window_seconds"] - s0["window_seconds"]},
+        "kernel_us_per_window": kernel_us(s0, s1),
         "sign": s1["sign"], "refresh_max_drift": s1["max_drift"],
         "aborted_windows": s1["aborted_windows"] - s0["aborted_windows"],
     }
@@ -133,9 +148,7 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
         # figures come from eager sweeps right after the timed region
         w.set_graphs(False)
         r0 = w.stats()
-        for _ in range(min(steps, 30)):
-            w.sweep(1)
-            w.measure(acc, aux)
+        w.sweep_measure(min(steps, 30), acc, aux)
         torch.cuda.synchronize()
         res["roofline"] = roofline(r0, w.stats(), precision, fold_traffic(workload, precision))
         if res["roofline"]:
@@ -160,12 +173,10 @@ def run_batch(precision, steps, warmup, n_walkers=512):
     w.sweep(warmup)
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
-    w.set_timing(True)
+    w.set_timing(TIMING_EVERY)
     s0 = w.stats()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        w.sweep(1)
-        w.measure(acc, aux)
+    w.sweep_measure(steps, acc, aux)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     s1 = w.stats()
@@ -176,7 +187,8 @@ def run_batch(precision, steps, warmup, n_walkers=512):
            "proposals_per_s": (s1["proposals"] - s0["proposals"]) / dt,
            "order_min_mean_max": [min(orders), sum(orders) / len(orders), max(orders)],
            "mean_fold_rank": (s1["flips_folded"] - s0["flips_folded"]) / max(s1["windows"] - s0["windows"], 1),
-           "warmup_seconds": t_warm, "roofline": roofline(s0, s1, precision)}
+           "warmup_seconds": t_warm, "roofline": roofline(s0, s1, precision),
+           "kernel_us_per_window": kernel_us(s0, s1)}
     w.close()
     return res
 

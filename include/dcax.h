@@ -131,13 +131,15 @@ typedef struct {
   double sign;              /* sign of the current configuration */
   double fold_flops;        /* algorithmic flops of the rank-m folds, 2 k'^2 m per spin */
   double fold_bytes;        /* algorithmic bytes of the folds: N read and written once */
-  double fold_seconds;      /* summed fold kernel time (dcax_set_timing) */
-  int64_t fold_launches;    /* fold launches timed */
-  double accept_seconds;    /* summed accept-loop kernel time (dcax_set_timing) */
-  double window_seconds;    /* summed time of whole windows (dcax_set_timing) */
+  double fold_seconds;      /* fold kernel time summed over the timed windows (dcax_set_timing) */
+  int64_t fold_launches;    /* timed windows (one fold launch each) */
+  double accept_seconds;    /* accept-loop kernel time summed over the timed windows */
+  double window_seconds;    /* whole-window time summed over the timed windows */
   int64_t aborted_windows;  /* windows closed early by a carried removal */
   double last_drift;        /* drift of the last refresh inside dcax_sweep */
   double max_drift;         /* largest such drift */
+  int64_t windows_enqueued; /* windows launched while timing was on, timed or not
+                               (fold_launches / windows_enqueued is the sampled share) */
 } dcax_stats;
 
 /* Create a batch of n_walkers independent walkers (Markov chains; Sec. 3.1,
@@ -188,6 +190,14 @@ dcax_status dcax_refresh(dcax_walker w, double* drift_out);
  * The trace terms are the equal-time coefficient of G's 1/(i w)^2 tail. */
 dcax_status dcax_measure_G(dcax_walker w, double* acc_dev, double* aux_dev);
 
+/* The Monte Carlo loop with one measurement per sweep (the paper's
+ * sweeps-per-measurement = 1): n_sweeps times dcax_sweep(w, 1, NULL, 0,
+ * NULL) followed by dcax_measure_G(w, acc_dev, aux_dev), with no host
+ * round trip between a sweep and its measurement beyond the sweep's own
+ * completion check.  Same arguments, errors and accumulator layout as those
+ * two calls; the measurements are enqueued on the walker's stream. */
+dcax_status dcax_sweep_measure(dcax_walker w, int32_t n_sweeps, double* acc_dev, double* aux_dev);
+
 /* G(K, i w_n) = G0 - G0 <M> G0 / beta with <M> = acc / sign (Sec. 2.3), and
  * G(K, tau) on n_tau_out points tau_l = l beta / (n_tau_out - 1) (l = 0 is 0+,
  * the last point beta-) from the frequency data with the 1/(i w)^2 tail
@@ -231,8 +241,11 @@ dcax_status dcax_set_config(dcax_walker w, int32_t walker, const dcax_vertex* ho
 /* walker = -1 sums the counters over the batch (sign: walker 0's). */
 dcax_status dcax_get_stats(dcax_walker w, int32_t walker, dcax_stats* out);
 /* Time the fold and accept kernels and whole windows with HIP events on the
- * walker's stream (on != 0) or stop timing (on == 0).  Timings accumulate into
- * dcax_stats; they cost two events per timed launch. */
+ * walker's stream: on = n > 0 times every n-th window, on = 0 stops timing
+ * (on < 0: DCAX_E_INVAL).  The events ride on the kernels' own dispatches;
+ * a timed window still leaves the queue idle for a few microseconds per
+ * event, so sampling keeps the overhead out of throughput measurements.
+ * Timings accumulate into dcax_stats over the timed windows. */
 dcax_status dcax_set_timing(dcax_walker w, int32_t on);
 /* The G0(r, tau) table the walker uses, [Nc][n_tau], standard sign convention
  * G0 = -<T c c+>. */

@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_ext.h>
 #include "dcax_dev.h"
 #include "dcax_window.hip"
 #include "dcax_refresh.hip"
@@ -221,8 +222,13 @@ struct dcax_walker_s {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   bool capturing = false;
-  // live kernel timing (dcax_set_timing)
+  // the host copies of the control blocks match the device (nothing that
+  // changes a walker has been enqueued since the last sync_all)
+  bool fresh = false;
+  // live kernel timing (dcax_set_timing): every timing_every-th window
   bool timing = false;
+  int timing_every = 1;
+  long long win_seq = 0;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pend_fold, pend_accept, pend_window;
   double fold_s = 0.0, accept_s = 0.0, window_s = 0.0;
@@ -288,11 +294,21 @@ struct dcax_walker_s {
   void mark(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, hipEvent_t a, hipEvent_t b) {
     if (timing && a && b) v.push_back({a, b});
   }
-  hipEvent_t rec() {
-    if (!timing || capturing) return nullptr;
-    hipEvent_t e = ev();
-    if (e) (void)hipEventRecord(e, stream);
-    return e;
+  // An event for a timed launch: attached to the kernel's own dispatch
+  // (hipExtLaunchKernelGGL) rather than recorded as a separate stream
+  // command, which would idle the queue between kernels.
+  hipEvent_t tev(bool timed) { return timed ? ev() : nullptr; }
+  // whether the next window is timed: a pseudo-random 1/timing_every share
+  // (a fixed stride would always pick the same window of a sweep)
+  bool timed_window() {
+    if (!timing || capturing) return false;
+    ++win_seq;
+    if (timing_every == 1) return true;
+    unsigned long long x = (unsigned long long)win_seq * 0x9E3779B97F4A7C15ull;
+    x ^= x >> 31;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 29;
+    return x % (unsigned long long)timing_every == 0;
   }
   template <typename T>
   const View<T>* views(int first = 0) const {
@@ -365,20 +381,23 @@ dcax_status sync_all(dcax_walker w) {
       w->wk[i].latched = true;
     }
   }
+  w->fresh = true;
   return st;
 }
 
 template <typename T>
 void enqueue_window(dcax_walker w, int kb, bool replay) {
+  w->fresh = false;
+  const bool timed = w->timed_window();
   const View<T>* vs = w->views<T>();
   hipStream_t s = w->stream;
   const int W = w->W;
   const int ks = w->ks_max;
   const int kx = std::min(kb + ks, w->cap_max);
   const int kb1 = std::max(kb, 1);
-  hipEvent_t e_w0 = w->rec();
-  if (replay) hipLaunchKernelGGL(k_prep_replay<T>, dim3(1, 1, W), dim3(WG), 0, s, vs);
-  else hipLaunchKernelGGL(k_prep_rng<T>, dim3(1, 1, W), dim3(PW), 0, s, vs);
+  hipEvent_t e_w0 = w->tev(timed);
+  if (replay) hipExtLaunchKernelGGL(k_prep_replay<T>, dim3(1, 1, W), dim3(WG), 0, s, e_w0, nullptr, 0, vs);
+  else hipExtLaunchKernelGGL(k_prep_rng<T>, dim3(1, 1, W), dim3(PW), 0, s, e_w0, nullptr, 0, vs);
   const int ne = std::min(2 * ks, KS_MAX);   // elements: candidates, targets, second attempts
   hipLaunchKernelGGL(k_gather<T>, dim3(cdiv(kb1, WG), ne, W), dim3(WG), 0, s, vs);
   // few workgroups: 16 wavefronts each; large batches: 4
@@ -387,25 +406,24 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   else hipLaunchKernelGGL((k_cand_x<T, 4>), dim3(cdiv(kb1, 16), 2, W), dim3(256), 0, s, vs);
   if ((long long)ne * 2 * W < 4096) hipLaunchKernelGGL((k_gram<T, 16>), dim3(ne, 2, W), dim3(1024), 0, s, vs);
   else hipLaunchKernelGGL((k_gram<T, 4>), dim3(ne, 2, W), dim3(256), 0, s, vs);
-  hipEvent_t e_a0 = w->rec();
-  hipLaunchKernelGGL(k_accept<T>, dim3(1, 1, W), dim3(AW), 0, s, vs);
-  hipEvent_t e_a1 = w->rec();
+  hipEvent_t e_a0 = w->tev(timed), e_a1 = w->tev(timed);
+  hipExtLaunchKernelGGL(k_accept<T>, dim3(1, 1, W), dim3(AW), 0, s, e_a0, e_a1, 0, vs);
   w->mark(w->pend_accept, e_a0, e_a1);
   if (wide) hipLaunchKernelGGL((k_ygemm<T, 16>), dim3(cdiv(kb1, 16), 2, W), dim3(1024), 0, s, vs);
   else hipLaunchKernelGGL((k_ygemm<T, 4>), dim3(cdiv(kb1, 16), 2, W), dim3(256), 0, s, vs);
   hipLaunchKernelGGL(k_fold_prep<T>, dim3(cdiv(kx, 64), 2, W), dim3(WG), 0, s, vs);
-  hipEvent_t e_f0 = w->rec();
-  hipLaunchKernelGGL(k_fold<T>, dim3(cdiv(kx, 64), cdiv(kx, 64), 2 * W), dim3(WG), 0, s, vs);
-  hipEvent_t e_f1 = w->rec();
+  hipEvent_t e_f0 = w->tev(timed), e_f1 = w->tev(timed);
+  hipExtLaunchKernelGGL(k_fold<T>, dim3(cdiv(kx, 64), cdiv(kx, 64), 2 * W), dim3(WG), 0, s, e_f0, e_f1, 0, vs);
   w->mark(w->pend_fold, e_f0, e_f1);
-  hipLaunchKernelGGL(k_compact_move<T>, dim3(cdiv(kx, WG), 1, 2 * W), dim3(WG), 0, s, vs);
-  hipEvent_t e_w1 = w->rec();
+  hipEvent_t e_w1 = w->tev(timed);
+  hipExtLaunchKernelGGL(k_compact_move<T>, dim3(cdiv(kx, WG), 1, 2 * W), dim3(WG), 0, s, nullptr, e_w1, 0, vs);
   w->mark(w->pend_window, e_w0, e_w1);
 }
 
 // FP64 refresh of N for walkers [first, first + n); nothing is read back.
 template <typename T>
 void enqueue_refresh(dcax_walker w, int first, int n, int kmax, bool measure) {
+  w->fresh = false;
   const View<T>* vs = w->views<T>(first);
   hipStream_t s = w->stream;
   hipLaunchKernelGGL(k_refresh_begin<T>, dim3(1, 1, n), dim3(1), 0, s, vs);
@@ -457,6 +475,7 @@ void enqueue_measure(dcax_walker w, double* acc, double* aux) {
 
 // One sweep's kernels (sweep start plus nwin windows with growing bounds).
 void enqueue_sweep(dcax_walker w, int kb, int nwin) {
+  w->fresh = false;
   if (w->mixed) hipLaunchKernelGGL(k_begin_sweep<float>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<float>());
   else hipLaunchKernelGGL(k_begin_sweep<double>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<double>());
   for (int i = 0; i < nwin; ++i) {
@@ -470,6 +489,7 @@ void enqueue_sweep(dcax_walker w, int kb, int nwin) {
 // count).  Graphs run on the library's own stream, ordered after and before
 // the caller's stream by events.
 dcax_status launch_sweep_graph(dcax_walker w, int kb, int nwin) {
+  w->fresh = false;
   const int kq = std::min(w->mo_max, ((kb + 63) / 64) * 64);
   const auto key = std::make_pair(kq, nwin);
   auto it = w->graphs.find(key);
@@ -513,8 +533,13 @@ dcax_status launch_sweep_graph(dcax_walker w, int kb, int nwin) {
 }
 
 dcax_status sweep_rng(dcax_walker w, int n_sweeps) {
-  dcax_status st = sync_all(w);
-  if (st != DCAX_OK) return st;
+  // every call that changes a walker ends with a sync; only work that leaves
+  // the walkers alone (a measurement) may be in flight here
+  dcax_status st = DCAX_OK;
+  if (!w->fresh) {
+    st = sync_all(w);
+    if (st != DCAX_OK) return st;
+  }
   for (int sw = 0; sw < n_sweeps; ++sw) {
     int nwin = 1, kb = 0;
     for (int i = 0; i < w->W; ++i) {
@@ -898,6 +923,7 @@ dcax_status dcax_set_config(dcax_walker w, int32_t walker, const dcax_vertex* v,
   h.sign = 1.0;
   h.carry_id = -1;
   h.sweep_len = x.p.sweep_length;
+  w->fresh = false;
   HIPCHK(hipMemcpyAsync(w->ctl_all + walker, &h, sizeof(Ctl), hipMemcpyHostToDevice, w->stream));
   if (w->mixed) {
     enqueue_refresh<float>(w, walker, 1, k, false);
@@ -959,6 +985,21 @@ dcax_status dcax_sweep(dcax_walker w, int32_t n_sweeps, const dcax_proposal* rep
   }
   if (n_sweeps < 0) return fail(DCAX_E_INVAL, "n_sweeps < 0");
   return sweep_rng(w, n_sweeps);
+}
+
+dcax_status dcax_sweep_measure(dcax_walker w, int32_t n_sweeps, double* acc_dev, double* aux_dev) {
+  dcax_status st = check_latched(w);
+  if (st != DCAX_OK) return st;
+  if (n_sweeps < 0) return fail(DCAX_E_INVAL, "n_sweeps < 0");
+  if (!aux_dev || (!acc_dev && w->nf_max > 0)) return fail(DCAX_E_INVAL, "NULL accumulator");
+  for (int i = 0; i < n_sweeps; ++i) {
+    st = sweep_rng(w, 1);
+    if (st != DCAX_OK) return st;
+    if (w->mixed) enqueue_measure<float>(w, acc_dev, aux_dev);
+    else enqueue_measure<double>(w, acc_dev, aux_dev);
+    HIPCHK(hipGetLastError());
+  }
+  return DCAX_OK;
 }
 
 dcax_status dcax_refresh(dcax_walker w, double* drift_out) {
@@ -1090,6 +1131,7 @@ dcax_status dcax_get_stats(dcax_walker w, int32_t walker, dcax_stats* out) {
   out->sweeps = w->sweeps_done;
   out->fold_seconds = w->fold_s;
   out->fold_launches = w->fold_launches;
+  out->windows_enqueued = w->win_seq;
   out->accept_seconds = w->accept_s;
   out->window_seconds = w->window_s;
   out->last_drift = w->last_drift;
@@ -1159,9 +1201,11 @@ dcax_status dcax_set_graphs(dcax_walker w, int32_t on) {
 
 dcax_status dcax_set_timing(dcax_walker w, int32_t on) {
   if (!w) return fail(DCAX_E_INVAL, "walker is NULL");
+  if (on < 0) return fail(DCAX_E_INVAL, "on must be >= 0");
   dcax_status st = sync_all(w);  // drains pending events
   if (w->timing != (on != 0)) w->clear_graphs();
   w->timing = on != 0;
+  w->timing_every = on > 0 ? on : 1;
   return st;
 }
 

@@ -58,7 +58,8 @@ class Stats(ctypes.Structure):
                 ("fold_bytes", ctypes.c_double), ("fold_seconds", ctypes.c_double),
                 ("fold_launches", ctypes.c_int64), ("accept_seconds", ctypes.c_double),
                 ("window_seconds", ctypes.c_double), ("aborted_windows", ctypes.c_int64),
-                ("last_drift", ctypes.c_double), ("max_drift", ctypes.c_double)]
+                ("last_drift", ctypes.c_double), ("max_drift", ctypes.c_double),
+                ("windows_enqueued", ctypes.c_int64)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -76,6 +77,7 @@ VERTEX_DTYPE = np.dtype([("id", np.int64), ("site", np.int32), ("aux_spin", np.i
 
 # exported symbols, in the order include/dcax.h declares them
 EXPORTS = ("dcax_walker_create", "dcax_walker_destroy", "dcax_sweep", "dcax_refresh", "dcax_measure_G",
+           "dcax_sweep_measure",
            "dcax_finalize_G", "dcax_get_order", "dcax_copy_N", "dcax_get_config", "dcax_set_config",
            "dcax_set_submatrix_k", "dcax_autotune", "dcax_set_graphs", "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table",
            "dcax_cluster", "dcax_last_error")
@@ -99,6 +101,7 @@ def load():
         "dcax_sweep": [vp, ctypes.c_int32, vp, ctypes.c_int64, vp],
         "dcax_refresh": [vp, P(ctypes.c_double)],
         "dcax_measure_G": [vp, vp, vp],
+        "dcax_sweep_measure": [vp, ctypes.c_int32, vp, vp],
         "dcax_finalize_G": [vp, vp, vp, vp, ctypes.c_int32, vp],
         "dcax_get_order": [vp, ctypes.c_int32, P(ctypes.c_int32)],
         "dcax_copy_N": [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64, vp],
@@ -280,7 +283,8 @@ class Walker:
         _check(load().dcax_set_graphs(self._h, 1 if on else 0))
 
     def set_timing(self, on=True):
-        _check(load().dcax_set_timing(self._h, 1 if on else 0))
+        """on: True / 1 times every window, n > 1 a pseudo-random 1/n of them, 0 / False stops."""
+        _check(load().dcax_set_timing(self._h, int(on)))
 
     def g0_table(self, walker=0):
         p = self.plist[walker]
@@ -307,6 +311,11 @@ class Walker:
 
     def measure(self, acc, aux):
         _check(load().dcax_measure_G(self._h, ctypes.c_void_p(acc.data_ptr()), ctypes.c_void_p(aux.data_ptr())))
+
+    def sweep_measure(self, n_sweeps, acc, aux):
+        """n_sweeps generator sweeps, each followed by a measurement into (acc, aux)."""
+        _check(load().dcax_sweep_measure(self._h, int(n_sweeps), ctypes.c_void_p(acc.data_ptr()),
+                                         ctypes.c_void_p(aux.data_ptr())))
 
     def finalize(self, acc, aux, n_tau_out=0):
         torch = self._torch
