@@ -160,7 +160,9 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
 
 def run_batch(precision, steps, warmup, n_walkers=512):
     """The batched workload: n_walkers walkers of uneven cluster size, U and
-    beta in one handle (one launch per kernel covers all of them)."""
+    beta in one handle (one launch per kernel covers all of them), free
+    running (dcax_run_rounds): a step is one round of four windows per
+    walker plus the measurements of the walkers whose sweep ended in it."""
     import torch
     from paper_1901_01047_amd import dcax
     from paper_1901_01047_amd.workloads import batch_configs
@@ -176,7 +178,7 @@ def run_batch(precision, steps, warmup, n_walkers=512):
     w.set_timing(TIMING_EVERY)
     s0 = w.stats()
     t0 = time.perf_counter()
-    w.sweep_measure(steps, acc, aux)
+    w.run_rounds(steps, acc, aux)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     s1 = w.stats()

@@ -191,12 +191,24 @@ dcax_status dcax_refresh(dcax_walker w, double* drift_out);
 dcax_status dcax_measure_G(dcax_walker w, double* acc_dev, double* aux_dev);
 
 /* The Monte Carlo loop with one measurement per sweep (the paper's
- * sweeps-per-measurement = 1): n_sweeps times dcax_sweep(w, 1, NULL, 0,
- * NULL) followed by dcax_measure_G(w, acc_dev, aux_dev), with no host
- * round trip between a sweep and its measurement beyond the sweep's own
- * completion check.  Same arguments, errors and accumulator layout as those
- * two calls; the measurements are enqueued on the walker's stream. */
+ * sweeps-per-measurement = 1): the result of n_sweeps times dcax_sweep(w, 1,
+ * NULL, 0, NULL) followed by dcax_measure_G(w, acc_dev, aux_dev), bit for
+ * bit, except that refreshes fall at other sweeps.  The sweeps are scheduled
+ * on the device: each walker begins its next sweep when its previous one has
+ * been measured, without host round trips; the call returns when every
+ * walker has made n_sweeps sweeps.  Same errors and accumulator layout as
+ * those two calls. */
 dcax_status dcax_sweep_measure(dcax_walker w, int32_t n_sweeps, double* acc_dev, double* aux_dev);
+
+/* Free-running batch (Sec. 3.1: walkers of a process run independently):
+ * every walker sweeps continuously, with a measurement after each of its
+ * sweeps, for n_rounds rounds of windows (four windows per round for a
+ * batch, one sweep's worth for a single walker), then finishes the sweep it
+ * is in.  Walkers with short sweeps therefore make more sweeps than long
+ * ones instead of waiting for them; each walker's chain, sweep boundaries
+ * and measurements are exactly those of dcax_sweep_measure.  Same
+ * accumulators and errors as dcax_measure_G. */
+dcax_status dcax_run_rounds(dcax_walker w, int32_t n_rounds, double* acc_dev, double* aux_dev);
 
 /* G(K, i w_n) = G0 - G0 <M> G0 / beta with <M> = acc / sign (Sec. 2.3), and
  * G(K, tau) on n_tau_out points tau_l = l beta / (n_tau_out - 1) (l = 0 is 0+,

@@ -139,10 +139,7 @@ __global__ void k_set_cursor(const View<T>* __restrict__ vs, long long pos, long
 // A sweep is max(k, 1) proposals rounded up to a multiple of k_s, with k the
 // order at the sweep's start.
 template <typename T>
-__global__ void k_begin_sweep(const View<T>* __restrict__ vs) {
-  const View<T>& w = vs[blockIdx.z];
-  Ctl* c = w.ctl;
-  if (c->status != 0) return;
+__device__ void begin_sweep(const View<T>& w, Ctl* c) {
   long long L = c->sweep_len;
   if (L == 0) {
     // warm-up: the length follows the order; the second half's mean order
@@ -159,6 +156,46 @@ __global__ void k_begin_sweep(const View<T>* __restrict__ vs) {
   }
   c->end = c->pos + ((L + w.ks - 1) / w.ks) * w.ks;
   c->n_sweeps += 1;
+}
+
+template <typename T>
+__global__ void k_begin_sweep(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
+  Ctl* c = w.ctl;
+  if (c->status != 0) return;
+  begin_sweep(w, c);
+}
+
+// Device-scheduled sweeps: each walker begins its next sweep as soon as the
+// previous one has ended and been measured, independently of the others.
+template <typename T>
+__global__ void k_set_rounds(const View<T>* __restrict__ vs, long long n) {
+  Ctl* c = vs[blockIdx.z].ctl;
+  c->sweeps_left = n;
+  c->meas_due = 0;
+}
+
+// no walker begins another sweep (a running one still ends and is measured)
+template <typename T>
+__global__ void k_stop_rounds(const View<T>* __restrict__ vs) {
+  vs[blockIdx.z].ctl->sweeps_left = 0;
+}
+
+template <typename T>
+__global__ void k_round_begin(const View<T>* __restrict__ vs) {
+  const View<T>& w = vs[blockIdx.z];
+  Ctl* c = w.ctl;
+  if (c->status != 0 || c->pos < c->end || c->meas_due || c->sweeps_left <= 0) return;
+  begin_sweep(w, c);
+  c->sweeps_left -= 1;
+  c->meas_due = 1;
+}
+
+// closes the gated measurement of the walkers it covered
+template <typename T>
+__global__ void k_meas_done(const View<T>* __restrict__ vs) {
+  Ctl* c = vs[blockIdx.z].ctl;
+  if (!meas_skip(c, 1)) c->meas_due = 0;
 }
 
 template <typename T>
@@ -225,6 +262,7 @@ struct dcax_walker_s {
   // the host copies of the control blocks match the device (nothing that
   // changes a walker has been enqueued since the last sync_all)
   bool fresh = false;
+  long long rounds_done = 0;   // rounds of device-scheduled sweeps
   // live kernel timing (dcax_set_timing): every timing_every-th window
   bool timing = false;
   int timing_every = 1;
@@ -385,6 +423,17 @@ dcax_status sync_all(dcax_walker w) {
   return st;
 }
 
+// Workgroups per walker and spin along a kernel's tile dimension.  The
+// kernels stride over their tiles by the device-side order, so any count
+// covers the work; the tiles of one walker are latency-bound chains, so a
+// launch keeps all of them in flight (idle workgroups of small walkers cost
+// little) up to a ceiling on the launch size.
+static int spread(int tiles, int W, int units) {
+  constexpr long long budget = 1ll << 21;   // workgroups per launch
+  const long long g = std::max<long long>(1, budget / ((long long)W * units));
+  return (int)std::max<long long>(1, std::min<long long>(tiles, g));
+}
+
 template <typename T>
 void enqueue_window(dcax_walker w, int kb, bool replay) {
   w->fresh = false;
@@ -399,24 +448,29 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   if (replay) hipExtLaunchKernelGGL(k_prep_replay<T>, dim3(1, 1, W), dim3(WG), 0, s, e_w0, nullptr, 0, vs);
   else hipExtLaunchKernelGGL(k_prep_rng<T>, dim3(1, 1, W), dim3(PW), 0, s, e_w0, nullptr, 0, vs);
   const int ne = std::min(2 * ks, KS_MAX);   // elements: candidates, targets, second attempts
-  hipLaunchKernelGGL(k_gather<T>, dim3(cdiv(kb1, WG), ne, W), dim3(WG), 0, s, vs);
+  const int gx = spread(cdiv(kb1, WG), W, 1);
+  hipLaunchKernelGGL(k_gather<T>, dim3(gx, spread(ne, W, gx), W), dim3(WG), 0, s, vs);
   // few workgroups: 16 wavefronts each; large batches: 4
-  const bool wide = (long long)cdiv(kb1, 16) * 2 * W < 4096;
-  if (wide) hipLaunchKernelGGL((k_cand_x<T, 16>), dim3(cdiv(kb1, 16), 2, W), dim3(1024), 0, s, vs);
-  else hipLaunchKernelGGL((k_cand_x<T, 4>), dim3(cdiv(kb1, 16), 2, W), dim3(256), 0, s, vs);
-  if ((long long)ne * 2 * W < 4096) hipLaunchKernelGGL((k_gram<T, 16>), dim3(ne, 2, W), dim3(1024), 0, s, vs);
-  else hipLaunchKernelGGL((k_gram<T, 4>), dim3(ne, 2, W), dim3(256), 0, s, vs);
+  const int g16 = spread(cdiv(kb1, 16), W, 2);
+  const bool wide = (long long)g16 * 2 * W < 4096;
+  if (wide) hipLaunchKernelGGL((k_cand_x<T, 16>), dim3(g16, 2, W), dim3(1024), 0, s, vs);
+  else hipLaunchKernelGGL((k_cand_x<T, 4>), dim3(g16, 2, W), dim3(256), 0, s, vs);
+  const int gr = spread(ne, W, 2);
+  if ((long long)gr * 2 * W < 4096) hipLaunchKernelGGL((k_gram<T, 16>), dim3(gr, 2, W), dim3(1024), 0, s, vs);
+  else hipLaunchKernelGGL((k_gram<T, 4>), dim3(gr, 2, W), dim3(256), 0, s, vs);
   hipEvent_t e_a0 = w->tev(timed), e_a1 = w->tev(timed);
   hipExtLaunchKernelGGL(k_accept<T>, dim3(1, 1, W), dim3(AW), 0, s, e_a0, e_a1, 0, vs);
   w->mark(w->pend_accept, e_a0, e_a1);
-  if (wide) hipLaunchKernelGGL((k_ygemm<T, 16>), dim3(cdiv(kb1, 16), 2, W), dim3(1024), 0, s, vs);
-  else hipLaunchKernelGGL((k_ygemm<T, 4>), dim3(cdiv(kb1, 16), 2, W), dim3(256), 0, s, vs);
-  hipLaunchKernelGGL(k_fold_prep<T>, dim3(cdiv(kx, 64), 2, W), dim3(WG), 0, s, vs);
+  if (wide) hipLaunchKernelGGL((k_ygemm<T, 16>), dim3(g16, 2, W), dim3(1024), 0, s, vs);
+  else hipLaunchKernelGGL((k_ygemm<T, 4>), dim3(g16, 2, W), dim3(256), 0, s, vs);
+  hipLaunchKernelGGL(k_fold_prep<T>, dim3(spread(cdiv(kx, 64), W, 2), 2, W), dim3(WG), 0, s, vs);
   hipEvent_t e_f0 = w->tev(timed), e_f1 = w->tev(timed);
-  hipExtLaunchKernelGGL(k_fold<T>, dim3(cdiv(kx, 64), cdiv(kx, 64), 2 * W), dim3(WG), 0, s, e_f0, e_f1, 0, vs);
+  const int ft = cdiv(kx, 64);
+  hipExtLaunchKernelGGL(k_fold<T>, dim3(spread(ft * ft, W, 2), 1, 2 * W), dim3(WG), 0, s, e_f0, e_f1, 0, vs);
   w->mark(w->pend_fold, e_f0, e_f1);
   hipEvent_t e_w1 = w->tev(timed);
-  hipExtLaunchKernelGGL(k_compact_move<T>, dim3(cdiv(kx, WG), 1, 2 * W), dim3(WG), 0, s, nullptr, e_w1, 0, vs);
+  hipExtLaunchKernelGGL(k_compact_move<T>, dim3(spread(cdiv(kx, WG), W, 2), 1, 2 * W), dim3(WG), 0, s, nullptr, e_w1,
+                        0, vs);
   w->mark(w->pend_window, e_w0, e_w1);
 }
 
@@ -455,22 +509,28 @@ dcax_status refresh_all(dcax_walker w, double* drift) {
 }
 
 template <typename T>
-void enqueue_measure(dcax_walker w, double* acc, double* aux) {
+void enqueue_measure(dcax_walker w, double* acc, double* aux, int gated) {
   const View<T>* vs = w->views<T>();
   hipStream_t s = w->stream;
   const int W = w->W;
-  hipLaunchKernelGGL(k_meas_diag<T>, dim3(2, 1, W), dim3(WG), 0, s, vs, aux);
+  hipLaunchKernelGGL(k_meas_diag<T>, dim3(2, 1, W), dim3(WG), 0, s, vs, aux, gated);
   const int nf = w->nf_max;
-  if (nf == 0) return;
+  if (nf == 0) {
+    if (gated) hipLaunchKernelGGL(k_meas_done<T>, dim3(1, 1, W), dim3(1), 0, s, vs);
+    return;
+  }
   const int ncm = w->nc_max;
   const int kb = std::min(w->kpad_max, w->kmax_host() + 16 * ncm);
   const int kb1 = std::max(kb, 1);
-  hipLaunchKernelGGL(k_meas_sort<T>, dim3(1, 1, W), dim3(WG), 0, s, vs);
-  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cdiv(kb1, WG), cdiv(kb1, MCOLS), W), dim3(WG), 0, s, vs);
-  hipLaunchKernelGGL(k_meas_phase<T>, dim3(cdiv(nf, WG), cdiv(kb1, MCOLS), W), dim3(WG), 0, s, vs);
-  const int groups = cdiv(ncm * ncm, (WG / 64) * MPAIRS);
-  hipLaunchKernelGGL(k_meas_block<T>, dim3(2 * groups, cdiv(nf, 16), W), dim3(WG), 0, s, vs, ncm);
-  hipLaunchKernelGGL(k_meas_K<T>, dim3(cdiv(nf, WG), ncm, 2 * W), dim3(WG), 0, s, vs, acc);
+  hipLaunchKernelGGL(k_meas_sort<T>, dim3(1, 1, W), dim3(WG), 0, s, vs, gated);
+  const int cx = spread(cdiv(kb1, WG), W, 1);
+  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cx, spread(cdiv(kb1, MCOLS), W, cx), W), dim3(WG), 0, s, vs, gated);
+  const int px = cdiv(nf, WG);
+  hipLaunchKernelGGL(k_meas_phase<T>, dim3(px, spread(cdiv(kb1, MCOLS), W, px), W), dim3(WG), 0, s, vs, gated);
+  const int groups = cdiv(ncm * ncm, (WG / 64) * MPAIRS), fy = cdiv(nf, 16);
+  hipLaunchKernelGGL(k_meas_block<T>, dim3(2 * spread(groups, W, 2 * fy), fy, W), dim3(WG), 0, s, vs, gated);
+  hipLaunchKernelGGL(k_meas_K<T>, dim3(px, spread(ncm, W, 2 * px), 2 * W), dim3(WG), 0, s, vs, acc, gated);
+  if (gated) hipLaunchKernelGGL(k_meas_done<T>, dim3(1, 1, W), dim3(1), 0, s, vs);
 }
 
 // One sweep's kernels (sweep start plus nwin windows with growing bounds).
@@ -760,6 +820,88 @@ dcax_status create_walkers(dcax_walker w) {
 }
 
 // Replay buffers are shared by the views; (re)point them after a reallocation.
+// One round of device-scheduled sweeps: walkers between sweeps begin their
+// next one, nwin windows run, and the walkers whose sweep has ended are
+// measured (gated measurement).
+template <typename T>
+void enqueue_round(dcax_walker w, int kb, int nwin, double* acc, double* aux) {
+  w->fresh = false;
+  hipLaunchKernelGGL(k_round_begin<T>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<T>());
+  for (int i = 0; i < nwin; ++i) enqueue_window<T>(w, kb, false);
+  enqueue_measure<T>(w, acc, aux, 1);
+}
+
+// Sweeps of every walker, each followed by its measurement, scheduled on the
+// device: a walker starts its next sweep as soon as the previous one has been
+// measured, so walkers of different sweep lengths in one batch do not wait
+// for the longest.  With free_rounds == 0 every walker makes n sweeps; with
+// free_rounds > 0 every walker sweeps for that many rounds and then finishes
+// the sweep it is in (short walkers make more sweeps than long ones).
+// Kernel grids follow the order seen at the last sync (the kernels stride
+// over the device-side order); the host syncs only to refresh, and at the
+// end to check that every walker has finished (rounds lost to windows closed
+// early are made up).
+dcax_status sweep_rounds(dcax_walker w, int n, double* acc, double* aux, long long free_rounds = 0) {
+  dcax_status st = DCAX_OK;
+  if (!w->fresh) {
+    st = sync_all(w);
+    if (st != DCAX_OK) return st;
+  }
+  if (n == 0 && free_rounds == 0) return DCAX_OK;
+  w->fresh = false;
+  const long long each = free_rounds > 0 ? (1ll << 60) : (long long)n;
+  if (w->mixed) hipLaunchKernelGGL(k_set_rounds<float>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<float>(), each);
+  else hipLaunchKernelGGL(k_set_rounds<double>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<double>(), each);
+  // windows per sweep of each walker; a single walker runs one sweep per
+  // round, a batch ROUND_WINDOWS windows per round
+  long long nw_max = 1, nw_sum = 0;
+  for (int i = 0; i < w->W; ++i) {
+    const auto& x = w->wk[i];
+    const long long L = w->h_ctl[i].sweep_len > 0 ? w->h_ctl[i].sweep_len : std::max(x.k_host, 1);
+    const long long nw = std::max<long long>(1, (L + x.ks - 1) / x.ks);
+    nw_max = std::max(nw_max, nw);
+    nw_sum += nw;
+  }
+  constexpr int ROUND_WINDOWS = 4;
+  const int R = (w->W == 1) ? (int)std::min<long long>(nw_max, 1 << 20) : (int)std::min<long long>(nw_max, ROUND_WINDOWS);
+  const long long rounds_per_sweep = (nw_max + R - 1) / R;
+  // refresh every refresh_every sweeps of the average walker
+  const int re = w->wk[0].p.refresh_every;
+  const long long nw_mean = std::max<long long>(1, (nw_sum + w->W - 1) / w->W);
+  const long long refresh_rounds = re > 0 ? std::max<long long>(1, re * ((nw_mean + R - 1) / R)) : 0;
+  long long planned = free_rounds > 0 ? free_rounds : (long long)n * rounds_per_sweep;
+  for (int pass = 0;; ++pass) {
+    if (pass > 64) return fail(DCAX_E_STATE, "device-scheduled sweeps made no progress");
+    const int kb = std::min(w->mo_max, w->kmax_host() + 2 * w->ks_max);
+    for (long long r = 0; r < planned; ++r) {
+      if (w->mixed) enqueue_round<float>(w, kb, R, acc, aux);
+      else enqueue_round<double>(w, kb, R, acc, aux);
+      HIPCHK(hipGetLastError());
+      ++w->rounds_done;
+      if (refresh_rounds > 0 && w->rounds_done % refresh_rounds == 0) {
+        double d = 0.0;
+        st = refresh_all(w, &d);
+        if (st != DCAX_OK) return st;
+        w->last_drift = d;
+        w->max_drift = std::max(w->max_drift, d);
+      }
+    }
+    if (free_rounds > 0 && pass == 0) {
+      if (w->mixed) hipLaunchKernelGGL(k_stop_rounds<float>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<float>());
+      else hipLaunchKernelGGL(k_stop_rounds<double>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<double>());
+    }
+    st = sync_all(w);
+    if (st != DCAX_OK) return st;
+    long long left = 0;
+    for (const Ctl& h : w->h_ctl)
+      left = std::max(left, h.sweeps_left + ((h.meas_due || h.pos < h.end) ? 1 : 0));
+    if (left == 0) break;
+    planned = left * rounds_per_sweep;
+  }
+  if (free_rounds == 0) w->sweeps_done += n;
+  return DCAX_OK;
+}
+
 template <typename T>
 dcax_status repoint_replay(dcax_walker w) {
   std::vector<View<T>> hv(w->W);
@@ -992,14 +1134,27 @@ dcax_status dcax_sweep_measure(dcax_walker w, int32_t n_sweeps, double* acc_dev,
   if (st != DCAX_OK) return st;
   if (n_sweeps < 0) return fail(DCAX_E_INVAL, "n_sweeps < 0");
   if (!aux_dev || (!acc_dev && w->nf_max > 0)) return fail(DCAX_E_INVAL, "NULL accumulator");
-  for (int i = 0; i < n_sweeps; ++i) {
-    st = sweep_rng(w, 1);
-    if (st != DCAX_OK) return st;
-    if (w->mixed) enqueue_measure<float>(w, acc_dev, aux_dev);
-    else enqueue_measure<double>(w, acc_dev, aux_dev);
-    HIPCHK(hipGetLastError());
+  if (w->use_graphs) {
+    // captured sweeps: one sweep, then its measurement, at a time
+    for (int i = 0; i < n_sweeps; ++i) {
+      st = sweep_rng(w, 1);
+      if (st != DCAX_OK) return st;
+      if (w->mixed) enqueue_measure<float>(w, acc_dev, aux_dev, 0);
+      else enqueue_measure<double>(w, acc_dev, aux_dev, 0);
+      HIPCHK(hipGetLastError());
+    }
+    return DCAX_OK;
   }
-  return DCAX_OK;
+  return sweep_rounds(w, n_sweeps, acc_dev, aux_dev);
+}
+
+dcax_status dcax_run_rounds(dcax_walker w, int32_t n_rounds, double* acc_dev, double* aux_dev) {
+  dcax_status st = check_latched(w);
+  if (st != DCAX_OK) return st;
+  if (n_rounds < 0) return fail(DCAX_E_INVAL, "n_rounds < 0");
+  if (!aux_dev || (!acc_dev && w->nf_max > 0)) return fail(DCAX_E_INVAL, "NULL accumulator");
+  if (n_rounds == 0) return DCAX_OK;
+  return sweep_rounds(w, 0, acc_dev, aux_dev, n_rounds);
 }
 
 dcax_status dcax_refresh(dcax_walker w, double* drift_out) {
@@ -1012,8 +1167,8 @@ dcax_status dcax_measure_G(dcax_walker w, double* acc_dev, double* aux_dev) {
   dcax_status st = check_latched(w);
   if (st != DCAX_OK) return st;
   if (!aux_dev || (!acc_dev && w->nf_max > 0)) return fail(DCAX_E_INVAL, "NULL accumulator");
-  if (w->mixed) enqueue_measure<float>(w, acc_dev, aux_dev);
-  else enqueue_measure<double>(w, acc_dev, aux_dev);
+  if (w->mixed) enqueue_measure<float>(w, acc_dev, aux_dev, 0);
+  else enqueue_measure<double>(w, acc_dev, aux_dev, 0);
   HIPCHK(hipGetLastError());
   return DCAX_OK;
 }

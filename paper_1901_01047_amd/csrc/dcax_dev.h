@@ -46,6 +46,11 @@ struct Ctl {
   long long sweep_len; // frozen proposals per sweep before rounding to k_s, 0 while warming up
   double warm_sum;     // sum of the order at sweep starts over the warm-up's second half
   long long warm_n;    // number of such sweeps
+  // sweeps scheduled on the device (dcax_sweep_measure): sweeps still to
+  // begin, and whether the finished sweep still awaits its measurement
+  long long sweeps_left;
+  int meas_due;
+  int pad_;
 };
 
 struct WinProp {      // one proposal of the current window
@@ -131,6 +136,12 @@ struct View {
 
 // ---------------------------------------------------------------- helpers
 __device__ inline void latch(Ctl* c, int code) { atomicCAS(&c->status, 0, code); }
+
+// A gated measurement covers the walkers whose sweep has ended and not yet
+// been measured (device-scheduled sweeps); an ungated one covers all.
+__device__ inline bool meas_skip(const Ctl* c, int gated) {
+  return gated && !(c->status == 0 && c->meas_due && c->pos >= c->end);
+}
 
 __device__ inline int s01(int s) { return s > 0 ? 0 : 1; }
 

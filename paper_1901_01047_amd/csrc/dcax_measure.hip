@@ -19,8 +19,9 @@ namespace dcax {
 // original order (stable).
 constexpr int SORT_MAX = 32768 + 128;
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_sort(const View<T>* __restrict__ vs) {
+__global__ void __launch_bounds__(WG) k_meas_sort(const View<T>* __restrict__ vs, int gated) {
   const View<T>& w = vs[blockIdx.z];
+  if (meas_skip(w.ctl, gated)) return;
   const auto order = gp(w.m_order);
   const auto off = gp(w.m_off);
   const auto v_site = gp(w.v_site);
@@ -58,12 +59,13 @@ __global__ void __launch_bounds__(WG) k_meas_sort(const View<T>* __restrict__ vs
   }
 }
 
-// Ms[i'][j'] = (e^{V_i} - 1) N[i][j] in sorted order (zero on padding), 16
-// sorted columns per workgroup.
+// Ms[i'][j'] = (e^{V_i} - 1) N[i][j] in sorted order (zero on padding), in
+// groups of 16 sorted columns (grid-strided over blockIdx.y, rows over x).
 constexpr int MCOLS = 16;
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_copy(const View<T>* __restrict__ vs) {
+__global__ void __launch_bounds__(WG) k_meas_copy(const View<T>* __restrict__ vs, int gated) {
   const View<T>& w = vs[blockIdx.z];
+  if (meas_skip(w.ctl, gated)) return;
   const auto order = gp(w.m_order);
   const auto off = gp(w.m_off);
   const auto Ms0 = gp(w.m_Ms[0]);
@@ -72,33 +74,35 @@ __global__ void __launch_bounds__(WG) k_meas_copy(const View<T>* __restrict__ vs
   const auto N1 = gp(w.N[1]);
   const int ldm = w.kpad_cap;
   const int kpad = off[w.Nc];
-  const int ip = blockIdx.x * WG + threadIdx.x;
-  if (ip >= kpad || (int)blockIdx.y * MCOLS >= kpad) return;
-  const int i = order[ip];
-  double f0 = 0.0, f1 = 0.0;
-  if (i >= 0) {
-    const int si = s01(w.v_s[i]);
-    f0 = w.ev[0][si] - 1.0;
-    f1 = w.ev[1][si] - 1.0;
-  }
-  for (int jp = blockIdx.y * MCOLS; jp < (int)(blockIdx.y + 1) * MCOLS && jp < kpad; ++jp) {
-    const int j = order[jp];
-    T v0 = 0, v1 = 0;
-    if (i >= 0 && j >= 0) {
-      const size_t o = i + (size_t)j * w.ld;
-      v0 = (T)(f0 * (double)N0[o]);
-      v1 = (T)(f1 * (double)N1[o]);
+  for (int ip = blockIdx.x * WG + threadIdx.x; ip < kpad; ip += gridDim.x * WG) {
+    const int i = order[ip];
+    double f0 = 0.0, f1 = 0.0;
+    if (i >= 0) {
+      const int si = s01(w.v_s[i]);
+      f0 = w.ev[0][si] - 1.0;
+      f1 = w.ev[1][si] - 1.0;
     }
-    Ms0[ip + (size_t)jp * ldm] = v0;
-    Ms1[ip + (size_t)jp * ldm] = v1;
+    for (int j0 = blockIdx.y * MCOLS; j0 < kpad; j0 += gridDim.y * MCOLS)
+      for (int jp = j0; jp < j0 + MCOLS && jp < kpad; ++jp) {
+        const int j = order[jp];
+        T v0 = 0, v1 = 0;
+        if (i >= 0 && j >= 0) {
+          const size_t o = i + (size_t)j * w.ld;
+          v0 = (T)(f0 * (double)N0[o]);
+          v1 = (T)(f1 * (double)N1[o]);
+        }
+        Ms0[ip + (size_t)jp * ldm] = v0;
+        Ms1[ip + (size_t)jp * ldm] = v1;
+      }
   }
 }
 
-// Phase table E[j'][n] = e^{-i w_n tau_j} in sorted order, 16 rows per
-// workgroup.
+// Phase table E[j'][n] = e^{-i w_n tau_j} in sorted order, in groups of 16
+// rows (grid-strided over blockIdx.y).
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_phase(const View<T>* __restrict__ vs) {
+__global__ void __launch_bounds__(WG) k_meas_phase(const View<T>* __restrict__ vs, int gated) {
   const View<T>& w = vs[blockIdx.z];
+  if (meas_skip(w.ctl, gated)) return;
   const auto order = gp(w.m_order);
   const auto off = gp(w.m_off);
   const auto E = gp(w.m_E);
@@ -107,25 +111,27 @@ __global__ void __launch_bounds__(WG) k_meas_phase(const View<T>* __restrict__ v
   const int n = blockIdx.x * WG + threadIdx.x;
   if (n >= n_freq) return;
   const double wn = (2.0 * n + 1.0) * M_PI / w.beta;
-  for (int jp = blockIdx.y * MCOLS; jp < (int)(blockIdx.y + 1) * MCOLS && jp < kpad; ++jp) {
-    const int j = order[jp];
-    double c = 0.0, s = 0.0;
-    if (j >= 0) sincos(wn * w.v_tau[j], &s, &c);
-    E[2 * ((size_t)jp * n_freq + n)] = (T)c;
-    E[2 * ((size_t)jp * n_freq + n) + 1] = (T)(-s);
-  }
+  for (int j0 = blockIdx.y * MCOLS; j0 < kpad; j0 += gridDim.y * MCOLS)
+    for (int jp = j0; jp < j0 + MCOLS && jp < kpad; ++jp) {
+      const int j = order[jp];
+      double c = 0.0, s = 0.0;
+      if (j >= 0) sincos(wn * w.v_tau[j], &s, &c);
+      E[2 * ((size_t)jp * n_freq + n)] = (T)c;
+      E[2 * ((size_t)jp * n_freq + n) + 1] = (T)(-s);
+    }
 }
 
 // For each pair of sites (a, b), spin and tile of 16 frequencies:
 // D^T[n][i'] = sum_{j' in b} E[j'][n] Ms[i'][j'] on the matrix cores (real
 // and imaginary parts of E separately), then the row phases e^{i w_n tau_i}
 // and the sum over i' in a.  A wavefront takes MPAIRS consecutive pairs; a
-// workgroup four wavefronts (blockIdx.x = 2 group + spin).
+// workgroup four wavefronts (blockIdx.x = 2 group + spin), grid-strided over
+// the groups of pairs.
 constexpr int MPAIRS = 1;
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_block(const View<T>* __restrict__ vs, int nc_max) {
-  (void)nc_max;
+__global__ void __launch_bounds__(WG) k_meas_block(const View<T>* __restrict__ vs, int gated) {
   const View<T>& w = vs[blockIdx.z];
+  if (meas_skip(w.ctl, gated)) return;
   const auto order = gp(w.m_order);
   const auto off = gp(w.m_off);
   const int ldm = w.kpad_cap;
@@ -135,63 +141,65 @@ __global__ void __launch_bounds__(WG) k_meas_block(const View<T>* __restrict__ v
   const int Nc = w.Nc;
   const int sp = blockIdx.x & 1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int pair0 = ((blockIdx.x >> 1) * (WG / 64) + wv) * MPAIRS;
   const int n0 = blockIdx.y * 16;
-  if (pair0 >= Nc * Nc || n0 >= n_freq) return;
+  if (n0 >= n_freq) return;
   const auto Ms = gp(w.m_Ms[sp]);
   const auto Mab = gp(w.m_Mab[sp]);
   const int li = lane & 15, lk = lane >> 4;
   const int na = n0 + li;   // frequency of this lane's A' operand row
-  for (int ab = pair0; ab < pair0 + MPAIRS && ab < Nc * Nc; ++ab) {
-    const int a = ab / Nc, b = ab % Nc;
-    const int ia0 = off[a], ia1 = off[a + 1], jb0 = off[b], jb1 = off[b + 1];
-    double sre[4] = {0, 0, 0, 0}, sim[4] = {0, 0, 0, 0};
-    for (int ib = ia0; ib < ia1; ib += 16) {
-      typename Mfma<T>::acc_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
-      const int ip = ib + li;
-      for (int jp = jb0; jp < jb1; jp += 4) {
-        const int jk = jp + lk;
-        const T m = Ms[ip + (size_t)jk * ldm];
-        T er = 0, ei = 0;
-        if (na < n_freq) {
-          er = E[2 * ((size_t)jk * n_freq + na)];
-          ei = E[2 * ((size_t)jk * n_freq + na) + 1];
+  const int gstride = (gridDim.x >> 1) * (WG / 64) * MPAIRS;
+  for (int pair0 = ((blockIdx.x >> 1) * (WG / 64) + wv) * MPAIRS; pair0 < Nc * Nc; pair0 += gstride) {
+    for (int ab = pair0; ab < pair0 + MPAIRS && ab < Nc * Nc; ++ab) {
+      const int a = ab / Nc, b = ab % Nc;
+      const int ia0 = off[a], ia1 = off[a + 1], jb0 = off[b], jb1 = off[b + 1];
+      double sre[4] = {0, 0, 0, 0}, sim[4] = {0, 0, 0, 0};
+      for (int ib = ia0; ib < ia1; ib += 16) {
+        typename Mfma<T>::acc_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+        const int ip = ib + li;
+        for (int jp = jb0; jp < jb1; jp += 4) {
+          const int jk = jp + lk;
+          const T m = Ms[ip + (size_t)jk * ldm];
+          T er = 0, ei = 0;
+          if (na < n_freq) {
+            er = E[2 * ((size_t)jk * n_freq + na)];
+            ei = E[2 * ((size_t)jk * n_freq + na) + 1];
+          }
+          dr = Mfma<T>::run(er, m, dr);
+          di = Mfma<T>::run(ei, m, di);
         }
-        dr = Mfma<T>::run(er, m, dr);
-        di = Mfma<T>::run(ei, m, di);
+        // lane holds D[n = n0 + row(lane, r)][i' = ib + li]
+        const int i = order[ip];
+        if (i >= 0) {
+          const double ti = v_tau[i];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int n = n0 + Mfma<T>::row(lane, r);
+            const double wn = (2.0 * n + 1.0) * M_PI / w.beta;
+            double s, c;
+            sincos(wn * ti, &s, &c);
+            const double xr = (double)dr[r], xi = (double)di[r];
+            sre[r] += c * xr - s * xi;
+            sim[r] += c * xi + s * xr;
+          }
+        }
       }
-      // lane holds D[n = n0 + row(lane, r)][i' = ib + li]
-      const int i = order[ip];
-      if (i >= 0) {
-        const double ti = v_tau[i];
+      // sum over the 16 lanes that share a frequency set (li varies)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        for (int o = 1; o < 16; o <<= 1) {
+          sre[r] += __shfl_xor(sre[r], o, 64);
+          sim[r] += __shfl_xor(sim[r], o, 64);
+        }
+      }
+      if (li == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int n = n0 + Mfma<T>::row(lane, r);
-          const double wn = (2.0 * n + 1.0) * M_PI / w.beta;
-          double s, c;
-          sincos(wn * ti, &s, &c);
-          const double xr = (double)dr[r], xi = (double)di[r];
-          sre[r] += c * xr - s * xi;
-          sim[r] += c * xi + s * xr;
-        }
-      }
-    }
-    // sum over the 16 lanes that share a frequency set (li varies)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      for (int o = 1; o < 16; o <<= 1) {
-        sre[r] += __shfl_xor(sre[r], o, 64);
-        sim[r] += __shfl_xor(sim[r], o, 64);
-      }
-    }
-    if (li == 0) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int n = n0 + Mfma<T>::row(lane, r);
-        if (n < n_freq) {
-          const size_t o = 2 * (((size_t)a * Nc + b) * n_freq + n);
-          Mab[o] = sre[r];
-          Mab[o + 1] = sim[r];
+          if (n < n_freq) {
+            const size_t o = 2 * (((size_t)a * Nc + b) * n_freq + n);
+            Mab[o] = sre[r];
+            Mab[o + 1] = sim[r];
+          }
         }
       }
     }
@@ -203,49 +211,70 @@ __global__ void __launch_bounds__(WG) k_meas_block(const View<T>* __restrict__ v
 // e^{-i K (r_a - r_b)} = phi(K, a) conj(phi(K, b)).
 constexpr int MEAS_NC_MAX = 256;
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_K(const View<T>* __restrict__ vs, double* acc_all) {
+__global__ void __launch_bounds__(WG) k_meas_K(const View<T>* __restrict__ vs, double* acc_all, int gated) {
   const View<T>& w = vs[blockIdx.z >> 1];
+  if (meas_skip(w.ctl, gated)) return;
   const int sp = blockIdx.z & 1;
   const int Nc = w.Nc;
   const int n_freq = w.n_freq;
   const int n = blockIdx.x * WG + threadIdx.x;
-  const int q = blockIdx.y;
-  if (q >= Nc) return;
   __shared__ double pr_s[MEAS_NC_MAX], pi_s[MEAS_NC_MAX];
-  for (int a = threadIdx.x; a < Nc; a += WG) {
-    const double ph = -(w.Kp[2 * q] * (double)w.sites[2 * a] + w.Kp[2 * q + 1] * (double)w.sites[2 * a + 1]);
-    double s, c;
-    sincos(ph, &s, &c);
-    pr_s[a] = c;
-    pi_s[a] = s;
-  }
-  __syncthreads();
-  if (n >= n_freq) return;
   const auto Mab = gp(w.m_Mab[sp]);
-  double re = 0.0, im = 0.0;
-  for (int a = 0; a < Nc; ++a) {
-    // t = sum_b conj(phi_b) M(a, b)
-    double tr = 0.0, ti = 0.0;
-    for (int b = 0; b < Nc; ++b) {
-      const size_t o = 2 * (((size_t)a * Nc + b) * n_freq + n);
-      const double mr = Mab[o], mi = Mab[o + 1];
-      tr += pr_s[b] * mr + pi_s[b] * mi;
-      ti += pr_s[b] * mi - pi_s[b] * mr;
-    }
-    re += pr_s[a] * tr - pi_s[a] * ti;
-    im += pr_s[a] * ti + pi_s[a] * tr;
-  }
   const auto acc = gp(acc_all + w.acc_off);
   const double sign = w.ctl->sign;
-  const size_t o = 2 * (((size_t)sp * Nc + q) * n_freq + n);
-  acc[o] += sign * re / (double)Nc;
-  acc[o + 1] += sign * im / (double)Nc;
+  // momenta q grid-strided over blockIdx.y
+  for (int q = blockIdx.y; q < Nc; q += gridDim.y) {
+    for (int a = threadIdx.x; a < Nc; a += WG) {
+      const double ph = -(w.Kp[2 * q] * (double)w.sites[2 * a] + w.Kp[2 * q + 1] * (double)w.sites[2 * a + 1]);
+      double s, c;
+      sincos(ph, &s, &c);
+      pr_s[a] = c;
+      pi_s[a] = s;
+    }
+    __syncthreads();
+    if (n < n_freq) {
+      double re = 0.0, im = 0.0;
+      for (int a = 0; a < Nc; ++a) {
+        // t = sum_b conj(phi_b) M(a, b), four independent partial sums so
+        // that the loads of a row are in flight together
+        double tr[4] = {0, 0, 0, 0}, ti[4] = {0, 0, 0, 0};
+        const auto row = Mab + 2 * ((size_t)a * Nc * n_freq + n);
+        int b = 0;
+        for (; b + 4 <= Nc; b += 4) {
+          double mr[4], mi[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            mr[u] = row[2 * (size_t)(b + u) * n_freq];
+            mi[u] = row[2 * (size_t)(b + u) * n_freq + 1];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            tr[u] += pr_s[b + u] * mr[u] + pi_s[b + u] * mi[u];
+            ti[u] += pr_s[b + u] * mi[u] - pi_s[b + u] * mr[u];
+          }
+        }
+        for (; b < Nc; ++b) {
+          const double mr = row[2 * (size_t)b * n_freq], mi = row[2 * (size_t)b * n_freq + 1];
+          tr[0] += pr_s[b] * mr + pi_s[b] * mi;
+          ti[0] += pr_s[b] * mi - pi_s[b] * mr;
+        }
+        const double trs = (tr[0] + tr[1]) + (tr[2] + tr[3]), tis = (ti[0] + ti[1]) + (ti[2] + ti[3]);
+        re += pr_s[a] * trs - pi_s[a] * tis;
+        im += pr_s[a] * tis + pi_s[a] * trs;
+      }
+      const size_t o = 2 * (((size_t)sp * Nc + q) * n_freq + n);
+      acc[o] += sign * re / (double)Nc;
+      acc[o + 1] += sign * im / (double)Nc;
+    }
+    __syncthreads();      // the phase table is rewritten for the next momentum
+  }
 }
 
 // aux += [sign, sign tr(M_up)/Nc, sign tr(M_dn)/Nc]; one block per spin.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_diag(const View<T>* __restrict__ vs, double* aux_all) {
+__global__ void __launch_bounds__(WG) k_meas_diag(const View<T>* __restrict__ vs, double* aux_all, int gated) {
   const View<T>& w = vs[blockIdx.z];
+  if (meas_skip(w.ctl, gated)) return;
   double* aux = aux_all + 3 * (size_t)w.wid;
   const int sp = blockIdx.x;
   const double sign = w.ctl->sign;
@@ -322,12 +351,12 @@ __global__ void __launch_bounds__(WG) k_finalize(const View<T>* __restrict__ vs,
 }
 
 #define DCAX_INSTANTIATE_MEASURE(T)                                                             \
-  template __global__ void k_meas_sort<T>(const View<T>*);                                      \
-  template __global__ void k_meas_copy<T>(const View<T>*);                                      \
-  template __global__ void k_meas_phase<T>(const View<T>*);                                     \
+  template __global__ void k_meas_sort<T>(const View<T>*, int);                                 \
+  template __global__ void k_meas_copy<T>(const View<T>*, int);                                 \
+  template __global__ void k_meas_phase<T>(const View<T>*, int);                                \
   template __global__ void k_meas_block<T>(const View<T>*, int);                                \
-  template __global__ void k_meas_K<T>(const View<T>*, double*);                                \
-  template __global__ void k_meas_diag<T>(const View<T>*, double*);                             \
+  template __global__ void k_meas_K<T>(const View<T>*, double*, int);                           \
+  template __global__ void k_meas_diag<T>(const View<T>*, double*, int);                        \
   template __global__ void k_finalize<T>(const View<T>*, const double*, const double*, double*, int, double*);
 
 DCAX_INSTANTIATE_MEASURE(double)

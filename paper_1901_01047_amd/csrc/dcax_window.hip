@@ -185,34 +185,11 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
       }
     }
   }
-  __shared__ int kind_s[PW], slot_s[PW], el_s[PW];
-  kind_s[lane] = kind;
-  slot_s[lane] = slot;
-  __syncthreads();
-  bool fresh = false;
-  int first = lane;
-  if (kind == 0) {
-    fresh = true;
-  } else if (kind == 1 && slot >= 0) {
-    for (int x = 0; x < lane; ++x)
-      if (kind_s[x] == 1 && slot_s[x] == slot) {
-        first = x;
-        break;
-      }
-    fresh = first == lane;
-  }
-  const unsigned long long fresh_m = __ballot(fresh), ins_m = __ballot(kind == 0);
-  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int e_own = fresh ? __popcll(fresh_m & below) : -1;
-  const int cc = (kind == 0) ? __popcll(ins_m & below) : -1;
-  el_s[lane] = e_own;
-  __syncthreads();
-  const int e = (kind == 1 && slot >= 0 && !fresh) ? el_s[first] : e_own;
   // A removal's second target attempt is prepared too (as long as elements
   // remain), so that a redraw after hitting an already removed vertex rarely
   // has to close the window.  Its slot does not depend on the state; whether
   // the attempt happens does, and an unused element costs nothing.
-  const int nE0 = __popcll(fresh_m);
+  const int slot_r = (kind == 1) ? slot : -1;
   int slot1 = -1;
   if (kind == 1 && !(lane == 0 && carry >= 0) && k0 > 0) {
     double ub1, ui1;
@@ -220,14 +197,25 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
     slot1 = (int)(ui1 * (double)k0);
     if (slot1 >= k0) slot1 = k0 - 1;
   }
-  // duplicates: a slot already prepared by any first attempt, or by the
-  // second attempt of an earlier proposal (register broadcasts, no LDS)
+  // duplicates, by register broadcasts: the first removal aiming at a slot
+  // owns its element; a second attempt is fresh unless some first attempt or
+  // an earlier second attempt already prepares its slot
+  int first = lane;
   bool fresh1 = slot1 >= 0;
-  const int slot_r = (kind == 1) ? slot : -1;
   for (int x = 0; x < nP; ++x) {
-    fresh1 &= __builtin_amdgcn_readlane(slot_r, x) != slot1;
-    fresh1 &= !(x < lane && __builtin_amdgcn_readlane(slot1, x) == slot1);
+    const int sx = __builtin_amdgcn_readlane(slot_r, x), s1x = __builtin_amdgcn_readlane(slot1, x);
+    if (x < first && sx >= 0 && sx == slot_r) first = x;
+    fresh1 &= sx != slot1;
+    fresh1 &= !(x < lane && s1x == slot1);
   }
+  const bool fresh = (kind == 0) || (slot_r >= 0 && first == lane);
+  const unsigned long long fresh_m = __ballot(fresh), ins_m = __ballot(kind == 0);
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int e_own = fresh ? __popcll(fresh_m & below) : -1;
+  const int cc = (kind == 0) ? __popcll(ins_m & below) : -1;
+  const int e_first = __shfl(e_own, first, PW);
+  const int e = (slot_r >= 0 && !fresh) ? e_first : e_own;
+  const int nE0 = __popcll(fresh_m);
   const unsigned long long fresh1_m = __ballot(fresh1);
   const int e1 = nE0 + __popcll(fresh1_m & below);
   const int nE = min(nE0 + __popcll(fresh1_m), KS_MAX);
@@ -289,34 +277,36 @@ __global__ void __launch_bounds__(WG) k_gather(const View<T>* __restrict__ vs) {
   T* R1 = w.R[1];
   const Ctl* c = w.ctl;
   if (!c->active) return;
-  const int e = blockIdx.y;
-  if (e >= c->nE) return;
-  const int k0 = c->k0;
-  const int i = blockIdx.x * WG + threadIdx.x;
-  const int cc = w.el_cand[e];
-  if (cc >= 0) {
-    const int rc = w.el_site[e];
-    const double tc = w.el_tau[e];
-    if (i < k0) {
-      const int ri = w.v_site[i];
-      const double ti = w.v_tau[i];
-      const int si = s01(w.v_s[i]);
-      const double gic = gfun(w, ri, ti, rc, tc);
-      const double gci = gfun(w, rc, tc, ri, ti);
-      const size_t o = (size_t)cc * w.cap + i;
-      w.gcol[o] = (T)gic;
-      w.W[0][o] = (T)(gci * (w.ev[0][si] - 1.0));
-      w.W[1][o] = (T)(gci * (w.ev[1][si] - 1.0));
+  const int nE = c->nE, k0 = c->k0;
+  // elements over blockIdx.y, rows over blockIdx.x (both grid-strided)
+  for (int e = blockIdx.y; e < nE; e += gridDim.y) {
+    const int cc = w.el_cand[e];
+    if (cc >= 0) {
+      const int rc = w.el_site[e];
+      const double tc = w.el_tau[e];
+      for (int i = blockIdx.x * WG + threadIdx.x; i < k0; i += gridDim.x * WG) {
+        const int ri = w.v_site[i];
+        const double ti = w.v_tau[i];
+        const int si = s01(w.v_s[i]);
+        const double gic = gfun(w, ri, ti, rc, tc);
+        const double gci = gfun(w, rc, tc, ri, ti);
+        const size_t o = (size_t)cc * w.cap + i;
+        w.gcol[o] = (T)gic;
+        w.W[0][o] = (T)(gci * (w.ev[0][si] - 1.0));
+        w.W[1][o] = (T)(gci * (w.ev[1][si] - 1.0));
+      }
+      if (blockIdx.x == 0 && (int)threadIdx.x < c->nC) {
+        const int e2 = w.cand_el[threadIdx.x];
+        w.gCC[cc * KS_MAX + threadIdx.x] = gfun(w, rc, tc, w.el_site[e2], w.el_tau[e2]);
+      }
+    } else {
+      const int p = w.el_slot[e];
+      for (int i = blockIdx.x * WG + threadIdx.x; i < k0; i += gridDim.x * WG) {
+        const size_t o = (size_t)e * w.cap + i;
+        R0[o] = w.N[0][p + (size_t)i * w.ld];
+        R1[o] = w.N[1][p + (size_t)i * w.ld];
+      }
     }
-    if (blockIdx.x == 0 && (int)threadIdx.x < c->nC) {
-      const int e2 = w.cand_el[threadIdx.x];
-      w.gCC[cc * KS_MAX + threadIdx.x] = gfun(w, rc, tc, w.el_site[e2], w.el_tau[e2]);
-    }
-  } else if (i < k0) {
-    const int p = w.el_slot[e];
-    const size_t o = (size_t)e * w.cap + i;
-    R0[o] = w.N[0][p + (size_t)i * w.ld];
-    R1[o] = w.N[1][p + (size_t)i * w.ld];
   }
 }
 
@@ -343,45 +333,49 @@ __global__ void __launch_bounds__(NW * 64) k_cand_x(const View<T>* __restrict__ 
   if (!c->active) return;
   const int nC = c->nC;
   const int k0 = c->k0;
-  const int j0 = blockIdx.x * 16;
-  if (nC == 0 || j0 >= k0) return;
+  if (nC == 0) return;
   const int sp = blockIdx.y;
   const auto N = gp(w.N[sp]);
   const auto Wm = gp(w.W[sp]);
+  const auto R = gp(w.R[sp]);
+  const auto cand_el = gp(w.cand_el);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nRB = (nC + 15) >> 4;
-  const int jc = j0 + li;
-  acc_t acc[4];
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb) acc[rb] = acc_t{0, 0, 0, 0};
-#pragma unroll 4
-  for (int i0 = 4 * wv; i0 < k0; i0 += 4 * GWV) {
-    const int ik = i0 + lk;
-    const bool kin = ik < k0;
-    const T b = (kin && jc < k0) ? N[ik + (size_t)jc * w.ld] : (T)0;
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
-      if (rb < nRB) {
-        const int cr = rb * 16 + li;
-        const T a = (kin && cr < nC) ? Wm[(size_t)cr * w.cap + ik] : (T)0;
-        acc[rb] = Mfma<T>::run(a, b, acc[rb]);
-      }
-  }
   __shared__ acc_t red[GWV][4][64];
+  // column tiles of 16, grid-strided over blockIdx.x
+  for (int j0 = blockIdx.x * 16; j0 < k0; j0 += gridDim.x * 16) {
+    const int jc = j0 + li;
+    acc_t acc[4];
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb) red[wv][rb][lane] = acc[rb];
-  __syncthreads();
-  const int rb = wv;
-  if (rb >= nRB) return;
-  acc_t sum = red[0][rb][lane];
-  for (int v = 1; v < GWV; ++v) sum += red[v][rb][lane];
-  const auto R = gp(w.R[sp]);
-  const auto cand_el = gp(w.cand_el);
+    for (int rb = 0; rb < 4; ++rb) acc[rb] = acc_t{0, 0, 0, 0};
+#pragma unroll 4
+    for (int i0 = 4 * wv; i0 < k0; i0 += 4 * GWV) {
+      const int ik = i0 + lk;
+      const bool kin = ik < k0;
+      const T b = (kin && jc < k0) ? N[ik + (size_t)jc * w.ld] : (T)0;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int cr = rb * 16 + Mfma<T>::row(lane, r);
-    if (cr < nC && jc < k0) R[(size_t)cand_el[cr] * w.cap + jc] = sum[r];
+      for (int rb = 0; rb < 4; ++rb)
+        if (rb < nRB) {
+          const int cr = rb * 16 + li;
+          const T a = (kin && cr < nC) ? Wm[(size_t)cr * w.cap + ik] : (T)0;
+          acc[rb] = Mfma<T>::run(a, b, acc[rb]);
+        }
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) red[wv][rb][lane] = acc[rb];
+    __syncthreads();
+    const int rb = wv;
+    if (rb < nRB) {
+      acc_t sum = red[0][rb][lane];
+      for (int v = 1; v < GWV; ++v) sum += red[v][rb][lane];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int cr = rb * 16 + Mfma<T>::row(lane, r);
+        if (cr < nC && jc < k0) R[(size_t)cand_el[cr] * w.cap + jc] = sum[r];
+      }
+    }
+    __syncthreads();      // red is rewritten by the next tile
   }
 }
 
@@ -400,29 +394,31 @@ __global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
   if (!c->active) return;
-  const int x = blockIdx.x, sp = blockIdx.y;
+  const int sp = blockIdx.y;
   const int nE = c->nE;
-  if (x >= nE) return;
   const int k0 = c->k0, nC = c->nC;
-  const int cx = w.el_cand[x];
-  const auto Rx = gp(w.R[sp] + (size_t)x * w.cap);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const auto G = gp(w.gram[sp] + x * KS_MAX);
-  for (int cc = wv; cc < nC; cc += GWV) {
-    const auto gc = gp(w.gcol + (size_t)cc * w.cap);
-    double s = 0.0;
-    for (int i = lane; i < k0; i += 64) s += (double)Rx[i] * (double)gc[i];
-    s = wave_sum(s);
-    if (lane == 0) {
-      const int ec = w.cand_el[cc];
-      const double Dc = w.ev[sp][s01(w.el_s[ec])] - 1.0;
-      const double g = s + (cx >= 0 ? w.gCC[cx * KS_MAX + cc] : 0.0);
-      G[ec] = -Dc * g + (ec == x ? 1.0 + Dc : 0.0);
+  // rows x of Gt, grid-strided over blockIdx.x
+  for (int x = blockIdx.x; x < nE; x += gridDim.x) {
+    const int cx = w.el_cand[x];
+    const auto Rx = gp(w.R[sp] + (size_t)x * w.cap);
+    const auto G = gp(w.gram[sp] + x * KS_MAX);
+    for (int cc = wv; cc < nC; cc += GWV) {
+      const auto gc = gp(w.gcol + (size_t)cc * w.cap);
+      double s = 0.0;
+      for (int i = lane; i < k0; i += 64) s += (double)Rx[i] * (double)gc[i];
+      s = wave_sum(s);
+      if (lane == 0) {
+        const int ec = w.cand_el[cc];
+        const double Dc = w.ev[sp][s01(w.el_s[ec])] - 1.0;
+        const double g = s + (cx >= 0 ? w.gCC[cx * KS_MAX + cc] : 0.0);
+        G[ec] = -Dc * g + (ec == x ? 1.0 + Dc : 0.0);
+      }
     }
-  }
-  for (int y = threadIdx.x; y < nE; y += GW) {
-    const int py = w.el_slot[y];
-    if (py >= 0) G[y] = (double)Rx[py];
+    for (int y = threadIdx.x; y < nE; y += GW) {
+      const int py = w.el_slot[y];
+      if (py >= 0) G[y] = (double)Rx[py];
+    }
   }
 }
 
@@ -847,8 +843,7 @@ __global__ void __launch_bounds__(NW * 64) k_ygemm(const View<T>* __restrict__ v
   const Ctl* c = w.ctl;
   if (!c->active) return;
   const int mi = c->mi, k0 = c->k0;
-  const int r0 = blockIdx.x * 16;
-  if (mi == 0 || r0 >= k0) return;
+  if (mi == 0) return;
   const int sp = blockIdx.y;
   const auto N = gp(w.N[sp]);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -863,35 +858,40 @@ __global__ void __launch_bounds__(NW * 64) k_ygemm(const View<T>* __restrict__ v
     const int jj = cb * 16 + li;
     goff[cb] = (jj < mi) ? (long long)w.el_cand[w.ins_el[jj]] * w.cap : -1;
   }
-  const int ir = r0 + li;
-  acc_t acc[4];
-#pragma unroll
-  for (int cb = 0; cb < 4; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
-#pragma unroll 4
-  for (int j0 = 4 * wv; j0 < k0; j0 += 4 * GWV) {
-    const int jk = j0 + lk;
-    const bool kin = jk < k0;
-    const T a = (kin && ir < k0) ? N[ir + (size_t)jk * w.ld] : (T)0;
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-      if (cb < ncb) {
-        const T b = (kin && goff[cb] >= 0) ? gcol[goff[cb] + jk] : (T)0;
-        acc[cb] = Mfma<T>::run(a, b, acc[cb]);
-      }
-  }
   __shared__ acc_t red[GWV][4][64];
+  // row tiles of 16, grid-strided over blockIdx.x
+  for (int r0 = blockIdx.x * 16; r0 < k0; r0 += gridDim.x * 16) {
+    const int ir = r0 + li;
+    acc_t acc[4];
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) red[wv][cb][lane] = acc[cb];
-  __syncthreads();
-  const int cb = wv;
-  if (cb >= ncb) return;
-  acc_t sum = red[0][cb][lane];
-  for (int v = 1; v < GWV; ++v) sum += red[v][cb][lane];
-  const int jj = cb * 16 + li;
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
+#pragma unroll 4
+    for (int j0 = 4 * wv; j0 < k0; j0 += 4 * GWV) {
+      const int jk = j0 + lk;
+      const bool kin = jk < k0;
+      const T a = (kin && ir < k0) ? N[ir + (size_t)jk * w.ld] : (T)0;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = r0 + Mfma<T>::row(lane, r);
-    if (i < k0 && jj < mi) gp(w.Y[sp])[(size_t)jj * w.cap + i] = sum[r];
+      for (int cb = 0; cb < 4; ++cb)
+        if (cb < ncb) {
+          const T b = (kin && goff[cb] >= 0) ? gcol[goff[cb] + jk] : (T)0;
+          acc[cb] = Mfma<T>::run(a, b, acc[cb]);
+        }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) red[wv][cb][lane] = acc[cb];
+    __syncthreads();
+    const int cb = wv;
+    if (cb < ncb) {
+      acc_t sum = red[0][cb][lane];
+      for (int v = 1; v < GWV; ++v) sum += red[v][cb][lane];
+      const int jj = cb * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + Mfma<T>::row(lane, r);
+        if (i < k0 && jj < mi) gp(w.Y[sp])[(size_t)jj * w.cap + i] = sum[r];
+      }
+    }
+    __syncthreads();      // red is rewritten by the next tile
   }
 }
 
@@ -914,8 +914,7 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
   const int m = c->m;
   const int sp = blockIdx.y;
   const int k0 = c->k0, mi = c->mi, kx = k0 + mi;
-  const int i0 = blockIdx.x * 64;
-  if (i0 >= kx) return;
+  if ((int)blockIdx.x * 64 >= kx) return;
   __shared__ double gi_s[KS_MAX * KS_MAX];
   __shared__ double rv_s[KS_MAX][64];
   __shared__ int e_s[KS_MAX], row_s[KS_MAX], cand_s[KS_MAX], slot_s[KS_MAX], ins_s[KS_MAX];
@@ -935,45 +934,50 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
   }
   if (t < mi) ins_s[t] = w.ins_el[t];
   __syncthreads();
-  const int i = i0 + lane;
-  const bool live = i < kx;
   const T* R = w.R[sp];
   T* N = w.N[sp];
   const size_t ld = w.ld;
-  for (int b = wv; b < m; b += WG / 64) {
-    double x = 0.0;
+  // groups of 64 columns, grid-strided over blockIdx.x
+  for (int i0 = blockIdx.x * 64; i0 < kx; i0 += gridDim.x * 64) {
+    const int i = i0 + lane;
+    const bool live = i < kx;
+    for (int b = wv; b < m; b += WG / 64) {
+      double x = 0.0;
+      if (live) {
+        if (i < k0) x = (double)R[(size_t)e_s[b] * w.cap + i];
+        else x = (cand_s[b] >= 0 && row_s[b] == i) ? 1.0 : 0.0;
+      }
+      rv_s[b][lane] = x;
+    }
+    __syncthreads();
     if (live) {
-      if (i < k0) x = (double)R[(size_t)e_s[b] * w.cap + i];
-      else x = (cand_s[b] >= 0 && row_s[b] == i) ? 1.0 : 0.0;
+      // A, column-major [s][i]
+      for (int s = wv; s < m; s += WG / 64) {
+        double v;
+        if (cand_s[s] >= 0) {
+          const int jj = row_s[s] - k0;
+          if (i < k0) v = d_s[s] * (double)w.Y[sp][(size_t)jj * w.cap + i];
+          else v = (i - k0 == jj ? 1.0 : 0.0) - w.gram[sp][ins_s[i - k0] * KS_MAX + e_s[s]];
+        } else {
+          const int p = slot_s[s];
+          const double nip = (i < k0) ? (double)N[i + (size_t)p * ld] : (double)R[(size_t)ins_s[i - k0] * w.cap + p];
+          v = (i == p ? 1.0 : 0.0) - nip;
+        }
+        w.A[sp][(size_t)s * w.cap + i] = (T)v;
+      }
+      // B, row-major [a][i] = sum_b Gt^{-1}[a][b] Row_{S_b}[i]
+      for (int a = wv; a < m; a += WG / 64) {
+        double acc = 0.0;
+        for (int b = 0; b < m; ++b) acc += gi_s[a * KS_MAX + b] * rv_s[b][lane];
+        w.B[sp][(size_t)a * w.cap + i] = (T)acc;
+      }
+      // extension of N (no workgroup reads rows or columns >= k0 of N here)
+      for (int jj = wv; jj < mi; jj += WG / 64) {
+        if (i < k0) N[(k0 + jj) + (size_t)i * ld] = R[(size_t)ins_s[jj] * w.cap + i];
+        N[i + (size_t)(k0 + jj) * ld] = (i == k0 + jj) ? (T)1 : (T)0;
+      }
     }
-    rv_s[b][lane] = x;
-  }
-  __syncthreads();
-  if (!live) return;
-  // A, column-major [s][i]
-  for (int s = wv; s < m; s += WG / 64) {
-    double v;
-    if (cand_s[s] >= 0) {
-      const int jj = row_s[s] - k0;
-      if (i < k0) v = d_s[s] * (double)w.Y[sp][(size_t)jj * w.cap + i];
-      else v = (i - k0 == jj ? 1.0 : 0.0) - w.gram[sp][ins_s[i - k0] * KS_MAX + e_s[s]];
-    } else {
-      const int p = slot_s[s];
-      const double nip = (i < k0) ? (double)N[i + (size_t)p * ld] : (double)R[(size_t)ins_s[i - k0] * w.cap + p];
-      v = (i == p ? 1.0 : 0.0) - nip;
-    }
-    w.A[sp][(size_t)s * w.cap + i] = (T)v;
-  }
-  // B, row-major [a][i] = sum_b Gt^{-1}[a][b] Row_{S_b}[i]
-  for (int a = wv; a < m; a += WG / 64) {
-    double acc = 0.0;
-    for (int b = 0; b < m; ++b) acc += gi_s[a * KS_MAX + b] * rv_s[b][lane];
-    w.B[sp][(size_t)a * w.cap + i] = (T)acc;
-  }
-  // extension of N (reads above touch only rows and columns < k0 of N)
-  for (int jj = wv; jj < mi; jj += WG / 64) {
-    if (i < k0) N[(k0 + jj) + (size_t)i * ld] = R[(size_t)ins_s[jj] * w.cap + i];
-    N[i + (size_t)(k0 + jj) * ld] = (i == k0 + jj) ? (T)1 : (T)0;
+    __syncthreads();      // rv_s is rewritten by the next group
   }
 }
 
@@ -1031,9 +1035,11 @@ __global__ void __launch_bounds__(WG) k_fold(const View<T>* __restrict__ vs) {
   const Ctl* c = w.ctl;
   if (!c->active) return;
   const int kx = c->kx, m = c->m;
-  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
-  if (m == 0 || i0 >= kx || j0 >= kx) return;
-  fold_tile<T>(w.N[sp], w.ld, w.A[sp], w.cap, w.B[sp], w.cap, kx, kx, m, i0, j0);
+  if (m == 0) return;
+  // 64 x 64 tiles of N, grid-strided over blockIdx.x
+  const int nt = (kx + 63) >> 6;
+  for (int t = blockIdx.x; t < nt * nt; t += gridDim.x)
+    fold_tile<T>(w.N[sp], w.ld, w.A[sp], w.cap, w.B[sp], w.cap, kx, kx, m, (t % nt) * 64, (t / nt) * 64);
 }
 
 // ----------------------------------------------------------- compaction
@@ -1051,15 +1057,33 @@ __global__ void __launch_bounds__(WG) k_compact_move(const View<T>* __restrict__
   const int sp = blockIdx.z & 1;
   const int nh = moves[2 * KS_MAX];
   const int knew = c->knew;
-  const int i = blockIdx.x * WG + threadIdx.x;
-  if (nh == 0 || i >= knew) return;
+  if (nh == 0) return;
   const auto N = gp(w.N[sp]);
   const size_t ld = w.ld;
-  const int si = remap[i];
-  for (int h = 0; h < nh; ++h) {
-    const int d = moves[2 * h], s = moves[2 * h + 1];
-    N[i + (size_t)d * ld] = N[si + (size_t)s * ld];
-    N[d + (size_t)i * ld] = N[s + (size_t)si * ld];
+  // the moves are read into LDS once; the copies of eight moves are loaded
+  // together before they are stored (sources are never destinations)
+  __shared__ int mv_s[2 * KS_MAX];
+  for (int x = threadIdx.x; x < 2 * nh; x += WG) mv_s[x] = moves[x];
+  __syncthreads();
+  for (int i = blockIdx.x * WG + threadIdx.x; i < knew; i += gridDim.x * WG) {
+    const int si = remap[i];
+    for (int h0 = 0; h0 < nh; h0 += 8) {
+      T cv[8], rv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (h0 + u < nh) {
+          const int s = mv_s[2 * (h0 + u) + 1];
+          cv[u] = N[si + (size_t)s * ld];
+          rv[u] = N[s + (size_t)si * ld];
+        }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (h0 + u < nh) {
+          const int d = mv_s[2 * (h0 + u)];
+          N[i + (size_t)d * ld] = cv[u];
+          N[d + (size_t)i * ld] = rv[u];
+        }
+    }
   }
 }
 

@@ -77,7 +77,7 @@ VERTEX_DTYPE = np.dtype([("id", np.int64), ("site", np.int32), ("aux_spin", np.i
 
 # exported symbols, in the order include/dcax.h declares them
 EXPORTS = ("dcax_walker_create", "dcax_walker_destroy", "dcax_sweep", "dcax_refresh", "dcax_measure_G",
-           "dcax_sweep_measure",
+           "dcax_sweep_measure", "dcax_run_rounds",
            "dcax_finalize_G", "dcax_get_order", "dcax_copy_N", "dcax_get_config", "dcax_set_config",
            "dcax_set_submatrix_k", "dcax_autotune", "dcax_set_graphs", "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table",
            "dcax_cluster", "dcax_last_error")
@@ -102,6 +102,7 @@ def load():
         "dcax_refresh": [vp, P(ctypes.c_double)],
         "dcax_measure_G": [vp, vp, vp],
         "dcax_sweep_measure": [vp, ctypes.c_int32, vp, vp],
+        "dcax_run_rounds": [vp, ctypes.c_int32, vp, vp],
         "dcax_finalize_G": [vp, vp, vp, vp, ctypes.c_int32, vp],
         "dcax_get_order": [vp, ctypes.c_int32, P(ctypes.c_int32)],
         "dcax_copy_N": [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64, vp],
@@ -311,6 +312,11 @@ class Walker:
 
     def measure(self, acc, aux):
         _check(load().dcax_measure_G(self._h, ctypes.c_void_p(acc.data_ptr()), ctypes.c_void_p(aux.data_ptr())))
+
+    def run_rounds(self, n_rounds, acc, aux):
+        """Free-running batch: every walker sweeps and measures for n_rounds rounds."""
+        _check(load().dcax_run_rounds(self._h, int(n_rounds), ctypes.c_void_p(acc.data_ptr()),
+                                      ctypes.c_void_p(aux.data_ptr())))
 
     def sweep_measure(self, n_sweeps, acc, aux):
         """n_sweeps generator sweeps, each followed by a measurement into (acc, aux)."""
