@@ -428,11 +428,14 @@ dcax_status sync_all(dcax_walker w) {
 // covers the work; the tiles of one walker are latency-bound chains, so a
 // launch keeps all of them in flight (idle workgroups of small walkers cost
 // little) up to a ceiling on the launch size.
-static int spread(int tiles, int W, int units) {
-  constexpr long long budget = 1ll << 21;   // workgroups per launch
+static int spread(int tiles, int W, int units, long long budget = 1ll << 21) {
   const long long g = std::max<long long>(1, budget / ((long long)W * units));
   return (int)std::max<long long>(1, std::min<long long>(tiles, g));
 }
+// Gated measurements cover the few walkers whose sweep has just ended: a
+// launch sized for every walker would spend its time dispatching workgroups
+// that return at once, so the measurement grids stay within this budget.
+constexpr long long MEAS_BUDGET = 1ll << 15;
 
 template <typename T>
 void enqueue_window(dcax_walker w, int kb, bool replay) {
@@ -455,9 +458,10 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   const bool wide = (long long)g16 * 2 * W < 4096;
   if (wide) hipLaunchKernelGGL((k_cand_x<T, 16>), dim3(g16, 2, W), dim3(1024), 0, s, vs);
   else hipLaunchKernelGGL((k_cand_x<T, 4>), dim3(g16, 2, W), dim3(256), 0, s, vs);
-  const int gr = spread(ne, W, 2);
-  if ((long long)gr * 2 * W < 4096) hipLaunchKernelGGL((k_gram<T, 16>), dim3(gr, 2, W), dim3(1024), 0, s, vs);
-  else hipLaunchKernelGGL((k_gram<T, 4>), dim3(gr, 2, W), dim3(256), 0, s, vs);
+  // Gram: a workgroup per row for few walkers, the matrix-core form for
+  // batches (a workgroup per 16 candidates)
+  if ((long long)ne * 2 * W < 4096) hipLaunchKernelGGL((k_gram_rows<T, 16>), dim3(ne, 2, W), dim3(1024), 0, s, vs);
+  else hipLaunchKernelGGL((k_gram<T, 4>), dim3(cdiv(ks, 16), 2, W), dim3(256), 0, s, vs);
   hipEvent_t e_a0 = w->tev(timed), e_a1 = w->tev(timed);
   hipExtLaunchKernelGGL(k_accept<T>, dim3(1, 1, W), dim3(AW), 0, s, e_a0, e_a1, 0, vs);
   w->mark(w->pend_accept, e_a0, e_a1);
@@ -523,13 +527,14 @@ void enqueue_measure(dcax_walker w, double* acc, double* aux, int gated) {
   const int kb = std::min(w->kpad_max, w->kmax_host() + 16 * ncm);
   const int kb1 = std::max(kb, 1);
   hipLaunchKernelGGL(k_meas_sort<T>, dim3(1, 1, W), dim3(WG), 0, s, vs, gated);
-  const int cx = spread(cdiv(kb1, WG), W, 1);
-  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cx, spread(cdiv(kb1, MCOLS), W, cx), W), dim3(WG), 0, s, vs, gated);
+  const long long mb = MEAS_BUDGET;
+  const int cx = spread(cdiv(kb1, WG), W, 1, mb);
+  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cx, spread(cdiv(kb1, MCOLS), W, cx, mb), W), dim3(WG), 0, s, vs, gated);
   const int px = cdiv(nf, WG);
-  hipLaunchKernelGGL(k_meas_phase<T>, dim3(px, spread(cdiv(kb1, MCOLS), W, px), W), dim3(WG), 0, s, vs, gated);
+  hipLaunchKernelGGL(k_meas_phase<T>, dim3(px, spread(cdiv(kb1, MCOLS), W, px, mb), W), dim3(WG), 0, s, vs, gated);
   const int groups = cdiv(ncm * ncm, (WG / 64) * MPAIRS), fy = cdiv(nf, 16);
-  hipLaunchKernelGGL(k_meas_block<T>, dim3(2 * spread(groups, W, 2 * fy), fy, W), dim3(WG), 0, s, vs, gated);
-  hipLaunchKernelGGL(k_meas_K<T>, dim3(px, spread(ncm, W, 2 * px), 2 * W), dim3(WG), 0, s, vs, acc, gated);
+  hipLaunchKernelGGL(k_meas_block<T>, dim3(2 * spread(groups, W, 2 * fy, mb), fy, W), dim3(WG), 0, s, vs, gated);
+  hipLaunchKernelGGL(k_meas_K<T>, dim3(px, spread(ncm, W, 2 * px, mb), 2 * W), dim3(WG), 0, s, vs, acc, gated);
   if (gated) hipLaunchKernelGGL(k_meas_done<T>, dim3(1, 1, W), dim3(1), 0, s, vs);
 }
 

@@ -388,8 +388,12 @@ __global__ void __launch_bounds__(NW * 64) k_cand_x(const View<T>* __restrict__ 
 //   target p:     Gt_{x,p} = R_x[p], from G (e^V - 1) = N e^V - 1 with
 //                 Delta_p = e^{-V_p} - 1;
 // where R_x is row x of the extended N (X_c for candidates, N_{p.} for targets).
+// Row form of the Gram kernel for launches with few walkers: a workgroup
+// owns one row x of Gt, its wavefronts take the candidate columns in turn
+// (each a k0-long dot product summed across the lanes), so a single walker
+// spreads over nE workgroups per spin.
 template <typename T, int NW>
-__global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs) {
+__global__ void __launch_bounds__(NW * 64) k_gram_rows(const View<T>* __restrict__ vs) {
   constexpr int GWV = NW, GW = NW * 64;
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
@@ -398,7 +402,6 @@ __global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs
   const int nE = c->nE;
   const int k0 = c->k0, nC = c->nC;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // rows x of Gt, grid-strided over blockIdx.x
   for (int x = blockIdx.x; x < nE; x += gridDim.x) {
     const int cx = w.el_cand[x];
     const auto Rx = gp(w.R[sp] + (size_t)x * w.cap);
@@ -422,12 +425,80 @@ __global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs
   }
 }
 
+// Matrix-core form for batches: one workgroup per 16 candidates and spin.
+template <typename T, int NW>
+__global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs) {
+  constexpr int GWV = NW, GW = NW * 64;
+  typedef typename Mfma<double>::acc_t acc_t;
+  const View<T>& w = vs[blockIdx.z];
+  const Ctl* c = w.ctl;
+  if (!c->active) return;
+  const int sp = blockIdx.y;
+  const int nE = c->nE;
+  const int k0 = c->k0, nC = c->nC;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nRB = (nE + 15) >> 4;
+  const auto R = gp(w.R[sp]);
+  const auto gcol = gp(w.gcol);
+  const auto G = gp(w.gram[sp]);
+  __shared__ acc_t red[GWV][4][64];
+  // candidate columns: R (nE x k0) times gcol^T (k0 x 16 candidates) on the
+  // FP64 matrix cores, the wavefronts splitting k0 and summing in LDS in a
+  // fixed order; blocks of 16 candidates grid-strided over blockIdx.x
+  for (int cc0 = blockIdx.x * 16; cc0 < nC; cc0 += gridDim.x * 16) {
+    const int cc = cc0 + li;
+    acc_t acc[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[rb] = acc_t{0, 0, 0, 0};
+#pragma unroll 4
+    for (int i0 = 4 * wv; i0 < k0; i0 += 4 * GWV) {
+      const int ik = i0 + lk;
+      const bool kin = ik < k0;
+      const double b = (kin && cc < nC) ? (double)gcol[(size_t)cc * w.cap + ik] : 0.0;
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+        if (rb < nRB) {
+          const int x = rb * 16 + li;
+          const double a = (kin && x < nE) ? (double)R[(size_t)x * w.cap + ik] : 0.0;
+          acc[rb] = Mfma<double>::run(a, b, acc[rb]);
+        }
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) red[wv][rb][lane] = acc[rb];
+    __syncthreads();
+    const int rb = wv;
+    if (rb < nRB && cc < nC) {
+      acc_t sum = red[0][rb][lane];
+      for (int v = 1; v < GWV; ++v) sum += red[v][rb][lane];
+      const int ec = w.cand_el[cc];
+      const double Dc = w.ev[sp][s01(w.el_s[ec])] - 1.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = rb * 16 + Mfma<double>::row(lane, r);
+        if (x < nE) {
+          const int cx = w.el_cand[x];
+          const double g = sum[r] + (cx >= 0 ? w.gCC[cx * KS_MAX + cc] : 0.0);
+          G[x * KS_MAX + ec] = -Dc * g + (ec == x ? 1.0 + Dc : 0.0);
+        }
+      }
+    }
+    __syncthreads();      // red is rewritten by the next block
+  }
+  // columns of window-start vertices: Gt_{x,p} = R_x[p]
+  if (blockIdx.x == 0)
+    for (int idx = threadIdx.x; idx < nE * nE; idx += GW) {
+      const int x = idx / nE, y = idx % nE;
+      const int py = w.el_slot[y];
+      if (py >= 0) G[x * KS_MAX + y] = (double)R[(size_t)x * w.cap + py];
+    }
+}
+
 // ---------------------------------------------------------- accept loop
-// The sequential Metropolis decisions of the window, in FP64, on one
-// wavefront: lane a owns row a of Gt_S^{-1} for both spins, so a proposal
-// costs O(m) LDS operations per lane and no cross-wave synchronisation.
-// Gt is the column-scaled Gamma of k_gram, Gt_S = Gamma_S diag(-Delta_S):
-// adding q to S multiplies the determinant ratio by the Schur complement
+// The sequential Metropolis decisions of the window, in FP64, in one
+// workgroup per walker.  Gt is the column-scaled Gamma of k_gram,
+// Gt_S = Gamma_S diag(-Delta_S): adding q to S multiplies the determinant
+// ratio by the Schur complement
 //   Gt_qq - Gt_qS Gt_S^{-1} Gt_Sq,
 // taking an inserted spin out again (its removal later in the same window)
 // multiplies it by (Gt_S^{-1})_qq.  The acceptance ratio is K/(k+1) or k/K
@@ -1094,7 +1165,7 @@ __global__ void __launch_bounds__(WG) k_compact_move(const View<T>* __restrict__
   template __global__ void k_cand_x<T, 4>(const View<T>*);               \
   template __global__ void k_cand_x<T, 16>(const View<T>*);              \
   template __global__ void k_gram<T, 4>(const View<T>*);                 \
-  template __global__ void k_gram<T, 16>(const View<T>*);                \
+  template __global__ void k_gram_rows<T, 16>(const View<T>*);           \
   template __global__ void k_accept<T>(const View<T>*);                  \
   template __global__ void k_ygemm<T, 4>(const View<T>*);                \
   template __global__ void k_ygemm<T, 16>(const View<T>*);               \
