@@ -605,10 +605,74 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
   double sign = uni(c->sign);
   long long next_id = uni(c->next_id), carry = -1;
   long long n_ins = 0, n_rem = 0, n_mis = 0;
-  for (int j = 0; j < nP; ++j) {
-    const int kind = lane_value(p_kind, j), el = lane_value(p_el, j);
-    const int forced = lane_value(p_forced, j), carried = lane_value(p_carried, j);
-    int q = el, ab = 0;
+  // Proposals are settled in runs: every lane from the current proposal on
+  // evaluates its own proposal against the current state (valid up to the
+  // first accepted one, which is what changes the state); the run's
+  // rejections are recorded at once and the first acceptance is applied.
+  // Proposals whose evaluation needs more than the lane has (a redrawn or
+  // unprepared removal target, a non-finite ratio, the order limit) end the
+  // run too and go through the wavefront-uniform path.
+  int j = 0;
+  while (j < nP) {
+    const double facI = K_exp / (double)(kcur + 1), facR = (double)kcur / K_exp;
+    const bool inr = lane >= j && lane < nP;
+    const bool genrem = p_forced < 0 && p_kind == 1 && !p_carried;
+    int q_l = p_el, idx_l = 0;
+    bool cx = false, use_insl = false;
+    if (genrem) {
+      if (kcur <= 0) {
+        q_l = -1;                       // removal at order 0: a no-op
+      } else if (p_ub0 * (double)(k0 + nins) < (double)k0) {
+        if (p_el < 0) cx = true;        // the first target was not prepared
+      } else {
+        int idx = (int)(p_ui0 * (double)nins);
+        if (idx >= nins) idx = nins - 1;
+        idx_l = idx < 0 ? 0 : idx;
+        use_insl = true;
+      }
+    }
+    const int q_ins = __shfl(insl, idx_l, 64);
+    if (use_insl) q_l = q_ins;
+    const int qs = q_l < 0 ? 0 : q_l;
+    const int pq_l = __shfl(pos_r, qs, 64);
+    const double d0_l = __hiloint2double(__shfl(__double2hiint(dg0), qs, 64), __shfl(__double2loint(dg0), qs, 64));
+    const double d1_l = __hiloint2double(__shfl(__double2hiint(dg1), qs, 64), __shfl(__double2loint(dg1), qs, 64));
+    if (genrem && kcur > 0 && !use_insl && p_el >= 0 && pq_l >= 0) cx = true;   // redraw needed
+    const double sgn_l = (pq_l >= 0) ? -1.0 : 1.0;
+    const double R_l = ((p_kind == 0) ? facI : facR) * (sgn_l * d0_l) * (sgn_l * d1_l);
+    const int mine_l = p_u < fabs(R_l);
+    const int dec_l = (q_l < 0) ? 0 : ((p_forced >= 0) ? p_forced : mine_l);
+    if (q_l >= 0 && (!isfinite(R_l) || (dec_l && p_kind == 0 && kcur + 1 > max_order))) cx = true;
+    const unsigned long long evm = __ballot(inr && (cx || dec_l));
+    const int E = evm ? (int)__ffsll((long long)evm) - 1 : nP;
+    // the rejections before the event
+    const bool rej = lane >= j && lane < E;
+    if (w0 && rej) rout_s[lane] = (q_l < 0) ? 0.0 : R_l;
+    n_mis += __popcll(__ballot(rej && q_l >= 0 && p_forced >= 0 && mine_l != p_forced));
+    if (E >= nP) break;
+    j = E;
+    int q, pq, kind, forced, dec;
+    double R, d0, d1, sgn;
+    if (!lane_value((int)cx, j)) {
+      // a plain acceptance: everything the run computed for it holds
+      q = lane_value(q_l, j);
+      pq = lane_value(pq_l, j);
+      kind = lane_value(p_kind, j);
+      forced = lane_value(p_forced, j);
+      d0 = lane_value(d0_l, j);
+      d1 = lane_value(d1_l, j);
+      R = lane_value(R_l, j);
+      sgn = (pq >= 0) ? -1.0 : 1.0;
+      if (forced >= 0 && lane_value(mine_l, j) != forced) ++n_mis;
+      if (t0) rout_s[j] = R;
+      dec = 1;
+    } else {
+    kind = lane_value(p_kind, j);
+    const int el = lane_value(p_el, j);
+    forced = lane_value(p_forced, j);
+    const int carried = lane_value(p_carried, j);
+    q = el;
+    int ab = 0;
     if (forced < 0 && kind == 1 && !carried) {
       q = -1;
       if (kcur > 0) {
@@ -651,14 +715,15 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     }
     if (q < 0) {
       if (t0) rout_s[j] = 0.0;
+      ++j;
       continue;
     }
-    const int pq = lane_value(pos_r, q);
-    const double sgn = (pq >= 0) ? -1.0 : 1.0;
-    const double d0 = lane_value(dg0, q), d1 = lane_value(dg1, q);
-    const double fac = (kind == 0) ? K_exp / (double)(kcur + 1) : (double)kcur / K_exp;
-    const double R = fac * (sgn * d0) * (sgn * d1);
-    int dec;
+    pq = lane_value(pos_r, q);
+    sgn = (pq >= 0) ? -1.0 : 1.0;
+    d0 = lane_value(dg0, q);
+    d1 = lane_value(dg1, q);
+    const double fac = (kind == 0) ? facI : facR;
+    R = fac * (sgn * d0) * (sgn * d1);
     if (!isfinite(R)) {
       bad = 1;
       dec = 0;
@@ -672,6 +737,8 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
       if (t0) latch(c, ST_CAPACITY);
       dec = 0;
     }
+    }
+    ++j;
     if (!dec) continue;
     kcur += (kind == 0) ? 1 : -1;
     if (R < 0.0) sign = -sign;
