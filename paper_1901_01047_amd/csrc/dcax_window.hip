@@ -310,11 +310,16 @@ __global__ void __launch_bounds__(WG) k_gather(const View<T>* __restrict__ vs) {
   }
 }
 
+// inner-dimension steps per pass of the candidate GEMMs and the Gram: two
+// with up to 8 wavefronts, one with 16 (whose register budget is half)
+template <int NW> struct Unroll { static constexpr int value = NW >= 16 ? 1 : 2; };
+
 // The candidate GEMMs and the Gram kernel split the inner dimension (the
 // order k) over the NW wavefronts of a workgroup: 16 when a launch has few
-// workgroups (a single walker: short chains of dependent loads per
-// wavefront, many loads in flight), 4 for large batches (enough workgroups
-// already; fewer idle wavefronts on small walkers).
+// workgroups (a single walker:
+// short chains of dependent loads per wavefront, many loads in flight), 4
+// for large batches (enough workgroups already; fewer idle wavefronts on
+// small walkers).
 
 // ------------------------------------------------------- candidate rows
 // X_c = W_c N for all candidates and both spins (an nC x k0 x k0 product on
@@ -326,19 +331,22 @@ __global__ void __launch_bounds__(WG) k_gather(const View<T>* __restrict__ vs) {
 // load latency, not by bandwidth.
 template <typename T, int NW>
 __global__ void __launch_bounds__(NW * 64) k_cand_x(const View<T>* __restrict__ vs) {
-  constexpr int GWV = NW;
+  constexpr int GWV = NW, UNR = Unroll<NW>::value;
   typedef typename Mfma<T>::acc_t acc_t;
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
   if (!c->active) return;
-  const int nC = c->nC;
-  const int k0 = c->k0;
+  // sizes read as wavefront-uniform values, so that the loops below branch
+  // on scalars and their loads can be issued together
+  const int nC = uni(c->nC);
+  const int k0 = uni(c->k0);
   if (nC == 0) return;
   const int sp = blockIdx.y;
   const auto N = gp(w.N[sp]);
   const auto Wm = gp(w.W[sp]);
   const auto R = gp(w.R[sp]);
   const auto cand_el = gp(w.cand_el);
+  const size_t ld = uni((long long)w.ld), cap = uni((long long)w.cap);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nRB = (nC + 15) >> 4;
@@ -349,18 +357,30 @@ __global__ void __launch_bounds__(NW * 64) k_cand_x(const View<T>* __restrict__ 
     acc_t acc[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) acc[rb] = acc_t{0, 0, 0, 0};
-#pragma unroll 4
-    for (int i0 = 4 * wv; i0 < k0; i0 += 4 * GWV) {
-      const int ik = i0 + lk;
-      const bool kin = ik < k0;
-      const T b = (kin && jc < k0) ? N[ik + (size_t)jc * w.ld] : (T)0;
+    // UNR steps of the wavefront's share of the inner dimension per pass,
+    // their loads issued together: addresses are clamped into the matrices
+    // and out-of-range values multiplied by zero (a select would let the
+    // compiler sink each load into its own branch)
+    const int jcc = jc < k0 ? jc : 0;
+    for (int i0 = 4 * wv; i0 < k0; i0 += 4 * UNR * GWV) {
+      T bv[UNR], av[UNR][4];
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-        if (rb < nRB) {
+      for (int u = 0; u < UNR; ++u) {
+        const int ik = i0 + 4 * GWV * u + lk;
+        const bool kin = ik < k0;
+        const int ikc = kin ? ik : 0;
+        bv[u] = N[ikc + (size_t)jcc * ld] * (T)((kin && jc < k0) ? 1 : 0);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
           const int cr = rb * 16 + li;
-          const T a = (kin && cr < nC) ? Wm[(size_t)cr * w.cap + ik] : (T)0;
-          acc[rb] = Mfma<T>::run(a, b, acc[rb]);
+          av[u][rb] = Wm[(size_t)(cr < nC ? cr : 0) * cap + ikc] * (T)((kin && cr < nC) ? 1 : 0);
         }
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+          if (rb < nRB) acc[rb] = Mfma<T>::run(av[u][rb], bv[u], acc[rb]);
     }
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) red[wv][rb][lane] = acc[rb];
@@ -372,7 +392,7 @@ __global__ void __launch_bounds__(NW * 64) k_cand_x(const View<T>* __restrict__ 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int cr = rb * 16 + Mfma<T>::row(lane, r);
-        if (cr < nC && jc < k0) R[(size_t)cand_el[cr] * w.cap + jc] = sum[r];
+        if (cr < nC && jc < k0) R[(size_t)cand_el[cr] * cap + jc] = sum[r];
       }
     }
     __syncthreads();      // red is rewritten by the next tile
@@ -428,14 +448,15 @@ __global__ void __launch_bounds__(NW * 64) k_gram_rows(const View<T>* __restrict
 // Matrix-core form for batches: one workgroup per 16 candidates and spin.
 template <typename T, int NW>
 __global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs) {
-  constexpr int GWV = NW, GW = NW * 64;
+  constexpr int GWV = NW, GW = NW * 64, UNR = Unroll<NW>::value;
   typedef typename Mfma<double>::acc_t acc_t;
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
   if (!c->active) return;
   const int sp = blockIdx.y;
-  const int nE = c->nE;
-  const int k0 = c->k0, nC = c->nC;
+  const int nE = uni(c->nE);
+  const int k0 = uni(c->k0), nC = uni(c->nC);
+  const size_t cap = uni((long long)w.cap);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nRB = (nE + 15) >> 4;
@@ -451,18 +472,27 @@ __global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs
     acc_t acc[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) acc[rb] = acc_t{0, 0, 0, 0};
-#pragma unroll 4
-    for (int i0 = 4 * wv; i0 < k0; i0 += 4 * GWV) {
-      const int ik = i0 + lk;
-      const bool kin = ik < k0;
-      const double b = (kin && cc < nC) ? (double)gcol[(size_t)cc * w.cap + ik] : 0.0;
+    // UNR steps per pass, loads issued together (clamped, zero-weighted)
+    const int ccc = cc < nC ? cc : 0;
+    for (int i0 = 4 * wv; i0 < k0; i0 += 4 * UNR * GWV) {
+      double bv[UNR], av[UNR][4];
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-        if (rb < nRB) {
+      for (int u = 0; u < UNR; ++u) {
+        const int ik = i0 + 4 * GWV * u + lk;
+        const bool kin = ik < k0;
+        const int ikc = kin ? ik : 0;
+        bv[u] = (double)gcol[(size_t)ccc * cap + ikc] * ((kin && cc < nC) ? 1.0 : 0.0);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
           const int x = rb * 16 + li;
-          const double a = (kin && x < nE) ? (double)R[(size_t)x * w.cap + ik] : 0.0;
-          acc[rb] = Mfma<double>::run(a, b, acc[rb]);
+          av[u][rb] = (double)R[(size_t)(x < nE ? x : 0) * cap + ikc] * ((kin && x < nE) ? 1.0 : 0.0);
         }
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+          if (rb < nRB) acc[rb] = Mfma<double>::run(av[u][rb], bv[u], acc[rb]);
     }
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) red[wv][rb][lane] = acc[rb];
@@ -975,14 +1005,15 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
 // partial tiles are summed in LDS in a fixed order.
 template <typename T, int NW>
 __global__ void __launch_bounds__(NW * 64) k_ygemm(const View<T>* __restrict__ vs) {
-  constexpr int GWV = NW;
+  constexpr int GWV = NW, UNR = Unroll<NW>::value;
   typedef typename Mfma<T>::acc_t acc_t;
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
   if (!c->active) return;
-  const int mi = c->mi, k0 = c->k0;
+  const int mi = uni(c->mi), k0 = uni(c->k0);
   if (mi == 0) return;
   const int sp = blockIdx.y;
+  const size_t ld = uni((long long)w.ld);
   const auto N = gp(w.N[sp]);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -1003,17 +1034,25 @@ __global__ void __launch_bounds__(NW * 64) k_ygemm(const View<T>* __restrict__ v
     acc_t acc[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
-#pragma unroll 4
-    for (int j0 = 4 * wv; j0 < k0; j0 += 4 * GWV) {
-      const int jk = j0 + lk;
-      const bool kin = jk < k0;
-      const T a = (kin && ir < k0) ? N[ir + (size_t)jk * w.ld] : (T)0;
+    // UNR steps per pass, loads issued together (clamped, zero-weighted)
+    const int irc = ir < k0 ? ir : 0;
+    for (int j0 = 4 * wv; j0 < k0; j0 += 4 * UNR * GWV) {
+      T av[UNR], bv[UNR][4];
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
-        if (cb < ncb) {
-          const T b = (kin && goff[cb] >= 0) ? gcol[goff[cb] + jk] : (T)0;
-          acc[cb] = Mfma<T>::run(a, b, acc[cb]);
-        }
+      for (int u = 0; u < UNR; ++u) {
+        const int jk = j0 + 4 * GWV * u + lk;
+        const bool kin = jk < k0;
+        const int jkc = kin ? jk : 0;
+        av[u] = N[irc + (size_t)jkc * ld] * (T)((kin && ir < k0) ? 1 : 0);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          bv[u][cb] = gcol[(goff[cb] >= 0 ? goff[cb] : 0) + jkc] * (T)((kin && goff[cb] >= 0) ? 1 : 0);
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          if (cb < ncb) acc[cb] = Mfma<T>::run(av[u], bv[u][cb], acc[cb]);
     }
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) red[wv][cb][lane] = acc[cb];
@@ -1133,33 +1172,51 @@ __device__ inline void fold_tile(T* C, int ldc, const T* A, int lda, const T* B,
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int jb = j0 + wv * 16;
   const int li = lane & 15, lk = lane >> 4;
+  // the tile of C is loaded up front (addresses below cap in both
+  // dimensions are inside N) and added after the products, so that its loads
+  // and the panels' overlap
+  T cv[4][4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int ii = i0 + rb * 16 + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cv[rb][r] = Cg[ii + (size_t)(jb + Mfma<T>::row(lane, r)) * ldc];
+  }
   typename Mfma<T>::acc_t acc[4];
 #pragma unroll
+  for (int rb = 0; rb < 4; ++rb) acc[rb] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+  // Sixteen steps of the inner dimension per pass, all their loads issued
+  // before the first product.  Rows and columns outside the tile are read
+  // (the panels hold KS_MAX rows of cap entries, so every address is in
+  // bounds) but never stored; steps beyond K are zeroed, since the panels'
+  // unused rows hold earlier windows' data.
+  for (int s0 = 0; s0 < K; s0 += 16) {
+    T bv[4], av[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int sk = s0 + 4 * u + lk;
+      const bool kin = sk < K;
+      const size_t skc = kin ? (size_t)sk : 0;
+      const T bb = Bg[skc * ldb + jb + li];
+      bv[u] = kin ? bb : (T)0;
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const T aa = Ag[skc * lda + i0 + rb * 16 + li];
+        av[u][rb] = kin ? aa : (T)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) acc[rb] = Mfma<T>::run(bv[u], av[u][rb], acc[rb]);
+  }
+#pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
     const int ii = i0 + rb * 16 + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int jj = jb + Mfma<T>::row(lane, r);
-      acc[rb][r] = (ii < M && jj < Nn) ? Cg[ii + (size_t)jj * ldc] : (T)0;
-    }
-  }
-  for (int s = 0; s < K; s += 4) {
-    const int sk = s + lk;
-    const T a = (sk < K && jb + li < Nn) ? Bg[(size_t)sk * ldb + jb + li] : (T)0;
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const int ii = i0 + rb * 16 + li;
-      const T b = (sk < K && ii < M) ? Ag[(size_t)sk * lda + ii] : (T)0;
-      acc[rb] = Mfma<T>::run(a, b, acc[rb]);
-    }
-  }
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb) {
-    const int ii = i0 + rb * 16 + li;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int jj = jb + Mfma<T>::row(lane, r);
-      if (ii < M && jj < Nn) Cg[ii + (size_t)jj * ldc] = acc[rb][r];
+      if (ii < M && jj < Nn) Cg[ii + (size_t)jj * ldc] = cv[rb][r] + acc[rb][r];
     }
   }
 }
@@ -1172,7 +1229,7 @@ __global__ void __launch_bounds__(WG) k_fold(const View<T>* __restrict__ vs) {
   const int sp = blockIdx.z & 1;
   const Ctl* c = w.ctl;
   if (!c->active) return;
-  const int kx = c->kx, m = c->m;
+  const int kx = uni(c->kx), m = uni(c->m);
   if (m == 0) return;
   // 64 x 64 tiles of N, grid-strided over blockIdx.x
   const int nt = (kx + 63) >> 6;
