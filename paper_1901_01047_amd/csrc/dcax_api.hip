@@ -465,7 +465,7 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   hipEvent_t e_a0 = w->tev(timed), e_a1 = w->tev(timed);
   hipExtLaunchKernelGGL(k_accept<T>, dim3(1, 1, W), dim3(AW), 0, s, e_a0, e_a1, 0, vs);
   w->mark(w->pend_accept, e_a0, e_a1);
-  if (wide) hipLaunchKernelGGL((k_ygemm<T, 16>), dim3(g16, 2, W), dim3(1024), 0, s, vs);
+  if (wide) hipLaunchKernelGGL((k_ygemm<T, 8>), dim3(g16, 2, W), dim3(512), 0, s, vs);
   else hipLaunchKernelGGL((k_ygemm<T, 4>), dim3(g16, 2, W), dim3(256), 0, s, vs);
   hipLaunchKernelGGL(k_fold_prep<T>, dim3(spread(cdiv(kx, 64), W, 2), 2, W), dim3(WG), 0, s, vs);
   hipEvent_t e_f0 = w->tev(timed), e_f1 = w->tev(timed);

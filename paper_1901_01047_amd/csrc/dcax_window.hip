@@ -310,16 +310,50 @@ __global__ void __launch_bounds__(WG) k_gather(const View<T>* __restrict__ vs) {
   }
 }
 
-// inner-dimension steps per pass of the candidate GEMMs and the Gram: two
-// with up to 8 wavefronts, one with 16 (whose register budget is half)
-template <int NW> struct Unroll { static constexpr int value = NW >= 16 ? 1 : 2; };
+// Four consecutive elements of a global array (16-byte aligned) in one or
+// two vector loads.
+template <typename T> struct Load4;
+template <> struct Load4<double> {
+  __device__ static inline void run(const __attribute__((address_space(1))) double* p, double (&v)[4]) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const auto q = (const __attribute__((address_space(1))) d2*)p;
+    const d2 a = q[0], b = q[1];
+    v[0] = a[0];
+    v[1] = a[1];
+    v[2] = b[0];
+    v[3] = b[1];
+  }
+};
+template <> struct Load4<float> {
+  __device__ static inline void run(const __attribute__((address_space(1))) float* p, float (&v)[4]) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 a = *(const __attribute__((address_space(1))) f4*)p;
+    v[0] = a[0];
+    v[1] = a[1];
+    v[2] = a[2];
+    v[3] = a[3];
+  }
+};
+
+// Four consecutive elements p[i0 .. i0+3] (i0 a multiple of 4, the row
+// 16-byte aligned): vector loads when the caller knows them all valid
+// (full), else element by element with those at or past n read as zero.
+template <typename T, typename P>
+__device__ inline void load4_row(P p, int i0, int n, bool full, T (&v)[4]) {
+  if (full) {
+    Load4<T>::run(p + i0, v);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = (i0 + s < n) ? p[i0 + s] : (T)0;
+  }
+}
 
 // The candidate GEMMs and the Gram kernel split the inner dimension (the
-// order k) over the NW wavefronts of a workgroup: 16 when a launch has few
-// workgroups (a single walker:
-// short chains of dependent loads per wavefront, many loads in flight), 4
-// for large batches (enough workgroups already; fewer idle wavefronts on
-// small walkers).
+// order k) over the NW wavefronts of a workgroup: 16 (8 for the Y product,
+// whose registers need it) when a launch has few workgroups (a single
+// walker: short chains of dependent loads per wavefront, many loads in
+// flight), 4 for large batches (enough workgroups already; fewer idle
+// wavefronts on small walkers).
 
 // ------------------------------------------------------- candidate rows
 // X_c = W_c N for all candidates and both spins (an nC x k0 x k0 product on
@@ -331,7 +365,7 @@ template <int NW> struct Unroll { static constexpr int value = NW >= 16 ? 1 : 2;
 // load latency, not by bandwidth.
 template <typename T, int NW>
 __global__ void __launch_bounds__(NW * 64) k_cand_x(const View<T>* __restrict__ vs) {
-  constexpr int GWV = NW, UNR = Unroll<NW>::value;
+  constexpr int GWV = NW;
   typedef typename Mfma<T>::acc_t acc_t;
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
@@ -357,30 +391,58 @@ __global__ void __launch_bounds__(NW * 64) k_cand_x(const View<T>* __restrict__ 
     acc_t acc[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) acc[rb] = acc_t{0, 0, 0, 0};
-    // UNR steps of the wavefront's share of the inner dimension per pass,
-    // their loads issued together: addresses are clamped into the matrices
-    // and out-of-range values multiplied by zero (a select would let the
-    // compiler sink each load into its own branch)
+    // The inner dimension in blocks of 16 rows of N, dealt to the
+    // wavefronts in turn.  Step s of a block pairs row i0 + 4 lk + s with
+    // k-slot lk, so that each lane reads four consecutive rows of its column
+    // of N and of its row of W (vector loads; the 16 rows of a column are
+    // one 128-byte line); columns and candidates beyond the sizes are read
+    // from valid ones and zeroed.
     const int jcc = jc < k0 ? jc : 0;
-    for (int i0 = 4 * wv; i0 < k0; i0 += 4 * UNR * GWV) {
-      T bv[UNR], av[UNR][4];
+    const T jmask = (T)(jc < k0 ? 1 : 0);
+    if constexpr (NW < 8) {
+      // batches: two steps per pass, lighter on registers (occupancy matters
+      // more than vector loads when many workgroups share a compute unit)
+      for (int i0 = 4 * wv; i0 < k0; i0 += 8 * GWV) {
+        T bv[2], av[2][4];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int ik = i0 + 4 * GWV * u + lk;
-        const bool kin = ik < k0;
-        const int ikc = kin ? ik : 0;
-        bv[u] = N[ikc + (size_t)jcc * ld] * (T)((kin && jc < k0) ? 1 : 0);
+        for (int u = 0; u < 2; ++u) {
+          const int ik = i0 + 4 * GWV * u + lk;
+          const bool kin = ik < k0;
+          const int ikc = kin ? ik : 0;
+          bv[u] = N[ikc + (size_t)jcc * ld] * (T)(kin ? 1 : 0) * jmask;
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-          const int cr = rb * 16 + li;
-          av[u][rb] = Wm[(size_t)(cr < nC ? cr : 0) * cap + ikc] * (T)((kin && cr < nC) ? 1 : 0);
+          for (int rb = 0; rb < 4; ++rb) {
+            const int cr = rb * 16 + li;
+            av[u][rb] = Wm[(size_t)(cr < nC ? cr : 0) * cap + ikc] * (T)((kin && cr < nC) ? 1 : 0);
+          }
         }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+            if (rb < nRB) acc[rb] = Mfma<T>::run(av[u][rb], bv[u], acc[rb]);
+      }
+    } else
+    for (int i0 = 16 * uni(wv); i0 < k0; i0 += 16 * GWV) {
+      const int ib = i0 + 4 * lk;
+      const bool full = i0 + 16 <= k0;      // the same in every lane
+      T bv[4], av[4][4];
+      load4_row(N + (size_t)jcc * ld, ib, k0, full, bv);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const int cr = rb * 16 + li;
+        load4_row(Wm + (size_t)(cr < nC ? cr : 0) * cap, ib, k0, full, av[rb]);
+        if (cr >= nC)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) av[rb][u] = (T)0;
       }
 #pragma unroll
-      for (int u = 0; u < UNR; ++u)
+      for (int u = 0; u < 4; ++u) {
+        bv[u] *= jmask;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
-          if (rb < nRB) acc[rb] = Mfma<T>::run(av[u][rb], bv[u], acc[rb]);
+          if (rb < nRB) acc[rb] = Mfma<T>::run(av[rb][u], bv[u], acc[rb]);
+      }
     }
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) red[wv][rb][lane] = acc[rb];
@@ -448,7 +510,7 @@ __global__ void __launch_bounds__(NW * 64) k_gram_rows(const View<T>* __restrict
 // Matrix-core form for batches: one workgroup per 16 candidates and spin.
 template <typename T, int NW>
 __global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs) {
-  constexpr int GWV = NW, GW = NW * 64, UNR = Unroll<NW>::value;
+  constexpr int GWV = NW, GW = NW * 64;
   typedef typename Mfma<double>::acc_t acc_t;
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
@@ -472,27 +534,49 @@ __global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs
     acc_t acc[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) acc[rb] = acc_t{0, 0, 0, 0};
-    // UNR steps per pass, loads issued together (clamped, zero-weighted)
+    // blocks of 16 of the inner dimension, four consecutive per lane (as
+    // in the candidate rows)
     const int ccc = cc < nC ? cc : 0;
-    for (int i0 = 4 * wv; i0 < k0; i0 += 4 * UNR * GWV) {
-      double bv[UNR], av[UNR][4];
+    if constexpr (NW < 8) {
+      // batches: two steps per pass (see the candidate rows)
+      for (int i0 = 4 * wv; i0 < k0; i0 += 8 * GWV) {
+        double bv[2], av[2][4];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int ik = i0 + 4 * GWV * u + lk;
-        const bool kin = ik < k0;
-        const int ikc = kin ? ik : 0;
-        bv[u] = (double)gcol[(size_t)ccc * cap + ikc] * ((kin && cc < nC) ? 1.0 : 0.0);
+        for (int u = 0; u < 2; ++u) {
+          const int ik = i0 + 4 * GWV * u + lk;
+          const bool kin = ik < k0;
+          const int ikc = kin ? ik : 0;
+          bv[u] = (double)gcol[(size_t)ccc * cap + ikc] * ((kin && cc < nC) ? 1.0 : 0.0);
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-          const int x = rb * 16 + li;
-          av[u][rb] = (double)R[(size_t)(x < nE ? x : 0) * cap + ikc] * ((kin && x < nE) ? 1.0 : 0.0);
+          for (int rb = 0; rb < 4; ++rb) {
+            const int x = rb * 16 + li;
+            av[u][rb] = (double)R[(size_t)(x < nE ? x : 0) * cap + ikc] * ((kin && x < nE) ? 1.0 : 0.0);
+          }
         }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+            if (rb < nRB) acc[rb] = Mfma<double>::run(av[u][rb], bv[u], acc[rb]);
+      }
+    } else
+    for (int i0 = 16 * uni(wv); i0 < k0; i0 += 16 * GWV) {
+      const int ib = i0 + 4 * lk;
+      const bool full = i0 + 16 <= k0;      // the same in every lane
+      T bt[4], at[4][4];
+      load4_row(gcol + (size_t)ccc * cap, ib, k0, full, bt);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const int x = rb * 16 + li;
+        load4_row(R + (size_t)(x < nE ? x : 0) * cap, ib, k0, full, at[rb]);
       }
 #pragma unroll
-      for (int u = 0; u < UNR; ++u)
+      for (int u = 0; u < 4; ++u) {
+        const double b = (cc < nC) ? (double)bt[u] : 0.0;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
-          if (rb < nRB) acc[rb] = Mfma<double>::run(av[u][rb], bv[u], acc[rb]);
+          if (rb < nRB) acc[rb] = Mfma<double>::run(rb * 16 + li < nE ? (double)at[rb][u] : 0.0, b, acc[rb]);
+      }
     }
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) red[wv][rb][lane] = acc[rb];
@@ -1005,7 +1089,7 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
 // partial tiles are summed in LDS in a fixed order.
 template <typename T, int NW>
 __global__ void __launch_bounds__(NW * 64) k_ygemm(const View<T>* __restrict__ vs) {
-  constexpr int GWV = NW, UNR = Unroll<NW>::value;
+  constexpr int GWV = NW;
   typedef typename Mfma<T>::acc_t acc_t;
   const View<T>& w = vs[blockIdx.z];
   const Ctl* c = w.ctl;
@@ -1034,25 +1118,53 @@ __global__ void __launch_bounds__(NW * 64) k_ygemm(const View<T>* __restrict__ v
     acc_t acc[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
-    // UNR steps per pass, loads issued together (clamped, zero-weighted)
+    // blocks of 16 columns of N, four consecutive per lane: the lane's four
+    // column entries (each load coalesced over the 16 rows of the tile) and
+    // four consecutive entries of each g column (vector loads)
     const int irc = ir < k0 ? ir : 0;
-    for (int j0 = 4 * wv; j0 < k0; j0 += 4 * UNR * GWV) {
-      T av[UNR], bv[UNR][4];
+    const T imask = (T)(ir < k0 ? 1 : 0);
+    if constexpr (NW < 8) {
+      // batches: two steps per pass (see the candidate rows)
+      for (int j0 = 4 * wv; j0 < k0; j0 += 8 * GWV) {
+        T av[2], bv[2][4];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int jk = j0 + 4 * GWV * u + lk;
-        const bool kin = jk < k0;
-        const int jkc = kin ? jk : 0;
-        av[u] = N[irc + (size_t)jkc * ld] * (T)((kin && ir < k0) ? 1 : 0);
+        for (int u = 0; u < 2; ++u) {
+          const int jk = j0 + 4 * GWV * u + lk;
+          const bool kin = jk < k0;
+          const int jkc = kin ? jk : 0;
+          av[u] = N[irc + (size_t)jkc * ld] * (T)(kin ? 1 : 0) * imask;
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-          bv[u][cb] = gcol[(goff[cb] >= 0 ? goff[cb] : 0) + jkc] * (T)((kin && goff[cb] >= 0) ? 1 : 0);
+          for (int cb = 0; cb < 4; ++cb)
+            bv[u][cb] = gcol[(goff[cb] >= 0 ? goff[cb] : 0) + jkc] * (T)((kin && goff[cb] >= 0) ? 1 : 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+            if (cb < ncb) acc[cb] = Mfma<T>::run(av[u], bv[u][cb], acc[cb]);
+      }
+    } else
+    for (int j0 = 16 * uni(wv); j0 < k0; j0 += 16 * GWV) {
+      const int jb = j0 + 4 * lk;
+      const bool full = j0 + 16 <= k0;      // the same in every lane
+      T av[4], bt[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int jk = jb + u;
+        av[u] = (full || jk < k0) ? N[irc + (size_t)(full || jk < k0 ? jk : 0) * ld] : (T)0;
       }
 #pragma unroll
-      for (int u = 0; u < UNR; ++u)
+      for (int cb = 0; cb < 4; ++cb) {
+        load4_row(gcol + (goff[cb] >= 0 ? goff[cb] : 0), jb, k0, full, bt[cb]);
+        if (goff[cb] < 0)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) bt[cb][u] = (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
-          if (cb < ncb) acc[cb] = Mfma<T>::run(av[u], bv[u][cb], acc[cb]);
+          if (cb < ncb) acc[cb] = Mfma<T>::run(av[u] * imask, bt[cb][u], acc[cb]);
     }
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) red[wv][cb][lane] = acc[cb];
@@ -1292,7 +1404,7 @@ __global__ void __launch_bounds__(WG) k_compact_move(const View<T>* __restrict__
   template __global__ void k_gram_rows<T, 16>(const View<T>*);           \
   template __global__ void k_accept<T>(const View<T>*);                  \
   template __global__ void k_ygemm<T, 4>(const View<T>*);                \
-  template __global__ void k_ygemm<T, 16>(const View<T>*);               \
+  template __global__ void k_ygemm<T, 8>(const View<T>*);                \
   template __global__ void k_fold_prep<T>(const View<T>*);               \
   template __global__ void k_fold<T>(const View<T>*);                    \
   template __global__ void k_compact_move<T>(const View<T>*);
