@@ -203,6 +203,8 @@ __global__ void k_refresh_begin(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
   w.detsign[0] = 1.0;
   w.detsign[1] = 1.0;
+  *reinterpret_cast<unsigned int*>(w.gjc[0]) = 0u;
+  *reinterpret_cast<unsigned int*>(w.gjc[1]) = 0u;
   w.ctl->drift = 0.0;
 }
 
@@ -488,7 +490,11 @@ void enqueue_refresh(dcax_walker w, int first, int n, int kmax, bool measure) {
   if (kmax == 0) return;
   hipLaunchKernelGGL(k_build_ninv<T>, dim3(cdiv(kmax, WG), kmax, n), dim3(WG), 0, s, vs);
   for (int p0 = 0; p0 < kmax; p0 += NB) {
-    hipLaunchKernelGGL(k_gj_panel<T>, dim3(2, 1, n), dim3(WG), 0, s, vs, p0);
+    if (kmax <= PANEL_ROWS)
+      hipLaunchKernelGGL(k_gj_panel<T>, dim3(2, 1, n), dim3(WG), 0, s, vs, p0);
+    else
+      for (int c = 0; c <= std::min(NB, kmax - p0); ++c)
+        hipLaunchKernelGGL(k_gj_col<T>, dim3(cdiv(kmax, WG), 2, n), dim3(WG), 0, s, vs, p0, c);
     hipLaunchKernelGGL(k_gj_prep<T>, dim3(cdiv(kmax, WG), 2, n), dim3(WG), 0, s, vs, p0);
     hipLaunchKernelGGL(k_gj_update<T>, dim3(cdiv(kmax, 64), cdiv(kmax, 64), 2 * n), dim3(WG), 0, s, vs, p0);
   }
@@ -683,6 +689,7 @@ size_t walker_bytes(const WalkerHost& x) {
     add(sizeof(double) * cap * NB);              // Tm
     add(sizeof(int) * cap);                      // ipiv
     add(sizeof(int) * cap);                      // perm
+    add(sizeof(double) * gjc_len(cap));          // gjc
     add(sizeof(T) * kp * kp);                    // m_Ms
     add(sizeof(double) * 2 * Nc * Nc * nf);      // m_Mab
   }
@@ -762,6 +769,7 @@ void wire_walker(dcax_walker w, WalkerHost& x, int wid, char* base, Ctl* ctl) {
     v.Tm[sp] = (double*)take(sizeof(double) * cap * NB);
     v.ipiv[sp] = (int*)take(sizeof(int) * cap);
     v.perm[sp] = (int*)take(sizeof(int) * cap);
+    v.gjc[sp] = (double*)take(sizeof(double) * gjc_len(cap));
     v.m_Ms[sp] = (T*)take(sizeof(T) * kp * kp);
     v.m_Mab[sp] = (double*)take(sizeof(double) * 2 * Nc * Nc * nf);
   }

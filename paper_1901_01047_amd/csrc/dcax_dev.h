@@ -119,6 +119,7 @@ struct View {
   double* Tm[2];              // [NB][cap] panel rows
   int* ipiv[2];               // [cap]
   int* perm[2];               // [cap]
+  double* gjc[2];             // column-step pivot records (gjc_len(cap))
   double* blkmax;             // per-block maxima of the drift
   double* detsign;            // [2]
   // measurement scratch

@@ -3,8 +3,10 @@
 // N_sigma^{-1} = e^{V_sigma} - g (e^{V_sigma} - 1) is assembled from k^2
 // propagator gathers (Sec. 2.3's definition of N through Z_k) and inverted by
 // blocked Gauss-Jordan elimination with partial pivoting:
-//   for each panel of NB columns, one workgroup eliminates the panel columns
-//   (pivot search over the not yet pivoted rows, row swap, in-place GJ step);
+//   for each panel of NB columns, the panel columns are eliminated one by one
+//   (pivot search over the not yet pivoted rows, row swap, in-place GJ step):
+//   by one workgroup in LDS for orders up to PANEL_ROWS, otherwise by one
+//   launch per column over workgroups that hold one panel row per thread;
 //   the other columns receive the panel's row swaps and then the rank-NB
 //   update  A_{.x} <- P_{.J} A_{Jx} + (A_{.x} with rows J zeroed),
 //   where P holds the eliminated panel columns, run on the MFMA fold tile.
@@ -16,6 +18,8 @@
 namespace dcax {
 
 constexpr int NB = 32;
+constexpr int GJC_RS = 2, GJC_OC = 2 + NB, GJC_SLOT = 2 + 2 * NB;
+inline size_t gjc_len(int cap) { return GJC_SLOT + 2 * (size_t)((cap + WG - 1) / WG); }
 
 template <typename T>
 __global__ void __launch_bounds__(WG) k_build_ninv(const View<T>* __restrict__ vs) {
@@ -152,6 +156,144 @@ __global__ void __launch_bounds__(WG) k_gj_panel(const View<T>* __restrict__ vs,
     dsign = gj_panel_steps(PanelGlobal{Mg, ldm, p0}, k, p0, nb, gp(w.ipiv[sp]), w.ctl);
   }
   if (t == 0) w.detsign[sp] *= dsign;
+}
+
+// Column-step panel elimination for orders above PANEL_ROWS.  The panel rows
+// are spread over workgroups, one row of the panel per thread (in registers).
+// Launch cidx (0 .. nb) first applies the Gauss-Jordan step of panel column
+// cidx - 1, whose pivot the previous launch chose, and stores the rows; then
+// (cidx < nb) each workgroup publishes its best pivot candidate for column
+// cidx among rows >= p0 + cidx, and the last workgroup to finish reduces the
+// candidates and writes the pivot record that the next launch applies: the
+// pivot row divided by the pivot (its own entry 1 / a_pp) and the old row at
+// the pivot position.  The arithmetic and tie rule are those of the LDS form.
+// Record layout (gjc, doubles per spin): [0] arrival counter (unsigned),
+// [1] pivot row index, [GJC_RS ..) scaled pivot row, [GJC_OC ..) old row at
+// the pivot position, [GJC_SLOT ..) (|value|, row) per workgroup.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, int p0, int cidx) {
+  const View<T>& w = vs[blockIdx.z];
+  const int k = w.ctl->k;
+  if (p0 >= k) return;
+  const int nb = (k - p0 < NB) ? k - p0 : NB;
+  const int nwg = (k + WG - 1) / WG;
+  if (cidx > nb || (int)blockIdx.x >= nwg) return;
+  const int sp = blockIdx.y;
+  const auto Mg = gp(w.M[sp]);
+  const size_t ld = w.cap;
+  double* rec = w.gjc[sp];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int r = blockIdx.x * WG + t;
+  const bool live = r < k;
+  const size_t ro = live ? (size_t)r : 0;
+  double a[NB];
+#pragma unroll
+  for (int x = 0; x < NB; ++x) a[x] = Mg[ro + (size_t)(p0 + (x < nb ? x : 0)) * ld];
+  if (cidx > 0) {
+    const int cm = cidx - 1, cp = p0 + cm;
+    const int pv = (int)rec[1];
+    const double* rs = rec + GJC_RS;
+    const double* oc = rec + GJC_OC;
+    if (r == cp) {
+#pragma unroll
+      for (int x = 0; x < NB; ++x) a[x] = rs[x];
+    } else {
+      if (r == pv)
+#pragma unroll
+        for (int x = 0; x < NB; ++x) a[x] = oc[x];
+      double f = 0.0;
+#pragma unroll
+      for (int x = 0; x < NB; ++x) f = (x == cm) ? a[x] : f;
+#pragma unroll
+      for (int x = 0; x < NB; ++x) a[x] = (x == cm) ? -f * rs[x] : a[x] - f * rs[x];
+    }
+    if (live)
+#pragma unroll
+      for (int x = 0; x < NB; ++x)
+        if (x < nb) Mg[r + (size_t)(p0 + x) * ld] = a[x];
+  }
+  if (cidx == nb) return;
+  const int c = p0 + cidx;
+  double best = -1.0;
+  int bi = k;
+  if (live && r >= c) {
+#pragma unroll
+    for (int x = 0; x < NB; ++x) best = (x == cidx) ? fabs(a[x]) : best;
+    bi = r;
+  }
+  __shared__ double vmax_s[WG / 64];
+  __shared__ int imax_s[WG / 64];
+  __shared__ int last_s;
+  argmax_wave(best, bi);
+  if (lane == 0) {
+    vmax_s[wv] = best;
+    imax_s[wv] = bi;
+  }
+  __syncthreads();
+  auto* cnt = reinterpret_cast<unsigned int*>(rec);
+  if (t == 0) {
+    double pv = vmax_s[0];
+    int piv = imax_s[0];
+    for (int x = 1; x < WG / 64; ++x)
+      if (vmax_s[x] > pv || (vmax_s[x] == pv && imax_s[x] < piv)) {
+        pv = vmax_s[x];
+        piv = imax_s[x];
+      }
+    rec[GJC_SLOT + 2 * blockIdx.x] = pv;
+    rec[GJC_SLOT + 2 * blockIdx.x + 1] = (double)piv;
+  }
+  // every thread's row stores, then the candidate, before the arrival
+  __threadfence();
+  __syncthreads();
+  if (t == 0) last_s = (atomicAdd(cnt, 1u) == (unsigned)(nwg - 1)) ? 1 : 0;
+  __syncthreads();
+  if (!last_s) return;
+  __threadfence();
+  // last workgroup: reduce the candidates (nwg <= WG)
+  best = -1.0;
+  bi = k;
+  for (int b = t; b < nwg; b += WG) {
+    const double v = rec[GJC_SLOT + 2 * b];
+    const int i = (int)rec[GJC_SLOT + 2 * b + 1];
+    if (v > best || (v == best && i < bi)) {
+      best = v;
+      bi = i;
+    }
+  }
+  argmax_wave(best, bi);
+  __syncthreads();
+  if (lane == 0) {
+    vmax_s[wv] = best;
+    imax_s[wv] = bi;
+  }
+  __syncthreads();
+  double pvv = vmax_s[0];
+  int piv = imax_s[0];
+  for (int x = 1; x < WG / 64; ++x)
+    if (vmax_s[x] > pvv || (vmax_s[x] == pvv && imax_s[x] < piv)) {
+      pvv = vmax_s[x];
+      piv = imax_s[x];
+    }
+  const int pr = (piv >= c && piv < k) ? piv : c;
+  __shared__ double app_s;
+  if (t == cidx) app_s = Mg[pr + (size_t)(p0 + t) * ld];
+  __syncthreads();
+  const double a_pp = app_s;
+  if (t < nb) {
+    const double vp = Mg[pr + (size_t)(p0 + t) * ld];
+    rec[GJC_OC + t] = Mg[c + (size_t)(p0 + t) * ld];
+    rec[GJC_RS + t] = (t == cidx) ? 1.0 / a_pp : vp / a_pp;
+  } else if (t < NB) {
+    rec[GJC_OC + t] = 0.0;
+    rec[GJC_RS + t] = 0.0;
+  }
+  if (t == 0) {
+    rec[1] = (double)pr;
+    w.ipiv[sp][c] = pr;
+    if (!(pvv > 0.0) || !isfinite(pvv)) latch(w.ctl, ST_NUMERIC);
+    w.detsign[sp] *= ((a_pp < 0.0) ? -1.0 : 1.0) * ((pr != c) ? -1.0 : 1.0);
+    *cnt = 0u;
+  }
 }
 
 // Applies the panel's row swaps to the other columns, moves their panel rows
@@ -306,6 +448,7 @@ __global__ void __launch_bounds__(WG) k_drift(const View<T>* __restrict__ vs) {
 #define DCAX_INSTANTIATE_REFRESH(T)                                   \
   template __global__ void k_build_ninv<T>(const View<T>*);           \
   template __global__ void k_gj_panel<T>(const View<T>*, int);        \
+  template __global__ void k_gj_col<T>(const View<T>*, int, int);     \
   template __global__ void k_gj_prep<T>(const View<T>*, int);         \
   template __global__ void k_gj_update<T>(const View<T>*, int);       \
   template __global__ void k_refresh_store<T>(const View<T>*, int);   \

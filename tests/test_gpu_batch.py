@@ -121,3 +121,35 @@ def test_graph_sweeps_equal_eager_sweeps(precision, timing):
     print(f"  graph replays identical; timed {st['window_seconds']:.4f} s", flush=True)
     we.close()
     wg.close()
+
+
+def test_refresh_forms_agree_in_a_batch():
+    """A batch whose largest order exceeds 512 refreshes every walker with the
+    column-step panel form; a walker of order 100 alone takes the LDS form.
+    Both forms make the same pivot choices and the same arithmetic."""
+    print("[batch] refresh forms", flush=True)
+    d = dict(cluster=(4, 0, 0, 4), U=4.0, beta=10.0, mu=-0.3, n_tau=2001, submatrix_k=32, seed=21)
+    p = dcax.make_params(max_order=1024, n_freq=16, refresh_every=0, **d)
+    rng = np.random.default_rng(5)
+    cfg = [(rng.integers(0, 16, size=n).astype(np.int32), rng.random(n) * 10.0,
+            np.where(rng.random(n) < 0.5, 1, -1).astype(np.int32)) for n in (700, 100)]
+    wb = dcax.Walker([p, p])
+    for i, c in enumerate(cfg):
+        wb.set_config(*c, walker=i)
+    drift = wb.refresh()
+    print(f"  batch refresh drift {drift:.2e}", flush=True)
+    assert drift < 1e-9
+    for i, c in enumerate(cfg):
+        w1 = dcax.Walker(p)
+        w1.set_config(*c)
+        for sp in range(2):
+            ib, Nb = wb.copy_N(sp, walker=i)
+            i1, N1 = w1.copy_N(sp)
+            assert np.array_equal(ib, i1)
+            e = np.max(np.abs(Nb - N1)) / np.max(np.abs(N1))
+            print(f"  walker {i} (k={len(i1)}) spin {sp}: max diff {e:.2e}"
+                  f"{' (bit-identical)' if e == 0 else ''}", flush=True)
+            assert e < 1e-12
+        assert wb.stats(walker=i)["sign"] == w1.stats()["sign"]
+        w1.close()
+    wb.close()

@@ -64,16 +64,18 @@ def test_g0_table(name):
     w.close()
 
 
-@pytest.mark.parametrize("name,k", [("2x2_U4_b5", 30), ("4x4_U4_b10", 300), ("4x4_U4_b10", 77)])
+@pytest.mark.parametrize("name,k", [("2x2_U4_b5", 30), ("4x4_U4_b10", 300), ("4x4_U4_b10", 77),
+                                    ("4x4_U4_b10", 700), ("6x6_U6_b20", 1030)])
 def test_refresh_equals_direct_inverse(name, k):
     """Random (unequilibrated) configurations can be very ill-conditioned, so
     the GJ inverse is checked by its backward residual |A N - 1| / (|A| |N|)
-    and against NumPy's LU inverse within 20 cond(A) eps."""
+    and against NumPy's LU inverse within 20 cond(A) eps.  Orders above 512
+    take the column-step panel form (with a narrower last panel here)."""
     print(f"[refresh] {name} k={k}", flush=True)
     m = model(name)
     ow = ctaux.Walker(m, seed=7)
     ow.random_config(k)
-    w = walker(name)
+    w = walker(name, max_order=max(1024, k + 64))
     w.set_config(ow.r, ow.t, ow.s, ow.id)
     assert w.order == k
     ids_o, Nu, Nd = ow.canonical()
