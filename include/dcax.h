@@ -161,7 +161,8 @@ dcax_status dcax_walker_destroy(dcax_walker w);
  *     submatrix_k: L = sweep_length if that is positive; otherwise, during
  *     the first warmup_sweeps sweeps L = max(k, 1) with k the order at the
  *     sweep's start, and when they end L freezes at the mean order over
- *     their second half (rounded, at least 1).  A length that depends on the
+ *     their second half, which holds at least the last of them (rounded,
+ *     at least 1).  A length that depends on the
  *     current state would bias every quantity measured between sweeps, so
  *     measurements belong after the warm-up.  dcax_set_config restarts the
  *     warm-up count.  N is refreshed every refresh_every sweeps (walker 0's

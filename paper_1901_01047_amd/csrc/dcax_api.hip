@@ -142,10 +142,11 @@ template <typename T>
 __device__ void begin_sweep(const View<T>& w, Ctl* c) {
   long long L = c->sweep_len;
   if (L == 0) {
-    // warm-up: the length follows the order; the second half's mean order
-    // becomes the frozen length when the warm-up ends
+    // warm-up: the length follows the order; the mean order over the second
+    // half (which holds at least the last warm-up sweep) becomes the frozen
+    // length when the warm-up ends
     L = c->k > 1 ? c->k : 1;
-    if (2 * c->n_sweeps >= w.warmup) {
+    if (2 * c->n_sweeps >= w.warmup || c->n_sweeps + 1 == w.warmup) {
       c->warm_sum += (double)c->k;
       c->warm_n += 1;
     }

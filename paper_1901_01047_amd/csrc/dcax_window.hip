@@ -1209,9 +1209,22 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
   __shared__ int e_s[KS_MAX], row_s[KS_MAX], cand_s[KS_MAX], slot_s[KS_MAX], ins_s[KS_MAX];
   __shared__ double d_s[KS_MAX];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  for (int idx = t; idx < m * KS_MAX; idx += WG) {
-    const int b = idx % KS_MAX;
-    gi_s[idx] = (b < m) ? w.ginv[sp][idx] : 0.0;
+  {
+    // Gt_S^{-1} rows into LDS, the loads of eight entries per thread together
+    const auto gi = gp(w.ginv[sp]);
+    for (int x0 = t; x0 < m * KS_MAX; x0 += 8 * WG) {
+      double gv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = x0 + u * WG;
+        gv[u] = gi[idx < m * KS_MAX ? idx : x0];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = x0 + u * WG;
+        if (idx < m * KS_MAX) gi_s[idx] = (idx % KS_MAX < m) ? gv[u] : 0.0;
+      }
+    }
   }
   if (t < m) {
     const int e = w.S[t];
@@ -1226,44 +1239,86 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
   const T* R = w.R[sp];
   T* N = w.N[sp];
   const size_t ld = w.ld;
-  // groups of 64 columns, grid-strided over blockIdx.x
+  const T* Y = w.Y[sp];
+  const auto gram = gp(w.gram[sp]);
+  const auto Ag = gp(w.A[sp]);
+  const auto Bg = gp(w.B[sp]);
+  constexpr int NWV = WG / 64;
+  // groups of 64 columns, grid-strided over blockIdx.x.  A wavefront takes
+  // the entries q = wv, wv + 4, ... of S (and of the inserted spins, mi <= m)
+  // eight at a time: the rows of N for B, the entries of A and the extension
+  // of N are loaded together, then stored.
   for (int i0 = blockIdx.x * 64; i0 < kx; i0 += gridDim.x * 64) {
     const int i = i0 + lane;
     const bool live = i < kx;
-    for (int b = wv; b < m; b += WG / 64) {
-      double x = 0.0;
-      if (live) {
-        if (i < k0) x = (double)R[(size_t)e_s[b] * w.cap + i];
-        else x = (cand_s[b] >= 0 && row_s[b] == i) ? 1.0 : 0.0;
+    const int ic = live ? i : 0;
+    const int il = (ic < k0) ? ic : 0;
+    const int insr = (ic >= k0) ? ins_s[ic - k0] : 0;
+    for (int q0 = wv; q0 < m; q0 += 8 * NWV) {
+      T rv[8], tv[8], xv[8];
+      double gv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * NWV;
+        const int sc = q < m ? q : q0;
+        rv[u] = R[(size_t)e_s[sc] * w.cap + il];
+        size_t off;
+        const T* src;
+        if (cand_s[sc] >= 0) {
+          src = Y;
+          off = (ic < k0) ? (size_t)(row_s[sc] - k0) * w.cap + ic : 0;
+        } else {
+          const int p = slot_s[sc];
+          src = (ic < k0) ? N : R;
+          off = (ic < k0) ? ic + (size_t)p * ld : (size_t)insr * w.cap + p;
+        }
+        tv[u] = src[off];
+        gv[u] = gram[insr * KS_MAX + e_s[sc]];
+        xv[u] = R[(size_t)(q < mi ? ins_s[q] : e_s[sc]) * w.cap + il];
       }
-      rv_s[b][lane] = x;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * NWV;
+        if (q < m) {
+          double x = 0.0;
+          if (live) x = (i < k0) ? (double)rv[u] : ((cand_s[q] >= 0 && row_s[q] == i) ? 1.0 : 0.0);
+          rv_s[q][lane] = x;
+        }
+        if (live && q < m) {
+          // A, column-major [s][i]
+          double v;
+          if (cand_s[q] >= 0) {
+            const int jj = row_s[q] - k0;
+            v = (i < k0) ? d_s[q] * (double)tv[u] : (i - k0 == jj ? 1.0 : 0.0) - gv[u];
+          } else {
+            v = (i == slot_s[q] ? 1.0 : 0.0) - (double)tv[u];
+          }
+          Ag[(size_t)q * w.cap + i] = (T)v;
+        }
+        // extension of N (no workgroup reads rows or columns >= k0 of N here)
+        if (live && q < mi) {
+          if (i < k0) N[(k0 + q) + (size_t)i * ld] = xv[u];
+          N[i + (size_t)(k0 + q) * ld] = (i == k0 + q) ? (T)1 : (T)0;
+        }
+      }
     }
     __syncthreads();
     if (live) {
-      // A, column-major [s][i]
-      for (int s = wv; s < m; s += WG / 64) {
-        double v;
-        if (cand_s[s] >= 0) {
-          const int jj = row_s[s] - k0;
-          if (i < k0) v = d_s[s] * (double)w.Y[sp][(size_t)jj * w.cap + i];
-          else v = (i - k0 == jj ? 1.0 : 0.0) - w.gram[sp][ins_s[i - k0] * KS_MAX + e_s[s]];
-        } else {
-          const int p = slot_s[s];
-          const double nip = (i < k0) ? (double)N[i + (size_t)p * ld] : (double)R[(size_t)ins_s[i - k0] * w.cap + p];
-          v = (i == p ? 1.0 : 0.0) - nip;
+      // B, row-major [a][i] = sum_b Gt^{-1}[a][b] Row_{S_b}[i], four rows a
+      // per pass over rv_s (each sum runs over b in order)
+      for (int a0 = wv; a0 < m; a0 += 4 * NWV) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int ar[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ar[u] = (a0 + u * NWV < m) ? a0 + u * NWV : a0;
+        for (int b = 0; b < m; ++b) {
+          const double r = rv_s[b][lane];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[u] += gi_s[ar[u] * KS_MAX + b] * r;
         }
-        w.A[sp][(size_t)s * w.cap + i] = (T)v;
-      }
-      // B, row-major [a][i] = sum_b Gt^{-1}[a][b] Row_{S_b}[i]
-      for (int a = wv; a < m; a += WG / 64) {
-        double acc = 0.0;
-        for (int b = 0; b < m; ++b) acc += gi_s[a * KS_MAX + b] * rv_s[b][lane];
-        w.B[sp][(size_t)a * w.cap + i] = (T)acc;
-      }
-      // extension of N (no workgroup reads rows or columns >= k0 of N here)
-      for (int jj = wv; jj < mi; jj += WG / 64) {
-        if (i < k0) N[(k0 + jj) + (size_t)i * ld] = R[(size_t)ins_s[jj] * w.cap + i];
-        N[i + (size_t)(k0 + jj) * ld] = (i == k0 + jj) ? (T)1 : (T)0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (a0 + u * NWV < m) Bg[(size_t)(a0 + u * NWV) * w.cap + i] = (T)acc[u];
       }
     }
     __syncthreads();      // rv_s is rewritten by the next group

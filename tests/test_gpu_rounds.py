@@ -98,3 +98,34 @@ def test_free_running_rounds_match_single_walkers(precision):
         w1.close()
     assert len({n for n, _ in props}) > 1, "walkers of different sweep lengths made the same number of sweeps"
     wb.close()
+
+
+@pytest.mark.parametrize("warmup", [1, 2])
+def test_sweep_length_freezes_at_the_warm_up_order(warmup):
+    """Sweeps have max(k, 1) proposals (rounded up to a multiple of k_s)
+    during the warm-up, then a length frozen at the mean order over the
+    warm-up's second half, which holds at least its last sweep: with one
+    warm-up sweep from a configuration of order 240, every later sweep keeps
+    that sweep's length (and not the minimal one window)."""
+    print(f"[sweep length] warm-up {warmup}", flush=True)
+    p = params(dict(BATCH[2], seed=31), dcax.DCAX_FP64)
+    p.warmup_sweeps = warmup
+    p.max_order = 1024
+    w = dcax.Walker(p)
+    rng = np.random.default_rng(3)
+    n = 240
+    w.set_config(rng.integers(0, 16, size=n).astype(np.int32), rng.random(n) * 3.0,
+                 np.where(rng.random(n) < 0.5, 1, -1).astype(np.int32))
+    ks = p.submatrix_k
+    first = -(-n // ks) * ks
+    w.sweep(1)
+    assert w.stats()["proposals"] == first
+    k1 = w.order
+    w.sweep(3)
+    per = w.stats()["proposals"] - first
+    print(f"  first sweep {first} proposals, order then {k1}, next three {per}", flush=True)
+    # warm-up 1: frozen at the order 240 of the first sweep's start; warm-up
+    # 2: the second sweep has max(k1, 1) proposals and the length freezes at k1
+    frozen = n if warmup == 1 else max(k1, 1)
+    assert per == 3 * (-(-frozen // ks) * ks)
+    w.close()
