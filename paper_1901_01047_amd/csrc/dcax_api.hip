@@ -456,9 +456,15 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   const int ne = std::min(2 * ks, KS_MAX);   // elements: candidates, targets, second attempts
   const int gx = spread(cdiv(kb1, WG), W, 1);
   hipLaunchKernelGGL(k_gather<T>, dim3(gx, spread(ne, W, gx), W), dim3(WG), 0, s, vs);
-  // few workgroups: 16 wavefronts each; large batches: 4
+  // Candidate rows: 16 wavefronts per workgroup for few workgroups and for
+  // large orders (long column segments per workgroup stream best), 4 for
+  // large batches of small walkers.  Y columns: 8 wavefronts while the row
+  // tiles are few; in FP64, from a few hundred tiles on (a single walker of
+  // order ~5000) the 4-wavefront form streams N faster, in FP32 only from
+  // the batch bound on.
   const int g16 = spread(cdiv(kb1, 16), W, 2);
-  const bool wide = (long long)g16 * 2 * W < 4096;
+  const bool wide = (long long)g16 * 2 * W < 4096 || kb1 >= 1024;
+  const bool ywide = (long long)g16 * 2 * W < (sizeof(T) == 8 ? 512 : 4096);
   if (wide) hipLaunchKernelGGL((k_cand_x<T, 16>), dim3(g16, 2, W), dim3(1024), 0, s, vs);
   else hipLaunchKernelGGL((k_cand_x<T, 4>), dim3(g16, 2, W), dim3(256), 0, s, vs);
   // Gram: a workgroup per row for few walkers, the matrix-core form for
@@ -468,7 +474,7 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   hipEvent_t e_a0 = w->tev(timed), e_a1 = w->tev(timed);
   hipExtLaunchKernelGGL(k_accept<T>, dim3(1, 1, W), dim3(AW), 0, s, e_a0, e_a1, 0, vs);
   w->mark(w->pend_accept, e_a0, e_a1);
-  if (wide) hipLaunchKernelGGL((k_ygemm<T, 8>), dim3(g16, 2, W), dim3(512), 0, s, vs);
+  if (ywide) hipLaunchKernelGGL((k_ygemm<T, 8>), dim3(g16, 2, W), dim3(512), 0, s, vs);
   else hipLaunchKernelGGL((k_ygemm<T, 4>), dim3(g16, 2, W), dim3(256), 0, s, vs);
   hipLaunchKernelGGL(k_fold_prep<T>, dim3(spread(cdiv(kx, 64), W, 2), 2, W), dim3(WG), 0, s, vs);
   hipEvent_t e_f0 = w->tev(timed), e_f1 = w->tev(timed);
