@@ -498,7 +498,7 @@ void enqueue_refresh(dcax_walker w, int first, int n, int kmax, bool measure) {
   hipLaunchKernelGGL(k_build_ninv<T>, dim3(cdiv(kmax, WG), kmax, n), dim3(WG), 0, s, vs);
   for (int p0 = 0; p0 < kmax; p0 += NB) {
     if (kmax <= PANEL_ROWS)
-      hipLaunchKernelGGL(k_gj_panel<T>, dim3(2, 1, n), dim3(WG), 0, s, vs, p0);
+      hipLaunchKernelGGL(k_gj_panel<T>, dim3(2, 1, n), dim3(cdiv(kmax, 64) * 64), 0, s, vs, p0);
     else
       for (int c = 0; c <= std::min(NB, kmax - p0); ++c)
         hipLaunchKernelGGL(k_gj_col<T>, dim3(cdiv(kmax, WG), 2, n), dim3(WG), 0, s, vs, p0, c);

@@ -4,9 +4,9 @@
 // propagator gathers (Sec. 2.3's definition of N through Z_k) and inverted by
 // blocked Gauss-Jordan elimination with partial pivoting:
 //   for each panel of NB columns, the panel columns are eliminated one by one
-//   (pivot search over the not yet pivoted rows, row swap, in-place GJ step):
-//   by one workgroup in LDS for orders up to PANEL_ROWS, otherwise by one
-//   launch per column over workgroups that hold one panel row per thread;
+//   (pivot search over the not yet pivoted rows, row swap, in-place GJ step)
+//   with one panel row per thread in registers: by one workgroup for orders
+//   up to PANEL_ROWS, otherwise by one launch per column over workgroups;
 //   the other columns receive the panel's row swaps and then the rank-NB
 //   update  A_{.x} <- P_{.J} A_{Jx} + (A_{.x} with rows J zeroed),
 //   where P holds the eliminated panel columns, run on the MFMA fold tile.
@@ -36,11 +36,14 @@ __global__ void __launch_bounds__(WG) k_build_ninv(const View<T>* __restrict__ v
   w.M[1][o] = (i == j ? e1 : 0.0) - g * (e1 - 1.0);
 }
 
-// Eliminates panel columns [p0, p0 + nb) (blockIdx.x = spin, blockIdx.z =
-// walker).  The k x nb panel is staged in LDS when it fits (k <= PANEL_ROWS),
-// otherwise the steps run on global memory; the pivot search reduces within
-// wavefronts first.  Ties in |pivot| go to the smaller row index.
-constexpr int PANEL_ROWS = 512;
+// Eliminates panel columns [p0, p0 + nb) in one workgroup for orders up to
+// PANEL_ROWS (blockIdx.x = spin, blockIdx.z = walker; at least k threads):
+// one row of the panel per thread, in registers.  Per column: the pivot
+// search (wavefronts, then their candidates in LDS; ties in |pivot| go to
+// the smaller row index), the pivot row divided by the pivot and the old row
+// at the pivot position shared through LDS, and the Gauss-Jordan step of
+// every row.
+constexpr int PANEL_ROWS = 1024;
 
 __device__ inline void argmax_wave(double& v, int& i) {
   for (int o = 32; o > 0; o >>= 1) {
@@ -53,38 +56,33 @@ __device__ inline void argmax_wave(double& v, int& i) {
   }
 }
 
-// Panel element (r, x): LDS column-major with stride k, or M in global memory.
-struct PanelLds {
-  double* s;
-  int k;
-  __device__ double& operator()(int r, int x) const { return s[x * k + r]; }
-};
-struct PanelGlobal {
-  __attribute__((address_space(1))) double* m;
-  size_t ld;
-  int p0;
-  __device__ __attribute__((address_space(1))) double& operator()(int r, int x) const {
-    return m[r + (size_t)(p0 + x) * ld];
-  }
-};
-
-template <typename Acc>
-__device__ inline double gj_panel_steps(Acc at, int k, int p0, int nb, __attribute__((address_space(1))) int* ipiv,
-                                        Ctl* ctl) {
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  __shared__ double vmax_s[WG / 64], row_s[NB];
-  __shared__ int imax_s[WG / 64];
+template <typename T>
+__global__ void __launch_bounds__(PANEL_ROWS) k_gj_panel(const View<T>* __restrict__ vs, int p0) {
+  const View<T>& w = vs[blockIdx.z];
+  const int k = w.ctl->k;
+  if (p0 >= k) return;
+  const int nb = (k - p0 < NB) ? k - p0 : NB;
+  const int sp = blockIdx.x;
+  const auto Mg = gp(w.M[sp]);
+  const size_t ld = w.cap;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nwv = (int)(blockDim.x >> 6);
+  const bool live = t < k;
+  const size_t ro = live ? (size_t)t : 0;
+  __shared__ double rs_s[NB], oc_s[NB], vmax_s[PANEL_ROWS / 64];
+  __shared__ int imax_s[PANEL_ROWS / 64];
+  __shared__ double app_s;
+  double a[NB];
+#pragma unroll
+  for (int x = 0; x < NB; ++x) a[x] = Mg[ro + (size_t)(p0 + (x < nb ? x : 0)) * ld];
   double dsign = 1.0;
   for (int cidx = 0; cidx < nb; ++cidx) {
     const int c = p0 + cidx;
     double best = -1.0;
     int bi = k;
-    for (int r = c + t; r < k; r += WG) {
-      const double v = fabs((double)at(r, cidx));
-      if (v > best) {
-        best = v;
-        bi = r;
-      }
+    if (live && t >= c) {
+#pragma unroll
+      for (int x = 0; x < NB; ++x) best = (x == cidx) ? fabs(a[x]) : best;
+      bi = t;
     }
     argmax_wave(best, bi);
     if (lane == 0) {
@@ -94,67 +92,50 @@ __device__ inline double gj_panel_steps(Acc at, int k, int p0, int nb, __attribu
     __syncthreads();
     double pv = vmax_s[0];
     int piv = imax_s[0];
-    for (int x = 1; x < WG / 64; ++x)
+    for (int x = 1; x < nwv; ++x)
       if (vmax_s[x] > pv || (vmax_s[x] == pv && imax_s[x] < piv)) {
         pv = vmax_s[x];
         piv = imax_s[x];
       }
+    const int pr = (piv >= c && piv < k) ? piv : c;
+    if (t == pr) {
+      double app = 0.0;
+#pragma unroll
+      for (int x = 0; x < NB; ++x) app = (x == cidx) ? a[x] : app;
+      app_s = app;
+#pragma unroll
+      for (int x = 0; x < NB; ++x) rs_s[x] = (x == cidx) ? 1.0 / app : a[x] / app;
+    }
+    if (t == c)
+#pragma unroll
+      for (int x = 0; x < NB; ++x) oc_s[x] = a[x];
+    __syncthreads();
+    const double a_pp = app_s;
     if (t == 0) {
-      ipiv[c] = piv;
-      if (!(pv > 0.0) || !isfinite(pv)) latch(ctl, ST_NUMERIC);
+      w.ipiv[sp][c] = pr;
+      if (!(pv > 0.0) || !isfinite(pv)) latch(w.ctl, ST_NUMERIC);
     }
-    // swap rows c and piv inside the panel, then scale row c
-    if (t < nb && piv != c && piv < k) {
-      const double x = at(c, t);
-      at(c, t) = at(piv, t);
-      at(piv, t) = x;
-    }
-    __syncthreads();
-    const double a_cc = at(c, cidx);
     // sign of det: product of the pivots, one factor -1 per row interchange
-    dsign *= ((a_cc < 0.0) ? -1.0 : 1.0) * ((piv != c) ? -1.0 : 1.0);
-    __syncthreads();
-    if (t < nb) {
-      const double v = (t == cidx) ? 1.0 / a_cc : at(c, t) / a_cc;
-      at(c, t) = v;
-      row_s[t] = v;
+    dsign *= ((a_pp < 0.0) ? -1.0 : 1.0) * ((pr != c) ? -1.0 : 1.0);
+    if (t == c) {
+#pragma unroll
+      for (int x = 0; x < NB; ++x) a[x] = rs_s[x];
+    } else {
+      if (t == pr)
+#pragma unroll
+        for (int x = 0; x < NB; ++x) a[x] = oc_s[x];
+      double f = 0.0;
+#pragma unroll
+      for (int x = 0; x < NB; ++x) f = (x == cidx) ? a[x] : f;
+#pragma unroll
+      for (int x = 0; x < NB; ++x) a[x] = (x == cidx) ? -f * rs_s[x] : a[x] - f * rs_s[x];
     }
-    __syncthreads();
-    for (int r = t; r < k; r += WG) {
-      if (r == c) continue;
-      const double f = at(r, cidx);
-      for (int x = 0; x < nb; ++x) {
-        if (x == cidx) at(r, x) = -f * row_s[x];
-        else at(r, x) -= f * row_s[x];
-      }
-    }
-    __syncthreads();
+    __syncthreads();      // rs_s, oc_s and the candidates are rewritten
   }
-  return dsign;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(WG) k_gj_panel(const View<T>* __restrict__ vs, int p0) {
-  const View<T>& w = vs[blockIdx.z];
-  const int k = w.ctl->k;
-  if (p0 >= k) return;
-  const int nb = (k - p0 < NB) ? k - p0 : NB;
-  const int sp = blockIdx.x;
-  const auto Mg = gp(w.M[sp]);
-  const size_t ldm = w.cap;
-  const int t = threadIdx.x;
-  __shared__ double pan_s[PANEL_ROWS * NB];
-  double dsign;
-  if (k <= PANEL_ROWS) {
-    for (int x = 0; x < nb; ++x)
-      for (int r = t; r < k; r += WG) pan_s[x * k + r] = Mg[r + (size_t)(p0 + x) * ldm];
-    __syncthreads();
-    dsign = gj_panel_steps(PanelLds{pan_s, k}, k, p0, nb, gp(w.ipiv[sp]), w.ctl);
-    for (int x = 0; x < nb; ++x)
-      for (int r = t; r < k; r += WG) Mg[r + (size_t)(p0 + x) * ldm] = pan_s[x * k + r];
-  } else {
-    dsign = gj_panel_steps(PanelGlobal{Mg, ldm, p0}, k, p0, nb, gp(w.ipiv[sp]), w.ctl);
-  }
+  if (live)
+#pragma unroll
+    for (int x = 0; x < NB; ++x)
+      if (x < nb) Mg[t + (size_t)(p0 + x) * ld] = a[x];
   if (t == 0) w.detsign[sp] *= dsign;
 }
 

@@ -124,15 +124,16 @@ def test_graph_sweeps_equal_eager_sweeps(precision, timing):
 
 
 def test_refresh_forms_agree_in_a_batch():
-    """A batch whose largest order exceeds 512 refreshes every walker with the
-    column-step panel form; a walker of order 100 alone takes the LDS form.
-    Both forms make the same pivot choices and the same arithmetic."""
+    """A batch whose largest order exceeds 1024 refreshes every walker with
+    the column-step panel form; a walker of order 100 alone takes the
+    one-workgroup form.  Both forms make the same pivot choices and the same
+    arithmetic."""
     print("[batch] refresh forms", flush=True)
     d = dict(cluster=(4, 0, 0, 4), U=4.0, beta=10.0, mu=-0.3, n_tau=2001, submatrix_k=32, seed=21)
-    p = dcax.make_params(max_order=1024, n_freq=16, refresh_every=0, **d)
+    p = dcax.make_params(max_order=2048, n_freq=16, refresh_every=0, **d)
     rng = np.random.default_rng(5)
     cfg = [(rng.integers(0, 16, size=n).astype(np.int32), rng.random(n) * 10.0,
-            np.where(rng.random(n) < 0.5, 1, -1).astype(np.int32)) for n in (700, 100)]
+            np.where(rng.random(n) < 0.5, 1, -1).astype(np.int32)) for n in (1100, 100)]
     wb = dcax.Walker([p, p])
     for i, c in enumerate(cfg):
         wb.set_config(*c, walker=i)

@@ -69,7 +69,7 @@ def test_g0_table(name):
 def test_refresh_equals_direct_inverse(name, k):
     """Random (unequilibrated) configurations can be very ill-conditioned, so
     the GJ inverse is checked by its backward residual |A N - 1| / (|A| |N|)
-    and against NumPy's LU inverse within 20 cond(A) eps.  Orders above 512
+    and against NumPy's LU inverse within 20 cond(A) eps.  Orders above 1024
     take the column-step panel form (with a narrower last panel here)."""
     print(f"[refresh] {name} k={k}", flush=True)
     m = model(name)
