@@ -195,6 +195,45 @@ def run_batch(precision, steps, warmup, n_walkers=512):
     return res
 
 
+def run_nfft(workload, precision="fp64", half_width=8, reps=5):
+    """Per-measurement time of the direct contraction (dcax_measure_G) and of
+    the delayed-NFFT gridding (dcax_measure_nfft) on one walker of the
+    workload after a few sweeps, the one-off transform, and the largest
+    difference of the two accumulators relative to their largest entry."""
+    import numpy as np
+    import torch
+    from paper_1901_01047_amd import dcax
+    from paper_1901_01047_amd.workloads import CONFIGS, params_kwargs
+    cfg = CONFIGS[workload]
+    prec = dcax.DCAX_FP64 if precision == "fp64" else dcax.DCAX_FP32_MIXED
+    w = dcax.Walker(dcax.make_params(**params_kwargs(workload, warmup_sweeps=2), precision=prec, refresh_every=0))
+    rng = np.random.default_rng(cfg["seed"] + 100)
+    w.set_config(*initial_config(rng, w.Ncs[0], cfg["beta"], cfg["k_init"]))
+    w.sweep(2)
+    acc, aux = w.new_accumulator()
+    grid = w.new_nfft_grid()
+    aux2 = torch.zeros_like(aux)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    direct = timed(lambda: w.measure(acc, aux))
+    gridding = timed(lambda: w.measure_nfft(grid, aux2, half_width))
+    acc2 = torch.zeros_like(acc)
+    transform = timed(lambda: (acc2.zero_(), w.nfft_transform(grid, acc2, half_width)))
+    err = float((acc2 - acc).abs().max() / acc.abs().max())
+    out = {"workload": workload, "precision": precision, "order": w.order, "n_freq": cfg["n_freq"],
+           "half_width": half_width, "direct_ms": direct, "nfft_grid_ms": gridding, "nfft_transform_ms": transform,
+           "max_rel_diff": err}
+    w.close()
+    return out
+
+
 def cpu_baseline(seconds=15.0, workload=None):
     """The oracle, as it stands, timed on the host: the same workload from a
     seeded random configuration of the workload's typical order."""
@@ -241,6 +280,8 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD,
                     help="single-walker (or --walkers) workload from paper_1901_01047_amd.workloads.CONFIGS")
     ap.add_argument("--walkers", type=int, default=1)
+    ap.add_argument("--nfft", action="store_true",
+                    help="also time the delayed-NFFT measurement against the direct one on the workload")
     ap.add_argument("--batch", type=int, default=0,
                     help="also run the batched workload with this many walkers (FP64 and FP32-mixed)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -290,6 +331,8 @@ def main():
     if not args.fp64_only:
         r32, _ = run_gpu("mixed", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers)
         out["fp32_mixed"] = r32
+    if args.nfft:
+        out["measurement"] = run_nfft(wl)
     if args.batch:
         out["batch"] = {"fp64": run_batch("fp64", args.steps, args.warmup, args.batch),
                         "fp32_mixed": run_batch("mixed", args.steps, args.warmup, args.batch)}

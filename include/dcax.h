@@ -221,6 +221,37 @@ dcax_status dcax_run_rounds(dcax_walker w, int32_t n_rounds, double* acc_dev, do
 dcax_status dcax_finalize_G(dcax_walker w, const double* acc_dev, const double* aux_dev,
                             double* Giw_dev, int32_t n_tau_out, double* Gtau_dev);
 
+/* Delayed-NFFT measurement (Sec. 2.3, non-equidistant FFT measurements): the
+ * same quantity as dcax_measure_G, accumulated as gridded samples.  Every
+ * pair (i, j) of every walker's configuration contributes M_ij = (e^{V_i} -
+ * 1) N_ij at tau_i - tau_j (a negative difference as its antiperiodic image
+ * at + beta with the opposite sign) to row d = r_i - r_j of an equispaced
+ * grid of L = 4 n_freq points on [0, beta), spread with the Gaussian kernel
+ * of Greengard & Lee (SIAM Review 46, 2004; oversampling ratio 2) over
+ * 2 half_width points, and the configuration's sign times that grid is added
+ * to grid_dev.
+ *   half_width: kernel half-width in grid points, 2..16, the same in every
+ *     call on one grid; the transform's error is of order
+ *     exp(-(2/3) pi half_width) times sum |M_ij| (3.5e-6 at 6, 5.3e-8 at 8).
+ *   grid_dev (device, doubles): one [2][Nc][4 n_freq] block per walker, in
+ *     walker order (twice the size of dcax_measure_G's accumulator), +=.
+ *   aux_dev: as for dcax_measure_G.
+ * Needs 1 <= n_freq <= 2048 and 2 half_width <= 4 n_freq for every walker
+ * (DCAX_E_INVAL otherwise).  Enqueued on the walker's stream. */
+dcax_status dcax_measure_nfft(dcax_walker w, int32_t half_width, double* grid_dev, double* aux_dev);
+
+/* The single transform at the end of a delayed-NFFT run: for every walker,
+ * spin, displacement row d and frequency w_n = (2n+1) pi / beta,
+ *   F_d(w_n) = h sum_l G_d[l] e^{i w_n l h} / g(w_n),  h = beta / (4 n_freq),
+ * with g the kernel's Fourier transform, and
+ *   acc_dev[K][n] += (1/Nc) sum_d e^{-i K r_d} F_d(w_n),
+ * i.e. what dcax_measure_G would have accumulated over the same
+ * configurations, to the NFFT error.  grid_dev as filled by dcax_measure_nfft
+ * with the same half_width; acc_dev in dcax_measure_G's layout (start from
+ * zeros to obtain that accumulator; then dcax_finalize_G applies).  Uses the
+ * walker's measurement scratch; enqueued on the walker's stream. */
+dcax_status dcax_nfft_transform(dcax_walker w, int32_t half_width, const double* grid_dev, double* acc_dev);
+
 /* Change the submatrix size of one walker (walker >= 0) or of all (-1),
  * 1..64; takes effect at the next window.  The Markov chain is unaffected:
  * the submatrix size only groups proposals (Sec. 2.3, submatrix updates). */

@@ -20,6 +20,7 @@
 #include "dcax_window.hip"
 #include "dcax_refresh.hip"
 #include "dcax_measure.hip"
+#include "dcax_nfft.hip"
 
 using namespace dcax;
 
@@ -549,6 +550,37 @@ void enqueue_measure(dcax_walker w, double* acc, double* aux, int gated) {
   hipLaunchKernelGGL(k_meas_block<T>, dim3(2 * spread(groups, W, 2 * fy, mb), fy, W), dim3(WG), 0, s, vs, gated);
   hipLaunchKernelGGL(k_meas_K<T>, dim3(px, spread(ncm, W, 2 * px, mb), 2 * W), dim3(WG), 0, s, vs, acc, gated);
   if (gated) hipLaunchKernelGGL(k_meas_done<T>, dim3(1, 1, W), dim3(1), 0, s, vs);
+}
+
+// Checks shared by the delayed-NFFT entry points.
+dcax_status nfft_check(dcax_walker w, int32_t half_width) {
+  if (half_width < 2 || half_width > NFFT_MSP_MAX) return fail(DCAX_E_INVAL, "half_width must be in [2, 16]");
+  for (const auto& x : w->wk) {
+    const int nf = x.p.n_freq;
+    if (nf < 1) return fail(DCAX_E_INVAL, "the NFFT measurement needs n_freq >= 1");
+    if (4 * nf > NFFT_L_MAX) return fail(DCAX_E_INVAL, "the NFFT grid holds at most 2048 frequencies");
+    if (2 * half_width > 4 * nf) return fail(DCAX_E_INVAL, "half_width wider than the grid");
+  }
+  return DCAX_OK;
+}
+
+template <typename T>
+void enqueue_nfft(dcax_walker w, int half_width, double* grid, double* aux) {
+  const View<T>* vs = w->views<T>();
+  hipStream_t s = w->stream;
+  const int W = w->W;
+  hipLaunchKernelGGL(k_meas_diag<T>, dim3(2, 1, W), dim3(WG), 0, s, vs, aux, 0);
+  const int ncm = w->nc_max;
+  const int kb = std::min(w->kpad_max, w->kmax_host() + 16 * ncm);
+  const int kb1 = std::max(kb, 1);
+  hipLaunchKernelGGL(k_meas_sort<T>, dim3(1, 1, W), dim3(WG), 0, s, vs, 0);
+  const long long mb = MEAS_BUDGET;
+  const int cx = spread(cdiv(kb1, WG), W, 1, mb);
+  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cx, spread(cdiv(kb1, MCOLS), W, cx, mb), W), dim3(WG), 0, s, vs, 0);
+  // rows split over groups of sites until the launch has ~1024 workgroups
+  const int groups = (int)std::max<long long>(1, std::min<long long>(ncm, 1024 / (2ll * ncm * W)));
+  const size_t lds = sizeof(double) * 4 * (size_t)w->nf_max;
+  hipLaunchKernelGGL(k_nfft_grid<T>, dim3(ncm * groups, 2, W), dim3(WG), lds, s, vs, half_width, groups, grid);
 }
 
 // One sweep's kernels (sweep start plus nwin windows with growing bounds).
@@ -1189,6 +1221,38 @@ dcax_status dcax_measure_G(dcax_walker w, double* acc_dev, double* aux_dev) {
   if (!aux_dev || (!acc_dev && w->nf_max > 0)) return fail(DCAX_E_INVAL, "NULL accumulator");
   if (w->mixed) enqueue_measure<float>(w, acc_dev, aux_dev, 0);
   else enqueue_measure<double>(w, acc_dev, aux_dev, 0);
+  HIPCHK(hipGetLastError());
+  return DCAX_OK;
+}
+
+dcax_status dcax_measure_nfft(dcax_walker w, int32_t half_width, double* grid_dev, double* aux_dev) {
+  dcax_status st = check_latched(w);
+  if (st != DCAX_OK) return st;
+  if (!grid_dev || !aux_dev) return fail(DCAX_E_INVAL, "NULL accumulator");
+  st = nfft_check(w, half_width);
+  if (st != DCAX_OK) return st;
+  if (w->mixed) enqueue_nfft<float>(w, half_width, grid_dev, aux_dev);
+  else enqueue_nfft<double>(w, half_width, grid_dev, aux_dev);
+  HIPCHK(hipGetLastError());
+  return DCAX_OK;
+}
+
+dcax_status dcax_nfft_transform(dcax_walker w, int32_t half_width, const double* grid_dev, double* acc_dev) {
+  if (!w || !grid_dev || !acc_dev) return fail(DCAX_E_INVAL, "NULL argument");
+  dcax_status st = nfft_check(w, half_width);
+  if (st != DCAX_OK) return st;
+  const int nf = w->nf_max, ncm = w->nc_max, W = w->W;
+  if (w->mixed) {
+    hipLaunchKernelGGL(k_nfft_rows<float>, dim3(cdiv(nf, WG), ncm, 2 * W), dim3(WG), 0, w->stream,
+                       w->views<float>(), half_width, grid_dev);
+    hipLaunchKernelGGL(k_nfft_K<float>, dim3(cdiv(nf, WG), ncm, 2 * W), dim3(WG), 0, w->stream, w->views<float>(),
+                       acc_dev);
+  } else {
+    hipLaunchKernelGGL(k_nfft_rows<double>, dim3(cdiv(nf, WG), ncm, 2 * W), dim3(WG), 0, w->stream,
+                       w->views<double>(), half_width, grid_dev);
+    hipLaunchKernelGGL(k_nfft_K<double>, dim3(cdiv(nf, WG), ncm, 2 * W), dim3(WG), 0, w->stream, w->views<double>(),
+                       acc_dev);
+  }
   HIPCHK(hipGetLastError());
   return DCAX_OK;
 }
