@@ -103,7 +103,7 @@ def kernel_us(s0, s1):
         {"timed_windows": n, "windows": s1["windows_enqueued"] - s0["windows_enqueued"]}
 
 
-def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None, walkers=1):
+def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None, walkers=1, nfft_hw=0):
     import numpy as np
     import torch
     from paper_1901_01047_amd import dcax
@@ -119,12 +119,21 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
         rng = np.random.default_rng(cfg["seed"] + 100 + seed_offset + i)
         w.set_config(*initial_config(rng, w.Ncs[i], cfg["beta"], cfg["k_init"]), walker=i)
     acc, aux = w.new_accumulator()
-    w.sweep_measure(warmup, acc, aux)
+    if nfft_hw:
+        # the measurement is the delayed-NFFT gridding (same chain)
+        grid = w.new_nfft_grid()
+
+        def sweep_measure(n):
+            w.sweep_measure_nfft(n, grid, aux, nfft_hw)
+    else:
+        def sweep_measure(n):
+            w.sweep_measure(n, acc, aux)
+    sweep_measure(warmup)
     w.set_timing(TIMING_EVERY)
     torch.cuda.synchronize()
     s0 = w.stats()
     t0 = time.perf_counter()
-    w.sweep_measure(steps, acc, aux)
+    sweep_measure(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     s1 = w.stats()
@@ -148,7 +157,7 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
         # figures come from eager sweeps right after the timed region
         w.set_graphs(False)
         r0 = w.stats()
-        w.sweep_measure(min(steps, 30), acc, aux)
+        sweep_measure(min(steps, 30))
         torch.cuda.synchronize()
         res["roofline"] = roofline(r0, w.stats(), precision, fold_traffic(workload, precision))
         if res["roofline"]:
@@ -333,6 +342,8 @@ def main():
         out["fp32_mixed"] = r32
     if args.nfft:
         out["measurement"] = run_nfft(wl)
+        rn, _ = run_gpu("fp64", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers, nfft_hw=8)
+        out["fp64_nfft_measurement"] = {k: v for k, v in rn.items() if k != "roofline"}
     if args.batch:
         out["batch"] = {"fp64": run_batch("fp64", args.steps, args.warmup, args.batch),
                         "fp32_mixed": run_batch("mixed", args.steps, args.warmup, args.batch)}

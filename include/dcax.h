@@ -240,6 +240,15 @@ dcax_status dcax_finalize_G(dcax_walker w, const double* acc_dev, const double* 
  * (DCAX_E_INVAL otherwise).  Enqueued on the walker's stream. */
 dcax_status dcax_measure_nfft(dcax_walker w, int32_t half_width, double* grid_dev, double* aux_dev);
 
+/* dcax_sweep_measure with the delayed-NFFT measurement: the result of
+ * n_sweeps times dcax_sweep(w, 1, NULL, 0, NULL) followed by
+ * dcax_measure_nfft(w, half_width, grid_dev, aux_dev), scheduled on the
+ * device the same way (each walker's chain, sweep boundaries and measured
+ * configurations as with dcax_sweep_measure).  Same arguments and errors as
+ * dcax_measure_nfft. */
+dcax_status dcax_sweep_measure_nfft(dcax_walker w, int32_t n_sweeps, int32_t half_width, double* grid_dev,
+                                    double* aux_dev);
+
 /* The single transform at the end of a delayed-NFFT run: for every walker,
  * spin, displacement row d and frequency w_n = (2n+1) pi / beta,
  *   F_d(w_n) = h sum_l G_d[l] e^{i w_n l h} / g(w_n),  h = beta / (4 n_freq),

@@ -564,23 +564,28 @@ dcax_status nfft_check(dcax_walker w, int32_t half_width) {
   return DCAX_OK;
 }
 
+// The delayed-NFFT measurement: aux terms, the site sort and sorted copy of M
+// shared with the direct measurement, then the gridding.  gated: only the
+// walkers whose sweep has ended (device-scheduled sweeps).
 template <typename T>
-void enqueue_nfft(dcax_walker w, int half_width, double* grid, double* aux) {
+void enqueue_nfft(dcax_walker w, int half_width, double* grid, double* aux, int gated) {
   const View<T>* vs = w->views<T>();
   hipStream_t s = w->stream;
   const int W = w->W;
-  hipLaunchKernelGGL(k_meas_diag<T>, dim3(2, 1, W), dim3(WG), 0, s, vs, aux, 0);
+  hipLaunchKernelGGL(k_meas_diag<T>, dim3(2, 1, W), dim3(WG), 0, s, vs, aux, gated);
   const int ncm = w->nc_max;
   const int kb = std::min(w->kpad_max, w->kmax_host() + 16 * ncm);
   const int kb1 = std::max(kb, 1);
-  hipLaunchKernelGGL(k_meas_sort<T>, dim3(1, 1, W), dim3(WG), 0, s, vs, 0);
+  hipLaunchKernelGGL(k_meas_sort<T>, dim3(1, 1, W), dim3(WG), 0, s, vs, gated);
   const long long mb = MEAS_BUDGET;
   const int cx = spread(cdiv(kb1, WG), W, 1, mb);
-  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cx, spread(cdiv(kb1, MCOLS), W, cx, mb), W), dim3(WG), 0, s, vs, 0);
+  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cx, spread(cdiv(kb1, MCOLS), W, cx, mb), W), dim3(WG), 0, s, vs, gated);
   // rows split over groups of sites until the launch has ~1024 workgroups
   const int groups = (int)std::max<long long>(1, std::min<long long>(ncm, 1024 / (2ll * ncm * W)));
   const size_t lds = sizeof(double) * 4 * (size_t)w->nf_max;
-  hipLaunchKernelGGL(k_nfft_grid<T>, dim3(ncm * groups, 2, W), dim3(WG), lds, s, vs, half_width, groups, grid);
+  hipLaunchKernelGGL(k_nfft_grid<T>, dim3(ncm * groups, 2, W), dim3(WG), lds, s, vs, half_width, groups, grid,
+                     gated);
+  if (gated) hipLaunchKernelGGL(k_meas_done<T>, dim3(1, 1, W), dim3(1), 0, s, vs);
 }
 
 // One sweep's kernels (sweep start plus nwin windows with growing bounds).
@@ -876,11 +881,12 @@ dcax_status create_walkers(dcax_walker w) {
 // next one, nwin windows run, and the walkers whose sweep has ended are
 // measured (gated measurement).
 template <typename T>
-void enqueue_round(dcax_walker w, int kb, int nwin, double* acc, double* aux) {
+void enqueue_round(dcax_walker w, int kb, int nwin, double* acc, double* aux, int nfft_hw) {
   w->fresh = false;
   hipLaunchKernelGGL(k_round_begin<T>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<T>());
   for (int i = 0; i < nwin; ++i) enqueue_window<T>(w, kb, false);
-  enqueue_measure<T>(w, acc, aux, 1);
+  if (nfft_hw > 0) enqueue_nfft<T>(w, nfft_hw, acc, aux, 1);
+  else enqueue_measure<T>(w, acc, aux, 1);
 }
 
 // Sweeps of every walker, each followed by its measurement, scheduled on the
@@ -892,8 +898,10 @@ void enqueue_round(dcax_walker w, int kb, int nwin, double* acc, double* aux) {
 // Kernel grids follow the order seen at the last sync (the kernels stride
 // over the device-side order); the host syncs only to refresh, and at the
 // end to check that every walker has finished (rounds lost to windows closed
-// early are made up).
-dcax_status sweep_rounds(dcax_walker w, int n, double* acc, double* aux, long long free_rounds = 0) {
+// early are made up).  nfft_hw > 0: the measurement is the delayed-NFFT
+// gridding into acc (a grid) with that kernel half-width.
+dcax_status sweep_rounds(dcax_walker w, int n, double* acc, double* aux, long long free_rounds = 0,
+                         int nfft_hw = 0) {
   dcax_status st = DCAX_OK;
   if (!w->fresh) {
     st = sync_all(w);
@@ -926,8 +934,8 @@ dcax_status sweep_rounds(dcax_walker w, int n, double* acc, double* aux, long lo
     if (pass > 64) return fail(DCAX_E_STATE, "device-scheduled sweeps made no progress");
     const int kb = std::min(w->mo_max, w->kmax_host() + 2 * w->ks_max);
     for (long long r = 0; r < planned; ++r) {
-      if (w->mixed) enqueue_round<float>(w, kb, R, acc, aux);
-      else enqueue_round<double>(w, kb, R, acc, aux);
+      if (w->mixed) enqueue_round<float>(w, kb, R, acc, aux, nfft_hw);
+      else enqueue_round<double>(w, kb, R, acc, aux, nfft_hw);
       HIPCHK(hipGetLastError());
       ++w->rounds_done;
       if (refresh_rounds > 0 && w->rounds_done % refresh_rounds == 0) {
@@ -1200,6 +1208,27 @@ dcax_status dcax_sweep_measure(dcax_walker w, int32_t n_sweeps, double* acc_dev,
   return sweep_rounds(w, n_sweeps, acc_dev, aux_dev);
 }
 
+dcax_status dcax_sweep_measure_nfft(dcax_walker w, int32_t n_sweeps, int32_t half_width, double* grid_dev,
+                                    double* aux_dev) {
+  dcax_status st = check_latched(w);
+  if (st != DCAX_OK) return st;
+  if (n_sweeps < 0) return fail(DCAX_E_INVAL, "n_sweeps < 0");
+  if (!grid_dev || !aux_dev) return fail(DCAX_E_INVAL, "NULL accumulator");
+  st = nfft_check(w, half_width);
+  if (st != DCAX_OK) return st;
+  if (w->use_graphs) {
+    for (int i = 0; i < n_sweeps; ++i) {
+      st = sweep_rng(w, 1);
+      if (st != DCAX_OK) return st;
+      if (w->mixed) enqueue_nfft<float>(w, half_width, grid_dev, aux_dev, 0);
+      else enqueue_nfft<double>(w, half_width, grid_dev, aux_dev, 0);
+      HIPCHK(hipGetLastError());
+    }
+    return DCAX_OK;
+  }
+  return sweep_rounds(w, n_sweeps, grid_dev, aux_dev, 0, half_width);
+}
+
 dcax_status dcax_run_rounds(dcax_walker w, int32_t n_rounds, double* acc_dev, double* aux_dev) {
   dcax_status st = check_latched(w);
   if (st != DCAX_OK) return st;
@@ -1231,8 +1260,8 @@ dcax_status dcax_measure_nfft(dcax_walker w, int32_t half_width, double* grid_de
   if (!grid_dev || !aux_dev) return fail(DCAX_E_INVAL, "NULL accumulator");
   st = nfft_check(w, half_width);
   if (st != DCAX_OK) return st;
-  if (w->mixed) enqueue_nfft<float>(w, half_width, grid_dev, aux_dev);
-  else enqueue_nfft<double>(w, half_width, grid_dev, aux_dev);
+  if (w->mixed) enqueue_nfft<float>(w, half_width, grid_dev, aux_dev, 0);
+  else enqueue_nfft<double>(w, half_width, grid_dev, aux_dev, 0);
   HIPCHK(hipGetLastError());
   return DCAX_OK;
 }

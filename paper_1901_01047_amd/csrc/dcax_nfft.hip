@@ -34,8 +34,9 @@ constexpr int NFFT_MSP_MAX = 16;
 
 template <typename T>
 __global__ void __launch_bounds__(WG) k_nfft_grid(const View<T>* __restrict__ vs, int m_sp, int groups,
-                                                  double* grid_all) {
+                                                  double* grid_all, int gated) {
   const View<T>& w = vs[blockIdx.z];
+  if (meas_skip(w.ctl, gated)) return;
   const int Nc = w.Nc;
   const int d = blockIdx.x % Nc, grp = blockIdx.x / Nc;
   // sites a of this workgroup: [a0, a1)
@@ -177,7 +178,7 @@ __global__ void __launch_bounds__(WG) k_nfft_K(const View<T>* __restrict__ vs, d
 }
 
 #define DCAX_INSTANTIATE_NFFT(T)                                                     \
-  template __global__ void k_nfft_grid<T>(const View<T>*, int, int, double*);        \
+  template __global__ void k_nfft_grid<T>(const View<T>*, int, int, double*, int);   \
   template __global__ void k_nfft_rows<T>(const View<T>*, int, const double*);       \
   template __global__ void k_nfft_K<T>(const View<T>*, double*);
 

@@ -77,7 +77,8 @@ VERTEX_DTYPE = np.dtype([("id", np.int64), ("site", np.int32), ("aux_spin", np.i
 
 # exported symbols, in the order include/dcax.h declares them
 EXPORTS = ("dcax_walker_create", "dcax_walker_destroy", "dcax_sweep", "dcax_refresh", "dcax_measure_G",
-           "dcax_sweep_measure", "dcax_run_rounds", "dcax_measure_nfft", "dcax_nfft_transform",
+           "dcax_sweep_measure", "dcax_run_rounds", "dcax_measure_nfft", "dcax_sweep_measure_nfft",
+           "dcax_nfft_transform",
            "dcax_finalize_G", "dcax_get_order", "dcax_copy_N", "dcax_get_config", "dcax_set_config",
            "dcax_set_submatrix_k", "dcax_autotune", "dcax_set_graphs", "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table",
            "dcax_cluster", "dcax_last_error")
@@ -322,6 +323,11 @@ class Walker:
         """Delayed-NFFT measurement: grid += sign * gridded M, aux as for measure."""
         _check(load().dcax_measure_nfft(self._h, int(half_width), ctypes.c_void_p(grid.data_ptr()),
                                         ctypes.c_void_p(aux.data_ptr())))
+
+    def sweep_measure_nfft(self, n_sweeps, grid, aux, half_width=8):
+        """n_sweeps device-scheduled sweeps, each followed by a delayed-NFFT measurement."""
+        _check(load().dcax_sweep_measure_nfft(self._h, int(n_sweeps), int(half_width),
+                                              ctypes.c_void_p(grid.data_ptr()), ctypes.c_void_p(aux.data_ptr())))
 
     def nfft_transform(self, grid, acc, half_width=8):
         """acc += the transform of an accumulated grid (the layout of measure's acc)."""

@@ -131,3 +131,35 @@ def test_bad_arguments_rejected():
         with pytest.raises(dcax.DcaxError):
             w.nfft_transform(grid, acc, hw)
     w.close()
+
+
+@pytest.mark.parametrize("which", ["single", "batch"])
+def test_device_scheduled_sweeps_with_nfft_equal_lockstep(which):
+    """dcax_sweep_measure_nfft(n) = n x (sweep(1) + measure_nfft): the same
+    chains bit for bit, the same signs, and the same grids up to the order of
+    the atomic additions of workgroups that share a grid row."""
+    print(f"[nfft rounds] {which}", flush=True)
+    plist = [params(d) for d in BATCH]
+    if which == "single":
+        plist = plist[2]
+    hw, n = 6, 7
+    wa, wb = dcax.Walker(plist), dcax.Walker(plist)
+    ga, gb = wa.new_nfft_grid(), wb.new_nfft_grid()
+    _, aa = wa.new_accumulator()
+    _, ab = wb.new_accumulator()
+    for _ in range(n):
+        wa.sweep(1)
+        wa.measure_nfft(ga, aa, hw)
+    wb.sweep_measure_nfft(3, gb, ab, hw)
+    wb.sweep_measure_nfft(n - 3, gb, ab, hw)
+    assert torch.equal(aa, ab)
+    for i in range(wa.W):
+        assert np.array_equal(wa.get_config(i), wb.get_config(i))
+        for sp in range(2):
+            assert np.array_equal(wa.copy_N(sp, walker=i)[1], wb.copy_N(sp, walker=i)[1])
+    err = float((ga - gb).abs().max())
+    scale = float(ga.abs().max())
+    print(f"  grids: max diff {err:.2e} of max {scale:.2e}", flush=True)
+    assert err <= 1e-12 * scale
+    wa.close()
+    wb.close()
