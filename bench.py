@@ -103,7 +103,8 @@ def kernel_us(s0, s1):
         {"timed_windows": n, "windows": s1["windows_enqueued"] - s0["windows_enqueued"]}
 
 
-def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None, walkers=1, nfft_hw=0):
+def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None, walkers=1, nfft_hw=0,
+            autotune=0):
     import numpy as np
     import torch
     from paper_1901_01047_amd import dcax
@@ -128,6 +129,11 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
     else:
         def sweep_measure(n):
             w.sweep_measure(n, acc, aux)
+    # the submatrix size comes from the autotuner, whose trial sweeps are
+    # part of the warm-up (untimed)
+    chosen_ks = None
+    if autotune:
+        chosen_ks, _ = w.autotune(sweeps_per_trial=autotune)
     sweep_measure(warmup)
     w.set_timing(TIMING_EVERY)
     torch.cuda.synchronize()
@@ -151,6 +157,7 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
         "kernel_us_per_window": kernel_us(s0, s1),
         "sign": s1["sign"], "refresh_max_drift": s1["max_drift"],
         "aborted_windows": s1["aborted_windows"] - s0["aborted_windows"],
+        "submatrix_k": chosen_ks if chosen_ks else plist[0].submatrix_k,
     }
     if graphs:
         # kernels inside a replayed graph cannot be timed one by one: the fold
@@ -262,18 +269,30 @@ def cpu_baseline(seconds=15.0, workload=None):
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = 1
-    a0 = w.n_acc_ins + w.n_acc_rem
-    p0 = w.n_prop
-    t0 = time.perf_counter()
-    n = 0
-    while time.perf_counter() - t0 < seconds:
-        w.step()
-        n += 1
-    dt = time.perf_counter() - t0
-    acc = w.n_acc_ins + w.n_acc_rem - a0
-    return {"value": acc / dt, "unit": "updates/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{n} single-vertex proposals ({w.n_prop - p0}) of the {workload} chain from a seeded "
-                      f"random configuration of order {c['k_init']}, {dt:.1f} s wall"}
+    def run_for(sec):
+        a0 = w.n_acc_ins + w.n_acc_rem
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < sec:
+            w.step()
+            n += 1
+        dt = time.perf_counter() - t0
+        return (w.n_acc_ins + w.n_acc_rem - a0) / dt, n, dt
+
+    v, n, dt = run_for(seconds)
+    out = {"value": v, "unit": "updates/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"{n} single-vertex proposals of the {workload} chain from a seeded "
+                     f"random configuration of order {c['k_init']}, {dt:.1f} s wall"}
+    try:
+        # the same chain continued with one BLAS thread
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            v1, n1, dt1 = run_for(seconds / 3)
+        out["value_1thread"] = v1
+        out["sample_1thread"] = f"the next {n1} proposals with one thread, {dt1:.1f} s wall"
+    except Exception:
+        pass
+    return out
 
 
 def main():
@@ -289,6 +308,8 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD,
                     help="single-walker (or --walkers) workload from paper_1901_01047_amd.workloads.CONFIGS")
     ap.add_argument("--walkers", type=int, default=1)
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="sweeps per candidate k_s for the autotuner during the warm-up (0: the workload's k_s)")
     ap.add_argument("--nfft", action="store_true",
                     help="also time the delayed-NFFT measurement against the direct one on the workload")
     ap.add_argument("--batch", type=int, default=0,
@@ -322,7 +343,10 @@ def main():
     wl = args.workload
     c = CONFIGS[wl]
     graphs = args.graphs == "on"
-    r64, cfg_v = run_gpu("fp64", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers)
+    at = args.autotune
+    r64, cfg_v = run_gpu("fp64", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers,
+                         autotune=at)
+    ks_text = f"k_s={r64['submatrix_k']} (autotuned)" if at else f"k_s={c['submatrix_k']}"
     out = {
         "metric": "accepted vertex updates/s (CT-AUX walker, FP64) + N-update fold TFLOP/s (% roofline)",
         "value": r64["value"], "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -330,7 +354,7 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{wl}: {c['cluster'][0]}x{c['cluster'][3]} periodic Hubbard cluster, t=1, "
                                f"t'={c['tp']}, U={c['U']}, beta={c['beta']}, mu={c['mu']} (n~{c['n_target']}), "
-                               f"K=1, {args.walkers} walker(s), k_s={c['submatrix_k']}, "
+                               f"K=1, {args.walkers} walker(s), {ks_text}, "
                                f"{c['n_freq']} Matsubara freqs, refresh every 32 sweeps",
                    "step": "1 sweep + 1 measurement of M(K,iw_n)",
                    "launch": "hipGraph per sweep" if graphs else "eager launches"},
@@ -338,11 +362,13 @@ def main():
         "fp64": {k: v for k, v in r64.items() if k != "roofline"},
     }
     if not args.fp64_only:
-        r32, _ = run_gpu("mixed", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers)
+        r32, _ = run_gpu("mixed", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers,
+                         autotune=at)
         out["fp32_mixed"] = r32
     if args.nfft:
         out["measurement"] = run_nfft(wl)
-        rn, _ = run_gpu("fp64", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers, nfft_hw=8)
+        rn, _ = run_gpu("fp64", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers, nfft_hw=8,
+                        autotune=at)
         out["fp64_nfft_measurement"] = {k: v for k, v in rn.items() if k != "roofline"}
     if args.batch:
         out["batch"] = {"fp64": run_batch("fp64", args.steps, args.warmup, args.batch),
