@@ -205,8 +205,6 @@ __global__ void k_refresh_begin(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
   w.detsign[0] = 1.0;
   w.detsign[1] = 1.0;
-  *reinterpret_cast<unsigned int*>(w.gjc[0]) = 0u;
-  *reinterpret_cast<unsigned int*>(w.gjc[1]) = 0u;
   w.ctl->drift = 0.0;
 }
 

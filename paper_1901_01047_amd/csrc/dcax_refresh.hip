@@ -18,8 +18,13 @@
 namespace dcax {
 
 constexpr int NB = 32;
-constexpr int GJC_RS = 2, GJC_OC = 2 + NB, GJC_SLOT = 2 + 2 * NB;
-inline size_t gjc_len(int cap) { return GJC_SLOT + 2 * (size_t)((cap + WG - 1) / WG); }
+// column-step pivot records: two rows at the pivot position, then per parity
+// one slot of 2 + NB doubles per workgroup of WG rows
+constexpr int GJC_OC = 0, GJC_SLOT = 2 * NB;
+__host__ __device__ inline size_t gjc_slot(int par, int b, int cap) {
+  return GJC_SLOT + ((size_t)par * ((cap + WG - 1) / WG) + b) * (2 + NB);
+}
+inline size_t gjc_len(int cap) { return gjc_slot(2, 0, cap); }
 
 template <typename T>
 __global__ void __launch_bounds__(WG) k_build_ninv(const View<T>* __restrict__ vs) {
@@ -141,16 +146,23 @@ __global__ void __launch_bounds__(PANEL_ROWS) k_gj_panel(const View<T>* __restri
 
 // Column-step panel elimination for orders above PANEL_ROWS.  The panel rows
 // are spread over workgroups, one row of the panel per thread (in registers).
-// Launch cidx (0 .. nb) first applies the Gauss-Jordan step of panel column
-// cidx - 1, whose pivot the previous launch chose, and stores the rows; then
-// (cidx < nb) each workgroup publishes its best pivot candidate for column
-// cidx among rows >= p0 + cidx, and the last workgroup to finish reduces the
-// candidates and writes the pivot record that the next launch applies: the
-// pivot row divided by the pivot (its own entry 1 / a_pp) and the old row at
-// the pivot position.  The arithmetic and tie rule are those of the LDS form.
-// Record layout (gjc, doubles per spin): [0] arrival counter (unsigned),
-// [1] pivot row index, [GJC_RS ..) scaled pivot row, [GJC_OC ..) old row at
-// the pivot position, [GJC_SLOT ..) (|value|, row) per workgroup.
+// Launch cidx (0 .. nb):
+// * cidx > 0: every workgroup reduces the pivot candidates that the previous
+//   launch published for column cidx - 1 (the same winner everywhere: the
+//   largest |value|, ties to the smaller row), takes the winner's row from
+//   its slot and the old row at the pivot position, and applies that
+//   column's Gauss-Jordan step to its rows, which it stores; workgroup 0
+//   records the pivot and the determinant sign;
+// * cidx < nb: each workgroup publishes its best candidate for column cidx
+//   among rows >= p0 + cidx with that row's values, and the owner of row
+//   p0 + cidx publishes it.
+// The next launch reads what this one wrote; two sets of slots alternate
+// between launches, so no launch writes what the one before it reads, and
+// kernel boundaries order everything (no fences, counters or waits).  The
+// arithmetic and tie rule are those of the one-workgroup form (k_gj_panel).
+// Record layout (gjc, doubles per spin): [GJC_OC + p NB ..) the row at the
+// pivot position for parity p = column & 1; then per parity and workgroup b
+// a slot of 2 + NB doubles at gjc_slot(p, b, cap): |value|, row, row values.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, int p0, int cidx) {
   const View<T>& w = vs[blockIdx.z];
@@ -167,52 +179,31 @@ __global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, i
   const int r = blockIdx.x * WG + t;
   const bool live = r < k;
   const size_t ro = live ? (size_t)r : 0;
+  __shared__ double vmax_s[WG / 64], rs_s[NB], oc_s[NB];
+  __shared__ int imax_s[WG / 64];
+  __shared__ double app_s;
   double a[NB];
 #pragma unroll
   for (int x = 0; x < NB; ++x) a[x] = Mg[ro + (size_t)(p0 + (x < nb ? x : 0)) * ld];
   if (cidx > 0) {
-    const int cm = cidx - 1, cp = p0 + cm;
-    const int pv = (int)rec[1];
-    const double* rs = rec + GJC_RS;
-    const double* oc = rec + GJC_OC;
-    if (r == cp) {
-#pragma unroll
-      for (int x = 0; x < NB; ++x) a[x] = rs[x];
-    } else {
-      if (r == pv)
-#pragma unroll
-        for (int x = 0; x < NB; ++x) a[x] = oc[x];
-      double f = 0.0;
-#pragma unroll
-      for (int x = 0; x < NB; ++x) f = (x == cm) ? a[x] : f;
-#pragma unroll
-      for (int x = 0; x < NB; ++x) a[x] = (x == cm) ? -f * rs[x] : a[x] - f * rs[x];
+    const int cm = cidx - 1, cp = p0 + cm, par = cm & 1;
+    double best = -1.0;
+    int bi = k;
+    for (int b = t; b < nwg; b += WG) {
+      const double* sl = rec + gjc_slot(par, b, w.cap);
+      const double v = sl[0];
+      const int i = (int)sl[1];
+      if (v > best || (v == best && i < bi)) {
+        best = v;
+        bi = i;
+      }
     }
-    if (live)
-#pragma unroll
-      for (int x = 0; x < NB; ++x)
-        if (x < nb) Mg[r + (size_t)(p0 + x) * ld] = a[x];
-  }
-  if (cidx == nb) return;
-  const int c = p0 + cidx;
-  double best = -1.0;
-  int bi = k;
-  if (live && r >= c) {
-#pragma unroll
-    for (int x = 0; x < NB; ++x) best = (x == cidx) ? fabs(a[x]) : best;
-    bi = r;
-  }
-  __shared__ double vmax_s[WG / 64];
-  __shared__ int imax_s[WG / 64];
-  __shared__ int last_s;
-  argmax_wave(best, bi);
-  if (lane == 0) {
-    vmax_s[wv] = best;
-    imax_s[wv] = bi;
-  }
-  __syncthreads();
-  auto* cnt = reinterpret_cast<unsigned int*>(rec);
-  if (t == 0) {
+    argmax_wave(best, bi);
+    if (lane == 0) {
+      vmax_s[wv] = best;
+      imax_s[wv] = bi;
+    }
+    __syncthreads();
     double pv = vmax_s[0];
     int piv = imax_s[0];
     for (int x = 1; x < WG / 64; ++x)
@@ -220,61 +211,76 @@ __global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, i
         pv = vmax_s[x];
         piv = imax_s[x];
       }
-    rec[GJC_SLOT + 2 * blockIdx.x] = pv;
-    rec[GJC_SLOT + 2 * blockIdx.x + 1] = (double)piv;
-  }
-  // every thread's row stores, then the candidate, before the arrival
-  __threadfence();
-  __syncthreads();
-  if (t == 0) last_s = (atomicAdd(cnt, 1u) == (unsigned)(nwg - 1)) ? 1 : 0;
-  __syncthreads();
-  if (!last_s) return;
-  __threadfence();
-  // last workgroup: reduce the candidates (nwg <= WG)
-  best = -1.0;
-  bi = k;
-  for (int b = t; b < nwg; b += WG) {
-    const double v = rec[GJC_SLOT + 2 * b];
-    const int i = (int)rec[GJC_SLOT + 2 * b + 1];
-    if (v > best || (v == best && i < bi)) {
-      best = v;
-      bi = i;
+    const bool valid = piv >= cp && piv < k;
+    const int pr = valid ? piv : cp;
+    // the pivot row: the winner's slot (or, without a valid pivot, the row at
+    // the pivot position itself)
+    const double* prow = valid ? rec + gjc_slot(par, piv / WG, w.cap) + 2 : rec + GJC_OC + par * NB;
+    if (t == 0) app_s = prow[cm];
+    __syncthreads();
+    const double a_pp = app_s;
+    if (t < NB) {
+      rs_s[t] = (t == cm) ? 1.0 / a_pp : prow[t] / a_pp;
+      oc_s[t] = rec[GJC_OC + par * NB + t];
     }
+    if (blockIdx.x == 0 && t == 0) {
+      w.ipiv[sp][cp] = pr;
+      if (!(pv > 0.0) || !isfinite(pv)) latch(w.ctl, ST_NUMERIC);
+      w.detsign[sp] *= ((a_pp < 0.0) ? -1.0 : 1.0) * ((pr != cp) ? -1.0 : 1.0);
+    }
+    __syncthreads();
+    if (r == cp) {
+#pragma unroll
+      for (int x = 0; x < NB; ++x) a[x] = rs_s[x];
+    } else {
+      if (r == pr)
+#pragma unroll
+        for (int x = 0; x < NB; ++x) a[x] = oc_s[x];
+      double f = 0.0;
+#pragma unroll
+      for (int x = 0; x < NB; ++x) f = (x == cm) ? a[x] : f;
+#pragma unroll
+      for (int x = 0; x < NB; ++x) a[x] = (x == cm) ? -f * rs_s[x] : a[x] - f * rs_s[x];
+    }
+    if (live)
+#pragma unroll
+      for (int x = 0; x < NB; ++x)
+        if (x < nb) Mg[r + (size_t)(p0 + x) * ld] = a[x];
+    __syncthreads();      // the candidates below reuse vmax_s / imax_s
+  }
+  if (cidx == nb) return;
+  const int c = p0 + cidx, par = cidx & 1;
+  double best = -1.0;
+  int bi = k;
+  if (live && r >= c) {
+#pragma unroll
+    for (int x = 0; x < NB; ++x) best = (x == cidx) ? fabs(a[x]) : best;
+    bi = r;
   }
   argmax_wave(best, bi);
-  __syncthreads();
   if (lane == 0) {
     vmax_s[wv] = best;
     imax_s[wv] = bi;
   }
   __syncthreads();
-  double pvv = vmax_s[0];
-  int piv = imax_s[0];
+  double wbest = vmax_s[0];
+  int wbi = imax_s[0];
   for (int x = 1; x < WG / 64; ++x)
-    if (vmax_s[x] > pvv || (vmax_s[x] == pvv && imax_s[x] < piv)) {
-      pvv = vmax_s[x];
-      piv = imax_s[x];
+    if (vmax_s[x] > wbest || (vmax_s[x] == wbest && imax_s[x] < wbi)) {
+      wbest = vmax_s[x];
+      wbi = imax_s[x];
     }
-  const int pr = (piv >= c && piv < k) ? piv : c;
-  __shared__ double app_s;
-  if (t == cidx) app_s = Mg[pr + (size_t)(p0 + t) * ld];
-  __syncthreads();
-  const double a_pp = app_s;
-  if (t < nb) {
-    const double vp = Mg[pr + (size_t)(p0 + t) * ld];
-    rec[GJC_OC + t] = Mg[c + (size_t)(p0 + t) * ld];
-    rec[GJC_RS + t] = (t == cidx) ? 1.0 / a_pp : vp / a_pp;
-  } else if (t < NB) {
-    rec[GJC_OC + t] = 0.0;
-    rec[GJC_RS + t] = 0.0;
-  }
+  double* sl = rec + gjc_slot(par, blockIdx.x, w.cap);
   if (t == 0) {
-    rec[1] = (double)pr;
-    w.ipiv[sp][c] = pr;
-    if (!(pvv > 0.0) || !isfinite(pvv)) latch(w.ctl, ST_NUMERIC);
-    w.detsign[sp] *= ((a_pp < 0.0) ? -1.0 : 1.0) * ((pr != c) ? -1.0 : 1.0);
-    *cnt = 0u;
+    sl[0] = wbest;
+    sl[1] = (double)wbi;
   }
+  if (r == wbi)
+#pragma unroll
+    for (int x = 0; x < NB; ++x) sl[2 + x] = a[x];
+  if (r == c)
+#pragma unroll
+    for (int x = 0; x < NB; ++x) rec[GJC_OC + par * NB + x] = a[x];
 }
 
 // Applies the panel's row swaps to the other columns, moves their panel rows
