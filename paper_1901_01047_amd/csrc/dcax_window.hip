@@ -1353,29 +1353,39 @@ __device__ inline void fold_tile(T* C, int ldc, const T* A, int lda, const T* B,
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) acc[rb] = typename Mfma<T>::acc_t{0, 0, 0, 0};
   // Sixteen steps of the inner dimension per pass, all their loads issued
-  // before the first product.  Rows and columns outside the tile are read
-  // (the panels hold KS_MAX rows of cap entries, so every address is in
-  // bounds) but never stored; steps beyond K are zeroed, since the panels'
-  // unused rows hold earlier windows' data.
-  for (int s0 = 0; s0 < K; s0 += 16) {
+  // before the first product; the remaining steps in passes of four.  Rows
+  // and columns outside the tile are read (the panels hold KS_MAX rows of cap
+  // entries, so every address is in bounds) but never stored; steps beyond K
+  // are zeroed, since the panels' unused rows hold earlier windows' data.
+  int s0 = 0;
+  for (; s0 + 16 <= K; s0 += 16) {
     T bv[4], av[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int sk = s0 + 4 * u + lk;
-      const bool kin = sk < K;
-      const size_t skc = kin ? (size_t)sk : 0;
-      const T bb = Bg[skc * ldb + jb + li];
-      bv[u] = kin ? bb : (T)0;
+      const size_t sk = (size_t)(s0 + 4 * u + lk);
+      bv[u] = Bg[sk * ldb + jb + li];
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
-        const T aa = Ag[skc * lda + i0 + rb * 16 + li];
-        av[u][rb] = kin ? aa : (T)0;
-      }
+      for (int rb = 0; rb < 4; ++rb) av[u][rb] = Ag[sk * lda + i0 + rb * 16 + li];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) acc[rb] = Mfma<T>::run(bv[u], av[u][rb], acc[rb]);
+  }
+  for (; s0 < K; s0 += 4) {
+    const int sk = s0 + lk;
+    const bool kin = sk < K;
+    const size_t skc = kin ? (size_t)sk : 0;
+    const T bb = Bg[skc * ldb + jb + li];
+    const T bv = kin ? bb : (T)0;
+    T av[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const T aa = Ag[skc * lda + i0 + rb * 16 + li];
+      av[rb] = kin ? aa : (T)0;
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[rb] = Mfma<T>::run(bv, av[rb], acc[rb]);
   }
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
