@@ -103,6 +103,20 @@ def kernel_us(s0, s1):
         {"timed_windows": n, "windows": s1["windows_enqueued"] - s0["windows_enqueued"]}
 
 
+def fold_ranks(s0, s1):
+    """Windows of the timed region by fold rank m: counts per bin (m = 0,
+    then 1-4, 5-8, ..., 61-64) and the m range holding the median window."""
+    h = [b - a for a, b in zip(s0["fold_rank_hist"], s1["fold_rank_hist"])]
+    tot, run, med = sum(h), 0, 0
+    for b, n in enumerate(h):
+        run += n
+        if 2 * run >= tot:
+            med = b
+            break
+    lo, hi = (0, 0) if med == 0 else (4 * med - 3, 4 * med)
+    return {"bins_m_0_then_by_4": h, "median_m_range": [lo, hi]}
+
+
 def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None, walkers=1, nfft_hw=0,
             autotune=0):
     import numpy as np
@@ -153,6 +167,7 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
         "proposals_per_s": props / dt, "acceptance": acc_upd / max(props, 1),
         "mean_order": sum(w.orders()) / walkers, "windows": windows, "walkers": walkers,
         "mean_fold_rank": (s1["flips_folded"] - s0["flips_folded"]) / max(windows, 1),
+        "fold_rank_distribution": fold_ranks(s0, s1),
         "roofline": roofline(s0, s1, precision, fold_traffic(workload, precision)),
         "kernel_us_per_window": kernel_us(s0, s1),
         "sign": s1["sign"], "refresh_max_drift": s1["max_drift"],
@@ -205,6 +220,7 @@ def run_batch(precision, steps, warmup, n_walkers=512):
            "proposals_per_s": (s1["proposals"] - s0["proposals"]) / dt,
            "order_min_mean_max": [min(orders), sum(orders) / len(orders), max(orders)],
            "mean_fold_rank": (s1["flips_folded"] - s0["flips_folded"]) / max(s1["windows"] - s0["windows"], 1),
+           "fold_rank_distribution": fold_ranks(s0, s1),
            "warmup_seconds": t_warm, "roofline": roofline(s0, s1, precision),
            "kernel_us_per_window": kernel_us(s0, s1)}
     w.close()

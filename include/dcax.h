@@ -140,6 +140,7 @@ typedef struct {
   double max_drift;         /* largest such drift */
   int64_t windows_enqueued; /* windows launched while timing was on, timed or not
                                (fold_launches / windows_enqueued is the sampled share) */
+  int64_t fold_rank_hist[17]; /* windows by fold rank m: [0] m = 0, [b] 4b-3 <= m <= 4b */
 } dcax_stats;
 
 /* Create a batch of n_walkers independent walkers (Markov chains; Sec. 3.1,

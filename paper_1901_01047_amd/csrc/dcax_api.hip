@@ -1375,6 +1375,9 @@ dcax_status dcax_copy_N(dcax_walker w, int32_t walker, int32_t spin, double* hos
   return st;
 }
 
+static_assert(sizeof(dcax_stats::fold_rank_hist) == sizeof(int64_t) * FOLD_RANK_BINS,
+              "fold-rank histogram bins of the ABI and of the control block differ");
+
 dcax_status dcax_get_stats(dcax_walker w, int32_t walker, dcax_stats* out) {
   if (!w || !out) return fail(DCAX_E_INVAL, "NULL argument");
   if (walker < -1 || walker >= w->W) return fail(DCAX_E_INVAL, "walker index out of range");
@@ -1392,6 +1395,7 @@ dcax_status dcax_get_stats(dcax_walker w, int32_t walker, dcax_stats* out) {
     out->fold_flops += h.fold_flops;
     out->fold_bytes += h.fold_bytes;
     out->aborted_windows += h.n_abort;
+    for (int b = 0; b < FOLD_RANK_BINS; ++b) out->fold_rank_hist[b] += h.m_hist[b];
   }
   out->sign = w->h_ctl[walker >= 0 ? walker : 0].sign;
   out->sweeps = w->sweeps_done;

@@ -19,6 +19,8 @@ constexpr int WG = 256;      // threads per workgroup of the streaming kernels
 
 enum StatusCode { ST_OK = 0, ST_NUMERIC = 1, ST_CAPACITY = 2, ST_TRACE = 3 };
 
+constexpr int FOLD_RANK_BINS = 17;  // m = 0 and sixteen bins of four up to m = 64
+
 struct Ctl {
   int k;            // current expansion order
   int status;       // latched StatusCode
@@ -51,6 +53,8 @@ struct Ctl {
   long long sweeps_left;
   int meas_due;
   int pad_;
+  // windows by fold rank: bin 0 is m = 0, bin b holds 4b - 3 <= m <= 4b
+  long long m_hist[FOLD_RANK_BINS];
 };
 
 struct WinProp {      // one proposal of the current window

@@ -1009,6 +1009,7 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     c->n_mismatch += n_mis;
     c->pos += n_done;
     c->n_windows += 1;
+    c->m_hist[(m + 3) >> 2] += 1;
     if (carry >= 0) {
       c->carry_id = carry;
       c->n_abort += 1;

@@ -59,7 +59,7 @@ class Stats(ctypes.Structure):
                 ("fold_launches", ctypes.c_int64), ("accept_seconds", ctypes.c_double),
                 ("window_seconds", ctypes.c_double), ("aborted_windows", ctypes.c_int64),
                 ("last_drift", ctypes.c_double), ("max_drift", ctypes.c_double),
-                ("windows_enqueued", ctypes.c_int64)]
+                ("windows_enqueued", ctypes.c_int64), ("fold_rank_hist", ctypes.c_int64 * 17)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -269,7 +269,9 @@ class Walker:
         """Counters of one walker, or summed over the batch (walker=-1)."""
         s = Stats()
         _check(load().dcax_get_stats(self._h, int(walker), ctypes.byref(s)))
-        return {f: getattr(s, f) for f, _ in Stats._fields_}
+        out = {f: getattr(s, f) for f, _ in Stats._fields_}
+        out["fold_rank_hist"] = list(s.fold_rank_hist)
+        return out
 
     def set_submatrix_k(self, ks, walker=-1):
         _check(load().dcax_set_submatrix_k(self._h, int(walker), int(ks)))

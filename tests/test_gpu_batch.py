@@ -52,8 +52,13 @@ def test_batch_equals_individual_walkers(precision):
         assert torch.equal(aux_b[i], aux1)
         s1 = w1.stats()
         sb = wb.stats(walker=i)
-        for key in ("proposals", "accepted_insertions", "accepted_removals", "windows"):
+        for key in ("proposals", "accepted_insertions", "accepted_removals", "windows", "fold_rank_hist"):
             assert sb[key] == s1[key], (i, key)
+        # every window lands in one fold-rank bin; the bins bound the summed rank
+        h = s1["fold_rank_hist"]
+        assert sum(h) == s1["windows"]
+        assert sum((4 * b - 3) * n for b, n in enumerate(h) if b) <= s1["flips_folded"] <= \
+            sum(4 * b * n for b, n in enumerate(h))
         print(f"  walker {i}: order {len(c1)}, proposals {s1['proposals']}, identical", flush=True)
         w1.close()
     assert wb.refresh() < (1e-9 if precision == dcax.DCAX_FP64 else 1e-3)
