@@ -484,16 +484,56 @@ __global__ void __launch_bounds__(NW * 64) k_gram_rows(const View<T>* __restrict
   const int nE = c->nE;
   const int k0 = c->k0, nC = c->nC;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // a wavefront takes its candidate columns cc = wv, wv + NW, ... together,
+  // so that each entry of the row is loaded once, with four steps of 64
+  // entries per pass in flight and a partial sum per step (the last pass
+  // weighs the steps beyond the order zero)
+  constexpr int MAXC = (KS_MAX + GWV - 1) / GWV;
+  const auto gcol = gp(w.gcol);
+  const size_t cap = w.cap;
   for (int x = blockIdx.x; x < nE; x += gridDim.x) {
     const int cx = w.el_cand[x];
-    const auto Rx = gp(w.R[sp] + (size_t)x * w.cap);
+    const auto Rx = gp(w.R[sp] + (size_t)x * cap);
     const auto G = gp(w.gram[sp] + x * KS_MAX);
-    for (int cc = wv; cc < nC; cc += GWV) {
-      const auto gc = gp(w.gcol + (size_t)cc * w.cap);
-      double s = 0.0;
-      for (int i = lane; i < k0; i += 64) s += (double)Rx[i] * (double)gc[i];
-      s = wave_sum(s);
-      if (lane == 0) {
+    size_t goff[MAXC];
+#pragma unroll
+    for (int q = 0; q < MAXC; ++q) {
+      const int cc = wv + q * GWV;
+      goff[q] = (size_t)(cc < nC ? cc : 0) * cap;
+    }
+    // columns this wavefront owns (the same count in every lane)
+    const int nq = uni(nC > wv ? (nC - wv + GWV - 1) / GWV : 0);
+    double acc[MAXC][4];
+#pragma unroll
+    for (int q = 0; q < MAXC; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[q][u] = 0.0;
+    for (int i = lane; i < k0; i += 256) {
+      // steps past the order read a valid entry and weigh it zero
+      double a[4], g[MAXC][4];
+      int ic[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int iu = i + 64 * u;
+        ic[u] = iu < k0 ? iu : i;
+        a[u] = (double)Rx[ic[u]] * (iu < k0 ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < MAXC; ++q)
+        if (q < nq)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) g[q][u] = (double)gcol[goff[q] + ic[u]];
+#pragma unroll
+      for (int q = 0; q < MAXC; ++q)
+        if (q < nq)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[q][u] += a[u] * g[q][u];
+    }
+#pragma unroll
+    for (int q = 0; q < MAXC; ++q) {
+      const int cc = wv + q * GWV;
+      const double s = wave_sum((acc[q][0] + acc[q][1]) + (acc[q][2] + acc[q][3]));
+      if (lane == 0 && cc < nC) {
         const int ec = w.cand_el[cc];
         const double Dc = w.ev[sp][s01(w.el_s[ec])] - 1.0;
         const double g = s + (cx >= 0 ? w.gCC[cx * KS_MAX + cc] : 0.0);
