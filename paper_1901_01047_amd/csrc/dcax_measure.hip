@@ -153,19 +153,27 @@ __global__ void __launch_bounds__(WG) k_meas_block(const View<T>* __restrict__ v
       const int a = ab / Nc, b = ab % Nc;
       const int ia0 = off[a], ia1 = off[a + 1], jb0 = off[b], jb1 = off[b + 1];
       double sre[4] = {0, 0, 0, 0}, sim[4] = {0, 0, 0, 0};
+      // buckets are padded to multiples of 16 rows, so the inner dimension
+      // runs in passes of four 4-step MFMAs whose loads are issued together
+      const int nac = na < n_freq ? na : 0;
+      const T ew = (T)(na < n_freq ? 1 : 0);
       for (int ib = ia0; ib < ia1; ib += 16) {
         typename Mfma<T>::acc_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
         const int ip = ib + li;
-        for (int jp = jb0; jp < jb1; jp += 4) {
-          const int jk = jp + lk;
-          const T m = Ms[ip + (size_t)jk * ldm];
-          T er = 0, ei = 0;
-          if (na < n_freq) {
-            er = E[2 * ((size_t)jk * n_freq + na)];
-            ei = E[2 * ((size_t)jk * n_freq + na) + 1];
+        for (int jp = jb0; jp < jb1; jp += 16) {
+          T m[4], er[4], ei[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const size_t jk = (size_t)(jp + 4 * u + lk);
+            m[u] = Ms[ip + jk * ldm];
+            er[u] = E[2 * (jk * n_freq + nac)] * ew;
+            ei[u] = E[2 * (jk * n_freq + nac) + 1] * ew;
           }
-          dr = Mfma<T>::run(er, m, dr);
-          di = Mfma<T>::run(ei, m, di);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            dr = Mfma<T>::run(er[u], m[u], dr);
+            di = Mfma<T>::run(ei[u], m[u], di);
+          }
         }
         // lane holds D[n = n0 + row(lane, r)][i' = ib + li]
         const int i = order[ip];
