@@ -15,8 +15,8 @@
 namespace dcax {
 
 // Counting sort of the vertices by site, buckets padded to 16 rows.  The
-// sites are staged in LDS; one thread per site places its vertices in their
-// original order (stable).
+// sites are staged in LDS; one wavefront per site places its vertices in
+// their original order (stable).
 constexpr int SORT_MAX = 32768 + 128;
 template <typename T>
 __global__ void __launch_bounds__(WG) k_meas_sort(const View<T>* __restrict__ vs, int gated) {
@@ -52,10 +52,19 @@ __global__ void __launch_bounds__(WG) k_meas_sort(const View<T>* __restrict__ vs
   for (int a = threadIdx.x; a <= Nc; a += WG) off[a] = cnt_s[a];
   for (int i = threadIdx.x; i < kpad && i < kpad_cap; i += WG) order[i] = -1;
   __syncthreads();
-  for (int a = threadIdx.x; a < Nc; a += WG) {
+  // stable placement: one wavefront per site at a time, the vertices in
+  // chunks of 64 ranked by a ballot
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int a = threadIdx.x >> 6; a < Nc; a += WG / 64) {
     int o = cnt_s[a];
-    for (int i = 0; i < k; ++i)
-      if (site_s[i] == a) order[o++] = i;
+    for (int i0 = 0; i0 < k; i0 += 64) {
+      const int i = i0 + lane;
+      const bool hit = i < k && site_s[i] == a;
+      const unsigned long long msk = __ballot(hit);
+      if (hit) order[o + __popcll(msk & below)] = i;
+      o += __popcll(msk);
+    }
   }
 }
 
