@@ -252,11 +252,24 @@ __global__ void __launch_bounds__(WG) k_meas_K(const View<T>* __restrict__ vs, d
     if (n < n_freq) {
       double re = 0.0, im = 0.0;
       for (int a = 0; a < Nc; ++a) {
-        // t = sum_b conj(phi_b) M(a, b), four independent partial sums so
-        // that the loads of a row are in flight together
+        // t = sum_b conj(phi_b) M(a, b), sixteen loads of a row in flight
+        // together and four independent partial sums
         double tr[4] = {0, 0, 0, 0}, ti[4] = {0, 0, 0, 0};
         const auto row = Mab + 2 * ((size_t)a * Nc * n_freq + n);
         int b = 0;
+        for (; b + 16 <= Nc; b += 16) {
+          double mr[16], mi[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            mr[u] = row[2 * (size_t)(b + u) * n_freq];
+            mi[u] = row[2 * (size_t)(b + u) * n_freq + 1];
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            tr[u & 3] += pr_s[b + u] * mr[u] + pi_s[b + u] * mi[u];
+            ti[u & 3] += pr_s[b + u] * mi[u] - pi_s[b + u] * mr[u];
+          }
+        }
         for (; b + 4 <= Nc; b += 4) {
           double mr[4], mi[4];
 #pragma unroll
