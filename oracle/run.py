@@ -39,32 +39,26 @@ def estimate_G(model, acc, B=32, taus=None, n_freq=None, spin_average=False):
     Returns a dict with 'Giw', 'Giw_err' of shape (2, Nc, n_freq) and, if
     taus is given, 'Gtau', 'Gtau_err' of shape (2, Nc, len(taus)); with
     spin_average the leading spin axis is averaged away (inside the
-    jackknife, so the error bars are those of the average).
+    jackknife, so the error bars are those of the average).  Errors of the
+    complex G(K, i w_n) are sigma_re + 1j sigma_im.
     """
     s, sM, sD = acc.arrays()
     nf = acc.n_freq if n_freq is None else n_freq
     out = {}
 
-    def giw(Mavg):
+    def giw(tot_M, tot_D, tot_s):
+        Mavg = tot_M / tot_s
         g = np.stack([measure.finalize_G_iw(model, Mavg[sp], nf) for sp in range(2)])
         return g.mean(axis=0) if spin_average else g
 
-    def gtau(Mavg, Davg):
+    def gtau(tot_M, tot_D, tot_s):
+        Mavg, Davg = tot_M / tot_s, tot_D / tot_s
         g = np.stack([measure.G_tau_from_iw(model, Mavg[sp], Davg[sp], nf, taus) for sp in range(2)])
         return g.mean(axis=0) if spin_average else g
 
-    sMb = stats.bins(sM[:, :, :, :nf], B)
-    sDb = stats.bins(sD, B)
-    sb = stats.bins(s, B)
-    tot_M, tot_D, tot_s = sMb.sum(0), sDb.sum(0), sb.sum()
-    out["Giw"] = giw(tot_M / tot_s)
-    loo = np.array([giw((tot_M - sMb[b]) / (tot_s - sb[b])) for b in range(B)])
-    out["Giw_err"] = np.sqrt((B - 1) / B * ((loo.real - loo.real.mean(0)) ** 2).sum(0)) + \
-        1j * np.sqrt((B - 1) / B * ((loo.imag - loo.imag.mean(0)) ** 2).sum(0))
+    binned = (stats.bins(sM[:, :, :, :nf], B), stats.bins(sD, B), stats.bins(s, B))
+    out["Giw"], out["Giw_err"] = stats.jackknife(giw, binned)
     if taus is not None:
-        out["Gtau"] = gtau(tot_M / tot_s, tot_D / tot_s)
-        loo = np.array([gtau((tot_M - sMb[b]) / (tot_s - sb[b]), (tot_D - sDb[b]) / (tot_s - sb[b]))
-                        for b in range(B)])
-        out["Gtau_err"] = np.sqrt((B - 1) / B * ((loo - loo.mean(0)) ** 2).sum(0))
+        out["Gtau"], out["Gtau_err"] = stats.jackknife(gtau, binned)
     out["sign"] = s.mean()
     return out

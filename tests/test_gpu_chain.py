@@ -69,14 +69,16 @@ def test_atom_order_distribution():
     w.close()
 
 
-def test_2x2_green_function_vs_ed():
-    print("[chain] 2x2 vs ED", flush=True)
+def chain_vs_ed(precision=dcax.DCAX_FP64, refresh_every=50, B=32, per=100, nf=512, seed_offset=0):
+    """A 2x2 chain on the walker's own generator: spin-averaged G(K, i w_n)
+    and G(K, tau) with jackknife errors over B bins of `per` sweeps (the
+    oracle's pinned jackknife), z scores against exact diagonalisation."""
     name = "2x2_U4_b5"
-    nf = 512
-    w = dcax.Walker(dcax.make_params(**params_kwargs(name, n_freq=nf, refresh_every=50)))
+    kw = params_kwargs(name, n_freq=nf)
+    kw["seed"] += seed_offset
+    w = dcax.Walker(dcax.make_params(**kw, precision=precision, refresh_every=refresh_every))
     m = model(name)
     w.sweep(100)
-    B, per = 32, 100
     accs = []
     for b in range(B):
         acc, aux = w.new_accumulator()
@@ -90,29 +92,25 @@ def test_2x2_green_function_vs_ed():
     e = ed.ED(geometry.hopping_matrix(m.a1, m.a2), U=m.U, mu=m.mu, beta=m.beta)
     ph = ed.momentum_phases(m.sites, m.K)
     taus = np.linspace(0.05, m.beta - 0.05, 20)
-
-    def G_of(sMb, sAb):
-        Mavg = sMb / sAb[0]
-        g_iw = np.mean([measure.finalize_G_iw(m, Mavg[sp][:, :24], 24) for sp in range(2)], axis=0)
-        g_t = np.mean([measure.G_tau_from_iw(m, Mavg[sp], sAb[1 + sp] / sAb[0], nf, taus)
-                       for sp in range(2)], axis=0)
-        return g_iw, g_t
-
-    tot_M, tot_A = sM.sum(0), sA.sum(0)
-    g_iw, g_t = G_of(tot_M[..., :nf], tot_A)
-    loo = [G_of(tot_M - sM[b], tot_A - sA[b]) for b in range(B)]
-    li = np.array([x[0] for x in loo])
-    lt = np.array([x[1] for x in loo])
-    err_re = np.sqrt((B - 1) / B * ((li.real - li.real.mean(0)) ** 2).sum(0))
-    err_im = np.sqrt((B - 1) / B * ((li.imag - li.imag.mean(0)) ** 2).sum(0))
-    err_t = np.sqrt((B - 1) / B * ((lt - lt.mean(0)) ** 2).sum(0))
+    g_iw, err_iw = stats.jackknife(
+        lambda M, A: np.mean([measure.finalize_G_iw(m, (M / A[0])[sp][:, :24], 24) for sp in range(2)], axis=0),
+        (sM, sA))
+    g_t, err_t = stats.jackknife(
+        lambda M, A: np.mean([measure.G_tau_from_iw(m, (M / A[0])[sp], A[1 + sp] / A[0], nf, taus)
+                              for sp in range(2)], axis=0),
+        (sM, sA))
     zs = []
     for iK in range(2):     # (pi,pi) and (0,pi) mirror these at half filling
         want = e.G_iw(ph[iK], 0, 24)
-        zs.append(np.abs(g_iw[iK].real - want.real) / np.maximum(err_re[iK], 1e-12))
-        zs.append(np.abs(g_iw[iK].imag - want.imag) / err_im[iK])
+        zs.append(np.abs(g_iw[iK].real - want.real) / np.maximum(err_iw[iK].real, 1e-12))
+        zs.append(np.abs(g_iw[iK].imag - want.imag) / err_iw[iK].imag)
         zs.append(np.abs(g_t[iK] - e.G_tau(ph[iK], 0, taus)) / err_t[iK])
-    z = np.concatenate(zs)
+    return w, np.concatenate(zs), g_iw
+
+
+def test_2x2_green_function_vs_ed():
+    print("[chain] 2x2 vs ED", flush=True)
+    w, z, _ = chain_vs_ed()
     n_out = int((z >= 3).sum())
     print(f"  points {len(z)}, beyond 3 sigma {n_out}, max z {z.max():.2f}", flush=True)
     assert n_out <= max(1, round(0.01 * len(z))) and z.max() < 4.5
