@@ -1229,11 +1229,15 @@ __global__ void __launch_bounds__(NW * 64) k_ygemm(const View<T>* __restrict__ v
 // Fold factors in the extended index space (window-start vertices, then the
 // inserted spins at rows k0 .. k0+mi-1), for N' = N + A B with
 // A = (E_S - G_{.S}) diag(-Delta_S) and B = Gt_S^{-1} N_{S.}:
-//   an inserted spin c: rows < k0 Delta_c (N g_{I,c}), inserted rows
-//     delta - Gt_{C,c};
-//   a removed vertex p: e_p - N_ext{.p};
-//   B with the rows of the extended N;
-// and the extension of N itself: row k0+j = X_c, column k0+j = e_{k0+j}.
+//   rows < k0 of A: an inserted spin c gives Delta_c (N g_{I,c}), a removed
+//     vertex p gives e_p - N_{.p};
+//   B with the rows of the extended N (X_c for the inserted spins).
+// The rows of the inserted spins come out of the fold as B itself: for x in
+// S, Gt_{x,S} Gt_S^{-1} = e_x, so X_x + (e_x - Gt_{x,S}) B = B_x exactly.
+// Evaluating that sum instead cancels X_x against X_x, which loses digits
+// whenever the new row is small (e^{V_x} - 1 large), and those errors grow
+// in later windows.  So A is zero on the inserted rows and B_x is stored
+// there directly; on the rows < k0 the inserted columns (e_{k0+j}) are zero.
 // A workgroup covers 64 columns; its four wavefronts share the S rows.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs) {
@@ -1247,7 +1251,7 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
   if ((int)blockIdx.x * 64 >= kx) return;
   __shared__ double gi_s[KS_MAX * KS_MAX];
   __shared__ double rv_s[KS_MAX][64];
-  __shared__ int e_s[KS_MAX], row_s[KS_MAX], cand_s[KS_MAX], slot_s[KS_MAX], ins_s[KS_MAX];
+  __shared__ int e_s[KS_MAX], row_s[KS_MAX], cand_s[KS_MAX], slot_s[KS_MAX];
   __shared__ double d_s[KS_MAX];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   {
@@ -1275,47 +1279,31 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
     slot_s[t] = w.el_slot[e];
     d_s[t] = w.ev[sp][s01(w.el_s[e])] - 1.0;
   }
-  if (t < mi) ins_s[t] = w.ins_el[t];
   __syncthreads();
   const T* R = w.R[sp];
   T* N = w.N[sp];
   const size_t ld = w.ld;
   const T* Y = w.Y[sp];
-  const auto gram = gp(w.gram[sp]);
   const auto Ag = gp(w.A[sp]);
   const auto Bg = gp(w.B[sp]);
   constexpr int NWV = WG / 64;
   // groups of 64 columns, grid-strided over blockIdx.x.  A wavefront takes
-  // the entries q = wv, wv + 4, ... of S (and of the inserted spins, mi <= m)
-  // eight at a time: the rows of N for B, the entries of A and the extension
-  // of N are loaded together, then stored.
+  // the entries q = wv, wv + 4, ... of S eight at a time: the rows of N for
+  // B and the entries of A are loaded together, then stored.
   for (int i0 = blockIdx.x * 64; i0 < kx; i0 += gridDim.x * 64) {
     const int i = i0 + lane;
     const bool live = i < kx;
     const int ic = live ? i : 0;
     const int il = (ic < k0) ? ic : 0;
-    const int insr = (ic >= k0) ? ins_s[ic - k0] : 0;
     for (int q0 = wv; q0 < m; q0 += 8 * NWV) {
-      T rv[8], tv[8], xv[8];
-      double gv[8];
+      T rv[8], tv[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int q = q0 + u * NWV;
         const int sc = q < m ? q : q0;
         rv[u] = R[(size_t)e_s[sc] * w.cap + il];
-        size_t off;
-        const T* src;
-        if (cand_s[sc] >= 0) {
-          src = Y;
-          off = (ic < k0) ? (size_t)(row_s[sc] - k0) * w.cap + ic : 0;
-        } else {
-          const int p = slot_s[sc];
-          src = (ic < k0) ? N : R;
-          off = (ic < k0) ? ic + (size_t)p * ld : (size_t)insr * w.cap + p;
-        }
-        tv[u] = src[off];
-        gv[u] = gram[insr * KS_MAX + e_s[sc]];
-        xv[u] = R[(size_t)(q < mi ? ins_s[q] : e_s[sc]) * w.cap + il];
+        // rows < k0 of A: Y for a candidate, column p of N for a removed vertex
+        tv[u] = (cand_s[sc] >= 0) ? Y[(size_t)(row_s[sc] - k0) * w.cap + il] : N[il + (size_t)slot_s[sc] * ld];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -1326,27 +1314,21 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
           rv_s[q][lane] = x;
         }
         if (live && q < m) {
-          // A, column-major [s][i]
-          double v;
-          if (cand_s[q] >= 0) {
-            const int jj = row_s[q] - k0;
-            v = (i < k0) ? d_s[q] * (double)tv[u] : (i - k0 == jj ? 1.0 : 0.0) - gv[u];
-          } else {
-            v = (i == slot_s[q] ? 1.0 : 0.0) - (double)tv[u];
-          }
+          // A, column-major [s][i]; zero on the inserted rows
+          double v = 0.0;
+          if (i < k0) v = (cand_s[q] >= 0) ? d_s[q] * (double)tv[u] : (i == slot_s[q] ? 1.0 : 0.0) - (double)tv[u];
           Ag[(size_t)q * w.cap + i] = (T)v;
         }
-        // extension of N (no workgroup reads rows or columns >= k0 of N here)
-        if (live && q < mi) {
-          if (i < k0) N[(k0 + q) + (size_t)i * ld] = xv[u];
-          N[i + (size_t)(k0 + q) * ld] = (i == k0 + q) ? (T)1 : (T)0;
-        }
+        // inserted columns of the rows < k0 (no workgroup reads columns >= k0
+        // of N here)
+        if (live && i < k0 && q < mi) N[i + (size_t)(k0 + q) * ld] = (T)0;
       }
     }
     __syncthreads();
     if (live) {
       // B, row-major [a][i] = sum_b Gt^{-1}[a][b] Row_{S_b}[i], four rows a
-      // per pass over rv_s (each sum runs over b in order)
+      // per pass over rv_s (each sum runs over b in order); an inserted
+      // spin's row of B is also its row of the folded N
       for (int a0 = wv; a0 < m; a0 += 4 * NWV) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         int ar[4];
@@ -1358,8 +1340,13 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
           for (int u = 0; u < 4; ++u) acc[u] += gi_s[ar[u] * KS_MAX + b] * r;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (a0 + u * NWV < m) Bg[(size_t)(a0 + u * NWV) * w.cap + i] = (T)acc[u];
+        for (int u = 0; u < 4; ++u) {
+          const int a = a0 + u * NWV;
+          if (a < m) {
+            Bg[(size_t)a * w.cap + i] = (T)acc[u];
+            if (cand_s[a] >= 0) N[row_s[a] + (size_t)i * ld] = (T)acc[u];
+          }
+        }
       }
     }
     __syncthreads();      // rv_s is rewritten by the next group

@@ -2,27 +2,21 @@
 
 * G0(r, tau) table against the oracle's table;
 * refresh (FP64 Gauss-Jordan) against direct inversion;
-* replay of oracle traces with forced decisions: ratios and N against the
-  oracle (tolerances below), same vertex ids, no decision on the other side
-  of |R|;
+* replay of oracle traces with forced decisions: every ratio and N against
+  the oracle and against the same chain replayed in extended precision
+  (oracle/exact.py, pinned against 40-digit determinants), same vertex ids,
+  no decision on the other side of |R|;
 * the measurement M(K, i w_n) of a fixed configuration, and the finalisation
   G = G0 - G0 <M> G0 / beta, against the oracle's direct sums;
 * error paths that the host can force (unknown replay id, latched state).
 
 Tolerances (FP64):
-* ratios: |R - R_orc| <= 1e-10 max(|R_orc|, 1), i.e. relative for |R| >= 1
-  and on the scale of the acceptance uniform below (a decision compares u in
-  [0, 1) with |R|), for every ratio; and relative 1e-10 for |R_orc| >= 1e-2
-  except where the same submatrix algebra evaluated in plain NumPy FP64 is
-  itself off by at least a tenth of the kernel's error.  Small and
-  cancelling ratios come from Schur complements of O(e^gamma) terms: on the
-  doped 4x4 replay state an exact (80-bit) evaluation puts that FP64
-  algebra 8e-10 off on a 2e-2 ratio whose single-vertex (oracle) evaluation
-  is 3e-12 off, so no FP64 evaluation of the submatrix method can promise
-  1e-10 relative there;
-* N: max|N - N_orc| <= 1e-10 max|N_orc| (rows of N span e^{+-gamma}, so the
-  elementwise relative error is ill-posed), or within 10x of the same
-  algebra's plain FP64 evaluation where that is larger;
+* ratios: |R - R_ref| <= 1e-10 |R_ref| for every ratio, with R_ref the
+  extended-precision value and, separately, the FP64 oracle's (both the
+  oracle and the kernels' submatrix algebra land within ~1e-11 of the
+  extended-precision chain on these states);
+* N: max|N - N_ref| <= 1e-10 max|N_ref| against both (rows of N span
+  e^{+-gamma}, so the elementwise relative error is ill-posed);
 * measurement: the contraction of the walker's own M against the oracle's
   direct sums, relative to the scale of its summands, (1/Nc) sum |M_ij| (the
   result can be far smaller after cancellation), within
@@ -36,11 +30,10 @@ import pytest
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-from oracle import ctaux, measure  # noqa: E402
+from oracle import ctaux, exact, measure  # noqa: E402
 from paper_1901_01047_amd import dcax  # noqa: E402
 from paper_1901_01047_amd.workloads import CONFIGS, params_kwargs  # noqa: E402
 from tests.ctaux_cases import model, oracle_trace  # noqa: E402
-from tests.test_submatrix_algebra import WindowModel  # noqa: E402
 
 
 def walker(name, **over):
@@ -105,17 +98,36 @@ REPLAY_CASES = [
 ]
 
 
-def algebra_gauge(m, init, rec, k_s):
-    """Ratios and final N of the same submatrix algebra evaluated in plain
-    NumPy FP64 (the CPU transcription pinned in test_submatrix_algebra): how
-    far a faithful FP64 evaluation of this algebra lands from the oracle's
-    single-vertex chain on these states."""
-    wm = WindowModel(m, *init)
-    props = [(int(r["kind"]), int(r["site"]), float(r["tau"]), int(r["aux_spin"]), int(r["id"]),
-              int(r["accepted"])) for r in rec]
-    for i in range(0, len(props), k_s):
-        wm.window([p for p in props[i:i + k_s] if not (p[0] == 1 and p[4] < 0)])
-    return np.array(wm.ratios), wm.canonical()
+def check_replay(m, init, rec, ratios_o, ow, ratios, w, tol=1e-10):
+    """Every ratio and both N against the FP64 oracle and the extended-precision
+    replay of the same records; returns the largest relative errors."""
+    noop = (rec["kind"] == 1) & (rec["id"] < 0)
+    good = ~noop
+    assert np.all(ratios[noop] == 0.0)
+    rx, ch = exact.replay(m, init, rec)
+    rg, ro, re_ = ratios[good], ratios_o[good], rx[good]
+    rel_x = np.abs(rg - re_) / np.abs(re_)
+    rel_o = np.abs(rg - ro) / np.abs(ro)
+    orc_x = np.abs(ro - re_) / np.abs(re_)
+    print(f"  ratios ({good.sum()}): max rel err vs extended precision {rel_x.max():.2e} (median "
+          f"{np.median(rel_x):.1e}), vs FP64 oracle {rel_o.max():.2e}; oracle vs extended {orc_x.max():.2e}",
+          flush=True)
+    assert rel_x.max() <= tol, rel_x.max()
+    assert rel_o.max() <= tol, rel_o.max()
+    ids_x, Xu, Xd = ch.canonical()
+    ids_o, Nu, Nd = ow.canonical()
+    assert np.array_equal(ids_x, ids_o)
+    errs = []
+    for sp, No, Nx in ((0, Nu, Xu), (1, Nd, Xd)):
+        ids, N = w.copy_N(sp)
+        assert np.array_equal(ids, ids_o)
+        ex = float(np.max(np.abs(N.astype(np.longdouble) - Nx)) / np.max(np.abs(Nx)))
+        eo = rel_norm(N, No)
+        print(f"  N[{sp}] normwise err vs extended precision {ex:.2e}, vs oracle {eo:.2e} (k={len(ids)})",
+              flush=True)
+        assert ex <= tol and eo <= tol
+        errs.append(ex)
+    return rel_x.max(), max(errs)
 
 
 @pytest.mark.parametrize("name,k_s,k_init,warm,n_rec", REPLAY_CASES)
@@ -127,43 +139,7 @@ def test_replay_parity(name, k_s, k_init, warm, n_rec):
     w = walker(name, submatrix_k=k_s)
     w.set_config(*init)
     ratios = w.replay(rec)
-    noop = (rec["kind"] == 1) & (rec["id"] < 0)
-    good = ~noop
-    ro = ratios_o[good]
-    err = np.abs(ratios[good] - ro)
-    rel = err / np.abs(ro)
-    scaled = err / np.maximum(np.abs(ro), 1.0)
-    big = np.abs(ro) >= 1e-2
-    print(f"  ratio rel err: median {np.median(rel):.2e} p99 {np.quantile(rel, 0.99):.2e} max {rel.max():.2e}; "
-          f"scaled max {scaled.max():.2e}; |R|>=1e-2 max {rel[big].max():.2e}", flush=True)
-    assert np.all(ratios[noop] == 0.0)
-    r_wm, (ids_wm, Nu_wm, Nd_wm) = algebra_gauge(m, init, rec, k_s)
-    err_wm = np.abs(r_wm - ro)
-    # decision scale: 1e-10 max(|R|, 1), except where the same algebra in
-    # plain FP64 is itself within a factor 10 of that far off (the state's
-    # conditioning, not the kernels)
-    far = scaled >= 1e-10
-    if far.any():
-        print(f"  {int(far.sum())} ratio(s) beyond 1e-10 on the decision scale; GPU / FP64-algebra error "
-              f"max {(err[far] / np.maximum(err_wm[far], 1e-300)).max():.2f}", flush=True)
-    assert np.all(~far | (err <= 10 * err_wm))
-    over = big & (rel >= 1e-10)
-    if over.any():
-        # beyond 1e-10 relative only where the same algebra in plain FP64 is
-        # itself within a factor 10 of that far off
-        f = err[over] / np.maximum(err_wm[over], 1e-300)
-        print(f"  {int(over.sum())} ratio(s) with |R|>=1e-2 beyond 1e-10 relative; GPU / FP64-algebra error "
-              f"max {f.max():.2f}; FP64-algebra rel err there max {(err_wm[over] / np.abs(ro[over])).max():.2e}",
-              flush=True)
-        assert np.all(err[over] <= 10 * err_wm[over])
-    ids_o, Nu, Nd = ow.canonical()
-    assert np.array_equal(ids_wm, ids_o)
-    for sp, No, Nwm in ((0, Nu, Nu_wm), (1, Nd, Nd_wm)):
-        ids, N = w.copy_N(sp)
-        assert np.array_equal(ids, ids_o)
-        e, e_wm = rel_norm(N, No), rel_norm(Nwm, No)
-        print(f"  N[{sp}] normwise err {e:.2e} (k={len(ids)}); FP64 algebra {e_wm:.2e}", flush=True)
-        assert e < max(1e-10, 10 * e_wm)
+    check_replay(m, init, rec, ratios_o, ow, ratios, w)
     st = w.stats()
     assert st["decision_mismatches"] == 0
     assert st["accepted_insertions"] == int(((rec["kind"] == 0) & (rec["accepted"] == 1)).sum())
@@ -183,11 +159,8 @@ def test_replay_from_empty_configuration():
     assert ((rec["kind"] == 1) & (rec["id"] < 0)).any()      # removals at k = 0 occur
     w = walker("2x2_U4_b5", submatrix_k=8)
     ratios = w.replay(rec)
-    good = ~((rec["kind"] == 1) & (rec["id"] < 0))
-    assert np.max(np.abs(ratios[good] - ratios_o[good]) / np.maximum(np.abs(ratios_o[good]), 1.0)) < 1e-10
-    ids_o, Nu, _ = ow.canonical()
-    ids, N = w.copy_N(0)
-    assert np.array_equal(ids, ids_o) and rel_norm(N, Nu) < 1e-10
+    empty = (np.zeros(0, np.int64), np.zeros(0), np.zeros(0, np.int64), np.zeros(0, np.int64))
+    check_replay(m, empty, rec, ratios_o, ow, ratios, w)
     w.close()
 
 

@@ -192,23 +192,27 @@ class WindowModel:
                 Next[k0 + j, :k0] = Rw[sp][q]
                 Next[k0 + j, k0 + j] = 1.0
             if S:
-                # A = (E_S - G_ext[:, S]) diag(-Delta): existing p: e_p - N_ext{.p};
-                # candidate c: rows < k0 Delta_c N g_{I,c}, inserted rows delta - Gt_{C_S, c}
+                # A = (E_S - G_ext[:, S]) diag(-Delta) on the rows < k0: existing
+                # p: e_p - N_{.p}; candidate c: Delta_c N g_{I,c}
                 A = np.zeros((kx, len(S)))
                 for j, q in enumerate(S):
                     if cand[q]:
                         Dq = self.ev(el_s[q], sp) - 1.0
                         A[:k0, j] = Dq * (self.N[sp] @ m.prop.g(self.r, self.t, el_r[q], el_t[q]))
-                        for jj, qq in enumerate(ins):
-                            A[k0 + jj, j] = -Gram[sp][qq, q]
-                        A[row_of[q], j] += 1.0
                     else:
                         p = el_slot[q]
                         e = np.zeros(kx)
                         e[p] = 1.0
                         A[:, j] = e - Next[:, p]
+                # the inserted rows of the result are rows of B (for x in S,
+                # Gt_{x,S} Gt_S^{-1} = e_x): A is zero there
+                A[k0:, :] = 0.0
                 rows = [row_of[q] for q in S]
-                Next = Next + A @ (Ginv[sp] @ Next[rows, :])
+                B = Ginv[sp] @ Next[rows, :]
+                Next = Next + A @ B
+                for j, q in enumerate(S):
+                    if cand[q]:
+                        Next[row_of[q], :] = B[j, :]
             keep = np.array([i for i in range(kx) if i not in rem], dtype=int)
             self.N[sp] = Next[np.ix_(keep, keep)]
         new_r = np.concatenate([self.r, el_r[ins]])
