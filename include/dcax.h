@@ -63,9 +63,11 @@ typedef enum {
 
 typedef struct dcax_walker_s* dcax_walker;
 
-/* Device memory source.  alloc(bytes, ctx) returns a device pointer aligned
- * to 256 bytes or NULL; free(ptr, ctx) releases it.  A NULL allocator makes
- * the library call hipMalloc/hipFree itself. */
+/* Device memory source: every byte of device memory the library uses comes
+ * from it (the library never calls hipMalloc itself).  alloc(bytes, ctx)
+ * returns a device pointer aligned to 256 bytes or NULL; free(ptr, ctx)
+ * releases it.  Required (dcax_walker_create answers DCAX_E_INVAL without
+ * one); a C caller may pass a thin wrapper of hipMalloc/hipFree. */
 typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);

@@ -236,7 +236,6 @@ struct dcax_walker_s {
   int W = 0;
   bool mixed = false;
   dcax_allocator alloc{};
-  bool have_alloc = false;
   hipStream_t stream = nullptr;
   std::vector<WalkerHost> wk;
   std::vector<void*> blocks;
@@ -274,14 +273,10 @@ struct dcax_walker_s {
   double fold_s = 0.0, accept_s = 0.0, window_s = 0.0;
   long long fold_launches = 0;
 
+  // all device memory comes from the caller's allocator
   void* dalloc(size_t bytes) {
     bytes = (bytes + 255) & ~size_t(255);
-    void* ptr = nullptr;
-    if (have_alloc) {
-      ptr = alloc.alloc(bytes, alloc.ctx);
-    } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
-      ptr = nullptr;
-    }
+    void* ptr = alloc.alloc(bytes, alloc.ctx);
     if (ptr) blocks.push_back(ptr);
     return ptr;
   }
@@ -299,10 +294,7 @@ struct dcax_walker_s {
     gstream = nullptr;
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     ev_pool.clear();
-    for (void* b : blocks) {
-      if (have_alloc) alloc.free(b, alloc.ctx);
-      else (void)hipFree(b);
-    }
+    for (void* b : blocks) alloc.free(b, alloc.ctx);
     blocks.clear();
   }
   hipEvent_t ev() {
@@ -1026,13 +1018,10 @@ dcax_status dcax_walker_create(const dcax_params* p, int32_t n_walkers, const dc
     if (st != DCAX_OK) return fail(st, "walker " + std::to_string(i) + ": " + g_err);
     if (p[i].precision != p[0].precision) return fail(DCAX_E_INVAL, "all walkers of a batch share one precision");
   }
-  if (a && (!a->alloc || !a->free)) return fail(DCAX_E_INVAL, "allocator needs alloc and free");
+  if (!a || !a->alloc || !a->free) return fail(DCAX_E_INVAL, "an allocator with alloc and free is required");
   dcax_walker w = new dcax_walker_s();
   w->W = n_walkers;
-  if (a) {
-    w->alloc = *a;
-    w->have_alloc = true;
-  }
+  w->alloc = *a;
   w->stream = (hipStream_t)stream;
   w->mixed = p[0].precision == DCAX_FP32_MIXED;
   w->wk.resize(n_walkers);

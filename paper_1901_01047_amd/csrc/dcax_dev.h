@@ -150,6 +150,10 @@ __device__ inline bool meas_skip(const Ctl* c, int gated) {
 
 __device__ inline int s01(int s) { return s > 0 ? 0 : 1; }
 
+// Maximum that propagates NaN from either operand (fmax drops a NaN operand,
+// so a reduction built on it would report a NaN matrix as drift 0).
+__host__ __device__ inline double max_nan(double a, double b) { return (a > b || a != a) ? a : b; }
+
 // Linear interpolation of the table at dtau in [0, beta]: l = floor(dtau/h),
 // f = dtau/h - l, (1 - f) T[l] + f T[l+1], l clamped to n_tau - 2; dtau = 0
 // gives the 0+ value.

@@ -395,8 +395,8 @@ __global__ void __launch_bounds__(WG) k_refresh_store(const View<T>* __restrict_
   __syncthreads();
   for (int o = WG / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) {
-      a_s[threadIdx.x] = fmax(a_s[threadIdx.x], a_s[threadIdx.x + o]);
-      b_s[threadIdx.x] = fmax(b_s[threadIdx.x], b_s[threadIdx.x + o]);
+      a_s[threadIdx.x] = max_nan(a_s[threadIdx.x], a_s[threadIdx.x + o]);
+      b_s[threadIdx.x] = max_nan(b_s[threadIdx.x], b_s[threadIdx.x + o]);
     }
     __syncthreads();
   }
@@ -407,7 +407,8 @@ __global__ void __launch_bounds__(WG) k_refresh_store(const View<T>* __restrict_
   }
 }
 
-// drift = max |N_old - N_new| / max |N_new| over both spins, into ctl->drift.
+// drift = max |N_old - N_new| / max |N_new| over both spins, into ctl->drift
+// (NaN if either maximum met a NaN).
 template <typename T>
 __global__ void __launch_bounds__(WG) k_drift(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
@@ -415,8 +416,8 @@ __global__ void __launch_bounds__(WG) k_drift(const View<T>* __restrict__ vs) {
   const size_t n = (size_t)2 * k * ((k + WG - 1) / WG);
   double a = 0.0, b = 0.0;
   for (size_t x = threadIdx.x; x < n; x += WG) {
-    a = fmax(a, w.blkmax[2 * x]);
-    b = fmax(b, w.blkmax[2 * x + 1]);
+    a = max_nan(a, w.blkmax[2 * x]);
+    b = max_nan(b, w.blkmax[2 * x + 1]);
   }
   __shared__ double a_s[WG], b_s[WG];
   a_s[threadIdx.x] = a;
@@ -424,12 +425,18 @@ __global__ void __launch_bounds__(WG) k_drift(const View<T>* __restrict__ vs) {
   __syncthreads();
   for (int o = WG / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) {
-      a_s[threadIdx.x] = fmax(a_s[threadIdx.x], a_s[threadIdx.x + o]);
-      b_s[threadIdx.x] = fmax(b_s[threadIdx.x], b_s[threadIdx.x + o]);
+      a_s[threadIdx.x] = max_nan(a_s[threadIdx.x], a_s[threadIdx.x + o]);
+      b_s[threadIdx.x] = max_nan(b_s[threadIdx.x], b_s[threadIdx.x + o]);
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) w.ctl->drift = (b_s[0] > 0.0) ? a_s[0] / b_s[0] : 0.0;
+  if (threadIdx.x == 0) {
+    // a non-finite N before the refresh (the chain's decisions since the
+    // last refresh are void) is latched rather than silently replaced
+    const double d = (b_s[0] > 0.0) ? a_s[0] / b_s[0] : (a_s[0] != a_s[0] ? a_s[0] : 0.0);
+    w.ctl->drift = d;
+    if (!isfinite(d)) latch(w.ctl, ST_NUMERIC);
+  }
 }
 
 #define DCAX_INSTANTIATE_REFRESH(T)                                   \

@@ -96,3 +96,52 @@ def test_null_walker_calls(lib):
     k = ctypes.c_int32()
     assert lib.dcax_get_order(None, 0, ctypes.byref(k)) == -1
     assert lib.dcax_sweep(None, 1, None, 0, None) == -1
+
+
+def test_drift_reduction_propagates_nan(tmp_path):
+    """The refresh's drift reductions use max_nan from the library's device
+    header: a NaN entry on either side must survive a max-reduction (IEEE fmax
+    would drop it and report the NaN matrix as drift 0)."""
+    import re
+    import shutil
+    import subprocess
+    if shutil.which("g++") is None:
+        pytest.skip("needs g++")
+    src = open(os.path.join(ROOT, "paper_1901_01047_amd", "csrc", "dcax_dev.h")).read()
+    fn = re.search(r"__host__ __device__ inline double max_nan\(double a, double b\) \{[^}]*\}", src).group(0)
+    prog = tmp_path / "m.cpp"
+    prog.write_text("#include <cmath>\n#include <cstdio>\n#define __host__\n#define __device__\n" + fn + """
+int main() {
+  const double nan = std::nan("");
+  double xs[6] = {0.5, 2.0, nan, 1.0, 0.0, 3.0};
+  int bad = 0;
+  // a left-to-right reduction and a pairwise tree, as in the kernels
+  double a = 0.0;
+  for (double x : xs) a = max_nan(a, x);
+  bad += !std::isnan(a);
+  double t[8] = {0.5, 2.0, 1.0, nan, 0.0, 3.0, 0.25, 0.125};
+  for (int o = 4; o > 0; o >>= 1)
+    for (int i = 0; i < o; ++i) t[i] = max_nan(t[i], t[i + o]);
+  bad += !std::isnan(t[0]);
+  bad += max_nan(1.0, 2.0) != 2.0;
+  bad += max_nan(2.0, 1.0) != 2.0;
+  bad += !std::isnan(max_nan(nan, 1.0)) + !std::isnan(max_nan(1.0, nan));
+  std::printf("%d\\n", bad);
+  return bad;
+}
+""")
+    exe = tmp_path / "m"
+    subprocess.run(["g++", "-O2", str(prog), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout
+
+
+def test_create_requires_an_allocator():
+    """Every byte of device memory comes through the caller's allocator: a
+    NULL allocator is an argument error, answered before any HIP call."""
+    lib = dcax.load()
+    p = dcax.make_params()
+    h = ctypes.c_void_p()
+    st = lib.dcax_walker_create(ctypes.byref(p), 1, None, None, ctypes.byref(h))
+    assert st == -1 and h.value is None
+    assert b"allocator" in lib.dcax_last_error()
