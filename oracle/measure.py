@@ -23,16 +23,23 @@ def M_matrix(model, walker, spin):
     return (ev - 1.0)[:, None] * walker.N[spin]
 
 
-def M_K_iw(model, r, t, M, n_freq):
-    """M(K, i w_n) for one spin, shape (Nc, n_freq) complex, by direct sums."""
-    w = matsubara(n_freq, model.beta)
-    out = np.zeros((model.Nc, n_freq), dtype=complex)
+def M_K_iw(model, r, t, M, n_freq, freqs=None, Ks=None):
+    """M(K, i w_n) for one spin, shape (Nc, n_freq) complex, by direct sums.
+
+    freqs / Ks (optional index arrays) restrict the sums to those Matsubara
+    indices n and momentum indices: the result is then (len(Ks), len(freqs)),
+    each entry the same direct sum (sampled outputs at large orders)."""
+    n_idx = np.arange(n_freq) if freqs is None else np.asarray(freqs, np.int64)
+    K_idx = np.arange(model.Nc) if Ks is None else np.asarray(Ks, np.int64)
+    w = (2 * n_idx + 1) * np.pi / model.beta
+    out = np.zeros((len(K_idx), len(n_idx)), dtype=complex)
     if len(r) == 0:
         return out
     pos = model.sites[np.asarray(r)].astype(np.float64)        # (k, 2)
-    for iK, K in enumerate(model.K):
-        phi = np.exp(1j * (np.outer(t, w) - (pos @ K)[:, None]))   # (k, n_freq)
-        out[iK] = np.sum(phi * (M @ phi.conj()), axis=0) / model.Nc
+    for o, iK in enumerate(K_idx):
+        K = model.K[iK]
+        phi = np.exp(1j * (np.outer(t, w) - (pos @ K)[:, None]))   # (k, n)
+        out[o] = np.sum(phi * (M @ phi.conj()), axis=0) / model.Nc
     return out
 
 

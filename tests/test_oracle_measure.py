@@ -101,3 +101,21 @@ def test_expansion_parameter_independence(cluster_2x2):
     assert np.mean(z < 3) > 0.97 and z.max() < 5
     # <k> = K_exp - beta <H_int>: the orders shift by Delta K_exp = 1
     assert abs((orders2.mean() - orders1.mean()) - 1.0) < 1.0
+
+
+def test_sampled_direct_sums_equal_full_sums():
+    """The sampled form of the direct sums (chosen frequencies or momenta)
+    returns exactly the corresponding entries of the full evaluation."""
+    m = ctaux.Model(a1=(2, 0), a2=(0, 2), U=4.0, beta=5.0, n_tau=200)
+    rng = np.random.default_rng(3)
+    k = 17
+    r = rng.integers(0, m.Nc, k)
+    t = rng.random(k) * m.beta
+    M = rng.standard_normal((k, k))
+    from oracle import measure
+    full = measure.M_K_iw(m, r, t, M, 40)
+    freqs, Ks = [0, 7, 39], [1, 3]
+    assert np.allclose(measure.M_K_iw(m, r, t, M, 40, freqs=freqs), full[:, freqs], rtol=0, atol=1e-13)
+    assert np.allclose(measure.M_K_iw(m, r, t, M, 40, Ks=Ks), full[Ks, :], rtol=0, atol=1e-13)
+    assert np.allclose(measure.M_K_iw(m, r, t, M, 40, freqs=freqs, Ks=Ks), full[np.ix_(Ks, freqs)], rtol=0,
+                       atol=1e-13)
