@@ -1,12 +1,15 @@
-"""Benchmark: accepted vertex updates per second of the CT-AUX walker.
+"""Benchmark: accepted vertex updates per second of the CT-AUX walkers.
 
-A step is one pass of the whole hot path: one Markov-chain sweep (submatrix
-windows: gathers, candidate GEMM, FP64 accept loop, rank-m fold, compaction),
-one measurement of M(K, i w_n) accumulated on the GPU, and, every
-`refresh_every` sweeps, the FP64 refresh of N.  The workload is the 4x4
-Hubbard cluster (U = 4, beta = 10, n ~ 0.95, one walker, k_s = 32, 256
-Matsubara frequencies), synthetic inputs.  The same workload runs in FP64 and
-in the FP32-mixed mode; `value` is the FP64 figure.
+A step is one pass of the whole hot path for every walker: one Markov-chain
+sweep (submatrix windows: gathers, candidate GEMMs, FP64 accept loop, rank-m
+fold, compaction), one measurement of M(K, i w_n) accumulated on the GPU,
+and, every `refresh_every` sweeps, the FP64 refresh of N.  The default
+workload is the large one: the 8x8 Hubbard cluster (U = 7, beta = 30,
+n ~ 0.9, expansion order ~ 6000), 32 walkers sharing the GPU, FP32-mixed
+(N and its GEMMs in FP32, ratios and refresh in FP64), 512 Matsubara
+frequencies measured every sweep; the same workload in FP64 runs beside it.
+`value` is the FP32-mixed figure.  Synthetic inputs: seeded starting
+configurations (workloads.initial_config), inputs resident in HBM.
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
 """
@@ -20,59 +23,67 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBs": 8000.0, "fp64_mfma_TFs": 78.6, "fp32_mfma_TFs": 157.3}
-WORKLOAD = "4x4_U4_b10"
-# a pseudo-random 1/TIMING_EVERY of the windows carries HIP events (each
-# event idles the queue for a few microseconds)
+WORKLOAD = "8x8_U7_b30"
+WALKERS = 32
+# a pseudo-random 1/TIMING_EVERY of the windows of a small workload carries
+# HIP events (each event idles the queue for a few microseconds); windows of
+# orders above TIME_ALL_ORDER take milliseconds and are all timed
 TIMING_EVERY = 8
+TIME_ALL_ORDER = 1024
 
 
-def initial_config(rng, Nc, beta, k):
-    """Seeded random vertices: sites, times and auxiliary spins uniform."""
-    import numpy as np
-    site = rng.integers(0, Nc, size=k).astype(np.int32)
-    tau = rng.random(k) * beta
-    s = np.where(rng.random(k) < 0.5, 1, -1).astype(np.int32)
-    return site, tau, s
+# kernel -> (stats prefix for flops/bytes/seconds, source section of
+# csrc/dcax_window.hip from its header comment to the next one)
+KERNELS = {
+    "k_cand_x": ("cand", "// ------------------------------------------------------- candidate rows\n",
+                 "// -------------------------------------------------------------- Gram"),
+    "k_ygemm": ("y", "// --------------------------------------------------------- Y = N g_{I,c}\n",
+                "// ------------------------------------------------------------ fold prep"),
+    "k_fold": ("fold", "// ---------------------------------------------------------------- fold\n",
+               "// ----------------------------------------------------------- compaction"),
+}
 
 
-def fold_traffic(workload, precision):
-    """HBM bytes per k_fold launch from the committed counter summary, while
-    the fold kernel's source is the one the counters were taken on."""
+def kernel_source_hash(kernel):
     import hashlib
-    if workload != WORKLOAD or precision != "fp64":
-        return None
+    src = open(os.path.join(ROOT, "paper_1901_01047_amd", "csrc", "dcax_window.hip")).read()
+    _, a, b = KERNELS[kernel]
+    return hashlib.sha256(src[src.index(a):src.index(b)].encode()).hexdigest()
+
+
+def kernel_traffic(kernel, workload, walkers, precision):
+    """HBM bytes per launch of `kernel` from a committed counter summary
+    (profiles/traffic_<kernel>_<workload>_<walkers>w_<precision>.md), while
+    the kernel's source is the one the counters were taken on; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{walkers}w_{precision}.md")
     try:
-        src = open(os.path.join(ROOT, "paper_1901_01047_amd", "csrc", "dcax_window.hip")).read()
-        a = src.index("// ---------------------------------------------------------------- fold\n")
-        b = src.index("// ----------------------------------------------------------- compaction")
-        h = hashlib.sha256(src[a:b].encode()).hexdigest()
         vals = {}
-        for line in open(os.path.join(ROOT, "profiles", "traffic_k_fold_4x4_U4_b10.md")):
-            if " = " in line and line.split(" = ")[0].strip() in ("traffic_bytes_per_launch", "fold_source_sha256"):
+        for line in open(path):
+            if " = " in line:
                 k, v = line.split(" = ", 1)
                 vals[k.strip()] = v.strip()
-        if vals.get("fold_source_sha256") != h:
+        if vals.get("kernel_source_sha256") != kernel_source_hash(kernel):
             return None
         return float(vals["traffic_bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         return None
 
 
-def roofline(stats0, stats1, precision, traffic=None):
-    """Fold-kernel roofline over the timed region.  The algorithmic flops and
-    bytes cover every fold launch; the durations come from the sampled
-    launches (HIP events on a pseudo-random share of the windows), so the
+def roofline(stats0, stats1, precision, kernel, traffic=None):
+    """Roofline of one window kernel over the timed region.  Algorithmic
+    flops and bytes cover every launch; durations come from the timed
+    launches (HIP events attached to the kernel's own dispatch), so the
     per-launch averages of both are divided into each other."""
+    pre = KERNELS[kernel][0]
     d = lambda k: stats1[k] - stats0[k]
-    timed = d("fold_launches")
+    timed = d("fold_launches")           # timed windows (one launch of each kernel)
     total = d("windows_enqueued")
-    secs_timed = d("fold_seconds")
+    secs_timed = d(f"{pre}_seconds")
     if secs_timed <= 0 or timed <= 0 or total <= 0:
         return None
-    launches = total
-    secs = secs_timed / timed * total        # estimated fold time over every launch
-    flops = d("fold_flops")
-    nbytes = d("fold_bytes")
+    secs = secs_timed / timed * total     # estimated time over every launch
+    flops = d(f"{pre}_flops")
+    nbytes = d(f"{pre}_bytes")
     peak_tf = PEAK["fp64_mfma_TFs"] if precision == "fp64" else PEAK["fp32_mfma_TFs"]
     ai = flops / max(nbytes, 1.0)
     ridge = peak_tf * 1e12 / (PEAK["hbm_GBs"] * 1e9)
@@ -85,21 +96,23 @@ def roofline(stats0, stats1, precision, traffic=None):
         out = {"bound": "mfma", "achieved": achieved, "peak": peak_tf, "unit": "TFLOP/s",
                "frac": achieved / peak_tf}
     attainable = min(peak_tf, PEAK["hbm_GBs"] * 1e9 * ai / 1e12)
-    out.update({"traffic": traffic, "kernel": "k_fold", "launches": launches, "timed_launches": timed,
-                "avg_launch_us": secs / launches * 1e6, "flops_per_launch": flops / launches,
-                "bytes_per_launch": nbytes / launches, "arith_intensity": ai, "tflops": flops / secs / 1e12,
+    out.update({"traffic": traffic, "kernel": kernel, "launches": total, "timed_launches": timed,
+                "avg_launch_us": secs / total * 1e6, "flops_per_launch": flops / total,
+                "bytes_per_launch": nbytes / total, "arith_intensity": ai, "tflops": flops / secs / 1e12,
                 "frac_of_mfma_peak": flops / secs / 1e12 / peak_tf,
-                "attainable_tflops": attainable, "frac_of_attainable": flops / secs / 1e12 / attainable})
+                "attainable_tflops": attainable, "frac_of_attainable": flops / secs / 1e12 / attainable,
+                "seconds_in_timed_region": secs})
     return out
 
 
 def kernel_us(s0, s1):
-    """Average fold, accept-loop and whole-window durations of the timed windows."""
+    """Average durations of the timed windows' kernels."""
     n = s1["fold_launches"] - s0["fold_launches"]
     if n <= 0:
         return None
     return {k: (s1[f] - s0[f]) / n * 1e6 for k, f in
-            (("fold", "fold_seconds"), ("accept_loop", "accept_seconds"), ("window", "window_seconds"))} | \
+            (("cand_x", "cand_seconds"), ("ygemm", "y_seconds"), ("fold", "fold_seconds"),
+             ("accept_loop", "accept_seconds"), ("window", "window_seconds"))} | \
         {"timed_windows": n, "windows": s1["windows_enqueued"] - s0["windows_enqueued"]}
 
 
@@ -118,21 +131,21 @@ def fold_ranks(s0, s1):
 
 
 def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None, walkers=1, nfft_hw=0,
-            autotune=0):
+            autotune=0, refresh_every=32):
     import numpy as np
     import torch
     from paper_1901_01047_amd import dcax
-    from paper_1901_01047_amd.workloads import CONFIGS, params_kwargs
+    from paper_1901_01047_amd.workloads import CONFIGS, initial_config, params_kwargs
     workload = workload or WORKLOAD
     cfg = CONFIGS[workload]
     prec = dcax.DCAX_FP64 if precision == "fp64" else dcax.DCAX_FP32_MIXED
     plist = [dcax.make_params(**params_kwargs(workload, seed=cfg["seed"] + seed_offset + i, warmup_sweeps=warmup),
-                              precision=prec, refresh_every=32) for i in range(walkers)]
+                              precision=prec, refresh_every=refresh_every) for i in range(walkers)]
     w = dcax.Walker(plist if walkers > 1 else plist[0])
     w.set_graphs(graphs)
     for i in range(walkers):
-        rng = np.random.default_rng(cfg["seed"] + 100 + seed_offset + i)
-        w.set_config(*initial_config(rng, w.Ncs[i], cfg["beta"], cfg["k_init"]), walker=i)
+        w.set_config(*initial_config(w.Ncs[i], cfg["beta"], cfg["k_init"], cfg["seed"] + 100 + seed_offset + i),
+                     walker=i)
     acc, aux = w.new_accumulator()
     if nfft_hw:
         # the measurement is the delayed-NFFT gridding (same chain)
@@ -149,7 +162,8 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
     if autotune:
         chosen_ks, _ = w.autotune(sweeps_per_trial=autotune)
     sweep_measure(warmup)
-    w.set_timing(TIMING_EVERY)
+    every = 1 if cfg["k_init"] > TIME_ALL_ORDER else TIMING_EVERY
+    w.set_timing(every)
     torch.cuda.synchronize()
     s0 = w.stats()
     t0 = time.perf_counter()
@@ -162,30 +176,58 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
         (s1["accepted_removals"] - s0["accepted_removals"])
     props = s1["proposals"] - s0["proposals"]
     windows = s1["windows"] - s0["windows"]
+    kern = {k: roofline(s0, s1, precision, k, kernel_traffic(k, workload, walkers, precision)) for k in KERNELS}
+    timed_k = {k: v for k, v in kern.items() if v}
+    dominant = max(timed_k, key=lambda k: timed_k[k]["seconds_in_timed_region"]) if timed_k else "k_fold"
+    orders = w.orders()
     res = {
         "value": acc_upd / dt, "seconds": dt, "ms_per_step": dt / steps * 1e3,
         "proposals_per_s": props / dt, "acceptance": acc_upd / max(props, 1),
-        "mean_order": sum(w.orders()) / walkers, "windows": windows, "walkers": walkers,
+        "mean_order": sum(orders) / walkers, "order_min_max": [min(orders), max(orders)],
+        "windows": windows, "walkers": walkers,
         "mean_fold_rank": (s1["flips_folded"] - s0["flips_folded"]) / max(windows, 1),
         "fold_rank_distribution": fold_ranks(s0, s1),
-        "roofline": roofline(s0, s1, precision, fold_traffic(workload, precision)),
-        "kernel_us_per_window": kernel_us(s0, s1),
-        "sign": s1["sign"], "refresh_max_drift": s1["max_drift"],
+        "roofline": kern[dominant], "dominant_kernel": dominant,
+        "kernels": {k: v for k, v in kern.items() if k != dominant},
+        "kernel_us_per_window": kernel_us(s0, s1), "timed_share_of_windows": 1.0 / every,
+        "sign": s1["sign"], "refresh_every": refresh_every,
+        "refreshes_in_timed_region": steps // refresh_every if refresh_every else 0,
+        "refresh_max_drift": s1["max_drift"],
         "aborted_windows": s1["aborted_windows"] - s0["aborted_windows"],
         "submatrix_k": chosen_ks if chosen_ks else plist[0].submatrix_k,
     }
     if graphs:
-        # kernels inside a replayed graph cannot be timed one by one: the fold
-        # figures come from eager sweeps right after the timed region
+        # kernels inside a replayed graph cannot be timed one by one: the
+        # kernel figures come from eager sweeps right after the timed region
         w.set_graphs(False)
         r0 = w.stats()
         sweep_measure(min(steps, 30))
         torch.cuda.synchronize()
-        res["roofline"] = roofline(r0, w.stats(), precision, fold_traffic(workload, precision))
-        if res["roofline"]:
-            res["roofline"]["pass"] = "eager sweeps after the timed region"
+        r1 = w.stats()
+        for k in KERNELS:
+            x = roofline(r0, r1, precision, k, kernel_traffic(k, workload, walkers, precision))
+            if x:
+                x["pass"] = "eager sweeps after the timed region"
+            if k == dominant:
+                res["roofline"] = x
+            else:
+                res["kernels"][k] = x
+    if precision != "fp64" and not nfft_hw:
+        # the N error the mixed chain carries at the end of the run, and the
+        # error it puts into one measurement of M(K, i w_n): measure, refresh
+        # in FP64, measure again
+        a1, x1 = w.new_accumulator()
+        w.measure(a1, x1)
+        drift = w.refresh()
+        a2, x2 = w.new_accumulator()
+        w.measure(a2, x2)
+        torch.cuda.synchronize()
+        res["end_of_run_N_drift"] = drift
+        res["end_of_run_M_Kw_err_rel_max"] = float((a1 - a2).abs().max() / a2.abs().max())
     cfg_out = w.get_config()
     w.close()
+    del acc, aux
+    torch.cuda.empty_cache()
     return res, cfg_out
 
 
@@ -221,7 +263,8 @@ def run_batch(precision, steps, warmup, n_walkers=512):
            "order_min_mean_max": [min(orders), sum(orders) / len(orders), max(orders)],
            "mean_fold_rank": (s1["flips_folded"] - s0["flips_folded"]) / max(s1["windows"] - s0["windows"], 1),
            "fold_rank_distribution": fold_ranks(s0, s1),
-           "warmup_seconds": t_warm, "roofline": roofline(s0, s1, precision),
+           "warmup_seconds": t_warm, "roofline": roofline(s0, s1, precision, "k_fold"),
+           "kernels": {k: roofline(s0, s1, precision, k) for k in ("k_cand_x", "k_ygemm")},
            "kernel_us_per_window": kernel_us(s0, s1)}
     w.close()
     return res
@@ -235,12 +278,11 @@ def run_nfft(workload, precision="fp64", half_width=8, reps=5):
     import numpy as np
     import torch
     from paper_1901_01047_amd import dcax
-    from paper_1901_01047_amd.workloads import CONFIGS, params_kwargs
+    from paper_1901_01047_amd.workloads import CONFIGS, initial_config, params_kwargs
     cfg = CONFIGS[workload]
     prec = dcax.DCAX_FP64 if precision == "fp64" else dcax.DCAX_FP32_MIXED
     w = dcax.Walker(dcax.make_params(**params_kwargs(workload, warmup_sweeps=2), precision=prec, refresh_every=0))
-    rng = np.random.default_rng(cfg["seed"] + 100)
-    w.set_config(*initial_config(rng, w.Ncs[0], cfg["beta"], cfg["k_init"]))
+    w.set_config(*initial_config(w.Ncs[0], cfg["beta"], cfg["k_init"], cfg["seed"] + 100))
     w.sweep(2)
     acc, aux = w.new_accumulator()
     grid = w.new_nfft_grid()
@@ -267,24 +309,27 @@ def run_nfft(workload, precision="fp64", half_width=8, reps=5):
 
 
 def cpu_baseline(seconds=15.0, workload=None):
-    """The oracle, as it stands, timed on the host: the same workload from a
-    seeded random configuration of the workload's typical order."""
-    import numpy as np
+    """The oracle, as it stands, timed on the host: one chain of the same
+    workload from the same kind of seeded starting configuration, first with
+    the BLAS threads numpy has, then with one thread."""
     from oracle import ctaux
-    from paper_1901_01047_amd.workloads import CONFIGS
+    from paper_1901_01047_amd.workloads import CONFIGS, initial_config
     workload = workload or WORKLOAD
     c = CONFIGS[workload]
     cl = c["cluster"]
     m = ctaux.Model(a1=(cl[0], cl[1]), a2=(cl[2], cl[3]), t=c["t"], tp=c["tp"], U=c["U"], beta=c["beta"],
                     mu=c["mu"], K_exp=c["K_exp"], n_tau=c["n_tau"])
     w = ctaux.Walker(m, seed=c["seed"] + 7, k_s=c["submatrix_k"])
-    rng = np.random.default_rng(c["seed"] + 200)
-    w.set_config(*initial_config(rng, m.Nc, c["beta"], c["k_init"]))
+    t_init = time.perf_counter()
+    w.set_config(*initial_config(m.Nc, c["beta"], c["k_init"], c["seed"] + 100))
+    t_init = time.perf_counter() - t_init
+    host_cores = len(os.sched_getaffinity(0))
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
-        cores = 1
+        blas_threads = None
+
     def run_for(sec):
         a0 = w.n_acc_ins + w.n_acc_rem
         t0 = time.perf_counter()
@@ -296,9 +341,10 @@ def cpu_baseline(seconds=15.0, workload=None):
         return (w.n_acc_ins + w.n_acc_rem - a0) / dt, n, dt
 
     v, n, dt = run_for(seconds)
-    out = {"value": v, "unit": "updates/s", "cores": int(cores), "kind": "oracle",
-           "sample": f"{n} single-vertex proposals of the {workload} chain from a seeded "
-                     f"random configuration of order {c['k_init']}, {dt:.1f} s wall"}
+    out = {"value": v, "unit": "updates/s", "cores": blas_threads or 1, "kind": "oracle",
+           "host_cores": host_cores, "blas_threads": blas_threads,
+           "sample": f"{n} single-vertex proposals of one {workload} chain (order {c['k_init']}, seeded "
+                     f"starting configuration, inverted in {t_init:.1f} s, not timed), {dt:.1f} s wall"}
     try:
         # the same chain continued with one BLAS thread
         from threadpoolctl import threadpool_limits
@@ -314,16 +360,21 @@ def cpu_baseline(seconds=15.0, workload=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fp64-only", action="store_true")
+    ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed",
+                    help="precision of the headline leg (`value`); the other runs beside it")
+    ap.add_argument("--headline-only", action="store_true", help="skip the other precision's leg")
+    ap.add_argument("--refresh-every", type=int, default=10,
+                    help="sweeps between FP64 refreshes of N (at most --steps, so the timed region holds one)")
     ap.add_argument("--graphs", choices=("on", "off"), default="off",
                     help="replay each sweep as a captured hipGraph")
     ap.add_argument("--workload", default=WORKLOAD,
-                    help="single-walker (or --walkers) workload from paper_1901_01047_amd.workloads.CONFIGS")
-    ap.add_argument("--walkers", type=int, default=1)
+                    help="workload from paper_1901_01047_amd.workloads.CONFIGS")
+    ap.add_argument("--walkers", type=int, default=None,
+                    help=f"walkers sharing the GPU (default {WALKERS} for {WORKLOAD}, else 1)")
     ap.add_argument("--autotune", type=int, default=0,
                     help="sweeps per candidate k_s for the autotuner during the warm-up (0: the workload's k_s)")
     ap.add_argument("--nfft", action="store_true",
@@ -358,33 +409,42 @@ def main():
     from paper_1901_01047_amd.workloads import CONFIGS
     wl = args.workload
     c = CONFIGS[wl]
+    walkers = args.walkers if args.walkers else (WALKERS if wl == WORKLOAD else 1)
     graphs = args.graphs == "on"
     at = args.autotune
-    r64, cfg_v = run_gpu("fp64", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers,
-                         autotune=at)
-    ks_text = f"k_s={r64['submatrix_k']} (autotuned)" if at else f"k_s={c['submatrix_k']}"
+    re = max(1, min(args.refresh_every, args.steps))
+    legs = [args.precision] + ([] if args.headline_only else [p for p in ("mixed", "fp64") if p != args.precision])
+    res = {}
+    for prec in legs:
+        res[prec], _ = run_gpu(prec, args.steps, args.warmup, graphs=graphs, workload=wl, walkers=walkers,
+                               autotune=at, refresh_every=re)
+    head = res[args.precision]
+    ks_text = f"k_s={head['submatrix_k']} (autotuned)" if at else f"k_s={c['submatrix_k']}"
+    mode = "FP32-mixed (N and its GEMMs FP32 on MFMA; ratios, Gamma and refresh FP64)" \
+        if args.precision == "mixed" else "FP64"
     out = {
-        "metric": "accepted vertex updates/s (CT-AUX walker, FP64) + N-update fold TFLOP/s (% roofline)",
-        "value": r64["value"], "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": r64["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "metric": "accepted vertex updates/s (CT-AUX walkers) + N-update TFLOP/s (% roofline), FP64 vs FP32-mixed",
+        "value": head["value"], "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": f"{wl}: {c['cluster'][0]}x{c['cluster'][3]} periodic Hubbard cluster, t=1, "
                                f"t'={c['tp']}, U={c['U']}, beta={c['beta']}, mu={c['mu']} (n~{c['n_target']}), "
-                               f"K=1, {args.walkers} walker(s), {ks_text}, "
-                               f"{c['n_freq']} Matsubara freqs, refresh every 32 sweeps",
-                   "step": "1 sweep + 1 measurement of M(K,iw_n)",
+                               f"K=1, expansion order ~{c['k_init']}, {walkers} walker(s), {mode}, {ks_text}, "
+                               f"{c['n_freq']} Matsubara freqs measured every sweep, FP64 refresh every {re} sweeps",
+                   "step": "1 sweep + 1 measurement of M(K,iw_n) per walker (+ the refresh every "
+                           f"{re} sweeps)",
                    "launch": "hipGraph per sweep" if graphs else "eager launches"},
-        "roofline": r64["roofline"],
-        "fp64": {k: v for k, v in r64.items() if k != "roofline"},
+        "roofline": head["roofline"],
     }
-    if not args.fp64_only:
-        r32, _ = run_gpu("mixed", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers,
-                         autotune=at)
-        out["fp32_mixed"] = r32
+    for prec in legs:
+        key = "fp32_mixed" if prec == "mixed" else "fp64"
+        out[key] = {k: v for k, v in res[prec].items() if k != "roofline" or prec != args.precision}
+    if "mixed" in res and "fp64" in res:
+        out["mixed_over_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
     if args.nfft:
         out["measurement"] = run_nfft(wl)
-        rn, _ = run_gpu("fp64", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=args.walkers, nfft_hw=8,
-                        autotune=at)
+        rn, _ = run_gpu("fp64", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=walkers, nfft_hw=8,
+                        autotune=at, refresh_every=re)
         out["fp64_nfft_measurement"] = {k: v for k, v in rn.items() if k != "roofline"}
     if args.batch:
         out["batch"] = {"fp64": run_batch("fp64", args.steps, args.warmup, args.batch),

@@ -143,6 +143,12 @@ typedef struct {
   int64_t windows_enqueued; /* windows launched while timing was on, timed or not
                                (fold_launches / windows_enqueued is the sampled share) */
   int64_t fold_rank_hist[17]; /* windows by fold rank m: [0] m = 0, [b] 4b-3 <= m <= 4b */
+  double cand_flops;        /* algorithmic flops of the candidate-row products X_C = W_C N, 2 k^2 n_C per spin */
+  double cand_bytes;        /* their algorithmic bytes: N read once, W_C read and X_C written */
+  double cand_seconds;      /* candidate-row kernel time summed over the timed windows */
+  double y_flops;           /* algorithmic flops of the Y columns N g_{I,c} of inserted spins, 2 k^2 m_i per spin */
+  double y_bytes;           /* their algorithmic bytes: N read once, g columns read and Y written */
+  double y_seconds;         /* Y-column kernel time summed over the timed windows */
 } dcax_stats;
 
 /* Create a batch of n_walkers independent walkers (Markov chains; Sec. 3.1,

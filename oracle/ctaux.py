@@ -40,9 +40,12 @@ class Model:
     """Hubbard model on a periodic cluster, finite-size mode."""
 
     def __init__(self, a1=(2, 0), a2=(0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0,
-                 K_exp=1.0, n_tau=1000, use_table=True):
+                 K_exp=1.0, n_tau=1000, use_table=True, h=0.0):
+        """h: a Zeeman field, -h sum_i (n_iup - n_idown) in H0, so that the
+        spins see xi_sigma = eps_K - mu - sigma h (sigma = +1 up, -1 down)
+        and the walker one bare propagator per spin."""
         self.a1, self.a2 = tuple(a1), tuple(a2)
-        self.t, self.tp, self.U, self.beta, self.mu = t, tp, U, beta, mu
+        self.t, self.tp, self.U, self.beta, self.mu, self.h = t, tp, U, beta, mu, h
         self.K_exp = K_exp
         self.n_tau = n_tau
         self.sites = geometry.cluster_sites(self.a1, self.a2)
@@ -50,19 +53,26 @@ class Model:
         self.Nc = len(self.sites)
         self.diff = geometry.diff_table(self.a1, self.a2)
         self.eps = geometry.dispersion(self.K, t, tp)
-        self.xi = self.eps - mu
+        self.xis = [self.eps - mu - h, self.eps - mu + h]
+        self.xi = self.xis[0]
         self.gamma = math.acosh(1.0 + U * beta * self.Nc / (2.0 * K_exp))
-        self.table = g0mod.g0_table(self.sites, self.K, self.xi, beta, n_tau)
-        analytic = (lambda d, tau: self._g0_exact(d, tau))
-        self.prop = g0mod.Propagator(self.diff, beta,
-                                     table=self.table if use_table else None,
-                                     analytic=analytic)
+        self.tables, self.props = [], []
+        for sp in range(2 if h != 0.0 else 1):
+            tab = g0mod.g0_table(self.sites, self.K, self.xis[sp], beta, n_tau)
+            analytic = (lambda d, tau, sp=sp: self._g0_exact(d, tau, sp))
+            self.tables.append(tab)
+            self.props.append(g0mod.Propagator(self.diff, beta, table=tab if use_table else None,
+                                               analytic=analytic))
+        if h == 0.0:
+            self.tables.append(self.tables[0])
+            self.props.append(self.props[0])
+        self.table, self.prop = self.tables[0], self.props[0]
 
-    def _g0_exact(self, d, tau):
+    def _g0_exact(self, d, tau, spin=0):
         d = np.asarray(d)
         tau = np.asarray(tau, float)
         flat_d, flat_t = d.ravel(), tau.ravel()
-        gk = g0mod.g0_K_tau(self.xi, flat_t, self.beta)               # (NcK, T)
+        gk = g0mod.g0_K_tau(self.xis[spin], flat_t, self.beta)        # (NcK, T)
         ph = np.exp(1j * self.sites[flat_d].astype(float) @ self.K.T)  # (T, NcK)
         val = np.einsum("tk,kt->t", ph, gk).real / self.Nc
         return val.reshape(d.shape)
@@ -76,7 +86,7 @@ class Model:
 def n_inverse(model, r, t, s, spin):
     """N_sigma^{-1} = e^V - g (e^V - 1) for a vertex list."""
     ev = model.ev(s, spin)
-    g = model.prop.matrix(r, t)
+    g = model.props[spin].matrix(r, t)
     return np.diag(ev) - g * (ev - 1.0)[None, :]
 
 
@@ -146,10 +156,10 @@ class Walker:
     def _insert_ratio(self, rq, tq, sq):
         m = self.m
         out = []
-        g_Iq = m.prop.g(self.r, self.t, rq, tq)
-        g_qI = m.prop.g(rq, tq, self.r, self.t)
-        g_qq = float(m.prop.g(rq, tq, rq, tq))
         for spin in range(2):
+            g_Iq = m.props[spin].g(self.r, self.t, rq, tq)
+            g_qI = m.props[spin].g(rq, tq, self.r, self.t)
+            g_qq = float(m.props[spin].g(rq, tq, rq, tq))
             evq = float(m.ev(sq, spin))
             evI = m.ev(self.s, spin)
             Q = -g_Iq * (evq - 1.0)

@@ -30,8 +30,9 @@ def _create(state, orb):
     return sign, state | (1 << orb)
 
 
-def hamiltonian(tij, U, mu):
-    """Dense many-body Hamiltonian on all 4^Nc Fock states."""
+def hamiltonian(tij, U, mu, h=0.0):
+    """Dense many-body Hamiltonian on all 4^Nc Fock states; h is a Zeeman
+    field, -h sum_i (n_iup - n_idown)."""
     Nc = tij.shape[0]
     n_orb = 2 * Nc
     dim = 1 << n_orb
@@ -41,7 +42,7 @@ def hamiltonian(tij, U, mu):
         diag = 0.0
         for i in range(Nc):
             nu, nd = occ[2 * i], occ[2 * i + 1]
-            diag += U * (nu - 0.5) * (nd - 0.5) - mu * (nu + nd)
+            diag += U * (nu - 0.5) * (nd - 0.5) - mu * (nu + nd) - h * (nu - nd)
         H[st, st] += diag
         for s in range(2):
             for i in range(Nc):
@@ -71,10 +72,10 @@ def annihilator(Nc, orb):
 class ED:
     """Eigen-decomposition plus single-particle Green's functions."""
 
-    def __init__(self, tij, U, mu, beta):
+    def __init__(self, tij, U, mu, beta, h=0.0):
         self.Nc = tij.shape[0]
         self.beta = beta
-        H = hamiltonian(tij, U, mu)
+        H = hamiltonian(tij, U, mu, h)
         E, V = np.linalg.eigh(H)
         self.E0 = E[0]
         self.E = E - E[0]

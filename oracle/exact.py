@@ -48,6 +48,8 @@ class ExactChain:
     """The single-vertex chain in extended precision, replaying forced decisions."""
 
     def __init__(self, model, r, t, s, ids, reinvert_every=64):
+        if getattr(model, "h", 0.0) != 0.0:
+            raise ValueError("the extended-precision replay takes one propagator for both spins (h = 0)")
         self.m = model
         self.r = np.asarray(r, np.int64).copy()
         self.t = np.asarray(t, np.float64).copy()
@@ -191,6 +193,8 @@ class RefinedChain:
     """
 
     def __init__(self, model, r, t, s, ids, reinvert_every=32, refine=True):
+        if getattr(model, "h", 0.0) != 0.0:
+            raise ValueError("the extended-precision replay takes one propagator for both spins (h = 0)")
         self.m = model
         self.refine = refine
         self.r = np.asarray(r, np.int64).copy()

@@ -67,14 +67,14 @@ class Accumulator:
         return s, sM, sD
 
 
-def finalize_G_iw(model, M_avg, n_freq):
+def finalize_G_iw(model, M_avg, n_freq, spin=0):
     """G(K, i w_n) = G0 - (1/beta) G0 <M> G0 for one spin; M_avg (Nc, n_freq)."""
     from .g0 import g0_K_iw
-    G0 = g0_K_iw(model.xi, n_freq, model.beta)
+    G0 = g0_K_iw(model.xis[spin], n_freq, model.beta)
     return G0 - G0 * M_avg * G0 / model.beta
 
 
-def G_tau_from_iw(model, M_avg, Mdiag_avg, n_freq, taus):
+def G_tau_from_iw(model, M_avg, Mdiag_avg, n_freq, taus, spin=0):
     """G(K, tau) from the frequency estimator with the 1/(i w)^2 tail removed.
 
     dG = G - G0 behaves as A / (i w)^2 with A = -(1/beta) <(1/Nc) sum_i M_ii>;
@@ -84,11 +84,12 @@ def G_tau_from_iw(model, M_avg, Mdiag_avg, n_freq, taus):
     from .g0 import g0_K_iw, g0_K_tau
     beta = model.beta
     w = matsubara(n_freq, beta)
-    G0w = g0_K_iw(model.xi, n_freq, beta)
+    xi = model.xis[spin]
+    G0w = g0_K_iw(xi, n_freq, beta)
     dG = -G0w * M_avg * G0w / beta                       # (Nc, n_freq)
     A = -Mdiag_avg / beta
     resid = dG - A / (1j * w[None, :]) ** 2
     taus = np.asarray(taus, float)
     ph = np.exp(-1j * np.outer(w, taus))                 # (n_freq, T)
     dGt = (2.0 / beta) * (resid @ ph).real + A * (2 * taus[None, :] - beta) / 4.0
-    return g0_K_tau(model.xi, taus, beta) + dGt
+    return g0_K_tau(xi, taus, beta) + dGt

@@ -48,12 +48,12 @@ def estimate_G(model, acc, B=32, taus=None, n_freq=None, spin_average=False):
 
     def giw(tot_M, tot_D, tot_s):
         Mavg = tot_M / tot_s
-        g = np.stack([measure.finalize_G_iw(model, Mavg[sp], nf) for sp in range(2)])
+        g = np.stack([measure.finalize_G_iw(model, Mavg[sp], nf, spin=sp) for sp in range(2)])
         return g.mean(axis=0) if spin_average else g
 
     def gtau(tot_M, tot_D, tot_s):
         Mavg, Davg = tot_M / tot_s, tot_D / tot_s
-        g = np.stack([measure.G_tau_from_iw(model, Mavg[sp], Davg[sp], nf, taus) for sp in range(2)])
+        g = np.stack([measure.G_tau_from_iw(model, Mavg[sp], Davg[sp], nf, taus, spin=sp) for sp in range(2)])
         return g.mean(axis=0) if spin_average else g
 
     binned = (stats.bins(sM[:, :, :, :nf], B), stats.bins(sD, B), stats.bins(s, B))

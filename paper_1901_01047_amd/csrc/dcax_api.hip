@@ -269,8 +269,8 @@ struct dcax_walker_s {
   int timing_every = 1;
   long long win_seq = 0;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pend_fold, pend_accept, pend_window;
-  double fold_s = 0.0, accept_s = 0.0, window_s = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pend_fold, pend_accept, pend_window, pend_cand, pend_y;
+  double fold_s = 0.0, accept_s = 0.0, window_s = 0.0, cand_s = 0.0, y_s = 0.0;
   long long fold_launches = 0;
 
   // all device memory comes from the caller's allocator
@@ -322,6 +322,8 @@ struct dcax_walker_s {
     drain(pend_fold, fold_s, &fold_launches);
     drain(pend_accept, accept_s, nullptr);
     drain(pend_window, window_s, nullptr);
+    drain(pend_cand, cand_s, nullptr);
+    drain(pend_y, y_s, nullptr);
   }
   void mark(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, hipEvent_t a, hipEvent_t b) {
     if (timing && a && b) v.push_back({a, b});
@@ -456,8 +458,10 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   const int g16 = spread(cdiv(kb1, 16), W, 2);
   const bool wide = (long long)g16 * 2 * W < 4096 || kb1 >= 1024;
   const bool ywide = (long long)g16 * 2 * W < (sizeof(T) == 8 ? 512 : 4096);
-  if (wide) hipLaunchKernelGGL((k_cand_x<T, 16>), dim3(g16, 2, W), dim3(1024), 0, s, vs);
-  else hipLaunchKernelGGL((k_cand_x<T, 4>), dim3(g16, 2, W), dim3(256), 0, s, vs);
+  hipEvent_t e_c0 = w->tev(timed), e_c1 = w->tev(timed);
+  if (wide) hipExtLaunchKernelGGL((k_cand_x<T, 16>), dim3(g16, 2, W), dim3(1024), 0, s, e_c0, e_c1, 0, vs);
+  else hipExtLaunchKernelGGL((k_cand_x<T, 4>), dim3(g16, 2, W), dim3(256), 0, s, e_c0, e_c1, 0, vs);
+  w->mark(w->pend_cand, e_c0, e_c1);
   // Gram: a workgroup per row for few walkers, the matrix-core form for
   // batches (a workgroup per 16 candidates)
   if ((long long)ne * 2 * W < 4096) hipLaunchKernelGGL((k_gram_rows<T, 16>), dim3(ne, 2, W), dim3(1024), 0, s, vs);
@@ -465,8 +469,10 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   hipEvent_t e_a0 = w->tev(timed), e_a1 = w->tev(timed);
   hipExtLaunchKernelGGL(k_accept<T>, dim3(1, 1, W), dim3(AW), 0, s, e_a0, e_a1, 0, vs);
   w->mark(w->pend_accept, e_a0, e_a1);
-  if (ywide) hipLaunchKernelGGL((k_ygemm<T, 8>), dim3(g16, 2, W), dim3(512), 0, s, vs);
-  else hipLaunchKernelGGL((k_ygemm<T, 4>), dim3(g16, 2, W), dim3(256), 0, s, vs);
+  hipEvent_t e_y0 = w->tev(timed), e_y1 = w->tev(timed);
+  if (ywide) hipExtLaunchKernelGGL((k_ygemm<T, 8>), dim3(g16, 2, W), dim3(512), 0, s, e_y0, e_y1, 0, vs);
+  else hipExtLaunchKernelGGL((k_ygemm<T, 4>), dim3(g16, 2, W), dim3(256), 0, s, e_y0, e_y1, 0, vs);
+  w->mark(w->pend_y, e_y0, e_y1);
   hipLaunchKernelGGL(k_fold_prep<T>, dim3(spread(cdiv(kx, 64), W, 2), 2, W), dim3(WG), 0, s, vs);
   hipEvent_t e_f0 = w->tev(timed), e_f1 = w->tev(timed);
   const int ft = cdiv(kx, 64);
@@ -1383,6 +1389,10 @@ dcax_status dcax_get_stats(dcax_walker w, int32_t walker, dcax_stats* out) {
     out->decision_mismatches += h.n_mismatch;
     out->fold_flops += h.fold_flops;
     out->fold_bytes += h.fold_bytes;
+    out->cand_flops += h.cand_flops;
+    out->cand_bytes += h.cand_bytes;
+    out->y_flops += h.y_flops;
+    out->y_bytes += h.y_bytes;
     out->aborted_windows += h.n_abort;
     for (int b = 0; b < FOLD_RANK_BINS; ++b) out->fold_rank_hist[b] += h.m_hist[b];
   }
@@ -1393,6 +1403,8 @@ dcax_status dcax_get_stats(dcax_walker w, int32_t walker, dcax_stats* out) {
   out->windows_enqueued = w->win_seq;
   out->accept_seconds = w->accept_s;
   out->window_seconds = w->window_s;
+  out->cand_seconds = w->cand_s;
+  out->y_seconds = w->y_s;
   out->last_drift = w->last_drift;
   out->max_drift = w->max_drift;
   return st;

@@ -55,6 +55,9 @@ struct Ctl {
   int pad_;
   // windows by fold rank: bin 0 is m = 0, bin b holds 4b - 3 <= m <= 4b
   long long m_hist[FOLD_RANK_BINS];
+  // algorithmic work of the candidate-row (X_C = W_C N) and Y-column
+  // (N g_{I,c}) products: flops, and bytes with N read once
+  double cand_flops, cand_bytes, y_flops, y_bytes;
 };
 
 struct WinProp {      // one proposal of the current window

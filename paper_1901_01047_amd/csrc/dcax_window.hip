@@ -1054,6 +1054,19 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
       c->carry_id = carry;
       c->n_abort += 1;
     }
+    {
+      // both spins: X_C reads N and W_C, writes X_C; Y reads N and the
+      // inserted spins' g columns, writes Y
+      const double kk = (double)k0, b = (double)sizeof(T);
+      if (nC > 0) {
+        c->cand_flops += 2.0 * 2.0 * kk * kk * (double)nC;
+        c->cand_bytes += 2.0 * (kk * kk + 2.0 * nC * kk) * b;
+      }
+      if (mi > 0) {
+        c->y_flops += 2.0 * 2.0 * kk * kk * (double)mi;
+        c->y_bytes += 2.0 * (kk * kk + 2.0 * mi * kk) * b;
+      }
+    }
     if (m > 0) {
       const double x = (double)kx;
       c->fold_flops += 2.0 * 2.0 * x * x * (double)m;

@@ -59,7 +59,9 @@ class Stats(ctypes.Structure):
                 ("fold_launches", ctypes.c_int64), ("accept_seconds", ctypes.c_double),
                 ("window_seconds", ctypes.c_double), ("aborted_windows", ctypes.c_int64),
                 ("last_drift", ctypes.c_double), ("max_drift", ctypes.c_double),
-                ("windows_enqueued", ctypes.c_int64), ("fold_rank_hist", ctypes.c_int64 * 17)]
+                ("windows_enqueued", ctypes.c_int64), ("fold_rank_hist", ctypes.c_int64 * 17),
+                ("cand_flops", ctypes.c_double), ("cand_bytes", ctypes.c_double), ("cand_seconds", ctypes.c_double),
+                ("y_flops", ctypes.c_double), ("y_bytes", ctypes.c_double), ("y_seconds", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

@@ -31,6 +31,25 @@ CONFIGS = {
 }
 
 
+def initial_config(Nc, beta, k, seed):
+    """A seeded starting configuration of k vertices: sites and times uniform,
+    and every vertex at a site carrying that site's auxiliary spin (one spin
+    per site, +1 or -1 with probability 1/2).
+
+    Equilibrated CT-AUX configurations have strongly site-correlated
+    auxiliary spins (the atom's weight (1 + cosh(gamma sum s)) / 2 favours
+    aligned spins by e^{2 gamma}); vertices of opposite spin at one site and
+    nearby times make N^{-1} nearly singular, which uniformly random spins
+    produce in large numbers at these orders.  Returns (site int32,
+    tau float64, aux_spin int32)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    site_spin = np.where(rng.random(Nc) < 0.5, 1, -1).astype(np.int32)
+    site = rng.integers(0, Nc, size=k).astype(np.int32)
+    tau = rng.random(k) * beta
+    return site, tau, site_spin[site]
+
+
 def params_kwargs(name, **over):
     """Keyword arguments for paper_1901_01047_amd.dcax.make_params."""
     c = dict(CONFIGS[name])

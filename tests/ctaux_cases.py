@@ -29,12 +29,16 @@ def records(trace):
     return r, a["ratio"]
 
 
-def oracle_trace(m, seed, k_s, init_order, warm_sweeps, rec_proposals):
+def oracle_trace(m, seed, k_s, init_order, warm_sweeps, rec_proposals, init=None):
     """Equilibrate an oracle walker, refresh it, then record rec_proposals.
 
-    Returns (initial config (r, t, s, id), records, oracle ratios, walker)."""
+    init: a starting configuration (site, tau, aux_spin), else init_order
+    random vertices.  Returns (initial config (r, t, s, id), records, oracle
+    ratios, walker)."""
     w = ctaux.Walker(m, seed=seed, k_s=k_s)
-    if init_order:
+    if init is not None:
+        w.set_config(*init)
+    elif init_order:
         w.random_config(init_order)
     for _ in range(warm_sweeps):
         w.sweep()

@@ -93,3 +93,22 @@ def test_ed_dimer_ground_state():
     E = np.linalg.eigvalsh(H[np.ix_(idx, idx)])
     E_std = E[0] + U / 2 * 2 - 2 * U / 4
     assert abs(E_std - (U - np.sqrt(U * U + 16 * t * t)) / 2) < 1e-12
+
+
+def test_atom_in_a_field_closed_form():
+    """Hubbard atom with a Zeeman field, H = U (n_u - 1/2)(n_d - 1/2)
+    - mu (n_u + n_d) - h (n_u - n_d): four states E_0 = U/4,
+    E_up = -U/4 - mu - h, E_dn = -U/4 - mu + h, E_2 = U/4 - 2 mu, and
+    G_s(i w) = [(e^{-b E_0} + e^{-b E_s}) / (i w + E_0 - E_s)
+               + (e^{-b E_sbar} + e^{-b E_2}) / (i w + E_sbar - E_2)] / Z."""
+    U, mu, h, beta = 4.0, 0.3, 0.5, 5.0
+    e = ed.ED(np.zeros((1, 1)), U=U, mu=mu, beta=beta, h=h)
+    E = {"0": U / 4, "u": -U / 4 - mu - h, "d": -U / 4 - mu + h, "2": U / 4 - 2 * mu}
+    Z = sum(np.exp(-beta * x) for x in E.values())
+    wn = (2 * np.arange(20) + 1) * np.pi / beta
+    for spin, (s, sb) in enumerate((("u", "d"), ("d", "u"))):
+        want = ((np.exp(-beta * E["0"]) + np.exp(-beta * E[s])) / (1j * wn + E["0"] - E[s])
+                + (np.exp(-beta * E[sb]) + np.exp(-beta * E["2"])) / (1j * wn + E[sb] - E["2"])) / Z
+        assert np.allclose(e.G_iw(np.array([1.0]), spin, 20), want, atol=1e-13)
+    # the field splits the spins: G_up != G_down
+    assert np.max(np.abs(e.G_iw(np.array([1.0]), 0, 20) - e.G_iw(np.array([1.0]), 1, 20))) > 1e-2

@@ -51,6 +51,33 @@ def test_atom_green_function():
     assert res["sign"] == 1.0
 
 
+def test_atom_in_a_field_green_function():
+    """One bare propagator per spin (a Zeeman field h splits xi_up and
+    xi_down): the chain's G_up and G_down against the four-state exact
+    result, which the ED tests pin by its closed form.  A dropped spin index
+    (one propagator for both spins) fails: the two G differ by ~0.1.  At
+    beta U = 4 the chain passes through low orders often enough to flip the
+    atom's moment (at larger beta U insert/remove moves flip it too rarely
+    for the minority configurations to be sampled in a short run)."""
+    U, beta, mu, h = 2.0, 2.0, 0.3, 0.5
+    m = ctaux.Model(a1=(1, 0), a2=(0, 1), t=0.0, U=U, beta=beta, mu=mu, n_tau=2, use_table=False, h=h)
+    nf = 256
+    w, acc, orders = run.run_chain(m, seed=31, sweeps=8000, warmup=200, n_freq=nf, k_s=8)
+    taus = np.linspace(0.1, beta - 0.1, 12)
+    res = run.estimate_G(m, acc, taus=taus)
+    e = ed.ED(np.zeros((1, 1)), U=U, mu=mu, beta=beta, h=h)
+    zs = []
+    for sp in range(2):
+        want = e.G_iw(np.array([1.0]), sp, 16)
+        zs.append(_zscores(res["Giw"][sp, 0, :16].real, res["Giw_err"][sp, 0, :16].real + 1e-14, want.real))
+        zs.append(_zscores(res["Giw"][sp, 0, :16].imag, res["Giw_err"][sp, 0, :16].imag, want.imag))
+        zs.append(_zscores(res["Gtau"][sp, 0], res["Gtau_err"][sp, 0], e.G_tau(np.array([1.0]), sp, taus)))
+    _check(zs, None, None)
+    # the two spins are measured apart and differ as the exact ones do
+    d_exact = e.G_tau(np.array([1.0]), 0, taus) - e.G_tau(np.array([1.0]), 1, taus)
+    assert np.max(np.abs(d_exact)) > 0.05
+
+
 @pytest.fixture(scope="module")
 def cluster_2x2():
     m = ctaux.Model(a1=(2, 0), a2=(0, 2), U=4.0, beta=5.0, mu=0.0, n_tau=1000)
