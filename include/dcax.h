@@ -118,6 +118,25 @@ typedef struct {
   int32_t warmup_sweeps;   /* "warm-up-sweeps": generator sweeps after which the sweep length freezes */
   int32_t sweep_length;    /* proposals per sweep (rounded up to a multiple of submatrix_k);
                               0 = taken from the warm-up, see dcax_sweep */
+  /* The bare propagator of the cluster problem (Sec. 2.1: the cluster-
+   * excluded G0 is the solver's input in the DCA loop).
+   *   n_spin_tables = 0: the library builds G0 of the isolated periodic
+   *     cluster from t, tp and mu (finite-size mode), one table for both spins;
+   *   1: g0_tau holds one table for both spins; 2: one per spin (up, then
+   *     down), e.g. for a magnetic field or a symmetry-broken G0.
+   * g0_tau (host, [n_spin_tables][Nc][n_tau], copied by dcax_walker_create):
+   *   G0_sigma(r_d, tau_l) in the standard convention G0 = -<T c c+>_0, d the
+   *   displacement r_i - r_j as a site of the cluster enumeration below,
+   *   tau_l = l beta / (n_tau - 1), point 0 the 0+ value and point n_tau - 1
+   *   the beta- value (interpolated linearly between points).
+   * g0_Kw (host, nullable, complex [n_spin_tables][Nc][n_freq] as (re, im),
+   *   copied): G0_sigma(K, i w_n), n = 0 .. n_freq - 1, for dcax_finalize_G;
+   *   without it dcax_finalize_G answers DCAX_E_INVAL for this walker.
+   * t, tp and mu are ignored when n_spin_tables > 0. */
+  int32_t n_spin_tables;
+  int32_t reserved;        /* must be 0 */
+  const double* g0_tau;
+  const double* g0_Kw;
 } dcax_params;
 
 /* Counters since creation or the last dcax_set_config (timings and drifts
@@ -290,6 +309,23 @@ dcax_status dcax_autotune(dcax_walker w, int32_t sweeps_per_trial, int32_t* chos
  * times of dcax_stats come from eagerly launched windows only. */
 dcax_status dcax_set_graphs(dcax_walker w, int32_t on);
 
+/* Kernel forms of the two candidate products of a window (Sec. 2.3's
+ * "large matrix-matrix multiplications" of the submatrix update): X_C = W_C N
+ * (candidate rows) and N g_{I,c} (Y columns of inserted spins).
+ *   DCAX_VARIANT_AUTO   chosen per launch from its size (default);
+ *   DCAX_VARIANT_TILED  64-wide tiles of N staged in LDS, one workgroup per
+ *                       tile over the whole inner dimension (fits launches
+ *                       with many workgroups: batches of walkers);
+ *   DCAX_VARIANT_WIDE   16-wide tiles, the inner dimension split over 16
+ *                       (candidate rows) or 8 (Y columns) wavefronts (few
+ *                       workgroups: a single walker);
+ *   DCAX_VARIANT_NARROW 16-wide tiles over 4 wavefronts.
+ * Every form computes the same products; they differ in summation order
+ * only.  Answers DCAX_E_INVAL for an unknown value. */
+typedef enum { DCAX_VARIANT_AUTO = 0, DCAX_VARIANT_TILED = 1, DCAX_VARIANT_WIDE = 2,
+               DCAX_VARIANT_NARROW = 3 } dcax_variant;
+dcax_status dcax_set_variants(dcax_walker w, int32_t cand_rows, int32_t y_columns);
+
 /* Introspection and checkpointing; `walker` indexes the batch (0-based). */
 dcax_status dcax_get_order(dcax_walker w, int32_t walker, int32_t* k);
 /* Copy N_spin in canonical order (vertex id ascending) into host[ld * k];
@@ -309,8 +345,8 @@ dcax_status dcax_get_stats(dcax_walker w, int32_t walker, dcax_stats* out);
  * event, so sampling keeps the overhead out of throughput measurements.
  * Timings accumulate into dcax_stats over the timed windows. */
 dcax_status dcax_set_timing(dcax_walker w, int32_t on);
-/* The G0(r, tau) table the walker uses, [Nc][n_tau], standard sign convention
- * G0 = -<T c c+>. */
+/* The G0(r, tau) table the walker uses for spin up (the only one unless two
+ * tables were given), [Nc][n_tau], standard sign convention G0 = -<T c c+>. */
 dcax_status dcax_copy_g0_table(dcax_walker w, int32_t walker, double* host);
 /* Cluster geometry: sites [Nc][2] (int32) and momenta [Nc][2] (double). */
 dcax_status dcax_cluster(const dcax_params* p, int32_t* n_sites, int32_t* sites, double* momenta);

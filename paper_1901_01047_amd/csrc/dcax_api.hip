@@ -220,7 +220,8 @@ __global__ void k_set_sign(const View<T>* __restrict__ vs) {
 
 // One Markov chain of the batch.
 struct WalkerHost {
-  dcax_params p{};
+  dcax_params p{};            // host pointers g0_tau / g0_Kw are cleared after creation
+  bool has_g0Kw = false;
   Geometry geo;
   int ks = 0, cap = 0, ld = 0, max_order = 0, kpad_cap = 0;
   double gamma = 0.0;
@@ -256,6 +257,7 @@ struct dcax_walker_s {
   // rejects them), so a replayed sweep is timed as a whole from events
   // around its launch, and per-kernel times come from eager sweeps.
   bool use_graphs = false;
+  int cand_variant = DCAX_VARIANT_AUTO, y_variant = DCAX_VARIANT_AUTO;   // dcax_set_variants
   hipStream_t gstream = nullptr;         // library stream the graphs run on
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
@@ -380,6 +382,10 @@ dcax_status validate(const dcax_params* p) {
   if (p->n_freq < 0 || p->n_freq > 65536) return fail(DCAX_E_INVAL, "n_freq out of range");
   if (p->warmup_sweeps < 0) return fail(DCAX_E_INVAL, "warmup_sweeps must be >= 0");
   if (p->sweep_length < 0) return fail(DCAX_E_INVAL, "sweep_length must be >= 0");
+  if (p->n_spin_tables < 0 || p->n_spin_tables > 2) return fail(DCAX_E_INVAL, "n_spin_tables must be 0, 1 or 2");
+  if (p->n_spin_tables > 0 && !p->g0_tau) return fail(DCAX_E_INVAL, "n_spin_tables > 0 needs g0_tau");
+  if (p->n_spin_tables == 0 && (p->g0_tau || p->g0_Kw)) return fail(DCAX_E_INVAL, "g0_tau or g0_Kw given with n_spin_tables = 0");
+  if (p->reserved != 0) return fail(DCAX_E_INVAL, "reserved must be 0");
   Geometry g;
   if (!build_geometry(p->cluster, g)) return fail(DCAX_E_INVAL, "degenerate or too large cluster");
   if (p->n_freq > 0 && g.Nc > MEAS_NC_MAX)
@@ -432,6 +438,10 @@ static int spread(int tiles, int W, int units, long long budget = 1ll << 21) {
 // launch sized for every walker would spend its time dispatching workgroups
 // that return at once, so the measurement grids stay within this budget.
 constexpr long long MEAS_BUDGET = 1ll << 15;
+// orders from which a single walker's device-scheduled rounds carry spare
+// windows (below it an empty window's ~10 launches are a visible share of a
+// full one)
+constexpr int SPARE_MIN_ORDER = 512;
 
 template <typename T>
 void enqueue_window(dcax_walker w, int kb, bool replay) {
@@ -455,11 +465,24 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   // tiles are few; in FP64, from a few hundred tiles on (a single walker of
   // order ~5000) the 4-wavefront form streams N faster, in FP32 only from
   // the batch bound on.
+  // With many workgroups (batches) the FP32 products run on 64-wide tiles of
+  // N staged in LDS, whose small operand is then read once per 64 columns or
+  // rows (measured on 32 walkers of order 6000: 7.5 -> 4.8 ms and 5.6 ->
+  // 4.2 ms per launch; in FP64 the split-inner-dimension forms stay faster,
+  // 8.0 and 8.4 ms against 13.5 and 12.8 ms).
   const int g16 = spread(cdiv(kb1, 16), W, 2);
-  const bool wide = (long long)g16 * 2 * W < 4096 || kb1 >= 1024;
-  const bool ywide = (long long)g16 * 2 * W < (sizeof(T) == 8 ? 512 : 4096);
+  const int g64 = spread(cdiv(kb1, 64), W, 2);
+  const bool big = sizeof(T) == 4 && (long long)g64 * 2 * W >= 1024;
+  const int cv = w->cand_variant != DCAX_VARIANT_AUTO ? w->cand_variant
+      : big ? DCAX_VARIANT_TILED : ((long long)g16 * 2 * W < 4096 || kb1 >= 1024) ? DCAX_VARIANT_WIDE
+      : DCAX_VARIANT_NARROW;
+  const int yv = w->y_variant != DCAX_VARIANT_AUTO ? w->y_variant
+      : big ? DCAX_VARIANT_TILED : ((long long)g16 * 2 * W < (sizeof(T) == 8 ? 512 : 4096)) ? DCAX_VARIANT_WIDE
+      : DCAX_VARIANT_NARROW;
+  const bool tiled = cv == DCAX_VARIANT_TILED, wide = cv == DCAX_VARIANT_WIDE;
   hipEvent_t e_c0 = w->tev(timed), e_c1 = w->tev(timed);
-  if (wide) hipExtLaunchKernelGGL((k_cand_x<T, 16>), dim3(g16, 2, W), dim3(1024), 0, s, e_c0, e_c1, 0, vs);
+  if (tiled) hipExtLaunchKernelGGL(k_cand_xt<T>, dim3(g64, 2, W), dim3(256), 0, s, e_c0, e_c1, 0, vs);
+  else if (wide) hipExtLaunchKernelGGL((k_cand_x<T, 16>), dim3(g16, 2, W), dim3(1024), 0, s, e_c0, e_c1, 0, vs);
   else hipExtLaunchKernelGGL((k_cand_x<T, 4>), dim3(g16, 2, W), dim3(256), 0, s, e_c0, e_c1, 0, vs);
   w->mark(w->pend_cand, e_c0, e_c1);
   // Gram: a workgroup per row for few walkers, the matrix-core form for
@@ -470,7 +493,8 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
   hipExtLaunchKernelGGL(k_accept<T>, dim3(1, 1, W), dim3(AW), 0, s, e_a0, e_a1, 0, vs);
   w->mark(w->pend_accept, e_a0, e_a1);
   hipEvent_t e_y0 = w->tev(timed), e_y1 = w->tev(timed);
-  if (ywide) hipExtLaunchKernelGGL((k_ygemm<T, 8>), dim3(g16, 2, W), dim3(512), 0, s, e_y0, e_y1, 0, vs);
+  if (yv == DCAX_VARIANT_TILED) hipExtLaunchKernelGGL(k_ygemm_t<T>, dim3(g64, 2, W), dim3(256), 0, s, e_y0, e_y1, 0, vs);
+  else if (yv == DCAX_VARIANT_WIDE) hipExtLaunchKernelGGL((k_ygemm<T, 8>), dim3(g16, 2, W), dim3(512), 0, s, e_y0, e_y1, 0, vs);
   else hipExtLaunchKernelGGL((k_ygemm<T, 4>), dim3(g16, 2, W), dim3(256), 0, s, e_y0, e_y1, 0, vs);
   w->mark(w->pend_y, e_y0, e_y1);
   hipLaunchKernelGGL(k_fold_prep<T>, dim3(spread(cdiv(kx, 64), W, 2), 2, W), dim3(WG), 0, s, vs);
@@ -699,7 +723,9 @@ size_t walker_bytes(const WalkerHost& x) {
   size_t b = 0;
   auto add = [&](size_t n) { b += (n + 255) & ~size_t(255); };
   add(sizeof(int) * Nc * Nc);                    // diff
-  add(sizeof(double) * Nc * x.p.n_tau);          // table
+  const size_t nt = x.p.n_spin_tables == 2 ? 2 : 1;
+  add(sizeof(double) * nt * Nc * x.p.n_tau);     // table(s)
+  if (x.p.g0_Kw) add(sizeof(double) * 2 * nt * Nc * nf);  // caller's G0(K, i w_n)
   add(sizeof(int) * 2 * Nc);                     // sites
   add(sizeof(double) * 2 * Nc);                  // K
   add(sizeof(double) * Nc);                      // xi
@@ -714,8 +740,10 @@ size_t walker_bytes(const WalkerHost& x) {
   add(sizeof(long long) * KS_MAX);               // cand_id
   add(sizeof(int) * cap);                        // remap
   add(sizeof(int) * (2 * KS_MAX + 1));           // moves
-  add(sizeof(T) * ks * cap);                     // gcol
-  add(sizeof(double) * KS_MAX * KS_MAX);         // gCC
+  for (size_t sp = 0; sp < nt; ++sp) {
+    add(sizeof(T) * ks * cap);                   // gcol
+    add(sizeof(double) * KS_MAX * KS_MAX);       // gCC
+  }
   for (int sp = 0; sp < 2; ++sp) {
     add(sizeof(T) * ks * cap);                   // W
     add(sizeof(T) * KS_MAX * cap);               // R
@@ -771,7 +799,12 @@ void wire_walker(dcax_walker w, WalkerHost& x, int wid, char* base, Ctl* ctl) {
   }
   v.seed = x.p.seed;
   v.diff = (const int*)take(sizeof(int) * Nc * Nc);
-  v.table = (const double*)take(sizeof(double) * Nc * x.p.n_tau);
+  const int nt = x.p.n_spin_tables == 2 ? 2 : 1;
+  v.spin_tables = nt;
+  v.ext_g0 = x.p.n_spin_tables > 0 ? 1 : 0;
+  v.table[0] = (const double*)take(sizeof(double) * nt * Nc * x.p.n_tau);
+  v.table[1] = v.table[0] + (nt == 2 ? Nc * (size_t)x.p.n_tau : 0);
+  v.g0Kw = x.p.g0_Kw ? (const double*)take(sizeof(double) * 2 * nt * Nc * nf) : nullptr;
   v.sites = (const int*)take(sizeof(int) * 2 * Nc);
   v.Kp = (const double*)take(sizeof(double) * 2 * Nc);
   v.xi = (const double*)take(sizeof(double) * Nc);
@@ -794,8 +827,14 @@ void wire_walker(dcax_walker w, WalkerHost& x, int wid, char* base, Ctl* ctl) {
   v.cand_id = (long long*)take(sizeof(long long) * KS_MAX);
   v.remap = (int*)take(sizeof(int) * cap);
   v.moves = (int*)take(sizeof(int) * (2 * KS_MAX + 1));
-  v.gcol = (T*)take(sizeof(T) * ks * cap);
-  v.gCC = (double*)take(sizeof(double) * KS_MAX * KS_MAX);
+  for (int sp = 0; sp < nt; ++sp) {
+    v.gcol[sp] = (T*)take(sizeof(T) * ks * cap);
+    v.gCC[sp] = (double*)take(sizeof(double) * KS_MAX * KS_MAX);
+  }
+  if (nt == 1) {
+    v.gcol[1] = v.gcol[0];
+    v.gCC[1] = v.gCC[0];
+  }
   for (int sp = 0; sp < 2; ++sp) {
     v.W[sp] = (T*)take(sizeof(T) * ks * cap);
     v.R[sp] = (T*)take(sizeof(T) * KS_MAX * cap);
@@ -856,9 +895,19 @@ dcax_status create_walkers(dcax_walker w) {
     HIPCHK(hipMemcpyAsync((void*)v.sites, x.geo.sites.data(), sizeof(int) * 2 * Nc, hipMemcpyHostToDevice, w->stream));
     HIPCHK(hipMemcpyAsync((void*)v.Kp, x.geo.K.data(), sizeof(double) * 2 * Nc, hipMemcpyHostToDevice, w->stream));
     HIPCHK(hipMemcpyAsync((void*)v.xi, xi.data(), sizeof(double) * Nc, hipMemcpyHostToDevice, w->stream));
-    hipLaunchKernelGGL(k_g0_table, dim3(cdiv(x.p.n_tau, WG), Nc), dim3(WG), 0, w->stream, (double*)v.table, Nc,
-                       x.p.n_tau, x.p.beta, v.sites, v.Kp, v.xi);
-    HIPCHK(hipGetLastError());
+    if (x.p.n_spin_tables == 0) {
+      hipLaunchKernelGGL(k_g0_table, dim3(cdiv(x.p.n_tau, WG), Nc), dim3(WG), 0, w->stream, (double*)v.table[0], Nc,
+                         x.p.n_tau, x.p.beta, v.sites, v.Kp, v.xi);
+      HIPCHK(hipGetLastError());
+    } else {
+      // the caller's propagator, copied before this call returns (it syncs)
+      const size_t nt = (size_t)v.spin_tables;
+      HIPCHK(hipMemcpyAsync((void*)v.table[0], x.p.g0_tau, sizeof(double) * nt * Nc * x.p.n_tau,
+                            hipMemcpyHostToDevice, w->stream));
+      if (x.p.g0_Kw)
+        HIPCHK(hipMemcpyAsync((void*)v.g0Kw, x.p.g0_Kw, sizeof(double) * 2 * nt * Nc * std::max(x.p.n_freq, 1),
+                              hipMemcpyHostToDevice, w->stream));
+    }
   }
   std::vector<Ctl> h(w->W);
   std::memset(h.data(), 0, sizeof(Ctl) * w->W);
@@ -869,6 +918,12 @@ dcax_status create_walkers(dcax_walker w) {
   }
   HIPCHK(hipMemcpyAsync(w->ctl_all, h.data(), sizeof(Ctl) * w->W, hipMemcpyHostToDevice, w->stream));
   HIPCHK(hipStreamSynchronize(w->stream));
+  // the caller's buffers are not referenced after creation
+  for (auto& x : w->wk) {
+    x.has_g0Kw = x.p.g0_Kw != nullptr;
+    x.p.g0_tau = nullptr;
+    x.p.g0_Kw = nullptr;
+  }
   return DCAX_OK;
 }
 
@@ -929,9 +984,21 @@ dcax_status sweep_rounds(dcax_walker w, int n, double* acc, double* aux, long lo
   for (int pass = 0;; ++pass) {
     if (pass > 64) return fail(DCAX_E_STATE, "device-scheduled sweeps made no progress");
     const int kb = std::min(w->mo_max, w->kmax_host() + 2 * w->ks_max);
+    // A single walker runs one sweep per round.  A window closed early by a
+    // carried removal makes its sweep need one window more, and a sweep left
+    // unfinished would cost a whole round of empty windows, so at large
+    // orders (where an empty window's launches cost little beside a full
+    // one) the round carries spare windows in proportion to the observed
+    // share of such windows; unused spares find the sweep complete and exit.
+    int spare = 0;
+    if (w->W == 1 && kb >= SPARE_MIN_ORDER) {
+      const Ctl& h = w->h_ctl[0];
+      const double expect = h.n_windows > 0 ? (double)R * (double)h.n_abort / (double)h.n_windows : 0.0;
+      if (expect > 0.0) spare = (int)std::ceil(expect + 2.0 * std::sqrt(expect) + 1.0);
+    }
     for (long long r = 0; r < planned; ++r) {
-      if (w->mixed) enqueue_round<float>(w, kb, R, acc, aux, nfft_hw);
-      else enqueue_round<double>(w, kb, R, acc, aux, nfft_hw);
+      if (w->mixed) enqueue_round<float>(w, kb, R + spare, acc, aux, nfft_hw);
+      else enqueue_round<double>(w, kb, R + spare, acc, aux, nfft_hw);
       HIPCHK(hipGetLastError());
       ++w->rounds_done;
       if (refresh_rounds > 0 && w->rounds_done % refresh_rounds == 0) {
@@ -1283,6 +1350,9 @@ dcax_status dcax_finalize_G(dcax_walker w, const double* acc_dev, const double* 
                             int32_t n_tau_out, double* Gtau_dev) {
   if (!w || !acc_dev || !aux_dev || !Giw_dev) return fail(DCAX_E_INVAL, "NULL argument");
   if (n_tau_out < 0 || n_tau_out == 1 || (n_tau_out > 0 && !Gtau_dev)) return fail(DCAX_E_INVAL, "bad n_tau_out");
+  for (const auto& x : w->wk)
+    if (x.p.n_spin_tables > 0 && !x.has_g0Kw && x.p.n_freq > 0)
+      return fail(DCAX_E_INVAL, "a walker was given g0_tau without g0_Kw: G0(K, i w_n) is unknown");
   const int nx = std::max(w->nf_max, n_tau_out);
   if (nx == 0) return DCAX_OK;
   double* gt = n_tau_out > 0 ? Gtau_dev : nullptr;
@@ -1470,6 +1540,18 @@ dcax_status dcax_set_graphs(dcax_walker w, int32_t on) {
   return st;
 }
 
+dcax_status dcax_set_variants(dcax_walker w, int32_t cand_rows, int32_t y_columns) {
+  if (!w) return fail(DCAX_E_INVAL, "walker is NULL");
+  if (cand_rows < DCAX_VARIANT_AUTO || cand_rows > DCAX_VARIANT_NARROW || y_columns < DCAX_VARIANT_AUTO ||
+      y_columns > DCAX_VARIANT_NARROW)
+    return fail(DCAX_E_INVAL, "unknown kernel variant");
+  dcax_status st = sync_all(w);
+  w->cand_variant = cand_rows;
+  w->y_variant = y_columns;
+  w->clear_graphs();       // captured sweeps hold the previous kernels
+  return st;
+}
+
 dcax_status dcax_set_timing(dcax_walker w, int32_t on) {
   if (!w) return fail(DCAX_E_INVAL, "walker is NULL");
   if (on < 0) return fail(DCAX_E_INVAL, "on must be >= 0");
@@ -1484,7 +1566,7 @@ dcax_status dcax_copy_g0_table(dcax_walker w, int32_t walker, double* host) {
   if (!w || !host) return fail(DCAX_E_INVAL, "NULL argument");
   if (walker < 0 || walker >= w->W) return fail(DCAX_E_INVAL, "walker index out of range");
   const WalkerHost& x = w->wk[walker];
-  const double* t = w->mixed ? x.v32.table : x.v64.table;
+  const double* t = w->mixed ? x.v32.table[0] : x.v64.table[0];
   HIPCHK(hipMemcpyAsync(host, t, sizeof(double) * (size_t)x.geo.Nc * x.p.n_tau, hipMemcpyDeviceToHost, w->stream));
   HIPCHK(hipStreamSynchronize(w->stream));
   return DCAX_OK;

@@ -84,7 +84,10 @@ struct View {
   double ev[2][2];            // e^{V}: [spin][0 for s = +1, 1 for s = -1]
   uint64_t seed;              // generator key
   const int* diff;            // [Nc * Nc] index of r_i - r_j
-  const double* table;        // [Nc][n_tau] G0(r, tau_l), standard convention
+  const double* table[2];     // [Nc][n_tau] G0_sigma(r, tau_l), standard convention (one shared table or one per spin)
+  int spin_tables;            // 1: table[1] == table[0]; 2: a table per spin
+  const double* g0Kw;         // [spin_tables][Nc][n_freq][2] caller's G0(K, i w_n), or null
+  int ext_g0;                 // the tables came from the caller (G0(K, .) from them in the finalisation)
   const int* sites;           // [Nc][2]
   const double* Kp;           // [Nc][2]
   const double* xi;           // [Nc] eps_K - mu
@@ -109,9 +112,9 @@ struct View {
   int* ins_el;                // inserted elements in S order (mi)
   int* remap;                 // [cap] compaction source of each destination
   int* moves;                 // [2 KS_MAX + 1] compaction (dst, src) pairs, count
-  T* gcol;                    // [ks][cap] g_{I,c}
+  T* gcol[2];                 // [ks][cap] g_{I,c} per spin (gcol[1] == gcol[0] for one table)
   T* W[2];                    // [ks][cap] g_{c,I} (e^{V_I} - 1)
-  double* gCC;                // [ks][ks] g_{c,c'}
+  double* gCC[2];             // [ks][ks] g_{c,c'} per spin (shared like gcol)
   T* R[2];                    // [KS_MAX][cap] rows of the extended N per element
   double* gram[2];            // [ks][ks] G restricted to the window elements
   double* ginv[2];            // [ks][ks] Gamma_S^{-1}
@@ -161,12 +164,12 @@ __host__ __device__ inline double max_nan(double a, double b) { return (a > b ||
 // f = dtau/h - l, (1 - f) T[l] + f T[l+1], l clamped to n_tau - 2; dtau = 0
 // gives the 0+ value.
 template <typename T>
-__device__ inline double g0_interp(const View<T>& w, int d, double dtau) {
+__device__ inline double g0_interp(const View<T>& w, int sp, int d, double dtau) {
   double x = dtau / w.h;
   int l = (int)floor(x);
   l = l < 0 ? 0 : (l > w.n_tau - 2 ? w.n_tau - 2 : l);
   double f = x - (double)l;
-  const double* t = w.table + (size_t)d * w.n_tau;
+  const double* t = w.table[sp] + (size_t)d * w.n_tau;
   return (1.0 - f) * t[l] + f * t[l + 1];
 }
 
@@ -174,11 +177,11 @@ __device__ inline double g0_interp(const View<T>& w, int d, double dtau) {
 // tau_i >= tau_j (0+ at equal times), and +G0(r_i - r_j, tau_i - tau_j + beta)
 // for tau_i < tau_j (antiperiodicity).
 template <typename T>
-__device__ inline double gfun(const View<T>& w, int ri, double ti, int rj, double tj) {
+__device__ inline double gfun(const View<T>& w, int sp, int ri, double ti, int rj, double tj) {
   int d = w.diff[ri * w.Nc + rj];
   double dt = ti - tj;
-  if (dt < 0.0) return g0_interp(w, d, dt + w.beta);
-  return -g0_interp(w, d, dt);
+  if (dt < 0.0) return g0_interp(w, sp, d, dt + w.beta);
+  return -g0_interp(w, sp, d, dt);
 }
 
 // ------------------------------------------------------------------ MFMA

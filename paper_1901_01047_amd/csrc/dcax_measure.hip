@@ -325,6 +325,39 @@ __global__ void __launch_bounds__(WG) k_meas_diag(const View<T>* __restrict__ vs
   }
 }
 
+// G0(K, i w_n): the caller's when it gave the propagator, else the isolated
+// cluster's 1 / (i w_n - xi_K) = (-xi - i w) / (xi^2 + w^2).
+template <typename T>
+__device__ inline void g0_K_iw(const View<T>& w, int sp, int q, int n, double& gr, double& gi) {
+  if (w.ext_g0) {
+    const double* g = w.g0Kw + 2 * (((size_t)(w.spin_tables == 2 ? sp : 0) * w.Nc + q) * w.n_freq + n);
+    gr = g[0];
+    gi = g[1];
+    return;
+  }
+  const double e = w.xi[q];
+  const double wn = (2.0 * n + 1.0) * M_PI / w.beta;
+  const double d = e * e + wn * wn;
+  gr = -e / d;
+  gi = -wn / d;
+}
+
+// G0(K, tau) for 0 <= tau <= beta: from the caller's table,
+// sum_r e^{-i K r} G0(r, tau) (its real part: the tables of inversion-
+// symmetric clusters are even in r), else the isolated cluster's closed form.
+template <typename T>
+__device__ inline double g0_K_tau(const View<T>& w, int sp, int q, double tau) {
+  if (w.ext_g0) {
+    const double Kx = w.Kp[2 * q], Ky = w.Kp[2 * q + 1];
+    double s = 0.0;
+    for (int d = 0; d < w.Nc; ++d)
+      s += cos(Kx * w.sites[2 * d] + Ky * w.sites[2 * d + 1]) * g0_interp(w, sp, d, tau);
+    return s;
+  }
+  const double e = w.xi[q], beta = w.beta;
+  return (e >= 0.0) ? -exp(-e * tau) / (1.0 + exp(-beta * e)) : -exp(e * (beta - tau)) / (exp(beta * e) + 1.0);
+}
+
 // G(K, i w_n) = G0 - G0 <M> G0 / beta and the tail-corrected G(K, tau)
 // (blockIdx.z = 2 walker + spin, blockIdx.y = momentum).
 template <typename T>
@@ -342,12 +375,9 @@ __global__ void __launch_bounds__(WG) k_finalize(const View<T>* __restrict__ vs,
   const double* aux = aux_all + 3 * (size_t)w.wid;
   const int x = blockIdx.x * WG + threadIdx.x;
   const double sgn = aux[0];
-  const double e = w.xi[q];
   if (x < n_freq) {
-    const double wn = (2.0 * x + 1.0) * M_PI / beta;
-    // G0 = 1 / (i w - xi) = (-xi - i w) / (xi^2 + w^2)
-    const double d = e * e + wn * wn;
-    const double gr = -e / d, gi = -wn / d;
+    double gr, gi;
+    g0_K_iw(w, sp, q, x, gr, gi);
     const size_t o = 2 * (((size_t)sp * Nc + q) * n_freq + x);
     const double mr = acc[o] / sgn, mi = acc[o + 1] / sgn;
     const double g2r = gr * gr - gi * gi, g2i = 2.0 * gr * gi;
@@ -361,8 +391,8 @@ __global__ void __launch_bounds__(WG) k_finalize(const View<T>* __restrict__ vs,
     double s = 0.0;
     for (int n = 0; n < n_freq; ++n) {
       const double wn = (2.0 * n + 1.0) * M_PI / beta;
-      const double d = e * e + wn * wn;
-      const double gr = -e / d, gi = -wn / d;
+      double gr, gi;
+      g0_K_iw(w, sp, q, n, gr, gi);
       const double g2r = gr * gr - gi * gi, g2i = 2.0 * gr * gi;
       const size_t o = 2 * (((size_t)sp * Nc + q) * n_freq + n);
       const double mr = acc[o] / sgn, mi = acc[o + 1] / sgn;
@@ -375,7 +405,7 @@ __global__ void __launch_bounds__(WG) k_finalize(const View<T>* __restrict__ vs,
       // Re[e^{-i w tau} (rr + i ri)] = cs rr + sn ri
       s += cs * rr + sn * ri;
     }
-    const double g0 = (e >= 0.0) ? -exp(-e * tau) / (1.0 + exp(-beta * e)) : -exp(e * (beta - tau)) / (exp(beta * e) + 1.0);
+    const double g0 = g0_K_tau(w, sp, q, tau);
     Gtau[((size_t)sp * Nc + q) * n_tau_out + x] = g0 + (2.0 / beta) * s + A * (2.0 * tau - beta) / 4.0;
   }
 }

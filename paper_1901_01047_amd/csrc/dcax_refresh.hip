@@ -33,12 +33,15 @@ __global__ void __launch_bounds__(WG) k_build_ninv(const View<T>* __restrict__ v
   const int j = blockIdx.y;
   const int i = blockIdx.x * WG + threadIdx.x;
   if (i >= k || j >= k) return;
-  const double g = gfun(w, w.v_site[i], w.v_tau[i], w.v_site[j], w.v_tau[j]);
+  const int ri = w.v_site[i], rj = w.v_site[j];
+  const double ti = w.v_tau[i], tj = w.v_tau[j];
+  const double g = gfun(w, 0, ri, ti, rj, tj);
+  const double g1 = w.spin_tables == 2 ? gfun(w, 1, ri, ti, rj, tj) : g;
   const int sj = s01(w.v_s[j]);
   const double e0 = w.ev[0][sj], e1 = w.ev[1][sj];
   const size_t o = i + (size_t)j * w.cap;
   w.M[0][o] = (i == j ? e0 : 0.0) - g * (e0 - 1.0);
-  w.M[1][o] = (i == j ? e1 : 0.0) - g * (e1 - 1.0);
+  w.M[1][o] = (i == j ? e1 : 0.0) - g1 * (e1 - 1.0);
 }
 
 // Eliminates panel columns [p0, p0 + nb) in one workgroup for orders up to

@@ -288,16 +288,22 @@ __global__ void __launch_bounds__(WG) k_gather(const View<T>* __restrict__ vs) {
         const int ri = w.v_site[i];
         const double ti = w.v_tau[i];
         const int si = s01(w.v_s[i]);
-        const double gic = gfun(w, ri, ti, rc, tc);
-        const double gci = gfun(w, rc, tc, ri, ti);
         const size_t o = (size_t)cc * w.cap + i;
-        w.gcol[o] = (T)gic;
+        const double gic = gfun(w, 0, ri, ti, rc, tc);
+        const double gci = gfun(w, 0, rc, tc, ri, ti);
+        w.gcol[0][o] = (T)gic;
         w.W[0][o] = (T)(gci * (w.ev[0][si] - 1.0));
-        w.W[1][o] = (T)(gci * (w.ev[1][si] - 1.0));
+        if (w.spin_tables == 2) {
+          w.gcol[1][o] = (T)gfun(w, 1, ri, ti, rc, tc);
+          w.W[1][o] = (T)(gfun(w, 1, rc, tc, ri, ti) * (w.ev[1][si] - 1.0));
+        } else {
+          w.W[1][o] = (T)(gci * (w.ev[1][si] - 1.0));
+        }
       }
       if (blockIdx.x == 0 && (int)threadIdx.x < c->nC) {
         const int e2 = w.cand_el[threadIdx.x];
-        w.gCC[cc * KS_MAX + threadIdx.x] = gfun(w, rc, tc, w.el_site[e2], w.el_tau[e2]);
+        for (int sp = 0; sp < w.spin_tables; ++sp)
+          w.gCC[sp][cc * KS_MAX + threadIdx.x] = gfun(w, sp, rc, tc, w.el_site[e2], w.el_tau[e2]);
       }
     } else {
       const int p = w.el_slot[e];
@@ -461,6 +467,144 @@ __global__ void __launch_bounds__(NW * 64) k_cand_x(const View<T>* __restrict__ 
   }
 }
 
+// Candidate rows for launches with many workgroups (batches of walkers): a
+// workgroup owns 64 columns of X and runs over the whole inner dimension in
+// chunks of 32 rows of N, staged in LDS by coalesced loads (each column's
+// chunk is one or two 128-byte lines), with W_C's chunk beside it: W_C is
+// then read once per 64 columns instead of once per 16.  The next chunk's
+// loads are in flight while the current chunk's MFMA steps run.  Wavefront
+// v computes the 16-column block v for every candidate block.
+constexpr int XT_COLS = 64, XT_KC = 32, XT_GROUP = 8;
+template <typename T> struct LdsPad { static constexpr int P = sizeof(T) == 8 ? 34 : 36; };
+
+template <typename T>
+__device__ inline void lds_read4(const T* p, T (&v)[4]) {
+  if constexpr (sizeof(T) == 8) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 a = ((const d2*)p)[0], b = ((const d2*)p)[1];
+    v[0] = a[0];
+    v[1] = a[1];
+    v[2] = b[0];
+    v[3] = b[1];
+  } else {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 a = *(const f4*)p;
+    v[0] = a[0];
+    v[1] = a[1];
+    v[2] = a[2];
+    v[3] = a[3];
+  }
+}
+
+// Eight consecutive elements p[i0 .. i0+7] (i0 a multiple of 8, 16-byte
+// aligned), those at or past n read as zero unless the caller knows them all
+// valid (full).
+template <typename T, typename P>
+__device__ inline void load8_row(P p, int i0, int n, bool full, T (&v)[8]) {
+  T a[4], b[4];
+  load4_row(p, i0, n, full, a);
+  load4_row(p, i0 + 4, n, full, b);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    v[u] = a[u];
+    v[4 + u] = b[u];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cand_xt(const View<T>* __restrict__ vs) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int P = LdsPad<T>::P;
+  const View<T>& w = vs[blockIdx.z];
+  const Ctl* c = w.ctl;
+  if (!c->active) return;
+  const int nC = uni(c->nC), k0 = uni(c->k0);
+  if (nC == 0) return;
+  const int sp = blockIdx.y;
+  const auto N = gp(w.N[sp]);
+  const auto Wm = gp(w.W[sp]);
+  const auto R = gp(w.R[sp]);
+  const auto cand_el = gp(w.cand_el);
+  const size_t ld = uni((long long)w.ld), cap = uni((long long)w.cap);
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nRB = (nC + 15) >> 4;
+  __shared__ __attribute__((aligned(16))) T Ns[XT_COLS * P];
+  __shared__ __attribute__((aligned(16))) T Ws[KS_MAX * P];
+  // loader role: column (and candidate row) t / 4, chunk rows 8 (t % 4) .. + 7
+  const int lc = t >> 2, lr = (t & 3) * 8;
+  const bool wrow = lc < nC;
+  const auto wsrc = Wm + (size_t)(wrow ? lc : 0) * cap;
+  for (int j0 = blockIdx.x * XT_COLS; j0 < k0; j0 += gridDim.x * XT_COLS) {
+    const bool jin = j0 + lc < k0;
+    const auto nsrc = N + (size_t)(jin ? j0 + lc : 0) * ld;
+    // two-level sums: the MFMA steps of XT_GROUP chunks accumulate in acc,
+    // which is then added to tot (in FP32 a single chain over an order of
+    // thousands would carry k/4 roundings per entry)
+    acc_t acc[4], tot[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[rb] = tot[rb] = acc_t{0, 0, 0, 0};
+    T nv[8], wr[8];
+    auto fetch = [&](int i0) {
+      const bool full = i0 + XT_KC <= k0;
+      load8_row(nsrc, i0 + lr, k0, full, nv);
+      load8_row(wsrc, i0 + lr, k0, full, wr);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        nv[u] = jin ? nv[u] : (T)0;
+        wr[u] = wrow ? wr[u] : (T)0;
+      }
+    };
+    fetch(0);
+    for (int i0 = 0; i0 < k0; i0 += XT_KC) {
+      __syncthreads();      // the previous chunk's LDS reads are done
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        Ns[lc * P + lr + u] = nv[u];
+        Ws[lc * P + lr + u] = wr[u];
+      }
+      __syncthreads();
+      if (i0 + XT_KC < k0) fetch(i0 + XT_KC);
+#pragma unroll
+      for (int kb = 0; kb < XT_KC / 16; ++kb) {
+        // step s pairs chunk row 16 kb + 4 lk + s with k-slot lk (any
+        // bijection of rows onto k-slots sums the same terms)
+        T b4[4];
+        lds_read4(&Ns[(wv * 16 + li) * P + kb * 16 + 4 * lk], b4);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          if (rb < nRB) {
+            T a4[4];
+            lds_read4(&Ws[(rb * 16 + li) * P + kb * 16 + 4 * lk], a4);
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) acc[rb] = Mfma<T>::run(a4[s2], b4[s2], acc[rb]);
+          }
+        }
+      }
+      if ((i0 / XT_KC) % XT_GROUP == XT_GROUP - 1) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          tot[rb] += acc[rb];
+          acc[rb] = acc_t{0, 0, 0, 0};
+        }
+      }
+    }
+    const int j = j0 + wv * 16 + li;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      if (rb < nRB) {
+        tot[rb] += acc[rb];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int cr = rb * 16 + Mfma<T>::row(lane, r);
+          if (cr < nC && j < k0) R[(size_t)cand_el[cr] * cap + j] = tot[rb][r];
+        }
+      }
+    }
+    __syncthreads();        // LDS is rewritten by the next column tile
+  }
+}
+
 // -------------------------------------------------------------- Gram
 // The column-scaled Gamma of the window elements, both spins, in FP64:
 //   Gt_{x,y} = -Delta_y G_{x,y} + delta_xy (1 + Delta_y),  G = N_ext g,
@@ -489,7 +633,7 @@ __global__ void __launch_bounds__(NW * 64) k_gram_rows(const View<T>* __restrict
   // entries per pass in flight and a partial sum per step (the last pass
   // weighs the steps beyond the order zero)
   constexpr int MAXC = (KS_MAX + GWV - 1) / GWV;
-  const auto gcol = gp(w.gcol);
+  const auto gcol = gp(w.gcol[sp]);
   const size_t cap = w.cap;
   for (int x = blockIdx.x; x < nE; x += gridDim.x) {
     const int cx = w.el_cand[x];
@@ -536,7 +680,7 @@ __global__ void __launch_bounds__(NW * 64) k_gram_rows(const View<T>* __restrict
       if (lane == 0 && cc < nC) {
         const int ec = w.cand_el[cc];
         const double Dc = w.ev[sp][s01(w.el_s[ec])] - 1.0;
-        const double g = s + (cx >= 0 ? w.gCC[cx * KS_MAX + cc] : 0.0);
+        const double g = s + (cx >= 0 ? w.gCC[sp][cx * KS_MAX + cc] : 0.0);
         G[ec] = -Dc * g + (ec == x ? 1.0 + Dc : 0.0);
       }
     }
@@ -563,7 +707,7 @@ __global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs
   const int li = lane & 15, lk = lane >> 4;
   const int nRB = (nE + 15) >> 4;
   const auto R = gp(w.R[sp]);
-  const auto gcol = gp(w.gcol);
+  const auto gcol = gp(w.gcol[sp]);
   const auto G = gp(w.gram[sp]);
   __shared__ acc_t red[GWV][4][64];
   // candidate columns: R (nE x k0) times gcol^T (k0 x 16 candidates) on the
@@ -632,7 +776,7 @@ __global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs
         const int x = rb * 16 + Mfma<double>::row(lane, r);
         if (x < nE) {
           const int cx = w.el_cand[x];
-          const double g = sum[r] + (cx >= 0 ? w.gCC[cx * KS_MAX + cc] : 0.0);
+          const double g = sum[r] + (cx >= 0 ? w.gCC[sp][cx * KS_MAX + cc] : 0.0);
           G[x * KS_MAX + ec] = -Dc * g + (ec == x ? 1.0 + Dc : 0.0);
         }
       }
@@ -1158,7 +1302,7 @@ __global__ void __launch_bounds__(NW * 64) k_ygemm(const View<T>* __restrict__ v
   const int ncb = (mi + 15) >> 4;
   // the inserted spins' columns g_{I,c}; absent columns read a zero column
   // offset of -1 (never dereferenced)
-  const auto gcol = gp(w.gcol);
+  const auto gcol = gp(w.gcol[sp]);
   long long goff[4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
@@ -1235,6 +1379,101 @@ __global__ void __launch_bounds__(NW * 64) k_ygemm(const View<T>* __restrict__ v
       }
     }
     __syncthreads();      // red is rewritten by the next tile
+  }
+}
+
+// Y columns for launches with many workgroups: a workgroup owns 64 rows of
+// Y and runs over the inner dimension in chunks of 32 columns of N (a
+// column's 64 rows are two or four 128-byte lines, loaded coalesced),
+// staged in LDS transposed beside the chunk of the inserted spins' g
+// columns, which are then read once per 64 rows instead of once per 16.  Wavefront v computes
+// rows 16 v .. 16 v + 15 of the tile for every block of inserted spins.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ygemm_t(const View<T>* __restrict__ vs) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int P = LdsPad<T>::P;
+  const View<T>& w = vs[blockIdx.z];
+  const Ctl* c = w.ctl;
+  if (!c->active) return;
+  const int mi = uni(c->mi), k0 = uni(c->k0);
+  if (mi == 0) return;
+  const int sp = blockIdx.y;
+  const auto N = gp(w.N[sp]);
+  const auto Y = gp(w.Y[sp]);
+  const auto gcol = gp(w.gcol[sp]);
+  const size_t ld = uni((long long)w.ld), cap = uni((long long)w.cap);
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ncb = (mi + 15) >> 4;
+  __shared__ __attribute__((aligned(16))) T Ns[64 * P];        // [row][chunk column]
+  __shared__ __attribute__((aligned(16))) T Gs[KS_MAX * P];    // [inserted spin][chunk column]
+  // loader roles: N column t / 8 of the chunk, tile rows 8 (t % 8) .. + 7;
+  // g column of inserted spin t / 4, chunk columns 8 (t % 4) .. + 7
+  const int nj = t >> 3, nr = (t & 7) * 8;
+  const int gc = t >> 2, gj = (t & 3) * 8;
+  const bool gin = gc < mi;
+  const auto gsrc = gcol + (gin ? (size_t)w.el_cand[w.ins_el[gc]] * cap : (size_t)0);
+  for (int r0 = blockIdx.x * 64; r0 < k0; r0 += gridDim.x * 64) {
+    acc_t acc[4], tot[4];     // two-level sums, as in the candidate rows
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = tot[cb] = acc_t{0, 0, 0, 0};
+    T nv[8], gv[8];
+    auto fetch = [&](int j0) {
+      const int jj = j0 + nj;
+      const bool jin = jj < k0;
+      load8_row(N + (size_t)(jin ? jj : 0) * ld, r0 + nr, k0, r0 + 64 <= k0, nv);
+      load8_row(gsrc, j0 + gj, k0, j0 + XT_KC <= k0, gv);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        nv[u] = jin ? nv[u] : (T)0;
+        gv[u] = gin ? gv[u] : (T)0;
+      }
+    };
+    fetch(0);
+    for (int j0 = 0; j0 < k0; j0 += XT_KC) {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        Ns[(nr + u) * P + nj] = nv[u];
+        Gs[gc * P + gj + u] = gv[u];
+      }
+      __syncthreads();
+      if (j0 + XT_KC < k0) fetch(j0 + XT_KC);
+#pragma unroll
+      for (int kb = 0; kb < XT_KC / 16; ++kb) {
+        T a4[4];
+        lds_read4(&Ns[(wv * 16 + li) * P + kb * 16 + 4 * lk], a4);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          if (cb < ncb) {
+            T b4[4];
+            lds_read4(&Gs[(cb * 16 + li) * P + kb * 16 + 4 * lk], b4);
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) acc[cb] = Mfma<T>::run(a4[s2], b4[s2], acc[cb]);
+          }
+        }
+      }
+      if ((j0 / XT_KC) % XT_GROUP == XT_GROUP - 1) {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          tot[cb] += acc[cb];
+          acc[cb] = acc_t{0, 0, 0, 0};
+        }
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      if (cb < ncb) {
+        tot[cb] += acc[cb];
+        const int cc = cb * 16 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = r0 + wv * 16 + Mfma<T>::row(lane, r);
+          if (i < k0 && cc < mi) Y[(size_t)cc * cap + i] = tot[cb][r];
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1511,6 +1750,8 @@ __global__ void __launch_bounds__(WG) k_compact_move(const View<T>* __restrict__
   template __global__ void k_accept<T>(const View<T>*);                  \
   template __global__ void k_ygemm<T, 4>(const View<T>*);                \
   template __global__ void k_ygemm<T, 8>(const View<T>*);                \
+  template __global__ void k_ygemm_t<T>(const View<T>*);                 \
+  template __global__ void k_cand_xt<T>(const View<T>*);                 \
   template __global__ void k_fold_prep<T>(const View<T>*);               \
   template __global__ void k_fold<T>(const View<T>*);                    \
   template __global__ void k_compact_move<T>(const View<T>*);

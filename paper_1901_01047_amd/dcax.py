@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdcax.so")
 
 DCAX_ABI_VERSION = 1
 DCAX_FP64 = 0
+DCAX_VARIANT_AUTO, DCAX_VARIANT_TILED, DCAX_VARIANT_WIDE, DCAX_VARIANT_NARROW = 0, 1, 2, 3
 DCAX_FP32_MIXED = 1
 
 STATUS = {0: "DCAX_OK", -1: "DCAX_E_INVAL", -2: "DCAX_E_NOMEM", -3: "DCAX_E_HIP", -4: "DCAX_E_NUMERIC",
@@ -36,7 +37,9 @@ class Params(ctypes.Structure):
                 ("beta", ctypes.c_double), ("mu", ctypes.c_double), ("K_exp", ctypes.c_double),
                 ("n_tau", ctypes.c_int32), ("precision", ctypes.c_int32), ("submatrix_k", ctypes.c_int32),
                 ("refresh_every", ctypes.c_int32), ("max_order", ctypes.c_int32), ("n_freq", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("warmup_sweeps", ctypes.c_int32), ("sweep_length", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("warmup_sweeps", ctypes.c_int32), ("sweep_length", ctypes.c_int32),
+                ("n_spin_tables", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("g0_tau", ctypes.c_void_p), ("g0_Kw", ctypes.c_void_p)]
 
 
 class Vertex(ctypes.Structure):
@@ -82,7 +85,7 @@ EXPORTS = ("dcax_walker_create", "dcax_walker_destroy", "dcax_sweep", "dcax_refr
            "dcax_sweep_measure", "dcax_run_rounds", "dcax_measure_nfft", "dcax_sweep_measure_nfft",
            "dcax_nfft_transform",
            "dcax_finalize_G", "dcax_get_order", "dcax_copy_N", "dcax_get_config", "dcax_set_config",
-           "dcax_set_submatrix_k", "dcax_autotune", "dcax_set_graphs", "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table",
+           "dcax_set_submatrix_k", "dcax_autotune", "dcax_set_graphs", "dcax_set_variants", "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table",
            "dcax_cluster", "dcax_last_error")
 
 _lib = None
@@ -116,6 +119,7 @@ def load():
         "dcax_set_submatrix_k": [vp, ctypes.c_int32, ctypes.c_int32],
         "dcax_autotune": [vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_double)],
         "dcax_set_graphs": [vp, ctypes.c_int32],
+        "dcax_set_variants": [vp, ctypes.c_int32, ctypes.c_int32],
         "dcax_copy_g0_table": [vp, ctypes.c_int32, vp],
         "dcax_cluster": [P(Params), P(ctypes.c_int32), vp, vp],
     }
@@ -136,7 +140,12 @@ def _check(st):
 
 def make_params(cluster=(2, 0, 0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0, K_exp=1.0, n_tau=1000,
                 precision=DCAX_FP64, submatrix_k=16, refresh_every=0, max_order=512, n_freq=64,
-                seed=985456376, warmup_sweeps=20, sweep_length=0):
+                seed=985456376, warmup_sweeps=20, sweep_length=0, g0_tau=None, g0_Kw=None):
+    """g0_tau: optional bare propagator tables, float64 [n_spin_tables][Nc][n_tau]
+    (or [Nc][n_tau] for one table) in the standard convention; g0_Kw: optional
+    complex128 [n_spin_tables][Nc][n_freq] G0(K, i w_n) for finalize.  The
+    arrays are kept alive with the returned Params (the library copies them
+    when a Walker is created)."""
     p = Params()
     p.abi_version = DCAX_ABI_VERSION
     for i in range(4):
@@ -145,6 +154,27 @@ def make_params(cluster=(2, 0, 0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0, K_
     p.n_tau, p.precision, p.submatrix_k = n_tau, precision, submatrix_k
     p.refresh_every, p.max_order, p.n_freq, p.seed = refresh_every, max_order, n_freq, seed
     p.warmup_sweeps, p.sweep_length = warmup_sweeps, sweep_length
+    keep = []
+    if g0_tau is not None:
+        t = np.ascontiguousarray(g0_tau, dtype=np.float64)
+        if t.ndim == 2:
+            t = t[None]
+        if t.ndim != 3 or t.shape[0] not in (1, 2) or t.shape[2] != n_tau:
+            raise ValueError("g0_tau must be [n_spin_tables][Nc][n_tau] with n_spin_tables 1 or 2")
+        p.n_spin_tables = t.shape[0]
+        p.g0_tau = t.ctypes.data
+        keep.append(t)
+        if g0_Kw is not None:
+            g = np.ascontiguousarray(g0_Kw, dtype=np.complex128)
+            if g.ndim == 2:
+                g = g[None]
+            if g.shape[0] != t.shape[0] or g.shape[1] != t.shape[1] or g.shape[2] != n_freq:
+                raise ValueError("g0_Kw must be [n_spin_tables][Nc][n_freq] complex")
+            p.g0_Kw = g.ctypes.data
+            keep.append(g)
+    elif g0_Kw is not None:
+        raise ValueError("g0_Kw needs g0_tau")
+    p._keep = keep
     return p
 
 
@@ -287,6 +317,11 @@ class Walker:
 
     def set_graphs(self, on=True):
         _check(load().dcax_set_graphs(self._h, 1 if on else 0))
+
+    def set_variants(self, cand_rows=0, y_columns=0):
+        """Kernel forms of the candidate-row and Y-column products: 0 auto,
+        1 tiled (LDS), 2 wide, 3 narrow (see dcax_set_variants)."""
+        _check(load().dcax_set_variants(self._h, int(cand_rows), int(y_columns)))
 
     def set_timing(self, on=True):
         """on: True / 1 times every window, n > 1 a pseudo-random 1/n of them, 0 / False stops."""

@@ -70,6 +70,27 @@ def test_create_rejects_bad_params(lib, field, value):
     assert len(lib.dcax_last_error()) > 0
 
 
+def test_create_rejects_bad_propagator_tables(lib):
+    """Caller-supplied G0 tables: n_spin_tables outside 0..2, tables missing
+    or given without a count, and a nonzero reserved word are argument
+    errors, answered before any device work."""
+    h = ctypes.c_void_p()
+    tab = np.zeros((1, 4, 1000))
+    for mutate in (lambda p: setattr(p, "n_spin_tables", 3),
+                   lambda p: setattr(p, "n_spin_tables", 1),                      # no table
+                   lambda p: setattr(p, "g0_tau", tab.ctypes.data),              # table, count 0
+                   lambda p: setattr(p, "reserved", 1)):
+        p = dcax.make_params()
+        mutate(p)
+        assert lib.dcax_walker_create(ctypes.byref(p), 1, None, None, ctypes.byref(h)) == -1 and not h.value
+    with pytest.raises(ValueError):
+        dcax.make_params(g0_tau=np.zeros((3, 4, 1000)))
+    with pytest.raises(ValueError):
+        dcax.make_params(g0_Kw=np.zeros((4, 64), complex))
+    p = dcax.make_params(g0_tau=np.zeros((2, 4, 1000)), g0_Kw=np.zeros((2, 4, 64), complex))
+    assert p.n_spin_tables == 2 and p.g0_tau and p.g0_Kw
+
+
 def test_create_rejects_degenerate_cluster_and_batch(lib):
     p = dcax.make_params(cluster=(2, 2, 1, 1))
     h = ctypes.c_void_p()

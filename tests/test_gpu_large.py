@@ -5,7 +5,9 @@ and precision the benchmark uses.  The oracle records a short trace (two
 windows at 6x6; one window and a quarter at 8x8) from the benchmark's kind
 of starting configuration (sites and times uniform, one auxiliary spin per
 site: workloads.initial_config); the library replays it with forced
-decisions, and every ratio and the final N are compared with the oracle's.
+decisions, and every ratio and the final N are compared with the oracle's,
+with the candidate products in the form the launch size picks (a single
+walker: split inner dimension) and in the LDS-tiled form batches use.
 
 These states are well conditioned (cond N^{-1} ~ 1e5-1e6; uniformly random
 auxiliary spins would give 1e10-1e11, see initial_config): the median first-
@@ -52,8 +54,12 @@ def test_large_replay_parity(name, n_rec):
     ids_o, Nu, Nd = ow.canonical()
     k_end = len(ids_o)
     out = {}
-    for prec, tag in ((dcax.DCAX_FP64, "fp64"), (dcax.DCAX_FP32_MIXED, "mixed")):
+    legs = [(dcax.DCAX_FP64, "fp64", 0), (dcax.DCAX_FP32_MIXED, "mixed", 0),
+            (dcax.DCAX_FP64, "fp64 tiled", dcax.DCAX_VARIANT_TILED),
+            (dcax.DCAX_FP32_MIXED, "mixed tiled", dcax.DCAX_VARIANT_TILED)]
+    for prec, tag, variant in legs:
         w = dcax.Walker(dcax.make_params(**params_kwargs(name), precision=prec))
+        w.set_variants(variant, variant)
         w.set_config(*init)
         ratios = w.replay(rec)
         err = np.abs(ratios[good] - ro)
@@ -71,11 +77,12 @@ def test_large_replay_parity(name, n_rec):
               f"({100 * within:.1f}% within 1e-10), max err/(eps b) {unit:.1f}; N normwise {nerr:.2e}; "
               f"k = {k_end}; decision mismatches {w.stats()['decision_mismatches']}", flush=True)
         w.close()
-    rel, unit, nerr, mis = out["fp64"]
-    assert mis == 0
-    assert rel.max() <= 1e-10 and nerr <= 1e-10
-    rel32, _, nerr32, _ = out["mixed"]
-    scale = np.finfo(np.float32).eps / EPS
-    assert rel32.max() <= 1e-3 and nerr32 <= 1e-5
-    assert rel32.max() <= 10 * scale * max(rel.max(), 10 * EPS)
-    assert nerr32 <= 10 * scale * max(nerr, 10 * EPS)
+    for suffix in ("", " tiled"):
+        rel, unit, nerr, mis = out["fp64" + suffix]
+        assert mis == 0
+        assert rel.max() <= 1e-10 and nerr <= 1e-10
+        rel32, _, nerr32, _ = out["mixed" + suffix]
+        scale = np.finfo(np.float32).eps / EPS
+        assert rel32.max() <= 1e-3 and nerr32 <= 1e-5
+        assert rel32.max() <= 10 * scale * max(rel.max(), 10 * EPS)
+        assert nerr32 <= 10 * scale * max(nerr, 10 * EPS)

@@ -130,13 +130,17 @@ def check_replay(m, init, rec, ratios_o, ow, ratios, w, tol=1e-10):
     return rel_x.max(), max(errs)
 
 
+@pytest.mark.parametrize("variant", [0, dcax.DCAX_VARIANT_TILED, dcax.DCAX_VARIANT_NARROW])
 @pytest.mark.parametrize("name,k_s,k_init,warm,n_rec", REPLAY_CASES)
-def test_replay_parity(name, k_s, k_init, warm, n_rec):
-    print(f"[replay] {name} k_s={k_s} k_init={k_init} n={n_rec}", flush=True)
+def test_replay_parity(name, k_s, k_init, warm, n_rec, variant):
+    """Each case with the candidate products in the form its launch size
+    picks and in the two other forms (every form must reach the oracle)."""
+    print(f"[replay] {name} k_s={k_s} k_init={k_init} n={n_rec} variant {variant}", flush=True)
     m = model(name)
     init, rec, ratios_o, ow = oracle_trace(m, seed=CONFIGS[name]["seed"], k_s=k_s, init_order=k_init,
                                            warm_sweeps=warm, rec_proposals=n_rec)
     w = walker(name, submatrix_k=k_s)
+    w.set_variants(variant, variant)
     w.set_config(*init)
     ratios = w.replay(rec)
     check_replay(m, init, rec, ratios_o, ow, ratios, w)
