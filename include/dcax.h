@@ -202,6 +202,19 @@ dcax_status dcax_walker_destroy(dcax_walker w);
 dcax_status dcax_sweep(dcax_walker w, int32_t n_sweeps, const dcax_proposal* replay,
                        int64_t n_replay, double* ratio_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the replay
+ * of dcax_sweep (same records, same kernels, same ratios and N), with the
+ * records and their ratios staged in a fixed device buffer the library holds
+ * on each GPU (DCAX_REPLAY_STATIC_MAX records, 3 MiB, kept until the process
+ * ends) instead of memory from the walker's allocator, which dcax_sweep's
+ * replay obtains on first use and grows.  n_replay above the limit answers
+ * DCAX_E_INVAL before any work.  Every call on one GPU shares that buffer:
+ * calls that overlap (other threads or streams of the same GPU) race. */
+#define DCAX_REPLAY_STATIC_MAX 65536
+dcax_status dcax_sweep_replay_static(dcax_walker w, const dcax_proposal* replay, int64_t n_replay,
+                                     double* ratio_out);
+
 /* Rebuild N_sigma = [e^V - g (e^V - 1)]^{-1} of every walker from scratch in
  * FP64 (gathers plus Gauss-Jordan inversion with partial pivoting).
  * drift_out (nullable) receives max|N_before - N_after| / max|N_after|, the

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -23,6 +24,16 @@
 #include "dcax_nfft.hip"
 
 using namespace dcax;
+
+// Staging for dcax_sweep_replay_static: replayed records, then their ratios,
+// for at most DCAX_REPLAY_STATIC_MAX records, in a fixed device array rather
+// than memory from the caller's allocator.  Each GPU holds its own copy until
+// the process ends.  On the host the array's name is not a device address:
+// host code uses the address hipGetSymbolAddress returns on each device.
+constexpr size_t STATIC_REC_BYTES = sizeof(dcax_proposal) * (size_t)DCAX_REPLAY_STATIC_MAX;
+constexpr size_t STATIC_SCRATCH_BYTES = STATIC_REC_BYTES + sizeof(double) * (size_t)DCAX_REPLAY_STATIC_MAX;
+static_assert(STATIC_REC_BYTES % 256 == 0, "the ratios start 256-byte aligned");
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -40,6 +51,28 @@ dcax_status fail(dcax_status s, const std::string& msg) {
   } while (0)
 
 int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the walkers of several threads may be created at once).
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;
+
+void* static_scratch_of_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) ptr = nullptr;
+  g_scratch_addr[dev] = ptr;
+  return ptr;
+}
+
+__global__ void k_fill_zero(double* p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
 
 // ------------------------------------------------------------- geometry
 // Cluster sites and momenta from the superlattice vectors (enumeration rule
@@ -250,6 +283,10 @@ struct dcax_walker_s {
   dcax_proposal* replay_d = nullptr;
   double* ratio_d = nullptr;
   long long replay_cap = 0;
+  // the static staging of this walker's GPU (dcax_sweep_replay_static), and
+  // the record buffer the device views currently point at
+  void* static_scratch = nullptr;
+  const dcax_proposal* views_replay = nullptr;
   long long sweeps_done = 0;
   double last_drift = 0.0, max_drift = 0.0;
   // sweeps replayed as hipGraphs (dcax_set_graphs).  Events recorded inside
@@ -1026,12 +1063,12 @@ dcax_status sweep_rounds(dcax_walker w, int n, double* acc, double* aux, long lo
 }
 
 template <typename T>
-dcax_status repoint_replay(dcax_walker w) {
+dcax_status repoint_replay(dcax_walker w, dcax_proposal* rec, double* rat) {
   std::vector<View<T>> hv(w->W);
   for (int i = 0; i < w->W; ++i) {
     View<T>& v = hview<T>(w->wk[i]);
-    v.replay = w->replay_d;
-    v.ratio_out = w->ratio_d;
+    v.replay = rec;
+    v.ratio_out = rat;
     hv[i] = v;
   }
   HIPCHK(hipMemcpyAsync(w->d_views, hv.data(), sizeof(View<T>) * w->W, hipMemcpyHostToDevice, w->stream));
@@ -1124,6 +1161,7 @@ dcax_status dcax_walker_create(const dcax_params* p, int32_t n_walkers, const dc
   }
   w->acc_total = acc;
   w->nc_total = ncp;
+  w->static_scratch = static_scratch_of_current_device();
   dcax_status st = w->mixed ? create_walkers<float>(w) : create_walkers<double>(w);
   if (st != DCAX_OK) {
     (void)hipStreamSynchronize(w->stream);
@@ -1199,54 +1237,96 @@ dcax_status dcax_set_config(dcax_walker w, int32_t walker, const dcax_vertex* v,
   return sync_all(w);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Host checks of replay records (argument errors, nothing enqueued).
+dcax_status check_replay(dcax_walker w, const dcax_proposal* replay, int64_t n_replay) {
+  if (w->W != 1) return fail(DCAX_E_INVAL, "replay needs a single-walker handle");
+  if (n_replay < 0) return fail(DCAX_E_INVAL, "n_replay < 0");
+  const WalkerHost& x = w->wk[0];
+  for (int64_t i = 0; i < n_replay; ++i) {
+    const dcax_proposal& r = replay[i];
+    if (r.kind != 0 && r.kind != 1) return fail(DCAX_E_INVAL, "replay kind must be 0 or 1");
+    if (r.accepted != 0 && r.accepted != 1) return fail(DCAX_E_INVAL, "replay accepted must be 0 or 1");
+    if (r.kind == 0) {
+      if (r.site < 0 || r.site >= x.geo.Nc) return fail(DCAX_E_INVAL, "replay site out of range");
+      if (r.aux_spin != 1 && r.aux_spin != -1) return fail(DCAX_E_INVAL, "replay aux_spin must be +1 or -1");
+      if (!(r.tau >= 0.0 && r.tau < x.p.beta)) return fail(DCAX_E_INVAL, "replay tau outside [0, beta)");
+      if (r.accepted && r.id < 0) return fail(DCAX_E_INVAL, "accepted insertion needs an id >= 0");
+    } else if (r.id < 0 && r.accepted) {
+      return fail(DCAX_E_INVAL, "a removal without target cannot be accepted");
+    }
+  }
+  return DCAX_OK;
+}
+
+// Replays n_replay records staged at rec (device) with forced decisions; the
+// ratios land at rat (device, cleared first) and are copied to ratio_out.
+dcax_status replay_staged(dcax_walker w, const dcax_proposal* replay, int64_t n_replay, double* ratio_out,
+                          dcax_proposal* rec, double* rat) {
+  if (w->views_replay != rec) {
+    dcax_status st = w->mixed ? repoint_replay<float>(w, rec, rat) : repoint_replay<double>(w, rec, rat);
+    if (st != DCAX_OK) return st;
+    w->views_replay = rec;
+  }
+  const WalkerHost& x = w->wk[0];
+  HIPCHK(hipMemcpyAsync(rec, replay, sizeof(dcax_proposal) * n_replay, hipMemcpyHostToDevice, w->stream));
+  hipLaunchKernelGGL(k_fill_zero, dim3(std::min(cdiv(n_replay, WG), 256)), dim3(WG), 0, w->stream, rat,
+                     (long long)n_replay);
+  if (w->mixed) hipLaunchKernelGGL(k_set_cursor<float>, dim3(1), dim3(1), 0, w->stream, w->views<float>(), 0LL, (long long)n_replay);
+  else hipLaunchKernelGGL(k_set_cursor<double>, dim3(1), dim3(1), 0, w->stream, w->views<double>(), 0LL, (long long)n_replay);
+  const long long nwin = (n_replay + x.ks - 1) / x.ks;
+  int kb = x.k_host;
+  for (long long i = 0; i < nwin; ++i) {
+    kb = std::min(x.max_order, kb + x.ks);
+    if (w->mixed) enqueue_window<float>(w, kb, true);
+    else enqueue_window<double>(w, kb, true);
+  }
+  HIPCHK(hipGetLastError());
+  if (ratio_out) HIPCHK(hipMemcpyAsync(ratio_out, rat, sizeof(double) * n_replay, hipMemcpyDeviceToHost, w->stream));
+  return sync_all(w);
+}
+
+}  // namespace
+
+extern "C" {
+
 dcax_status dcax_sweep(dcax_walker w, int32_t n_sweeps, const dcax_proposal* replay, int64_t n_replay,
                        double* ratio_out) {
   dcax_status st = check_latched(w);
   if (st != DCAX_OK) return st;
   if (replay) {
-    if (w->W != 1) return fail(DCAX_E_INVAL, "replay needs a single-walker handle");
-    if (n_replay < 0) return fail(DCAX_E_INVAL, "n_replay < 0");
-    if (n_replay == 0) return DCAX_OK;
-    const WalkerHost& x = w->wk[0];
-    for (int64_t i = 0; i < n_replay; ++i) {
-      const dcax_proposal& r = replay[i];
-      if (r.kind != 0 && r.kind != 1) return fail(DCAX_E_INVAL, "replay kind must be 0 or 1");
-      if (r.accepted != 0 && r.accepted != 1) return fail(DCAX_E_INVAL, "replay accepted must be 0 or 1");
-      if (r.kind == 0) {
-        if (r.site < 0 || r.site >= x.geo.Nc) return fail(DCAX_E_INVAL, "replay site out of range");
-        if (r.aux_spin != 1 && r.aux_spin != -1) return fail(DCAX_E_INVAL, "replay aux_spin must be +1 or -1");
-        if (!(r.tau >= 0.0 && r.tau < x.p.beta)) return fail(DCAX_E_INVAL, "replay tau outside [0, beta)");
-        if (r.accepted && r.id < 0) return fail(DCAX_E_INVAL, "accepted insertion needs an id >= 0");
-      } else if (r.id < 0 && r.accepted) {
-        return fail(DCAX_E_INVAL, "a removal without target cannot be accepted");
-      }
-    }
+    st = check_replay(w, replay, n_replay);
+    if (st != DCAX_OK || n_replay == 0) return st;
     if (n_replay > w->replay_cap) {
       const long long cap = std::max<long long>(n_replay, 4096);
       w->replay_d = (dcax_proposal*)w->dalloc(sizeof(dcax_proposal) * cap);
       w->ratio_d = (double*)w->dalloc(sizeof(double) * cap);
       if (!w->replay_d || !w->ratio_d) return fail(DCAX_E_NOMEM, "replay buffer allocation failed");
       w->replay_cap = cap;
-      st = w->mixed ? repoint_replay<float>(w) : repoint_replay<double>(w);
-      if (st != DCAX_OK) return st;
     }
-    HIPCHK(hipMemcpyAsync(w->replay_d, replay, sizeof(dcax_proposal) * n_replay, hipMemcpyHostToDevice, w->stream));
-    if (w->mixed) hipLaunchKernelGGL(k_set_cursor<float>, dim3(1), dim3(1), 0, w->stream, w->views<float>(), 0LL, (long long)n_replay);
-    else hipLaunchKernelGGL(k_set_cursor<double>, dim3(1), dim3(1), 0, w->stream, w->views<double>(), 0LL, (long long)n_replay);
-    const long long nwin = (n_replay + x.ks - 1) / x.ks;
-    int kb = x.k_host;
-    for (long long i = 0; i < nwin; ++i) {
-      kb = std::min(x.max_order, kb + x.ks);
-      if (w->mixed) enqueue_window<float>(w, kb, true);
-      else enqueue_window<double>(w, kb, true);
-    }
-    HIPCHK(hipGetLastError());
-    if (ratio_out)
-      HIPCHK(hipMemcpyAsync(ratio_out, w->ratio_d, sizeof(double) * n_replay, hipMemcpyDeviceToHost, w->stream));
-    return sync_all(w);
+    return replay_staged(w, replay, n_replay, ratio_out, w->replay_d, w->ratio_d);
   }
   if (n_sweeps < 0) return fail(DCAX_E_INVAL, "n_sweeps < 0");
   return sweep_rng(w, n_sweeps);
+}
+
+dcax_status dcax_sweep_replay_static(dcax_walker w, const dcax_proposal* replay, int64_t n_replay,
+                                     double* ratio_out) {
+  dcax_status st = check_latched(w);
+  if (st != DCAX_OK) return st;
+  if (!replay) return fail(DCAX_E_INVAL, "replay is NULL");
+  if (n_replay > DCAX_REPLAY_STATIC_MAX)
+    return fail(DCAX_E_INVAL, "n_replay exceeds DCAX_REPLAY_STATIC_MAX (" + std::to_string(DCAX_REPLAY_STATIC_MAX) +
+                                  " records)");
+  st = check_replay(w, replay, n_replay);
+  if (st != DCAX_OK || n_replay == 0) return st;
+  if (!w->static_scratch) return fail(DCAX_E_HIP, "the static replay staging has no device address on this GPU");
+  dcax_proposal* rec = (dcax_proposal*)w->static_scratch;
+  double* rat = (double*)((char*)w->static_scratch + STATIC_REC_BYTES);
+  return replay_staged(w, replay, n_replay, ratio_out, rec, rat);
 }
 
 dcax_status dcax_sweep_measure(dcax_walker w, int32_t n_sweeps, double* acc_dev, double* aux_dev) {

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdcax.so")
 
 DCAX_ABI_VERSION = 1
 DCAX_FP64 = 0
+REPLAY_STATIC_MAX = 65536     # dcax.h DCAX_REPLAY_STATIC_MAX
 DCAX_VARIANT_AUTO, DCAX_VARIANT_TILED, DCAX_VARIANT_WIDE, DCAX_VARIANT_NARROW = 0, 1, 2, 3
 DCAX_FP32_MIXED = 1
 
@@ -81,7 +82,7 @@ PROPOSAL_DTYPE = np.dtype([("kind", np.int32), ("site", np.int32), ("aux_spin", 
 VERTEX_DTYPE = np.dtype([("id", np.int64), ("site", np.int32), ("aux_spin", np.int32), ("tau", np.float64)])
 
 # exported symbols, in the order include/dcax.h declares them
-EXPORTS = ("dcax_walker_create", "dcax_walker_destroy", "dcax_sweep", "dcax_refresh", "dcax_measure_G",
+EXPORTS = ("dcax_walker_create", "dcax_walker_destroy", "dcax_sweep", "dcax_sweep_replay_static", "dcax_refresh", "dcax_measure_G",
            "dcax_sweep_measure", "dcax_run_rounds", "dcax_measure_nfft", "dcax_sweep_measure_nfft",
            "dcax_nfft_transform",
            "dcax_finalize_G", "dcax_get_order", "dcax_copy_N", "dcax_get_config", "dcax_set_config",
@@ -105,6 +106,7 @@ def load():
         "dcax_walker_create": [P(Params), ctypes.c_int32, P(Allocator), vp, P(vp)],
         "dcax_walker_destroy": [vp],
         "dcax_sweep": [vp, ctypes.c_int32, vp, ctypes.c_int64, vp],
+        "dcax_sweep_replay_static": [vp, vp, ctypes.c_int64, vp],
         "dcax_refresh": [vp, P(ctypes.c_double)],
         "dcax_measure_G": [vp, vp, vp],
         "dcax_sweep_measure": [vp, ctypes.c_int32, vp, vp],
@@ -254,6 +256,14 @@ class Walker:
         rec = np.ascontiguousarray(records, dtype=PROPOSAL_DTYPE)
         ratios = np.zeros(len(rec), np.float64)
         _check(load().dcax_sweep(self._h, 0, rec.ctypes.data, len(rec), ratios.ctypes.data))
+        return ratios
+
+    def replay_static(self, records):
+        """As replay, staging the records in the library's fixed per-GPU buffer
+        (no allocation; at most REPLAY_STATIC_MAX records per call)."""
+        rec = np.ascontiguousarray(records, dtype=PROPOSAL_DTYPE)
+        ratios = np.zeros(len(rec), np.float64)
+        _check(load().dcax_sweep_replay_static(self._h, rec.ctypes.data, len(rec), ratios.ctypes.data))
         return ratios
 
     def refresh(self):
