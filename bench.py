@@ -195,6 +195,7 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
         "refresh_max_drift": s1["max_drift"],
         "aborted_windows": s1["aborted_windows"] - s0["aborted_windows"],
         "submatrix_k": chosen_ks if chosen_ks else plist[0].submatrix_k,
+        "kernel_forms": list(w.variants()),
     }
     if graphs:
         # kernels inside a replayed graph cannot be timed one by one: the
@@ -231,7 +232,7 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
     return res, cfg_out
 
 
-def run_batch(precision, steps, warmup, n_walkers=512):
+def run_batch(precision, steps, warmup, n_walkers=512, graphs=False, autotune=0):
     """The batched workload: n_walkers walkers of uneven cluster size, U and
     beta in one handle (one launch per kernel covers all of them), free
     running (dcax_run_rounds): a step is one round of four windows per
@@ -243,7 +244,12 @@ def run_batch(precision, steps, warmup, n_walkers=512):
     plist = [dcax.make_params(**dict(d, warmup_sweeps=warmup), precision=prec, refresh_every=32)
              for d in batch_configs(n_walkers)]
     w = dcax.Walker(plist)
+    w.set_graphs(graphs)
     acc, aux = w.new_accumulator()
+    chosen = None
+    if autotune:
+        ks, _ = w.autotune(sweeps_per_trial=autotune)
+        chosen = {"submatrix_k": ks, "kernel_forms": list(w.variants())}
     t0 = time.perf_counter()
     w.sweep(warmup)
     torch.cuda.synchronize()
@@ -263,7 +269,8 @@ def run_batch(precision, steps, warmup, n_walkers=512):
            "order_min_mean_max": [min(orders), sum(orders) / len(orders), max(orders)],
            "mean_fold_rank": (s1["flips_folded"] - s0["flips_folded"]) / max(s1["windows"] - s0["windows"], 1),
            "fold_rank_distribution": fold_ranks(s0, s1),
-           "warmup_seconds": t_warm, "roofline": roofline(s0, s1, precision, "k_fold"),
+           "warmup_seconds": t_warm, "launch": "hipGraph per round" if graphs else "eager launches",
+           "autotuned": chosen, "roofline": roofline(s0, s1, precision, "k_fold"),
            "kernels": {k: roofline(s0, s1, precision, k) for k in ("k_cand_x", "k_ygemm")},
            "kernel_us_per_window": kernel_us(s0, s1)}
     w.close()
@@ -447,8 +454,8 @@ def main():
                         autotune=at, refresh_every=re)
         out["fp64_nfft_measurement"] = {k: v for k, v in rn.items() if k != "roofline"}
     if args.batch:
-        out["batch"] = {"fp64": run_batch("fp64", args.steps, args.warmup, args.batch),
-                        "fp32_mixed": run_batch("mixed", args.steps, args.warmup, args.batch)}
+        out["batch"] = {"fp64": run_batch("fp64", args.steps, args.warmup, args.batch, graphs, at),
+                        "fp32_mixed": run_batch("mixed", args.steps, args.warmup, args.batch, graphs, at)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, wl)
     print(json.dumps(out), flush=True)

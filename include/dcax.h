@@ -307,17 +307,24 @@ dcax_status dcax_nfft_transform(dcax_walker w, int32_t half_width, const double*
  * the submatrix size only groups proposals (Sec. 2.3, submatrix updates). */
 dcax_status dcax_set_submatrix_k(dcax_walker w, int32_t walker, int32_t ks);
 
-/* Autotuner for the submatrix size: runs sweeps_per_trial generator-mode
- * sweeps of the whole batch with each k_s in {8, 16, 24, 32, 48, 64}, timed
- * with HIP events, and keeps the k_s with the most accepted updates per
- * second (written to *chosen_ks, its rate to *rate_out; both nullable).  The
- * trial sweeps are ordinary Markov-chain sweeps (they count as warm-up). */
+/* Autotuner (App. A lists auto-tuning among the build options): runs
+ * sweeps_per_trial generator-mode sweeps of the whole batch with each k_s in
+ * {8, 16, 24, 32, 48, 64}, timed with HIP events, and keeps the k_s with the
+ * most accepted updates per second; then, with that k_s, tries each kernel
+ * form of the candidate-row product and then of the Y-column product (tiled,
+ * wide, narrow; dcax_set_variants) and keeps the fastest of each.  The chosen
+ * k_s is written to *chosen_ks and the best rate to *rate_out (both nullable);
+ * dcax_get_variants reports the chosen forms.  The trial sweeps are ordinary
+ * Markov-chain sweeps (they count as warm-up). */
 dcax_status dcax_autotune(dcax_walker w, int32_t sweeps_per_trial, int32_t* chosen_ks, double* rate_out);
 
 /* Replay generator-mode sweeps as hipGraphs (on != 0): one graph per
  * (order bound rounded up to 64, window count), captured on first use and
  * launched on a library-owned stream that is ordered after and before the
- * caller's stream with events.  Off by default.  With timing on, a replayed
+ * caller's stream with events.  The device-scheduled calls (dcax_sweep_measure,
+ * dcax_run_rounds, dcax_sweep_measure_nfft) then replay each round - sweep
+ * starts, windows, gated measurement - as one graph per (order bound,
+ * windows, accumulators).  Off by default.  With timing on, a replayed
  * sweep is timed as a whole (window_seconds); the fold and accept kernel
  * times of dcax_stats come from eagerly launched windows only. */
 dcax_status dcax_set_graphs(dcax_walker w, int32_t on);
@@ -338,6 +345,8 @@ dcax_status dcax_set_graphs(dcax_walker w, int32_t on);
 typedef enum { DCAX_VARIANT_AUTO = 0, DCAX_VARIANT_TILED = 1, DCAX_VARIANT_WIDE = 2,
                DCAX_VARIANT_NARROW = 3 } dcax_variant;
 dcax_status dcax_set_variants(dcax_walker w, int32_t cand_rows, int32_t y_columns);
+/* The forms in use (DCAX_VARIANT_AUTO until set or autotuned); both nullable. */
+dcax_status dcax_get_variants(dcax_walker w, int32_t* cand_rows, int32_t* y_columns);
 
 /* Introspection and checkpointing; `walker` indexes the batch (0-based). */
 dcax_status dcax_get_order(dcax_walker w, int32_t walker, int32_t* k);

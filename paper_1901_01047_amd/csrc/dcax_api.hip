@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <cstdio>
 #include <cstring>
@@ -298,6 +299,9 @@ struct dcax_walker_s {
   hipStream_t gstream = nullptr;         // library stream the graphs run on
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  // rounds of device-scheduled sweeps, keyed by (order bound, windows,
+  // delayed-NFFT half-width, accumulator, aux)
+  std::map<std::tuple<int, int, int, double*, double*>, hipGraphExec_t> round_graphs;
   bool capturing = false;
   // the host copies of the control blocks match the device (nothing that
   // changes a walker has been enqueued since the last sync_all)
@@ -323,6 +327,8 @@ struct dcax_walker_s {
   void clear_graphs() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
+    for (auto& kv : round_graphs) (void)hipGraphExecDestroy(kv.second);
+    round_graphs.clear();
   }
   void release() {
     clear_graphs();
@@ -657,35 +663,33 @@ void enqueue_sweep(dcax_walker w, int kb, int nwin) {
   }
 }
 
-// Replays the sweep as a hipGraph captured once per (order bound, window
-// count).  Graphs run on the library's own stream, ordered after and before
-// the caller's stream by events.
-dcax_status launch_sweep_graph(dcax_walker w, int kb, int nwin) {
-  w->fresh = false;
-  const int kq = std::min(w->mo_max, ((kb + 63) / 64) * 64);
-  const auto key = std::make_pair(kq, nwin);
-  auto it = w->graphs.find(key);
-  if (it == w->graphs.end()) {
-    if (!w->gstream) {
-      HIPCHK(hipStreamCreateWithFlags(&w->gstream, hipStreamNonBlocking));
-      HIPCHK(hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming));
-      HIPCHK(hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming));
-    }
-    hipGraphExec_t exec = nullptr;
-    hipStream_t user = w->stream;
-    HIPCHK(hipStreamBeginCapture(w->gstream, hipStreamCaptureModeThreadLocal));
-    w->stream = w->gstream;
-    w->capturing = true;
-    enqueue_sweep(w, kq, nwin);
-    w->capturing = false;
-    w->stream = user;
-    hipGraph_t graph = nullptr;
-    HIPCHK(hipStreamEndCapture(w->gstream, &graph));
-    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    HIPCHK(ie);
-    it = w->graphs.emplace(key, exec).first;
+// Captures what `enqueue` puts on the walker's stream as a graph on the
+// library's own stream.
+template <typename F>
+dcax_status capture_graph(dcax_walker w, F enqueue, hipGraphExec_t* exec) {
+  if (!w->gstream) {
+    HIPCHK(hipStreamCreateWithFlags(&w->gstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming));
   }
+  hipStream_t user = w->stream;
+  HIPCHK(hipStreamBeginCapture(w->gstream, hipStreamCaptureModeThreadLocal));
+  w->stream = w->gstream;
+  w->capturing = true;
+  enqueue();
+  w->capturing = false;
+  w->stream = user;
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamEndCapture(w->gstream, &graph));
+  const hipError_t ie = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(ie);
+  return DCAX_OK;
+}
+
+// Launches a captured graph on the library's stream, ordered after and
+// before the caller's stream by events (timed as a whole when timing is on).
+dcax_status launch_graph(dcax_walker w, hipGraphExec_t exec) {
   HIPCHK(hipEventRecord(w->ev_in, w->stream));
   HIPCHK(hipStreamWaitEvent(w->gstream, w->ev_in, 0));
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -693,7 +697,7 @@ dcax_status launch_sweep_graph(dcax_walker w, int kb, int nwin) {
     t0 = w->ev();
     if (t0) HIPCHK(hipEventRecord(t0, w->gstream));
   }
-  HIPCHK(hipGraphLaunch(it->second, w->gstream));
+  HIPCHK(hipGraphLaunch(exec, w->gstream));
   if (w->timing) {
     t1 = w->ev();
     if (t1) HIPCHK(hipEventRecord(t1, w->gstream));
@@ -702,6 +706,22 @@ dcax_status launch_sweep_graph(dcax_walker w, int kb, int nwin) {
   HIPCHK(hipEventRecord(w->ev_out, w->gstream));
   HIPCHK(hipStreamWaitEvent(w->stream, w->ev_out, 0));
   return DCAX_OK;
+}
+
+// Replays the sweep as a hipGraph captured once per (order bound, window
+// count).
+dcax_status launch_sweep_graph(dcax_walker w, int kb, int nwin) {
+  w->fresh = false;
+  const int kq = std::min(w->mo_max, ((kb + 63) / 64) * 64);
+  const auto key = std::make_pair(kq, nwin);
+  auto it = w->graphs.find(key);
+  if (it == w->graphs.end()) {
+    hipGraphExec_t exec = nullptr;
+    dcax_status st = capture_graph(w, [&] { enqueue_sweep(w, kq, nwin); }, &exec);
+    if (st != DCAX_OK) return st;
+    it = w->graphs.emplace(key, exec).first;
+  }
+  return launch_graph(w, it->second);
 }
 
 dcax_status sweep_rng(dcax_walker w, int n_sweeps) {
@@ -1033,9 +1053,33 @@ dcax_status sweep_rounds(dcax_walker w, int n, double* acc, double* aux, long lo
       const double expect = h.n_windows > 0 ? (double)R * (double)h.n_abort / (double)h.n_windows : 0.0;
       if (expect > 0.0) spare = (int)std::ceil(expect + 2.0 * std::sqrt(expect) + 1.0);
     }
+    hipGraphExec_t rg = nullptr;
+    if (w->use_graphs) {
+      // one round as a hipGraph, captured once per (order bound, windows,
+      // measurement buffers) and replayed for every round of this pass
+      const auto key = std::make_tuple(kb, R + spare, nfft_hw, acc, aux);
+      auto it = w->round_graphs.find(key);
+      if (it == w->round_graphs.end()) {
+        hipGraphExec_t exec = nullptr;
+        st = capture_graph(w, [&] {
+          if (w->mixed) enqueue_round<float>(w, kb, R + spare, acc, aux, nfft_hw);
+          else enqueue_round<double>(w, kb, R + spare, acc, aux, nfft_hw);
+        }, &exec);
+        if (st != DCAX_OK) return st;
+        it = w->round_graphs.emplace(key, exec).first;
+      }
+      rg = it->second;
+    }
     for (long long r = 0; r < planned; ++r) {
-      if (w->mixed) enqueue_round<float>(w, kb, R + spare, acc, aux, nfft_hw);
-      else enqueue_round<double>(w, kb, R + spare, acc, aux, nfft_hw);
+      if (rg) {
+        w->fresh = false;
+        st = launch_graph(w, rg);
+        if (st != DCAX_OK) return st;
+      } else if (w->mixed) {
+        enqueue_round<float>(w, kb, R + spare, acc, aux, nfft_hw);
+      } else {
+        enqueue_round<double>(w, kb, R + spare, acc, aux, nfft_hw);
+      }
       HIPCHK(hipGetLastError());
       ++w->rounds_done;
       if (refresh_rounds > 0 && w->rounds_done % refresh_rounds == 0) {
@@ -1334,17 +1378,6 @@ dcax_status dcax_sweep_measure(dcax_walker w, int32_t n_sweeps, double* acc_dev,
   if (st != DCAX_OK) return st;
   if (n_sweeps < 0) return fail(DCAX_E_INVAL, "n_sweeps < 0");
   if (!aux_dev || (!acc_dev && w->nf_max > 0)) return fail(DCAX_E_INVAL, "NULL accumulator");
-  if (w->use_graphs) {
-    // captured sweeps: one sweep, then its measurement, at a time
-    for (int i = 0; i < n_sweeps; ++i) {
-      st = sweep_rng(w, 1);
-      if (st != DCAX_OK) return st;
-      if (w->mixed) enqueue_measure<float>(w, acc_dev, aux_dev, 0);
-      else enqueue_measure<double>(w, acc_dev, aux_dev, 0);
-      HIPCHK(hipGetLastError());
-    }
-    return DCAX_OK;
-  }
   return sweep_rounds(w, n_sweeps, acc_dev, aux_dev);
 }
 
@@ -1356,16 +1389,6 @@ dcax_status dcax_sweep_measure_nfft(dcax_walker w, int32_t n_sweeps, int32_t hal
   if (!grid_dev || !aux_dev) return fail(DCAX_E_INVAL, "NULL accumulator");
   st = nfft_check(w, half_width);
   if (st != DCAX_OK) return st;
-  if (w->use_graphs) {
-    for (int i = 0; i < n_sweeps; ++i) {
-      st = sweep_rng(w, 1);
-      if (st != DCAX_OK) return st;
-      if (w->mixed) enqueue_nfft<float>(w, half_width, grid_dev, aux_dev, 0);
-      else enqueue_nfft<double>(w, half_width, grid_dev, aux_dev, 0);
-      HIPCHK(hipGetLastError());
-    }
-    return DCAX_OK;
-  }
   return sweep_rounds(w, n_sweeps, grid_dev, aux_dev, 0, half_width);
 }
 
@@ -1569,6 +1592,41 @@ dcax_status dcax_set_submatrix_k(dcax_walker w, int32_t walker, int32_t ks) {
   return set_ks(w, walker, ks);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Accepted updates per second of sweeps_per_trial generator sweeps of the
+// whole batch, timed with HIP events.
+dcax_status trial_rate(dcax_walker w, int sweeps_per_trial, double* rate) {
+  dcax_status st = sync_all(w);
+  if (st != DCAX_OK) return st;
+  long long a0 = 0;
+  for (const Ctl& h : w->h_ctl) a0 += h.n_acc_ins + h.n_acc_rem;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, w->stream));
+  st = sweep_rng(w, sweeps_per_trial);
+  if (st != DCAX_OK) return st;
+  HIPCHK(hipEventRecord(e1, w->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  st = sync_all(w);
+  if (st != DCAX_OK) return st;
+  long long a1 = 0;
+  for (const Ctl& h : w->h_ctl) a1 += h.n_acc_ins + h.n_acc_rem;
+  *rate = ms > 0.f ? (double)(a1 - a0) / (ms * 1e-3) : 0.0;
+  return DCAX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 dcax_status dcax_autotune(dcax_walker w, int32_t sweeps_per_trial, int32_t* chosen_ks, double* rate_out) {
   dcax_status st = check_latched(w);
   if (st != DCAX_OK) return st;
@@ -1579,27 +1637,9 @@ dcax_status dcax_autotune(dcax_walker w, int32_t sweeps_per_trial, int32_t* chos
   for (int ks : cand) {
     st = set_ks(w, -1, ks);
     if (st != DCAX_OK) return st;
-    st = sync_all(w);
+    double rate = 0.0;
+    st = trial_rate(w, sweeps_per_trial, &rate);
     if (st != DCAX_OK) return st;
-    long long a0 = 0;
-    for (const Ctl& h : w->h_ctl) a0 += h.n_acc_ins + h.n_acc_rem;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, w->stream));
-    st = sweep_rng(w, sweeps_per_trial);
-    if (st != DCAX_OK) return st;
-    HIPCHK(hipEventRecord(e1, w->stream));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    st = sync_all(w);
-    if (st != DCAX_OK) return st;
-    long long a1 = 0;
-    for (const Ctl& h : w->h_ctl) a1 += h.n_acc_ins + h.n_acc_rem;
-    const double rate = ms > 0.f ? (double)(a1 - a0) / (ms * 1e-3) : 0.0;
     if (rate > best_rate) {
       best_rate = rate;
       best = ks;
@@ -1607,8 +1647,37 @@ dcax_status dcax_autotune(dcax_walker w, int32_t sweeps_per_trial, int32_t* chos
   }
   st = set_ks(w, -1, best);
   if (st != DCAX_OK) return st;
+  // then the kernel forms of the two candidate products, one after the other
+  static const int forms[] = {DCAX_VARIANT_TILED, DCAX_VARIANT_WIDE, DCAX_VARIANT_NARROW};
+  for (int which = 0; which < 2; ++which) {
+    int best_form = forms[0];
+    double best_form_rate = -1.0;
+    for (int f : forms) {
+      if (which == 0) w->cand_variant = f;
+      else w->y_variant = f;
+      w->clear_graphs();
+      double rate = 0.0;
+      st = trial_rate(w, sweeps_per_trial, &rate);
+      if (st != DCAX_OK) return st;
+      if (rate > best_form_rate) {
+        best_form_rate = rate;
+        best_form = f;
+      }
+    }
+    best_rate = std::max(best_rate, best_form_rate);
+    if (which == 0) w->cand_variant = best_form;
+    else w->y_variant = best_form;
+    w->clear_graphs();
+  }
   if (chosen_ks) *chosen_ks = best;
   if (rate_out) *rate_out = best_rate;
+  return DCAX_OK;
+}
+
+dcax_status dcax_get_variants(dcax_walker w, int32_t* cand_rows, int32_t* y_columns) {
+  if (!w) return fail(DCAX_E_INVAL, "walker is NULL");
+  if (cand_rows) *cand_rows = w->cand_variant;
+  if (y_columns) *y_columns = w->y_variant;
   return DCAX_OK;
 }
 

@@ -86,7 +86,7 @@ EXPORTS = ("dcax_walker_create", "dcax_walker_destroy", "dcax_sweep", "dcax_swee
            "dcax_sweep_measure", "dcax_run_rounds", "dcax_measure_nfft", "dcax_sweep_measure_nfft",
            "dcax_nfft_transform",
            "dcax_finalize_G", "dcax_get_order", "dcax_copy_N", "dcax_get_config", "dcax_set_config",
-           "dcax_set_submatrix_k", "dcax_autotune", "dcax_set_graphs", "dcax_set_variants", "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table",
+           "dcax_set_submatrix_k", "dcax_autotune", "dcax_set_graphs", "dcax_set_variants", "dcax_get_variants", "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table",
            "dcax_cluster", "dcax_last_error")
 
 _lib = None
@@ -122,6 +122,7 @@ def load():
         "dcax_autotune": [vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_double)],
         "dcax_set_graphs": [vp, ctypes.c_int32],
         "dcax_set_variants": [vp, ctypes.c_int32, ctypes.c_int32],
+        "dcax_get_variants": [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
         "dcax_copy_g0_table": [vp, ctypes.c_int32, vp],
         "dcax_cluster": [P(Params), P(ctypes.c_int32), vp, vp],
     }
@@ -332,6 +333,12 @@ class Walker:
         """Kernel forms of the candidate-row and Y-column products: 0 auto,
         1 tiled (LDS), 2 wide, 3 narrow (see dcax_set_variants)."""
         _check(load().dcax_set_variants(self._h, int(cand_rows), int(y_columns)))
+
+    def variants(self):
+        """(candidate-row form, Y-column form) in use."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().dcax_get_variants(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def set_timing(self, on=True):
         """on: True / 1 times every window, n > 1 a pseudo-random 1/n of them, 0 / False stops."""

@@ -70,10 +70,14 @@ def test_autotune_picks_a_candidate_and_keeps_the_chain_valid():
     s0 = w.stats()
     ks, rate = w.autotune(sweeps_per_trial=3)
     s1 = w.stats()
-    print(f"  chose k_s = {ks} at {rate:.0f} accepted updates/s", flush=True)
+    cv, yv = w.variants()
+    print(f"  chose k_s = {ks}, kernel forms ({cv}, {yv}) at {rate:.0f} accepted updates/s", flush=True)
     assert ks in (8, 16, 24, 32, 48, 64)
+    forms = (dcax.DCAX_VARIANT_TILED, dcax.DCAX_VARIANT_WIDE, dcax.DCAX_VARIANT_NARROW)
+    assert cv in forms and yv in forms
     assert rate > 0
-    assert s1["proposals"] - s0["proposals"] >= 6 * 3 * 200
+    # six submatrix sizes and three forms of each of the two products
+    assert s1["proposals"] - s0["proposals"] >= 12 * 3 * 200
     acc, aux = w.new_accumulator()
     w.sweep_measure(5, acc, aux)
     assert w.refresh() < 1e-8

@@ -129,3 +129,42 @@ def test_sweep_length_freezes_at_the_warm_up_order(warmup):
     frozen = n if warmup == 1 else max(k1, 1)
     assert per == 3 * (-(-frozen // ks) * ks)
     w.close()
+
+
+@pytest.mark.parametrize("precision", [dcax.DCAX_FP64, dcax.DCAX_FP32_MIXED])
+@pytest.mark.parametrize("which", ["batch", "single"])
+def test_round_graphs_equal_eager_rounds(precision, which):
+    """With graphs on, each device-scheduled round (sweep starts, windows,
+    gated measurement) is one captured hipGraph, replayed round after round.
+    Walked one call at a time - eager work and synchronisation between the
+    replays - the state after every call equals the eager rounds'; at the
+    end N, accumulators and counters are bit-identical."""
+    print(f"[round graphs] {which} precision {precision}", flush=True)
+    plist = [params(d, precision) for d in (BATCH if which == "batch" else BATCH[:1])]
+    if which == "single":
+        plist = plist[0]
+    we, wg = dcax.Walker(plist), dcax.Walker(plist)
+    wg.set_graphs(True)
+    acc_e, aux_e = we.new_accumulator()
+    acc_g, aux_g = wg.new_accumulator()
+    for call in range(12):
+        if call % 2:
+            we.run_rounds(3, acc_e, aux_e)
+            wg.run_rounds(3, acc_g, aux_g)
+        else:
+            we.sweep_measure(2, acc_e, aux_e)
+            wg.sweep_measure(2, acc_g, aux_g)
+        for i in range(we.W):
+            assert np.array_equal(we.get_config(i), wg.get_config(i)), f"call {call} walker {i}"
+        assert torch.equal(acc_e, acc_g) and torch.equal(aux_e, aux_g), f"call {call}: accumulators differ"
+    for i in range(we.W):
+        for sp in range(2):
+            ie, Ne = we.copy_N(sp, walker=i)
+            ig, Ng = wg.copy_N(sp, walker=i)
+            assert np.array_equal(ie, ig) and np.array_equal(Ne, Ng), f"walker {i} spin {sp}: N differs"
+        se, sg = we.stats(walker=i), wg.stats(walker=i)
+        for key in ("proposals", "accepted_insertions", "accepted_removals", "windows"):
+            assert se[key] == sg[key], (i, key)
+    print(f"  12 calls identical; proposals {we.stats()['proposals']}", flush=True)
+    we.close()
+    wg.close()
