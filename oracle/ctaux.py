@@ -17,7 +17,12 @@ spin +1 if u3 < 1/2 else -1, accepted with probability
 min(1, |K_exp/(k+1) prod_sigma ratio_sigma|); otherwise the vertex at list
 position floor(u1 k) is proposed for removal with factor k/K_exp (a removal
 at k = 0 is a rejected no-op).  u4 is compared with |R|; the sign of the
-configuration is multiplied by sgn(R) on acceptance.
+configuration is multiplied by sgn(R) on acceptance.  With a flip share
+p_flip > 0 (the spin-flip move of the paper's figure of CT-AUX moves), u0
+below (1 - p_flip)/2 inserts, below 1 - p_flip removes, and otherwise the
+auxiliary spin of the vertex at list position floor(u1 k) is proposed to
+flip, accepted with min(1, |prod_sigma ratio_sigma|) (a symmetric move at
+fixed order: no expansion-parameter factor).
 
 Determinant ratios and updates are the textbook single-vertex ones:
 insertion is a bordered inverse (Schur complement d - W N Q), removal the
@@ -93,8 +98,13 @@ def n_inverse(model, r, t, s, spin):
 class Walker:
     """One CT-AUX Markov chain with single-vertex updates."""
 
-    def __init__(self, model, seed, k_s=16, record=False):
+    def __init__(self, model, seed, k_s=16, record=False, p_flip=0.0):
+        """p_flip: share of proposals that flip the auxiliary spin of an
+        existing vertex (Sec. 2.3's figure of the CT-AUX moves); insertions
+        and removals share the rest equally."""
         self.m = model
+        self.p_flip = float(p_flip)
+        self.n_acc_flip = 0
         self.rng = np.random.Generator(np.random.MT19937(seed))
         self.k_s = int(k_s)
         self.frozen_length = 0
@@ -203,13 +213,58 @@ class Walker:
             a[p] = a[last]
             setattr(self, name, a[:-1].copy())
 
+    def _flip_ratio(self, p):
+        """Ratio of det N'^{-1} / det N^{-1} per spin when s_p -> -s_p.
+
+        Only column p of N^{-1} = e^V - g (e^V - 1) changes, by
+        d = (e^{V'_p} - e^{V_p}) (e_p - g_{.p}), so the ratio is
+        1 + (N d)_p = 1 + N_{p.} d (matrix determinant lemma)."""
+        m = self.m
+        out = []
+        for spin in range(2):
+            ev_old = float(m.ev(self.s[p], spin))
+            ev_new = float(m.ev(-self.s[p], spin))
+            gp = m.props[spin].g(self.r, self.t, self.r[p], self.t[p])       # g_{.p}
+            d = -(ev_new - ev_old) * gp
+            d[p] += ev_new - ev_old
+            Nd = self.N[spin] @ d
+            out.append((1.0 + Nd[p], Nd))
+        return out
+
+    def _do_flip(self, p, parts):
+        """Sherman-Morrison update of N for the column change d e_p^T."""
+        for spin in range(2):
+            ratio, Nd = parts[spin]
+            N = self.N[spin]
+            self.N[spin] = N - np.outer(Nd, N[p]) / ratio
+        self.s[p] = -self.s[p]
+
     def step(self):
         """One proposal; returns (kind, accepted)."""
         m = self.m
         u = self.rng.random(5)
         self.n_prop += 1
         k = self.k
-        if u[0] < 0.5:
+        half = 0.5 * (1.0 - self.p_flip)
+        if u[0] >= 2.0 * half:
+            # flip of the auxiliary spin of vertex floor(u1 k) (a no-op at k = 0)
+            if k == 0:
+                if self.record:
+                    self.trace.append((2, -1, 0.0, 0, -1, u[4], 0.0, False))
+                return 2, False
+            p = int(math.floor(u[1] * k))
+            parts = self._flip_ratio(p)
+            R = parts[0][0] * parts[1][0]
+            acc = u[4] < abs(R)
+            tid = int(self.id[p])
+            if acc:
+                self.sign *= math.copysign(1.0, R)
+                self._do_flip(p, parts)
+                self.n_acc_flip += 1
+            if self.record:
+                self.trace.append((2, -1, 0.0, 0, tid, u[4], R, bool(acc)))
+            return 2, acc
+        if u[0] < half:
             rq = int(math.floor(u[1] * m.Nc))
             tq = u[2] * m.beta
             sq = 1 if u[3] < 0.5 else -1
@@ -280,8 +335,9 @@ TRACE_FIELDS = ("kind", "site", "tau", "aux_spin", "id", "u_accept", "ratio", "a
 def trace_arrays(trace):
     """Column arrays from a recorded trace.
 
-    id is the new vertex's id for an accepted insertion and the target's id
-    for a removal (-1 otherwise)."""
+    kind 0 insertion, 1 removal, 2 flip of an auxiliary spin; id is the new
+    vertex's id for an accepted insertion and the target's id for a removal
+    or a flip (-1 otherwise)."""
     if not trace:
         return {f: np.zeros(0) for f in TRACE_FIELDS}
     cols = list(zip(*trace))

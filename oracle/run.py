@@ -10,8 +10,8 @@ from . import ctaux, measure, stats
 
 
 def run_chain(model, seed, sweeps, warmup=100, n_freq=64, k_s=16, initial_order=0,
-              refresh_every=0, record=False):
-    w = ctaux.Walker(model, seed, k_s=k_s, record=record)
+              refresh_every=0, record=False, p_flip=0.0):
+    w = ctaux.Walker(model, seed, k_s=k_s, record=record, p_flip=p_flip)
     if initial_order:
         w.random_config(initial_order)
     warm_orders = []

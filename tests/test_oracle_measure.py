@@ -51,18 +51,21 @@ def test_atom_green_function():
     assert res["sign"] == 1.0
 
 
-def test_atom_in_a_field_green_function():
+@pytest.mark.parametrize("p_flip", [0.0, 0.3])
+def test_atom_in_a_field_green_function(p_flip):
     """One bare propagator per spin (a Zeeman field h splits xi_up and
     xi_down): the chain's G_up and G_down against the four-state exact
     result, which the ED tests pin by its closed form.  A dropped spin index
     (one propagator for both spins) fails: the two G differ by ~0.1.  At
     beta U = 4 the chain passes through low orders often enough to flip the
     atom's moment (at larger beta U insert/remove moves flip it too rarely
-    for the minority configurations to be sampled in a short run)."""
+    for the minority configurations to be sampled in a short run).  With a
+    share of spin-flip proposals the same exact G must come out."""
     U, beta, mu, h = 2.0, 2.0, 0.3, 0.5
     m = ctaux.Model(a1=(1, 0), a2=(0, 1), t=0.0, U=U, beta=beta, mu=mu, n_tau=2, use_table=False, h=h)
     nf = 256
-    w, acc, orders = run.run_chain(m, seed=31, sweeps=8000, warmup=200, n_freq=nf, k_s=8)
+    w, acc, orders = run.run_chain(m, seed=31, sweeps=8000, warmup=200, n_freq=nf, k_s=8, p_flip=p_flip)
+    assert p_flip == 0.0 or w.n_acc_flip > 1000
     taus = np.linspace(0.1, beta - 0.1, 12)
     res = run.estimate_G(m, acc, taus=taus)
     e = ed.ED(np.zeros((1, 1)), U=U, mu=mu, beta=beta, h=h)
