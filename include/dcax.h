@@ -86,7 +86,8 @@ typedef struct {
 /* One recorded proposal, replayed with its decision forced (dcax_sweep).
  * kind 0 = insertion at (site, tau, aux_spin), taking `id` if accepted;
  * kind 1 = removal of the vertex with id `id` (id -1: removal proposed at
- * order 0, a rejected no-op).  u_accept is the uniform the decision was drawn
+ * order 0, a rejected no-op); kind 2 = flip of the auxiliary spin of the
+ * vertex with id `id` (id -1: a no-op at order 0).  u_accept is the uniform the decision was drawn
  * with; the library counts decisions on which its own ratio would disagree. */
 typedef struct {
   int32_t kind;
@@ -137,6 +138,20 @@ typedef struct {
   int32_t reserved;        /* must be 0 */
   const double* g0_tau;
   const double* g0_Kw;
+  /* Spin-flip proposals (Sec. 2.3's figure of the CT-AUX moves): a share
+   * flip_share in [0, 1) of the generator's proposals flips the auxiliary
+   * spin of a uniformly chosen vertex (accepted with |prod_sigma ratio|);
+   * insertions and removals share the rest equally.
+   * touched_twice (Sec. 2.3, a spin touched twice within one submatrix
+   * window; App. B "neglect-Bennett-updates"):
+   *   0 = exact: the window closes before such a proposal, which opens the
+   *       next one ("abort"; a removal of a spin inserted in the same window
+   *       is still done exactly);
+   *   1 = neglect: such a proposal is rejected outright.  This breaks detailed
+   *       balance; its bias is measured against the exact chain. */
+  double flip_share;
+  int32_t touched_twice;
+  int32_t reserved2;       /* must be 0 */
 } dcax_params;
 
 /* Counters since creation or the last dcax_set_config (timings and drifts
@@ -168,6 +183,8 @@ typedef struct {
   double y_flops;           /* algorithmic flops of the Y columns N g_{I,c} of inserted spins, 2 k^2 m_i per spin */
   double y_bytes;           /* their algorithmic bytes: N read once, g columns read and Y written */
   double y_seconds;         /* Y-column kernel time summed over the timed windows */
+  int64_t accepted_flips;   /* accepted spin flips */
+  int64_t neglected;        /* proposals rejected as touching a spin twice (touched_twice = 1) */
 } dcax_stats;
 
 /* Create a batch of n_walkers independent walkers (Markov chains; Sec. 3.1,

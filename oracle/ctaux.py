@@ -218,16 +218,20 @@ class Walker:
 
         Only column p of N^{-1} = e^V - g (e^V - 1) changes, by
         d = (e^{V'_p} - e^{V_p}) (e_p - g_{.p}), so the ratio is
-        1 + (N d)_p = 1 + N_{p.} d (matrix determinant lemma)."""
+        1 + (N d)_p (matrix determinant lemma).  The unchanged column p of
+        N^{-1} is e^{V_p} e_p - g_{.p} (e^{V_p} - 1), so N g_{.p} =
+        (e^{V_p} N_{.p} - e_p) / (e^{V_p} - 1) and
+            N d = c (e_p - N_{.p}),  c = (e^{V'_p} - e^{V_p}) / (e^{V_p} - 1),
+        ratio 1 + c (1 - N_pp): the same quantity read off N itself, without
+        the sum over k products of size e^{gamma} that N d would take."""
         m = self.m
         out = []
         for spin in range(2):
             ev_old = float(m.ev(self.s[p], spin))
             ev_new = float(m.ev(-self.s[p], spin))
-            gp = m.props[spin].g(self.r, self.t, self.r[p], self.t[p])       # g_{.p}
-            d = -(ev_new - ev_old) * gp
-            d[p] += ev_new - ev_old
-            Nd = self.N[spin] @ d
+            c = (ev_new - ev_old) / (ev_old - 1.0)
+            Nd = -c * self.N[spin][:, p]
+            Nd[p] += c
             out.append((1.0 + Nd[p], Nd))
         return out
 

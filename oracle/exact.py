@@ -15,7 +15,9 @@ FP64's 2.2e-16) with the textbook single-vertex algebra:
   `reinvert_every` accepted moves;
 * insertion ratio d - W N Q (bordered inverse), removal ratio N_pp
   (cofactor identity), R = K/(k+1) or k/K times the product over spins;
-* the bordered-inverse and rank-one-downdate updates of N.
+  the flip of an auxiliary spin changes one column of N^{-1}: ratio
+  1 + (N d)_p per spin (matrix determinant lemma), R the product;
+* the bordered-inverse, rank-one-downdate and Sherman-Morrison updates of N.
 
 The propagator g between vertices is the same linear interpolation of the
 FP64 table as ``g0.interp``, evaluated in extended precision.  Results are
@@ -112,6 +114,21 @@ class ExactChain:
             parts.append((d - W @ NQ, NQ, WN))
         return parts
 
+    def flip_ratio(self, p):
+        """Flip of the auxiliary spin at row p: only column p of N^{-1}
+        changes, by d = (e^{V'_p} - e^{V_p}) (e_p - g_{.p}), so per spin the
+        ratio is 1 + (N d)_p (matrix determinant lemma) and N' = N - N d
+        N_{p.} / ratio (Sherman-Morrison)."""
+        g_p = self.g(self.r, self.t, self.r[p], self.t[p])
+        parts = []
+        for sp in (0, 1):
+            dv = self.ev(-self.s[p], sp) - self.ev(self.s[p], sp)
+            d = -dv * g_p
+            d[p] += dv
+            Nd = self.N[sp] @ d
+            parts.append((LD(1) + Nd[p], Nd))
+        return parts
+
     def step(self, kind, site, tau, aux_spin, vid, accepted):
         """Replay one record; returns the full acceptance ratio R (FP64)."""
         m = self.m
@@ -132,6 +149,17 @@ class ExactChain:
                 self.t = np.append(self.t, tau)
                 self.s = np.append(self.s, aux_spin)
                 self.id = np.append(self.id, vid)
+        elif kind == 2:
+            if vid < 0:
+                return 0.0
+            p = int(np.nonzero(self.id == vid)[0][0])
+            parts = self.flip_ratio(p)
+            R = parts[0][0] * parts[1][0]
+            if accepted:
+                for sp in (0, 1):
+                    ratio, Nd = parts[sp]
+                    self.N[sp] = self.N[sp] - np.outer(Nd, self.N[sp][p]) / ratio
+                self.s[p] = -self.s[p]
         else:
             if vid < 0:
                 return 0.0
@@ -159,7 +187,8 @@ def replay(model, init, records, reinvert_every=64):
     """Ratios (FP64) of every record and the final chain, in extended precision.
 
     init: (r, t, s, ids); records: rows with fields kind, site, tau, aux_spin,
-    id, accepted (a removal with id < 0 is the no-op at order 0, ratio 0)."""
+    id, accepted (kind 0 insertion, 1 removal, 2 flip; a removal or flip with
+    id < 0 is the no-op at order 0, ratio 0)."""
     ch = ExactChain(model, *init, reinvert_every=reinvert_every)
     out = np.array([ch.step(int(x["kind"]), int(x["site"]), float(x["tau"]), int(x["aux_spin"]), int(x["id"]),
                             int(x["accepted"])) for x in records])
@@ -260,6 +289,21 @@ class RefinedChain:
                 rho, bound = LD(d), abs(d)
             out.append((rho, float(bound), Q, W, d))
         return out
+
+    def flip_ratio(self, p):
+        """Flip of the auxiliary spin at row p: only column p of N^{-1}
+        changes, by d = (e^{V'_p} - e^{V_p}) (e_p - g_{.p}), so per spin the
+        ratio is 1 + (N d)_p (matrix determinant lemma) and N' = N - N d
+        N_{p.} / ratio (Sherman-Morrison)."""
+        g_p = self.g(self.r, self.t, self.r[p], self.t[p])
+        parts = []
+        for sp in (0, 1):
+            dv = self.ev(-self.s[p], sp) - self.ev(self.s[p], sp)
+            d = -dv * g_p
+            d[p] += dv
+            Nd = self.N[sp] @ d
+            parts.append((LD(1) + Nd[p], Nd))
+        return parts
 
     def step(self, kind, site, tau, aux_spin, vid, accepted):
         """Replay one record; returns (R, bound) in FP64 (R = 0, bound 0 for the

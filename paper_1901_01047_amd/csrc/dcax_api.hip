@@ -428,7 +428,9 @@ dcax_status validate(const dcax_params* p) {
   if (p->n_spin_tables < 0 || p->n_spin_tables > 2) return fail(DCAX_E_INVAL, "n_spin_tables must be 0, 1 or 2");
   if (p->n_spin_tables > 0 && !p->g0_tau) return fail(DCAX_E_INVAL, "n_spin_tables > 0 needs g0_tau");
   if (p->n_spin_tables == 0 && (p->g0_tau || p->g0_Kw)) return fail(DCAX_E_INVAL, "g0_tau or g0_Kw given with n_spin_tables = 0");
-  if (p->reserved != 0) return fail(DCAX_E_INVAL, "reserved must be 0");
+  if (p->reserved != 0 || p->reserved2 != 0) return fail(DCAX_E_INVAL, "reserved fields must be 0");
+  if (!(p->flip_share >= 0.0 && p->flip_share < 1.0)) return fail(DCAX_E_INVAL, "flip_share must be in [0, 1)");
+  if (p->touched_twice != 0 && p->touched_twice != 1) return fail(DCAX_E_INVAL, "touched_twice must be 0 or 1");
   Geometry g;
   if (!build_geometry(p->cluster, g)) return fail(DCAX_E_INVAL, "degenerate or too large cluster");
   if (p->n_freq > 0 && g.Nc > MEAS_NC_MAX)
@@ -792,7 +794,7 @@ size_t walker_bytes(const WalkerHost& x) {
   add(sizeof(long long) * cap);                  // v_id
   for (int sp = 0; sp < 2; ++sp) add(sizeof(T) * ld * cap);  // N
   add(sizeof(WinProp) * KS_MAX);
-  for (int i = 0; i < 8; ++i) add(sizeof(int) * KS_MAX);    // el_*, cand_el, S, ins_el, el_row
+  for (int i = 0; i < 9; ++i) add(sizeof(int) * KS_MAX);    // el_*, cand_el, S, ins_el, el_row, el_flip
   add(sizeof(double) * KS_MAX);                  // el_tau
   add(sizeof(long long) * KS_MAX);               // cand_id
   add(sizeof(int) * cap);                        // remap
@@ -855,6 +857,8 @@ void wire_walker(dcax_walker w, WalkerHost& x, int wid, char* base, Ctl* ctl) {
     v.ev[sp][1] = std::exp(-sig * x.gamma);
   }
   v.seed = x.p.seed;
+  v.flip_share = x.p.flip_share;
+  v.neglect = x.p.touched_twice;
   v.diff = (const int*)take(sizeof(int) * Nc * Nc);
   const int nt = x.p.n_spin_tables == 2 ? 2 : 1;
   v.spin_tables = nt;
@@ -875,6 +879,7 @@ void wire_walker(dcax_walker w, WalkerHost& x, int wid, char* base, Ctl* ctl) {
   v.el_site = (int*)take(sizeof(int) * KS_MAX);
   v.el_s = (int*)take(sizeof(int) * KS_MAX);
   v.el_slot = (int*)take(sizeof(int) * KS_MAX);
+  v.el_flip = (int*)take(sizeof(int) * KS_MAX);
   v.el_cand = (int*)take(sizeof(int) * KS_MAX);
   v.el_row = (int*)take(sizeof(int) * KS_MAX);
   v.cand_el = (int*)take(sizeof(int) * KS_MAX);
@@ -1292,7 +1297,7 @@ dcax_status check_replay(dcax_walker w, const dcax_proposal* replay, int64_t n_r
   const WalkerHost& x = w->wk[0];
   for (int64_t i = 0; i < n_replay; ++i) {
     const dcax_proposal& r = replay[i];
-    if (r.kind != 0 && r.kind != 1) return fail(DCAX_E_INVAL, "replay kind must be 0 or 1");
+    if (r.kind < 0 || r.kind > 2) return fail(DCAX_E_INVAL, "replay kind must be 0, 1 or 2");
     if (r.accepted != 0 && r.accepted != 1) return fail(DCAX_E_INVAL, "replay accepted must be 0 or 1");
     if (r.kind == 0) {
       if (r.site < 0 || r.site >= x.geo.Nc) return fail(DCAX_E_INVAL, "replay site out of range");
@@ -1300,7 +1305,7 @@ dcax_status check_replay(dcax_walker w, const dcax_proposal* replay, int64_t n_r
       if (!(r.tau >= 0.0 && r.tau < x.p.beta)) return fail(DCAX_E_INVAL, "replay tau outside [0, beta)");
       if (r.accepted && r.id < 0) return fail(DCAX_E_INVAL, "accepted insertion needs an id >= 0");
     } else if (r.id < 0 && r.accepted) {
-      return fail(DCAX_E_INVAL, "a removal without target cannot be accepted");
+      return fail(DCAX_E_INVAL, "a removal or flip without target cannot be accepted");
     }
   }
   return DCAX_OK;
@@ -1321,14 +1326,24 @@ dcax_status replay_staged(dcax_walker w, const dcax_proposal* replay, int64_t n_
                      (long long)n_replay);
   if (w->mixed) hipLaunchKernelGGL(k_set_cursor<float>, dim3(1), dim3(1), 0, w->stream, w->views<float>(), 0LL, (long long)n_replay);
   else hipLaunchKernelGGL(k_set_cursor<double>, dim3(1), dim3(1), 0, w->stream, w->views<double>(), 0LL, (long long)n_replay);
-  const long long nwin = (n_replay + x.ks - 1) / x.ks;
-  int kb = x.k_host;
-  for (long long i = 0; i < nwin; ++i) {
-    kb = std::min(x.max_order, kb + x.ks);
-    if (w->mixed) enqueue_window<float>(w, kb, true);
-    else enqueue_window<double>(w, kb, true);
+  // A window that ends before a second change of one spin (flip then
+  // removal, insertion then flip) leaves records for more windows than
+  // ceil(n / k_s): enqueue what the records left need, until none are left.
+  long long left = n_replay;
+  for (;;) {
+    const long long nwin = (left + x.ks - 1) / x.ks;
+    int kb = x.k_host;
+    for (long long i = 0; i < nwin; ++i) {
+      kb = std::min(x.max_order, kb + x.ks);
+      if (w->mixed) enqueue_window<float>(w, kb, true);
+      else enqueue_window<double>(w, kb, true);
+    }
+    HIPCHK(hipGetLastError());
+    dcax_status st = sync_all(w);
+    if (st != DCAX_OK) return st;
+    left = w->h_ctl[0].end - w->h_ctl[0].pos;
+    if (left <= 0) break;
   }
-  HIPCHK(hipGetLastError());
   if (ratio_out) HIPCHK(hipMemcpyAsync(ratio_out, rat, sizeof(double) * n_replay, hipMemcpyDeviceToHost, w->stream));
   return sync_all(w);
 }
@@ -1557,6 +1572,8 @@ dcax_status dcax_get_stats(dcax_walker w, int32_t walker, dcax_stats* out) {
     out->proposals += h.n_prop;
     out->accepted_insertions += h.n_acc_ins;
     out->accepted_removals += h.n_acc_rem;
+    out->accepted_flips += h.n_acc_flip;
+    out->neglected += h.n_neglect;
     out->windows += h.n_windows;
     out->flips_folded += h.sum_m;
     out->decision_mismatches += h.n_mismatch;

@@ -58,10 +58,14 @@ struct Ctl {
   // algorithmic work of the candidate-row (X_C = W_C N) and Y-column
   // (N g_{I,c}) products: flops, and bytes with N read once
   double cand_flops, cand_bytes, y_flops, y_bytes;
+  long long n_acc_flip;  // accepted spin flips
+  long long n_neglect;   // proposals rejected as touching a spin twice
+  int carry_kind;        // kind (1 removal, 2 flip) of the carried proposal's target
+  int pad2_;
 };
 
 struct WinProp {      // one proposal of the current window
-  int kind;           // 0 insertion, 1 removal
+  int kind;           // 0 insertion, 1 removal, 2 spin flip
   int el;             // window element, -1 for a no-op removal at k = 0
   int forced;         // replay decision (-1: decide from u)
   int carried;        // removal whose target was fixed before this window
@@ -82,6 +86,8 @@ struct View {
   int Nc, n_tau, ks, cap, ld, max_order, warmup;
   double beta, h, gamma, K_exp;
   double ev[2][2];            // e^{V}: [spin][0 for s = +1, 1 for s = -1]
+  double flip_share;          // share of spin-flip proposals
+  int neglect;                // touched twice: 0 close the window, 1 reject
   uint64_t seed;              // generator key
   const int* diff;            // [Nc * Nc] index of r_i - r_j
   const double* table[2];     // [Nc][n_tau] G0_sigma(r, tau_l), standard convention (one shared table or one per spin)
@@ -103,7 +109,8 @@ struct View {
   int* el_site;
   double* el_tau;
   int* el_s;
-  int* el_slot;               // slot of a removal target, -1 for a candidate
+  int* el_slot;               // slot of a removal or flip target, -1 for a candidate
+  int* el_flip;               // 1 for a flip target (its column of Gt and of A differ from a removal's)
   int* el_cand;               // candidate index or -1
   int* el_row;                // row of each element in the extended N
   int* cand_el;

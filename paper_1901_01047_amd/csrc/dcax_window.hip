@@ -26,14 +26,20 @@ namespace dcax {
 // ------------------------------------------------------------------ prep
 // Replay mode: the window's proposals come from a recorded trace with forced
 // decisions.  Builds the element list: one element per insertion candidate
-// and one per distinct window-start vertex proposed for removal; a removal
-// of a vertex inserted earlier in the same window refers to that candidate.
+// and one per distinct (window-start vertex, removal or flip) target; a
+// removal of a vertex inserted earlier in the same window refers to that
+// candidate, a second flip of a vertex to its flip element.  A proposal that
+// would change a spin the window has already changed otherwise (a flip of a
+// spin inserted in the window, a removal of a flipped spin) ends the window
+// before it, so that it opens the next one: the forced decisions make these
+// cases known here.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_prep_replay(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
   Ctl* c = w.ctl;
   __shared__ long long tid_s[KS_MAX];
   __shared__ int tslot_s[KS_MAX];
+  __shared__ int on_s[KS_MAX];      // element changed by the window so far (odd count)
   __shared__ int nP_s, k0_s;
   const int t = threadIdx.x;
   if (t == 0) {
@@ -44,14 +50,16 @@ __global__ void __launch_bounds__(WG) k_prep_replay(const View<T>* __restrict__ 
     if (nP == 0) c->active = 0;
   }
   __syncthreads();
-  const int nP = nP_s, k0 = k0_s;
+  int nP = nP_s;
+  const int k0 = k0_s;
   if (nP == 0) return;
   const long long pos = c->pos;
   if (t < nP) {
     const dcax_proposal& r = w.replay[pos + t];
-    tid_s[t] = (r.kind == 1) ? r.id : -2;
+    tid_s[t] = (r.kind >= 1) ? r.id : -2;
     tslot_s[t] = -1;
   }
+  if (t < KS_MAX) on_s[t] = 0;
   __syncthreads();
   for (int i = t; i < k0; i += WG) {
     long long id = w.v_id[i];
@@ -80,15 +88,21 @@ __global__ void __launch_bounds__(WG) k_prep_replay(const View<T>* __restrict__ 
       w.el_tau[e] = r.tau;
       w.el_s[e] = r.aux_spin;
       w.el_slot[e] = -1;
+      w.el_flip[e] = 0;
       w.el_cand[e] = cc;
       w.cand_el[cc] = e;
       w.cand_id[cc] = r.accepted ? r.id : -1;
       if (r.accepted && r.id >= next_id) next_id = r.id + 1;
       p.el = e;
     } else if (r.id >= 0) {
+      const int fl = r.kind == 2 ? 1 : 0;
       int e = -1;
       for (int cc = 0; cc < nC; ++cc)
         if (w.cand_id[cc] == r.id) e = w.cand_el[cc];
+      if (e >= 0 && fl) {
+        nP = j;           // a flip of a spin inserted in this window
+        break;
+      }
       if (e < 0) {
         int slot = tslot_s[j];
         if (slot < 0) {
@@ -96,19 +110,33 @@ __global__ void __launch_bounds__(WG) k_prep_replay(const View<T>* __restrict__ 
           c->active = 0;
           return;
         }
-        for (int x = 0; x < nE; ++x)
-          if (w.el_slot[x] == slot) e = x;
+        int twin = -1;
+        for (int x = 0; x < nE; ++x) {
+          if (w.el_slot[x] == slot && w.el_flip[x] == fl) e = x;
+          if (w.el_slot[x] == slot && w.el_flip[x] != fl) twin = x;
+        }
+        if (twin >= 0 && on_s[twin]) {
+          if (fl) {       // a flip of a vertex the window removed
+            latch(c, ST_TRACE);
+            c->active = 0;
+            return;
+          }
+          nP = j;         // a removal of a spin flipped in this window
+          break;
+        }
         if (e < 0) {
           e = nE++;
           w.el_site[e] = w.v_site[slot];
           w.el_tau[e] = w.v_tau[slot];
           w.el_s[e] = w.v_s[slot];
           w.el_slot[e] = slot;
+          w.el_flip[e] = fl;
           w.el_cand[e] = -1;
         }
       }
       p.el = e;
     }
+    if (p.el >= 0 && r.accepted) on_s[p.el] ^= 1;
     w.wp[j] = p;
   }
   c->next_id = next_id;
@@ -147,6 +175,7 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
   const int k0 = uni(c->k);
   const long long pos = uni(c->pos);
   const long long carry = uni(c->carry_id);
+  const int carry_kind = uni(c->carry_kind) == 2 ? 2 : 1;
   int carry_slot = -1;
   if (carry >= 0) {
     int found = -1;
@@ -163,6 +192,8 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
     }
   }
   const bool act = lane < nP;
+  // insertions and removals share 1 - flip_share equally, flips the rest
+  const double half = 0.5 * (1.0 - w.flip_share);
   double u_kind = 1.0, u_site = 0.0, u_tau = 0.0, u_spin = 0.0, u_acc = 0.0, u_dummy;
   double ub0 = 0.0, ui0 = 0.0;
   int kind = -1, slot = -1;
@@ -172,12 +203,12 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
     uniforms2(seed, g, 1u, u_tau, u_spin);
     uniforms2(seed, g, 2u, u_acc, u_dummy);
     if (lane == 0 && carry >= 0) {
-      kind = 1;
+      kind = carry_kind;
       slot = carry_slot;
-    } else if (u_kind < 0.5) {
+    } else if (u_kind < half) {
       kind = 0;
     } else {
-      kind = 1;
+      kind = (u_kind < 2.0 * half) ? 1 : 2;
       uniforms2(seed, g, 3u, ub0, ui0);
       if (k0 > 0) {     // the first attempt's window-start vertex
         slot = (int)(ui0 * (double)k0);
@@ -185,36 +216,41 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
       }
     }
   }
-  // A removal's second target attempt is prepared too (as long as elements
-  // remain), so that a redraw after hitting an already removed vertex rarely
-  // has to close the window.  Its slot does not depend on the state; whether
-  // the attempt happens does, and an unused element costs nothing.
-  const int slot_r = (kind == 1) ? slot : -1;
-  int slot1 = -1;
-  if (kind == 1 && !(lane == 0 && carry >= 0) && k0 > 0) {
+  // A target's element belongs to a (slot, kind) pair: a removal and a flip
+  // of one vertex change it differently and need their own columns.  Keys
+  // 2 slot + (flip).  A target's second attempt is prepared too (as long as
+  // elements remain), so that a redraw after hitting an already removed
+  // vertex rarely has to close the window.  Its slot does not depend on the
+  // state; whether the attempt happens does, and an unused element costs
+  // nothing.
+  const int fl = (kind == 2) ? 1 : 0;
+  const int key_r = (kind >= 1 && slot >= 0) ? 2 * slot + fl : -1;
+  int key1 = -1;
+  if (kind >= 1 && !(lane == 0 && carry >= 0) && k0 > 0) {
     double ub1, ui1;
     uniforms2(seed, pos + lane, 4u, ub1, ui1);
-    slot1 = (int)(ui1 * (double)k0);
+    int slot1 = (int)(ui1 * (double)k0);
     if (slot1 >= k0) slot1 = k0 - 1;
+    key1 = 2 * slot1 + fl;
   }
-  // duplicates, by register broadcasts: the first removal aiming at a slot
+  // duplicates, by register broadcasts: the first proposal aiming at a key
   // owns its element; a second attempt is fresh unless some first attempt or
-  // an earlier second attempt already prepares its slot
+  // an earlier second attempt already prepares its key
   int first = lane;
-  bool fresh1 = slot1 >= 0;
+  bool fresh1 = key1 >= 0;
   for (int x = 0; x < nP; ++x) {
-    const int sx = __builtin_amdgcn_readlane(slot_r, x), s1x = __builtin_amdgcn_readlane(slot1, x);
-    if (x < first && sx >= 0 && sx == slot_r) first = x;
-    fresh1 &= sx != slot1;
-    fresh1 &= !(x < lane && s1x == slot1);
+    const int sx = __builtin_amdgcn_readlane(key_r, x), s1x = __builtin_amdgcn_readlane(key1, x);
+    if (x < first && sx >= 0 && sx == key_r) first = x;
+    fresh1 &= sx != key1;
+    fresh1 &= !(x < lane && s1x == key1);
   }
-  const bool fresh = (kind == 0) || (slot_r >= 0 && first == lane);
+  const bool fresh = (kind == 0) || (key_r >= 0 && first == lane);
   const unsigned long long fresh_m = __ballot(fresh), ins_m = __ballot(kind == 0);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int e_own = fresh ? __popcll(fresh_m & below) : -1;
   const int cc = (kind == 0) ? __popcll(ins_m & below) : -1;
   const int e_first = __shfl(e_own, first, PW);
-  const int e = (slot_r >= 0 && !fresh) ? e_first : e_own;
+  const int e = (key_r >= 0 && !fresh) ? e_first : e_own;
   const int nE0 = __popcll(fresh_m);
   const unsigned long long fresh1_m = __ballot(fresh1);
   const int e1 = nE0 + __popcll(fresh1_m & below);
@@ -226,6 +262,7 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
     w.el_tau[e] = u_tau * w.beta;
     w.el_s[e] = (u_spin < 0.5) ? 1 : -1;
     w.el_slot[e] = -1;
+    w.el_flip[e] = 0;
     w.el_cand[e] = cc;
     w.cand_el[cc] = e;
     w.cand_id[cc] = -1;
@@ -234,13 +271,16 @@ __global__ void __launch_bounds__(PW) k_prep_rng(const View<T>* __restrict__ vs)
     w.el_tau[e] = w.v_tau[slot];
     w.el_s[e] = w.v_s[slot];
     w.el_slot[e] = slot;
+    w.el_flip[e] = fl;
     w.el_cand[e] = -1;
   }
   if (fresh1 && e1 < KS_MAX) {
+    const int slot1 = key1 >> 1;
     w.el_site[e1] = w.v_site[slot1];
     w.el_tau[e1] = w.v_tau[slot1];
     w.el_s[e1] = w.v_s[slot1];
     w.el_slot[e1] = slot1;
+    w.el_flip[e1] = key1 & 1;
     w.el_cand[e1] = -1;
   }
   if (act) {
@@ -612,8 +652,20 @@ __global__ void __launch_bounds__(256) k_cand_xt(const View<T>* __restrict__ vs)
 //   candidate c:  G_{x,c} = R_x . g_{I,c} (+ g_{x,c} for candidate rows x),
 //                 Delta_c = e^{V'_c} - 1;
 //   target p:     Gt_{x,p} = R_x[p], from G (e^V - 1) = N e^V - 1 with
-//                 Delta_p = e^{-V_p} - 1;
+//                 Delta_p = e^{-V_p} - 1 (removal; a flip: target_column);
 // where R_x is row x of the extended N (X_c for candidates, N_{p.} for targets).
+// Gt_{x,y} for a target y at slot p of the window-start vertices, from
+// r = R_x[p] = N_ext{x,p}: a removal (Delta_p = e^{-V_p} - 1) gives r itself;
+// a flip of the auxiliary spin (Delta_p = e^{-2 V_p} - 1) gives
+// (1 + e^{-V_p}) r - delta_xy e^{-V_p}, by the same identity
+// G (e^V - 1) = N e^V - 1.
+template <typename T>
+__device__ inline double target_column(const View<T>& w, int sp, int y, int x, double r) {
+  if (!w.el_flip[y]) return r;
+  const double em = w.ev[sp][1 - s01(w.el_s[y])];       // e^{-V_p}
+  return (1.0 + em) * r - (y == x ? em : 0.0);
+}
+
 // Row form of the Gram kernel for launches with few walkers: a workgroup
 // owns one row x of Gt, its wavefronts take the candidate columns in turn
 // (each a k0-long dot product summed across the lanes), so a single walker
@@ -686,7 +738,7 @@ __global__ void __launch_bounds__(NW * 64) k_gram_rows(const View<T>* __restrict
     }
     for (int y = threadIdx.x; y < nE; y += GW) {
       const int py = w.el_slot[y];
-      if (py >= 0) G[y] = (double)Rx[py];
+      if (py >= 0) G[y] = target_column(w, sp, y, x, (double)Rx[py]);
     }
   }
 }
@@ -783,12 +835,12 @@ __global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs
     }
     __syncthreads();      // red is rewritten by the next block
   }
-  // columns of window-start vertices: Gt_{x,p} = R_x[p]
+  // columns of window-start vertices (removal or flip targets)
   if (blockIdx.x == 0)
     for (int idx = threadIdx.x; idx < nE * nE; idx += GW) {
       const int x = idx / nE, y = idx % nE;
       const int py = w.el_slot[y];
-      if (py >= 0) G[x * KS_MAX + y] = (double)R[(size_t)x * w.cap + py];
+      if (py >= 0) G[x * KS_MAX + y] = target_column(w, sp, y, x, (double)R[(size_t)x * w.cap + py]);
     }
 }
 
@@ -889,11 +941,15 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     p_ridx = x.ridx;
     p_gidx = x.gidx;
   }
-  int e_cand = -1, e_spin = 0, e_slot = -1;
+  // e_twin: the element of the same window-start vertex with the other kind
+  // of change (removal / flip) is in S, i.e. that vertex was changed the
+  // other way in this window
+  int e_cand = -1, e_spin = 0, e_slot = -1, e_flip = 0, e_twin = 0;
   if (lane < nE) {
     e_cand = gp(w.el_cand)[lane];
     e_spin = gp(w.el_s)[lane];
     e_slot = gp(w.el_slot)[lane];
+    e_flip = gp(w.el_flip)[lane];
   }
   if (t < nC) cid_s[t] = gp(w.cand_id)[t];
   int pos_r = -1, sa = 0, insl = 0;
@@ -902,7 +958,9 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
   int m = 0, kcur = k0, nins = 0, bad = 0, n_done = nP;
   double sign = uni(c->sign);
   long long next_id = uni(c->next_id), carry = -1;
-  long long n_ins = 0, n_rem = 0, n_mis = 0;
+  int carry_kind = 1;
+  long long n_ins = 0, n_rem = 0, n_mis = 0, n_flip = 0, n_neg = 0;
+  const int neglect = uni(w.neglect);
   // Proposals are settled in runs: every lane from the current proposal on
   // evaluates its own proposal against the current state (valid up to the
   // first accepted one, which is what changes the state); the run's
@@ -915,8 +973,10 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     const double facI = K_exp / (double)(kcur + 1), facR = (double)kcur / K_exp;
     const bool inr = lane >= j && lane < nP;
     const bool genrem = p_forced < 0 && p_kind == 1 && !p_carried;
+    const bool genflip = p_forced < 0 && p_kind == 2 && !p_carried;
     int q_l = p_el, idx_l = 0;
     bool cx = false, use_insl = false;
+    if (genflip && kcur <= 0) q_l = -1;   // flip at order 0: a no-op
     if (genrem) {
       if (kcur <= 0) {
         q_l = -1;                       // removal at order 0: a no-op
@@ -936,8 +996,15 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     const double d0_l = __hiloint2double(__shfl(__double2hiint(dg0), qs, 64), __shfl(__double2loint(dg0), qs, 64));
     const double d1_l = __hiloint2double(__shfl(__double2hiint(dg1), qs, 64), __shfl(__double2loint(dg1), qs, 64));
     if (genrem && kcur > 0 && !use_insl && p_el >= 0 && pq_l >= 0) cx = true;   // redraw needed
+    // a removal of a vertex flipped in this window, and every generator flip
+    // (its target search checks both kinds of change), take the uniform path
+    // (the shuffle runs in every lane: a lane that skipped it would not serve
+    // its value to the others)
+    const int tw_l = __shfl(e_twin, qs, 64);
+    if (genrem && kcur > 0 && !use_insl && p_el >= 0 && tw_l) cx = true;
+    if (genflip && kcur > 0) cx = true;
     const double sgn_l = (pq_l >= 0) ? -1.0 : 1.0;
-    const double R_l = ((p_kind == 0) ? facI : facR) * (sgn_l * d0_l) * (sgn_l * d1_l);
+    const double R_l = ((p_kind == 0) ? facI : (p_kind == 1) ? facR : 1.0) * (sgn_l * d0_l) * (sgn_l * d1_l);
     const int mine_l = p_u < fabs(R_l);
     const int dec_l = (q_l < 0) ? 0 : ((p_forced >= 0) ? p_forced : mine_l);
     if (q_l >= 0 && (!isfinite(R_l) || (dec_l && p_kind == 0 && kcur + 1 > max_order))) cx = true;
@@ -971,7 +1038,11 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     const int carried = lane_value(p_carried, j);
     q = el;
     int ab = 0;
-    if (forced < 0 && kind == 1 && !carried) {
+    if (forced < 0 && (kind == 1 || kind == 2) && !carried) {
+      // the target, uniform among the current vertices (R6); a flip's and a
+      // removal's targets alike, each with the element of its own kind
+      const int fl = kind == 2 ? 1 : 0;
+      int conflict = 0;
       q = -1;
       if (kcur > 0) {
         const long long gidx = lane_value(p_gidx, j);
@@ -987,13 +1058,20 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
             if (slot >= k0) slot = k0 - 1;
             int e = el;
             if (a > 0) {
-              const unsigned long long hit = __ballot(lane < nE && e_slot == slot);
+              const unsigned long long hit = __ballot(lane < nE && e_cand < 0 && e_slot == slot && e_flip == fl);
               e = hit ? (int)__ffsll((long long)hit) - 1 : -1;
             }
-            if (e >= 0 && lane_value(pos_r, e) >= 0) continue;     // already removed in this window
+            const bool tgt = lane < nE && e_cand < 0 && e_slot == slot && pos_r >= 0;
+            if (__ballot(tgt && !e_flip)) continue;     // removed in this window: redraw
+            if (!fl && __ballot(tgt && e_flip)) {      // a removal of a spin flipped in this window
+              conflict = 1;
+              carry = uni(gp(w.v_id)[slot]);
+              break;
+            }
             if (e < 0) {
               ab = 1;
               carry = uni(gp(w.v_id)[slot]);
+              carry_kind = kind;
               break;
             }
             q = e;
@@ -1002,9 +1080,25 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
           int idx = (int)(ui * (double)nins);
           if (idx >= nins) idx = nins - 1;
           q = lane_value(insl, idx);
+          if (fl) {                                     // a flip of a spin inserted in this window
+            conflict = 1;
+            carry = uni(cid_s[lane_value(e_cand, q)]);
+            q = -1;
+          }
           break;
         }
-        if (q < 0 && !ab) bad = 1;
+        if (q < 0 && !ab && !conflict) bad = 1;
+      }
+      if (conflict) {
+        // the spin is touched twice in this window: close the window before
+        // this proposal (exact), or reject it (neglect mode)
+        if (neglect) {
+          ++n_neg;
+          carry = -1;
+        } else {
+          ab = 1;
+          carry_kind = kind;
+        }
       }
     }
     if (ab) {
@@ -1020,7 +1114,7 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     sgn = (pq >= 0) ? -1.0 : 1.0;
     d0 = lane_value(dg0, q);
     d1 = lane_value(dg1, q);
-    const double fac = (kind == 0) ? facI : facR;
+    const double fac = (kind == 0) ? facI : (kind == 1) ? facR : 1.0;
     R = fac * (sgn * d0) * (sgn * d1);
     if (!isfinite(R)) {
       bad = 1;
@@ -1038,9 +1132,11 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     }
     ++j;
     if (!dec) continue;
-    kcur += (kind == 0) ? 1 : -1;
+    kcur += (kind == 0) ? 1 : (kind == 1) ? -1 : 0;
     if (R < 0.0) sign = -sign;
-    if (kind == 0) {
+    if (kind == 2) {
+      ++n_flip;           // a flip, or the unflip of a spin flipped in this window
+    } else if (kind == 0) {
       ++n_ins;
       if (forced < 0) {
         const int cq = lane_value(e_cand, q);
@@ -1107,6 +1203,12 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
       if (lane == js) sa = el_last;
       m = last;
     }
+    {
+      // the other-kind element of q's vertex learns whether q is in S
+      const int qslot = lane_value(e_slot, q), qcand = lane_value(e_cand, q), qflip = lane_value(e_flip, q);
+      const int qin = pq < 0 ? 1 : 0;
+      if (qcand < 0 && lane < nE && e_cand < 0 && e_slot == qslot && e_flip != qflip) e_twin = qin;
+    }
     __syncthreads();
     dg0 = T_s[0][lane * LS + lane];
     dg1 = T_s[1][lane * LS + lane];
@@ -1142,8 +1244,10 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
   // its value to the others)
   const int e_l = lane < m ? sa : 0;
   const int cand_l = __shfl(e_cand, e_l, 64), eslot_l = __shfl(e_slot, e_l, 64);
+  const int flip_l = __shfl(e_flip, e_l, 64);
   const bool isc = lane < m && cand_l >= 0;
-  const bool isr = lane < m && !isc;
+  const bool isf = lane < m && !isc && flip_l;      // flipped: stays, with s -> -s
+  const bool isr = lane < m && !isc && !flip_l;
   const unsigned long long cmask = __ballot(isc), rmask = __ballot(isr);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int mi = __popcll(cmask), mr = __popcll(rmask);
@@ -1160,6 +1264,7 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
       row_s[lane] = slot_l;
       rem[rank] = slot_l;
     }
+    if (isf) row_s[lane] = eslot_l;
   }
   __syncthreads();
   const int kx = k0 + mi;
@@ -1190,12 +1295,15 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
     c->n_prop += n_done;
     c->n_acc_ins += n_ins;
     c->n_acc_rem += n_rem;
+    c->n_acc_flip += n_flip;
+    c->n_neglect += n_neg;
     c->n_mismatch += n_mis;
     c->pos += n_done;
     c->n_windows += 1;
     c->m_hist[(m + 3) >> 2] += 1;
     if (carry >= 0) {
       c->carry_id = carry;
+      c->carry_kind = carry_kind;
       c->n_abort += 1;
     }
     {
@@ -1238,6 +1346,10 @@ __global__ void __launch_bounds__(AW) k_accept(const View<T>* __restrict__ vs) {
   const auto v_site = gp(w.v_site), v_s = gp(w.v_s);
   const auto v_tau = gp(w.v_tau);
   const auto v_id = gp(w.v_id);
+  // flipped vertices keep their slots with the opposite auxiliary spin (the
+  // fold's factors use the element's spin from before the window)
+  if (w0 && isf) v_s[eslot_l] = -v_s[eslot_l];
+  __syncthreads();
   // window-start vertices that fill holes keep their values: read them
   // before the inserted spins land on slots >= k0
   int h_site = 0, h_s = 0;
@@ -1482,7 +1594,7 @@ __global__ void __launch_bounds__(256) k_ygemm_t(const View<T>* __restrict__ vs)
 // inserted spins at rows k0 .. k0+mi-1), for N' = N + A B with
 // A = (E_S - G_{.S}) diag(-Delta_S) and B = Gt_S^{-1} N_{S.}:
 //   rows < k0 of A: an inserted spin c gives Delta_c (N g_{I,c}), a removed
-//     vertex p gives e_p - N_{.p};
+//     vertex p gives e_p - N_{.p}, a flipped one (1 + e^{-V_p})(e_p - N_{.p});
 //   B with the rows of the extended N (X_c for the inserted spins).
 // The rows of the inserted spins come out of the fold as B itself: for x in
 // S, Gt_{x,S} Gt_S^{-1} = e_x, so X_x + (e_x - Gt_{x,S}) B = B_x exactly.
@@ -1490,6 +1602,12 @@ __global__ void __launch_bounds__(256) k_ygemm_t(const View<T>* __restrict__ vs)
 // whenever the new row is small (e^{V_x} - 1 large), and those errors grow
 // in later windows.  So A is zero on the inserted rows and B_x is stored
 // there directly; on the rows < k0 the inserted columns (e_{k0+j}) are zero.
+// The same holds for the row p of a flipped spin (row p of A is
+// e_p - Gt_{p,S}): its folded row is B_p, which the sum would reach only
+// through a cancellation of terms up to (1 + e^{gamma}) |N| (flips towards
+// e^{V} = e^{gamma}); so A is zero on flipped rows too and B_p is stored
+// there, over every column (the inserted ones included).  No workgroup reads
+// a flipped row of N here, so the stores cannot race with the loads of A.
 // A workgroup covers 64 columns; its four wavefronts share the S rows.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs) {
@@ -1503,8 +1621,8 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
   if ((int)blockIdx.x * 64 >= kx) return;
   __shared__ double gi_s[KS_MAX * KS_MAX];
   __shared__ double rv_s[KS_MAX][64];
-  __shared__ int e_s[KS_MAX], row_s[KS_MAX], cand_s[KS_MAX], slot_s[KS_MAX];
-  __shared__ double d_s[KS_MAX];
+  __shared__ int e_s[KS_MAX], row_s[KS_MAX], cand_s[KS_MAX], slot_s[KS_MAX], flip_s[KS_MAX];
+  __shared__ double d_s[KS_MAX], f_s[KS_MAX];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   {
     // Gt_S^{-1} rows into LDS, the loads of eight entries per thread together
@@ -1530,6 +1648,11 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
     cand_s[t] = w.el_cand[e];
     slot_s[t] = w.el_slot[e];
     d_s[t] = w.ev[sp][s01(w.el_s[e])] - 1.0;
+    // a target's column of A is f (e_p - N_{.p}): f = 1 for a removal,
+    // -Delta_p e^{V_p} / (e^{V_p} - 1) = 1 + e^{-V_p} for a flip (the
+    // element's spin is the one before the window)
+    f_s[t] = w.el_flip[e] ? 1.0 + w.ev[sp][1 - s01(w.el_s[e])] : 1.0;
+    flip_s[t] = w.el_flip[e];
   }
   __syncthreads();
   const T* R = w.R[sp];
@@ -1547,6 +1670,11 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
     const bool live = i < kx;
     const int ic = live ? i : 0;
     const int il = (ic < k0) ? ic : 0;
+    // row i is the slot of a flipped spin: its row of A is zero and no entry
+    // of it is read (the B phase stores it)
+    bool frow = false;
+    if (live && i < k0)
+      for (int q = 0; q < m; ++q) frow |= flip_s[q] && slot_s[q] == i;
     for (int q0 = wv; q0 < m; q0 += 8 * NWV) {
       T rv[8], tv[8];
 #pragma unroll
@@ -1554,8 +1682,10 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
         const int q = q0 + u * NWV;
         const int sc = q < m ? q : q0;
         rv[u] = R[(size_t)e_s[sc] * w.cap + il];
-        // rows < k0 of A: Y for a candidate, column p of N for a removed vertex
-        tv[u] = (cand_s[sc] >= 0) ? Y[(size_t)(row_s[sc] - k0) * w.cap + il] : N[il + (size_t)slot_s[sc] * ld];
+        // rows < k0 of A: Y for a candidate, column p of N for a removed or
+        // flipped vertex
+        tv[u] = (cand_s[sc] >= 0) ? Y[(size_t)(row_s[sc] - k0) * w.cap + il]
+                                  : (frow ? (T)0 : N[il + (size_t)slot_s[sc] * ld]);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -1568,19 +1698,20 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
         if (live && q < m) {
           // A, column-major [s][i]; zero on the inserted rows
           double v = 0.0;
-          if (i < k0) v = (cand_s[q] >= 0) ? d_s[q] * (double)tv[u] : (i == slot_s[q] ? 1.0 : 0.0) - (double)tv[u];
+          if (i < k0 && !frow)
+            v = (cand_s[q] >= 0) ? d_s[q] * (double)tv[u] : f_s[q] * ((i == slot_s[q] ? 1.0 : 0.0) - (double)tv[u]);
           Ag[(size_t)q * w.cap + i] = (T)v;
         }
         // inserted columns of the rows < k0 (no workgroup reads columns >= k0
-        // of N here)
-        if (live && i < k0 && q < mi) N[i + (size_t)(k0 + q) * ld] = (T)0;
+        // of N here); a flipped row gets them from B
+        if (live && i < k0 && q < mi && !frow) N[i + (size_t)(k0 + q) * ld] = (T)0;
       }
     }
     __syncthreads();
     if (live) {
       // B, row-major [a][i] = sum_b Gt^{-1}[a][b] Row_{S_b}[i], four rows a
-      // per pass over rv_s (each sum runs over b in order); an inserted
-      // spin's row of B is also its row of the folded N
+      // per pass over rv_s (each sum runs over b in order); an inserted or
+      // flipped spin's row of B is also its row of the folded N
       for (int a0 = wv; a0 < m; a0 += 4 * NWV) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         int ar[4];
@@ -1596,7 +1727,7 @@ __global__ void __launch_bounds__(WG) k_fold_prep(const View<T>* __restrict__ vs
           const int a = a0 + u * NWV;
           if (a < m) {
             Bg[(size_t)a * w.cap + i] = (T)acc[u];
-            if (cand_s[a] >= 0) N[row_s[a] + (size_t)i * ld] = (T)acc[u];
+            if (cand_s[a] >= 0 || flip_s[a]) N[row_s[a] + (size_t)i * ld] = (T)acc[u];
           }
         }
       }

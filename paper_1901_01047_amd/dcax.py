@@ -40,7 +40,8 @@ class Params(ctypes.Structure):
                 ("refresh_every", ctypes.c_int32), ("max_order", ctypes.c_int32), ("n_freq", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("warmup_sweeps", ctypes.c_int32), ("sweep_length", ctypes.c_int32),
                 ("n_spin_tables", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("g0_tau", ctypes.c_void_p), ("g0_Kw", ctypes.c_void_p)]
+                ("g0_tau", ctypes.c_void_p), ("g0_Kw", ctypes.c_void_p),
+                ("flip_share", ctypes.c_double), ("touched_twice", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class Vertex(ctypes.Structure):
@@ -65,7 +66,8 @@ class Stats(ctypes.Structure):
                 ("last_drift", ctypes.c_double), ("max_drift", ctypes.c_double),
                 ("windows_enqueued", ctypes.c_int64), ("fold_rank_hist", ctypes.c_int64 * 17),
                 ("cand_flops", ctypes.c_double), ("cand_bytes", ctypes.c_double), ("cand_seconds", ctypes.c_double),
-                ("y_flops", ctypes.c_double), ("y_bytes", ctypes.c_double), ("y_seconds", ctypes.c_double)]
+                ("y_flops", ctypes.c_double), ("y_bytes", ctypes.c_double), ("y_seconds", ctypes.c_double),
+                ("accepted_flips", ctypes.c_int64), ("neglected", ctypes.c_int64)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -143,7 +145,8 @@ def _check(st):
 
 def make_params(cluster=(2, 0, 0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0, K_exp=1.0, n_tau=1000,
                 precision=DCAX_FP64, submatrix_k=16, refresh_every=0, max_order=512, n_freq=64,
-                seed=985456376, warmup_sweeps=20, sweep_length=0, g0_tau=None, g0_Kw=None):
+                seed=985456376, warmup_sweeps=20, sweep_length=0, g0_tau=None, g0_Kw=None, flip_share=0.0,
+                touched_twice=0):
     """g0_tau: optional bare propagator tables, float64 [n_spin_tables][Nc][n_tau]
     (or [Nc][n_tau] for one table) in the standard convention; g0_Kw: optional
     complex128 [n_spin_tables][Nc][n_freq] G0(K, i w_n) for finalize.  The
@@ -157,6 +160,7 @@ def make_params(cluster=(2, 0, 0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0, K_
     p.n_tau, p.precision, p.submatrix_k = n_tau, precision, submatrix_k
     p.refresh_every, p.max_order, p.n_freq, p.seed = refresh_every, max_order, n_freq, seed
     p.warmup_sweeps, p.sweep_length = warmup_sweeps, sweep_length
+    p.flip_share, p.touched_twice = flip_share, touched_twice
     keep = []
     if g0_tau is not None:
         t = np.ascontiguousarray(g0_tau, dtype=np.float64)

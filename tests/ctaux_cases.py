@@ -49,3 +49,31 @@ def oracle_trace(m, seed, k_s, init_order, warm_sweeps, rec_proposals, init=None
         w.step()
     rec, ratios = records(w.trace)
     return init, rec, ratios, w
+
+
+def exact_replay_with_flip_conditioning(m, init, rec):
+    """The extended-precision replay of records (oracle.exact) plus, per
+    record, the relative condition number of its ratio with respect to the
+    diagonal entries of N it is computed from: 1 for insertions and removals,
+    and for a flip of the spin at row p, per spin rho = (1 + e^{-V_p}) N_pp -
+    e^{-V_p} (the flip ratio read off N) with condition
+    ((1 + e^{-V_p}) |N_pp| + e^{-V_p}) / |rho|, summed over the two spins
+    (a flip towards e^{V'} = e^{gamma} is a difference of terms of size
+    e^{gamma} N_pp).  Returns (ratios, chain, kappa)."""
+    from oracle import exact
+    ch = exact.ExactChain(m, *init)
+    out, kap = [], []
+    for x in rec:
+        kind, vid = int(x["kind"]), int(x["id"])
+        k = 1.0
+        if kind == 2 and vid >= 0:
+            p = int(np.nonzero(ch.id == vid)[0][0])
+            k = 0.0
+            for sp in (0, 1):
+                emv = 1.0 / float(ch.ev(ch.s[p], sp))
+                npp = float(ch.N[sp][p, p])
+                rho = (1.0 + emv) * npp - emv
+                k += ((1.0 + emv) * abs(npp) + emv) / abs(rho)
+        out.append(ch.step(kind, int(x["site"]), float(x["tau"]), int(x["aux_spin"]), vid, int(x["accepted"])))
+        kap.append(max(k, 1.0))
+    return np.array(out), ch, np.array(kap)

@@ -58,14 +58,24 @@ int main(int argc, char** argv) {
     int nC = std::min(ks, (int)(rng() % (ks + 1)));
     int nR = std::min(64 - nC, std::min(k0, (int)(rng() % 40)));
     if (cs % 4 == 0) { nC = std::min(ks, 64); nR = std::min(64 - nC, k0); }
+    // tiny orders with both kinds of target element for every vertex (so
+    // that removals and flips of one vertex meet in a window)
+    const bool twins = k0 > 0 && k0 < 6 && cs % 3 != 0;
+    if (twins) { nC = std::min(nC, 64 - 2 * k0); nR = 2 * k0; }
     const int nE = nC + nR;
-    v.el_cand = arr<int>(KS_MAX, -1); v.el_slot = arr<int>(KS_MAX, -1);
+    v.el_cand = arr<int>(KS_MAX, -1); v.el_slot = arr<int>(KS_MAX, -1); v.el_flip = arr<int>(KS_MAX, 0);
+    v.neglect = (cs % 4 == 2) ? 1 : 0;
     v.el_s = arr<int>(KS_MAX, 1); v.el_site = arr<int>(KS_MAX, 0); v.el_tau = arr<double>(KS_MAX, 0.0);
     std::vector<int> slots(k0);
     for (int i = 0; i < k0; ++i) slots[i] = i;
     std::shuffle(slots.begin(), slots.end(), rng);
     for (int e = 0; e < nC; ++e) { v.el_cand[e] = e; v.el_s[e] = (rng() & 1) ? 1 : -1; v.el_site[e] = rng() % 16; v.el_tau[e] = U(); }
-    for (int e = nC; e < nE; ++e) v.el_slot[e] = slots[e - nC];
+    for (int e = nC; e < nE && !twins; ++e) v.el_slot[e] = slots[e - nC];
+    // a share of the window-start targets are spin-flip elements
+    if (cs % 3 != 0)
+      for (int e = nC; e < nE; ++e) v.el_flip[e] = (rng() % 3 == 0) ? 1 : 0;
+    if (twins)
+      for (int e = nC; e < nE; ++e) { v.el_slot[e] = (e - nC) % k0; v.el_flip[e] = (e - nC) >= k0; }
     for (int sp = 0; sp < 2; ++sp) {
       v.gram[sp] = arr<double>(KS_MAX * KS_MAX, 0.0);
       for (int i = 0; i < nE; ++i)
@@ -78,6 +88,7 @@ int main(int argc, char** argv) {
     v.remap = arr<int>(cap, -1); v.moves = arr<int>(2 * KS_MAX + 1, -1);
     v.v_site = arr<int>(cap, -7); v.v_tau = arr<double>(cap, -7.0); v.v_s = arr<int>(cap, 0); v.v_id = arr<long long>(cap, -7);
     for (int i = 0; i < k0; ++i) { v.v_site[i] = rng() % 16; v.v_tau[i] = U(); v.v_s[i] = (rng() & 1) ? 1 : -1; v.v_id[i] = 5000 + i; }
+    std::vector<int> s_before(v.v_s, v.v_s + k0);
     // proposals
     const int nP = ks;
     v.wp = new WinProp[KS_MAX];
@@ -92,16 +103,21 @@ int main(int argc, char** argv) {
       const bool ins = next_c < nC && (rng() % 3 != 0);
       if (ins) { p.kind = 0; p.el = next_c++; }
       else {
-        p.kind = 1;
+        p.kind = (cs % 3 != 0 && rng() % 2) ? 2 : 1;
         p.ub0 = U(); p.ui0 = U();
         int slot = k0 ? std::min((int)(p.ui0 * k0), k0 - 1) : 0;
         p.el = -1;
-        for (int e = nC; e < nE; ++e) if (v.el_slot[e] == slot) p.el = e;
+        for (int e = nC; e < nE; ++e) if (v.el_slot[e] == slot && v.el_flip[e] == (p.kind == 2)) p.el = e;
         if (replay) {
-          // target: an unflipped window-start element or a flipped candidate
+          // removal: a window-start removal element not yet removed, or an
+          // inserted candidate; flip: any flip element (a second flip undoes it)
           std::vector<int> opts;
-          for (int e = nC; e < nE; ++e) if (!flipped[e]) opts.push_back(e);
-          for (int e = 0; e < nC; ++e) if (flipped[e]) opts.push_back(e);
+          if (p.kind == 1) {
+            for (int e = nC; e < nE; ++e) if (!v.el_flip[e] && !flipped[e]) opts.push_back(e);
+            for (int e = 0; e < nC; ++e) if (flipped[e]) opts.push_back(e);
+          } else {
+            for (int e = nC; e < nE; ++e) if (v.el_flip[e]) opts.push_back(e);
+          }
           p.el = opts.empty() ? -1 : opts[rng() % opts.size()];
         }
       }
@@ -110,7 +126,8 @@ int main(int argc, char** argv) {
         if (p.el >= 0 && p.forced) flipped[p.el] ^= 1;
       }
     }
-    if (!replay && cs % 3 == 1) v.wp[0].carried = 1, v.wp[0].kind = 1, v.wp[0].el = nE > nC ? nC : -1;
+    if (!replay && cs % 3 == 1)      // a carried target keeps the kind its element was prepared for
+      v.wp[0].carried = 1, v.wp[0].el = nE > nC ? nC : -1, v.wp[0].kind = (nE > nC && v.el_flip[nC]) ? 2 : 1;
     v.ratio_out = replay ? arr<double>(nP, NAN) : nullptr;
     if (!replay) for (int j = 0; j < nP; ++j) v.wp[j].ridx = -1;
     c->k = k0; c->active = 1; c->nP = nP; c->nE = nE; c->nC = nC; c->k0 = k0; c->next_id = 1000000;
@@ -132,7 +149,17 @@ int main(int argc, char** argv) {
       // vertex arrays: the survivors of the window start plus the inserted spins
       std::vector<long long> want, got(v.v_id, v.v_id + c->knew);
       std::vector<char> rm(k0, 0);
-      for (int a = 0; a < c->m; ++a) { int e = v.S[a]; if (v.el_cand[e] < 0) rm[v.el_slot[e]] = 1; }
+      for (int a = 0; a < c->m; ++a) { int e = v.S[a]; if (v.el_cand[e] < 0 && !v.el_flip[e]) rm[v.el_slot[e]] = 1; }
+      // flipped vertices keep their slots with the opposite spin (before compaction moves them)
+      std::vector<char> fl(k0, 0);
+      for (int a = 0; a < c->m; ++a) { int e = v.S[a]; if (v.el_cand[e] < 0 && v.el_flip[e]) fl[v.el_slot[e]] = 1; }
+      for (int d = 0; d < c->knew; ++d) {
+        long long id = v.v_id[d];
+        if (id >= 5000 && id < 5000 + k0) {
+          int i = (int)(id - 5000);
+          if (v.v_s[d] != (fl[i] ? -s_before[i] : s_before[i])) { printf("case %d: flipped spin of %d\n", cs, i); ok = false; break; }
+        }
+      }
       for (int i = 0; i < k0; ++i) if (!rm[i]) want.push_back(5000 + i);
       for (int a = 0; a < c->mi; ++a) want.push_back(v.cand_id[v.el_cand[v.ins_el[a]]]);
       std::sort(want.begin(), want.end()); std::sort(got.begin(), got.end());
@@ -163,11 +190,11 @@ int main(int argc, char** argv) {
         std::vector<int> S2 = S;
         if (it == S.end()) S2.push_back(q); else S2.erase(S2.begin() + (it - S.begin()));
         for (int sp = 0; sp < 2; ++sp) r[sp] = detS(v.gram[sp], S2) / detS(v.gram[sp], S);
-        double fac = p.kind == 0 ? 1.0 / (kcur + 1) : (double)kcur;
+        double fac = p.kind == 0 ? 1.0 / (kcur + 1) : p.kind == 1 ? (double)kcur : 1.0;
         double R = fac * r[0] * r[1];
         double e = std::fabs(R - v.ratio_out[j]) / std::max(1.0, std::fabs(R));
         if (!(e < 1e-10)) { printf("case %d: ratio %d ref %.15g got %.15g\n", cs, j, R, v.ratio_out[j]); ok = false; break; }
-        if (p.forced) { S = S2; kcur += p.kind == 0 ? 1 : -1; }
+        if (p.forced) { S = S2; kcur += p.kind == 0 ? 1 : p.kind == 1 ? -1 : 0; }
       }
     }
     if (c->active && m > 0 && c->status == 0) {
@@ -181,9 +208,9 @@ int main(int argc, char** argv) {
             if (std::fabs(s - (a == b)) > 1e-9) { printf("case %d: ginv check %d %d %g\n", cs, a, b, s); ok = false; a = m; break; }
           }
     }
-    printf("case %2d %s ks=%2d k0=%3d nC=%2d nE=%2d nP=%2d done=%lld m=%d mi=%d mr=%d knew=%d abort=%lld %s\n", cs,
-           replay ? "replay" : "gen   ", ks, k0, nC, nE, nP, c->n_prop, c->m, c->mi, c->mr, c->knew, c->n_abort,
-           ok ? "ok" : "FAIL");
+    printf("case %2d %s ks=%2d k0=%3d nC=%2d nE=%2d nP=%2d done=%lld m=%d mi=%d mr=%d knew=%d abort=%lld flips=%lld "
+           "neglected=%lld %s\n", cs, replay ? "replay" : "gen   ", ks, k0, nC, nE, nP, c->n_prop, c->m, c->mi, c->mr,
+           c->knew, c->n_abort, c->n_acc_flip, c->n_neglect, ok ? "ok" : "FAIL");
     fails += !ok;
   }
   printf("%d failures\n", fails);

@@ -60,7 +60,9 @@ def test_struct_layouts_match_header(tmp_path):
 @pytest.mark.parametrize("field,value", [("abi_version", 7), ("beta", -1.0), ("U", -0.5), ("K_exp", 0.0),
                                          ("n_tau", 1), ("precision", 5), ("submatrix_k", 0),
                                          ("submatrix_k", 65), ("max_order", 0), ("n_freq", -1),
-                                         ("refresh_every", -3), ("warmup_sweeps", -1), ("sweep_length", -2)])
+                                         ("refresh_every", -3), ("warmup_sweeps", -1), ("sweep_length", -2),
+                                         ("flip_share", -0.1), ("flip_share", 1.0), ("flip_share", float("nan")),
+                                         ("touched_twice", 2), ("touched_twice", -1), ("reserved2", 1)])
 def test_create_rejects_bad_params(lib, field, value):
     p = dcax.make_params()
     setattr(p, field, value)

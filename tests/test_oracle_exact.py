@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 from oracle import ctaux, exact
-from paper_1901_01047_amd.workloads import CONFIGS
+from paper_1901_01047_amd.workloads import CONFIGS, initial_config
 from tests.ctaux_cases import model, oracle_trace
 from tests.test_submatrix_algebra import WindowModel
 
@@ -37,10 +37,13 @@ def _mp_det(Ainv_rows):
     return mpmath.det(mpmath.matrix(Ainv_rows))
 
 
-def test_ratios_equal_40_digit_determinants():
+@pytest.mark.parametrize("p_flip", [0.0, 0.4])
+def test_ratios_equal_40_digit_determinants(p_flip):
+    """With p_flip > 0 the chain also flips auxiliary spins (weight ratio
+    with no order factor)."""
     mpmath.mp.dps = 40
     m = ctaux.Model(a1=(2, 0), a2=(0, 2), U=4.0, beta=3.0, n_tau=400)
-    w = ctaux.Walker(m, seed=5, k_s=4)
+    w = ctaux.Walker(m, seed=5, k_s=4, p_flip=p_flip)
     w.random_config(4)
     init = (w.r.copy(), w.t.copy(), w.s.copy(), w.id.copy())
     w.record = True
@@ -60,8 +63,8 @@ def test_ratios_equal_40_digit_determinants():
 
     checked = 0
     for x in rec:
-        if x["kind"] == 1 and x["id"] < 0:
-            ch.step(1, 0, 0.0, 1, -1, 0)
+        if x["kind"] >= 1 and x["id"] < 0:
+            ch.step(int(x["kind"]), 0, 0.0, 1, -1, 0)
             continue
         k0 = ch.k
         w0 = weight(ch)
@@ -69,13 +72,16 @@ def test_ratios_equal_40_digit_determinants():
         # the configuration after the proposal, whatever the recorded decision
         R = ch.step(int(x["kind"]), int(x["site"]), float(x["tau"]), int(x["aux_spin"]), int(x["id"]), 1)
         w1 = weight(ch)
-        fac = mpmath.mpf(m.K_exp) / (k0 + 1) if x["kind"] == 0 else mpmath.mpf(k0) / m.K_exp
+        fac = (mpmath.mpf(m.K_exp) / (k0 + 1) if x["kind"] == 0 else mpmath.mpf(k0) / m.K_exp if x["kind"] == 1
+               else mpmath.mpf(1))
         want = fac * w1 / w0
         assert abs(mpmath.mpf(R) - want) <= 1e-15 * abs(want), (R, want)
         checked += 1
         if not x["accepted"]:
             ch.r, ch.t, ch.s, ch.id, ch.N = before
     assert checked > 40
+    if p_flip:
+        assert (rec["kind"] == 2).sum() > 10
 
 
 def test_propagator_matches_the_oracle_interpolation():
@@ -90,6 +96,36 @@ def test_propagator_matches_the_oracle_interpolation():
 
 
 REPLAYS = [("2x2_U4_b5", 16, 20, 30, 800), ("4x4_U4_b10", 32, 280, 10, 700), ("4x4_U4_b10", 64, 280, 10, 700)]
+
+
+@pytest.mark.parametrize("name,k_init,warm", [("2x2_U4_b5", 20, 20), ("4x4_U4_b10", 220, 2)])
+def test_fp64_oracle_with_flips_meets_1e10(name, k_init, warm):
+    """The FP64 oracle's flip ratio 1 + c (1 - N_pp) and its Sherman-Morrison
+    update against the extended-precision chain's 1 + (N d)_p over the
+    explicit column change: two forms of the determinant lemma, within 1e-10
+    on every ratio of a chain with 30% flips (aligned-spin start)."""
+    m = model(name)
+    w = ctaux.Walker(m, seed=CONFIGS[name]["seed"] + 3, k_s=32, p_flip=0.3)
+    w.set_config(*initial_config(m.Nc, m.beta, k_init, 17))
+    for _ in range(warm):
+        w.sweep()
+    w.refresh()
+    init = (w.r.copy(), w.t.copy(), w.s.copy(), w.id.copy())
+    w.record = True
+    for _ in range(600):
+        w.step()
+    from tests.ctaux_cases import records
+    rec, ro = records(w.trace)
+    rx, ch = exact.replay(m, init, rec)
+    good = ~((rec["kind"] >= 1) & (rec["id"] < 0))
+    rel = np.abs(ro[good] - rx[good]) / np.abs(rx[good])
+    assert ((rec["kind"] == 2) & (rec["accepted"] == 1)).sum() > 10
+    assert rel.max() < 1e-10
+    ids_x, Xu, Xd = ch.canonical()
+    ids_o, Nu, Nd = w.canonical()
+    assert np.array_equal(ids_x, ids_o)
+    for A, X in ((Nu, Xu), (Nd, Xd)):
+        assert float(np.max(np.abs(A.astype(LD) - X)) / np.max(np.abs(X))) < 1e-10
 
 
 @pytest.mark.parametrize("name,k_s,k_init,warm,n_rec", REPLAYS)

@@ -23,7 +23,12 @@ which is finite everywhere:
   a removed vertex is exactly e_p - N_{.p} (since (-Delta_p) e^{V_p} /
   (e^{V_p} - 1) = 1), that of an inserted spin -Delta_c (e_c - G_{.c});
 * the column of Gt for a removed vertex p is N_ext{x,p} itself, from
-  G (e^V - 1) = N e^V - 1.
+  G (e^V - 1) = N e^V - 1; for a flipped vertex (V_p -> -V_p) it is
+  (1 + e^{-V_p}) N_ext{x,p} - delta_xp e^{-V_p}, and its scaled column of the
+  fold (1 + e^{-V_p}) (e_p - N_{.p});
+* for x in S, row x of (E_S - G_{.S}) diag(-Delta) is e_x - Gt_{x,S}, so the
+  folded row x is B_x exactly: inserted and flipped rows are taken from B
+  (the sum would cancel terms up to (1 + e^{gamma}) |N| for a flip).
 
 ``WindowModel`` is a NumPy transcription of the kernel pipeline (gathers,
 candidate rows, scaled Gram matrix of the window, sequential Schur loop,
@@ -36,6 +41,7 @@ import numpy as np
 import pytest
 
 from oracle import ctaux
+from tests.ctaux_cases import exact_replay_with_flip_conditioning, records
 
 
 def test_gamma_identities_random():
@@ -115,32 +121,51 @@ class WindowModel:
         return self.m.ev(s, sp)
 
     def window(self, props):
-        """props: list of (kind, site, tau, s, id, accepted)."""
+        """props: list of (kind, site, tau, s, id, accepted), kind 0 insertion,
+        1 removal, 2 flip of an auxiliary spin.  A proposal that would change
+        a spin the window has already changed otherwise (a flip of a spin
+        inserted in the window, a removal of a flipped one) ends the window
+        before it; returns the number of proposals taken."""
         m = self.m
         k0 = len(self.r)
         slot_of = {int(v): i for i, v in enumerate(self.id)}
         # -- element list: candidates and window-start targets --------------
-        el_r, el_t, el_s, el_slot = [], [], [], []      # slot -1 for candidates
+        el_r, el_t, el_s, el_slot, el_flip = [], [], [], [], []      # slot -1 for candidates
         cand_of_id = {}
         prop_el = []
+        on = []
         for (kind, site, tau, sq, vid, acc) in props:
             if kind == 0:
                 prop_el.append(len(el_r))
-                el_r.append(site); el_t.append(tau); el_s.append(sq); el_slot.append(-1)
+                el_r.append(site); el_t.append(tau); el_s.append(sq); el_slot.append(-1); el_flip.append(0)
+                on.append(0)
                 if acc:
                     cand_of_id[int(vid)] = prop_el[-1]
             else:
+                fl = int(kind == 2)
                 if int(vid) in cand_of_id:
+                    if fl:
+                        break
                     prop_el.append(cand_of_id[int(vid)])
-                    continue
-                p = slot_of[int(vid)]
-                if p in el_slot:
-                    prop_el.append(el_slot.index(p))
-                    continue
-                prop_el.append(len(el_r))
-                el_r.append(self.r[p]); el_t.append(self.t[p]); el_s.append(self.s[p]); el_slot.append(p)
+                else:
+                    p = slot_of[int(vid)]
+                    mine = [e for e in range(len(el_r)) if el_slot[e] == p and el_flip[e] == fl]
+                    twin = [e for e in range(len(el_r)) if el_slot[e] == p and el_flip[e] != fl]
+                    if twin and on[twin[0]]:
+                        assert not fl, "a flip of a vertex the window removed"
+                        break
+                    if mine:
+                        prop_el.append(mine[0])
+                    else:
+                        prop_el.append(len(el_r))
+                        el_r.append(self.r[p]); el_t.append(self.t[p]); el_s.append(self.s[p]); el_slot.append(p)
+                        el_flip.append(fl)
+                        on.append(0)
+            if acc:
+                on[prop_el[-1]] ^= 1
+        props = props[:len(prop_el)]
         nE = len(el_r)
-        el_r, el_t, el_s, el_slot = map(np.array, (el_r, el_t, el_s, el_slot))
+        el_r, el_t, el_s, el_slot, el_flip = map(np.array, (el_r, el_t, el_s, el_slot, el_flip))
         cand = el_slot < 0
         ci = np.where(cand)[0]
         ti = np.where(~cand)[0]
@@ -164,8 +189,14 @@ class WindowModel:
             Gm[np.ix_(ci, ci)] += gCC
             Gm[:, ci] *= -Dc[None, :]
             Gm[ci, ci] += 1.0 + Dc
-            # columns of existing vertices p: Gt_{x,p} = N_ext{x,p}
+            # columns of existing vertices p: Gt_{x,p} = N_ext{x,p} for a
+            # removal, (1 + e^{-V_p}) N_ext{x,p} - delta_xp e^{-V_p} for a flip
             Gm[:, ti] = R[:, tslot]
+            fi = ti[el_flip[ti] == 1]
+            if len(fi):
+                emv = 1.0 / self.ev(el_s[fi], sp)
+                Gm[:, fi] *= (1.0 + emv)[None, :]
+                Gm[fi, fi] -= emv
             Rw.append(R)
             Gram.append(Gm)
         # -- sequential Schur loop ---------------------------------------
@@ -173,7 +204,8 @@ class WindowModel:
         S, Ginv = loop(props, prop_el, Gram, k0)
         # -- fold in the extended space, then compaction --------------------
         ins = [q for q in S if cand[q]]
-        rem = [el_slot[q] for q in S if not cand[q]]
+        rem = [el_slot[q] for q in S if not cand[q] and not el_flip[q]]
+        flips = [el_slot[q] for q in S if el_flip[q]]
         mi = len(ins)
         kx = k0 + mi
         row_of = {}
@@ -204,23 +236,38 @@ class WindowModel:
                         e = np.zeros(kx)
                         e[p] = 1.0
                         A[:, j] = e - Next[:, p]
-                # the inserted rows of the result are rows of B (for x in S,
+                        if el_flip[q]:
+                            A[:, j] *= 1.0 + 1.0 / self.ev(el_s[q], sp)
+                # the inserted and the flipped rows of the result are rows of
+                # B (for x in S, row x of A is e_x - Gt_{x,S} and
                 # Gt_{x,S} Gt_S^{-1} = e_x): A is zero there
                 A[k0:, :] = 0.0
+                for q in S:
+                    if el_flip[q]:
+                        A[el_slot[q], :] = 0.0
                 rows = [row_of[q] for q in S]
                 B = Ginv[sp] @ Next[rows, :]
                 Next = Next + A @ B
                 for j, q in enumerate(S):
-                    if cand[q]:
+                    if cand[q] or el_flip[q]:
                         Next[row_of[q], :] = B[j, :]
             keep = np.array([i for i in range(kx) if i not in rem], dtype=int)
             self.N[sp] = Next[np.ix_(keep, keep)]
         new_r = np.concatenate([self.r, el_r[ins]])
         new_t = np.concatenate([self.t, el_t[ins]])
-        new_s = np.concatenate([self.s, el_s[ins]])
+        s_now = self.s.copy()
+        s_now[flips] = -s_now[flips]
+        new_s = np.concatenate([s_now, el_s[ins]])
         new_id = np.concatenate([self.id, np.array([cand_id[q] for q in ins], dtype=self.id.dtype)])
         keep = np.array([i for i in range(kx) if i not in rem], dtype=int)
         self.r, self.t, self.s, self.id = new_r[keep], new_t[keep], new_s[keep], new_id[keep]
+        return len(props)
+
+    def run(self, props, k_s):
+        """Windows of at most k_s proposals until every proposal is taken."""
+        i = 0
+        while i < len(props):
+            i += self.window(props[i:i + k_s])
 
     def _border_loop(self, props, prop_el, Gram, kcur):
         """Inverse over S grown by bordering and shrunk by a rank-1 downdate."""
@@ -241,7 +288,7 @@ class WindowModel:
                     schur = Gram[sp][q, q] - gqS @ L
                     rat.append(schur)
                     parts.append((L, Rr, schur))
-            fac = m.K_exp / (kcur + 1) if kind == 0 else kcur / m.K_exp
+            fac = m.K_exp / (kcur + 1) if kind == 0 else kcur / m.K_exp if kind == 1 else 1.0
             self.ratios.append(fac * rat[0] * rat[1])
             if not acc:
                 continue
@@ -264,7 +311,7 @@ class WindowModel:
                     B[n, n] = 1.0 / schur
                     Ginv[sp] = B
                 S.append(q)
-            kcur += 1 if kind == 0 else -1
+            kcur += 1 if kind == 0 else -1 if kind == 1 else 0
         return S, Ginv
 
     def _sweep_loop(self, props, prop_el, Gram, kcur):
@@ -278,7 +325,7 @@ class WindowModel:
         for (kind, site, tau, sq, vid, acc), q in zip(props, prop_el):
             sgn = -1.0 if q in S else 1.0
             rat = [sgn * T[sp][q, q] for sp in (0, 1)]
-            fac = self.m.K_exp / (kcur + 1) if kind == 0 else kcur / self.m.K_exp
+            fac = self.m.K_exp / (kcur + 1) if kind == 0 else kcur / self.m.K_exp if kind == 1 else 1.0
             self.ratios.append(fac * rat[0] * rat[1])
             if not acc:
                 continue
@@ -296,7 +343,7 @@ class WindowModel:
                 S.pop()
             else:
                 S.append(q)
-            kcur += 1 if kind == 0 else -1
+            kcur += 1 if kind == 0 else -1 if kind == 1 else 0
         return S, [-T[sp][np.ix_(S, S)] for sp in (0, 1)]
 
     def canonical(self):
@@ -343,3 +390,46 @@ def test_window_model_replays_oracle(k_s, seed, U, schur):
         assert n_unflip > 0      # the exact "spin touched twice" path was exercised
     if U == 0.0:
         assert np.array_equal(Nu2, np.eye(len(ids2))) and np.array_equal(Nd2, np.eye(len(ids2)))
+
+
+@pytest.mark.parametrize("k_s,seed", [(16, 5), (32, 6), (64, 7)])
+def test_window_model_replays_oracle_with_flips(k_s, seed):
+    """Flips of auxiliary spins in the window: the flip element's Gram column
+    (1 + e^{-V_p}) N_ext{x,p} - delta_xp e^{-V_p} and fold column
+    (1 + e^{-V_p}) (e_p - N_{.p}) reproduce the single-spin chain; windows
+    end before a second change of one spin.  A flip ratio is a difference of
+    terms up to e^{gamma} N_pp: it is held to 1e-10 times its condition
+    number kappa with respect to N_pp (insertions and removals: kappa = 1),
+    against the extended-precision chain, as is the FP64 oracle."""
+    m = ctaux.Model(a1=(2, 0), a2=(0, 2), U=4.0, beta=5.0, n_tau=1000)
+    w = ctaux.Walker(m, seed=seed, k_s=k_s, p_flip=0.3)
+    w.random_config(25)
+    for _ in range(20):
+        w.sweep()
+    w.refresh()
+    w.record = True
+    init = (w.r.copy(), w.t.copy(), w.s.copy(), w.id.copy())
+    for _ in range(30):
+        w.sweep()
+    rec, ro = records(w.trace)
+    good = ~((rec["kind"] >= 1) & (rec["id"] < 0))
+    rx, ch, kap = exact_replay_with_flip_conditioning(m, init, rec)
+    props = [(int(r["kind"]), int(r["site"]), float(r["tau"]), int(r["aux_spin"]), int(r["id"]), int(r["accepted"]))
+             for r in rec[good]]
+    assert sum(1 for p in props if p[0] == 2 and p[5]) > 20
+    wm = WindowModel(m, *init)
+    n_win = 0
+    i = 0
+    while i < len(props):
+        i += wm.window(props[i:i + k_s])
+        n_win += 1
+    assert n_win > -(-len(props) // k_s)          # some windows ended early
+    got = np.array(wm.ratios)
+    for r in (got, ro[good]):
+        assert np.all(np.abs(r - rx[good]) <= 1e-10 * kap[good] * np.abs(rx[good]))
+    ids_x, Xu, Xd = ch.canonical()
+    ids2, Nu2, Nd2 = wm.canonical()
+    assert np.array_equal(ids_x, ids2)
+    assert np.array_equal(ch.s[np.argsort(ch.id)], wm.s[np.argsort(wm.id)])
+    for A, X in ((Nu2, Xu), (Nd2, Xd)):
+        assert float(np.max(np.abs(A.astype(np.longdouble) - X)) / np.max(np.abs(X))) < 1e-10
