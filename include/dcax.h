@@ -152,6 +152,13 @@ typedef struct {
   double flip_share;
   int32_t touched_twice;
   int32_t reserved2;       /* must be 0 */
+  /* Drift control (finite, >= 0; 0 = off; walker 0's value governs the
+   * handle): after every sweep that ends without a periodic refresh, each
+   * walker's N is probed against its definition (dcax_probe_N) and rebuilt
+   * in FP64 when the largest sampled residual exceeds drift_tol.  Meant for
+   * FP32-mixed chains, whose rounding grows between refreshes and can be
+   * amplified by an update with a small ratio. */
+  double drift_tol;
 } dcax_params;
 
 /* Counters since creation or the last dcax_set_config (timings and drifts
@@ -185,6 +192,9 @@ typedef struct {
   double y_seconds;         /* Y-column kernel time summed over the timed windows */
   int64_t accepted_flips;   /* accepted spin flips */
   int64_t neglected;        /* proposals rejected as touching a spin twice (touched_twice = 1) */
+  int64_t probes;           /* probes of N (dcax_probe_N and the drift control), per handle */
+  int64_t probe_refreshes;  /* walkers rebuilt by the drift control */
+  double last_probe;        /* largest residual of the last probe over the walkers */
 } dcax_stats;
 
 /* Create a batch of n_walkers independent walkers (Markov chains; Sec. 3.1,
@@ -365,6 +375,16 @@ dcax_status dcax_set_variants(dcax_walker w, int32_t cand_rows, int32_t y_column
 /* The forms in use (DCAX_VARIANT_AUTO until set or autotuned); both nullable. */
 dcax_status dcax_get_variants(dcax_walker w, int32_t* cand_rows, int32_t* y_columns);
 
+/* Probe every walker's N against its definition without rebuilding it:
+ * for 64 index pairs (p, q) per spin (a quarter of them diagonal), drawn
+ * afresh at each probe, the normalised residual
+ *   |sum_i A_pi N_iq - delta_pq| / sum_i |A_pi N_iq|,  A = N^{-1} = e^V - g (e^V - 1)
+ * with A assembled from the propagator (O(k) work per pair).  A freshly
+ * rebuilt N gives the unit roundoff of its precision; the residual grows
+ * with the drift N accumulates between refreshes.  residual_out (host,
+ * nullable, [n_walkers]): the largest residual per walker over both spins. */
+dcax_status dcax_probe_N(dcax_walker w, double* residual_out);
+
 /* Introspection and checkpointing; `walker` indexes the batch (0-based). */
 dcax_status dcax_get_order(dcax_walker w, int32_t walker, int32_t* k);
 /* Copy N_spin in canonical order (vertex id ascending) into host[ld * k];
@@ -389,6 +409,114 @@ dcax_status dcax_set_timing(dcax_walker w, int32_t on);
 dcax_status dcax_copy_g0_table(dcax_walker w, int32_t walker, double* host);
 /* Cluster geometry: sites [Nc][2] (int32) and momenta [Nc][2] (double). */
 dcax_status dcax_cluster(const dcax_params* p, int32_t* n_sites, int32_t* sites, double* momenta);
+
+/* ------------------------------------------------------------ DCA loop
+ * The DCA self-consistency loop around the walkers (Sec. 2.1, the DCA loop
+ * figure and its equations): the lattice self-energy is the cluster one,
+ * constant on each of the Nc patches of the Brillouin zone (the patch of K
+ * is the Brillouin zone of the superlattice centred on K); the coarse-
+ * grained G averages the lattice G over each patch; the cluster-exclusion
+ * step gives the bare propagator G0cal of the cluster problem, which the
+ * walkers solve; Dyson's equation turns their G_c into a new self-energy,
+ * mixed with the previous one.
+ *
+ * Layouts (device, FP64; complex as interleaved (re, im)):
+ *   sigma, G:   [n_spin][Nc][n_freq] complex, the measured frequencies
+ *               w_n = (2n+1) pi / beta, n = 0 .. n_freq-1;
+ *   gbar, g0:   [n_spin][Nc][n_cg] complex (n_cg >= n_freq frequencies, for
+ *               the transform to tau);
+ *   g0_tau:     [n_spin][Nc][n_tau], G0cal(r_d, tau_l) in the layout and
+ *               convention of dcax_params.g0_tau.
+ * Spin blocks: n_spin = 1 carries one self-energy for both spins (G_c is
+ * the average of the walkers' two spins); n_spin = 2 one per spin (up,
+ * down), needed when h != 0.  Sites and momenta follow the cluster
+ * enumeration above.
+ *
+ * Quadrature of the patch average: the L x L points ((i+1/2)/L - 1/2) b1 +
+ * ((j+1/2)/L - 1/2) b2 of the reciprocal superlattice cell (a_i . b_j =
+ * 2 pi delta_ij), each moved to its least-length image under b1, b2 (the
+ * Wigner-Seitz cell); a point with several such images (within 1e-12 in
+ * squared length) gives each an equal share of its weight.  Sigma above the
+ * measured frequencies keeps its last real part and an imaginary part
+ * falling as 1/w_n.  The transform to tau removes the tail 1/(i w) +
+ * c2/(i w)^2 + c3/(i w)^3 and adds it back in closed form, with the exact
+ * moments c2 = (patch mean of eps) - mu - sigma h and c3 = c2^2 + (patch
+ * variance of eps). */
+typedef struct dcax_dca_s* dcax_dca;
+
+typedef struct {
+  int32_t abi_version;     /* must be DCAX_ABI_VERSION */
+  int32_t cluster[4];      /* superlattice vectors, as in dcax_params */
+  double t, tp;            /* lattice dispersion eps_k = -2t (cos kx + cos ky) - 4 tp cos kx cos ky */
+  double beta;
+  double mu;               /* measured from U/2, as in dcax_params */
+  double h;                /* Zeeman field: eps_k - mu - sigma h (needs n_spin = 2 when nonzero) */
+  int32_t n_spin;          /* 1 or 2 self-energy blocks */
+  int32_t n_freq;          /* measured frequencies (the walkers' n_freq), >= 1 */
+  int32_t n_cg;            /* frequencies of the coarse-graining and the transform, n_freq .. 2^20 */
+  int32_t n_tau;           /* points of the G0cal(r, tau) tables (the walkers' n_tau), >= 2 */
+  int32_t patch_points;    /* L, 1 .. 256: L x L points per patch (1: the isolated cluster) */
+  int32_t reserved;        /* must be 0 */
+} dcax_dca_params;
+
+/* What one dcax_dca_iterate call did. */
+typedef struct {
+  double max_change;       /* max over spin blocks, K, n of |Sigma_new - Sigma_old| */
+  double sign;             /* mean sign of the measured configurations */
+  double mean_order;       /* mean expansion order of the walkers at the end */
+  int64_t measurements;    /* measured configurations, summed over the walkers */
+} dcax_dca_report;
+
+/* Create a DCA handle: builds the patch quadrature and eps(K + k~) on the
+ * GPU.  Memory from the allocator (required), work on `stream`. */
+dcax_status dcax_dca_create(const dcax_dca_params* p, const dcax_allocator* a, void* stream, dcax_dca* out);
+dcax_status dcax_dca_destroy(dcax_dca d);
+
+/* Coarse-graining and cluster exclusion (Sec. 2.1): from sigma_dev, writes
+ * Gbar(K, i w_n) to gbar_dev (nullable) and G0cal = [Gbar^{-1} + Sigma]^{-1}
+ * to g0_dev, for n < n_cg. */
+dcax_status dcax_dca_coarse_grain(dcax_dca d, const double* sigma_dev, double* gbar_dev, double* g0_dev);
+
+/* The walkers' tables G0cal(r_d, tau_l) = (1/Nc) sum_K e^{i K r_d}
+ * G0cal(K, tau_l) from g0_dev (n_cg frequencies), into g0_tau_dev. */
+dcax_status dcax_dca_g0_tables(dcax_dca d, const double* g0_dev, double* g0_tau_dev);
+
+/* The cluster G (Sec. 2.3's estimator with G0cal): G_sigma = G0cal -
+ * G0cal <M_sigma> G0cal / beta with <M> = sum of n_blocks accumulator blocks
+ * over the sum of their signs; acc_dev and aux_dev in dcax_measure_G's
+ * layout for n_blocks walkers of this cluster and n_freq; G_dev [n_spin][Nc]
+ * [n_freq] (the spin average when n_spin = 1). */
+dcax_status dcax_dca_cluster_G(dcax_dca d, const double* g0_dev, const double* acc_dev, const double* aux_dev,
+                               int32_t n_blocks, double* G_dev);
+
+/* Dyson's equation and mixing: sigma_new = alpha (G0cal^{-1} - G^{-1}) +
+ * (1 - alpha) sigma_old on the measured frequencies, 0 < alpha <= 1
+ * (sigma_new may be sigma_old).  max_change_out (host, nullable): the
+ * largest |sigma_new - sigma_old|. */
+dcax_status dcax_dca_self_energy(dcax_dca d, const double* g0_dev, const double* G_dev, const double* sigma_old_dev,
+                                 double alpha, double* sigma_new_dev, double* max_change_out);
+
+/* One iteration of the loop with the walkers as the cluster solver:
+ * coarse-grain and exclude from sigma_dev, install G0cal in every walker
+ * (dcax_set_g0), warmup_sweeps sweeps, measure_sweeps sweeps with one
+ * measurement each (dcax_sweep_measure), the cluster G of all walkers, and
+ * sigma_dev <- the mixed new self-energy.  The walkers must all have this
+ * handle's cluster, beta, n_tau and n_freq and n_spin_tables = n_spin, and
+ * have been created with g0_tau and g0_Kw.  G_dev (nullable) receives G_c;
+ * report (host, nullable). */
+dcax_status dcax_dca_iterate(dcax_dca d, dcax_walker w, int32_t warmup_sweeps, int32_t measure_sweeps, double alpha,
+                             double* sigma_dev, double* G_dev, dcax_dca_report* report);
+
+/* Replace the bare propagator of every walker of a handle (Sec. 2.1: the
+ * solver's input changes at each DCA iteration) and rebuild N from scratch
+ * for the current configurations, with their signs.
+ *   g0_tau_dev: [n_spin_tables][Nc][n_tau] (device), as dcax_params.g0_tau;
+ *   g0_Kw_dev:  complex [n_spin_tables][Nc][g0_Kw_stride] (device; the first
+ *               n_freq entries of each row are taken), g0_Kw_stride >= n_freq.
+ * The walkers must share Nc, n_tau and n_freq, and have been created with
+ * g0_tau and g0_Kw of n_spin_tables tables. */
+dcax_status dcax_set_g0(dcax_walker w, const double* g0_tau_dev, int32_t n_spin_tables, const double* g0_Kw_dev,
+                        int32_t g0_Kw_stride);
 
 /* Thread-local message for the last non-OK status. */
 const char* dcax_last_error(void);

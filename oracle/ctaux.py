@@ -45,10 +45,14 @@ class Model:
     """Hubbard model on a periodic cluster, finite-size mode."""
 
     def __init__(self, a1=(2, 0), a2=(0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0,
-                 K_exp=1.0, n_tau=1000, use_table=True, h=0.0):
+                 K_exp=1.0, n_tau=1000, use_table=True, h=0.0, tables=None):
         """h: a Zeeman field, -h sum_i (n_iup - n_idown) in H0, so that the
         spins see xi_sigma = eps_K - mu - sigma h (sigma = +1 up, -1 down)
-        and the walker one bare propagator per spin."""
+        and the walker one bare propagator per spin.
+        tables: the bare propagator given as tables (one per spin, each
+        (Nc, n_tau), standard convention, the grid of ``g0.tau_grid``), e.g.
+        the cluster-excluded G0 of the DCA loop; t, tp, mu and h then only
+        describe the lattice."""
         self.a1, self.a2 = tuple(a1), tuple(a2)
         self.t, self.tp, self.U, self.beta, self.mu, self.h = t, tp, U, beta, mu, h
         self.K_exp = K_exp
@@ -62,6 +66,15 @@ class Model:
         self.xi = self.xis[0]
         self.gamma = math.acosh(1.0 + U * beta * self.Nc / (2.0 * K_exp))
         self.tables, self.props = [], []
+        if tables is not None:
+            for sp in range(2):
+                tab = np.asarray(tables[sp], np.float64)
+                if tab.shape != (self.Nc, n_tau):
+                    raise ValueError("a table must be (Nc, n_tau)")
+                self.tables.append(tab)
+                self.props.append(g0mod.Propagator(self.diff, beta, table=tab))
+            self.table, self.prop = self.tables[0], self.props[0]
+            return
         for sp in range(2 if h != 0.0 else 1):
             tab = g0mod.g0_table(self.sites, self.K, self.xis[sp], beta, n_tau)
             analytic = (lambda d, tau, sp=sp: self._g0_exact(d, tau, sp))

@@ -23,6 +23,7 @@
 #include "dcax_refresh.hip"
 #include "dcax_measure.hip"
 #include "dcax_nfft.hip"
+#include "dcax_dca.hip"
 
 using namespace dcax;
 
@@ -270,6 +271,10 @@ struct WalkerHost {
 struct dcax_walker_s {
   int W = 0;
   bool mixed = false;
+  // probes of N against its definition (dcax_probe_N, drift_tol)
+  double* probe_d = nullptr;   // [2 W] largest residual per walker and spin
+  long long probes = 0, probe_refreshes = 0;
+  double last_probe = 0.0;
   dcax_allocator alloc{};
   hipStream_t stream = nullptr;
   std::vector<WalkerHost> wk;
@@ -431,6 +436,7 @@ dcax_status validate(const dcax_params* p) {
   if (p->reserved != 0 || p->reserved2 != 0) return fail(DCAX_E_INVAL, "reserved fields must be 0");
   if (!(p->flip_share >= 0.0 && p->flip_share < 1.0)) return fail(DCAX_E_INVAL, "flip_share must be in [0, 1)");
   if (p->touched_twice != 0 && p->touched_twice != 1) return fail(DCAX_E_INVAL, "touched_twice must be 0 or 1");
+  if (!(p->drift_tol >= 0.0) || !std::isfinite(p->drift_tol)) return fail(DCAX_E_INVAL, "drift_tol must be finite and >= 0");
   Geometry g;
   if (!build_geometry(p->cluster, g)) return fail(DCAX_E_INVAL, "degenerate or too large cluster");
   if (p->n_freq > 0 && g.Nc > MEAS_NC_MAX)
@@ -588,6 +594,60 @@ dcax_status refresh_all(dcax_walker w, double* drift) {
   double d = 0.0;
   for (const Ctl& h : w->h_ctl) d = std::max(d, h.drift);
   if (drift) *drift = d;
+  return DCAX_OK;
+}
+
+// Largest sampled residual of N against N^{-1} = e^V - g (e^V - 1) per
+// walker (k_probe), into res[W]; synchronises.
+dcax_status probe_all(dcax_walker w, std::vector<double>& res) {
+  const unsigned long long salt = 0x9E3779B97F4A7C15ULL * (unsigned long long)(++w->probes) ^ w->wk[0].p.seed;
+  if (w->mixed)
+    hipLaunchKernelGGL(k_probe<float>, dim3(1, 2, w->W), dim3(WG), 0, w->stream, w->views<float>(), salt, w->probe_d);
+  else
+    hipLaunchKernelGGL(k_probe<double>, dim3(1, 2, w->W), dim3(WG), 0, w->stream, w->views<double>(), salt,
+                       w->probe_d);
+  HIPCHK(hipGetLastError());
+  std::vector<double> h(2 * w->W);
+  HIPCHK(hipMemcpyAsync(h.data(), w->probe_d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, w->stream));
+  HIPCHK(hipStreamSynchronize(w->stream));
+  res.assign(w->W, 0.0);
+  double m = 0.0;
+  for (int i = 0; i < w->W; ++i) {
+    const double a = h[2 * i], b = h[2 * i + 1];
+    res[i] = (a != a || b != b) ? a + b : std::max(a, b);
+    m = (res[i] != res[i] || res[i] > m) ? res[i] : m;
+  }
+  w->last_probe = m;
+  return DCAX_OK;
+}
+
+// The drift control of drift_tol (walker 0's parameter): probe every walker
+// and rebuild N in FP64 for those whose residual exceeds the tolerance.
+dcax_status probe_and_refresh(dcax_walker w) {
+  const double tol = w->wk[0].p.drift_tol;
+  if (!(tol > 0.0)) return DCAX_OK;
+  dcax_status st = sync_all(w);
+  if (st != DCAX_OK) return st;
+  std::vector<double> res;
+  st = probe_all(w, res);
+  if (st != DCAX_OK) return st;
+  bool any = false;
+  for (int i = 0; i < w->W; ++i) {
+    if (!(res[i] <= tol)) {
+      const int k = w->wk[i].k_host;
+      if (w->mixed) enqueue_refresh<float>(w, i, 1, k, true);
+      else enqueue_refresh<double>(w, i, 1, k, true);
+      ++w->probe_refreshes;
+      any = true;
+    }
+  }
+  if (!any) return DCAX_OK;
+  HIPCHK(hipGetLastError());
+  w->fresh = false;
+  st = sync_all(w);
+  if (st != DCAX_OK) return st;
+  for (int i = 0; i < w->W; ++i)
+    if (!(res[i] <= tol)) w->max_drift = std::max(w->max_drift, w->h_ctl[i].drift);
   return DCAX_OK;
 }
 
@@ -770,6 +830,9 @@ dcax_status sweep_rng(dcax_walker w, int n_sweeps) {
       if (st != DCAX_OK) return st;
       w->last_drift = d;
       w->max_drift = std::max(w->max_drift, d);
+    } else {
+      st = probe_and_refresh(w);
+      if (st != DCAX_OK) return st;
     }
   }
   return DCAX_OK;
@@ -931,7 +994,8 @@ void wire_walker(dcax_walker w, WalkerHost& x, int wid, char* base, Ctl* ctl) {
 template <typename T>
 dcax_status create_walkers(dcax_walker w) {
   w->ctl_all = (Ctl*)w->dalloc(sizeof(Ctl) * w->W);
-  if (!w->ctl_all) return fail(DCAX_E_NOMEM, "device allocation failed");
+  w->probe_d = (double*)w->dalloc(sizeof(double) * 2 * w->W);
+  if (!w->ctl_all || !w->probe_d) return fail(DCAX_E_NOMEM, "device allocation failed");
   for (int i = 0; i < w->W; ++i) {
     WalkerHost& x = w->wk[i];
     char* base = (char*)w->dalloc(walker_bytes<T>(x));
@@ -1093,6 +1157,10 @@ dcax_status sweep_rounds(dcax_walker w, int n, double* acc, double* aux, long lo
         if (st != DCAX_OK) return st;
         w->last_drift = d;
         w->max_drift = std::max(w->max_drift, d);
+      } else if (w->wk[0].p.drift_tol > 0.0 && w->rounds_done % rounds_per_sweep == 0) {
+        // once per sweep of the longest walker
+        st = probe_and_refresh(w);
+        if (st != DCAX_OK) return st;
       }
     }
     if (free_rounds > 0 && pass == 0) {
@@ -1597,7 +1665,22 @@ dcax_status dcax_get_stats(dcax_walker w, int32_t walker, dcax_stats* out) {
   out->y_seconds = w->y_s;
   out->last_drift = w->last_drift;
   out->max_drift = w->max_drift;
+  out->probes = w->probes;
+  out->probe_refreshes = w->probe_refreshes;
+  out->last_probe = w->last_probe;
   return st;
+}
+
+dcax_status dcax_probe_N(dcax_walker w, double* residual_out) {
+  dcax_status st = check_latched(w);
+  if (st != DCAX_OK) return st;
+  st = sync_all(w);
+  if (st != DCAX_OK) return st;
+  std::vector<double> res;
+  st = probe_all(w, res);
+  if (st != DCAX_OK) return st;
+  if (residual_out) std::copy(res.begin(), res.end(), residual_out);
+  return DCAX_OK;
 }
 
 dcax_status dcax_set_submatrix_k(dcax_walker w, int32_t walker, int32_t ks) {
@@ -1735,6 +1818,367 @@ dcax_status dcax_copy_g0_table(dcax_walker w, int32_t walker, double* host) {
   const double* t = w->mixed ? x.v32.table[0] : x.v64.table[0];
   HIPCHK(hipMemcpyAsync(host, t, sizeof(double) * (size_t)x.geo.Nc * x.p.n_tau, hipMemcpyDeviceToHost, w->stream));
   HIPCHK(hipStreamSynchronize(w->stream));
+  return DCAX_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- DCA loop
+// The self-consistency loop of Sec. 2.1 around a walker handle: the patch
+// quadrature is built here, every numerical step runs in the kernels of
+// dcax_dca.hip (enqueued on the handle's stream).
+struct dcax_dca_s {
+  dcax_dca_params p{};
+  Geometry geo;
+  int P = 0;                       // quadrature points of one patch
+  dcax_allocator alloc{};
+  hipStream_t stream = nullptr;
+  std::vector<void*> blocks;
+  DcaDev dev{};
+  double* g0 = nullptr;            // [n_spin][Nc][n_cg] complex: the last G0cal of dcax_dca_iterate
+  double* gk_tau = nullptr;        // [n_spin][Nc][n_tau] G0cal(K, tau)
+  double* tab = nullptr;           // [n_spin][Nc][n_tau] G0cal(r, tau)
+  double* G = nullptr;             // [n_spin][Nc][n_freq] complex
+  unsigned long long* maxchg = nullptr;
+  double* acc = nullptr;           // walker accumulators for dcax_dca_iterate
+  double* aux = nullptr;
+  long long acc_cap = 0, aux_cap = 0;
+
+  void* dalloc(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    void* ptr = alloc.alloc(bytes, alloc.ctx);
+    if (ptr) blocks.push_back(ptr);
+    return ptr;
+  }
+  void release() {
+    for (void* b : blocks) alloc.free(b, alloc.ctx);
+    blocks.clear();
+  }
+};
+
+namespace {
+
+dcax_status dca_validate(const dcax_dca_params* p) {
+  if (p->abi_version != DCAX_ABI_VERSION) return fail(DCAX_E_INVAL, "abi_version mismatch");
+  Geometry g;
+  if (!build_geometry(p->cluster, g)) return fail(DCAX_E_INVAL, "degenerate or too large cluster");
+  if (g.Nc > 1024) return fail(DCAX_E_INVAL, "the DCA loop takes clusters of at most 1024 sites");
+  if (!(p->beta > 0.0) || !std::isfinite(p->beta)) return fail(DCAX_E_INVAL, "beta must be positive");
+  if (!std::isfinite(p->t) || !std::isfinite(p->tp) || !std::isfinite(p->mu) || !std::isfinite(p->h))
+    return fail(DCAX_E_INVAL, "t, tp, mu and h must be finite");
+  if (p->n_spin != 1 && p->n_spin != 2) return fail(DCAX_E_INVAL, "n_spin must be 1 or 2");
+  if (p->h != 0.0 && p->n_spin != 2) return fail(DCAX_E_INVAL, "a field h != 0 needs n_spin = 2");
+  if (p->n_freq < 1) return fail(DCAX_E_INVAL, "n_freq must be >= 1");
+  if (p->n_cg < p->n_freq || p->n_cg > (1 << 20)) return fail(DCAX_E_INVAL, "n_cg must be in n_freq .. 2^20");
+  if (p->n_tau < 2) return fail(DCAX_E_INVAL, "n_tau must be >= 2");
+  if (p->patch_points < 1 || p->patch_points > 256) return fail(DCAX_E_INVAL, "patch_points must be in 1..256");
+  if (p->reserved != 0) return fail(DCAX_E_INVAL, "reserved must be 0");
+  return DCAX_OK;
+}
+
+// Offsets k~ and weights of the standard patch around K = 0 (quadrature rule
+// in include/dcax.h).
+void patch_quadrature(const int* c, int L, std::vector<double>& kt, std::vector<double>& wt) {
+  const double a1x = c[0], a1y = c[1], a2x = c[2], a2y = c[3];
+  const double det = a1x * a2y - a1y * a2x;
+  const double b1x = 2.0 * M_PI * a2y / det, b1y = -2.0 * M_PI * a2x / det;
+  const double b2x = -2.0 * M_PI * a1y / det, b2y = 2.0 * M_PI * a1x / det;
+  kt.clear();
+  wt.clear();
+  for (int j = 0; j < L; ++j)
+    for (int i = 0; i < L; ++i) {
+      const double fi = (i + 0.5) / L - 0.5, fj = (j + 0.5) / L - 0.5;
+      const double ux = fi * b1x + fj * b2x, uy = fi * b1y + fj * b2y;
+      double vx[25], vy[25], nv[25], best = 0.0;
+      int q = 0;
+      for (int n1 = -2; n1 <= 2; ++n1)
+        for (int n2 = -2; n2 <= 2; ++n2, ++q) {
+          vx[q] = ux + n1 * b1x + n2 * b2x;
+          vy[q] = uy + n1 * b1y + n2 * b2y;
+          nv[q] = vx[q] * vx[q] + vy[q] * vy[q];
+          if (q == 0 || nv[q] < best) best = nv[q];
+        }
+      int cnt = 0;
+      for (q = 0; q < 25; ++q) cnt += nv[q] <= best + 1e-12;
+      for (q = 0; q < 25; ++q)
+        if (nv[q] <= best + 1e-12) {
+          kt.push_back(vx[q]);
+          kt.push_back(vy[q]);
+          wt.push_back(1.0 / cnt);
+        }
+    }
+}
+
+dcax_status dca_launch_cg(dcax_dca d, const double* sigma, double* gbar, double* g0) {
+  hipLaunchKernelGGL(k_dca_coarse_grain, dim3(cdiv(d->p.n_cg, WG), d->geo.Nc, d->p.n_spin), dim3(WG), 0, d->stream,
+                     d->dev, sigma, gbar, g0);
+  HIPCHK(hipGetLastError());
+  return DCAX_OK;
+}
+
+dcax_status dca_launch_tables(dcax_dca d, const double* g0, double* tab) {
+  hipLaunchKernelGGL(k_dca_K_tau, dim3(cdiv(d->p.n_tau, WG), d->geo.Nc, d->p.n_spin), dim3(WG), 0, d->stream, d->dev,
+                     g0, d->gk_tau);
+  hipLaunchKernelGGL(k_dca_table, dim3(cdiv(d->p.n_tau, WG), d->geo.Nc, d->p.n_spin), dim3(WG), 0, d->stream, d->dev,
+                     (const double*)d->gk_tau, tab);
+  HIPCHK(hipGetLastError());
+  return DCAX_OK;
+}
+
+dcax_status dca_launch_sigma(dcax_dca d, const double* g0, const double* G, const double* s_old, double alpha,
+                             double* s_new, double* max_change) {
+  // the maximum starts at +0.0 (all bits clear), written by a kernel
+  hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(WG), 0, d->stream, (double*)d->maxchg, 1LL);
+  hipLaunchKernelGGL(k_dca_sigma, dim3(cdiv(d->p.n_freq, WG), d->geo.Nc, d->p.n_spin), dim3(WG), 0, d->stream,
+                     d->dev, g0, G, s_old, alpha, s_new, d->maxchg);
+  HIPCHK(hipGetLastError());
+  if (max_change) {
+    unsigned long long bits = 0;
+    HIPCHK(hipMemcpyAsync(&bits, d->maxchg, sizeof(bits), hipMemcpyDeviceToHost, d->stream));
+    HIPCHK(hipStreamSynchronize(d->stream));
+    double v;
+    std::memcpy(&v, &bits, sizeof(v));
+    *max_change = v;
+  }
+  return DCAX_OK;
+}
+
+// The walkers of a handle fit a DCA handle: same cluster, beta, n_tau,
+// n_freq, one table per spin block, and G0(K, i w_n) memory.
+dcax_status dca_fits(dcax_dca d, dcax_walker w) {
+  for (int i = 0; i < w->W; ++i) {
+    const WalkerHost& x = w->wk[i];
+    if (std::memcmp(x.p.cluster, d->p.cluster, sizeof(int32_t) * 4) != 0 || x.p.beta != d->p.beta ||
+        x.p.n_tau != d->p.n_tau || x.p.n_freq != d->p.n_freq)
+      return fail(DCAX_E_INVAL, "walker " + std::to_string(i) + " differs from the DCA handle in cluster, beta, "
+                                "n_tau or n_freq");
+    if (x.p.n_spin_tables != d->p.n_spin || !x.has_g0Kw)
+      return fail(DCAX_E_INVAL, "walker " + std::to_string(i) + " needs g0_tau and g0_Kw with n_spin_tables = n_spin");
+  }
+  return DCAX_OK;
+}
+
+dcax_status set_g0_all(dcax_walker w, const double* tab, int nt, const double* g0kw, int stride) {
+  const WalkerHost& x0 = w->wk[0];
+  const int Nc = x0.geo.Nc, n_tau = x0.p.n_tau, nf = x0.p.n_freq;
+  for (int i = 0; i < w->W; ++i) {
+    const WalkerHost& x = w->wk[i];
+    if (x.geo.Nc != Nc || x.p.n_tau != n_tau || x.p.n_freq != nf)
+      return fail(DCAX_E_INVAL, "the walkers of the handle differ in Nc, n_tau or n_freq");
+    if (x.p.n_spin_tables != nt) return fail(DCAX_E_INVAL, "n_spin_tables differs from the walkers' tables");
+    if (g0kw && !x.has_g0Kw) return fail(DCAX_E_INVAL, "the walkers were created without g0_Kw");
+  }
+  if (g0kw && stride < nf) return fail(DCAX_E_INVAL, "g0_Kw_stride < n_freq");
+  dcax_status st = sync_all(w);
+  if (st != DCAX_OK) return st;
+  for (int i = 0; i < w->W; ++i) {
+    const WalkerHost& x = w->wk[i];
+    const double* vt = w->mixed ? x.v32.table[0] : x.v64.table[0];
+    const double* vk = w->mixed ? x.v32.g0Kw : x.v64.g0Kw;
+    HIPCHK(hipMemcpyAsync((void*)vt, tab, sizeof(double) * nt * Nc * n_tau, hipMemcpyDeviceToDevice, w->stream));
+    if (g0kw && nf > 0)
+      HIPCHK(hipMemcpy2DAsync((void*)vk, sizeof(double) * 2 * nf, g0kw, sizeof(double) * 2 * stride,
+                              sizeof(double) * 2 * nf, (size_t)nt * Nc, hipMemcpyDeviceToDevice, w->stream));
+  }
+  // N of the current configurations under the new propagator, and their signs
+  const int kmax = w->kmax_host();
+  w->fresh = false;
+  if (w->mixed) {
+    enqueue_refresh<float>(w, 0, w->W, kmax, false);
+    hipLaunchKernelGGL(k_set_sign<float>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<float>());
+  } else {
+    enqueue_refresh<double>(w, 0, w->W, kmax, false);
+    hipLaunchKernelGGL(k_set_sign<double>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<double>());
+  }
+  HIPCHK(hipGetLastError());
+  return sync_all(w);
+}
+
+}  // namespace
+
+extern "C" {
+
+dcax_status dcax_dca_create(const dcax_dca_params* p, const dcax_allocator* a, void* stream, dcax_dca* out) {
+  if (!out) return fail(DCAX_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(DCAX_E_INVAL, "params is NULL");
+  dcax_status st = dca_validate(p);
+  if (st != DCAX_OK) return st;
+  if (!a || !a->alloc || !a->free) return fail(DCAX_E_INVAL, "an allocator with alloc and free is required");
+  dcax_dca d = new dcax_dca_s();
+  d->p = *p;
+  d->alloc = *a;
+  d->stream = (hipStream_t)stream;
+  build_geometry(p->cluster, d->geo);
+  const int Nc = d->geo.Nc, L = p->patch_points;
+  std::vector<double> kt, wt;
+  patch_quadrature(p->cluster, L, kt, wt);
+  d->P = (int)wt.size();
+  std::vector<double> eps((size_t)Nc * d->P), epsbar(Nc, 0.0), epsvar(Nc, 0.0), Kr((size_t)Nc * Nc);
+  for (int K = 0; K < Nc; ++K)
+    for (int q = 0; q < d->P; ++q) {
+      const double kx = d->geo.K[2 * K] + kt[2 * q], ky = d->geo.K[2 * K + 1] + kt[2 * q + 1];
+      const double cx = std::cos(kx), cy = std::cos(ky);
+      eps[(size_t)K * d->P + q] = -2.0 * p->t * (cx + cy) - 4.0 * p->tp * cx * cy;
+    }
+  for (int r = 0; r < Nc; ++r)
+    for (int K = 0; K < Nc; ++K)
+      Kr[(size_t)r * Nc + K] = (double)d->geo.sites[2 * r] * d->geo.K[2 * K] +
+                               (double)d->geo.sites[2 * r + 1] * d->geo.K[2 * K + 1];
+  const int ns = p->n_spin;
+  double* e_d = (double*)d->dalloc(sizeof(double) * eps.size());
+  double* w_d = (double*)d->dalloc(sizeof(double) * wt.size());
+  double* eb_d = (double*)d->dalloc(sizeof(double) * 2 * Nc);      // means, then variances
+  double* kr_d = (double*)d->dalloc(sizeof(double) * Kr.size());
+  d->g0 = (double*)d->dalloc(sizeof(double) * 2 * ns * Nc * (size_t)p->n_cg);
+  d->gk_tau = (double*)d->dalloc(sizeof(double) * ns * Nc * (size_t)p->n_tau);
+  d->tab = (double*)d->dalloc(sizeof(double) * ns * Nc * (size_t)p->n_tau);
+  d->G = (double*)d->dalloc(sizeof(double) * 2 * ns * Nc * (size_t)p->n_freq);
+  d->maxchg = (unsigned long long*)d->dalloc(sizeof(unsigned long long));
+  if (!e_d || !w_d || !eb_d || !kr_d || !d->g0 || !d->gk_tau || !d->tab || !d->G || !d->maxchg) {
+    d->release();
+    delete d;
+    return fail(DCAX_E_NOMEM, "device allocation failed");
+  }
+  // patch means and variances (two passes) of eps, from the eps values the
+  // kernels use: the first two moments of G0cal's tail
+  for (int K = 0; K < Nc; ++K) {
+    double s = 0.0, v = 0.0;
+    for (int q = 0; q < d->P; ++q) s += wt[q] * eps[(size_t)K * d->P + q];
+    epsbar[K] = s / ((double)L * L);
+    for (int q = 0; q < d->P; ++q) {
+      const double e = eps[(size_t)K * d->P + q] - epsbar[K];
+      v += wt[q] * e * e;
+    }
+    epsvar[K] = v / ((double)L * L);
+  }
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, d->stream);
+  };
+  if (up(e_d, eps.data(), sizeof(double) * eps.size()) != hipSuccess ||
+      up(w_d, wt.data(), sizeof(double) * wt.size()) != hipSuccess ||
+      up(eb_d, epsbar.data(), sizeof(double) * Nc) != hipSuccess ||
+      up(eb_d + Nc, epsvar.data(), sizeof(double) * Nc) != hipSuccess ||
+      up(kr_d, Kr.data(), sizeof(double) * Kr.size()) != hipSuccess ||
+      hipStreamSynchronize(d->stream) != hipSuccess) {
+    d->release();
+    delete d;
+    return fail(DCAX_E_HIP, "copying the patch tables failed");
+  }
+  d->dev = DcaDev{Nc, d->P, p->n_freq, p->n_cg, p->n_tau, ns, p->beta, p->mu, p->h, 1.0 / ((double)L * L),
+                  e_d, w_d, eb_d, eb_d + Nc, kr_d};
+  *out = d;
+  return DCAX_OK;
+}
+
+dcax_status dcax_dca_destroy(dcax_dca d) {
+  if (!d) return DCAX_OK;
+  (void)hipStreamSynchronize(d->stream);
+  d->release();
+  delete d;
+  return DCAX_OK;
+}
+
+dcax_status dcax_dca_coarse_grain(dcax_dca d, const double* sigma_dev, double* gbar_dev, double* g0_dev) {
+  if (!d || !sigma_dev || !g0_dev) return fail(DCAX_E_INVAL, "NULL argument");
+  return dca_launch_cg(d, sigma_dev, gbar_dev, g0_dev);
+}
+
+dcax_status dcax_dca_g0_tables(dcax_dca d, const double* g0_dev, double* g0_tau_dev) {
+  if (!d || !g0_dev || !g0_tau_dev) return fail(DCAX_E_INVAL, "NULL argument");
+  return dca_launch_tables(d, g0_dev, g0_tau_dev);
+}
+
+dcax_status dcax_dca_cluster_G(dcax_dca d, const double* g0_dev, const double* acc_dev, const double* aux_dev,
+                               int32_t n_blocks, double* G_dev) {
+  if (!d || !g0_dev || !acc_dev || !aux_dev || !G_dev) return fail(DCAX_E_INVAL, "NULL argument");
+  if (n_blocks < 1) return fail(DCAX_E_INVAL, "n_blocks must be >= 1");
+  hipLaunchKernelGGL(k_dca_cluster_G, dim3(cdiv(d->p.n_freq, WG), d->geo.Nc, d->p.n_spin), dim3(WG), 0, d->stream,
+                     d->dev, g0_dev, acc_dev, aux_dev, (int)n_blocks, G_dev);
+  HIPCHK(hipGetLastError());
+  return DCAX_OK;
+}
+
+dcax_status dcax_dca_self_energy(dcax_dca d, const double* g0_dev, const double* G_dev, const double* sigma_old_dev,
+                                 double alpha, double* sigma_new_dev, double* max_change_out) {
+  if (!d || !g0_dev || !G_dev || !sigma_old_dev || !sigma_new_dev) return fail(DCAX_E_INVAL, "NULL argument");
+  if (!(alpha > 0.0 && alpha <= 1.0)) return fail(DCAX_E_INVAL, "alpha must be in (0, 1]");
+  return dca_launch_sigma(d, g0_dev, G_dev, sigma_old_dev, alpha, sigma_new_dev, max_change_out);
+}
+
+dcax_status dcax_set_g0(dcax_walker w, const double* g0_tau_dev, int32_t n_spin_tables, const double* g0_Kw_dev,
+                        int32_t g0_Kw_stride) {
+  dcax_status st = check_latched(w);
+  if (st != DCAX_OK) return st;
+  if (!g0_tau_dev) return fail(DCAX_E_INVAL, "g0_tau_dev is NULL");
+  if (n_spin_tables != 1 && n_spin_tables != 2) return fail(DCAX_E_INVAL, "n_spin_tables must be 1 or 2");
+  return set_g0_all(w, g0_tau_dev, n_spin_tables, g0_Kw_dev, g0_Kw_stride);
+}
+
+dcax_status dcax_dca_iterate(dcax_dca d, dcax_walker w, int32_t warmup_sweeps, int32_t measure_sweeps, double alpha,
+                             double* sigma_dev, double* G_dev, dcax_dca_report* report) {
+  if (!d || !sigma_dev) return fail(DCAX_E_INVAL, "NULL argument");
+  dcax_status st = check_latched(w);
+  if (st != DCAX_OK) return st;
+  if (warmup_sweeps < 0 || measure_sweeps < 1) return fail(DCAX_E_INVAL, "warmup_sweeps >= 0, measure_sweeps >= 1");
+  if (!(alpha > 0.0 && alpha <= 1.0)) return fail(DCAX_E_INVAL, "alpha must be in (0, 1]");
+  st = dca_fits(d, w);
+  if (st != DCAX_OK) return st;
+  if (d->acc_cap < w->acc_total || d->aux_cap < 3LL * w->W) {
+    d->acc = (double*)d->dalloc(sizeof(double) * w->acc_total);
+    d->aux = (double*)d->dalloc(sizeof(double) * 3 * w->W);
+    if (!d->acc || !d->aux) return fail(DCAX_E_NOMEM, "device allocation failed");
+    d->acc_cap = w->acc_total;
+    d->aux_cap = 3LL * w->W;
+  }
+  // G0cal from the current self-energy, installed in every walker
+  st = dca_launch_cg(d, sigma_dev, nullptr, d->g0);
+  if (st != DCAX_OK) return st;
+  st = dca_launch_tables(d, d->g0, d->tab);
+  if (st != DCAX_OK) return st;
+  HIPCHK(hipStreamSynchronize(d->stream));
+  st = set_g0_all(w, d->tab, d->p.n_spin, d->g0, d->p.n_cg);
+  if (st != DCAX_OK) return st;
+  // the walkers: equilibrate under the new propagator, then measure
+  if (warmup_sweeps > 0) {
+    st = sweep_rng(w, warmup_sweeps);
+    if (st != DCAX_OK) return st;
+  }
+  hipLaunchKernelGGL(k_fill_zero, dim3(std::min(cdiv(w->acc_total, WG), 1024)), dim3(WG), 0, w->stream, d->acc,
+                     (long long)w->acc_total);
+  hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(WG), 0, w->stream, d->aux, 3LL * w->W);
+  HIPCHK(hipGetLastError());
+  st = sweep_rounds(w, measure_sweeps, d->acc, d->aux);
+  if (st != DCAX_OK) return st;
+  HIPCHK(hipStreamSynchronize(w->stream));
+  // cluster G and the new self-energy
+  hipLaunchKernelGGL(k_dca_cluster_G, dim3(cdiv(d->p.n_freq, WG), d->geo.Nc, d->p.n_spin), dim3(WG), 0, d->stream,
+                     d->dev, (const double*)d->g0, (const double*)d->acc, (const double*)d->aux, (int)w->W, d->G);
+  HIPCHK(hipGetLastError());
+  double chg = 0.0;
+  st = dca_launch_sigma(d, d->g0, d->G, sigma_dev, alpha, sigma_dev, &chg);
+  if (st != DCAX_OK) return st;
+  if (G_dev)
+    HIPCHK(hipMemcpyAsync(G_dev, d->G, sizeof(double) * 2 * d->p.n_spin * d->geo.Nc * d->p.n_freq,
+                          hipMemcpyDeviceToDevice, d->stream));
+  if (report) {
+    std::vector<double> aux(3 * w->W);
+    HIPCHK(hipMemcpyAsync(aux.data(), d->aux, sizeof(double) * aux.size(), hipMemcpyDeviceToHost, d->stream));
+    HIPCHK(hipStreamSynchronize(d->stream));
+    st = sync_all(w);
+    if (st != DCAX_OK) return st;
+    double sg = 0.0, ko = 0.0;
+    for (int i = 0; i < w->W; ++i) {
+      sg += aux[3 * i];
+      ko += w->h_ctl[i].k;
+    }
+    const long long nmeas = (long long)measure_sweeps * w->W;
+    report->max_change = chg;
+    report->sign = sg / (double)nmeas;
+    report->mean_order = ko / w->W;
+    report->measurements = nmeas;
+  }
+  HIPCHK(hipStreamSynchronize(d->stream));
   return DCAX_OK;
 }
 

@@ -442,7 +442,69 @@ __global__ void __launch_bounds__(WG) k_drift(const View<T>* __restrict__ vs) {
   }
 }
 
+// Probe of N against its definition, without rebuilding it: for PROBE_PAIRS
+// index pairs (p, q) per spin, drawn by a hash of (salt, walker, pair), the
+// normalised residual
+//   |sum_i A_pi N_iq - delta_pq| / sum_i |A_pi N_iq|,  A = N^{-1} = e^V - g (e^V - 1)
+// assembled from the propagator (O(k) work per pair).  N carries the
+// rounding of its updates; the residual measures what it has drifted from
+// the inverse of A.  out[2 walker + spin] = the largest over the pairs.
+// Grid (1, 2, W), WG threads: wavefront v takes pairs v, v + 4, ...
+constexpr int PROBE_PAIRS = 64;
+
+__device__ inline unsigned long long probe_mix(unsigned long long x) {
+  x += 0x9E3779B97F4A7C15ULL;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+  return x ^ (x >> 31);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_probe(const View<T>* __restrict__ vs, unsigned long long salt,
+                                              double* __restrict__ out) {
+  const View<T>& w = vs[blockIdx.z];
+  const int sp = blockIdx.y;
+  const int k = w.ctl->k;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const auto N = gp(w.N[sp]);
+  double worst = 0.0;
+  if (k > 0) {
+    for (int j = wv; j < PROBE_PAIRS; j += WG / 64) {
+      const unsigned long long h = probe_mix(salt ^ probe_mix(((unsigned long long)w.wid << 20) + (unsigned)j));
+      // every fourth pair is a diagonal one
+      const int p = (int)((h & 0xffffffffULL) % (unsigned long long)k);
+      const int q = (j & 3) == 0 ? p : (int)((h >> 32) % (unsigned long long)k);
+      const int rp = w.v_site[p];
+      const double tp = w.v_tau[p];
+      double sum = 0.0, mag = 0.0;
+      for (int i = lane; i < k; i += 64) {
+        const double e = w.ev[sp][s01(w.v_s[i])];
+        const double a = (i == p ? e : 0.0) - gfun(w, sp, rp, tp, w.v_site[i], w.v_tau[i]) * (e - 1.0);
+        const double t = a * (double)N[i + (size_t)q * w.ld];
+        sum += t;
+        mag += fabs(t);
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        sum += __shfl_xor(sum, o, 64);
+        mag += __shfl_xor(mag, o, 64);
+      }
+      const double r = fabs(sum - (p == q ? 1.0 : 0.0));
+      const double res = mag > 0.0 ? r / mag : r;
+      worst = (res > worst || res != res) ? res : worst;
+    }
+  }
+  __shared__ double w_s[WG / 64];
+  if (lane == 0) w_s[wv] = worst;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int v = 0; v < WG / 64; ++v) m = (w_s[v] > m || w_s[v] != w_s[v]) ? w_s[v] : m;
+    out[2 * blockIdx.z + sp] = m;
+  }
+}
+
 #define DCAX_INSTANTIATE_REFRESH(T)                                   \
+  template __global__ void k_probe<T>(const View<T>*, unsigned long long, double*); \
   template __global__ void k_build_ninv<T>(const View<T>*);           \
   template __global__ void k_gj_panel<T>(const View<T>*, int);        \
   template __global__ void k_gj_col<T>(const View<T>*, int, int);     \

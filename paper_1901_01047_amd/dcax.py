@@ -41,7 +41,8 @@ class Params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("warmup_sweeps", ctypes.c_int32), ("sweep_length", ctypes.c_int32),
                 ("n_spin_tables", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("g0_tau", ctypes.c_void_p), ("g0_Kw", ctypes.c_void_p),
-                ("flip_share", ctypes.c_double), ("touched_twice", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("flip_share", ctypes.c_double), ("touched_twice", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("drift_tol", ctypes.c_double)]
 
 
 class Vertex(ctypes.Structure):
@@ -67,7 +68,21 @@ class Stats(ctypes.Structure):
                 ("windows_enqueued", ctypes.c_int64), ("fold_rank_hist", ctypes.c_int64 * 17),
                 ("cand_flops", ctypes.c_double), ("cand_bytes", ctypes.c_double), ("cand_seconds", ctypes.c_double),
                 ("y_flops", ctypes.c_double), ("y_bytes", ctypes.c_double), ("y_seconds", ctypes.c_double),
-                ("accepted_flips", ctypes.c_int64), ("neglected", ctypes.c_int64)]
+                ("accepted_flips", ctypes.c_int64), ("neglected", ctypes.c_int64), ("probes", ctypes.c_int64),
+                ("probe_refreshes", ctypes.c_int64), ("last_probe", ctypes.c_double)]
+
+
+class DcaParams(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("cluster", ctypes.c_int32 * 4),
+                ("t", ctypes.c_double), ("tp", ctypes.c_double), ("beta", ctypes.c_double),
+                ("mu", ctypes.c_double), ("h", ctypes.c_double), ("n_spin", ctypes.c_int32),
+                ("n_freq", ctypes.c_int32), ("n_cg", ctypes.c_int32), ("n_tau", ctypes.c_int32),
+                ("patch_points", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class DcaReport(ctypes.Structure):
+    _fields_ = [("max_change", ctypes.c_double), ("sign", ctypes.c_double), ("mean_order", ctypes.c_double),
+                ("measurements", ctypes.c_int64)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -88,8 +103,9 @@ EXPORTS = ("dcax_walker_create", "dcax_walker_destroy", "dcax_sweep", "dcax_swee
            "dcax_sweep_measure", "dcax_run_rounds", "dcax_measure_nfft", "dcax_sweep_measure_nfft",
            "dcax_nfft_transform",
            "dcax_finalize_G", "dcax_get_order", "dcax_copy_N", "dcax_get_config", "dcax_set_config",
-           "dcax_set_submatrix_k", "dcax_autotune", "dcax_set_graphs", "dcax_set_variants", "dcax_get_variants", "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table",
-           "dcax_cluster", "dcax_last_error")
+           "dcax_set_submatrix_k", "dcax_autotune", "dcax_set_graphs", "dcax_set_variants", "dcax_get_variants", "dcax_probe_N", "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table",
+           "dcax_cluster", "dcax_dca_create", "dcax_dca_destroy", "dcax_dca_coarse_grain", "dcax_dca_g0_tables",
+           "dcax_dca_cluster_G", "dcax_dca_self_energy", "dcax_dca_iterate", "dcax_set_g0", "dcax_last_error")
 
 _lib = None
 
@@ -126,7 +142,16 @@ def load():
         "dcax_set_variants": [vp, ctypes.c_int32, ctypes.c_int32],
         "dcax_get_variants": [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
         "dcax_copy_g0_table": [vp, ctypes.c_int32, vp],
+        "dcax_probe_N": [vp, vp],
         "dcax_cluster": [P(Params), P(ctypes.c_int32), vp, vp],
+        "dcax_dca_create": [P(DcaParams), P(Allocator), vp, P(vp)],
+        "dcax_dca_destroy": [vp],
+        "dcax_dca_coarse_grain": [vp, vp, vp, vp],
+        "dcax_dca_g0_tables": [vp, vp, vp],
+        "dcax_dca_cluster_G": [vp, vp, vp, vp, ctypes.c_int32, vp],
+        "dcax_dca_self_energy": [vp, vp, vp, vp, ctypes.c_double, vp, P(ctypes.c_double)],
+        "dcax_dca_iterate": [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, vp, vp, P(DcaReport)],
+        "dcax_set_g0": [vp, vp, ctypes.c_int32, vp, ctypes.c_int32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -146,7 +171,7 @@ def _check(st):
 def make_params(cluster=(2, 0, 0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0, K_exp=1.0, n_tau=1000,
                 precision=DCAX_FP64, submatrix_k=16, refresh_every=0, max_order=512, n_freq=64,
                 seed=985456376, warmup_sweeps=20, sweep_length=0, g0_tau=None, g0_Kw=None, flip_share=0.0,
-                touched_twice=0):
+                touched_twice=0, drift_tol=0.0):
     """g0_tau: optional bare propagator tables, float64 [n_spin_tables][Nc][n_tau]
     (or [Nc][n_tau] for one table) in the standard convention; g0_Kw: optional
     complex128 [n_spin_tables][Nc][n_freq] G0(K, i w_n) for finalize.  The
@@ -160,7 +185,7 @@ def make_params(cluster=(2, 0, 0, 2), t=1.0, tp=0.0, U=4.0, beta=5.0, mu=0.0, K_
     p.n_tau, p.precision, p.submatrix_k = n_tau, precision, submatrix_k
     p.refresh_every, p.max_order, p.n_freq, p.seed = refresh_every, max_order, n_freq, seed
     p.warmup_sweeps, p.sweep_length = warmup_sweeps, sweep_length
-    p.flip_share, p.touched_twice = flip_share, touched_twice
+    p.flip_share, p.touched_twice, p.drift_tol = flip_share, touched_twice, drift_tol
     keep = []
     if g0_tau is not None:
         t = np.ascontiguousarray(g0_tau, dtype=np.float64)
@@ -333,6 +358,13 @@ class Walker:
     def set_graphs(self, on=True):
         _check(load().dcax_set_graphs(self._h, 1 if on else 0))
 
+    def probe(self):
+        """Largest sampled residual of each walker's N against its definition
+        (see dcax_probe_N), [W]."""
+        out = np.zeros(self.W, np.float64)
+        _check(load().dcax_probe_N(self._h, out.ctypes.data))
+        return out
+
     def set_variants(self, cand_rows=0, y_columns=0):
         """Kernel forms of the candidate-row and Y-column products: 0 auto,
         1 tiled (LDS), 2 wide, 3 narrow (see dcax_set_variants)."""
@@ -415,3 +447,125 @@ class Walker:
         if self.W == 1:
             Gt = Gt.view(2, self.Nc, max(n_tau_out, 1))
         return Giw, (Gt if n_tau_out else None)
+
+    def set_g0(self, g0_tau, g0_Kw=None):
+        """Install a new bare propagator in every walker (device tensors):
+        g0_tau float64 [n_spin_tables][Nc][n_tau], g0_Kw float64
+        [n_spin_tables][Nc][stride][2] (its first n_freq frequencies are
+        taken); N is rebuilt for the current configurations."""
+        nt = int(g0_tau.shape[0])
+        stride = int(g0_Kw.shape[2]) if g0_Kw is not None else 0
+        _check(load().dcax_set_g0(self._h, ctypes.c_void_p(g0_tau.data_ptr()), nt,
+                                  ctypes.c_void_p(g0_Kw.data_ptr()) if g0_Kw is not None else None, stride))
+
+
+def make_dca_params(cluster=(2, 0, 0, 2), t=1.0, tp=0.0, beta=5.0, mu=0.0, h=0.0, n_spin=1, n_freq=64, n_cg=2048,
+                    n_tau=1000, patch_points=8):
+    p = DcaParams()
+    p.abi_version = DCAX_ABI_VERSION
+    for i in range(4):
+        p.cluster[i] = int(cluster[i])
+    p.t, p.tp, p.beta, p.mu, p.h = t, tp, beta, mu, h
+    p.n_spin, p.n_freq, p.n_cg, p.n_tau, p.patch_points = n_spin, n_freq, n_cg, n_tau, patch_points
+    return p
+
+
+class DCA:
+    """The DCA self-consistency loop (Sec. 2.1) on the current torch device.
+
+    Arrays are torch float64 device tensors; complex quantities carry a last
+    axis (re, im): sigma and G [n_spin][Nc][n_freq][2], gbar and g0
+    [n_spin][Nc][n_cg][2], tables [n_spin][Nc][n_tau]."""
+
+    def __init__(self, params, device=None, stream=None):
+        import torch
+        self._torch = torch
+        self.p = params
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        dev_index = self.device.index
+        sptr = self.stream.cuda_stream
+
+        def _alloc(nbytes, ctx):
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev_index, sptr)
+
+        def _free(ptr, ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        self._allocator = Allocator(self._alloc_cb, self._free_cb, None)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(load().dcax_dca_create(ctypes.byref(params), ctypes.byref(self._allocator), ctypes.c_void_p(sptr),
+                                          ctypes.byref(h)))
+        self._h = h
+        q = Params()
+        q.cluster[:] = params.cluster[:]
+        self.Nc = len(cluster(q)[0])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().dcax_dca_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _z(self, nf):
+        return self._torch.zeros((self.p.n_spin, self.Nc, nf, 2), dtype=self._torch.float64, device=self.device)
+
+    def new_sigma(self):
+        return self._z(self.p.n_freq)
+
+    def coarse_grain(self, sigma):
+        """(gbar, g0): coarse-grained G and cluster-excluded G0cal."""
+        gbar, g0 = self._z(self.p.n_cg), self._z(self.p.n_cg)
+        _check(load().dcax_dca_coarse_grain(self._h, ctypes.c_void_p(sigma.data_ptr()),
+                                            ctypes.c_void_p(gbar.data_ptr()), ctypes.c_void_p(g0.data_ptr())))
+        return gbar, g0
+
+    def g0_tables(self, g0):
+        tab = self._torch.zeros((self.p.n_spin, self.Nc, self.p.n_tau), dtype=self._torch.float64,
+                                device=self.device)
+        _check(load().dcax_dca_g0_tables(self._h, ctypes.c_void_p(g0.data_ptr()), ctypes.c_void_p(tab.data_ptr())))
+        return tab
+
+    def cluster_G(self, g0, acc, aux, n_blocks=1):
+        G = self._z(self.p.n_freq)
+        _check(load().dcax_dca_cluster_G(self._h, ctypes.c_void_p(g0.data_ptr()), ctypes.c_void_p(acc.data_ptr()),
+                                         ctypes.c_void_p(aux.data_ptr()), int(n_blocks), ctypes.c_void_p(G.data_ptr())))
+        return G
+
+    def self_energy(self, g0, G, sigma_old, alpha=1.0, out=None):
+        """(new sigma, max |change|)."""
+        out = self._z(self.p.n_freq) if out is None else out
+        chg = ctypes.c_double()
+        _check(load().dcax_dca_self_energy(self._h, ctypes.c_void_p(g0.data_ptr()), ctypes.c_void_p(G.data_ptr()),
+                                           ctypes.c_void_p(sigma_old.data_ptr()), float(alpha),
+                                           ctypes.c_void_p(out.data_ptr()), ctypes.byref(chg)))
+        return out, chg.value
+
+    def walker_params(self, sigma, **kw):
+        """Params for walkers of this loop, with G0cal from `sigma` as their
+        initial propagator (host copies of the tables)."""
+        _, g0 = self.coarse_grain(sigma)
+        tab = self.g0_tables(g0).cpu().numpy()
+        g = g0.cpu().numpy()
+        gkw = g[:, :, :self.p.n_freq, 0] + 1j * g[:, :, :self.p.n_freq, 1]
+        return make_params(cluster=tuple(self.p.cluster), beta=self.p.beta, n_tau=self.p.n_tau, n_freq=self.p.n_freq,
+                           g0_tau=tab, g0_Kw=gkw, **kw)
+
+    def iterate(self, walker, sigma, warmup_sweeps, measure_sweeps, alpha=1.0, want_G=False):
+        """One DCA iteration with `walker` (a Walker) as the cluster solver;
+        sigma is updated in place.  Returns (report dict, G or None)."""
+        rep = DcaReport()
+        G = self._z(self.p.n_freq) if want_G else None
+        _check(load().dcax_dca_iterate(self._h, walker._h, int(warmup_sweeps), int(measure_sweeps), float(alpha),
+                                       ctypes.c_void_p(sigma.data_ptr()),
+                                       ctypes.c_void_p(G.data_ptr()) if G is not None else None,
+                                       ctypes.byref(rep)))
+        return {f: getattr(rep, f) for f, _ in DcaReport._fields_}, G

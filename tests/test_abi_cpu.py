@@ -33,7 +33,8 @@ def test_exports_every_declared_symbol(lib):
 def test_struct_layouts_match_header(tmp_path):
     """sizeof/offsetof of every ABI struct field, from gcc, equal the binding's."""
     structs = {"dcax_vertex": dcax.Vertex, "dcax_proposal": dcax.Proposal, "dcax_params": dcax.Params,
-               "dcax_stats": dcax.Stats, "dcax_allocator": dcax.Allocator}
+               "dcax_stats": dcax.Stats, "dcax_allocator": dcax.Allocator, "dcax_dca_params": dcax.DcaParams,
+               "dcax_dca_report": dcax.DcaReport}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dcax.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -62,7 +63,8 @@ def test_struct_layouts_match_header(tmp_path):
                                          ("submatrix_k", 65), ("max_order", 0), ("n_freq", -1),
                                          ("refresh_every", -3), ("warmup_sweeps", -1), ("sweep_length", -2),
                                          ("flip_share", -0.1), ("flip_share", 1.0), ("flip_share", float("nan")),
-                                         ("touched_twice", 2), ("touched_twice", -1), ("reserved2", 1)])
+                                         ("touched_twice", 2), ("touched_twice", -1), ("reserved2", 1),
+                                         ("drift_tol", -1.0), ("drift_tol", float("inf"))])
 def test_create_rejects_bad_params(lib, field, value):
     p = dcax.make_params()
     setattr(p, field, value)
@@ -168,3 +170,28 @@ def test_create_requires_an_allocator():
     st = lib.dcax_walker_create(ctypes.byref(p), 1, None, None, ctypes.byref(h))
     assert st == -1 and h.value is None
     assert b"allocator" in lib.dcax_last_error()
+
+
+@pytest.mark.parametrize("field,value", [("abi_version", 3), ("beta", 0.0), ("n_spin", 3), ("n_freq", 0),
+                                         ("n_cg", 8), ("n_tau", 1), ("patch_points", 0), ("patch_points", 257),
+                                         ("reserved", 1), ("mu", float("nan")), ("h", 0.3)])
+def test_dca_create_rejects_bad_params(lib, field, value):
+    """Argument errors of dcax_dca_create come back before any device work
+    (n_cg 8 < n_freq 16; a field h != 0 with one spin block)."""
+    p = dcax.make_dca_params(n_freq=16, n_cg=64, n_tau=50, patch_points=4)
+    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    al = dcax.Allocator(dcax.ALLOC_FN(lambda n, c: None), dcax.FREE_FN(lambda q, c: None), None)
+    st = lib.dcax_dca_create(ctypes.byref(p), ctypes.byref(al), None, ctypes.byref(h))
+    assert st == -1 and not h.value
+    assert len(lib.dcax_last_error()) > 0
+
+
+def test_dca_null_arguments(lib):
+    assert lib.dcax_dca_coarse_grain(None, None, None, None) == -1
+    assert lib.dcax_dca_g0_tables(None, None, None) == -1
+    assert lib.dcax_dca_cluster_G(None, None, None, None, 1, None) == -1
+    assert lib.dcax_dca_self_energy(None, None, None, None, 1.0, None, None) == -1
+    assert lib.dcax_dca_iterate(None, None, 0, 1, 1.0, None, None, None) == -1
+    assert lib.dcax_set_g0(None, None, 1, None, 0) == -1
+    assert lib.dcax_dca_destroy(None) == 0
