@@ -131,7 +131,7 @@ def fold_ranks(s0, s1):
 
 
 def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None, walkers=1, nfft_hw=0,
-            autotune=0, refresh_every=32):
+            autotune=0, refresh_every=32, drift_tol=0.0):
     import numpy as np
     import torch
     from paper_1901_01047_amd import dcax
@@ -140,7 +140,8 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
     cfg = CONFIGS[workload]
     prec = dcax.DCAX_FP64 if precision == "fp64" else dcax.DCAX_FP32_MIXED
     plist = [dcax.make_params(**params_kwargs(workload, seed=cfg["seed"] + seed_offset + i, warmup_sweeps=warmup),
-                              precision=prec, refresh_every=refresh_every) for i in range(walkers)]
+                              precision=prec, refresh_every=refresh_every, drift_tol=drift_tol)
+             for i in range(walkers)]
     w = dcax.Walker(plist if walkers > 1 else plist[0])
     w.set_graphs(graphs)
     for i in range(walkers):
@@ -190,7 +191,8 @@ def run_gpu(precision, steps, warmup, seed_offset=0, graphs=False, workload=None
         "roofline": kern[dominant], "dominant_kernel": dominant,
         "kernels": {k: v for k, v in kern.items() if k != dominant},
         "kernel_us_per_window": kernel_us(s0, s1), "timed_share_of_windows": 1.0 / every,
-        "sign": s1["sign"], "refresh_every": refresh_every,
+        "sign": s1["sign"], "refresh_every": refresh_every, "drift_tol": drift_tol,
+        "walkers_rebuilt_by_drift_control": s1["probe_refreshes"] - s0["probe_refreshes"],
         "refreshes_in_timed_region": steps // refresh_every if refresh_every else 0,
         "refresh_max_drift": s1["max_drift"],
         "aborted_windows": s1["aborted_windows"] - s0["aborted_windows"],
@@ -315,6 +317,48 @@ def run_nfft(workload, precision="fp64", half_width=8, reps=5):
     return out
 
 
+def run_g2(workload, walkers, precision="fp64", n_w4=16, w_transfer=0, qs=(0,), reps=3):
+    """The two-particle measurement (particle-particle up-down, dcax_measure_G2)
+    of every walker's configuration after one sweep: milliseconds per
+    measurement of the whole batch and the rate of its algorithmic work
+    (per walker and spin: the site-blocked transforms 4 k^2 n_w + 8 k Nc n_w^2
+    + 16 Nc^3 n_w^2 flops, then 8 n_q (2 n_w4 Nc)^2 for the products), an
+    FP64 ALU-bound kernel chain (peak 78.6 TFLOP/s FP64 vector)."""
+    import numpy as np
+    import torch
+    from paper_1901_01047_amd import dcax
+    from paper_1901_01047_amd.workloads import CONFIGS, initial_config, params_kwargs
+    cfg = CONFIGS[workload]
+    prec = dcax.DCAX_FP64 if precision == "fp64" else dcax.DCAX_FP32_MIXED
+    plist = [dcax.make_params(**params_kwargs(workload, seed=cfg["seed"] + i, warmup_sweeps=1), precision=prec)
+             for i in range(walkers)]
+    w = dcax.Walker(plist if walkers > 1 else plist[0])
+    for i in range(walkers):
+        w.set_config(*initial_config(w.Ncs[i], cfg["beta"], cfg["k_init"], cfg["seed"] + 100 + i), walker=i)
+    w.sweep(1)
+    g2, sg = w.new_g2_accumulator(n_w4, len(qs))
+    w.measure_G2(n_w4, w_transfer, qs, g2, sg)      # first call allocates the scratch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        w.measure_G2(n_w4, w_transfer, qs, g2, sg)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    orders = w.orders()
+    Nc = w.Nc
+    nw = 2 * n_w4 + w_transfer
+    flops = 0.0
+    for k in orders:
+        kp = k + 16 * Nc
+        flops += 2 * (4.0 * kp * kp * nw + 8.0 * kp * Nc * nw * nw + 16.0 * Nc ** 3 * nw * nw) \
+            + 8.0 * len(qs) * (2 * n_w4 * Nc) ** 2
+    w.close()
+    return {"workload": workload, "walkers": walkers, "precision": precision, "n_w4": n_w4,
+            "w_transfer": w_transfer, "n_q": len(qs), "mean_order": float(np.mean(orders)),
+            "ms_per_measurement": dt * 1e3, "flops_per_measurement": flops, "tflops": flops / dt / 1e12,
+            "bound": "alu", "peak_tflops": PEAK["fp64_mfma_TFs"], "frac": flops / dt / 1e12 / PEAK["fp64_mfma_TFs"]}
+
+
 def cpu_baseline(seconds=15.0, workload=None):
     """The oracle, as it stands, timed on the host: one chain of the same
     workload from the same kind of seeded starting configuration, first with
@@ -374,8 +418,11 @@ def main():
     ap.add_argument("--precision", choices=("mixed", "fp64"), default="mixed",
                     help="precision of the headline leg (`value`); the other runs beside it")
     ap.add_argument("--headline-only", action="store_true", help="skip the other precision's leg")
-    ap.add_argument("--refresh-every", type=int, default=10,
+    ap.add_argument("--refresh-every", type=int, default=20,
                     help="sweeps between FP64 refreshes of N (at most --steps, so the timed region holds one)")
+    ap.add_argument("--drift-tol", type=float, default=2e-3,
+                    help="FP32-mixed legs: after each sweep, rebuild in FP64 every walker whose sampled residual "
+                         "of N against its definition exceeds this (0: off)")
     ap.add_argument("--graphs", choices=("on", "off"), default="off",
                     help="replay each sweep as a captured hipGraph")
     ap.add_argument("--workload", default=WORKLOAD,
@@ -386,6 +433,8 @@ def main():
                     help="sweeps per candidate k_s for the autotuner during the warm-up (0: the workload's k_s)")
     ap.add_argument("--nfft", action="store_true",
                     help="also time the delayed-NFFT measurement against the direct one on the workload")
+    ap.add_argument("--g2", action="store_true",
+                    help="also time the two-particle measurement (n_w4 = 16, q = 0) of the workload's walkers")
     ap.add_argument("--batch", type=int, default=0,
                     help="also run the batched workload with this many walkers (FP64 and FP32-mixed)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -424,7 +473,7 @@ def main():
     res = {}
     for prec in legs:
         res[prec], _ = run_gpu(prec, args.steps, args.warmup, graphs=graphs, workload=wl, walkers=walkers,
-                               autotune=at, refresh_every=re)
+                               autotune=at, refresh_every=re, drift_tol=args.drift_tol if prec == "mixed" else 0.0)
     head = res[args.precision]
     ks_text = f"k_s={head['submatrix_k']} (autotuned)" if at else f"k_s={c['submatrix_k']}"
     mode = "FP32-mixed (N and its GEMMs FP32 on MFMA; ratios, Gamma and refresh FP64)" \
@@ -437,9 +486,12 @@ def main():
         "config": {"workload": f"{wl}: {c['cluster'][0]}x{c['cluster'][3]} periodic Hubbard cluster, t=1, "
                                f"t'={c['tp']}, U={c['U']}, beta={c['beta']}, mu={c['mu']} (n~{c['n_target']}), "
                                f"K=1, expansion order ~{c['k_init']}, {walkers} walker(s), {mode}, {ks_text}, "
-                               f"{c['n_freq']} Matsubara freqs measured every sweep, FP64 refresh every {re} sweeps",
+                               f"{c['n_freq']} Matsubara freqs measured every sweep, FP64 refresh every {re} sweeps"
+                               + (f" and of any walker whose sampled residual of N exceeds {args.drift_tol:g} after a "
+                                  "sweep" if args.precision == "mixed" and args.drift_tol > 0 else ""),
                    "step": "1 sweep + 1 measurement of M(K,iw_n) per walker (+ the refresh every "
-                           f"{re} sweeps)",
+                           f"{re} sweeps" + (", + the drift-triggered rebuilds)" if args.precision == "mixed" and
+                                             args.drift_tol > 0 else ")"),
                    "launch": "hipGraph per sweep" if graphs else "eager launches"},
         "roofline": head["roofline"],
     }
@@ -453,6 +505,8 @@ def main():
         rn, _ = run_gpu("fp64", args.steps, args.warmup, graphs=graphs, workload=wl, walkers=walkers, nfft_hw=8,
                         autotune=at, refresh_every=re)
         out["fp64_nfft_measurement"] = {k: v for k, v in rn.items() if k != "roofline"}
+    if args.g2:
+        out["two_particle"] = run_g2(wl, walkers)
     if args.batch:
         out["batch"] = {"fp64": run_batch("fp64", args.steps, args.warmup, args.batch, graphs, at),
                         "fp32_mixed": run_batch("mixed", args.steps, args.warmup, args.batch, graphs, at)}

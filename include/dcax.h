@@ -155,7 +155,8 @@ typedef struct {
   /* Drift control (finite, >= 0; 0 = off; walker 0's value governs the
    * handle): after every sweep that ends without a periodic refresh, each
    * walker's N is probed against its definition (dcax_probe_N) and rebuilt
-   * in FP64 when the largest sampled residual exceeds drift_tol.  Meant for
+   * in FP64 when the largest sampled residual exceeds drift_tol (the whole
+   * batch at once when a quarter of it or more exceeds it).  Meant for
    * FP32-mixed chains, whose rounding grows between refreshes and can be
    * amplified by an update with a small ratio. */
   double drift_tol;
@@ -288,6 +289,35 @@ dcax_status dcax_run_rounds(dcax_walker w, int32_t n_rounds, double* acc_dev, do
  * (nullable when n_tau_out == 0). */
 dcax_status dcax_finalize_G(dcax_walker w, const double* acc_dev, const double* aux_dev,
                             double* Giw_dev, int32_t n_tau_out, double* Gtau_dev);
+
+/* Two-particle Green's function of the cluster, particle-particle up-down
+ * channel (Sec. 2.5, the G_2 of the Bethe-Salpeter equation; App. B
+ * four-point type PARTICLE_PARTICLE_UP_DOWN, momentum and frequency
+ * transfer).  For every walker's current configuration (its spins are
+ * independent quadratic problems, so Wick's theorem factorises the up-down
+ * function):
+ *   g2[iq][K1][c1][K2][c2] += sign * G_up(k1, k2) G_down(q - k1, q - k2),
+ *   sign_dev[0] += sign,
+ * with k = (K, i w_n), n = c - n_w4 (c = 0 .. 2 n_w4 - 1), q = (K_{q_host[iq]},
+ * i 2 pi w_transfer / beta), q - k = (K_q - K, i w_{w_transfer - 1 - n}), and
+ * the configuration's Green's function (not diagonal in k)
+ *   G_sigma(k1, k2) = G0(k1) delta - G0(k1) M(k1, k2) G0(k2) / beta,
+ *   M(k1, k2) = (1/Nc) sum_ij e^{i (w1 tau_i - K1 r_i)} [(e^V - 1) N]_ij e^{-i (w2 tau_j - K2 r_j)}
+ * (its diagonal is the measurement of dcax_measure_G; G0 at negative
+ * frequencies is the conjugate of G0 at positive ones).  G2 / sum(sign) is
+ * the Monte Carlo estimate.
+ *   n_w4: 1..64 fermionic frequencies per sign ("four-point-fermionic-
+ *     frequencies"); w_transfer: 0..64; q_host: n_q (1..4096) momentum
+ *     indices of the cluster enumeration (host, copied);
+ *   g2_dev: complex [n_q][Nc][2 n_w4][Nc][2 n_w4] (device, +=, summed over
+ *     the walkers); sign_dev: one double (device, +=).
+ * The walkers of the handle must share cluster and beta; a walker created
+ * with g0_tau needs g0_Kw with n_freq >= n_w4 + w_transfer.  Work per walker
+ * and spin ~ k^2 n_w + k Nc n_w^2 + 2 Nc^3 n_w^2 complex operations (n_w =
+ * 2 n_w4 + w_transfer); scratch from the walker's allocator on first use.
+ * Synchronises the stream before returning. */
+dcax_status dcax_measure_G2(dcax_walker w, int32_t n_w4, int32_t w_transfer, int32_t n_q, const int32_t* q_host,
+                            double* g2_dev, double* sign_dev);
 
 /* Delayed-NFFT measurement (Sec. 2.3, non-equidistant FFT measurements): the
  * same quantity as dcax_measure_G, accumulated as gridded samples.  Every

@@ -24,6 +24,7 @@
 #include "dcax_measure.hip"
 #include "dcax_nfft.hip"
 #include "dcax_dca.hip"
+#include "dcax_g2.hip"
 
 using namespace dcax;
 
@@ -271,6 +272,12 @@ struct WalkerHost {
 struct dcax_walker_s {
   int W = 0;
   bool mixed = false;
+  // two-particle measurement scratch (dcax_measure_G2), grown on demand
+  G2Dev g2{};
+  size_t g2_kpad = 0, g2_nw = 0, g2_nc = 0;
+  int* g2_q = nullptr;          // [G2_Q_MAX] transfer momenta
+  int* g2_dK = nullptr;         // [Nc][Nc] index of K_a - K_b
+  int g2_dK_nc = 0;
   // probes of N against its definition (dcax_probe_N, drift_tol)
   double* probe_d = nullptr;   // [2 W] largest residual per walker and spin
   long long probes = 0, probe_refreshes = 0;
@@ -631,23 +638,30 @@ dcax_status probe_and_refresh(dcax_walker w) {
   std::vector<double> res;
   st = probe_all(w, res);
   if (st != DCAX_OK) return st;
-  bool any = false;
+  int nflag = 0;
+  for (int i = 0; i < w->W; ++i) nflag += !(res[i] <= tol);
+  if (nflag == 0) return DCAX_OK;
+  // a rebuild is latency-bound per walker (one launch per pivot column), so
+  // when a quarter of a batch or more is flagged, all walkers are rebuilt in
+  // one batched pass
+  const bool all = w->W > 1 && 4 * nflag >= w->W;
   for (int i = 0; i < w->W; ++i) {
-    if (!(res[i] <= tol)) {
-      const int k = w->wk[i].k_host;
-      if (w->mixed) enqueue_refresh<float>(w, i, 1, k, true);
-      else enqueue_refresh<double>(w, i, 1, k, true);
-      ++w->probe_refreshes;
-      any = true;
-    }
+    if (all || !(res[i] <= tol)) ++w->probe_refreshes;
+    if (all || res[i] <= tol) continue;
+    const int k = w->wk[i].k_host;
+    if (w->mixed) enqueue_refresh<float>(w, i, 1, k, true);
+    else enqueue_refresh<double>(w, i, 1, k, true);
   }
-  if (!any) return DCAX_OK;
+  if (all) {
+    if (w->mixed) enqueue_refresh<float>(w, 0, w->W, w->kmax_host(), true);
+    else enqueue_refresh<double>(w, 0, w->W, w->kmax_host(), true);
+  }
   HIPCHK(hipGetLastError());
   w->fresh = false;
   st = sync_all(w);
   if (st != DCAX_OK) return st;
   for (int i = 0; i < w->W; ++i)
-    if (!(res[i] <= tol)) w->max_drift = std::max(w->max_drift, w->h_ctl[i].drift);
+    if (all || !(res[i] <= tol)) w->max_drift = std::max(w->max_drift, w->h_ctl[i].drift);
   return DCAX_OK;
 }
 
@@ -1169,11 +1183,22 @@ dcax_status sweep_rounds(dcax_walker w, int n, double* acc, double* aux, long lo
     }
     st = sync_all(w);
     if (st != DCAX_OK) return st;
-    long long left = 0;
-    for (const Ctl& h : w->h_ctl)
-      left = std::max(left, h.sweeps_left + ((h.meas_due || h.pos < h.end) ? 1 : 0));
-    if (left == 0) break;
-    planned = left * rounds_per_sweep;
+    // rounds the slowest walker still needs: the rest of its sweep (or the
+    // pending measurement, which closes a round), then its whole sweeps; a
+    // sweep that windows closed early stretch is topped up by another pass
+    long long need = 0;
+    for (int i = 0; i < w->W; ++i) {
+      const Ctl& h = w->h_ctl[i];
+      const auto& x = w->wk[i];
+      const long long L = h.sweep_len > 0 ? h.sweep_len : std::max(x.k_host, 1);
+      const long long nw = std::max<long long>(1, (L + x.ks - 1) / x.ks);
+      long long r = h.sweeps_left * ((nw + R - 1) / R);
+      if (h.pos < h.end) r += ((h.end - h.pos + x.ks - 1) / x.ks + R - 1) / R;
+      else if (h.meas_due) r += 1;
+      need = std::max(need, r);
+    }
+    if (need == 0) break;
+    planned = need;
   }
   if (free_rounds == 0) w->sweeps_done += n;
   return DCAX_OK;
@@ -2179,6 +2204,115 @@ dcax_status dcax_dca_iterate(dcax_dca d, dcax_walker w, int32_t warmup_sweeps, i
     report->measurements = nmeas;
   }
   HIPCHK(hipStreamSynchronize(d->stream));
+  return DCAX_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- two-particle G2
+namespace {
+
+constexpr int G2_Q_MAX = 4096;
+
+template <typename T>
+dcax_status enqueue_g2(dcax_walker w, int n_w4, int wm, int n_q, double* g2, double* sign_acc) {
+  const int W = w->W, Nc = w->wk[0].geo.Nc;
+  const int nw = (int)w->g2_nw, n4 = 2 * n_w4;
+  hipStream_t s = w->stream;
+  // site-sorted M = (e^V - 1) N of every walker (the single-particle measurement's first two steps)
+  const View<T>* vs = w->views<T>();
+  const int kb1 = std::max(std::min(w->kpad_max, w->kmax_host() + 16 * w->nc_max), 1);
+  hipLaunchKernelGGL(k_meas_sort<T>, dim3(1, 1, W), dim3(WG), 0, s, vs, 0);
+  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cdiv(kb1, WG), cdiv(kb1, MCOLS), W), dim3(WG), 0, s, vs, 0);
+  const long long per = (long long)nw * Nc * nw, per4 = (long long)n4 * Nc * n4;
+  for (int i = 0; i < W; ++i) {
+    const View<T>* v = w->views<T>(i);
+    hipLaunchKernelGGL(k_g2_phase<T>, dim3(cdiv(nw, 64), cdiv(kb1, 4)), dim3(256), 0, s, v, w->g2);
+    for (int sp = 0; sp < 2; ++sp) {
+      hipLaunchKernelGGL(k_g2_t1<T>, dim3(cdiv(kb1, WG), Nc, cdiv(nw, G2_TC)), dim3(WG), 0, s, v, sp, w->g2);
+      hipLaunchKernelGGL(k_g2_f<T>, dim3(cdiv(per, WG), Nc), dim3(WG), 0, s, v, w->g2);
+      hipLaunchKernelGGL(k_g2_k1<T>, dim3(cdiv(per, WG), Nc), dim3(WG), 0, s, v, w->g2);
+      hipLaunchKernelGGL(k_g2_g<T>, dim3(cdiv(per, WG), Nc), dim3(WG), 0, s, v, sp, w->g2);
+    }
+    hipLaunchKernelGGL(k_g2_acc<T>, dim3(cdiv(per4, WG), Nc, n_q), dim3(WG), 0, s, v, w->g2, n4, wm,
+                       (const int*)w->g2_q, (const int*)w->g2_dK, (double2*)g2);
+    hipLaunchKernelGGL(k_g2_sign<T>, dim3(1), dim3(1), 0, s, v, sign_acc);
+  }
+  HIPCHK(hipGetLastError());
+  return DCAX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dcax_status dcax_measure_G2(dcax_walker w, int32_t n_w4, int32_t w_transfer, int32_t n_q, const int32_t* q_host,
+                            double* g2_dev, double* sign_dev) {
+  dcax_status st = check_latched(w);
+  if (st != DCAX_OK) return st;
+  if (n_w4 < 1 || n_w4 > 64) return fail(DCAX_E_INVAL, "n_w4 must be in 1..64");
+  if (w_transfer < 0 || w_transfer > 64) return fail(DCAX_E_INVAL, "w_transfer must be in 0..64");
+  if (n_q < 1 || n_q > G2_Q_MAX || !q_host) return fail(DCAX_E_INVAL, "n_q must be in 1..4096 with q_host given");
+  if (!g2_dev || !sign_dev) return fail(DCAX_E_INVAL, "NULL accumulator");
+  const WalkerHost& x0 = w->wk[0];
+  const int Nc = x0.geo.Nc;
+  for (int i = 0; i < n_q; ++i)
+    if (q_host[i] < 0 || q_host[i] >= Nc) return fail(DCAX_E_INVAL, "a transfer momentum index is out of range");
+  for (const auto& x : w->wk) {
+    if (std::memcmp(x.p.cluster, x0.p.cluster, sizeof(int32_t) * 4) != 0 || x.p.beta != x0.p.beta)
+      return fail(DCAX_E_INVAL, "the walkers of the handle differ in cluster or beta");
+    if (x.p.n_spin_tables > 0 && (!x.has_g0Kw || x.p.n_freq < n_w4 + w_transfer))
+      return fail(DCAX_E_INVAL, "walkers with a caller's propagator need g0_Kw with n_freq >= n_w4 + w_transfer");
+  }
+  const size_t nw = 2 * (size_t)n_w4 + w_transfer, kpad = (size_t)w->kpad_max;
+  if (nw > w->g2_nw || kpad > w->g2_kpad || (size_t)Nc > w->g2_nc) {
+    const size_t nn = std::max(nw, w->g2_nw), kk = std::max(kpad, w->g2_kpad), cc = std::max((size_t)Nc, w->g2_nc);
+    const size_t sq = cc * nn * cc * nn;
+    G2Dev g{};
+    g.P = (double2*)w->dalloc(sizeof(double2) * kk * nn);
+    g.T1 = (double2*)w->dalloc(sizeof(double2) * cc * nn * kk);
+    g.F = (double2*)w->dalloc(sizeof(double2) * sq);
+    g.H = (double2*)w->dalloc(sizeof(double2) * sq);
+    g.G[0] = (double2*)w->dalloc(sizeof(double2) * sq);
+    g.G[1] = (double2*)w->dalloc(sizeof(double2) * sq);
+    if (!w->g2_q) w->g2_q = (int*)w->dalloc(sizeof(int) * G2_Q_MAX);
+    if (!g.P || !g.T1 || !g.F || !g.H || !g.G[0] || !g.G[1] || !w->g2_q)
+      return fail(DCAX_E_NOMEM, "device allocation failed (two-particle scratch)");
+    w->g2 = g;
+    w->g2_nw = nn;
+    w->g2_kpad = kk;
+    w->g2_nc = cc;
+  }
+  w->g2.nw = (int)nw;
+  w->g2.n_lo = -n_w4;
+  w->g2.kpad = (int)w->g2_kpad;
+  if (w->g2_dK_nc != Nc) {
+    // K_a - K_b from the integer momenta q = K |det A| / (2 pi)
+    const long long D = std::llabs((long long)x0.p.cluster[0] * x0.p.cluster[3] - (long long)x0.p.cluster[1] * x0.p.cluster[2]);
+    std::vector<long long> qx(Nc), qy(Nc);
+    for (int a = 0; a < Nc; ++a) {
+      qx[a] = std::llround(x0.geo.K[2 * a] * (double)D / (2.0 * M_PI));
+      qy[a] = std::llround(x0.geo.K[2 * a + 1] * (double)D / (2.0 * M_PI));
+    }
+    std::vector<int> dk((size_t)Nc * Nc, -1);
+    for (int a = 0; a < Nc; ++a)
+      for (int b = 0; b < Nc; ++b) {
+        const long long dx = ((qx[a] - qx[b]) % D + D) % D, dy = ((qy[a] - qy[b]) % D + D) % D;
+        for (int c = 0; c < Nc; ++c)
+          if (qx[c] == dx && qy[c] == dy) dk[(size_t)a * Nc + b] = c;
+        if (dk[(size_t)a * Nc + b] < 0) return fail(DCAX_E_INVAL, "momentum difference outside the cluster");
+      }
+    w->g2_dK = (int*)w->dalloc(sizeof(int) * dk.size());
+    if (!w->g2_dK) return fail(DCAX_E_NOMEM, "device allocation failed");
+    HIPCHK(hipMemcpyAsync(w->g2_dK, dk.data(), sizeof(int) * dk.size(), hipMemcpyHostToDevice, w->stream));
+    w->g2_dK_nc = Nc;
+  }
+  HIPCHK(hipMemcpyAsync(w->g2_q, q_host, sizeof(int) * n_q, hipMemcpyHostToDevice, w->stream));
+  st = w->mixed ? enqueue_g2<float>(w, n_w4, w_transfer, n_q, g2_dev, sign_dev)
+                : enqueue_g2<double>(w, n_w4, w_transfer, n_q, g2_dev, sign_dev);
+  if (st != DCAX_OK) return st;
+  // the transfers were copied from the caller's host array: wait before returning
+  HIPCHK(hipStreamSynchronize(w->stream));
   return DCAX_OK;
 }
 

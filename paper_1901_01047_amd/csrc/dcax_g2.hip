@@ -1,0 +1,224 @@
+// Two-particle Green's function of the cluster, particle-particle up-down
+// channel (Sec. 2.5's G_2 of the Bethe-Salpeter equation; App. B four-point
+// type PARTICLE_PARTICLE_UP_DOWN).  For one configuration the spins are
+// independent quadratic problems, so
+//   G2(k1, k2; q) = G_up(k1, k2) G_down(q - k1, q - k2),
+// with the configuration's (not translation-averaged) Green's function
+//   G(k1, k2) = G0(k1) delta - G0(k1) M(k1, k2) G0(k2) / beta,
+//   M(k1, k2) = (1/Nc) sum_ij e^{i (w1 tau_i - K1 r_i)} M_ij e^{-i (w2 tau_j - K2 r_j)},
+// M = (e^V - 1) N in the site-sorted, padded order of the single-particle
+// measurement.  The contraction runs site-blocked like that measurement:
+//   T1[i'][b][w2] = sum_{j' in b} M_{i'j'} e^{-i w2 tau_j}            (k^2 n_w)
+//   F[a][w1][b][w2] = sum_{i' in a} e^{i w1 tau_i} T1[i'][b][w2]      (k Nc n_w^2)
+//   M(k1, k2) = (1/Nc) sum_ab e^{-i K1 r_a} F[a][w1][b][w2] e^{i K2 r_b}
+// (4 Nc^2 ... instead of the k^2 Nc^2 n_w^2 of the direct double sum).
+// Frequencies w_c = (2 (n_lo + c) + 1) pi / beta, c = 0 .. nw - 1; complex
+// numbers interleaved (re, im), FP64 throughout.
+#include "dcax_dev.h"
+
+namespace dcax {
+
+struct G2Dev {
+  int nw, n_lo, kpad;      // one-particle frequencies, their first index, rows of the scratch (>= every walker's kpad)
+  double2* P;              // [kpad][nw]    e^{-i w_c tau_j} (0 on padding)
+  double2* T1;             // [Nc][nw][kpad]
+  double2* F;              // [Nc a][nw][Nc b][nw]
+  double2* H;              // [Nc K1][nw][Nc b][nw]
+  double2* G[2];           // [Nc K1][nw][Nc K2][nw] per spin
+};
+
+__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 cmulc(double2 a, double2 b) {     // conj(a) b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// Phases of the sorted vertices; grid (ceil(nw / 64), ceil(kpad / 4)), 256 threads.
+template <typename T>
+__global__ void __launch_bounds__(256) k_g2_phase(const View<T>* __restrict__ vs, G2Dev g) {
+  const View<T>& w = vs[0];
+  const int kp = gp(w.m_off)[w.Nc];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int jp = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (c >= g.nw || jp >= kp) return;
+  const int j = gp(w.m_order)[jp];
+  double2 v = make_double2(0.0, 0.0);
+  if (j >= 0) {
+    const double wn = (2.0 * (g.n_lo + c) + 1.0) * M_PI / w.beta;
+    double s, co;
+    sincos(wn * w.v_tau[j], &s, &co);
+    v = make_double2(co, -s);
+  }
+  g.P[(size_t)jp * g.nw + c] = v;
+}
+
+// T1[b][c][i'] = sum_{j' in b} Ms[i'][j'] P[j'][c]; thread per sorted row i',
+// G2_TC frequencies each; grid (ceil(kpad / WG), Nc b, ceil(nw / G2_TC)).
+constexpr int G2_TC = 8;
+template <typename T>
+__global__ void __launch_bounds__(WG) k_g2_t1(const View<T>* __restrict__ vs, int sp, G2Dev g) {
+  const View<T>& w = vs[0];
+  const auto off = gp(w.m_off);
+  const int kp = off[w.Nc];
+  const int ip = blockIdx.x * WG + threadIdx.x;
+  const int b = blockIdx.y, c0 = blockIdx.z * G2_TC;
+  const bool live = ip < kp;
+  const auto Ms = gp(w.m_Ms[sp]);
+  const int ldm = w.kpad_cap;
+  double2 acc[G2_TC];
+#pragma unroll
+  for (int u = 0; u < G2_TC; ++u) acc[u] = make_double2(0.0, 0.0);
+  for (int jp = off[b]; jp < off[b + 1]; ++jp) {
+    const double m = live ? (double)Ms[ip + (size_t)jp * ldm] : 0.0;
+#pragma unroll
+    for (int u = 0; u < G2_TC; ++u) {
+      if (c0 + u < g.nw) {
+        const double2 p = g.P[(size_t)jp * g.nw + c0 + u];
+        acc[u].x += m * p.x;
+        acc[u].y += m * p.y;
+      }
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int u = 0; u < G2_TC; ++u)
+    if (c0 + u < g.nw) g.T1[((size_t)b * g.nw + c0 + u) * g.kpad + ip] = acc[u];
+}
+
+// F[a][c1][b][c2] = sum_{i' in a} conj(P[i'][c1]) T1[b][c2][i']; thread per
+// (c1, b, c2) with c1 fastest; grid (ceil(nw^2 Nc / WG), Nc a).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_g2_f(const View<T>* __restrict__ vs, G2Dev g) {
+  const View<T>& w = vs[0];
+  const auto off = gp(w.m_off);
+  const int Nc = w.Nc, nw = g.nw;
+  const int a = blockIdx.y;
+  const long long t = (long long)blockIdx.x * WG + threadIdx.x;
+  if (t >= (long long)nw * Nc * nw) return;
+  const int c1 = (int)(t % nw);
+  const long long bc2 = t / nw;                 // b nw + c2
+  const double2* t1 = g.T1 + (size_t)bc2 * g.kpad;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int ip = off[a]; ip < off[a + 1]; ++ip) {
+    const double2 x = cmulc(g.P[(size_t)ip * nw + c1], t1[ip]);
+    acc.x += x.x;
+    acc.y += x.y;
+  }
+  g.F[((size_t)a * nw + c1) * (size_t)Nc * nw + bc2] = acc;
+}
+
+// H[K1][c1][b][c2] = sum_a e^{-i K1 r_a} F[a][c1][b][c2]; thread per
+// (c1, b, c2) with c2 fastest; grid (ceil(nw^2 Nc / WG), Nc K1).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_g2_k1(const View<T>* __restrict__ vs, G2Dev g) {
+  const View<T>& w = vs[0];
+  const int Nc = w.Nc, nw = g.nw;
+  const int K1 = blockIdx.y;
+  const long long t = (long long)blockIdx.x * WG + threadIdx.x;
+  const long long per = (long long)nw * Nc * nw;
+  if (t >= per) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int a = 0; a < Nc; ++a) {
+    double s, c;
+    sincos(-(w.Kp[2 * K1] * (double)w.sites[2 * a] + w.Kp[2 * K1 + 1] * (double)w.sites[2 * a + 1]), &s, &c);
+    const double2 f = g.F[(size_t)a * per + t];
+    acc.x += c * f.x - s * f.y;
+    acc.y += c * f.y + s * f.x;
+  }
+  g.H[(size_t)K1 * per + t] = acc;
+}
+
+// G0(K, i w_n) for any fermionic index n (negative ones by conjugation).
+template <typename T>
+__device__ inline double2 g0_any(const View<T>& w, int sp, int K, int n) {
+  double gr, gi;
+  if (n >= 0) {
+    g0_K_iw(w, sp, K, n, gr, gi);
+    return make_double2(gr, gi);
+  }
+  g0_K_iw(w, sp, K, -n - 1, gr, gi);
+  return make_double2(gr, -gi);
+}
+
+// G[K1][c1][K2][c2] = G0(k1) delta - G0(k1) M(k1, k2) G0(k2) / beta with
+// M(k1, k2) = (1/Nc) sum_b H[K1][c1][b][c2] e^{i K2 r_b}; thread per
+// (c1, K2, c2) with c2 fastest; grid (ceil(nw^2 Nc / WG), Nc K1).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_g2_g(const View<T>* __restrict__ vs, int sp, G2Dev g) {
+  const View<T>& w = vs[0];
+  const int Nc = w.Nc, nw = g.nw;
+  const int K1 = blockIdx.y;
+  const long long t = (long long)blockIdx.x * WG + threadIdx.x;
+  const long long per = (long long)nw * Nc * nw;
+  if (t >= per) return;
+  const int c2 = (int)(t % nw);
+  const int K2 = (int)((t / nw) % Nc);
+  const int c1 = (int)(t / ((long long)nw * Nc));
+  const double2* h = g.H + (size_t)K1 * per + (size_t)c1 * Nc * nw + c2;
+  double2 m = make_double2(0.0, 0.0);
+  for (int b = 0; b < Nc; ++b) {
+    double s, c;
+    sincos(w.Kp[2 * K2] * (double)w.sites[2 * b] + w.Kp[2 * K2 + 1] * (double)w.sites[2 * b + 1], &s, &c);
+    const double2 x = h[(size_t)b * nw];
+    m.x += c * x.x - s * x.y;
+    m.y += c * x.y + s * x.x;
+  }
+  m.x /= (double)Nc;
+  m.y /= (double)Nc;
+  const double2 g1 = g0_any(w, sp, K1, g.n_lo + c1), g2 = g0_any(w, sp, K2, g.n_lo + c2);
+  double2 v = cmul(cmul(g1, m), g2);
+  v.x = -v.x / w.beta;
+  v.y = -v.y / w.beta;
+  if (K1 == K2 && c1 == c2) {
+    v.x += g1.x;
+    v.y += g1.y;
+  }
+  g.G[sp][(size_t)K1 * per + t] = v;
+}
+
+// G2[iq][K1][c1][K2][c2] += sign G_up(k1, k2) G_down(q - k1, q - k2) over the
+// output grid c < 2 n_w4 (n = n_lo + c); q - k = (dK[Q][K], m - 1 - n).
+// Thread per (c1, K2, c2); grid (ceil((2 n_w4)^2 Nc / WG), Nc K1, n_q).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_g2_acc(const View<T>* __restrict__ vs, G2Dev g, int n4, int wm,
+                                               const int* __restrict__ qs, const int* __restrict__ dK,
+                                               double2* __restrict__ G2) {
+  const View<T>& w = vs[0];
+  const int Nc = w.Nc, nw = g.nw;
+  const int K1 = blockIdx.y, iq = blockIdx.z;
+  const long long t = (long long)blockIdx.x * WG + threadIdx.x;
+  const long long per = (long long)n4 * Nc * n4;
+  if (t >= per) return;
+  const int c2 = (int)(t % n4);
+  const int K2 = (int)((t / n4) % Nc);
+  const int c1 = (int)(t / ((long long)n4 * Nc));
+  const int Q = qs[iq];
+  const int Kq1 = dK[Q * Nc + K1], Kq2 = dK[Q * Nc + K2];
+  const int cq1 = (wm - 1 - (g.n_lo + c1)) - g.n_lo, cq2 = (wm - 1 - (g.n_lo + c2)) - g.n_lo;
+  const long long gper = (long long)nw * Nc * nw;
+  const double2 up = g.G[0][(size_t)K1 * gper + ((size_t)c1 * Nc + K2) * nw + c2];
+  const double2 dn = g.G[1][(size_t)Kq1 * gper + ((size_t)cq1 * Nc + Kq2) * nw + cq2];
+  const double s = w.ctl->sign;
+  const double2 x = cmul(up, dn);
+  double2* o = G2 + (size_t)iq * Nc * per + (size_t)K1 * per + t;
+  o->x += s * x.x;
+  o->y += s * x.y;
+}
+
+template <typename T>
+__global__ void k_g2_sign(const View<T>* __restrict__ vs, double* sign_acc) {
+  sign_acc[0] += vs[0].ctl->sign;
+}
+
+#define DCAX_INSTANTIATE_G2(T)                                                                   \
+  template __global__ void k_g2_phase<T>(const View<T>*, G2Dev);                                 \
+  template __global__ void k_g2_t1<T>(const View<T>*, int, G2Dev);                               \
+  template __global__ void k_g2_f<T>(const View<T>*, G2Dev);                                     \
+  template __global__ void k_g2_k1<T>(const View<T>*, G2Dev);                                    \
+  template __global__ void k_g2_g<T>(const View<T>*, int, G2Dev);                                \
+  template __global__ void k_g2_acc<T>(const View<T>*, G2Dev, int, int, const int*, const int*, double2*); \
+  template __global__ void k_g2_sign<T>(const View<T>*, double*);
+
+DCAX_INSTANTIATE_G2(double)
+DCAX_INSTANTIATE_G2(float)
+
+}  // namespace dcax

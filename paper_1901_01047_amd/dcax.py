@@ -100,7 +100,7 @@ VERTEX_DTYPE = np.dtype([("id", np.int64), ("site", np.int32), ("aux_spin", np.i
 
 # exported symbols, in the order include/dcax.h declares them
 EXPORTS = ("dcax_walker_create", "dcax_walker_destroy", "dcax_sweep", "dcax_sweep_replay_static", "dcax_refresh", "dcax_measure_G",
-           "dcax_sweep_measure", "dcax_run_rounds", "dcax_measure_nfft", "dcax_sweep_measure_nfft",
+           "dcax_sweep_measure", "dcax_run_rounds", "dcax_measure_G2", "dcax_measure_nfft", "dcax_sweep_measure_nfft",
            "dcax_nfft_transform",
            "dcax_finalize_G", "dcax_get_order", "dcax_copy_N", "dcax_get_config", "dcax_set_config",
            "dcax_set_submatrix_k", "dcax_autotune", "dcax_set_graphs", "dcax_set_variants", "dcax_get_variants", "dcax_probe_N", "dcax_get_stats", "dcax_set_timing", "dcax_copy_g0_table",
@@ -129,6 +129,7 @@ def load():
         "dcax_measure_G": [vp, vp, vp],
         "dcax_sweep_measure": [vp, ctypes.c_int32, vp, vp],
         "dcax_run_rounds": [vp, ctypes.c_int32, vp, vp],
+        "dcax_measure_G2": [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp],
         "dcax_finalize_G": [vp, vp, vp, vp, ctypes.c_int32, vp],
         "dcax_get_order": [vp, ctypes.c_int32, P(ctypes.c_int32)],
         "dcax_copy_N": [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64, vp],
@@ -405,6 +406,21 @@ class Walker:
 
     def measure(self, acc, aux):
         _check(load().dcax_measure_G(self._h, ctypes.c_void_p(acc.data_ptr()), ctypes.c_void_p(aux.data_ptr())))
+
+    def new_g2_accumulator(self, n_w4, n_q):
+        """(g2, sign) for measure_G2: complex [n_q][Nc][2 n_w4][Nc][2 n_w4] as
+        float64 (..., 2) and one float64."""
+        torch = self._torch
+        n4 = 2 * n_w4
+        g2 = torch.zeros((n_q, self.Nc, n4, self.Nc, n4, 2), dtype=torch.float64, device=self.device)
+        return g2, torch.zeros(1, dtype=torch.float64, device=self.device)
+
+    def measure_G2(self, n_w4, w_transfer, qs, g2, sign):
+        """Two-particle (particle-particle up-down) measurement of every
+        walker's configuration into (g2, sign); qs: momentum indices."""
+        q = np.ascontiguousarray(qs, dtype=np.int32)
+        _check(load().dcax_measure_G2(self._h, int(n_w4), int(w_transfer), len(q), q.ctypes.data,
+                                      ctypes.c_void_p(g2.data_ptr()), ctypes.c_void_p(sign.data_ptr())))
 
     def new_nfft_grid(self):
         """Zeroed delayed-NFFT grid: one [2][Nc][4 n_freq] block per walker."""
