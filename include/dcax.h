@@ -155,8 +155,8 @@ typedef struct {
   /* Drift control (finite, >= 0; 0 = off; walker 0's value governs the
    * handle): after every sweep that ends without a periodic refresh, each
    * walker's N is probed against its definition (dcax_probe_N) and rebuilt
-   * in FP64 when the largest sampled residual exceeds drift_tol (the whole
-   * batch at once when a quarter of it or more exceeds it).  Meant for
+   * in FP64 when the largest sampled residual exceeds drift_tol (all such
+   * walkers of the batch in one rebuild pass).  Meant for
    * FP32-mixed chains, whose rounding grows between refreshes and can be
    * amplified by an update with a small ratio. */
   double drift_tol;

@@ -237,11 +237,13 @@ __global__ void k_meas_done(const View<T>* __restrict__ vs) {
 }
 
 template <typename T>
-__global__ void k_refresh_begin(const View<T>* __restrict__ vs) {
+__global__ void k_refresh_begin(const View<T>* __restrict__ vs, const int* __restrict__ mask) {
   const View<T>& w = vs[blockIdx.z];
   w.detsign[0] = 1.0;
   w.detsign[1] = 1.0;
   w.ctl->drift = 0.0;
+  // a masked refresh rebuilds only the flagged walkers
+  w.ctl->k_ref = (mask == nullptr || mask[blockIdx.z]) ? w.ctl->k : 0;
 }
 
 // After dcax_set_config's refresh: the sign of the configuration is the sign
@@ -280,6 +282,7 @@ struct dcax_walker_s {
   int g2_dK_nc = 0;
   // probes of N against its definition (dcax_probe_N, drift_tol)
   double* probe_d = nullptr;   // [2 W] largest residual per walker and spin
+  int* probe_mask_d = nullptr; // [W] walkers the drift control rebuilds
   long long probes = 0, probe_refreshes = 0;
   double last_probe = 0.0;
   dcax_allocator alloc{};
@@ -568,11 +571,11 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
 
 // FP64 refresh of N for walkers [first, first + n); nothing is read back.
 template <typename T>
-void enqueue_refresh(dcax_walker w, int first, int n, int kmax, bool measure) {
+void enqueue_refresh(dcax_walker w, int first, int n, int kmax, bool measure, const int* mask = nullptr) {
   w->fresh = false;
   const View<T>* vs = w->views<T>(first);
   hipStream_t s = w->stream;
-  hipLaunchKernelGGL(k_refresh_begin<T>, dim3(1, 1, n), dim3(1), 0, s, vs);
+  hipLaunchKernelGGL(k_refresh_begin<T>, dim3(1, 1, n), dim3(1), 0, s, vs, mask);
   if (kmax == 0) return;
   hipLaunchKernelGGL(k_build_ninv<T>, dim3(cdiv(kmax, WG), kmax, n), dim3(WG), 0, s, vs);
   for (int p0 = 0; p0 < kmax; p0 += NB) {
@@ -638,30 +641,28 @@ dcax_status probe_and_refresh(dcax_walker w) {
   std::vector<double> res;
   st = probe_all(w, res);
   if (st != DCAX_OK) return st;
-  int nflag = 0;
-  for (int i = 0; i < w->W; ++i) nflag += !(res[i] <= tol);
+  int nflag = 0, kflag = 0;
+  std::vector<int> flag(w->W, 0);
+  for (int i = 0; i < w->W; ++i)
+    if (!(res[i] <= tol)) {
+      flag[i] = 1;
+      ++nflag;
+      kflag = std::max(kflag, w->wk[i].k_host);
+    }
   if (nflag == 0) return DCAX_OK;
-  // a rebuild is latency-bound per walker (one launch per pivot column), so
-  // when a quarter of a batch or more is flagged, all walkers are rebuilt in
-  // one batched pass
-  const bool all = w->W > 1 && 4 * nflag >= w->W;
-  for (int i = 0; i < w->W; ++i) {
-    if (all || !(res[i] <= tol)) ++w->probe_refreshes;
-    if (all || res[i] <= tol) continue;
-    const int k = w->wk[i].k_host;
-    if (w->mixed) enqueue_refresh<float>(w, i, 1, k, true);
-    else enqueue_refresh<double>(w, i, 1, k, true);
-  }
-  if (all) {
-    if (w->mixed) enqueue_refresh<float>(w, 0, w->W, w->kmax_host(), true);
-    else enqueue_refresh<double>(w, 0, w->W, w->kmax_host(), true);
-  }
+  w->probe_refreshes += nflag;
+  // one refresh launch sequence for all flagged walkers: the others keep
+  // their N (their rebuild order is 0), so the sequence costs about what one
+  // walker's costs (its column steps are launch-latency-bound)
+  HIPCHK(hipMemcpyAsync(w->probe_mask_d, flag.data(), sizeof(int) * w->W, hipMemcpyHostToDevice, w->stream));
+  if (w->mixed) enqueue_refresh<float>(w, 0, w->W, kflag, true, w->probe_mask_d);
+  else enqueue_refresh<double>(w, 0, w->W, kflag, true, w->probe_mask_d);
   HIPCHK(hipGetLastError());
   w->fresh = false;
   st = sync_all(w);
   if (st != DCAX_OK) return st;
   for (int i = 0; i < w->W; ++i)
-    if (all || !(res[i] <= tol)) w->max_drift = std::max(w->max_drift, w->h_ctl[i].drift);
+    if (flag[i]) w->max_drift = std::max(w->max_drift, w->h_ctl[i].drift);
   return DCAX_OK;
 }
 
@@ -1009,7 +1010,8 @@ template <typename T>
 dcax_status create_walkers(dcax_walker w) {
   w->ctl_all = (Ctl*)w->dalloc(sizeof(Ctl) * w->W);
   w->probe_d = (double*)w->dalloc(sizeof(double) * 2 * w->W);
-  if (!w->ctl_all || !w->probe_d) return fail(DCAX_E_NOMEM, "device allocation failed");
+  w->probe_mask_d = (int*)w->dalloc(sizeof(int) * w->W);
+  if (!w->ctl_all || !w->probe_d || !w->probe_mask_d) return fail(DCAX_E_NOMEM, "device allocation failed");
   for (int i = 0; i < w->W; ++i) {
     WalkerHost& x = w->wk[i];
     char* base = (char*)w->dalloc(walker_bytes<T>(x));

@@ -1,4 +1,6 @@
-// From-scratch rebuild of the walker matrices in FP64.
+// From-scratch rebuild of the walker matrices in FP64.  The kernels rebuild
+// each walker at the order k_ref its control block holds: its order k, or 0
+// for a walker that a masked refresh (the drift control) leaves alone.
 //
 // N_sigma^{-1} = e^{V_sigma} - g (e^{V_sigma} - 1) is assembled from k^2
 // propagator gathers (Sec. 2.3's definition of N through Z_k) and inverted by
@@ -29,7 +31,7 @@ inline size_t gjc_len(int cap) { return gjc_slot(2, 0, cap); }
 template <typename T>
 __global__ void __launch_bounds__(WG) k_build_ninv(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
-  const int k = w.ctl->k;
+  const int k = w.ctl->k_ref;
   const int j = blockIdx.y;
   const int i = blockIdx.x * WG + threadIdx.x;
   if (i >= k || j >= k) return;
@@ -67,7 +69,7 @@ __device__ inline void argmax_wave(double& v, int& i) {
 template <typename T>
 __global__ void __launch_bounds__(PANEL_ROWS) k_gj_panel(const View<T>* __restrict__ vs, int p0) {
   const View<T>& w = vs[blockIdx.z];
-  const int k = w.ctl->k;
+  const int k = w.ctl->k_ref;
   if (p0 >= k) return;
   const int nb = (k - p0 < NB) ? k - p0 : NB;
   const int sp = blockIdx.x;
@@ -169,7 +171,7 @@ __global__ void __launch_bounds__(PANEL_ROWS) k_gj_panel(const View<T>* __restri
 template <typename T>
 __global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, int p0, int cidx) {
   const View<T>& w = vs[blockIdx.z];
-  const int k = w.ctl->k;
+  const int k = w.ctl->k_ref;
   if (p0 >= k) return;
   const int nb = (k - p0 < NB) ? k - p0 : NB;
   const int nwg = (k + WG - 1) / WG;
@@ -292,7 +294,7 @@ __global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, i
 template <typename T>
 __global__ void __launch_bounds__(WG) k_gj_prep(const View<T>* __restrict__ vs, int p0) {
   const View<T>& w = vs[blockIdx.z];
-  const int k = w.ctl->k;
+  const int k = w.ctl->k_ref;
   if (p0 >= k) return;
   const int nb = (k - p0 < NB) ? k - p0 : NB;
   const int sp = blockIdx.y;
@@ -331,7 +333,7 @@ template <typename T>
 __global__ void __launch_bounds__(WG) k_gj_update(const View<T>* __restrict__ vs, int p0) {
   const View<T>& w = vs[blockIdx.z >> 1];
   const int sp = blockIdx.z & 1;
-  const int k = w.ctl->k;
+  const int k = w.ctl->k_ref;
   if (p0 >= k) return;
   const int nb = (k - p0 < NB) ? k - p0 : NB;
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
@@ -346,7 +348,7 @@ constexpr int PERM_MAX = 32768 + 128;
 template <typename T>
 __global__ void __launch_bounds__(64) k_gj_perm(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
-  const int k = w.ctl->k;
+  const int k = w.ctl->k_ref;
   const int sp = blockIdx.x;
   __shared__ unsigned short col_s[PERM_MAX];
   for (int j = threadIdx.x; j < k; j += 64) col_s[j] = (unsigned short)j;
@@ -374,7 +376,7 @@ template <typename T>
 __global__ void __launch_bounds__(WG) k_refresh_store(const View<T>* __restrict__ vs, int measure) {
   const View<T>& w = vs[blockIdx.z >> 1];
   const int sp = blockIdx.z & 1;
-  const int k = w.ctl->k;
+  const int k = w.ctl->k_ref;
   const int nbx = (k + WG - 1) / WG;
   if ((int)blockIdx.x >= nbx || (int)blockIdx.y >= k) return;
   const double* M = w.M[sp];
@@ -415,7 +417,7 @@ __global__ void __launch_bounds__(WG) k_refresh_store(const View<T>* __restrict_
 template <typename T>
 __global__ void __launch_bounds__(WG) k_drift(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
-  const int k = w.ctl->k;
+  const int k = w.ctl->k_ref;
   const size_t n = (size_t)2 * k * ((k + WG - 1) / WG);
   double a = 0.0, b = 0.0;
   for (size_t x = threadIdx.x; x < n; x += WG) {

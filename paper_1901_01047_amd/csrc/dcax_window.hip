@@ -382,16 +382,16 @@ template <> struct Load4<float> {
 };
 
 // Four consecutive elements p[i0 .. i0+3] (i0 a multiple of 4, the row
-// 16-byte aligned): vector loads when the caller knows them all valid
-// (full), else element by element with those at or past n read as zero.
+// 16-byte aligned) by one vector load, those at or past n zeroed by selects
+// unless the caller knows them all valid (full).  The load is made whatever
+// `full` says (every caller's rows are allocated at least 16 elements past
+// the order), so no branch separates the loads of a step: they issue
+// together and are waited for once.
 template <typename T, typename P>
 __device__ inline void load4_row(P p, int i0, int n, bool full, T (&v)[4]) {
-  if (full) {
-    Load4<T>::run(p + i0, v);
-  } else {
+  Load4<T>::run(p + i0, v);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = (i0 + s < n) ? p[i0 + s] : (T)0;
-  }
+  for (int s = 0; s < 4; ++s) v[s] = (full || i0 + s < n) ? v[s] : (T)0;
 }
 
 // The candidate GEMMs and the Gram kernel split the inner dimension (the
@@ -537,13 +537,15 @@ __device__ inline void lds_read4(const T* p, T (&v)[4]) {
 }
 
 // Eight consecutive elements p[i0 .. i0+7] (i0 a multiple of 8, 16-byte
-// aligned), those at or past n read as zero unless the caller knows them all
-// valid (full).
+// aligned) by two vector loads, whatever lies there: the callers' rows are
+// allocated at least 32 elements past the order, and they zero the elements
+// past it when they store the values.  No branch separates the loads from
+// their use, so a chunk's loads issue together and are waited for once.
 template <typename T, typename P>
-__device__ inline void load8_row(P p, int i0, int n, bool full, T (&v)[8]) {
+__device__ inline void load8_raw(P p, int i0, T (&v)[8]) {
   T a[4], b[4];
-  load4_row(p, i0, n, full, a);
-  load4_row(p, i0 + 4, n, full, b);
+  Load4<T>::run(p + i0, a);
+  Load4<T>::run(p + i0 + 4, b);
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     v[u] = a[u];
@@ -585,23 +587,21 @@ __global__ void __launch_bounds__(256) k_cand_xt(const View<T>* __restrict__ vs)
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) acc[rb] = tot[rb] = acc_t{0, 0, 0, 0};
     T nv[8], wr[8];
+    // rows i0 + lr .. + 7 < k0 + 32 lie inside N's and W_C's rows of cap
+    // elements; columns past k0 read column 0 and candidates past nC row 0,
+    // all zeroed when stored
     auto fetch = [&](int i0) {
-      const bool full = i0 + XT_KC <= k0;
-      load8_row(nsrc, i0 + lr, k0, full, nv);
-      load8_row(wsrc, i0 + lr, k0, full, wr);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        nv[u] = jin ? nv[u] : (T)0;
-        wr[u] = wrow ? wr[u] : (T)0;
-      }
+      load8_raw(nsrc, i0 + lr, nv);
+      load8_raw(wsrc, i0 + lr, wr);
     };
     fetch(0);
     for (int i0 = 0; i0 < k0; i0 += XT_KC) {
       __syncthreads();      // the previous chunk's LDS reads are done
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        Ns[lc * P + lr + u] = nv[u];
-        Ws[lc * P + lr + u] = wr[u];
+        const bool row = i0 + lr + u < k0;
+        Ns[lc * P + lr + u] = (jin && row) ? nv[u] : (T)0;
+        Ws[lc * P + lr + u] = (wrow && row) ? wr[u] : (T)0;
       }
       __syncthreads();
       if (i0 + XT_KC < k0) fetch(i0 + XT_KC);
@@ -1530,24 +1530,22 @@ __global__ void __launch_bounds__(256) k_ygemm_t(const View<T>* __restrict__ vs)
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) acc[cb] = tot[cb] = acc_t{0, 0, 0, 0};
     T nv[8], gv[8];
+    // rows r0 + nr .. + 7 < k0 + 64 and columns j0 + gj .. + 7 < k0 + 32 lie
+    // inside the allocations (rows of cap elements); what lies past k0 is
+    // zeroed when stored
     auto fetch = [&](int j0) {
       const int jj = j0 + nj;
-      const bool jin = jj < k0;
-      load8_row(N + (size_t)(jin ? jj : 0) * ld, r0 + nr, k0, r0 + 64 <= k0, nv);
-      load8_row(gsrc, j0 + gj, k0, j0 + XT_KC <= k0, gv);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        nv[u] = jin ? nv[u] : (T)0;
-        gv[u] = gin ? gv[u] : (T)0;
-      }
+      load8_raw(N + (size_t)(jj < k0 ? jj : 0) * ld, r0 + nr, nv);
+      load8_raw(gsrc, j0 + gj, gv);
     };
     fetch(0);
     for (int j0 = 0; j0 < k0; j0 += XT_KC) {
       __syncthreads();
+      const bool jin = j0 + nj < k0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        Ns[(nr + u) * P + nj] = nv[u];
-        Gs[gc * P + gj + u] = gv[u];
+        Ns[(nr + u) * P + nj] = (jin && r0 + nr + u < k0) ? nv[u] : (T)0;
+        Gs[gc * P + gj + u] = (gin && j0 + gj + u < k0) ? gv[u] : (T)0;
       }
       __syncthreads();
       if (j0 + XT_KC < k0) fetch(j0 + XT_KC);
