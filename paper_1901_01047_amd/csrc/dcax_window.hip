@@ -472,19 +472,25 @@ __global__ void __launch_bounds__(NW * 64) k_cand_x(const View<T>* __restrict__ 
     for (int i0 = 16 * uni(wv); i0 < k0; i0 += 16 * GWV) {
       const int ib = i0 + 4 * lk;
       const bool full = i0 + 16 <= k0;      // the same in every lane
+      // every load of the step first (rows ib .. ib + 3 < k0 + 16 lie in
+      // the allocations; candidates past nC read row 0), then the masks, so
+      // that the loads issue together
       T bv[4], av[4][4];
-      load4_row(N + (size_t)jcc * ld, ib, k0, full, bv);
+      Load4<T>::run(N + (size_t)jcc * ld + ib, bv);
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) {
         const int cr = rb * 16 + li;
-        load4_row(Wm + (size_t)(cr < nC ? cr : 0) * cap, ib, k0, full, av[rb]);
-        if (cr >= nC)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) av[rb][u] = (T)0;
+        Load4<T>::run(Wm + (size_t)(cr < nC ? cr : 0) * cap + ib, av[rb]);
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        bv[u] *= jmask;
+        const bool row = full || ib + u < k0;
+        bv[u] = (row && jc < k0) ? bv[u] : (T)0;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) av[rb][u] = (row && rb * 16 + li < nC) ? av[rb][u] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
           if (rb < nRB) acc[rb] = Mfma<T>::run(av[rb][u], bv[u], acc[rb]);
@@ -799,19 +805,22 @@ __global__ void __launch_bounds__(NW * 64) k_gram(const View<T>* __restrict__ vs
     for (int i0 = 16 * uni(wv); i0 < k0; i0 += 16 * GWV) {
       const int ib = i0 + 4 * lk;
       const bool full = i0 + 16 <= k0;      // the same in every lane
+      // every load of the step first (rows of cap elements, ib + 3 < k0 +
+      // 16), then the masks, so that the loads issue together
       T bt[4], at[4][4];
-      load4_row(gcol + (size_t)ccc * cap, ib, k0, full, bt);
+      Load4<T>::run(gcol + (size_t)ccc * cap + ib, bt);
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) {
         const int x = rb * 16 + li;
-        load4_row(R + (size_t)(x < nE ? x : 0) * cap, ib, k0, full, at[rb]);
+        Load4<T>::run(R + (size_t)(x < nE ? x : 0) * cap + ib, at[rb]);
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const double b = (cc < nC) ? (double)bt[u] : 0.0;
+        const bool row = full || ib + u < k0;
+        const double b = (row && cc < nC) ? (double)bt[u] : 0.0;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
-          if (rb < nRB) acc[rb] = Mfma<double>::run(rb * 16 + li < nE ? (double)at[rb][u] : 0.0, b, acc[rb]);
+          if (rb < nRB) acc[rb] = Mfma<double>::run((row && rb * 16 + li < nE) ? (double)at[rb][u] : 0.0, b, acc[rb]);
       }
     }
 #pragma unroll
@@ -1457,24 +1466,25 @@ __global__ void __launch_bounds__(NW * 64) k_ygemm(const View<T>* __restrict__ v
     for (int j0 = 16 * uni(wv); j0 < k0; j0 += 16 * GWV) {
       const int jb = j0 + 4 * lk;
       const bool full = j0 + 16 <= k0;      // the same in every lane
+      // every load of the step first (columns jb + 3 < k0 + 16 lie inside N
+      // and the g columns), then the masks, so that the loads issue together
       T av[4], bt[4][4];
 #pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = N[irc + (size_t)(jb + u) * ld];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) Load4<T>::run(gcol + (goff[cb] >= 0 ? goff[cb] : 0) + jb, bt[cb]);
+#pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int jk = jb + u;
-        av[u] = (full || jk < k0) ? N[irc + (size_t)(full || jk < k0 ? jk : 0) * ld] : (T)0;
-      }
+        const bool col = full || jb + u < k0;
+        av[u] = col ? av[u] * imask : (T)0;
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        load4_row(gcol + (goff[cb] >= 0 ? goff[cb] : 0), jb, k0, full, bt[cb]);
-        if (goff[cb] < 0)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) bt[cb][u] = (T)0;
+        for (int cb = 0; cb < 4; ++cb) bt[cb][u] = (col && goff[cb] >= 0) ? bt[cb][u] : (T)0;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
-          if (cb < ncb) acc[cb] = Mfma<T>::run(av[u] * imask, bt[cb][u], acc[cb]);
+          if (cb < ncb) acc[cb] = Mfma<T>::run(av[u], bt[cb][u], acc[cb]);
     }
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) red[wv][cb][lane] = acc[cb];
