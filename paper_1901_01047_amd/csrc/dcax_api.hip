@@ -283,6 +283,9 @@ struct dcax_walker_s {
   // probes of N against its definition (dcax_probe_N, drift_tol)
   double* probe_d = nullptr;   // [2 W] largest residual per walker and spin
   int* probe_mask_d = nullptr; // [W] walkers the drift control rebuilds
+  // work list of a measurement launch: [1 + W] count and walkers, [W + 1] item prefix sums
+  int* meas_list_d = nullptr;
+  long long* meas_pre_d = nullptr;
   long long probes = 0, probe_refreshes = 0;
   double last_probe = 0.0;
   dcax_allocator alloc{};
@@ -499,6 +502,8 @@ static int spread(int tiles, int W, int units, long long budget = 1ll << 21) {
 // launch sized for every walker would spend its time dispatching workgroups
 // that return at once, so the measurement grids stay within this budget.
 constexpr long long MEAS_BUDGET = 1ll << 15;
+// workgroups of the persistent measurement contraction (8 per compute unit)
+constexpr long long MEAS_BLOCKS = 2048;
 // orders from which a single walker's device-scheduled rounds carry spare
 // windows (below it an empty window's ~10 launches are a visible share of a
 // full one)
@@ -686,8 +691,13 @@ void enqueue_measure(dcax_walker w, double* acc, double* aux, int gated) {
   hipLaunchKernelGGL(k_meas_copy<T>, dim3(cx, spread(cdiv(kb1, MCOLS), W, cx, mb), W), dim3(WG), 0, s, vs, gated);
   const int px = cdiv(nf, WG);
   hipLaunchKernelGGL(k_meas_phase<T>, dim3(px, spread(cdiv(kb1, MCOLS), W, px, mb), W), dim3(WG), 0, s, vs, gated);
-  const int groups = cdiv(ncm * ncm, (WG / 64) * MPAIRS), fy = cdiv(nf, 16);
-  hipLaunchKernelGGL(k_meas_block<T>, dim3(2 * spread(groups, W, 2 * fy, mb), fy, W), dim3(WG), 0, s, vs, gated);
+  // the contraction: a persistent grid over the work items of the walkers
+  // this launch covers, listed on the device
+  long long items = 0;
+  for (const auto& x : w->wk) items += meas_items(x.geo.Nc, x.p.n_freq);
+  const int nbk = (int)std::min<long long>(MEAS_BLOCKS, (std::max(1ll, (items + WG / 64 - 1) / (WG / 64)) + XCDS - 1) / XCDS * XCDS);
+  hipLaunchKernelGGL(k_meas_list<T>, dim3(1), dim3(64), 0, s, vs, W, gated, w->meas_list_d, w->meas_pre_d);
+  hipLaunchKernelGGL(k_meas_block<T>, dim3(nbk), dim3(WG), 0, s, vs, w->meas_list_d, w->meas_pre_d);
   hipLaunchKernelGGL(k_meas_K<T>, dim3(px, spread(ncm, W, 2 * px, mb), 2 * W), dim3(WG), 0, s, vs, acc, gated);
   if (gated) hipLaunchKernelGGL(k_meas_done<T>, dim3(1, 1, W), dim3(1), 0, s, vs);
 }
@@ -1011,7 +1021,10 @@ dcax_status create_walkers(dcax_walker w) {
   w->ctl_all = (Ctl*)w->dalloc(sizeof(Ctl) * w->W);
   w->probe_d = (double*)w->dalloc(sizeof(double) * 2 * w->W);
   w->probe_mask_d = (int*)w->dalloc(sizeof(int) * w->W);
-  if (!w->ctl_all || !w->probe_d || !w->probe_mask_d) return fail(DCAX_E_NOMEM, "device allocation failed");
+  w->meas_list_d = (int*)w->dalloc(sizeof(int) * (w->W + 1));
+  w->meas_pre_d = (long long*)w->dalloc(sizeof(long long) * (w->W + 1));
+  if (!w->ctl_all || !w->probe_d || !w->probe_mask_d || !w->meas_list_d || !w->meas_pre_d)
+    return fail(DCAX_E_NOMEM, "device allocation failed");
   for (int i = 0; i < w->W; ++i) {
     WalkerHost& x = w->wk[i];
     char* base = (char*)w->dalloc(walker_bytes<T>(x));

@@ -130,94 +130,244 @@ __global__ void __launch_bounds__(WG) k_meas_phase(const View<T>* __restrict__ v
     }
 }
 
-// For each pair of sites (a, b), spin and tile of 16 frequencies:
-// D^T[n][i'] = sum_{j' in b} E[j'][n] Ms[i'][j'] on the matrix cores (real
-// and imaginary parts of E separately), then the row phases e^{i w_n tau_i}
-// and the sum over i' in a.  A wavefront takes MPAIRS consecutive pairs; a
-// workgroup four wavefronts (blockIdx.x = 2 group + spin), grid-strided over
-// the groups of pairs.
-constexpr int MPAIRS = 1;
+// Work items of the contraction: one per (walker, spin, site b, group of
+// sites a, tile of 16 frequencies).  The sites a are split into groups so
+// that even one walker alone gives at least MEAS_ITEMS items (wavefronts).
+template <typename T> struct MeasTiles;                 // column blocks of 16 held in registers
+template <> struct MeasTiles<float> { static constexpr int NB = 8; };
+template <> struct MeasTiles<double> { static constexpr int NB = 4; };
+constexpr int MEAS_ITEMS = 4096;
+
+__host__ __device__ inline int meas_groups(int Nc, int n_freq) {
+  const int base = 2 * Nc * ((n_freq + 15) / 16);
+  const int ng = (MEAS_ITEMS + base - 1) / base;
+  return ng < 1 ? 1 : (ng > Nc ? Nc : ng);
+}
+__host__ __device__ inline long long meas_items(int Nc, int n_freq) {
+  return n_freq > 0 ? 2ll * Nc * meas_groups(Nc, n_freq) * ((n_freq + 15) / 16) : 0;
+}
+
+// Work list of one measurement launch: the walkers it covers (every walker,
+// or under gating those whose sweep has just ended), list[0] = count and
+// list[1 + c] = walker, and the prefix sums of their work items,
+// pre[c] = items of the listed walkers before the c-th.  One wavefront,
+// walkers in chunks of 64 (a scan over lanes per chunk).
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_block(const View<T>* __restrict__ vs, int gated) {
-  const View<T>& w = vs[blockIdx.z];
-  if (meas_skip(w.ctl, gated)) return;
-  const auto order = gp(w.m_order);
+__global__ void __launch_bounds__(64) k_meas_list(const View<T>* __restrict__ vs, int W, int gated,
+                                                  int* __restrict__ list, long long* __restrict__ pre) {
+  const int lane = threadIdx.x;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int cnt = 0;
+  long long run = 0;
+  for (int z0 = 0; z0 < W; z0 += 64) {
+    const int z = z0 + lane;
+    bool on = false;
+    long long items = 0;
+    if (z < W) {
+      const View<T>& w = vs[z];
+      on = !meas_skip(w.ctl, gated) && w.n_freq > 0;
+      if (on) items = meas_items(w.Nc, w.n_freq);
+    }
+    long long sc = items;     // inclusive scan over the lanes
+    for (int o = 1; o < 64; o <<= 1) {
+      const long long v = __shfl_up(sc, o, 64);
+      if (lane >= o) sc += v;
+    }
+    const unsigned long long msk = __ballot(on);
+    if (on) {
+      const int c = cnt + __popcll(msk & below);
+      list[1 + c] = z;
+      pre[c] = run + sc - items;
+    }
+    cnt += __popcll(msk);
+    run += __shfl(sc, 63, 64);
+  }
+  if (lane == 0) {
+    list[0] = cnt;
+    pre[cnt] = run;
+  }
+}
+
+// One chunk of NB column blocks of site b (columns jc .. jc + 16 NB) for the
+// sites a0 .. a1 - 1 and the 16 frequencies from n0, on one wavefront.  The
+// lane keeps its share of E[j][n] for the chunk in registers: in the 4-step
+// product u of block q it supplies column j = jc + 16 q + 4 u + (lane >> 4)
+// of frequency n0 + (lane & 15) (the A' operand) and M[i'][j] of row
+// i' = ib + (lane & 15) (the B operand).  Per 16 rows of a:
+//   D^T[n][i'] = sum_j E[j][n] Ms[i'][j]      (matrix cores)
+// then the row phases e^{i w_n tau_i} = conj E[i'][n] and the sum over i'.
+// The first chunk of b stores M(a, b; w_n), later chunks add to it.
+// Loads through a buffer resource (base address in scalar registers): a
+// lane offset in one vector register plus a wavefront-uniform offset in a
+// scalar register, so a block of loads needs no address register each.
+constexpr int BUF_WORD3 = 0x00020000;   // data format word of a raw buffer on gfx9
+template <typename T> __device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so);
+template <> __device__ inline float buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+}
+template <> __device__ inline double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+}
+
+// One chunk of NB column blocks of site b (columns jc .. jc + 16 NB) for the
+// sites a0 .. a1 - 1 and the 16 frequencies from n0, on one wavefront.  The
+// lane keeps its share of E[j][n] for the chunk in registers: in the 4-step
+// product u of block q it supplies column j = jc + 16 q + 4 u + (lane >> 4)
+// of frequency n0 + (lane & 15) (the A' operand) and M[i'][j] of row
+// i' = ib + (lane & 15) (the B operand).  Per 16 rows of a:
+//   D^T[n][i'] = sum_j E[j][n] Ms[i'][j]      (matrix cores)
+// then the row phases e^{i w_n tau_i} = conj E[i'][n] and the sum over i'.
+// The first chunk of b stores M(a, b; w_n), later chunks add to it.  Offsets
+// are taken from bases at the chunk's first column and the row block's
+// first row, so they stay far below 2^32 bytes.
+template <typename T, int NB>
+__device__ void meas_chunk(const View<T>& w, int sp, int b, int jc, int a0, int a1, int n0, bool add) {
+  typedef T t2 __attribute__((ext_vector_type(2)));
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int n_freq = w.n_freq, Nc = w.Nc;
+  const unsigned ldm = w.kpad_cap;
   const auto off = gp(w.m_off);
-  const int ldm = w.kpad_cap;
-  const auto E = gp(w.m_E);
-  const auto v_tau = gp(w.v_tau);
-  const int n_freq = w.n_freq;
-  const int Nc = w.Nc;
-  const int sp = blockIdx.x & 1;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int n0 = blockIdx.y * 16;
-  if (n0 >= n_freq) return;
-  const auto Ms = gp(w.m_Ms[sp]);
+  const int na = n0 + li;
+  const unsigned nac = na < n_freq ? na : 0;   // rows past n_freq are computed and never stored
+  const auto Ej = gp((const t2*)w.m_E + (size_t)jc * n_freq);
+  t2 e[NB][4];
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) e[q][u] = Ej[(unsigned)(16 * q + 4 * u + lk) * (unsigned)n_freq + nac];
+  const T* Mc = w.m_Ms[sp] + (size_t)jc * ldm;
+  const size_t rem = ((size_t)w.kpad_cap - jc) * ldm * sizeof(T);
+  const __amdgpu_buffer_rsrc_t rM =
+      __builtin_amdgcn_make_buffer_rsrc((void*)Mc, (short)0, (int)(rem < 0x7fffffffu ? rem : 0x7fffffffu), BUF_WORD3);
+  const unsigned vcol = (unsigned)lk * ldm * (unsigned)sizeof(T);
+  unsigned rowph[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int n = n0 + Mfma<T>::row(lane, r);
+    rowph[r] = (unsigned)li * n_freq + (n < n_freq ? n : 0);
+  }
   const auto Mab = gp(w.m_Mab[sp]);
-  const int li = lane & 15, lk = lane >> 4;
-  const int na = n0 + li;   // frequency of this lane's A' operand row
-  const int gstride = (gridDim.x >> 1) * (WG / 64) * MPAIRS;
-  for (int pair0 = ((blockIdx.x >> 1) * (WG / 64) + wv) * MPAIRS; pair0 < Nc * Nc; pair0 += gstride) {
-    for (int ab = pair0; ab < pair0 + MPAIRS && ab < Nc * Nc; ++ab) {
-      const int a = ab / Nc, b = ab % Nc;
-      const int ia0 = off[a], ia1 = off[a + 1], jb0 = off[b], jb1 = off[b + 1];
-      double sre[4] = {0, 0, 0, 0}, sim[4] = {0, 0, 0, 0};
-      // buckets are padded to multiples of 16 rows, so the inner dimension
-      // runs in passes of four 4-step MFMAs whose loads are issued together
-      const int nac = na < n_freq ? na : 0;
-      const T ew = (T)(na < n_freq ? 1 : 0);
-      for (int ib = ia0; ib < ia1; ib += 16) {
-        typename Mfma<T>::acc_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
-        const int ip = ib + li;
-        for (int jp = jb0; jp < jb1; jp += 16) {
-          T m[4], er[4], ei[4];
+#pragma unroll 1
+  for (int a = a0; a < a1; ++a) {
+    double sre[4] = {0, 0, 0, 0}, sim[4] = {0, 0, 0, 0};
+#pragma unroll 1
+    for (int ib = off[a]; ib < off[a + 1]; ib += 16) {
+      const unsigned vo = (unsigned)(ib + li) * (unsigned)sizeof(T) + vcol;
+      T m[NB][4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const size_t jk = (size_t)(jp + 4 * u + lk);
-            m[u] = Ms[ip + jk * ldm];
-            er[u] = E[2 * (jk * n_freq + nac)] * ew;
-            ei[u] = E[2 * (jk * n_freq + nac) + 1] * ew;
-          }
+      for (int q = 0; q < NB; ++q)
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            dr = Mfma<T>::run(er[u], m[u], dr);
-            di = Mfma<T>::run(ei[u], m[u], di);
-          }
+        for (int u = 0; u < 4; ++u) m[q][u] = buf_load<T>(rM, vo, (unsigned)(16 * q + 4 * u) * ldm * (unsigned)sizeof(T));
+      const auto Ei = gp((const t2*)w.m_E + (size_t)ib * n_freq);
+      t2 ph[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ph[r] = Ei[rowph[r]];
+      typename Mfma<T>::acc_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          dr = Mfma<T>::run(e[q][u].x, m[q][u], dr);
+          di = Mfma<T>::run(e[q][u].y, m[q][u], di);
         }
-        // lane holds D[n = n0 + row(lane, r)][i' = ib + li]
-        const int i = order[ip];
-        if (i >= 0) {
-          const double ti = v_tau[i];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int n = n0 + Mfma<T>::row(lane, r);
-            const double wn = (2.0 * n + 1.0) * M_PI / w.beta;
-            double s, c;
-            sincos(wn * ti, &s, &c);
-            const double xr = (double)dr[r], xi = (double)di[r];
-            sre[r] += c * xr - s * xi;
-            sim[r] += c * xi + s * xr;
-          }
-        }
-      }
-      // sum over the 16 lanes that share a frequency set (li varies)
+      // lane holds D[n = n0 + row(lane, r)][i' = ib + li]; padding rows of
+      // Ms and E are zero
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        for (int o = 1; o < 16; o <<= 1) {
-          sre[r] += __shfl_xor(sre[r], o, 64);
-          sim[r] += __shfl_xor(sim[r], o, 64);
+        const double c = (double)ph[r].x, s = -(double)ph[r].y;
+        const double xr = (double)dr[r], xi = (double)di[r];
+        sre[r] += c * xr - s * xi;
+        sim[r] += c * xi + s * xr;
+      }
+    }
+    // sum over the 16 lanes that share a frequency set (li varies)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      for (int o = 1; o < 16; o <<= 1) {
+        sre[r] += __shfl_xor(sre[r], o, 64);
+        sim[r] += __shfl_xor(sim[r], o, 64);
+      }
+    if (li == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = n0 + Mfma<T>::row(lane, r);
+        if (n < n_freq) {
+          const size_t o = 2 * (((size_t)a * Nc + b) * n_freq + n);
+          Mab[o] = add ? Mab[o] + sre[r] : sre[r];
+          Mab[o + 1] = add ? Mab[o + 1] + sim[r] : sim[r];
         }
       }
-      if (li == 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int n = n0 + Mfma<T>::row(lane, r);
-          if (n < n_freq) {
-            const size_t o = 2 * (((size_t)a * Nc + b) * n_freq + n);
-            Mab[o] = sre[r];
-            Mab[o + 1] = sim[r];
-          }
+    }
+  }
+}
+
+// The contraction for every pair of sites:
+//   M(a, b; w_n) = sum_{i in a} e^{i w_n tau_i} sum_{j in b} Ms_ij e^{-i w_n tau_j}.
+// A persistent grid takes the work items of the listed walkers (walker by
+// walker: spins, b, groups of a, frequency tiles fastest), one per
+// wavefront; the wavefronts working at one time thus share b's columns of
+// Ms.  Workgroups are dealt to the eight XCDs in turn, so they are numbered
+// here such that each XCD takes a contiguous range of items and its L2 holds
+// the columns they share.
+constexpr int XCDS = 8;
+template <typename T>
+__global__ void __launch_bounds__(WG, 2) k_meas_block(const View<T>* __restrict__ vs, const int* __restrict__ list,
+                                                   const long long* __restrict__ pre) {
+  constexpr int NB = MeasTiles<T>::NB;
+  const int cnt = list[0];
+  if (cnt == 0) return;
+  const long long total = pre[cnt];
+  // everything below is uniform over the wavefront (scalar registers)
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nb = gridDim.x;     // a multiple of XCDS
+  const int lb = (blockIdx.x % XCDS) * (nb / XCDS) + blockIdx.x / XCDS;
+  for (long long it = (long long)lb * (WG / 64) + wv; it < total; it += (long long)nb * (WG / 64)) {
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= it) lo = mid;
+      else hi = mid - 1;
+    }
+    const View<T>& w = vs[list[1 + lo]];
+    const int n_freq = w.n_freq, Nc = w.Nc;
+    const int nft = (n_freq + 15) / 16, ng = meas_groups(Nc, n_freq);
+    long long r = it - pre[lo];
+    const int n0 = 16 * (int)(r % nft);
+    r /= nft;
+    const int g = (int)(r % ng);
+    r /= ng;
+    const int b = (int)(r % Nc);
+    const int sp = (int)(r / Nc);
+    const int per = (Nc + ng - 1) / ng;
+    const int a0 = g * per, a1 = min(Nc, a0 + per);
+    if (a0 >= a1) continue;
+    const auto off = gp(w.m_off);
+    const int jb0 = off[b], jb1 = off[b + 1];
+    if (jb0 == jb1) {
+      // no vertex on site b
+      const auto Mab = gp(w.m_Mab[sp]);
+      for (int x = lane; x < (a1 - a0) * 16; x += 64) {
+        const int n = n0 + (x & 15);
+        if (n < n_freq) {
+          const size_t o = 2 * (((size_t)(a0 + (x >> 4)) * Nc + b) * n_freq + n);
+          Mab[o] = 0.0;
+          Mab[o + 1] = 0.0;
         }
+      }
+      continue;
+    }
+    for (int jc = jb0; jc < jb1; jc += 16 * NB) {
+      const int blocks = min(NB, (jb1 - jc) / 16);
+      const bool add = jc > jb0;
+      switch (blocks) {
+        case 1: meas_chunk<T, 1>(w, sp, b, jc, a0, a1, n0, add); break;
+        case 2: meas_chunk<T, 2>(w, sp, b, jc, a0, a1, n0, add); break;
+        case 3: meas_chunk<T, 3>(w, sp, b, jc, a0, a1, n0, add); break;
+        case 4: meas_chunk<T, 4>(w, sp, b, jc, a0, a1, n0, add); break;
+        case 5: meas_chunk<T, (NB >= 5 ? 5 : 1)>(w, sp, b, jc, a0, a1, n0, add); break;
+        case 6: meas_chunk<T, (NB >= 6 ? 6 : 1)>(w, sp, b, jc, a0, a1, n0, add); break;
+        case 7: meas_chunk<T, (NB >= 7 ? 7 : 1)>(w, sp, b, jc, a0, a1, n0, add); break;
+        default: meas_chunk<T, NB>(w, sp, b, jc, a0, a1, n0, add); break;
       }
     }
   }
@@ -414,7 +564,8 @@ __global__ void __launch_bounds__(WG) k_finalize(const View<T>* __restrict__ vs,
   template __global__ void k_meas_sort<T>(const View<T>*, int);                                 \
   template __global__ void k_meas_copy<T>(const View<T>*, int);                                 \
   template __global__ void k_meas_phase<T>(const View<T>*, int);                                \
-  template __global__ void k_meas_block<T>(const View<T>*, int);                                \
+  template __global__ void k_meas_list<T>(const View<T>*, int, int, int*, long long*);           \
+  template __global__ void k_meas_block<T>(const View<T>*, const int*, const long long*);         \
   template __global__ void k_meas_K<T>(const View<T>*, double*, int);                           \
   template __global__ void k_meas_diag<T>(const View<T>*, double*, int);                        \
   template __global__ void k_finalize<T>(const View<T>*, const double*, const double*, double*, int, double*);
