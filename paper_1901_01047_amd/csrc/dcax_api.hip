@@ -583,14 +583,16 @@ void enqueue_refresh(dcax_walker w, int first, int n, int kmax, bool measure, co
   hipLaunchKernelGGL(k_refresh_begin<T>, dim3(1, 1, n), dim3(1), 0, s, vs, mask);
   if (kmax == 0) return;
   hipLaunchKernelGGL(k_build_ninv<T>, dim3(cdiv(kmax, WG), kmax, n), dim3(WG), 0, s, vs);
-  for (int p0 = 0; p0 < kmax; p0 += NB) {
-    if (kmax <= PANEL_ROWS)
+  const bool one = kmax <= PANEL_ROWS;
+  const int pw = one ? NB_ONE : NB;
+  for (int p0 = 0; p0 < kmax; p0 += pw) {
+    if (one)
       hipLaunchKernelGGL(k_gj_panel<T>, dim3(2, 1, n), dim3(cdiv(kmax, 64) * 64), 0, s, vs, p0);
     else
       for (int c = 0; c <= std::min(NB, kmax - p0); ++c)
         hipLaunchKernelGGL(k_gj_col<T>, dim3(cdiv(kmax, WG), 2, n), dim3(WG), 0, s, vs, p0, c);
-    hipLaunchKernelGGL(k_gj_prep<T>, dim3(cdiv(kmax, WG), 2, n), dim3(WG), 0, s, vs, p0);
-    hipLaunchKernelGGL(k_gj_update<T>, dim3(cdiv(kmax, 64), cdiv(kmax, 64), 2 * n), dim3(WG), 0, s, vs, p0);
+    hipLaunchKernelGGL(k_gj_prep<T>, dim3(cdiv(kmax, WG), 2, n), dim3(WG), 0, s, vs, p0, pw);
+    hipLaunchKernelGGL(k_gj_update<T>, dim3(cdiv(kmax, 64), cdiv(kmax, 64), 2 * n), dim3(WG), 0, s, vs, p0, pw);
   }
   hipLaunchKernelGGL(k_gj_perm<T>, dim3(2, 1, n), dim3(64), 0, s, vs);
   hipLaunchKernelGGL(k_refresh_store<T>, dim3(cdiv(kmax, WG), kmax, 2 * n), dim3(WG), 0, s, vs, measure ? 1 : 0);
@@ -671,6 +673,25 @@ dcax_status probe_and_refresh(dcax_walker w) {
   return DCAX_OK;
 }
 
+// The work list of a measurement launch and the site-sorted copy of M.
+template <typename T>
+void enqueue_sorted_copy(dcax_walker w, int gated) {
+  const View<T>* vs = w->views<T>();
+  hipStream_t s = w->stream;
+  const int W = w->W;
+  const int kb1 = std::max(std::min(w->kpad_max, w->kmax_host() + 16 * w->nc_max), 1);
+  hipLaunchKernelGGL(k_meas_sort<T>, dim3(1, 1, W), dim3(WG), 0, s, vs, gated);
+  hipLaunchKernelGGL(k_meas_list<T>, dim3(1), dim3(64), 0, s, vs, W, gated, w->meas_list_d, w->meas_pre_d);
+  if (kb1 <= MCOPY_ROWS) {      // every walker's padded order fits the LDS column
+    hipLaunchKernelGGL(k_meas_copy<T>, dim3(std::min(kb1, 1024), W), dim3(WG), 0, s, vs, w->meas_list_d);
+  } else {
+    const long long mb = MEAS_BUDGET;
+    const int cx = spread(cdiv(kb1, WG), W, 1, mb);
+    hipLaunchKernelGGL(k_meas_copy_wide<T>, dim3(cx, spread(cdiv(kb1, MCOLS), W, cx, mb), W), dim3(WG), 0, s, vs,
+                       gated);
+  }
+}
+
 template <typename T>
 void enqueue_measure(dcax_walker w, double* acc, double* aux, int gated) {
   const View<T>* vs = w->views<T>();
@@ -685,10 +706,8 @@ void enqueue_measure(dcax_walker w, double* acc, double* aux, int gated) {
   const int ncm = w->nc_max;
   const int kb = std::min(w->kpad_max, w->kmax_host() + 16 * ncm);
   const int kb1 = std::max(kb, 1);
-  hipLaunchKernelGGL(k_meas_sort<T>, dim3(1, 1, W), dim3(WG), 0, s, vs, gated);
+  enqueue_sorted_copy<T>(w, gated);
   const long long mb = MEAS_BUDGET;
-  const int cx = spread(cdiv(kb1, WG), W, 1, mb);
-  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cx, spread(cdiv(kb1, MCOLS), W, cx, mb), W), dim3(WG), 0, s, vs, gated);
   const int px = cdiv(nf, WG);
   hipLaunchKernelGGL(k_meas_phase<T>, dim3(px, spread(cdiv(kb1, MCOLS), W, px, mb), W), dim3(WG), 0, s, vs, gated);
   // the contraction: a persistent grid over the work items of the walkers
@@ -696,7 +715,6 @@ void enqueue_measure(dcax_walker w, double* acc, double* aux, int gated) {
   long long items = 0;
   for (const auto& x : w->wk) items += meas_items(x.geo.Nc, x.p.n_freq);
   const int nbk = (int)std::min<long long>(MEAS_BLOCKS, (std::max(1ll, (items + WG / 64 - 1) / (WG / 64)) + XCDS - 1) / XCDS * XCDS);
-  hipLaunchKernelGGL(k_meas_list<T>, dim3(1), dim3(64), 0, s, vs, W, gated, w->meas_list_d, w->meas_pre_d);
   hipLaunchKernelGGL(k_meas_block<T>, dim3(nbk), dim3(WG), 0, s, vs, w->meas_list_d, w->meas_pre_d);
   hipLaunchKernelGGL(k_meas_K<T>, dim3(px, spread(ncm, W, 2 * px, mb), 2 * W), dim3(WG), 0, s, vs, acc, gated);
   if (gated) hipLaunchKernelGGL(k_meas_done<T>, dim3(1, 1, W), dim3(1), 0, s, vs);
@@ -726,10 +744,7 @@ void enqueue_nfft(dcax_walker w, int half_width, double* grid, double* aux, int 
   const int ncm = w->nc_max;
   const int kb = std::min(w->kpad_max, w->kmax_host() + 16 * ncm);
   const int kb1 = std::max(kb, 1);
-  hipLaunchKernelGGL(k_meas_sort<T>, dim3(1, 1, W), dim3(WG), 0, s, vs, gated);
-  const long long mb = MEAS_BUDGET;
-  const int cx = spread(cdiv(kb1, WG), W, 1, mb);
-  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cx, spread(cdiv(kb1, MCOLS), W, cx, mb), W), dim3(WG), 0, s, vs, gated);
+  enqueue_sorted_copy<T>(w, gated);
   // rows split over groups of sites until the launch has ~1024 workgroups
   const int groups = (int)std::max<long long>(1, std::min<long long>(ncm, 1024 / (2ll * ncm * W)));
   const size_t lds = sizeof(double) * 4 * (size_t)w->nf_max;
@@ -2237,8 +2252,7 @@ dcax_status enqueue_g2(dcax_walker w, int n_w4, int wm, int n_q, double* g2, dou
   // site-sorted M = (e^V - 1) N of every walker (the single-particle measurement's first two steps)
   const View<T>* vs = w->views<T>();
   const int kb1 = std::max(std::min(w->kpad_max, w->kmax_host() + 16 * w->nc_max), 1);
-  hipLaunchKernelGGL(k_meas_sort<T>, dim3(1, 1, W), dim3(WG), 0, s, vs, 0);
-  hipLaunchKernelGGL(k_meas_copy<T>, dim3(cdiv(kb1, WG), cdiv(kb1, MCOLS), W), dim3(WG), 0, s, vs, 0);
+  enqueue_sorted_copy<T>(w, 0);
   const long long per = (long long)nw * Nc * nw, per4 = (long long)n4 * Nc * n4;
   for (int i = 0; i < W; ++i) {
     const View<T>* v = w->views<T>(i);

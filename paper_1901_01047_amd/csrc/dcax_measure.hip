@@ -68,11 +68,63 @@ __global__ void __launch_bounds__(WG) k_meas_sort(const View<T>* __restrict__ vs
   }
 }
 
-// Ms[i'][j'] = (e^{V_i} - 1) N[i][j] in sorted order (zero on padding), in
-// groups of 16 sorted columns (grid-strided over blockIdx.y, rows over x).
+// Ms[i'][j'] = (e^{V_i} - 1) N[i][j] in sorted order (zero on padding).
+// Column by column: column j of N is read in its own order (coalesced) and
+// scaled into LDS, then column j' of Ms is written in sorted order from LDS.
+// One walker of the measurement's work list per blockIdx.y, columns
+// grid-strided over blockIdx.x; orders up to MCOPY_ROWS.
+constexpr int MCOPY_ROWS = 8192;
+template <typename T>
+__global__ void __launch_bounds__(WG) k_meas_copy(const View<T>* __restrict__ vs, const int* __restrict__ list) {
+  if ((int)blockIdx.y >= list[0]) return;
+  const View<T>& w = vs[list[1 + blockIdx.y]];
+  __shared__ T col_s[MCOPY_ROWS];
+  const auto order = gp(w.m_order);
+  const auto off = gp(w.m_off);
+  const auto v_s = gp(w.v_s);
+  const int kpad = off[w.Nc];
+  const int k = w.ctl->k;
+  const size_t ldm = w.kpad_cap;
+  const int t = threadIdx.x;
+  for (int jp = blockIdx.x; jp < kpad; jp += gridDim.x) {
+    const int j = order[jp];
+#pragma unroll 1
+    for (int sp = 0; sp < 2; ++sp) {
+      const auto Ms = gp(w.m_Ms[sp]) + (size_t)jp * ldm;
+      if (j < 0) {
+        for (int ip = t; ip < kpad; ip += WG) Ms[ip] = (T)0;
+        continue;
+      }
+      const auto Nj = gp(w.N[sp]) + (size_t)j * w.ld;
+      const double fu = w.ev[sp][0] - 1.0, fd = w.ev[sp][1] - 1.0;
+      for (int i0 = t; i0 < k; i0 += 4 * WG) {
+        T v[4];
+        int sv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + u * WG < k ? i0 + u * WG : i0;
+          v[u] = Nj[i];
+          sv[u] = v_s[i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 + u * WG < k) col_s[i0 + u * WG] = (T)((sv[u] > 0 ? fu : fd) * (double)v[u]);
+      }
+      __syncthreads();
+      for (int ip = t; ip < kpad; ip += WG) {
+        const int i = order[ip];
+        Ms[ip] = i >= 0 ? col_s[i] : (T)0;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// The same copy for orders above MCOPY_ROWS: a gather from N by sorted row,
+// in groups of 16 sorted columns (grid-strided over blockIdx.y, rows over x).
 constexpr int MCOLS = 16;
 template <typename T>
-__global__ void __launch_bounds__(WG) k_meas_copy(const View<T>* __restrict__ vs, int gated) {
+__global__ void __launch_bounds__(WG) k_meas_copy_wide(const View<T>* __restrict__ vs, int gated) {
   const View<T>& w = vs[blockIdx.z];
   if (meas_skip(w.ctl, gated)) return;
   const auto order = gp(w.m_order);
@@ -165,8 +217,8 @@ __global__ void __launch_bounds__(64) k_meas_list(const View<T>* __restrict__ vs
     long long items = 0;
     if (z < W) {
       const View<T>& w = vs[z];
-      on = !meas_skip(w.ctl, gated) && w.n_freq > 0;
-      if (on) items = meas_items(w.Nc, w.n_freq);
+      on = !meas_skip(w.ctl, gated);
+      if (on) items = meas_items(w.Nc, w.n_freq);      // none without frequencies
     }
     long long sc = items;     // inclusive scan over the lanes
     for (int o = 1; o < 64; o <<= 1) {
@@ -562,7 +614,8 @@ __global__ void __launch_bounds__(WG) k_finalize(const View<T>* __restrict__ vs,
 
 #define DCAX_INSTANTIATE_MEASURE(T)                                                             \
   template __global__ void k_meas_sort<T>(const View<T>*, int);                                 \
-  template __global__ void k_meas_copy<T>(const View<T>*, int);                                 \
+  template __global__ void k_meas_copy<T>(const View<T>*, const int*);                          \
+  template __global__ void k_meas_copy_wide<T>(const View<T>*, int);                            \
   template __global__ void k_meas_phase<T>(const View<T>*, int);                                \
   template __global__ void k_meas_list<T>(const View<T>*, int, int, int*, long long*);           \
   template __global__ void k_meas_block<T>(const View<T>*, const int*, const long long*);         \

@@ -19,7 +19,11 @@
 
 namespace dcax {
 
-constexpr int NB = 32;
+// Panel widths: 64 columns for the column-step form (each rank-NB update
+// streams the whole matrix once, so wider panels halve that traffic), 32 for
+// the one-workgroup form (one panel row per thread in registers at 1024
+// threads).  NB also sizes the panel buffers and pivot records.
+constexpr int NB = 64, NB_ONE = 32;
 // column-step pivot records: two rows at the pivot position, then per parity
 // one slot of 2 + NB doubles per workgroup of WG rows
 constexpr int GJC_OC = 0, GJC_SLOT = 2 * NB;
@@ -71,19 +75,19 @@ __global__ void __launch_bounds__(PANEL_ROWS) k_gj_panel(const View<T>* __restri
   const View<T>& w = vs[blockIdx.z];
   const int k = w.ctl->k_ref;
   if (p0 >= k) return;
-  const int nb = (k - p0 < NB) ? k - p0 : NB;
+  const int nb = (k - p0 < NB_ONE) ? k - p0 : NB_ONE;
   const int sp = blockIdx.x;
   const auto Mg = gp(w.M[sp]);
   const size_t ld = w.cap;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nwv = (int)(blockDim.x >> 6);
   const bool live = t < k;
   const size_t ro = live ? (size_t)t : 0;
-  __shared__ double rs_s[NB], oc_s[NB], vmax_s[PANEL_ROWS / 64];
+  __shared__ double rs_s[NB_ONE], oc_s[NB_ONE], vmax_s[PANEL_ROWS / 64];
   __shared__ int imax_s[PANEL_ROWS / 64];
   __shared__ double app_s;
-  double a[NB];
+  double a[NB_ONE];
 #pragma unroll
-  for (int x = 0; x < NB; ++x) a[x] = Mg[ro + (size_t)(p0 + (x < nb ? x : 0)) * ld];
+  for (int x = 0; x < NB_ONE; ++x) a[x] = Mg[ro + (size_t)(p0 + (x < nb ? x : 0)) * ld];
   double dsign = 1.0;
   for (int cidx = 0; cidx < nb; ++cidx) {
     const int c = p0 + cidx;
@@ -91,7 +95,7 @@ __global__ void __launch_bounds__(PANEL_ROWS) k_gj_panel(const View<T>* __restri
     int bi = k;
     if (live && t >= c) {
 #pragma unroll
-      for (int x = 0; x < NB; ++x) best = (x == cidx) ? fabs(a[x]) : best;
+      for (int x = 0; x < NB_ONE; ++x) best = (x == cidx) ? fabs(a[x]) : best;
       bi = t;
     }
     argmax_wave(best, bi);
@@ -111,14 +115,14 @@ __global__ void __launch_bounds__(PANEL_ROWS) k_gj_panel(const View<T>* __restri
     if (t == pr) {
       double app = 0.0;
 #pragma unroll
-      for (int x = 0; x < NB; ++x) app = (x == cidx) ? a[x] : app;
+      for (int x = 0; x < NB_ONE; ++x) app = (x == cidx) ? a[x] : app;
       app_s = app;
 #pragma unroll
-      for (int x = 0; x < NB; ++x) rs_s[x] = (x == cidx) ? 1.0 / app : a[x] / app;
+      for (int x = 0; x < NB_ONE; ++x) rs_s[x] = (x == cidx) ? 1.0 / app : a[x] / app;
     }
     if (t == c)
 #pragma unroll
-      for (int x = 0; x < NB; ++x) oc_s[x] = a[x];
+      for (int x = 0; x < NB_ONE; ++x) oc_s[x] = a[x];
     __syncthreads();
     const double a_pp = app_s;
     if (t == 0) {
@@ -129,22 +133,22 @@ __global__ void __launch_bounds__(PANEL_ROWS) k_gj_panel(const View<T>* __restri
     dsign *= ((a_pp < 0.0) ? -1.0 : 1.0) * ((pr != c) ? -1.0 : 1.0);
     if (t == c) {
 #pragma unroll
-      for (int x = 0; x < NB; ++x) a[x] = rs_s[x];
+      for (int x = 0; x < NB_ONE; ++x) a[x] = rs_s[x];
     } else {
       if (t == pr)
 #pragma unroll
-        for (int x = 0; x < NB; ++x) a[x] = oc_s[x];
+        for (int x = 0; x < NB_ONE; ++x) a[x] = oc_s[x];
       double f = 0.0;
 #pragma unroll
-      for (int x = 0; x < NB; ++x) f = (x == cidx) ? a[x] : f;
+      for (int x = 0; x < NB_ONE; ++x) f = (x == cidx) ? a[x] : f;
 #pragma unroll
-      for (int x = 0; x < NB; ++x) a[x] = (x == cidx) ? -f * rs_s[x] : a[x] - f * rs_s[x];
+      for (int x = 0; x < NB_ONE; ++x) a[x] = (x == cidx) ? -f * rs_s[x] : a[x] - f * rs_s[x];
     }
     __syncthreads();      // rs_s, oc_s and the candidates are rewritten
   }
   if (live)
 #pragma unroll
-    for (int x = 0; x < NB; ++x)
+    for (int x = 0; x < NB_ONE; ++x)
       if (x < nb) Mg[t + (size_t)(p0 + x) * ld] = a[x];
   if (t == 0) w.detsign[sp] *= dsign;
 }
@@ -290,13 +294,14 @@ __global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, i
 
 // Applies the panel's row swaps to the other columns, moves their panel rows
 // into Tm (row-major, [nb][cap]) and zeroes them; copies the panel columns
-// into P (column-major).  One thread per column (blockIdx.y = spin).
+// into P (column-major); pw is the panel width.  One thread per column
+// (blockIdx.y = spin).
 template <typename T>
-__global__ void __launch_bounds__(WG) k_gj_prep(const View<T>* __restrict__ vs, int p0) {
+__global__ void __launch_bounds__(WG) k_gj_prep(const View<T>* __restrict__ vs, int p0, int pw) {
   const View<T>& w = vs[blockIdx.z];
   const int k = w.ctl->k_ref;
   if (p0 >= k) return;
-  const int nb = (k - p0 < NB) ? k - p0 : NB;
+  const int nb = (k - p0 < pw) ? k - p0 : pw;
   const int sp = blockIdx.y;
   const auto M = gp(w.M[sp]);
   const auto ipiv = gp(w.ipiv[sp]);
@@ -328,14 +333,15 @@ __global__ void __launch_bounds__(WG) k_gj_prep(const View<T>* __restrict__ vs, 
   for (int x = 0; x < nb; ++x) P[j + (size_t)x * ldt] = M[j + (size_t)(p0 + x) * ldm];
 }
 
-// Trailing update M += P Tm of panel p0 (blockIdx.z = 2 walker + spin).
+// Trailing update M += P Tm of the panel of pw columns from p0
+// (blockIdx.z = 2 walker + spin).
 template <typename T>
-__global__ void __launch_bounds__(WG) k_gj_update(const View<T>* __restrict__ vs, int p0) {
+__global__ void __launch_bounds__(WG) k_gj_update(const View<T>* __restrict__ vs, int p0, int pw) {
   const View<T>& w = vs[blockIdx.z >> 1];
   const int sp = blockIdx.z & 1;
   const int k = w.ctl->k_ref;
   if (p0 >= k) return;
-  const int nb = (k - p0 < NB) ? k - p0 : NB;
+  const int nb = (k - p0 < pw) ? k - p0 : pw;
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   if (i0 >= k || j0 >= k) return;
   fold_tile<double>(w.M[sp], w.cap, w.P[sp], w.cap, w.Tm[sp], w.cap, k, k, nb, i0, j0);
@@ -510,8 +516,8 @@ __global__ void __launch_bounds__(WG) k_probe(const View<T>* __restrict__ vs, un
   template __global__ void k_build_ninv<T>(const View<T>*);           \
   template __global__ void k_gj_panel<T>(const View<T>*, int);        \
   template __global__ void k_gj_col<T>(const View<T>*, int, int);     \
-  template __global__ void k_gj_prep<T>(const View<T>*, int);         \
-  template __global__ void k_gj_update<T>(const View<T>*, int);       \
+  template __global__ void k_gj_prep<T>(const View<T>*, int, int);    \
+  template __global__ void k_gj_update<T>(const View<T>*, int, int);  \
   template __global__ void k_refresh_store<T>(const View<T>*, int);   \
   template __global__ void k_gj_perm<T>(const View<T>*);              \
   template __global__ void k_drift<T>(const View<T>*);
