@@ -153,12 +153,15 @@ typedef struct {
   int32_t touched_twice;
   int32_t reserved2;       /* must be 0 */
   /* Drift control (finite, >= 0; 0 = off; walker 0's value governs the
-   * handle): after every sweep that ends without a periodic refresh, each
-   * walker's N is probed against its definition (dcax_probe_N) and rebuilt
-   * in FP64 when the largest sampled residual exceeds drift_tol (all such
-   * walkers of the batch in one rebuild pass).  Meant for
-   * FP32-mixed chains, whose rounding grows between refreshes and can be
-   * amplified by an update with a small ratio. */
+   * handle): at the end of each of a walker's sweeps its N is probed against
+   * its definition (sampled entries of N^{-1} N, as dcax_probe_N) and, when
+   * the largest sampled residual exceeds drift_tol, rebuilt in FP64 before
+   * the sweep's measurement is taken (all such walkers of a batch in one
+   * rebuild pass).  Device-scheduled sweeps (dcax_sweep_measure,
+   * dcax_run_rounds) probe on the device before each measurement and hold
+   * the walker until the host has rebuilt it; dcax_sweep probes after each
+   * sweep.  Meant for FP32-mixed chains, whose rounding grows between
+   * refreshes and can be amplified by an update with a small ratio. */
   double drift_tol;
 } dcax_params;
 
@@ -193,9 +196,11 @@ typedef struct {
   double y_seconds;         /* Y-column kernel time summed over the timed windows */
   int64_t accepted_flips;   /* accepted spin flips */
   int64_t neglected;        /* proposals rejected as touching a spin twice (touched_twice = 1) */
-  int64_t probes;           /* probes of N (dcax_probe_N and the drift control), per handle */
+  int64_t probes;           /* probe passes of N (dcax_probe_N, the drift control after a
+                               dcax_sweep sweep or a round of device-scheduled sweeps) */
   int64_t probe_refreshes;  /* walkers rebuilt by the drift control */
-  double last_probe;        /* largest residual of the last probe over the walkers */
+  double last_probe;        /* largest residual of the last probe pass over the walkers (of
+                               device-scheduled sweeps: over the walkers it held) */
 } dcax_stats;
 
 /* Create a batch of n_walkers independent walkers (Markov chains; Sec. 3.1,

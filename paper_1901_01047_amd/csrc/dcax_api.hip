@@ -237,13 +237,16 @@ __global__ void k_meas_done(const View<T>* __restrict__ vs) {
 }
 
 template <typename T>
-__global__ void k_refresh_begin(const View<T>* __restrict__ vs, const int* __restrict__ mask) {
+__global__ void k_refresh_begin(const View<T>* __restrict__ vs, const int* __restrict__ mask, int by_hold) {
   const View<T>& w = vs[blockIdx.z];
   w.detsign[0] = 1.0;
   w.detsign[1] = 1.0;
   w.ctl->drift = 0.0;
-  // a masked refresh rebuilds only the flagged walkers
-  w.ctl->k_ref = (mask == nullptr || mask[blockIdx.z]) ? w.ctl->k : 0;
+  // a masked refresh rebuilds only the flagged walkers (by the mask, or those
+  // the sweep-end probe held); a rebuilt walker is released
+  const bool on = by_hold ? w.ctl->hold != 0 : (mask == nullptr || mask[blockIdx.z]);
+  w.ctl->k_ref = on ? w.ctl->k : 0;
+  if (on) w.ctl->hold = 0;
 }
 
 // After dcax_set_config's refresh: the sign of the configuration is the sign
@@ -288,6 +291,7 @@ struct dcax_walker_s {
   long long* meas_pre_d = nullptr;
   long long probes = 0, probe_refreshes = 0;
   double last_probe = 0.0;
+  long long held_since = -1;   // round at which the drift control first held a walker still held
   dcax_allocator alloc{};
   hipStream_t stream = nullptr;
   std::vector<WalkerHost> wk;
@@ -576,11 +580,12 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
 
 // FP64 refresh of N for walkers [first, first + n); nothing is read back.
 template <typename T>
-void enqueue_refresh(dcax_walker w, int first, int n, int kmax, bool measure, const int* mask = nullptr) {
+void enqueue_refresh(dcax_walker w, int first, int n, int kmax, bool measure, const int* mask = nullptr,
+                     bool by_hold = false) {
   w->fresh = false;
   const View<T>* vs = w->views<T>(first);
   hipStream_t s = w->stream;
-  hipLaunchKernelGGL(k_refresh_begin<T>, dim3(1, 1, n), dim3(1), 0, s, vs, mask);
+  hipLaunchKernelGGL(k_refresh_begin<T>, dim3(1, 1, n), dim3(1), 0, s, vs, mask, by_hold ? 1 : 0);
   if (kmax == 0) return;
   hipLaunchKernelGGL(k_build_ninv<T>, dim3(cdiv(kmax, WG), kmax, n), dim3(WG), 0, s, vs);
   const bool one = kmax <= PANEL_ROWS;
@@ -619,10 +624,11 @@ dcax_status refresh_all(dcax_walker w, double* drift) {
 dcax_status probe_all(dcax_walker w, std::vector<double>& res) {
   const unsigned long long salt = 0x9E3779B97F4A7C15ULL * (unsigned long long)(++w->probes) ^ w->wk[0].p.seed;
   if (w->mixed)
-    hipLaunchKernelGGL(k_probe<float>, dim3(1, 2, w->W), dim3(WG), 0, w->stream, w->views<float>(), salt, w->probe_d);
+    hipLaunchKernelGGL(k_probe<float>, dim3(1, 2, w->W), dim3(WG), 0, w->stream, w->views<float>(), salt, w->probe_d,
+                       0.0);
   else
     hipLaunchKernelGGL(k_probe<double>, dim3(1, 2, w->W), dim3(WG), 0, w->stream, w->views<double>(), salt,
-                       w->probe_d);
+                       w->probe_d, 0.0);
   HIPCHK(hipGetLastError());
   std::vector<double> h(2 * w->W);
   HIPCHK(hipMemcpyAsync(h.data(), w->probe_d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, w->stream));
@@ -1106,8 +1112,60 @@ void enqueue_round(dcax_walker w, int kb, int nwin, double* acc, double* aux, in
   w->fresh = false;
   hipLaunchKernelGGL(k_round_begin<T>, dim3(1, 1, w->W), dim3(1), 0, w->stream, w->views<T>());
   for (int i = 0; i < nwin; ++i) enqueue_window<T>(w, kb, false);
+  // drift control: each walker whose sweep has just ended is probed before
+  // its measurement, and held for a rebuild if N has drifted too far
+  const double tol = w->wk[0].p.drift_tol;
+  if (tol > 0.0)
+    hipLaunchKernelGGL(k_probe<T>, dim3(1, 2, w->W), dim3(WG), 0, w->stream, w->views<T>(),
+                       0xD1B54A32D192ED03ULL ^ w->wk[0].p.seed, w->probe_d, tol);
   if (nfft_hw > 0) enqueue_nfft<T>(w, nfft_hw, acc, aux, 1);
   else enqueue_measure<T>(w, acc, aux, 1);
+}
+
+// After a round: rebuild the walkers the sweep-end probe held (one masked
+// refresh for all of them), then take their pending measurements.  A rebuild
+// pass costs about the same for one walker as for many (its column steps are
+// launch-latency-bound), while a held walker only sits out the rounds (the
+// batch's launches shrink with it), so in a batch the pass waits until an
+// eighth of the walkers are held or the first of them has waited `wait`
+// rounds; force releases at once.  Synchronises.
+template <typename T>
+dcax_status release_held(dcax_walker w, double* acc, double* aux, int nfft_hw, long long wait, bool force) {
+  dcax_status st = sync_all(w);
+  if (st != DCAX_OK) return st;
+  ++w->probes;
+  int nheld = 0, kheld = 0;
+  for (int i = 0; i < w->W; ++i)
+    if (w->h_ctl[i].hold) {
+      ++nheld;
+      kheld = std::max(kheld, w->h_ctl[i].k);
+    }
+  if (nheld == 0) {
+    w->held_since = -1;
+    return DCAX_OK;
+  }
+  if (w->held_since < 0) w->held_since = w->rounds_done;
+  if (!force && nheld < std::max(1, w->W / 8) && w->rounds_done - w->held_since < wait) return DCAX_OK;
+  w->held_since = -1;
+  std::vector<double> h(2 * w->W);
+  HIPCHK(hipMemcpy(h.data(), w->probe_d, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+  double m = 0.0;
+  for (int i = 0; i < w->W; ++i)
+    if (w->h_ctl[i].hold)
+      for (int sp = 0; sp < 2; ++sp) m = (h[2 * i + sp] > m || h[2 * i + sp] != h[2 * i + sp]) ? h[2 * i + sp] : m;
+  w->last_probe = m;
+  w->probe_refreshes += nheld;
+  enqueue_refresh<T>(w, 0, w->W, kheld, true, nullptr, true);
+  if (nfft_hw > 0) enqueue_nfft<T>(w, nfft_hw, acc, aux, 1);
+  else enqueue_measure<T>(w, acc, aux, 1);
+  HIPCHK(hipGetLastError());
+  std::vector<int> was(w->W);
+  for (int i = 0; i < w->W; ++i) was[i] = w->h_ctl[i].hold;
+  st = sync_all(w);
+  if (st != DCAX_OK) return st;
+  for (int i = 0; i < w->W; ++i)
+    if (was[i]) w->max_drift = std::max(w->max_drift, w->h_ctl[i].drift);
+  return DCAX_OK;
 }
 
 // Sweeps of every walker, each followed by its measurement, scheduled on the
@@ -1201,9 +1259,23 @@ dcax_status sweep_rounds(dcax_walker w, int n, double* acc, double* aux, long lo
         if (st != DCAX_OK) return st;
         w->last_drift = d;
         w->max_drift = std::max(w->max_drift, d);
-      } else if (w->wk[0].p.drift_tol > 0.0 && w->rounds_done % rounds_per_sweep == 0) {
-        // once per sweep of the longest walker
-        st = probe_and_refresh(w);
+        // walkers the probe held are rebuilt too: take their measurements
+        if (w->wk[0].p.drift_tol > 0.0) {
+          if (nfft_hw > 0) {
+            if (w->mixed) enqueue_nfft<float>(w, nfft_hw, acc, aux, 1);
+            else enqueue_nfft<double>(w, nfft_hw, acc, aux, 1);
+          } else if (w->mixed) {
+            enqueue_measure<float>(w, acc, aux, 1);
+          } else {
+            enqueue_measure<double>(w, acc, aux, 1);
+          }
+          HIPCHK(hipGetLastError());
+        }
+      } else if (w->wk[0].p.drift_tol > 0.0) {
+        const long long wait = std::max<long long>(1, rounds_per_sweep / 4);
+        const bool last = r + 1 == planned;
+        st = w->mixed ? release_held<float>(w, acc, aux, nfft_hw, wait, last)
+                      : release_held<double>(w, acc, aux, nfft_hw, wait, last);
         if (st != DCAX_OK) return st;
       }
     }

@@ -63,7 +63,9 @@ struct Ctl {
   long long n_acc_flip;  // accepted spin flips
   long long n_neglect;   // proposals rejected as touching a spin twice
   int carry_kind;        // kind (1 removal, 2 flip) of the carried proposal's target
-  int pad2_;
+  // the drift probe at the end of this walker's sweep found N beyond the
+  // tolerance: its measurement and next sweep wait for the rebuild
+  int hold;
 };
 
 struct WinProp {      // one proposal of the current window
@@ -158,9 +160,10 @@ struct View {
 __device__ inline void latch(Ctl* c, int code) { atomicCAS(&c->status, 0, code); }
 
 // A gated measurement covers the walkers whose sweep has ended and not yet
-// been measured (device-scheduled sweeps); an ungated one covers all.
+// been measured (device-scheduled sweeps), unless held for a rebuild; an
+// ungated one covers all.
 __device__ inline bool meas_skip(const Ctl* c, int gated) {
-  return gated && !(c->status == 0 && c->meas_due && c->pos >= c->end);
+  return gated && !(c->status == 0 && c->meas_due && c->pos >= c->end && !c->hold);
 }
 
 __device__ inline int s01(int s) { return s > 0 ? 0 : 1; }

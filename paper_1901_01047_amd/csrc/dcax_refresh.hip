@@ -467,12 +467,19 @@ __device__ inline unsigned long long probe_mix(unsigned long long x) {
   return x ^ (x >> 31);
 }
 
+// gate_tol > 0: only walkers whose sweep has just ended with its measurement
+// pending are probed (the others report 0), each with pairs drawn afresh per
+// sweep, and a residual above gate_tol (or NaN) sets the walker's hold flag,
+// which keeps its measurement and next sweep back until N is rebuilt.
 template <typename T>
 __global__ void __launch_bounds__(WG) k_probe(const View<T>* __restrict__ vs, unsigned long long salt,
-                                              double* __restrict__ out) {
+                                              double* __restrict__ out, double gate_tol) {
   const View<T>& w = vs[blockIdx.z];
   const int sp = blockIdx.y;
-  const int k = w.ctl->k;
+  Ctl* ctl = w.ctl;
+  const bool gated = gate_tol > 0.0;
+  if (gated) salt ^= probe_mix((unsigned long long)ctl->n_sweeps + 0x51ED270B7ULL);
+  const int k = (gated && (ctl->hold || meas_skip(ctl, 1))) ? 0 : ctl->k;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const auto N = gp(w.N[sp]);
   double worst = 0.0;
@@ -508,11 +515,12 @@ __global__ void __launch_bounds__(WG) k_probe(const View<T>* __restrict__ vs, un
     double m = 0.0;
     for (int v = 0; v < WG / 64; ++v) m = (w_s[v] > m || w_s[v] != w_s[v]) ? w_s[v] : m;
     out[2 * blockIdx.z + sp] = m;
+    if (gated && !(m <= gate_tol)) atomicOr(&ctl->hold, 1);
   }
 }
 
 #define DCAX_INSTANTIATE_REFRESH(T)                                   \
-  template __global__ void k_probe<T>(const View<T>*, unsigned long long, double*); \
+  template __global__ void k_probe<T>(const View<T>*, unsigned long long, double*, double); \
   template __global__ void k_build_ninv<T>(const View<T>*);           \
   template __global__ void k_gj_panel<T>(const View<T>*, int);        \
   template __global__ void k_gj_col<T>(const View<T>*, int, int);     \
