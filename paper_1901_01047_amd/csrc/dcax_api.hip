@@ -581,21 +581,26 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
 // FP64 refresh of N for walkers [first, first + n); nothing is read back.
 template <typename T>
 void enqueue_refresh(dcax_walker w, int first, int n, int kmax, bool measure, const int* mask = nullptr,
-                     bool by_hold = false) {
+                     bool by_hold = false, int n_rebuilt = -1) {
   w->fresh = false;
   const View<T>* vs = w->views<T>(first);
   hipStream_t s = w->stream;
   hipLaunchKernelGGL(k_refresh_begin<T>, dim3(1, 1, n), dim3(1), 0, s, vs, mask, by_hold ? 1 : 0);
   if (kmax == 0) return;
   hipLaunchKernelGGL(k_build_ninv<T>, dim3(cdiv(kmax, WG), kmax, n), dim3(WG), 0, s, vs);
+  // panel width: see dcax_refresh.hip (wide panels pay off from three
+  // rebuilt walkers on)
   const bool one = kmax <= PANEL_ROWS;
-  const int pw = one ? NB_ONE : NB;
+  const int pw = (one || (n_rebuilt >= 0 ? n_rebuilt : n) < 3) ? NB_ONE : NB;
   for (int p0 = 0; p0 < kmax; p0 += pw) {
     if (one)
       hipLaunchKernelGGL(k_gj_panel<T>, dim3(2, 1, n), dim3(cdiv(kmax, 64) * 64), 0, s, vs, p0);
-    else
+    else if (pw == NB)
       for (int c = 0; c <= std::min(NB, kmax - p0); ++c)
-        hipLaunchKernelGGL(k_gj_col<T>, dim3(cdiv(kmax, WG), 2, n), dim3(WG), 0, s, vs, p0, c);
+        hipLaunchKernelGGL((k_gj_col<T, NB>), dim3(cdiv(kmax, WG), 2, n), dim3(WG), 0, s, vs, p0, c);
+    else
+      for (int c = 0; c <= std::min(NB_ONE, kmax - p0); ++c)
+        hipLaunchKernelGGL((k_gj_col<T, NB_ONE>), dim3(cdiv(kmax, WG), 2, n), dim3(WG), 0, s, vs, p0, c);
     hipLaunchKernelGGL(k_gj_prep<T>, dim3(cdiv(kmax, WG), 2, n), dim3(WG), 0, s, vs, p0, pw);
     hipLaunchKernelGGL(k_gj_update<T>, dim3(cdiv(kmax, 64), cdiv(kmax, 64), 2 * n), dim3(WG), 0, s, vs, p0, pw);
   }
@@ -668,8 +673,8 @@ dcax_status probe_and_refresh(dcax_walker w) {
   // their N (their rebuild order is 0), so the sequence costs about what one
   // walker's costs (its column steps are launch-latency-bound)
   HIPCHK(hipMemcpyAsync(w->probe_mask_d, flag.data(), sizeof(int) * w->W, hipMemcpyHostToDevice, w->stream));
-  if (w->mixed) enqueue_refresh<float>(w, 0, w->W, kflag, true, w->probe_mask_d);
-  else enqueue_refresh<double>(w, 0, w->W, kflag, true, w->probe_mask_d);
+  if (w->mixed) enqueue_refresh<float>(w, 0, w->W, kflag, true, w->probe_mask_d, false, nflag);
+  else enqueue_refresh<double>(w, 0, w->W, kflag, true, w->probe_mask_d, false, nflag);
   HIPCHK(hipGetLastError());
   w->fresh = false;
   st = sync_all(w);
@@ -1155,7 +1160,7 @@ dcax_status release_held(dcax_walker w, double* acc, double* aux, int nfft_hw, l
       for (int sp = 0; sp < 2; ++sp) m = (h[2 * i + sp] > m || h[2 * i + sp] != h[2 * i + sp]) ? h[2 * i + sp] : m;
   w->last_probe = m;
   w->probe_refreshes += nheld;
-  enqueue_refresh<T>(w, 0, w->W, kheld, true, nullptr, true);
+  enqueue_refresh<T>(w, 0, w->W, kheld, true, nullptr, true, nheld);
   if (nfft_hw > 0) enqueue_nfft<T>(w, nfft_hw, acc, aux, 1);
   else enqueue_measure<T>(w, acc, aux, 1);
   HIPCHK(hipGetLastError());

@@ -19,10 +19,12 @@
 
 namespace dcax {
 
-// Panel widths: 64 columns for the column-step form (each rank-NB update
-// streams the whole matrix once, so wider panels halve that traffic), 32 for
-// the one-workgroup form (one panel row per thread in registers at 1024
-// threads).  NB also sizes the panel buffers and pivot records.
+// Panel widths.  The column-step form takes 64 columns when it rebuilds
+// many walkers (each rank-64 update streams the matrix once per 64 columns
+// instead of per 32) and 32 for a few (its column launches, which dominate
+// then, read and write the whole panel each); the one-workgroup form takes
+// 32 (one panel row per thread in registers at 1024 threads).  NB sizes the
+// panel buffers and the pivot records for either width.
 constexpr int NB = 64, NB_ONE = 32;
 // column-step pivot records: two rows at the pivot position, then per parity
 // one slot of 2 + NB doubles per workgroup of WG rows
@@ -172,12 +174,12 @@ __global__ void __launch_bounds__(PANEL_ROWS) k_gj_panel(const View<T>* __restri
 // Record layout (gjc, doubles per spin): [GJC_OC + p NB ..) the row at the
 // pivot position for parity p = column & 1; then per parity and workgroup b
 // a slot of 2 + NB doubles at gjc_slot(p, b, cap): |value|, row, row values.
-template <typename T>
+template <typename T, int PW>
 __global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, int p0, int cidx) {
   const View<T>& w = vs[blockIdx.z];
   const int k = w.ctl->k_ref;
   if (p0 >= k) return;
-  const int nb = (k - p0 < NB) ? k - p0 : NB;
+  const int nb = (k - p0 < PW) ? k - p0 : PW;
   const int nwg = (k + WG - 1) / WG;
   if (cidx > nb || (int)blockIdx.x >= nwg) return;
   const int sp = blockIdx.y;
@@ -188,12 +190,12 @@ __global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, i
   const int r = blockIdx.x * WG + t;
   const bool live = r < k;
   const size_t ro = live ? (size_t)r : 0;
-  __shared__ double vmax_s[WG / 64], rs_s[NB], oc_s[NB];
+  __shared__ double vmax_s[WG / 64], rs_s[PW], oc_s[PW];
   __shared__ int imax_s[WG / 64];
   __shared__ double app_s;
-  double a[NB];
+  double a[PW];
 #pragma unroll
-  for (int x = 0; x < NB; ++x) a[x] = Mg[ro + (size_t)(p0 + (x < nb ? x : 0)) * ld];
+  for (int x = 0; x < PW; ++x) a[x] = Mg[ro + (size_t)(p0 + (x < nb ? x : 0)) * ld];
   if (cidx > 0) {
     const int cm = cidx - 1, cp = p0 + cm, par = cm & 1;
     double best = -1.0;
@@ -228,7 +230,7 @@ __global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, i
     if (t == 0) app_s = prow[cm];
     __syncthreads();
     const double a_pp = app_s;
-    if (t < NB) {
+    if (t < PW) {
       rs_s[t] = (t == cm) ? 1.0 / a_pp : prow[t] / a_pp;
       oc_s[t] = rec[GJC_OC + par * NB + t];
     }
@@ -240,20 +242,20 @@ __global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, i
     __syncthreads();
     if (r == cp) {
 #pragma unroll
-      for (int x = 0; x < NB; ++x) a[x] = rs_s[x];
+      for (int x = 0; x < PW; ++x) a[x] = rs_s[x];
     } else {
       if (r == pr)
 #pragma unroll
-        for (int x = 0; x < NB; ++x) a[x] = oc_s[x];
+        for (int x = 0; x < PW; ++x) a[x] = oc_s[x];
       double f = 0.0;
 #pragma unroll
-      for (int x = 0; x < NB; ++x) f = (x == cm) ? a[x] : f;
+      for (int x = 0; x < PW; ++x) f = (x == cm) ? a[x] : f;
 #pragma unroll
-      for (int x = 0; x < NB; ++x) a[x] = (x == cm) ? -f * rs_s[x] : a[x] - f * rs_s[x];
+      for (int x = 0; x < PW; ++x) a[x] = (x == cm) ? -f * rs_s[x] : a[x] - f * rs_s[x];
     }
     if (live)
 #pragma unroll
-      for (int x = 0; x < NB; ++x)
+      for (int x = 0; x < PW; ++x)
         if (x < nb) Mg[r + (size_t)(p0 + x) * ld] = a[x];
     __syncthreads();      // the candidates below reuse vmax_s / imax_s
   }
@@ -263,7 +265,7 @@ __global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, i
   int bi = k;
   if (live && r >= c) {
 #pragma unroll
-    for (int x = 0; x < NB; ++x) best = (x == cidx) ? fabs(a[x]) : best;
+    for (int x = 0; x < PW; ++x) best = (x == cidx) ? fabs(a[x]) : best;
     bi = r;
   }
   argmax_wave(best, bi);
@@ -286,10 +288,10 @@ __global__ void __launch_bounds__(WG) k_gj_col(const View<T>* __restrict__ vs, i
   }
   if (r == wbi)
 #pragma unroll
-    for (int x = 0; x < NB; ++x) sl[2 + x] = a[x];
+    for (int x = 0; x < PW; ++x) sl[2 + x] = a[x];
   if (r == c)
 #pragma unroll
-    for (int x = 0; x < NB; ++x) rec[GJC_OC + par * NB + x] = a[x];
+    for (int x = 0; x < PW; ++x) rec[GJC_OC + par * NB + x] = a[x];
 }
 
 // Applies the panel's row swaps to the other columns, moves their panel rows
@@ -523,7 +525,8 @@ __global__ void __launch_bounds__(WG) k_probe(const View<T>* __restrict__ vs, un
   template __global__ void k_probe<T>(const View<T>*, unsigned long long, double*, double); \
   template __global__ void k_build_ninv<T>(const View<T>*);           \
   template __global__ void k_gj_panel<T>(const View<T>*, int);        \
-  template __global__ void k_gj_col<T>(const View<T>*, int, int);     \
+  template __global__ void k_gj_col<T, NB>(const View<T>*, int, int);  \
+  template __global__ void k_gj_col<T, NB_ONE>(const View<T>*, int, int); \
   template __global__ void k_gj_prep<T>(const View<T>*, int, int);    \
   template __global__ void k_gj_update<T>(const View<T>*, int, int);  \
   template __global__ void k_refresh_store<T>(const View<T>*, int);   \

@@ -9,7 +9,8 @@ A N - 1 with A assembled from the propagator:
 * an FP32-mixed N starts near FP32 roundoff after a rebuild and its residual
   grows over sweeps without refresh; the rebuild brings it back;
 * with drift_tol the library rebuilds walkers whose residual exceeds the
-  tolerance after a sweep, so a fresh probe of the final state stays near it.
+  tolerance at the end of a sweep, before that sweep's measurement, so a
+  fresh probe of the final state stays near it and no measurement is lost.
 """
 import numpy as np
 import pytest
@@ -75,4 +76,9 @@ def test_drift_control_rebuilds_walkers_above_the_tolerance():
           f"fresh probe {r.max():.2e}", flush=True)
     assert st["probe_refreshes"] > 0 and st["probes"] >= 20
     assert r.max() < 30 * tol
+    # a walker held at its sweep end is measured once, after its rebuild:
+    # every walker has exactly one measurement (sign +-1) per sweep
+    s = aux[:, 0].cpu().numpy()
+    print(f"  sign sums {s}", flush=True)
+    assert np.all(np.abs(s) <= 10) and np.all(np.mod(10 - s, 2) == 0)
     w.close()
