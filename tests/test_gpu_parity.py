@@ -36,8 +36,9 @@ from paper_1901_01047_amd.workloads import CONFIGS, params_kwargs  # noqa: E402
 from tests.ctaux_cases import model, oracle_trace  # noqa: E402
 
 
-def walker(name, **over):
-    p = dcax.make_params(**params_kwargs(name, **over))
+def walker(name, precision=None, **over):
+    extra = {} if precision is None else {"precision": precision}
+    p = dcax.make_params(**params_kwargs(name, **over), **extra)
     return dcax.Walker(p)
 
 
@@ -168,14 +169,23 @@ def test_replay_from_empty_configuration():
     w.close()
 
 
-@pytest.mark.parametrize("name,k", [("2x2_U4_b5", 25), ("4x4_U4_b10", 300)])
-def test_measurement_matches_direct_sums(name, k):
-    print(f"[measure] {name} k={k}", flush=True)
+# (2x2, k = 600): site buckets of ~150 rows, so the contraction takes b's
+# columns in several register chunks (128 in FP32, 64 in FP64); (8x8, k = 24):
+# most sites hold no vertex (empty buckets on either side of a pair)
+@pytest.mark.parametrize("name,k,precision,max_order", [
+    ("2x2_U4_b5", 25, "fp64", None), ("4x4_U4_b10", 300, "fp64", None),
+    ("2x2_U4_b5", 600, "fp64", 1024), ("2x2_U4_b5", 600, "mixed", 1024),
+    ("8x8_U7_b30", 24, "fp64", None), ("8x8_U7_b30", 24, "mixed", None)])
+def test_measurement_matches_direct_sums(name, k, precision, max_order):
+    print(f"[measure] {name} k={k} {precision}", flush=True)
     m = model(name)
     ow = ctaux.Walker(m, seed=11)
     ow.random_config(k)
     nf = CONFIGS[name]["n_freq"]
-    w = walker(name)
+    over = {} if max_order is None else {"max_order": max_order}
+    if precision == "mixed":
+        over["precision"] = dcax.DCAX_FP32_MIXED
+    w = walker(name, **over)
     w.set_config(ow.r, ow.t, ow.s, ow.id)
     acc, aux = w.new_accumulator()
     w.measure(acc, aux)
@@ -202,7 +212,9 @@ def test_measurement_matches_direct_sums(name, k):
         scale = 2 * np.abs(Mg).sum() / m.Nc
         e = np.max(np.abs(got[sp] - want)) / scale
         w_max_beta = (2 * nf - 1) * np.pi
-        tol = np.finfo(float).eps * (4 * w_max_beta + 4 * k)
+        # FP32-mixed: the sorted copy, the phases and the products are FP32
+        eps = np.finfo(np.float32 if precision == "mixed" else np.float64).eps
+        tol = eps * (4 * w_max_beta + 4 * k)
         print(f"  spin {sp}: err / sum|M| {e:.2e} (bound {tol:.1e}), err / max|result| "
               f"{np.max(np.abs(got[sp] - want)) / np.max(np.abs(want)):.2e}", flush=True)
         assert e < tol
