@@ -2331,6 +2331,7 @@ dcax_status enqueue_g2(dcax_walker w, int n_w4, int wm, int n_q, double* g2, dou
   const int kb1 = std::max(std::min(w->kpad_max, w->kmax_host() + 16 * w->nc_max), 1);
   enqueue_sorted_copy<T>(w, 0);
   const long long per = (long long)nw * Nc * nw, per4 = (long long)n4 * Nc * n4;
+  hipLaunchKernelGGL(k_g2_kphase<T>, dim3(cdiv((long long)Nc * Nc, WG)), dim3(WG), 0, s, vs, w->g2);
   for (int i = 0; i < W; ++i) {
     const View<T>* v = w->views<T>(i);
     hipLaunchKernelGGL(k_g2_phase<T>, dim3(cdiv(nw, 64), cdiv(kb1, 4)), dim3(256), 0, s, v, w->g2);
@@ -2381,8 +2382,9 @@ dcax_status dcax_measure_G2(dcax_walker w, int32_t n_w4, int32_t w_transfer, int
     g.H = (double2*)w->dalloc(sizeof(double2) * sq);
     g.G[0] = (double2*)w->dalloc(sizeof(double2) * sq);
     g.G[1] = (double2*)w->dalloc(sizeof(double2) * sq);
+    g.ph = (double2*)w->dalloc(sizeof(double2) * cc * cc);
     if (!w->g2_q) w->g2_q = (int*)w->dalloc(sizeof(int) * G2_Q_MAX);
-    if (!g.P || !g.T1 || !g.F || !g.H || !g.G[0] || !g.G[1] || !w->g2_q)
+    if (!g.P || !g.T1 || !g.F || !g.H || !g.G[0] || !g.G[1] || !g.ph || !w->g2_q)
       return fail(DCAX_E_NOMEM, "device allocation failed (two-particle scratch)");
     w->g2 = g;
     w->g2_nw = nn;

@@ -25,6 +25,7 @@ struct G2Dev {
   double2* F;              // [Nc a][nw][Nc b][nw]
   double2* H;              // [Nc K1][nw][Nc b][nw]
   double2* G[2];           // [Nc K1][nw][Nc K2][nw] per spin
+  double2* ph;             // [Nc K][Nc a] e^{-i K r_a}
 };
 
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
@@ -49,6 +50,19 @@ __global__ void __launch_bounds__(256) k_g2_phase(const View<T>* __restrict__ vs
     v = make_double2(co, -s);
   }
   g.P[(size_t)jp * g.nw + c] = v;
+}
+
+// Momentum phases e^{-i K r_a} of the cluster; one thread per (K, a).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_g2_kphase(const View<T>* __restrict__ vs, G2Dev g) {
+  const View<T>& w = vs[0];
+  const int Nc = w.Nc;
+  const int t = blockIdx.x * WG + threadIdx.x;
+  if (t >= Nc * Nc) return;
+  const int K = t / Nc, a = t % Nc;
+  double s, c;
+  sincos(-(w.Kp[2 * K] * (double)w.sites[2 * a] + w.Kp[2 * K + 1] * (double)w.sites[2 * a + 1]), &s, &c);
+  g.ph[t] = make_double2(c, s);
 }
 
 // T1[b][c][i'] = sum_{j' in b} Ms[i'][j'] P[j'][c]; thread per sorted row i',
@@ -118,8 +132,8 @@ __global__ void __launch_bounds__(WG) k_g2_k1(const View<T>* __restrict__ vs, G2
   if (t >= per) return;
   double2 acc = make_double2(0.0, 0.0);
   for (int a = 0; a < Nc; ++a) {
-    double s, c;
-    sincos(-(w.Kp[2 * K1] * (double)w.sites[2 * a] + w.Kp[2 * K1 + 1] * (double)w.sites[2 * a + 1]), &s, &c);
+    const double2 e = g.ph[K1 * Nc + a];
+    const double c = e.x, s = e.y;
     const double2 f = g.F[(size_t)a * per + t];
     acc.x += c * f.x - s * f.y;
     acc.y += c * f.y + s * f.x;
@@ -156,8 +170,8 @@ __global__ void __launch_bounds__(WG) k_g2_g(const View<T>* __restrict__ vs, int
   const double2* h = g.H + (size_t)K1 * per + (size_t)c1 * Nc * nw + c2;
   double2 m = make_double2(0.0, 0.0);
   for (int b = 0; b < Nc; ++b) {
-    double s, c;
-    sincos(w.Kp[2 * K2] * (double)w.sites[2 * b] + w.Kp[2 * K2 + 1] * (double)w.sites[2 * b + 1], &s, &c);
+    const double2 e = g.ph[K2 * Nc + b];     // e^{+i K2 r_b} = conj
+    const double c = e.x, s = -e.y;
     const double2 x = h[(size_t)b * nw];
     m.x += c * x.x - s * x.y;
     m.y += c * x.y + s * x.x;
@@ -211,6 +225,7 @@ __global__ void k_g2_sign(const View<T>* __restrict__ vs, double* sign_acc) {
 
 #define DCAX_INSTANTIATE_G2(T)                                                                   \
   template __global__ void k_g2_phase<T>(const View<T>*, G2Dev);                                 \
+  template __global__ void k_g2_kphase<T>(const View<T>*, G2Dev);                                \
   template __global__ void k_g2_t1<T>(const View<T>*, int, G2Dev);                               \
   template __global__ void k_g2_f<T>(const View<T>*, G2Dev);                                     \
   template __global__ void k_g2_k1<T>(const View<T>*, G2Dev);                                    \
