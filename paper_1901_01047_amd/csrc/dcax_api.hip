@@ -237,16 +237,13 @@ __global__ void k_meas_done(const View<T>* __restrict__ vs) {
 }
 
 template <typename T>
-__global__ void k_refresh_begin(const View<T>* __restrict__ vs, const int* __restrict__ mask, int by_hold) {
+__global__ void k_refresh_begin(const View<T>* __restrict__ vs) {
   const View<T>& w = vs[blockIdx.z];
   w.detsign[0] = 1.0;
   w.detsign[1] = 1.0;
   w.ctl->drift = 0.0;
-  // a masked refresh rebuilds only the flagged walkers (by the mask, or those
-  // the sweep-end probe held); a rebuilt walker is released
-  const bool on = by_hold ? w.ctl->hold != 0 : (mask == nullptr || mask[blockIdx.z]);
-  w.ctl->k_ref = on ? w.ctl->k : 0;
-  if (on) w.ctl->hold = 0;
+  w.ctl->k_ref = w.ctl->k;
+  w.ctl->hold = 0;         // a walker held by the drift control is released
 }
 
 // After dcax_set_config's refresh: the sign of the configuration is the sign
@@ -285,7 +282,6 @@ struct dcax_walker_s {
   int g2_dK_nc = 0;
   // probes of N against its definition (dcax_probe_N, drift_tol)
   double* probe_d = nullptr;   // [2 W] largest residual per walker and spin
-  int* probe_mask_d = nullptr; // [W] walkers the drift control rebuilds
   // work list of a measurement launch: [1 + W] count and walkers, [W + 1] item prefix sums
   int* meas_list_d = nullptr;
   long long* meas_pre_d = nullptr;
@@ -299,6 +295,10 @@ struct dcax_walker_s {
   Ctl* ctl_all = nullptr;      // [W] control blocks, contiguous
   std::vector<Ctl> h_ctl;      // host copy after the last synchronisation
   void* d_views = nullptr;     // [W] View<T> on the device
+  // views of the walkers a partial rebuild covers (the drift control's), so
+  // that its launches span only those walkers
+  void* d_views_sel = nullptr; // [W] View<T>
+  std::vector<char> views_sel_host;
   int ks_max = 0, cap_max = 0, nc_max = 0, nf_max = 0, kpad_max = 0, mo_max = 0;
   long long acc_total = 0;
   int nc_total = 0;
@@ -580,18 +580,16 @@ void enqueue_window(dcax_walker w, int kb, bool replay) {
 
 // FP64 refresh of N for walkers [first, first + n); nothing is read back.
 template <typename T>
-void enqueue_refresh(dcax_walker w, int first, int n, int kmax, bool measure, const int* mask = nullptr,
-                     bool by_hold = false, int n_rebuilt = -1) {
+void enqueue_refresh_vs(dcax_walker w, const View<T>* vs, int n, int kmax, bool measure) {
   w->fresh = false;
-  const View<T>* vs = w->views<T>(first);
   hipStream_t s = w->stream;
-  hipLaunchKernelGGL(k_refresh_begin<T>, dim3(1, 1, n), dim3(1), 0, s, vs, mask, by_hold ? 1 : 0);
+  hipLaunchKernelGGL(k_refresh_begin<T>, dim3(1, 1, n), dim3(1), 0, s, vs);
   if (kmax == 0) return;
   hipLaunchKernelGGL(k_build_ninv<T>, dim3(cdiv(kmax, WG), kmax, n), dim3(WG), 0, s, vs);
   // panel width: see dcax_refresh.hip (wide panels pay off from three
   // rebuilt walkers on)
   const bool one = kmax <= PANEL_ROWS;
-  const int pw = (one || (n_rebuilt >= 0 ? n_rebuilt : n) < 3) ? NB_ONE : NB;
+  const int pw = (one || n < 3) ? NB_ONE : NB;
   for (int p0 = 0; p0 < kmax; p0 += pw) {
     if (one)
       hipLaunchKernelGGL(k_gj_panel<T>, dim3(2, 1, n), dim3(cdiv(kmax, 64) * 64), 0, s, vs, p0);
@@ -607,6 +605,25 @@ void enqueue_refresh(dcax_walker w, int first, int n, int kmax, bool measure, co
   hipLaunchKernelGGL(k_gj_perm<T>, dim3(2, 1, n), dim3(64), 0, s, vs);
   hipLaunchKernelGGL(k_refresh_store<T>, dim3(cdiv(kmax, WG), kmax, 2 * n), dim3(WG), 0, s, vs, measure ? 1 : 0);
   if (measure) hipLaunchKernelGGL(k_drift<T>, dim3(1, 1, n), dim3(WG), 0, s, vs);
+}
+
+template <typename T>
+void enqueue_refresh(dcax_walker w, int first, int n, int kmax, bool measure) {
+  enqueue_refresh_vs<T>(w, w->views<T>(first), n, kmax, measure);
+}
+
+// FP64 rebuild of the listed walkers only: their views are copied into a
+// separate array, so every launch of the sequence spans just them (a masked
+// sequence over the whole batch would dispatch mostly idle workgroups).
+template <typename T>
+void enqueue_refresh_some(dcax_walker w, const std::vector<int>& idx, int kmax) {
+  const int n = (int)idx.size();
+  if (n == 0) return;
+  w->views_sel_host.resize(sizeof(View<T>) * n);
+  View<T>* h = (View<T>*)w->views_sel_host.data();
+  for (int j = 0; j < n; ++j) h[j] = hview<T>(w->wk[idx[j]]);
+  (void)hipMemcpyAsync(w->d_views_sel, h, sizeof(View<T>) * n, hipMemcpyHostToDevice, w->stream);
+  enqueue_refresh_vs<T>(w, (const View<T>*)w->d_views_sel, n, kmax, true);
 }
 
 dcax_status refresh_all(dcax_walker w, double* drift) {
@@ -660,21 +677,20 @@ dcax_status probe_and_refresh(dcax_walker w) {
   st = probe_all(w, res);
   if (st != DCAX_OK) return st;
   int nflag = 0, kflag = 0;
-  std::vector<int> flag(w->W, 0);
+  std::vector<int> flag(w->W, 0), idx;
   for (int i = 0; i < w->W; ++i)
     if (!(res[i] <= tol)) {
       flag[i] = 1;
       ++nflag;
+      idx.push_back(i);
       kflag = std::max(kflag, w->wk[i].k_host);
     }
   if (nflag == 0) return DCAX_OK;
   w->probe_refreshes += nflag;
-  // one refresh launch sequence for all flagged walkers: the others keep
-  // their N (their rebuild order is 0), so the sequence costs about what one
-  // walker's costs (its column steps are launch-latency-bound)
-  HIPCHK(hipMemcpyAsync(w->probe_mask_d, flag.data(), sizeof(int) * w->W, hipMemcpyHostToDevice, w->stream));
-  if (w->mixed) enqueue_refresh<float>(w, 0, w->W, kflag, true, w->probe_mask_d, false, nflag);
-  else enqueue_refresh<double>(w, 0, w->W, kflag, true, w->probe_mask_d, false, nflag);
+  // one refresh launch sequence over the flagged walkers only (its column
+  // steps are launch-latency-bound, so it costs about what one walker's does)
+  if (w->mixed) enqueue_refresh_some<float>(w, idx, kflag);
+  else enqueue_refresh_some<double>(w, idx, kflag);
   HIPCHK(hipGetLastError());
   w->fresh = false;
   st = sync_all(w);
@@ -1046,10 +1062,9 @@ template <typename T>
 dcax_status create_walkers(dcax_walker w) {
   w->ctl_all = (Ctl*)w->dalloc(sizeof(Ctl) * w->W);
   w->probe_d = (double*)w->dalloc(sizeof(double) * 2 * w->W);
-  w->probe_mask_d = (int*)w->dalloc(sizeof(int) * w->W);
   w->meas_list_d = (int*)w->dalloc(sizeof(int) * (w->W + 1));
   w->meas_pre_d = (long long*)w->dalloc(sizeof(long long) * (w->W + 1));
-  if (!w->ctl_all || !w->probe_d || !w->probe_mask_d || !w->meas_list_d || !w->meas_pre_d)
+  if (!w->ctl_all || !w->probe_d || !w->meas_list_d || !w->meas_pre_d)
     return fail(DCAX_E_NOMEM, "device allocation failed");
   for (int i = 0; i < w->W; ++i) {
     WalkerHost& x = w->wk[i];
@@ -1058,7 +1073,8 @@ dcax_status create_walkers(dcax_walker w) {
     wire_walker<T>(w, x, i, base, w->ctl_all + i);
   }
   w->d_views = w->dalloc(sizeof(View<T>) * w->W);
-  if (!w->d_views) return fail(DCAX_E_NOMEM, "device allocation failed");
+  w->d_views_sel = w->dalloc(sizeof(View<T>) * w->W);
+  if (!w->d_views || !w->d_views_sel) return fail(DCAX_E_NOMEM, "device allocation failed");
   std::vector<View<T>> hv(w->W);
   for (int i = 0; i < w->W; ++i) hv[i] = hview<T>(w->wk[i]);
   HIPCHK(hipMemcpyAsync(w->d_views, hv.data(), sizeof(View<T>) * w->W, hipMemcpyHostToDevice, w->stream));
@@ -1160,7 +1176,10 @@ dcax_status release_held(dcax_walker w, double* acc, double* aux, int nfft_hw, l
       for (int sp = 0; sp < 2; ++sp) m = (h[2 * i + sp] > m || h[2 * i + sp] != h[2 * i + sp]) ? h[2 * i + sp] : m;
   w->last_probe = m;
   w->probe_refreshes += nheld;
-  enqueue_refresh<T>(w, 0, w->W, kheld, true, nullptr, true, nheld);
+  std::vector<int> idx;
+  for (int i = 0; i < w->W; ++i)
+    if (w->h_ctl[i].hold) idx.push_back(i);
+  enqueue_refresh_some<T>(w, idx, kheld);     // releases them (clears hold)
   if (nfft_hw > 0) enqueue_nfft<T>(w, nfft_hw, acc, aux, 1);
   else enqueue_measure<T>(w, acc, aux, 1);
   HIPCHK(hipGetLastError());

@@ -52,8 +52,7 @@ struct Ctl {
   // begin, and whether the finished sweep still awaits its measurement
   long long sweeps_left;
   int meas_due;
-  // order the refresh kernels rebuild: k, or 0 for a walker a masked
-  // refresh leaves alone (set by the refresh's first kernel)
+  // order the refresh kernels rebuild (k, set by the refresh's first kernel)
   int k_ref;
   // windows by fold rank: bin 0 is m = 0, bin b holds 4b - 3 <= m <= 4b
   long long m_hist[FOLD_RANK_BINS];

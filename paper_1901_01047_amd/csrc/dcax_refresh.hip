@@ -1,6 +1,7 @@
 // From-scratch rebuild of the walker matrices in FP64.  The kernels rebuild
-// each walker at the order k_ref its control block holds: its order k, or 0
-// for a walker that a masked refresh (the drift control) leaves alone.
+// each walker of the views array they are given (the whole batch, or the
+// walkers the drift control selected) at the order k_ref its control block
+// holds, set to its order k by the sequence's first kernel.
 //
 // N_sigma^{-1} = e^{V_sigma} - g (e^{V_sigma} - 1) is assembled from k^2
 // propagator gathers (Sec. 2.3's definition of N through Z_k) and inverted by
