@@ -1149,7 +1149,9 @@ void enqueue_round(dcax_walker w, int kb, int nwin, double* acc, double* aux, in
 // launch-latency-bound), while a held walker only sits out the rounds (the
 // batch's launches shrink with it), so in a batch the pass waits until an
 // eighth of the walkers are held or the first of them has waited `wait`
-// rounds; force releases at once.  Synchronises.
+// rounds (a sweep: 32 walkers of 8x8 make 57.6k accepted updates/s with a
+// quarter sweep, 59.9k with a sweep); force releases at once.
+// Synchronises.
 template <typename T>
 dcax_status release_held(dcax_walker w, double* acc, double* aux, int nfft_hw, long long wait, bool force) {
   dcax_status st = sync_all(w);
@@ -1296,7 +1298,7 @@ dcax_status sweep_rounds(dcax_walker w, int n, double* acc, double* aux, long lo
           HIPCHK(hipGetLastError());
         }
       } else if (w->wk[0].p.drift_tol > 0.0) {
-        const long long wait = std::max<long long>(1, rounds_per_sweep / 4);
+        const long long wait = std::max<long long>(1, rounds_per_sweep);
         const bool last = r + 1 == planned;
         st = w->mixed ? release_held<float>(w, acc, aux, nfft_hw, wait, last)
                       : release_held<double>(w, acc, aux, nfft_hw, wait, last);
