@@ -2357,7 +2357,7 @@ dcax_status enqueue_g2(dcax_walker w, int n_w4, int wm, int n_q, double* g2, dou
     const View<T>* v = w->views<T>(i);
     hipLaunchKernelGGL(k_g2_phase<T>, dim3(cdiv(nw, 64), cdiv(kb1, 4)), dim3(256), 0, s, v, w->g2);
     for (int sp = 0; sp < 2; ++sp) {
-      hipLaunchKernelGGL(k_g2_t1<T>, dim3(cdiv(kb1, WG), Nc, cdiv(nw, G2_TC)), dim3(WG), 0, s, v, sp, w->g2);
+      hipLaunchKernelGGL(k_g2_t1m<T>, dim3(cdiv(kb1, G2_RG), Nc, cdiv(nw, 16)), dim3(WG), 0, s, v, sp, w->g2);
       hipLaunchKernelGGL(k_g2_f<T>, dim3(cdiv(per, WG), Nc), dim3(WG), 0, s, v, w->g2);
       hipLaunchKernelGGL(k_g2_k1<T>, dim3(cdiv(per, WG), Nc), dim3(WG), 0, s, v, w->g2);
       hipLaunchKernelGGL(k_g2_g<T>, dim3(cdiv(per, WG), Nc), dim3(WG), 0, s, v, sp, w->g2);

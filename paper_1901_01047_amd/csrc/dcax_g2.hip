@@ -65,37 +65,85 @@ __global__ void __launch_bounds__(WG) k_g2_kphase(const View<T>* __restrict__ vs
   g.ph[t] = make_double2(c, s);
 }
 
-// T1[b][c][i'] = sum_{j' in b} Ms[i'][j'] P[j'][c]; thread per sorted row i',
-// G2_TC frequencies each; grid (ceil(kpad / WG), Nc b, ceil(nw / G2_TC)).
-constexpr int G2_TC = 8;
+// T1[b][c][i'] = sum_{j' in b} Ms[i'][j'] P[j'][c] on the FP64 matrix cores.
+// Workgroup (row group of 256, site b, tile of 16 frequencies); its four
+// wavefronts take the 16-row blocks of the group in turn.  A wavefront keeps a chunk of b's phase rows
+// P[j][c] (G2_NB blocks of 16 columns) in registers, the lane supplying
+// column j = jc + 16 q + 4 u + (lane >> 4) of frequency c0 + (lane & 15), and
+// streams the rows of Ms: per 16 rows D[c][i'] = sum_j P[j][c] Ms[i'][j]
+// (real and imaginary parts of P separately), stored as T1[b][c][i'] by the
+// first chunk of b and added by later ones.
+constexpr int G2_NB = 4, G2_RG = 256;
 template <typename T>
-__global__ void __launch_bounds__(WG) k_g2_t1(const View<T>* __restrict__ vs, int sp, G2Dev g) {
+__global__ void __launch_bounds__(WG) k_g2_t1m(const View<T>* __restrict__ vs, int sp, G2Dev g) {
   const View<T>& w = vs[0];
   const auto off = gp(w.m_off);
   const int kp = off[w.Nc];
-  const int ip = blockIdx.x * WG + threadIdx.x;
-  const int b = blockIdx.y, c0 = blockIdx.z * G2_TC;
-  const bool live = ip < kp;
+  const int b = blockIdx.y, c0 = blockIdx.z * 16;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int r0 = blockIdx.x * G2_RG;
+  if (r0 >= kp) return;
+  const int nw = g.nw;
+  const int ca = c0 + li < nw ? c0 + li : 0;       // rows past nw are computed and never stored
   const auto Ms = gp(w.m_Ms[sp]);
-  const int ldm = w.kpad_cap;
-  double2 acc[G2_TC];
+  const size_t ldm = w.kpad_cap;
+  const double2* __restrict__ P = g.P;
+  double2* __restrict__ T1 = g.T1;
+  const int jb0 = off[b], jb1 = off[b + 1];
+  const size_t tb = (size_t)b * nw;
+  if (jb0 == jb1) {
+    // no vertex on site b: its T1 rows are zero
+    for (int ib = r0 + wv * 16; ib < r0 + G2_RG && ib < kp; ib += 64)
 #pragma unroll
-  for (int u = 0; u < G2_TC; ++u) acc[u] = make_double2(0.0, 0.0);
-  for (int jp = off[b]; jp < off[b + 1]; ++jp) {
-    const double m = live ? (double)Ms[ip + (size_t)jp * ldm] : 0.0;
+      for (int r = 0; r < 4; ++r) {
+        const int c = c0 + Mfma<double>::row(lane, r);
+        if (c < nw) T1[(tb + c) * g.kpad + ib + li] = make_double2(0.0, 0.0);
+      }
+    return;
+  }
+  for (int jc = jb0; jc < jb1; jc += 16 * G2_NB) {
+    const int blocks = (jb1 - jc) / 16 < G2_NB ? (jb1 - jc) / 16 : G2_NB;
+    const bool add = jc > jb0;
+    double er[G2_NB][4], ei[G2_NB][4];
 #pragma unroll
-    for (int u = 0; u < G2_TC; ++u) {
-      if (c0 + u < g.nw) {
-        const double2 p = g.P[(size_t)jp * g.nw + c0 + u];
-        acc[u].x += m * p.x;
-        acc[u].y += m * p.y;
+    for (int q = 0; q < G2_NB; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = jc + 16 * q + 4 * u + lk;
+        const double2 p = P[(size_t)(q < blocks ? j : jc) * nw + ca];
+        er[q][u] = q < blocks ? p.x : 0.0;
+        ei[q][u] = q < blocks ? p.y : 0.0;
+      }
+    for (int ib = r0 + wv * 16; ib < r0 + G2_RG && ib < kp; ib += 64) {
+      const size_t ip = (size_t)ib + li;
+      double m[G2_NB][4];
+#pragma unroll
+      for (int q = 0; q < G2_NB; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = jc + 16 * q + 4 * u + lk;
+          m[q][u] = (double)Ms[ip + (size_t)(q < blocks ? j : jc) * ldm];
+        }
+      typename Mfma<double>::acc_t dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < G2_NB; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          dr = Mfma<double>::run(er[q][u], m[q][u], dr);
+          di = Mfma<double>::run(ei[q][u], m[q][u], di);
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = c0 + Mfma<double>::row(lane, r);
+        if (c < nw) {
+          double2* o = T1 + (tb + c) * g.kpad + ip;
+          const double2 prev = add ? *o : make_double2(0.0, 0.0);
+          *o = make_double2(prev.x + dr[r], prev.y + di[r]);
+        }
       }
     }
   }
-  if (!live) return;
-#pragma unroll
-  for (int u = 0; u < G2_TC; ++u)
-    if (c0 + u < g.nw) g.T1[((size_t)b * g.nw + c0 + u) * g.kpad + ip] = acc[u];
 }
 
 // F[a][c1][b][c2] = sum_{i' in a} conj(P[i'][c1]) T1[b][c2][i']; thread per
@@ -226,7 +274,7 @@ __global__ void k_g2_sign(const View<T>* __restrict__ vs, double* sign_acc) {
 #define DCAX_INSTANTIATE_G2(T)                                                                   \
   template __global__ void k_g2_phase<T>(const View<T>*, G2Dev);                                 \
   template __global__ void k_g2_kphase<T>(const View<T>*, G2Dev);                                \
-  template __global__ void k_g2_t1<T>(const View<T>*, int, G2Dev);                               \
+  template __global__ void k_g2_t1m<T>(const View<T>*, int, G2Dev);                              \
   template __global__ void k_g2_f<T>(const View<T>*, G2Dev);                                     \
   template __global__ void k_g2_k1<T>(const View<T>*, G2Dev);                                    \
   template __global__ void k_g2_g<T>(const View<T>*, int, G2Dev);                                \
