@@ -4,12 +4,13 @@
 // accumulated with the configuration's sign; G = G0 - G0 <M> G0 / beta.
 //
 // The contraction is site-blocked: vertices are bucketed by site (each
-// bucket padded to a multiple of 16), M is copied into that order, and for
-// every pair of sites (a, b) and tile of 16 frequencies one wavefront forms
+// bucket padded to a multiple of 16), M is copied into that order, and
 //   M(a, b; w_n) = sum_{i in a} e^{i w_n tau_i} sum_{j in b} M_ij e^{-i w_n tau_j}
-// with the inner sum on the matrix cores (4 k^2 N_w flops per spin rather
-// than the 4 k^2 Nc N_w of the unblocked form).  A small kernel then applies
-// the momentum phases and adds sign * M(K, i w_n) to the caller's buffer.
+// is formed for every pair of sites, the inner sum on the matrix cores (4 k^2
+// N_w flops per spin rather than the 4 k^2 Nc N_w of the unblocked form): a
+// wavefront takes one site b, a group of sites a and a tile of 16
+// frequencies.  A small kernel then applies the momentum phases and adds
+// sign * M(K, i w_n) to the caller's buffer.
 #include "dcax_dev.h"
 
 namespace dcax {
