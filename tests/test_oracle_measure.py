@@ -105,7 +105,7 @@ def test_2x2_matsubara_vs_ed(cluster_2x2):
         zs.append(_zscores(res["Giw"][iK].real, res["Giw_err"][iK].real + 1e-15, want.real))
         zs.append(_zscores(res["Giw"][iK].imag, res["Giw_err"][iK].imag, want.imag))
     _check(zs, None, None)
-    assert 20 < orders.mean() < 45         # the survey's estimate is about 30
+    assert 20 < orders.mean() < 45         # a mean order of about 30 is expected here
 
 
 def test_2x2_tau_vs_ed(cluster_2x2):
