@@ -98,23 +98,29 @@ __global__ void __launch_bounds__(WG) k_meas_copy(const View<T>* __restrict__ vs
       }
       const auto Nj = gp(w.N[sp]) + (size_t)j * w.ld;
       const double fu = w.ev[sp][0] - 1.0, fd = w.ev[sp][1] - 1.0;
-      for (int i0 = t; i0 < k; i0 += 4 * WG) {
-        T v[4];
-        int sv[4];
+      // sixteen loads per thread in flight (two passes at most for the
+      // largest order the LDS column holds)
+      for (int i0 = t; i0 < k; i0 += 16 * WG) {
+        T v[16];
+        int sv[16];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 16; ++u) {
           const int i = i0 + u * WG < k ? i0 + u * WG : i0;
           v[u] = Nj[i];
           sv[u] = v_s[i];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 16; ++u)
           if (i0 + u * WG < k) col_s[i0 + u * WG] = (T)((sv[u] > 0 ? fu : fd) * (double)v[u]);
       }
       __syncthreads();
-      for (int ip = t; ip < kpad; ip += WG) {
-        const int i = order[ip];
-        Ms[ip] = i >= 0 ? col_s[i] : (T)0;
+      for (int ip0 = t; ip0 < kpad; ip0 += 8 * WG) {
+        int iv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) iv[u] = ip0 + u * WG < kpad ? order[ip0 + u * WG] : -1;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (ip0 + u * WG < kpad) Ms[ip0 + u * WG] = iv[u] >= 0 ? col_s[iv[u]] : (T)0;
       }
       __syncthreads();
     }
